@@ -1,0 +1,262 @@
+/*
+ * lramm.h -- C ABI of the MI355X (gfx950) LRAMM hot path.
+ *
+ * LRAMM (arxiv 2405.16917) approximates C = A B by a randomised range finder
+ * on A followed by low-precision quantised GEMMs on the low-rank factors
+ * (paper Sec. 2.2, Alg. 1; Sec. 3.1, Alg. 2; Sec. 3.2, Alg. 3).  This library
+ * computes the one-sided form
+ *
+ *     Y = A Omega            Gaussian sketch, Omega is k x l, l = r + p
+ *     Q = orth(Y)            CholeskyQR2 with FP64 Gram/Cholesky/solve
+ *     (q power iterations:  Z = A^T Q, Q_Z = orth(Z), Y = A Q_Z, Q = orth(Y))
+ *     Bt = Q^T A             projection (Alg. 1, first line)
+ *     T  = Bt B              first quantised product
+ *     C  = alpha * Q T + beta * C        second quantised product
+ *
+ * where every product is Alg. 2: the left operand is quantised per row, the
+ * right operand per column, the integer (or low-precision) product is
+ * accumulated exactly in int32 (FP32 for fp8/bf16), and the result is
+ * dequantised as c = fl32(fl32(acc) * fl32(d_row * d_col)).
+ *
+ * Quantiser (paper Sec. 3.1, eqs. Quantization / get_lambda /
+ * Dequantization), per vector v of binary32 values, qmax = 2^(N-1) - 1:
+ *     amax = max |v_i|;  lambda = fl32(qmax / amax);
+ *     code_i = clamp(rne(fl32(v_i * lambda)), -qmax, qmax);
+ *     d = fl32(amax / qmax);  amax == 0 or lambda == inf  ->  codes 0, d = 0.
+ * fp8 e4m3 uses qmax = 448 with saturating round-to-nearest-even; bf16 is a
+ * plain round-to-nearest-even cast with d = 1.
+ *
+ * Conventions for every entry point
+ *   - Matrices are row-major with a leading dimension in ELEMENTS, except
+ *     quantised buffers whose leading dimension ("pitch") is in BYTES.
+ *   - All matrix / vector pointers are DEVICE pointers owned by the caller.
+ *     The library never allocates device memory after lramm_init(); scratch
+ *     space comes from a caller-owned workspace whose size a query returns.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous on that stream.  Host-checkable argument errors
+ *     return immediately without launching anything; conditions found on the
+ *     GPU (non-finite input, Cholesky breakdown) set bits in a device status
+ *     word that lramm_status_poll() reads.
+ *   - No exception or abort crosses this ABI.  A plan is not re-entrant on
+ *     concurrent streams.  Identical inputs, seed and plan give bit-identical
+ *     results.
+ */
+#ifndef LRAMM_H
+#define LRAMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define LRAMM_API __attribute__((visibility("default")))
+#else
+#define LRAMM_API
+#endif
+
+typedef enum {
+  LRAMM_OK = 0,
+  LRAMM_E_INVALID = 1,     /* null pointer, bad enum, bad flag            */
+  LRAMM_E_SHAPE = 2,       /* sizes / leading dimensions inconsistent     */
+  LRAMM_E_RANK = 3,        /* l = r + p outside [1, min(m, k)]            */
+  LRAMM_E_WORKSPACE = 4,   /* workspace missing or too small              */
+  LRAMM_E_NONFINITE = 5,   /* a quantiser met NaN / Inf (device flag)     */
+  LRAMM_E_BREAKDOWN = 6,   /* Cholesky pivot dropped (device flag, non-fatal) */
+  LRAMM_E_OVERFLOW = 7,    /* K too large for the int32 accumulator       */
+  LRAMM_E_HIP = 8,         /* a HIP runtime call failed                   */
+  LRAMM_E_UNSUPPORTED = 9  /* format / type combination not implemented   */
+} lramm_status;
+
+/* element types of A, B, C and of stage inputs */
+typedef enum { LRAMM_F32 = 0, LRAMM_BF16 = 1, LRAMM_F64 = 2 } lramm_dtype;
+
+/* operand format of one product stage (the paper's bit budgets d1..d3) */
+typedef enum {
+  LRAMM_INT8 = 0,    /* 8-bit symmetric, int32 accumulation                  */
+  LRAMM_INT4 = 1,    /* 4-bit symmetric, stored two per byte                 */
+  LRAMM_FP8 = 2,     /* OCP e4m3 scaled to 448, FP32 accumulation            */
+  LRAMM_BF16F = 3    /* bfloat16 cast, FP32 accumulation                     */
+} lramm_fmt;
+
+/* device status word bits (lramm_status_poll) */
+#define LRAMM_FLAG_NONFINITE 0x1u  /* a quantiser input held NaN or Inf       */
+#define LRAMM_FLAG_BREAKDOWN 0x2u  /* CholeskyQR dropped a dependent column    */
+#define LRAMM_FLAG_SQRTNEG   0x4u  /* a Cholesky pivot was negative / NaN      */
+
+/*
+ * Problem description (paper Alg. 3 inputs A, B, C, r and the bit budgets;
+ * Alg. 2's alpha, beta; plus oversampling p, power iterations q and seed).
+ * A is m x k, B is k x n, C is m x n.  The sketch has l = r + p columns and
+ * the factorisation keeps rank l (no truncation back to r).
+ */
+typedef struct {
+  int64_t m, n, k;
+  int32_t r, p, q;
+  int32_t fmt_sketch;   /* lramm_fmt of Y = A Omega and Y = A Q_Z          */
+  int32_t fmt_proj;     /* lramm_fmt of Z = A^T Q and Bt = Q^T A           */
+  int32_t fmt_g1;       /* lramm_fmt of T = Bt B                           */
+  int32_t fmt_g2;       /* lramm_fmt of C = Q T                            */
+  int32_t a_type, b_type, c_type;   /* lramm_dtype: F32 or BF16            */
+  int32_t reserved0;
+  uint64_t seed;        /* Philox key when the caller passes no Omega      */
+  float alpha, beta;
+  uint32_t flags;       /* reserved, must be 0                             */
+  uint32_t reserved1;
+} lramm_desc;
+
+typedef struct lramm_plan lramm_plan;   /* opaque, host memory */
+
+/* Library set-up on the current device: checks the device is gfx950.  Safe
+ * to call more than once.  Returns LRAMM_E_UNSUPPORTED on other devices. */
+LRAMM_API lramm_status lramm_init(void);
+
+LRAMM_API const char* lramm_status_string(lramm_status s);
+
+/* ------------------------------------------------------------------------
+ * Plan / forward / backward.
+ */
+
+/* Validate the description and build the stage schedule and workspace
+ * layout.  Host only; *out receives a plan owned by the caller. */
+LRAMM_API lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out);
+LRAMM_API void lramm_plan_destroy(lramm_plan* plan);
+
+/* Bytes of device workspace lramm_forward / lramm_backward need. */
+LRAMM_API lramm_status lramm_workspace_bytes(const lramm_plan* plan, size_t* bytes);
+
+/* Forward pass (paper Alg. 3 in the one-sided form above).
+ *   A: m x k (desc.a_type), lda >= k.   B: k x n (desc.b_type), ldb >= n.
+ *   C: m x n (desc.c_type), ldc >= n; read when beta != 0.
+ *   omega: optional k x l FP32 test matrix (ldo >= l); NULL draws it from
+ *          Philox4x32-10 with key desc.seed (see lramm_omega).
+ *   ws: device workspace of ws_bytes >= lramm_workspace_bytes().
+ * After the call the workspace holds the factors (lramm_factors). */
+LRAMM_API lramm_status lramm_forward(lramm_plan* plan, const void* A, int64_t lda,
+                           const void* B, int64_t ldb, void* C, int64_t ldc,
+                           const float* omega, int64_t ldo, void* ws,
+                           size_t ws_bytes, void* stream);
+
+/* Device views of the factors the last forward left in ws:
+ *   Q: m x l FP64 with leading dimension *ldq (columns >= l are zero);
+ *   Bt: l x k FP32 (the dequantised projection Q^T A), leading dim *ldbt. */
+LRAMM_API lramm_status lramm_factors(const lramm_plan* plan, const void* ws,
+                           const double** Q, int64_t* ldq, const float** Bt,
+                           int64_t* ldbt);
+
+/* Backward of C = Q Q^T A B with Q fixed and quantisation straight-through
+ * (the gradient of the frozen-Q surrogate):
+ *     W = Q^T dC,  dB = (Q^T A)^T W,  dA = Q (W B^T).
+ * Uses the Q of the preceding lramm_forward on the same ws; all products in
+ * FP32 with FP32 accumulation.  dC: m x n FP32 (lddc); A, B as in forward
+ * (FP32); dA: m x k FP32 (ldda) and dB: k x n FP32 (lddb), each may be NULL
+ * to skip it. */
+LRAMM_API lramm_status lramm_backward(lramm_plan* plan, const float* dC, int64_t lddc,
+                            const float* A, int64_t lda, const float* B,
+                            int64_t ldb, float* dA, int64_t ldda, float* dB,
+                            int64_t lddb, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* Synchronise the stream and read the device status word of ws.
+ * *flags (nullable) receives the LRAMM_FLAG_* bits; the return value is
+ * LRAMM_E_NONFINITE if that bit is set, else LRAMM_OK (breakdown is
+ * reported only through *flags). */
+LRAMM_API lramm_status lramm_status_poll(const lramm_plan* plan, const void* ws,
+                               void* stream, uint32_t* flags);
+
+/* Stage timing, for measurement.  While enabled, lramm_forward records a
+ * HIP event pair around every stage on the caller's stream (events are
+ * created on the host at the first use and reused).  lramm_stage_times
+ * synchronises those events, adds their elapsed times to per-stage totals
+ * (milliseconds, launch counts) and clears the record; entries beyond
+ * LRAMM_NSTAGES are ignored.  Stage names: lramm_stage_name(). */
+#define LRAMM_NSTAGES 17
+LRAMM_API lramm_status lramm_plan_set_timing(lramm_plan* plan, int32_t enable);
+LRAMM_API lramm_status lramm_stage_times(lramm_plan* plan, double* ms,
+                                         int64_t* counts);
+LRAMM_API const char* lramm_stage_name(int32_t stage);
+
+/* ------------------------------------------------------------------------
+ * Stage entry points (each is one step of the forward, usable alone).
+ */
+
+/* Quantise a rows x cols matrix X (xtype F32, BF16 or F64; ldx elements).
+ *   transpose == 0: each ROW is one vector (left-operand form);
+ *       Xq is rows x pitch bytes, scales has rows entries, K = cols.
+ *   transpose == 1: each COLUMN is one vector (right-operand form), stored
+ *       transposed: Xq is cols x pitch bytes, scales has cols entries, K = rows.
+ * int8/fp8/bf16: K codes per output row (bf16 takes 2 bytes each); int4: codes
+ * packed two per byte along K (element 2j in the low nibble).  pitch must be
+ * >= lramm_pitch(K, fmt); bytes past the codes up to the padded length are
+ * written as zeros.  F64 inputs are rounded once to binary32 first.
+ * flags: optional device word; LRAMM_FLAG_NONFINITE is or-ed in when X holds
+ * NaN/Inf (the codes of such a vector are then unspecified). */
+LRAMM_API lramm_status lramm_quantize(int64_t rows, int64_t cols, const void* X,
+                            int64_t ldx, int32_t xtype, int32_t fmt,
+                            int32_t transpose, void* Xq, int64_t pitch,
+                            float* scales, uint32_t* flags, void* stream);
+
+/* Padded byte length of one quantised vector of K elements (a multiple of
+ * 64 bytes, zero-filled past the codes). */
+LRAMM_API int64_t lramm_pitch(int64_t K, int32_t fmt);
+
+/* Quantised NT-GEMM (Alg. 2): C[M x N] = epilogue(Lq[M x K] . Rq[N x K]^T)
+ *   Lq, Rq: quantised rows with byte pitches ldl, ldr >= lramm_pitch(K, fmt),
+ *           zero past K (as lramm_quantize writes them).
+ *   dL (M), dR (N): dequantisation factors (ignored for bf16).
+ *   C: FP32 or BF16 (ctype), ldc >= N;  c = fl32(fl32(acc) fl32(dL dR));
+ *      out = fl32(alpha c) [+ fl32(beta C_in)] (C_in read only if beta != 0).
+ *   acc_out: optional raw int32 accumulators (int8/int4 only), M x ld_acc.
+ *   ws / ws_bytes: workspace for split-K partials (may be NULL / 0, then the
+ *   library does not split K).  Returns LRAMM_E_OVERFLOW if K * qmax^2 could
+ *   exceed the int32 accumulator. */
+LRAMM_API lramm_status lramm_gemm_nt(int64_t M, int64_t N, int64_t K, int32_t fmt,
+                           const void* Lq, int64_t ldl, const float* dL,
+                           const void* Rq, int64_t ldr, const float* dR,
+                           float alpha, float beta, void* C, int64_t ldc,
+                           int32_t ctype, int32_t* acc_out, int64_t ld_acc,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes lramm_gemm_nt may use for split-K on this shape. */
+LRAMM_API size_t lramm_gemm_nt_workspace(int64_t M, int64_t N, int64_t K, int32_t fmt);
+
+/* Gaussian test matrix (paper Sec. 2.2, Gaussian sampling), written
+ * TRANSPOSED: OmegaT is l x k FP32 with leading dimension ldo >= k.
+ * Element Omega[i][j] = OmegaT[j][i] has index e = j*k + i; it is word
+ * (e mod 4) of Philox4x32-10 at counter (c mod 2^32, c >> 32, 0, 0),
+ * c = e >> 2, key (seed mod 2^32, seed >> 32), turned into normals by the
+ * Box-Muller transform in FP64 -- u1 = (x0 + 1) 2^-32, u2 = x1 2^-32,
+ * z0 = sqrt(-2 ln u1) cos(2 pi u2), z1 = sqrt(-2 ln u1) sin(2 pi u2), same
+ * for (x2, x3) -> (z2, z3) -- and rounded once to binary32. */
+LRAMM_API lramm_status lramm_omega(uint64_t seed, int64_t k, int64_t l, float* OmegaT,
+                         int64_t ldo, void* stream);
+
+/* CholeskyQR2 of a rows x l matrix Y (ytype F32 or F64, ldy >= l):
+ * Q (rows x l FP64, ldq >= round_up(l, 32)) with orthonormal columns spanning
+ * range(Y) -- the thin QR factor with positive diagonal.  Gram matrices,
+ * Cholesky factors and triangular solves are FP64.  A pivot whose square
+ * falls to <= 64 l 2^-53 times its Gram diagonal marks a dependent column:
+ * its Q column is zero and LRAMM_FLAG_BREAKDOWN is or-ed into *flags.
+ * Columns l .. ldq-1 of Q are written as zero.  ws >= lramm_cholqr2_workspace. */
+LRAMM_API lramm_status lramm_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
+                           int32_t ytype, double* Q, int64_t ldq, void* ws,
+                           size_t ws_bytes, uint32_t* flags, void* stream);
+LRAMM_API size_t lramm_cholqr2_workspace(int64_t rows, int64_t l);
+
+/* Dense comparator GEMM (no quantisation, no vendor library):
+ * C[M x N] = L[M x K] . R[N x K]^T with both operands K-contiguous.
+ * dtype BF16: bf16 inputs (uint16 storage), FP32 accumulation, FP32 output.
+ * dtype F32: FP32 inputs and output, FP32 accumulation.  ldl, ldr, ldc are
+ * in elements; K must be a multiple of 64 and ldl, ldr multiples of 64. */
+LRAMM_API lramm_status lramm_dense_gemm_nt(int64_t M, int64_t N, int64_t K,
+                                 int32_t dtype, const void* L, int64_t ldl,
+                                 const void* R, int64_t ldr, float* C,
+                                 int64_t ldc, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRAMM_H */

@@ -1,0 +1,281 @@
+"""ctypes binding of ``liblramm.so`` (the C ABI of include/lramm.h).
+
+Argument marshalling only: every function passes device pointers of torch
+tensors, sizes and the current HIP stream straight to the library, which runs
+every step of the path in its own kernels.  torch is imported first so that
+the library binds to the HIP runtime torch already loaded (one runtime per
+process).  There is no fallback: a missing library raises.
+"""
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime before the library)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblramm.so")
+
+# enums of include/lramm.h
+OK, E_INVALID, E_SHAPE, E_RANK, E_WORKSPACE, E_NONFINITE, E_BREAKDOWN, E_OVERFLOW, E_HIP, E_UNSUPPORTED = range(10)
+F32, BF16, F64 = 0, 1, 2
+INT8, INT4, FP8, BF16F = 0, 1, 2, 3
+FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_SQRTNEG = 0x1, 0x2, 0x4
+
+FMT = {"int8": INT8, "int4": INT4, "fp8": FP8, "bf16": BF16F}
+DTYPE = {torch.float32: F32, torch.bfloat16: BF16, torch.float64: F64}
+
+EXPORTS = (
+    "lramm_init", "lramm_status_string", "lramm_plan_create", "lramm_plan_destroy",
+    "lramm_workspace_bytes", "lramm_forward", "lramm_factors", "lramm_backward",
+    "lramm_status_poll", "lramm_quantize", "lramm_pitch", "lramm_gemm_nt",
+    "lramm_gemm_nt_workspace", "lramm_omega", "lramm_cholqr2",
+    "lramm_cholqr2_workspace", "lramm_dense_gemm_nt",
+)
+
+
+class LrammError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {_status_string(code)} (status {code})")
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+        ("r", ctypes.c_int32), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
+        ("fmt_sketch", ctypes.c_int32), ("fmt_proj", ctypes.c_int32),
+        ("fmt_g1", ctypes.c_int32), ("fmt_g2", ctypes.c_int32),
+        ("a_type", ctypes.c_int32), ("b_type", ctypes.c_int32), ("c_type", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("alpha", ctypes.c_float), ("beta", ctypes.c_float),
+        ("flags", ctypes.c_uint32), ("reserved1", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+I32 = ctypes.c_int32
+SZ = ctypes.c_size_t
+
+
+def load(path=LIB_PATH):
+    """Load the library (once) and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    sig = {
+        "lramm_init": ([], I32),
+        "lramm_status_string": ([I32], ctypes.c_char_p),
+        "lramm_plan_create": ([ctypes.POINTER(Desc), ctypes.POINTER(P)], I32),
+        "lramm_plan_destroy": ([P], None),
+        "lramm_workspace_bytes": ([P, ctypes.POINTER(SZ)], I32),
+        "lramm_forward": ([P, P, I64, P, I64, P, I64, P, I64, P, SZ, P], I32),
+        "lramm_factors": ([P, P, ctypes.POINTER(P), ctypes.POINTER(I64), ctypes.POINTER(P),
+                           ctypes.POINTER(I64)], I32),
+        "lramm_backward": ([P, P, I64, P, I64, P, I64, P, I64, P, I64, P, SZ, P], I32),
+        "lramm_status_poll": ([P, P, P, ctypes.POINTER(ctypes.c_uint32)], I32),
+        "lramm_quantize": ([I64, I64, P, I64, I32, I32, I32, P, I64, P, P, P], I32),
+        "lramm_pitch": ([I64, I32], I64),
+        "lramm_gemm_nt": ([I64, I64, I64, I32, P, I64, P, P, I64, P, ctypes.c_float, ctypes.c_float,
+                           P, I64, I32, P, I64, P, SZ, P], I32),
+        "lramm_gemm_nt_workspace": ([I64, I64, I64, I32], SZ),
+        "lramm_omega": ([ctypes.c_uint64, I64, I64, P, I64, P], I32),
+        "lramm_cholqr2": ([I64, I64, P, I64, I32, P, I64, P, SZ, P, P], I32),
+        "lramm_cholqr2_workspace": ([I64, I64], SZ),
+        "lramm_dense_gemm_nt": ([I64, I64, I64, I32, P, I64, P, I64, P, I64, P], I32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _status_string(code):
+    if _lib is None:
+        return "status"
+    return _lib.lramm_status_string(code).decode()
+
+
+def _check(code, where):
+    if code != OK:
+        raise LrammError(code, where)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _fmt(f):
+    return FMT[f] if isinstance(f, str) else int(f)
+
+
+# ----------------------------------------------------------------- stages --
+
+def lramm_init():
+    _check(load().lramm_init(), "lramm_init")
+
+
+def lramm_pitch(K, fmt):
+    return int(load().lramm_pitch(K, _fmt(fmt)))
+
+
+def lramm_quantize(X, fmt, transpose=False, Xq=None, scales=None, flags=None):
+    """Quantise the rows (transpose=False) or the columns (transpose=True,
+    written transposed) of the 2-D tensor X.  Returns (Xq, scales)."""
+    lib = load()
+    rows, cols = X.shape
+    K = rows if transpose else cols
+    nvec = cols if transpose else rows
+    pitch = lramm_pitch(K, fmt)
+    if Xq is None:
+        Xq = torch.empty((nvec, pitch), dtype=torch.uint8, device=X.device)
+    if scales is None:
+        scales = torch.empty(nvec, dtype=torch.float32, device=X.device)
+    _check(lib.lramm_quantize(rows, cols, _ptr(X), X.stride(0), DTYPE[X.dtype], _fmt(fmt),
+                              1 if transpose else 0, _ptr(Xq), Xq.stride(0), _ptr(scales),
+                              _ptr(flags), _stream()), "lramm_quantize")
+    return Xq, scales
+
+
+def lramm_gemm_nt(M, N, K, fmt, Lq, dL, Rq, dR, alpha=1.0, beta=0.0, C=None, ctype=torch.float32,
+                  acc_out=None, ws=None):
+    """Quantised NT-GEMM: C = epi(Lq[:M] . Rq[:N]^T) on quantised rows."""
+    lib = load()
+    if C is None:
+        C = torch.empty((M, N), dtype=ctype, device=Lq.device)
+    wsz = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(lib.lramm_gemm_nt(M, N, K, _fmt(fmt), _ptr(Lq), Lq.stride(0), _ptr(dL), _ptr(Rq), Rq.stride(0),
+                             _ptr(dR), alpha, beta, _ptr(C), C.stride(0), DTYPE[C.dtype], _ptr(acc_out),
+                             0 if acc_out is None else acc_out.stride(0), _ptr(ws), wsz, _stream()),
+           "lramm_gemm_nt")
+    return C
+
+
+def lramm_gemm_nt_workspace(M, N, K, fmt):
+    return int(load().lramm_gemm_nt_workspace(M, N, K, _fmt(fmt)))
+
+
+def lramm_omega(seed, k, l, device="cuda"):
+    """Omega^T (l x k, FP32) of the seeded Gaussian test matrix."""
+    out = torch.empty((l, k), dtype=torch.float32, device=device)
+    _check(load().lramm_omega(seed, k, l, _ptr(out), out.stride(0), _stream()), "lramm_omega")
+    return out
+
+
+def lramm_cholqr2_workspace(rows, l):
+    return int(load().lramm_cholqr2_workspace(rows, l))
+
+
+def lramm_cholqr2(Y, l=None, Q=None, ws=None, flags=None):
+    """CholeskyQR2 of the first l columns of Y (FP32 or FP64) -> Q (FP64,
+    leading dimension round_up(l, 32), padding columns zero)."""
+    lib = load()
+    rows = Y.shape[0]
+    l = Y.shape[1] if l is None else l
+    lw = (l + 31) // 32 * 32
+    if Q is None:
+        Q = torch.empty((rows, lw), dtype=torch.float64, device=Y.device)
+    need = lramm_cholqr2_workspace(rows, l)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=Y.device)
+    _check(lib.lramm_cholqr2(rows, l, _ptr(Y), Y.stride(0), DTYPE[Y.dtype], _ptr(Q), Q.stride(0), _ptr(ws),
+                             ws.numel(), _ptr(flags), _stream()), "lramm_cholqr2")
+    return Q
+
+
+def lramm_dense_gemm_nt(L, R, C=None):
+    """Dense comparator: C = L . R^T (bf16 or fp32 operands, FP32 out)."""
+    lib = load()
+    M, K = L.shape
+    N = R.shape[0]
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float32, device=L.device)
+    dt = BF16 if L.dtype == torch.bfloat16 else F32
+    _check(lib.lramm_dense_gemm_nt(M, N, K, dt, _ptr(L), L.stride(0), _ptr(R), R.stride(0), _ptr(C),
+                                   C.stride(0), _stream()), "lramm_dense_gemm_nt")
+    return C
+
+
+# ------------------------------------------------------------------- plan --
+
+class LrammPlan:
+    """lramm_plan_create / lramm_forward / lramm_backward / lramm_factors /
+    lramm_status_poll on one problem description."""
+
+    def __init__(self, m, n, k, r, p=16, q=1, fmt=("int8",) * 4, a_type=torch.float32,
+                 b_type=torch.float32, c_type=torch.float32, seed=0, alpha=1.0, beta=0.0):
+        lib = load()
+        d = Desc()
+        d.m, d.n, d.k, d.r, d.p, d.q = m, n, k, r, p, q
+        d.fmt_sketch, d.fmt_proj, d.fmt_g1, d.fmt_g2 = (_fmt(f) for f in fmt)
+        d.a_type, d.b_type, d.c_type = DTYPE[a_type], DTYPE[b_type], DTYPE[c_type]
+        d.seed, d.alpha, d.beta, d.flags = seed, alpha, beta, 0
+        self.desc = d
+        self.c_type = c_type
+        h = P()
+        _check(lib.lramm_plan_create(ctypes.byref(d), ctypes.byref(h)), "lramm_plan_create")
+        self._h = h
+        sz = SZ()
+        _check(lib.lramm_workspace_bytes(h, ctypes.byref(sz)), "lramm_workspace_bytes")
+        self.ws_bytes = int(sz.value)
+        self.l = r + p
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.lramm_plan_destroy(self._h)
+            self._h = None
+
+    def workspace(self, device="cuda"):
+        return torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+
+    def forward(self, A, B, ws, C=None, omega=None):
+        d = self.desc
+        if C is None:
+            C = torch.empty((d.m, d.n), dtype=self.c_type, device=A.device)
+        _check(load().lramm_forward(self._h, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(C), C.stride(0),
+                                    _ptr(omega), 0 if omega is None else omega.stride(0), _ptr(ws),
+                                    ws.numel(), _stream()), "lramm_forward")
+        return C
+
+    def factors(self, ws):
+        """Views of (Q [m x l FP64], Bt [l x k FP32]) inside ws."""
+        q, ldq, bt, ldbt = P(), I64(), P(), I64()
+        _check(load().lramm_factors(self._h, _ptr(ws), ctypes.byref(q), ctypes.byref(ldq), ctypes.byref(bt),
+                                    ctypes.byref(ldbt)), "lramm_factors")
+        d = self.desc
+        base = ws.data_ptr()
+        qo, bo = q.value - base, bt.value - base
+        Q = ws[qo:qo + d.m * ldq.value * 8].view(torch.float64).view(d.m, ldq.value)[:, :self.l]
+        Bt = ws[bo:bo + self.l * ldbt.value * 4].view(torch.float32).view(self.l, ldbt.value)
+        return Q, Bt
+
+    def backward(self, dC, A, B, ws, dA=None, dB=None, need_dA=True, need_dB=True):
+        d = self.desc
+        if need_dA and dA is None:
+            dA = torch.empty((d.m, d.k), dtype=torch.float32, device=dC.device)
+        if need_dB and dB is None:
+            dB = torch.empty((d.k, d.n), dtype=torch.float32, device=dC.device)
+        _check(load().lramm_backward(self._h, _ptr(dC), dC.stride(0), _ptr(A), A.stride(0), _ptr(B),
+                                     B.stride(0), _ptr(dA) if need_dA else None, dA.stride(0) if need_dA else 0,
+                                     _ptr(dB) if need_dB else None, dB.stride(0) if need_dB else 0, _ptr(ws),
+                                     ws.numel(), _stream()), "lramm_backward")
+        return dA, dB
+
+    def status(self, ws):
+        """Synchronise and return the device status flags (raises on NaN/Inf)."""
+        f = ctypes.c_uint32()
+        code = load().lramm_status_poll(self._h, _ptr(ws), _stream(), ctypes.byref(f))
+        _check(code, "lramm_status_poll")
+        return int(f.value)

@@ -1,0 +1,186 @@
+// Internal helpers shared by the HIP sources of the LRAMM library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lramm.h"
+
+namespace lramm {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+
+constexpr int kWave = 64;
+
+#define LRAMM_HIP(expr)                              \
+  do {                                               \
+    hipError_t _e = (expr);                          \
+    if (_e != hipSuccess) return LRAMM_E_HIP;        \
+  } while (0)
+
+#define LRAMM_TRY(expr)                              \
+  do {                                               \
+    lramm_status _s = (expr);                        \
+    if (_s != LRAMM_OK) return _s;                   \
+  } while (0)
+
+static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+// Bytes of one quantised vector of K elements in format fmt: padded to 64
+// bytes (128 for bf16, so that a padded row always holds whole 64-element
+// tiles).
+static inline int64_t pitch_bytes(int64_t K, int fmt) {
+  int64_t raw = (fmt == LRAMM_INT4) ? ceil_div(K, 2) : (fmt == LRAMM_BF16F ? 2 * K : K);
+  return round_up(raw > 0 ? raw : 1, fmt == LRAMM_BF16F ? 128 : 64);
+}
+
+// Elements one padded quantised vector holds.
+static inline int64_t pitch_elems(int64_t pitch, int fmt) {
+  return fmt == LRAMM_INT4 ? 2 * pitch : (fmt == LRAMM_BF16F ? pitch / 2 : pitch);
+}
+
+static inline int qmax_of(int fmt) {
+  return fmt == LRAMM_INT8 ? 127 : (fmt == LRAMM_INT4 ? 7 : 448);
+}
+
+// ---------------------------------------------------------------- device ---
+
+// Wavefront maximum of unsigned values (absmax bit patterns).
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, o, 64));
+  return v;
+}
+
+// Largest |x| bit pattern: for non-negative floats the IEEE bits order like
+// the values, so an unsigned max of |x| bits is the absmax (NaN/Inf compare
+// above every finite value and are caught separately).
+__device__ __forceinline__ unsigned abs_bits(float x) { return __float_as_uint(x) & 0x7fffffffu; }
+
+// Quantiser parameters from the absmax (rule of the paper's Sec. 3.1 with the
+// readings documented in lramm.h): lambda = fl32(qmax / amax),
+// d = fl32(amax / qmax); zero / overflowing lambda -> all-zero codes, d = 0.
+struct QParams {
+  float lam;
+  float d;
+};
+
+__device__ __forceinline__ QParams qparams(float amax, float qmax) {
+  QParams p;
+  if (!(amax > 0.0f) || !(amax <= 3.4028234663852886e38f)) {
+    p.lam = 0.0f;
+    p.d = 0.0f;
+    return p;
+  }
+  float lam = __fdiv_rn(qmax, amax);
+  if (!(lam <= 3.4028234663852886e38f)) {
+    p.lam = 0.0f;
+    p.d = 0.0f;
+    return p;
+  }
+  p.lam = lam;
+  p.d = __fdiv_rn(amax, qmax);
+  return p;
+}
+
+// One code: clamp(rne(fl32(v * lam)), -qmax, qmax).
+__device__ __forceinline__ int qcode(float v, float lam, float qmax) {
+  float y = __fmul_rn(v, lam);
+  y = __builtin_rintf(y);
+  y = fminf(fmaxf(y, -qmax), qmax);
+  return (int)y;
+}
+
+// OCP e4m3 (bias 7, max 448, no infinity): saturating round-to-nearest-even
+// of a finite binary32 value, returned as the 8-bit pattern.
+__device__ __forceinline__ uint32_t e4m3_bits(float y) {
+  uint32_t sign = (__float_as_uint(y) >> 24) & 0x80u;
+  float a = fabsf(y);
+  if (a >= 448.0f) return sign | 0x7eu;            // saturate (S.1111.110 = 448)
+  // spacing of the e4m3 grid in a's binade: 2^(e-3) for normals, 2^-9 below 2^-6
+  int e;
+  frexpf(a, &e);                                   // a = f 2^e, 0.5 <= f < 1
+  int sp_exp = e - 4;
+  if (sp_exp < -9) sp_exp = -9;
+  float sp = ldexpf(1.0f, sp_exp);
+  float qv = __builtin_rintf(a / sp) * sp;         // exact: a / sp is a power-of-2 scaling
+  if (qv >= 448.0f) return sign | 0x7eu;
+  if (qv == 0.0f) return sign;
+  int qe;
+  float qf = frexpf(qv, &qe);                      // qv = qf 2^qe
+  int biased = qe - 1 + 7;
+  if (biased <= 0) {                               // subnormal: value = m/8 * 2^-6
+    uint32_t mant = (uint32_t)(qv * 512.0f);       // qv / 2^-9
+    return sign | mant;
+  }
+  uint32_t mant = (uint32_t)((qf * 2.0f - 1.0f) * 8.0f);
+  return sign | ((uint32_t)biased << 3) | mant;
+}
+
+// bf16 round-to-nearest-even of a finite binary32 value (16-bit pattern).
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+template <typename T>
+__device__ __forceinline__ float load_as_f32(const T* p);
+template <>
+__device__ __forceinline__ float load_as_f32<float>(const float* p) { return *p; }
+template <>
+__device__ __forceinline__ float load_as_f32<uint16_t>(const uint16_t* p) { return bf16_to_float(*p); }
+template <>
+__device__ __forceinline__ float load_as_f32<double>(const double* p) { return (float)(*p); }
+
+// Simple fill kernel (used instead of hipMemsetAsync so that sequences stay
+// safe to capture in a graph).
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n);
+
+lramm_status fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+
+// ------------------------------------------------------------ host-side ---
+// Internal launchers (no argument validation beyond what the kernels need;
+// the C ABI layer validates).
+
+lramm_status launch_quantize(int64_t rows, int64_t cols, const void* X, int64_t ldx, int xtype, int fmt,
+                             int transpose, void* Xq, int64_t pitch, float* scales, uint32_t* flags,
+                             hipStream_t s);
+
+lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void* Lq, int64_t ldl,
+                            const float* dL, const void* Rq, int64_t ldr, const float* dR, float alpha,
+                            float beta, void* C, int64_t ldc, int ctype, int32_t* acc_out, int64_t ld_acc,
+                            void* ws, size_t ws_bytes, hipStream_t s);
+size_t gemm_nt_workspace(int64_t M, int64_t N, int64_t K, int fmt);
+
+lramm_status launch_omega(uint64_t seed, int64_t k, int64_t l, int64_t lrows, float* OmegaT, int64_t ldo,
+                          hipStream_t s);
+
+lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
+                            int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s);
+size_t cholqr2_workspace(int64_t rows, int64_t l);
+
+lramm_status launch_dense_gemm_nt(int64_t M, int64_t N, int64_t K, int dtype, const void* L, int64_t ldl,
+                                  const void* R, int64_t ldr, float* C, int64_t ldc, hipStream_t s);
+
+// FP32 GEMM with either operand stored K-contiguous ("t" = transposed
+// storage) or M/N-contiguous: C[M x N] = op(A) op(B) (+ C if accumulate).
+//   a_kmajor == 0: A stored M x K (lda, K contiguous)  -- A[i][k] = A[i*lda+k]
+//   a_kmajor == 1: A stored K x M (lda, M contiguous)  -- A[i][k] = A[k*lda+i]
+//   b_kmajor == 0: B stored N x K (ldb, K contiguous)  -- B[k][j] = B[j*ldb+k]
+//   b_kmajor == 1: B stored K x N (ldb, N contiguous)  -- B[k][j] = B[k*ldb+j]
+// A and B element type: float or double (converted to float).
+lramm_status launch_gemm_f32(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, int a_kmajor,
+                             int a_f64, const float* B, int64_t ldb, int b_kmajor, float* C, int64_t ldc,
+                             hipStream_t s);
+
+}  // namespace lramm

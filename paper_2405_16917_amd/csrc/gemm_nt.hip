@@ -1,0 +1,401 @@
+// Quantised NT-GEMM of the LRAMM hot path on gfx950 MFMA (paper Sec. 3.1,
+// Alg. 2: integer GEMM of the quantised operands, then dequantisation and
+// the alpha/beta update):
+//
+//   C[M x N] = epi( L[M x K] . R[N x K]^T ),  both operands K-contiguous.
+//
+// Tiling: 256 threads = 4 wavefronts in a 2 x 2 grid; a block tile is
+// BM x BN, each wavefront owns (BM/2) x (BN/2) as (BM/64) x (BN/64) tiles of
+// the 32 x 32 MFMA.  K advances in stages of 64 bytes of the widened operand
+// (64 int8 / int4 / fp8 elements, 32 bf16 elements), double-buffered in LDS
+// with a 16-byte row pad (80-byte pitch) so the 16-byte MFMA operand reads of
+// 8 consecutive rows fall in distinct banks.  Packed int4 rows are read as 32
+// bytes per stage and widened to int8 on the way into LDS (no int4 MFMA on
+// CDNA4), so the MFMA loop is the int8 one.
+//
+// MFMA operand layout (v_mfma_*_32x32x*): lane l supplies row (l % 32) of its
+// operand and a 16-byte slice of K chosen by l / 32; both operands use the
+// same slice mapping, so the K order inside a 32-byte chunk does not matter.
+// Result layout: lane l, accumulator r holds row 8(r/4) + 4(l/32) + r%4,
+// column l % 32 of the 32 x 32 tile.
+//
+// Integer accumulation is exact and split-K partials are summed as integers
+// in a fixed order, so the result is bit-reproducible for any split.
+#include "common.hpp"
+
+namespace lramm {
+
+enum { KIND_I8 = 0, KIND_I4 = 1, KIND_BF16 = 2 };
+
+struct GemmArgs {
+  int M, N;
+  int nst;                 // K stages of 64 widened bytes
+  int st_per_split;        // stages per split-K slice
+  const uint8_t* L;
+  int64_t ldl;             // bytes
+  const uint8_t* R;
+  int64_t ldr;             // bytes
+  const float* dL;
+  const float* dR;
+  float alpha, beta;
+  void* C;
+  int64_t ldc;             // elements
+  int ctype;
+  int32_t* acc_out;
+  int64_t ld_acc;
+  int32_t* part;           // split-K partials [split][M][N] (int32 or float bits)
+  int tiles_m, tiles_n;
+};
+
+constexpr int kLdsPitch = 80;   // bytes per LDS row (64 data + 16 pad)
+
+template <int KIND>
+struct Acc;
+template <>
+struct Acc<KIND_I8> { typedef v16i T; };
+template <>
+struct Acc<KIND_I4> { typedef v16i T; };
+template <>
+struct Acc<KIND_BF16> { typedef v16f T; };
+
+// Sign-extend the 8 nibbles of w to 8 bytes in element order
+// (byte j of w holds element 2j in its low and 2j+1 in its high nibble).
+__device__ __forceinline__ uint2 widen_int4(uint32_t w) {
+  uint32_t lo = w & 0x0f0f0f0fu;
+  uint32_t hi = (w >> 4) & 0x0f0f0f0fu;
+  lo |= ((lo >> 3) & 0x01010101u) * 0xf0u;
+  hi |= ((hi >> 3) & 0x01010101u) * 0xf0u;
+  uint2 o;
+  o.x = (lo & 0xffu) | ((hi & 0xffu) << 8) | ((lo & 0xff00u) << 8) | ((hi & 0xff00u) << 16);
+  o.y = ((lo >> 16) & 0xffu) | (((hi >> 16) & 0xffu) << 8) | ((lo >> 8) & 0xff0000u) | (hi & 0xff000000u);
+  return o;
+}
+
+// Global -> registers for one operand tile of ROWS rows at stage st.
+template <int ROWS, int KIND>
+struct TileLoader {
+  // int8 / bf16: ROWS x 64 bytes = ROWS*4 vectors of 16 B.
+  // int4: ROWS x 32 bytes = ROWS*2 vectors of 16 B (widened to 32 B each).
+  static constexpr int kVecPerRow = KIND == KIND_I4 ? 2 : 4;
+  static constexpr int kVecs = ROWS * kVecPerRow;
+  static constexpr int kPerThread = (kVecs + 255) / 256;
+  uint4 r[kPerThread];
+
+  __device__ __forceinline__ void load(const uint8_t* base, int64_t ld, int row0, int rows_total, int st, int tid) {
+    const int64_t kb = (int64_t)st * (KIND == KIND_I4 ? 32 : 64);
+#pragma unroll
+    for (int i = 0; i < kPerThread; ++i) {
+      int v = tid + 256 * i;
+      if (kVecs % 256 == 0 || v < kVecs) {
+        int row = v / kVecPerRow;
+        int c16 = v % kVecPerRow;
+        int gr = row0 + row;
+        gr = gr < rows_total ? gr : rows_total - 1;     // clamp: results of such rows are discarded
+        r[i] = *reinterpret_cast<const uint4*>(base + (int64_t)gr * ld + kb + c16 * 16);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(uint8_t* lds, int tid) const {
+#pragma unroll
+    for (int i = 0; i < kPerThread; ++i) {
+      int v = tid + 256 * i;
+      if (kVecs % 256 == 0 || v < kVecs) {
+        int row = v / kVecPerRow;
+        int c16 = v % kVecPerRow;
+        if constexpr (KIND == KIND_I4) {
+          uint2 a = widen_int4(r[i].x), b = widen_int4(r[i].y);
+          uint2 c = widen_int4(r[i].z), d = widen_int4(r[i].w);
+          uint4* dst = reinterpret_cast<uint4*>(lds + row * kLdsPitch + c16 * 32);
+          dst[0] = make_uint4(a.x, a.y, b.x, b.y);
+          dst[1] = make_uint4(c.x, c.y, d.x, d.y);
+        } else {
+          *reinterpret_cast<uint4*>(lds + row * kLdsPitch + c16 * 16) = r[i];
+        }
+      }
+    }
+  }
+};
+
+template <int KIND>
+__device__ __forceinline__ void mfma_32x32(typename Acc<KIND>::T& acc, const uint4& a, const uint4& b) {
+  if constexpr (KIND == KIND_BF16) {
+    v8bf av = __builtin_bit_cast(v8bf, a);
+    v8bf bv = __builtin_bit_cast(v8bf, b);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+  } else {
+    v4i av = __builtin_bit_cast(v4i, a);
+    v4i bv = __builtin_bit_cast(v4i, b);
+    acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv, acc, 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void store_out(void* C, int64_t idx, int ctype, float v) {
+  if (ctype == LRAMM_F32) {
+    reinterpret_cast<float*>(C)[idx] = v;
+  } else {
+    reinterpret_cast<uint16_t*>(C)[idx] = bf16_bits(v);
+  }
+}
+
+__device__ __forceinline__ float load_cin(const void* C, int64_t idx, int ctype) {
+  return ctype == LRAMM_F32 ? reinterpret_cast<const float*>(C)[idx]
+                            : bf16_to_float(reinterpret_cast<const uint16_t*>(C)[idx]);
+}
+
+// Dequantising epilogue: c = fl32(fl32(acc) * fl32(dL dR)); out = fl32(alpha c)
+// [+ fl32(beta Cin)].  For bf16 operands there are no scales (factor 1).
+template <bool INT>
+__device__ __forceinline__ float epilogue_value(float accf, const GemmArgs& a, int gm, int gn, int64_t cidx) {
+  float c = accf;
+  if (INT) {
+    float s = __fmul_rn(a.dL[gm], a.dR[gn]);
+    c = __fmul_rn(c, s);
+  }
+  c = __fmul_rn(a.alpha, c);
+  if (a.beta != 0.0f) c = __fadd_rn(c, __fmul_rn(a.beta, load_cin(a.C, cidx, a.ctype)));
+  return c;
+}
+
+template <int BM, int BN, int KIND, bool SPLIT>
+__global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
+  constexpr int RM = BM / 64;   // 32x32 MFMA tiles per wave along M
+  constexpr int RN = BN / 64;
+  __shared__ __attribute__((aligned(16))) uint8_t sA[2][BM * kLdsPitch];
+  __shared__ __attribute__((aligned(16))) uint8_t sB[2][BN * kLdsPitch];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // XCD-aware tile order: consecutive workgroup ids land on different XCDs
+  // (round robin over 8); remap so that each XCD walks a contiguous band of
+  // tiles and shares operand rows in its own L2.
+  int ntiles = a.tiles_m * a.tiles_n;
+  int bid = blockIdx.x;
+  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
+  const int tm = bid / a.tiles_n;
+  const int tn = bid % a.tiles_n;
+  const int row0 = tm * BM, col0 = tn * BN;
+  const int split = blockIdx.y;
+  const int st0 = split * a.st_per_split;
+  int st1 = st0 + a.st_per_split;
+  st1 = st1 < a.nst ? st1 : a.nst;
+
+  typename Acc<KIND>::T acc[RM][RN];
+#pragma unroll
+  for (int i = 0; i < RM; ++i)
+#pragma unroll
+    for (int j = 0; j < RN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
+
+  TileLoader<BM, KIND> la;
+  TileLoader<BN, KIND> lb;
+  if (st0 < st1) {
+    la.load(a.L, a.ldl, row0, a.M, st0, tid);
+    lb.load(a.R, a.ldr, col0, a.N, st0, tid);
+    la.store(sA[0], tid);
+    lb.store(sB[0], tid);
+  }
+  __syncthreads();
+
+  const int arow = wm * (BM / 2) + (lane & 31);
+  const int brow = wn * (BN / 2) + (lane & 31);
+  const int kofs = (lane >> 5) * 16;
+
+  for (int st = st0; st < st1; ++st) {
+    const int buf = (st - st0) & 1;
+    const bool more = st + 1 < st1;
+    if (more) {
+      la.load(a.L, a.ldl, row0, a.M, st + 1, tid);
+      lb.load(a.R, a.ldr, col0, a.N, st + 1, tid);
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint4 av[RM], bv[RN];
+#pragma unroll
+      for (int i = 0; i < RM; ++i)
+        av[i] = *reinterpret_cast<const uint4*>(&sA[buf][(arow + 32 * i) * kLdsPitch + c * 32 + kofs]);
+#pragma unroll
+      for (int j = 0; j < RN; ++j)
+        bv[j] = *reinterpret_cast<const uint4*>(&sB[buf][(brow + 32 * j) * kLdsPitch + c * 32 + kofs]);
+#pragma unroll
+      for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int j = 0; j < RN; ++j) mfma_32x32<KIND>(acc[i][j], av[i], bv[j]);
+    }
+    if (more) {
+      la.store(sA[buf ^ 1], tid);
+      lb.store(sB[buf ^ 1], tid);
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue
+  constexpr bool INT = KIND != KIND_BF16;
+#pragma unroll
+  for (int i = 0; i < RM; ++i) {
+#pragma unroll
+    for (int j = 0; j < RN; ++j) {
+      const int gn = col0 + wn * (BN / 2) + 32 * j + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int gm = row0 + wm * (BM / 2) + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (gm < a.M && gn < a.N) {
+          if constexpr (SPLIT) {
+            int32_t bits;
+            if constexpr (INT) bits = acc[i][j][r];
+            else bits = __float_as_int(acc[i][j][r]);
+            a.part[((int64_t)split * a.M + gm) * a.N + gn] = bits;
+          } else {
+            float accf;
+            if constexpr (INT) {
+              accf = (float)acc[i][j][r];          // v_cvt_f32_i32: round to nearest even
+              if (a.acc_out) a.acc_out[(int64_t)gm * a.ld_acc + gn] = acc[i][j][r];
+            } else {
+              accf = acc[i][j][r];
+            }
+            const int64_t cidx = (int64_t)gm * a.ldc + gn;
+            store_out(a.C, cidx, a.ctype, epilogue_value<INT>(accf, a, gm, gn, cidx));
+          }
+        }
+      }
+    }
+  }
+}
+
+// Sum the split-K partials in split order and apply the epilogue.
+template <bool INT>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs a, int nsplit) {
+  int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t total = (int64_t)a.M * a.N;
+  if (idx >= total) return;
+  int gm = (int)(idx / a.N), gn = (int)(idx % a.N);
+  float accf;
+  if constexpr (INT) {
+    int32_t s = 0;
+    for (int k = 0; k < nsplit; ++k) s += a.part[(int64_t)k * total + idx];
+    if (a.acc_out) a.acc_out[(int64_t)gm * a.ld_acc + gn] = s;
+    accf = (float)s;
+  } else {
+    float s = 0.0f;
+    for (int k = 0; k < nsplit; ++k) s = __fadd_rn(s, __int_as_float(a.part[(int64_t)k * total + idx]));
+    accf = s;
+  }
+  const int64_t cidx = (int64_t)gm * a.ldc + gn;
+  store_out(a.C, cidx, a.ctype, epilogue_value<INT>(accf, a, gm, gn, cidx));
+}
+
+// ------------------------------------------------------------------ host --
+
+static int kind_of(int fmt) {
+  switch (fmt) {
+    case LRAMM_INT8: return KIND_I8;
+    case LRAMM_INT4: return KIND_I4;
+    case LRAMM_BF16F: return KIND_BF16;
+    default: return -1;
+  }
+}
+
+struct Plan {
+  int bm, bn, split, st_per_split, nst, tiles_m, tiles_n;
+};
+
+static Plan plan_gemm(int64_t M, int64_t N, int64_t K, int fmt, bool allow_split) {
+  Plan p;
+  int epst = fmt == LRAMM_BF16F ? 32 : 64;      // elements per stage
+  p.nst = (int)ceil_div(K, epst);
+  p.bm = M >= 128 ? 128 : 64;
+  p.bn = N >= 128 ? 128 : 64;
+  // prefer the 64-wide N tile when it wastes noticeably less of a skinny N
+  if (p.bn == 128 && (round_up(N, 128) - N) * 4 > N && (round_up(N, 64) - N) < (round_up(N, 128) - N)) p.bn = 64;
+  p.tiles_m = (int)ceil_div(M, p.bm);
+  p.tiles_n = (int)ceil_div(N, p.bn);
+  int tiles = p.tiles_m * p.tiles_n;
+  p.split = 1;
+  if (allow_split && tiles < 128) {
+    // too few tiles to occupy the 256 CUs and a long K: split K (each slice
+    // keeps at least 8 stages); partials are summed in a second pass.
+    while (tiles * p.split < 256 && p.nst / (p.split * 2) >= 8 && p.split < 16) p.split *= 2;
+  }
+  p.st_per_split = (int)ceil_div(p.nst, p.split);
+  p.split = (int)ceil_div(p.nst, p.st_per_split);
+  return p;
+}
+
+size_t gemm_nt_workspace(int64_t M, int64_t N, int64_t K, int fmt) {
+  Plan p = plan_gemm(M, N, K, fmt, true);
+  return p.split > 1 ? (size_t)p.split * M * N * sizeof(int32_t) : 0;
+}
+
+template <int BM, int BN, int KIND>
+static void launch_tile(const GemmArgs& a, int split, hipStream_t s) {
+  dim3 grid(a.tiles_m * a.tiles_n, split);
+  if (split > 1)
+    hipLaunchKernelGGL((gemm_nt_kernel<BM, BN, KIND, true>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((gemm_nt_kernel<BM, BN, KIND, false>), grid, dim3(256), 0, s, a);
+}
+
+template <int KIND>
+static void launch_kind(const GemmArgs& a, const Plan& p, hipStream_t s) {
+  if (p.bm == 128 && p.bn == 128) launch_tile<128, 128, KIND>(a, p.split, s);
+  else if (p.bm == 128) launch_tile<128, 64, KIND>(a, p.split, s);
+  else if (p.bn == 128) launch_tile<64, 128, KIND>(a, p.split, s);
+  else launch_tile<64, 64, KIND>(a, p.split, s);
+}
+
+lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void* Lq, int64_t ldl,
+                            const float* dL, const void* Rq, int64_t ldr, const float* dR, float alpha,
+                            float beta, void* C, int64_t ldc, int ctype, int32_t* acc_out, int64_t ld_acc,
+                            void* ws, size_t ws_bytes, hipStream_t s) {
+  int kind = kind_of(fmt);
+  if (kind < 0) return LRAMM_E_UNSUPPORTED;
+  if (M == 0 || N == 0) return LRAMM_OK;
+  size_t need = gemm_nt_workspace(M, N, K, fmt);
+  bool can_split = ws != nullptr && need > 0 && ws_bytes >= need;
+  Plan p = plan_gemm(M, N, K, fmt, can_split);
+  GemmArgs a;
+  a.M = (int)M;
+  a.N = (int)N;
+  a.nst = p.nst;
+  a.st_per_split = p.st_per_split;
+  a.L = (const uint8_t*)Lq;
+  a.ldl = ldl;
+  a.R = (const uint8_t*)Rq;
+  a.ldr = ldr;
+  a.dL = dL;
+  a.dR = dR;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.C = C;
+  a.ldc = ldc;
+  a.ctype = ctype;
+  a.acc_out = acc_out;
+  a.ld_acc = ld_acc;
+  a.part = (int32_t*)ws;
+  a.tiles_m = p.tiles_m;
+  a.tiles_n = p.tiles_n;
+  if (K == 0) p.nst = a.nst = 0;
+  switch (kind) {
+    case KIND_I8: launch_kind<KIND_I8>(a, p, s); break;
+    case KIND_I4: launch_kind<KIND_I4>(a, p, s); break;
+    default: launch_kind<KIND_BF16>(a, p, s); break;
+  }
+  LRAMM_HIP(hipGetLastError());
+  if (p.split > 1) {
+    int64_t total = M * N;
+    if (kind == KIND_BF16)
+      hipLaunchKernelGGL(splitk_reduce_kernel<false>, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, a,
+                         p.split);
+    else
+      hipLaunchKernelGGL(splitk_reduce_kernel<true>, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, a,
+                         p.split);
+    LRAMM_HIP(hipGetLastError());
+  }
+  return LRAMM_OK;
+}
+
+}  // namespace lramm

@@ -1,0 +1,479 @@
+// C ABI of the LRAMM hot path: argument validation, workspace layout and the
+// stream-ordered stage sequence of the forward and backward passes.  No
+// device memory is allocated here; every buffer is a slice of the caller's
+// workspace and no host synchronisation happens inside forward / backward.
+//
+// Forward (paper Sec. 2.2 range finder + Alg. 1 projection + Sec. 3.2 chain
+// of Alg. 2 products, one-sided form):
+//   A_r  = quant_rows(A)  [fmt_sketch]      A_c = quant_cols(A) [fmt_proj]
+//   B_c  = quant_cols(B)  [fmt_g1]          Om  = quant_cols(Omega) [fmt_sketch]
+//   Y    = A_r . Om^T                       Q   = cholqr2(Y)
+//   repeat q times:  Z = A_c . quant_cols(Q)^T ; Q_Z = cholqr2(Z)
+//                    Y = A_r . quant_cols(Q_Z)^T ; Q = cholqr2(Y)
+//   Bt   = quant_cols(Q)[fmt_proj] . A_c^T          (Q^T A, l x k)
+//   T^T  = B_c . quant_rows(Bt)[fmt_g1]^T           (n x l)
+//   C    = alpha quant_rows(Q)[fmt_g2] . quant_rows(T^T)[fmt_g2]^T + beta C
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "common.hpp"
+
+struct lramm_plan {
+  lramm_desc d;
+  int64_t l, lp;            // sketch width and its 32-padded leading dimension
+  // workspace offsets (bytes)
+  size_t off_flags;
+  size_t off_Ar, off_sAr, off_Ac, off_sAc, off_Bc, off_sBc;
+  size_t off_OmT, off_Om, off_sOm;
+  size_t off_Y, off_Q, off_Z, off_QZ, off_QZc, off_sQZc;
+  size_t off_Qc, off_sQc, off_Qr, off_sQr;
+  size_t off_Bt, off_Btq, off_sBt, off_Tt, off_Ttq, off_sTt;
+  size_t off_chol, chol_bytes, off_split, split_bytes;
+  size_t off_W, off_Bte, off_V;
+  size_t total;
+  int64_t pAr, pAc, pBc, pOm, pQZc, pQc, pQr, pBtq, pTtq;
+  // stage timing (measurement only)
+  bool timing = false;
+  std::vector<hipEvent_t> events;     // pool, reused
+  std::vector<int> rec_stage;         // stage of each recorded pair
+  size_t next_event = 0;
+  double stage_ms[LRAMM_NSTAGES] = {0};
+  int64_t stage_n[LRAMM_NSTAGES] = {0};
+};
+
+using namespace lramm;
+
+namespace {
+
+bool valid_fmt(int f) { return f == LRAMM_INT8 || f == LRAMM_INT4 || f == LRAMM_BF16F; }
+bool valid_io(int t) { return t == LRAMM_F32 || t == LRAMM_BF16; }
+
+size_t carve(size_t* cur, size_t bytes) {
+  size_t o = (size_t)round_up((int64_t)*cur, 256);
+  *cur = o + bytes;
+  return o;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<uint8_t*>(ws) + off);
+}
+
+enum Stage {
+  ST_QUANT_A_ROWS, ST_QUANT_A_COLS, ST_QUANT_B, ST_OMEGA, ST_QUANT_OMEGA, ST_SKETCH, ST_CHOLQR2, ST_QUANT_Q_COLS,
+  ST_POWER_Z, ST_QUANT_QZ, ST_POWER_Y, ST_PROJ, ST_QUANT_BT, ST_G1, ST_QUANT_Q_ROWS, ST_QUANT_TT, ST_G2
+};
+const char* kStageNames[LRAMM_NSTAGES] = {
+    "quant_A_rows", "quant_A_cols", "quant_B_cols", "omega", "quant_omega", "sketch_gemm", "cholqr2",
+    "quant_Q_cols", "power_gemm_Z", "quant_QZ_cols", "power_gemm_Y", "proj_gemm", "quant_Bt_rows", "g1_gemm",
+    "quant_Q_rows", "quant_Tt_rows", "g2_gemm"};
+
+// Event pair around one stage when the plan measures (no-op otherwise).
+struct StageTimer {
+  lramm_plan* p;
+  hipStream_t s;
+  int stage;
+  hipEvent_t stop = nullptr;
+  StageTimer(lramm_plan* p_, hipStream_t s_, int st) : p(p_), s(s_), stage(st) {
+    if (!p->timing) return;
+    while (p->events.size() < p->next_event + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        p->timing = false;
+        return;
+      }
+      p->events.push_back(e);
+    }
+    hipEvent_t start = p->events[p->next_event];
+    stop = p->events[p->next_event + 1];
+    p->next_event += 2;
+    p->rec_stage.push_back(stage);
+    (void)hipEventRecord(start, s);
+  }
+  ~StageTimer() {
+    if (stop) (void)hipEventRecord(stop, s);
+  }
+};
+
+int64_t qk_bound(int fmt) { return fmt == LRAMM_INT4 ? (int64_t)(2147483647LL / 49) : (int64_t)(2147483647LL / 16129); }
+
+}  // namespace
+
+extern "C" {
+
+const char* lramm_status_string(lramm_status s) {
+  switch (s) {
+    case LRAMM_OK: return "ok";
+    case LRAMM_E_INVALID: return "invalid argument";
+    case LRAMM_E_SHAPE: return "inconsistent sizes or leading dimensions";
+    case LRAMM_E_RANK: return "sketch width l = r + p outside [1, min(m, k)]";
+    case LRAMM_E_WORKSPACE: return "workspace missing or too small";
+    case LRAMM_E_NONFINITE: return "non-finite value met by a quantiser";
+    case LRAMM_E_BREAKDOWN: return "Cholesky breakdown";
+    case LRAMM_E_OVERFLOW: return "K too large for the int32 accumulator";
+    case LRAMM_E_HIP: return "HIP runtime error";
+    case LRAMM_E_UNSUPPORTED: return "unsupported format, type or device";
+    default: return "unknown status";
+  }
+}
+
+lramm_status lramm_init(void) {
+  int dev = 0;
+  LRAMM_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  LRAMM_HIP(hipGetDeviceProperties(&prop, dev));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LRAMM_E_UNSUPPORTED;
+  return LRAMM_OK;
+}
+
+int64_t lramm_pitch(int64_t K, int32_t fmt) { return pitch_bytes(K, fmt); }
+
+lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
+  if (!desc || !out) return LRAMM_E_INVALID;
+  const lramm_desc& d = *desc;
+  if (d.m <= 0 || d.n <= 0 || d.k <= 0) return LRAMM_E_SHAPE;
+  if (d.m > INT32_MAX || d.n > INT32_MAX || d.k > INT32_MAX) return LRAMM_E_SHAPE;
+  if (d.r < 0 || d.p < 0 || d.q < 0 || d.q > 16) return LRAMM_E_INVALID;
+  int64_t l = (int64_t)d.r + d.p;
+  if (l < 1 || l > d.m || l > d.k) return LRAMM_E_RANK;
+  if (!valid_fmt(d.fmt_sketch) || !valid_fmt(d.fmt_proj) || !valid_fmt(d.fmt_g1) || !valid_fmt(d.fmt_g2))
+    return LRAMM_E_UNSUPPORTED;
+  if (!valid_io(d.a_type) || !valid_io(d.b_type) || !valid_io(d.c_type)) return LRAMM_E_UNSUPPORTED;
+  if (d.flags != 0) return LRAMM_E_INVALID;
+  // int32 accumulator bound of every integer product
+  if ((d.fmt_sketch != LRAMM_BF16F && d.k > qk_bound(d.fmt_sketch)) ||
+      (d.fmt_proj != LRAMM_BF16F && d.m > qk_bound(d.fmt_proj)) ||
+      (d.fmt_g1 != LRAMM_BF16F && d.k > qk_bound(d.fmt_g1)))
+    return LRAMM_E_OVERFLOW;
+  int64_t lp = round_up(l, 32);
+  if (lp > 1024) return LRAMM_E_UNSUPPORTED;    // FP64 TRSM row block must fit LDS
+
+  lramm_plan* p = new (std::nothrow) lramm_plan();
+  if (!p) return LRAMM_E_INVALID;
+  p->d = d;
+  p->l = l;
+  p->lp = lp;
+  const int64_t m = d.m, n = d.n, k = d.k;
+  p->pAr = pitch_bytes(k, d.fmt_sketch);
+  p->pAc = pitch_bytes(m, d.fmt_proj);
+  p->pBc = pitch_bytes(k, d.fmt_g1);
+  p->pOm = pitch_bytes(k, d.fmt_sketch);
+  p->pQZc = pitch_bytes(k, d.fmt_sketch);
+  p->pQc = pitch_bytes(m, d.fmt_proj);
+  p->pQr = pitch_bytes(l, d.fmt_g2);
+  p->pBtq = pitch_bytes(k, d.fmt_g1);
+  p->pTtq = pitch_bytes(l, d.fmt_g2);
+
+  size_t c = 0;
+  p->off_flags = carve(&c, 256);
+  p->off_Ar = carve(&c, (size_t)m * p->pAr);
+  p->off_sAr = carve(&c, (size_t)m * 4);
+  p->off_Ac = carve(&c, (size_t)k * p->pAc);
+  p->off_sAc = carve(&c, (size_t)k * 4);
+  p->off_Bc = carve(&c, (size_t)n * p->pBc);
+  p->off_sBc = carve(&c, (size_t)n * 4);
+  p->off_OmT = carve(&c, (size_t)l * k * 4);
+  p->off_Om = carve(&c, (size_t)l * p->pOm);
+  p->off_sOm = carve(&c, (size_t)l * 4);
+  p->off_Y = carve(&c, (size_t)m * lp * 4);
+  p->off_Q = carve(&c, (size_t)m * lp * 8);
+  if (d.q > 0) {
+    p->off_Z = carve(&c, (size_t)k * lp * 4);
+    p->off_QZ = carve(&c, (size_t)k * lp * 8);
+    p->off_QZc = carve(&c, (size_t)l * p->pQZc);
+    p->off_sQZc = carve(&c, (size_t)l * 4);
+  }
+  p->off_Qc = carve(&c, (size_t)l * p->pQc);
+  p->off_sQc = carve(&c, (size_t)l * 4);
+  p->off_Qr = carve(&c, (size_t)m * p->pQr);
+  p->off_sQr = carve(&c, (size_t)m * 4);
+  p->off_Bt = carve(&c, (size_t)l * k * 4);
+  p->off_Btq = carve(&c, (size_t)l * p->pBtq);
+  p->off_sBt = carve(&c, (size_t)l * 4);
+  p->off_Tt = carve(&c, (size_t)n * lp * 4);
+  p->off_Ttq = carve(&c, (size_t)n * p->pTtq);
+  p->off_sTt = carve(&c, (size_t)n * 4);
+  p->chol_bytes = cholqr2_workspace(m > k ? m : k, l);
+  p->off_chol = carve(&c, p->chol_bytes);
+  size_t sb = 0, t;
+  t = gemm_nt_workspace(m, l, k, d.fmt_sketch); sb = t > sb ? t : sb;
+  t = gemm_nt_workspace(k, l, m, d.fmt_proj); sb = t > sb ? t : sb;
+  t = gemm_nt_workspace(l, k, m, d.fmt_proj); sb = t > sb ? t : sb;
+  t = gemm_nt_workspace(n, l, k, d.fmt_g1); sb = t > sb ? t : sb;
+  t = gemm_nt_workspace(m, n, l, d.fmt_g2); sb = t > sb ? t : sb;
+  p->split_bytes = sb;
+  p->off_split = carve(&c, sb);
+  // backward scratch
+  p->off_W = carve(&c, (size_t)l * n * 4);
+  p->off_Bte = carve(&c, (size_t)l * k * 4);
+  p->off_V = carve(&c, (size_t)l * k * 4);
+  p->total = c + 256;
+  *out = p;
+  return LRAMM_OK;
+}
+
+void lramm_plan_destroy(lramm_plan* plan) {
+  if (!plan) return;
+  for (hipEvent_t e : plan->events) (void)hipEventDestroy(e);
+  delete plan;
+}
+
+lramm_status lramm_plan_set_timing(lramm_plan* plan, int32_t enable) {
+  if (!plan) return LRAMM_E_INVALID;
+  plan->timing = enable != 0;
+  return LRAMM_OK;
+}
+
+lramm_status lramm_stage_times(lramm_plan* plan, double* ms, int64_t* counts) {
+  if (!plan) return LRAMM_E_INVALID;
+  for (size_t i = 0; i < plan->rec_stage.size(); ++i) {
+    hipEvent_t a = plan->events[2 * i], b = plan->events[2 * i + 1];
+    LRAMM_HIP(hipEventSynchronize(b));
+    float t = 0.0f;
+    LRAMM_HIP(hipEventElapsedTime(&t, a, b));
+    int st = plan->rec_stage[i];
+    plan->stage_ms[st] += t;
+    plan->stage_n[st] += 1;
+  }
+  plan->rec_stage.clear();
+  plan->next_event = 0;
+  for (int i = 0; i < LRAMM_NSTAGES; ++i) {
+    if (ms) ms[i] = plan->stage_ms[i];
+    if (counts) counts[i] = plan->stage_n[i];
+    plan->stage_ms[i] = 0.0;
+    plan->stage_n[i] = 0;
+  }
+  return LRAMM_OK;
+}
+
+const char* lramm_stage_name(int32_t stage) {
+  return (stage >= 0 && stage < LRAMM_NSTAGES) ? kStageNames[stage] : "unknown";
+}
+
+lramm_status lramm_workspace_bytes(const lramm_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return LRAMM_E_INVALID;
+  *bytes = plan->total;
+  return LRAMM_OK;
+}
+
+lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                           int64_t ldc, const float* omega, int64_t ldo, void* ws, size_t ws_bytes, void* stream) {
+  if (!P || !A || !B || !C) return LRAMM_E_INVALID;
+  if (!ws || ws_bytes < P->total) return LRAMM_E_WORKSPACE;
+  const lramm_desc& d = P->d;
+  const int64_t m = d.m, n = d.n, k = d.k, l = P->l, lp = P->lp;
+  if (lda < k || ldb < n || ldc < n) return LRAMM_E_SHAPE;
+  if (omega && ldo < l) return LRAMM_E_SHAPE;
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* base = reinterpret_cast<uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
+  void* W = base;
+  uint32_t* flags = at<uint32_t>(W, P->off_flags);
+  LRAMM_TRY(fill_u32(flags, 0u, 1, s));
+  void* split = P->split_bytes ? at<void>(W, P->off_split) : nullptr;
+  const size_t sb = P->split_bytes;
+
+  uint8_t* Ar = at<uint8_t>(W, P->off_Ar);
+  float* sAr = at<float>(W, P->off_sAr);
+  uint8_t* Ac = at<uint8_t>(W, P->off_Ac);
+  float* sAc = at<float>(W, P->off_sAc);
+  uint8_t* Bc = at<uint8_t>(W, P->off_Bc);
+  float* sBc = at<float>(W, P->off_sBc);
+  uint8_t* Om = at<uint8_t>(W, P->off_Om);
+  float* sOm = at<float>(W, P->off_sOm);
+  float* Y = at<float>(W, P->off_Y);
+  double* Q = at<double>(W, P->off_Q);
+  void* cws = at<void>(W, P->off_chol);
+
+  // operand quantisation
+#define TIMED(stage, expr)                \
+  do {                                    \
+    StageTimer _t(P, s, stage);           \
+    LRAMM_TRY(expr);                      \
+  } while (0)
+  TIMED(ST_QUANT_A_ROWS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_sketch, 0, Ar, P->pAr, sAr, flags, s));
+  TIMED(ST_QUANT_A_COLS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_proj, 1, Ac, P->pAc, sAc, flags, s));
+  TIMED(ST_QUANT_B, launch_quantize(k, n, B, ldb, d.b_type, d.fmt_g1, 1, Bc, P->pBc, sBc, flags, s));
+  if (omega) {
+    TIMED(ST_QUANT_OMEGA, launch_quantize(k, l, omega, ldo, LRAMM_F32, d.fmt_sketch, 1, Om, P->pOm, sOm, flags, s));
+  } else {
+    float* OmT = at<float>(W, P->off_OmT);
+    TIMED(ST_OMEGA, launch_omega(d.seed, k, l, l, OmT, k, s));
+    TIMED(ST_QUANT_OMEGA, launch_quantize(l, k, OmT, k, LRAMM_F32, d.fmt_sketch, 0, Om, P->pOm, sOm, flags, s));
+  }
+  // sketch and orthonormalisation
+  TIMED(ST_SKETCH, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, P->pAr, sAr, Om, P->pOm, sOm, 1.0f, 0.0f, Y, lp,
+                                  LRAMM_F32, nullptr, 0, split, sb, s));
+  TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s));
+  uint8_t* Qc = at<uint8_t>(W, P->off_Qc);
+  float* sQc = at<float>(W, P->off_sQc);
+  for (int it = 0; it < d.q; ++it) {
+    float* Z = at<float>(W, P->off_Z);
+    double* QZ = at<double>(W, P->off_QZ);
+    uint8_t* QZc = at<uint8_t>(W, P->off_QZc);
+    float* sQZc = at<float>(W, P->off_sQZc);
+    TIMED(ST_QUANT_Q_COLS, launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s));
+    TIMED(ST_POWER_Z, launch_gemm_nt(k, l, m, d.fmt_proj, Ac, P->pAc, sAc, Qc, P->pQc, sQc, 1.0f, 0.0f, Z, lp,
+                                     LRAMM_F32, nullptr, 0, split, sb, s));
+    TIMED(ST_CHOLQR2, launch_cholqr2(k, l, Z, lp, LRAMM_F32, QZ, lp, cws, P->chol_bytes, flags, s));
+    TIMED(ST_QUANT_QZ, launch_quantize(k, l, QZ, lp, LRAMM_F64, d.fmt_sketch, 1, QZc, P->pQZc, sQZc, flags, s));
+    TIMED(ST_POWER_Y, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, P->pAr, sAr, QZc, P->pQZc, sQZc, 1.0f, 0.0f, Y, lp,
+                                     LRAMM_F32, nullptr, 0, split, sb, s));
+    TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s));
+  }
+  // projection Bt = Q^T A  (l x k)
+  float* Bt = at<float>(W, P->off_Bt);
+  TIMED(ST_QUANT_Q_COLS, launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s));
+  TIMED(ST_PROJ, launch_gemm_nt(l, k, m, d.fmt_proj, Qc, P->pQc, sQc, Ac, P->pAc, sAc, 1.0f, 0.0f, Bt, k, LRAMM_F32,
+                                nullptr, 0, split, sb, s));
+  // G1: T^T = B_c . Bt_q^T  (n x l)
+  uint8_t* Btq = at<uint8_t>(W, P->off_Btq);
+  float* sBt = at<float>(W, P->off_sBt);
+  float* Tt = at<float>(W, P->off_Tt);
+  TIMED(ST_QUANT_BT, launch_quantize(l, k, Bt, k, LRAMM_F32, d.fmt_g1, 0, Btq, P->pBtq, sBt, flags, s));
+  TIMED(ST_G1, launch_gemm_nt(n, l, k, d.fmt_g1, Bc, P->pBc, sBc, Btq, P->pBtq, sBt, 1.0f, 0.0f, Tt, lp, LRAMM_F32,
+                              nullptr, 0, split, sb, s));
+  // G2: C = alpha Q_r . Tt_q^T + beta C  (m x n)
+  uint8_t* Qr = at<uint8_t>(W, P->off_Qr);
+  float* sQr = at<float>(W, P->off_sQr);
+  uint8_t* Ttq = at<uint8_t>(W, P->off_Ttq);
+  float* sTt = at<float>(W, P->off_sTt);
+  TIMED(ST_QUANT_Q_ROWS, launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_g2, 0, Qr, P->pQr, sQr, flags, s));
+  TIMED(ST_QUANT_TT, launch_quantize(n, l, Tt, lp, LRAMM_F32, d.fmt_g2, 0, Ttq, P->pTtq, sTt, flags, s));
+  TIMED(ST_G2, launch_gemm_nt(m, n, l, d.fmt_g2, Qr, P->pQr, sQr, Ttq, P->pTtq, sTt, d.alpha, d.beta, C, ldc,
+                              d.c_type, nullptr, 0, split, sb, s));
+#undef TIMED
+  return LRAMM_OK;
+}
+
+lramm_status lramm_factors(const lramm_plan* P, const void* ws, const double** Q, int64_t* ldq, const float** Bt,
+                           int64_t* ldbt) {
+  if (!P || !ws) return LRAMM_E_INVALID;
+  const uint8_t* base = reinterpret_cast<const uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
+  if (Q) *Q = reinterpret_cast<const double*>(base + P->off_Q);
+  if (ldq) *ldq = P->lp;
+  if (Bt) *Bt = reinterpret_cast<const float*>(base + P->off_Bt);
+  if (ldbt) *ldbt = P->d.k;
+  return LRAMM_OK;
+}
+
+lramm_status lramm_backward(lramm_plan* P, const float* dC, int64_t lddc, const float* A, int64_t lda,
+                            const float* B, int64_t ldb, float* dA, int64_t ldda, float* dB, int64_t lddb, void* ws,
+                            size_t ws_bytes, void* stream) {
+  if (!P || !dC) return LRAMM_E_INVALID;
+  if (!ws || ws_bytes < P->total) return LRAMM_E_WORKSPACE;
+  const lramm_desc& d = P->d;
+  if (d.a_type != LRAMM_F32 || d.b_type != LRAMM_F32) return LRAMM_E_UNSUPPORTED;
+  const int64_t m = d.m, n = d.n, k = d.k, l = P->l, lp = P->lp;
+  if (lddc < n) return LRAMM_E_SHAPE;
+  if (dA && (!B || ldb < n || ldda < k)) return LRAMM_E_SHAPE;
+  if (dB && (!A || lda < k || lddb < n)) return LRAMM_E_SHAPE;
+  hipStream_t s = (hipStream_t)stream;
+  void* W = reinterpret_cast<uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
+  const double* Q = at<double>(W, P->off_Q);
+  float* Wm = at<float>(W, P->off_W);      // l x n
+  float* Bte = at<float>(W, P->off_Bte);   // l x k
+  float* V = at<float>(W, P->off_V);       // l x k
+  // W = Q^T dC: A-operand Q^T stored K x M (Q is m x lp), B-operand dC stored K x N
+  LRAMM_TRY(launch_gemm_f32(l, n, m, Q, lp, 1, 1, dC, lddc, 1, Wm, n, s));
+  if (dB) {
+    // Bte = Q^T A (l x k), dB = Bte^T W (k x n)
+    LRAMM_TRY(launch_gemm_f32(l, k, m, Q, lp, 1, 1, A, lda, 1, Bte, k, s));
+    LRAMM_TRY(launch_gemm_f32(k, n, l, Bte, k, 1, 0, Wm, n, 1, dB, lddb, s));
+  }
+  if (dA) {
+    // V = W B^T (l x k): B-operand B^T, i.e. B stored N(=k) x K(=n) K-contiguous
+    LRAMM_TRY(launch_gemm_f32(l, k, n, Wm, n, 0, 0, B, ldb, 0, V, k, s));
+    // dA = Q V (m x k): A-operand Q stored M x K (f64), B-operand V stored K x N
+    LRAMM_TRY(launch_gemm_f32(m, k, l, Q, lp, 0, 1, V, k, 1, dA, ldda, s));
+  }
+  return LRAMM_OK;
+}
+
+lramm_status lramm_status_poll(const lramm_plan* P, const void* ws, void* stream, uint32_t* flags) {
+  if (!P || !ws) return LRAMM_E_INVALID;
+  const uint8_t* base = reinterpret_cast<const uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
+  uint32_t h = 0;
+  hipStream_t s = (hipStream_t)stream;
+  LRAMM_HIP(hipMemcpyAsync(&h, base + P->off_flags, sizeof(h), hipMemcpyDeviceToHost, s));
+  LRAMM_HIP(hipStreamSynchronize(s));
+  if (flags) *flags = h;
+  return (h & LRAMM_FLAG_NONFINITE) ? LRAMM_E_NONFINITE : LRAMM_OK;
+}
+
+// ------------------------------------------------------------ stage APIs --
+
+lramm_status lramm_quantize(int64_t rows, int64_t cols, const void* X, int64_t ldx, int32_t xtype, int32_t fmt,
+                            int32_t transpose, void* Xq, int64_t pitch, float* scales, uint32_t* flags,
+                            void* stream) {
+  if (rows < 0 || cols < 0) return LRAMM_E_SHAPE;
+  if ((rows > 0 && cols > 0) && (!X || !Xq || !scales)) return LRAMM_E_INVALID;
+  if (!valid_fmt(fmt) && fmt != LRAMM_FP8) return LRAMM_E_INVALID;
+  if (xtype != LRAMM_F32 && xtype != LRAMM_BF16 && xtype != LRAMM_F64) return LRAMM_E_INVALID;
+  if (transpose != 0 && transpose != 1) return LRAMM_E_INVALID;
+  if (ldx < cols) return LRAMM_E_SHAPE;
+  int64_t K = transpose ? rows : cols;
+  if (pitch < pitch_bytes(K, fmt) || pitch % 16 != 0) return LRAMM_E_SHAPE;
+  if ((uintptr_t)Xq % 16 != 0) return LRAMM_E_INVALID;
+  return launch_quantize(rows, cols, X, ldx, xtype, fmt, transpose, Xq, pitch, scales, flags, (hipStream_t)stream);
+}
+
+size_t lramm_gemm_nt_workspace(int64_t M, int64_t N, int64_t K, int32_t fmt) {
+  return gemm_nt_workspace(M, N, K, fmt);
+}
+
+lramm_status lramm_gemm_nt(int64_t M, int64_t N, int64_t K, int32_t fmt, const void* Lq, int64_t ldl,
+                           const float* dL, const void* Rq, int64_t ldr, const float* dR, float alpha, float beta,
+                           void* C, int64_t ldc, int32_t ctype, int32_t* acc_out, int64_t ld_acc, void* ws,
+                           size_t ws_bytes, void* stream) {
+  if (M < 0 || N < 0 || K < 0 || M > INT32_MAX || N > INT32_MAX) return LRAMM_E_SHAPE;
+  if (!valid_fmt(fmt)) return LRAMM_E_UNSUPPORTED;
+  if (ctype != LRAMM_F32 && ctype != LRAMM_BF16) return LRAMM_E_INVALID;
+  if (M == 0 || N == 0) return LRAMM_OK;
+  if (!Lq || !Rq || !C) return LRAMM_E_INVALID;
+  if (fmt != LRAMM_BF16F && (!dL || !dR)) return LRAMM_E_INVALID;
+  if (ldl < pitch_bytes(K, fmt) || ldr < pitch_bytes(K, fmt) || ldl % 16 || ldr % 16) return LRAMM_E_SHAPE;
+  if ((uintptr_t)Lq % 16 || (uintptr_t)Rq % 16) return LRAMM_E_INVALID;
+  if (ldc < N) return LRAMM_E_SHAPE;
+  if (acc_out && (fmt == LRAMM_BF16F || ld_acc < N)) return LRAMM_E_INVALID;
+  if (fmt != LRAMM_BF16F && K > qk_bound(fmt)) return LRAMM_E_OVERFLOW;
+  return launch_gemm_nt(M, N, K, fmt, Lq, ldl, dL, Rq, ldr, dR, alpha, beta, C, ldc, ctype, acc_out, ld_acc, ws,
+                        ws_bytes, (hipStream_t)stream);
+}
+
+lramm_status lramm_omega(uint64_t seed, int64_t k, int64_t l, float* OmegaT, int64_t ldo, void* stream) {
+  if (k < 0 || l < 0) return LRAMM_E_SHAPE;
+  if (k == 0 || l == 0) return LRAMM_OK;
+  if (!OmegaT) return LRAMM_E_INVALID;
+  if (ldo < k) return LRAMM_E_SHAPE;
+  return launch_omega(seed, k, l, l, OmegaT, ldo, (hipStream_t)stream);
+}
+
+size_t lramm_cholqr2_workspace(int64_t rows, int64_t l) { return cholqr2_workspace(rows, l); }
+
+lramm_status lramm_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int32_t ytype, double* Q,
+                           int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, void* stream) {
+  if (rows < 0 || l < 0) return LRAMM_E_SHAPE;
+  if (rows == 0 || l == 0) return LRAMM_OK;
+  if (!Y || !Q) return LRAMM_E_INVALID;
+  if (l > rows) return LRAMM_E_RANK;
+  if (ldy < l || ldq < round_up(l, 32)) return LRAMM_E_SHAPE;
+  if (round_up(l, 32) > 1024) return LRAMM_E_UNSUPPORTED;
+  if (ytype != LRAMM_F32 && ytype != LRAMM_F64) return LRAMM_E_UNSUPPORTED;
+  if (!ws || ws_bytes < cholqr2_workspace(rows, l)) return LRAMM_E_WORKSPACE;
+  return launch_cholqr2(rows, l, Y, ldy, ytype, Q, ldq, ws, ws_bytes, flags, (hipStream_t)stream);
+}
+
+lramm_status lramm_dense_gemm_nt(int64_t M, int64_t N, int64_t K, int32_t dtype, const void* L, int64_t ldl,
+                                 const void* R, int64_t ldr, float* C, int64_t ldc, void* stream) {
+  if (M < 0 || N < 0 || K < 0) return LRAMM_E_SHAPE;
+  if (M == 0 || N == 0) return LRAMM_OK;
+  if (!L || !R || !C) return LRAMM_E_INVALID;
+  if (K % 64 || ldl % 64 || ldr % 64 || ldl < K || ldr < K || ldc < N) return LRAMM_E_SHAPE;
+  if (dtype != LRAMM_BF16 && dtype != LRAMM_F32) return LRAMM_E_UNSUPPORTED;
+  return launch_dense_gemm_nt(M, N, K, dtype, L, ldl, R, ldr, C, ldc, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,322 @@
+// Quantisers of the LRAMM hot path (paper Sec. 3.1: symmetric linear
+// quantiser, eqs. Quantization / get_lambda / Dequantization) for gfx950.
+//
+// Two layouts:
+//   rows  -- each row of X is one vector; one wavefront owns a row, reads it
+//            once for the absmax (wavefront max reduction) and again (from
+//            L2) to write the codes; K-contiguous output.
+//   cols  -- each column of X is one vector and the codes are written
+//            transposed (cols x K).  Pass 1 reduces column maxima with
+//            atomicMax on the absmax bit patterns (order independent, hence
+//            deterministic); pass 2 quantises 64 x 64 tiles and transposes
+//            them through LDS so that both the FP reads and the code writes
+//            are coalesced; pass 3 turns the maxima into scales.
+// HBM bound: bytes = FP input read (x2 for columns) + code bytes written.
+#include "common.hpp"
+
+namespace lramm {
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+lramm_status fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return LRAMM_OK;
+  int blocks = (int)(ceil_div(n, 256) < 1024 ? ceil_div(n, 256) : 1024);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks), dim3(256), 0, s, p, v, n);
+  LRAMM_HIP(hipGetLastError());
+  return LRAMM_OK;
+}
+
+// ------------------------------------------------------------------ codes --
+
+// Encode 4 consecutive values (elements c0..c0+3, c0 % 4 == 0) of one vector
+// and store them at element offset c0 of the output row.
+template <int FMT>
+__device__ __forceinline__ void store4(uint8_t* row, int64_t c0, const float v[4], bool live[4], float lam) {
+  if constexpr (FMT == LRAMM_INT8) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int q = live[j] ? qcode(v[j], lam, 127.0f) : 0;
+      w |= ((uint32_t)(q & 0xff)) << (8 * j);
+    }
+    *reinterpret_cast<uint32_t*>(row + c0) = w;
+  } else if constexpr (FMT == LRAMM_INT4) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int q = live[j] ? qcode(v[j], lam, 7.0f) : 0;
+      w |= ((uint32_t)(q & 0xf)) << (4 * j);
+    }
+    *reinterpret_cast<uint16_t*>(row + c0 / 2) = (uint16_t)w;
+  } else if constexpr (FMT == LRAMM_FP8) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint32_t b = live[j] ? e4m3_bits(__fmul_rn(v[j], lam)) : 0u;
+      w |= b << (8 * j);
+    }
+    *reinterpret_cast<uint32_t*>(row + c0) = w;
+  } else {  // bf16
+    uint32_t lo = (live[0] ? bf16_bits(v[0]) : 0u) | ((uint32_t)(live[1] ? bf16_bits(v[1]) : 0u) << 16);
+    uint32_t hi = (live[2] ? bf16_bits(v[2]) : 0u) | ((uint32_t)(live[3] ? bf16_bits(v[3]) : 0u) << 16);
+    uint2 w;
+    w.x = lo;
+    w.y = hi;
+    *reinterpret_cast<uint2*>(row + 2 * c0) = w;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void load4(const T* row, int64_t c0, int64_t cols, bool vec, float v[4], bool live[4]) {
+  if (vec && c0 + 3 < cols) {
+    if constexpr (sizeof(T) == 4) {
+      float4 f = *reinterpret_cast<const float4*>(row + c0);
+      v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+    } else if constexpr (sizeof(T) == 2) {
+      uint2 u = *reinterpret_cast<const uint2*>(row + c0);
+      v[0] = __uint_as_float(u.x << 16);
+      v[1] = __uint_as_float(u.x & 0xffff0000u);
+      v[2] = __uint_as_float(u.y << 16);
+      v[3] = __uint_as_float(u.y & 0xffff0000u);
+    } else {
+      double4 d = *reinterpret_cast<const double4*>(row + c0);
+      v[0] = (float)d.x; v[1] = (float)d.y; v[2] = (float)d.z; v[3] = (float)d.w;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) live[j] = true;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      live[j] = (c0 + j) < cols;
+      v[j] = live[j] ? load_as_f32<T>(row + c0 + j) : 0.0f;
+    }
+  }
+}
+
+// ------------------------------------------------------------ row kernel --
+
+template <typename T, int FMT>
+__global__ __launch_bounds__(256) void quant_rows_kernel(int64_t rows, int64_t cols, const T* __restrict__ X,
+                                                         int64_t ldx, uint8_t* __restrict__ Xq, int64_t pitch,
+                                                         int64_t pelems, float* __restrict__ scales,
+                                                         uint32_t* flags, int vec) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const T* xr = X + row * ldx;
+  uint8_t* qr = Xq + row * pitch;
+  const float qmax = FMT == LRAMM_INT8 ? 127.0f : (FMT == LRAMM_INT4 ? 7.0f : 448.0f);
+
+  float lam = 1.0f;
+  if constexpr (FMT != LRAMM_BF16F) {
+    unsigned amax = 0;
+    for (int64_t c0 = (int64_t)lane * 4; c0 < cols; c0 += 256) {
+      float v[4];
+      bool live[4];
+      load4<T>(xr, c0, cols, vec != 0, v, live);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (live[j]) amax = max(amax, abs_bits(v[j]));
+    }
+    unsigned mb = wave_max_u32(amax);             // bit order == value order for |x|
+    float m = __uint_as_float(mb);
+    if (mb >= 0x7f800000u) {
+      if (lane == 0 && flags) atomicOr(flags, LRAMM_FLAG_NONFINITE);
+    }
+    QParams qp = qparams(m, qmax);
+    lam = qp.lam;
+    if (lane == 0) scales[row] = qp.d;
+  } else {
+    if (lane == 0) scales[row] = 1.0f;
+  }
+
+  for (int64_t c0 = (int64_t)lane * 4; c0 < pelems; c0 += 256) {
+    float v[4];
+    bool live[4];
+    load4<T>(xr, c0, cols, vec != 0, v, live);
+    if constexpr (FMT != LRAMM_BF16F) {
+      if (lam == 0.0f) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) live[j] = false;
+      }
+    }
+    store4<FMT>(qr, c0, v, live, lam);
+  }
+}
+
+// --------------------------------------------------------- column kernels --
+
+template <typename T>
+__global__ __launch_bounds__(256) void colmax_kernel(int64_t rows, int64_t cols, const T* __restrict__ X,
+                                                     int64_t ldx, uint32_t* __restrict__ amax_bits,
+                                                     int64_t rows_per_block) {
+  int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (col >= cols) return;
+  int64_t r0 = (int64_t)blockIdx.y * rows_per_block;
+  int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
+  unsigned m = 0;
+  for (int64_t r = r0; r < r1; ++r) m = max(m, abs_bits(load_as_f32<T>(X + r * ldx + col)));
+  if (m) atomicMax(amax_bits + col, m);
+}
+
+// Quantise a 64 (K) x 64 (cols) tile and write it transposed.
+template <typename T, int FMT>
+__global__ __launch_bounds__(256) void quant_cols_t_kernel(int64_t rows, int64_t cols, const T* __restrict__ X,
+                                                           int64_t ldx, const uint32_t* __restrict__ amax_bits,
+                                                           uint8_t* __restrict__ Xq, int64_t pitch) {
+  // codes of the tile, transposed: sT[col][k]; 2 bytes per code for bf16
+  __shared__ uint16_t sT[64][66];
+  const int t = threadIdx.x;
+  const int cl = t & 63;            // column within the tile
+  const int64_t col = (int64_t)blockIdx.x * 64 + cl;
+  const int64_t k0 = (int64_t)blockIdx.y * 64;
+  const float qmax = FMT == LRAMM_INT8 ? 127.0f : (FMT == LRAMM_INT4 ? 7.0f : 448.0f);
+  float lam = 0.0f;
+  if (col < cols) {
+    if constexpr (FMT == LRAMM_BF16F) {
+      lam = 1.0f;
+    } else {
+      lam = qparams(__uint_as_float(amax_bits[col]), qmax).lam;
+    }
+  }
+#pragma unroll 4
+  for (int i = 0; i < 16; ++i) {
+    int kr = (t >> 6) + 4 * i;       // row within the tile
+    int64_t r = k0 + kr;
+    uint16_t code = 0;
+    if (col < cols && r < rows && lam != 0.0f) {
+      float v = load_as_f32<T>(X + r * ldx + col);
+      if constexpr (FMT == LRAMM_INT8) {
+        code = (uint16_t)(qcode(v, lam, qmax) & 0xff);
+      } else if constexpr (FMT == LRAMM_INT4) {
+        code = (uint16_t)(qcode(v, lam, qmax) & 0xf);
+      } else if constexpr (FMT == LRAMM_FP8) {
+        code = (uint16_t)e4m3_bits(__fmul_rn(v, lam));
+      } else {
+        code = bf16_bits(v);
+      }
+    }
+    sT[cl][kr] = code;
+  }
+  __syncthreads();
+  // write: output row = column of X, 64 elements of K starting at k0
+  const int orow = t >> 2;           // 0..63
+  const int part = t & 3;            // quarter of the 64-element chunk
+  int64_t oc = (int64_t)blockIdx.x * 64 + orow;
+  if (oc >= cols) return;
+  uint8_t* dst = Xq + oc * pitch;
+  if constexpr (FMT == LRAMM_INT8 || FMT == LRAMM_FP8) {
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int kk = part * 16 + q * 4;
+      w[q] = (uint32_t)sT[orow][kk] | ((uint32_t)sT[orow][kk + 1] << 8) | ((uint32_t)sT[orow][kk + 2] << 16) |
+             ((uint32_t)sT[orow][kk + 3] << 24);
+    }
+    *reinterpret_cast<uint4*>(dst + k0 + part * 16) = make_uint4(w[0], w[1], w[2], w[3]);
+  } else if constexpr (FMT == LRAMM_INT4) {
+    uint32_t w[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      int kk = part * 16 + q * 8;
+      uint32_t x = 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) x |= ((uint32_t)sT[orow][kk + j]) << (4 * j);
+      w[q] = x;
+    }
+    *reinterpret_cast<uint2*>(dst + k0 / 2 + part * 8) = make_uint2(w[0], w[1]);
+  } else {
+    uint32_t w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      int kk = part * 16 + 2 * q;
+      w[q] = (uint32_t)sT[orow][kk] | ((uint32_t)sT[orow][kk + 1] << 16);
+    }
+    uint4* d4 = reinterpret_cast<uint4*>(dst + 2 * k0 + part * 32);
+    d4[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    d4[1] = make_uint4(w[4], w[5], w[6], w[7]);
+  }
+}
+
+template <int FMT>
+__global__ void col_scales_kernel(int64_t cols, float* scales, uint32_t* flags) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  if constexpr (FMT == LRAMM_BF16F) {
+    scales[c] = 1.0f;
+  } else {
+    uint32_t b = __float_as_uint(scales[c]);
+    if (b >= 0x7f800000u && flags) atomicOr(flags, LRAMM_FLAG_NONFINITE);
+    const float qmax = FMT == LRAMM_INT8 ? 127.0f : (FMT == LRAMM_INT4 ? 7.0f : 448.0f);
+    scales[c] = qparams(__uint_as_float(b), qmax).d;
+  }
+}
+
+// ---------------------------------------------------------------- launch --
+
+template <typename T, int FMT>
+static lramm_status quantize_typed(int64_t rows, int64_t cols, const T* X, int64_t ldx, int transpose, uint8_t* Xq,
+                                   int64_t pitch, float* scales, uint32_t* flags, hipStream_t s) {
+  if (!transpose) {
+    if (rows == 0) return LRAMM_OK;
+    int64_t pe = pitch_elems(pitch, FMT);
+    bool vec = ((uintptr_t)X % (4 * sizeof(T)) == 0) && (ldx % 4 == 0);
+    dim3 grid((unsigned)ceil_div(rows, 4));
+    hipLaunchKernelGGL((quant_rows_kernel<T, FMT>), grid, dim3(256), 0, s, rows, cols, X, ldx, Xq, pitch, pe, scales,
+                       flags, vec ? 1 : 0);
+    LRAMM_HIP(hipGetLastError());
+    return LRAMM_OK;
+  }
+  // column vectors, transposed output: cols x pitch
+  if (cols == 0) return LRAMM_OK;
+  uint32_t* amax = reinterpret_cast<uint32_t*>(scales);
+  LRAMM_TRY(fill_u32(amax, 0u, cols, s));
+  if (FMT != LRAMM_BF16F && rows > 0) {
+    int64_t rpb = 64;
+    dim3 g1((unsigned)ceil_div(cols, 256), (unsigned)ceil_div(rows, rpb));
+    hipLaunchKernelGGL((colmax_kernel<T>), g1, dim3(256), 0, s, rows, cols, X, ldx, amax, rpb);
+    LRAMM_HIP(hipGetLastError());
+  }
+  int64_t pe = pitch_elems(pitch, FMT);
+  dim3 g2((unsigned)ceil_div(cols, 64), (unsigned)(pe / 64));
+  hipLaunchKernelGGL((quant_cols_t_kernel<T, FMT>), g2, dim3(256), 0, s, rows, cols, X, ldx, amax, Xq, pitch);
+  LRAMM_HIP(hipGetLastError());
+  hipLaunchKernelGGL((col_scales_kernel<FMT>), dim3((unsigned)ceil_div(cols, 256)), dim3(256), 0, s, cols, scales,
+                     flags);
+  LRAMM_HIP(hipGetLastError());
+  return LRAMM_OK;
+}
+
+template <typename T>
+static lramm_status quantize_fmt(int64_t rows, int64_t cols, const T* X, int64_t ldx, int fmt, int transpose,
+                                 uint8_t* Xq, int64_t pitch, float* scales, uint32_t* flags, hipStream_t s) {
+  switch (fmt) {
+    case LRAMM_INT8: return quantize_typed<T, LRAMM_INT8>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s);
+    case LRAMM_INT4: return quantize_typed<T, LRAMM_INT4>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s);
+    case LRAMM_FP8: return quantize_typed<T, LRAMM_FP8>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s);
+    case LRAMM_BF16F: return quantize_typed<T, LRAMM_BF16F>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s);
+    default: return LRAMM_E_INVALID;
+  }
+}
+
+lramm_status launch_quantize(int64_t rows, int64_t cols, const void* X, int64_t ldx, int xtype, int fmt,
+                             int transpose, void* Xq, int64_t pitch, float* scales, uint32_t* flags,
+                             hipStream_t s) {
+  uint8_t* q = reinterpret_cast<uint8_t*>(Xq);
+  switch (xtype) {
+    case LRAMM_F32:
+      return quantize_fmt<float>(rows, cols, (const float*)X, ldx, fmt, transpose, q, pitch, scales, flags, s);
+    case LRAMM_BF16:
+      return quantize_fmt<uint16_t>(rows, cols, (const uint16_t*)X, ldx, fmt, transpose, q, pitch, scales, flags, s);
+    case LRAMM_F64:
+      return quantize_fmt<double>(rows, cols, (const double*)X, ldx, fmt, transpose, q, pitch, scales, flags, s);
+    default:
+      return LRAMM_E_INVALID;
+  }
+}
+
+}  // namespace lramm

@@ -1,0 +1,97 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+symbol include/lramm.h declares, and host-checkable argument errors return
+the documented status codes without launching anything."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lramm.h")
+LIB = os.path.join(ROOT, "paper_2405_16917_amd", "liblramm.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"LRAMM_API\s+[\w\s\*]*?\b(lramm_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        import __graft_entry__
+        __graft_entry__.build()
+    import paper_2405_16917_amd._lib as L
+    return L.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(lib, n), n
+    import paper_2405_16917_amd._lib as L
+    assert sorted(L.EXPORTS) == names
+
+
+def test_status_strings_and_pitch(lib):
+    assert lib.lramm_status_string(0) == b"ok"
+    assert lib.lramm_status_string(3).startswith(b"sketch width")
+    assert lib.lramm_pitch(272, 0) == 320      # int8: 272 bytes -> 64-byte multiple
+    assert lib.lramm_pitch(272, 1) == 192      # int4: 136 bytes -> 192
+    assert lib.lramm_pitch(100, 3) == 256      # bf16: 200 bytes -> 128-byte multiple
+    assert lib.lramm_pitch(1, 0) == 64
+
+
+def _desc(L, **kw):
+    d = L.Desc()
+    d.m, d.n, d.k, d.r, d.p, d.q = 512, 512, 512, 64, 10, 1
+    d.fmt_sketch = d.fmt_proj = d.fmt_g1 = d.fmt_g2 = L.INT8
+    d.a_type = d.b_type = d.c_type = L.F32
+    d.seed, d.alpha, d.beta, d.flags = 0, 1.0, 0.0, 0
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+def _create(lib, d):
+    h = ctypes.c_void_p()
+    code = lib.lramm_plan_create(ctypes.byref(d), ctypes.byref(h))
+    return code, h
+
+
+def test_plan_validation(lib):
+    import paper_2405_16917_amd._lib as L
+    code, h = _create(lib, _desc(L))
+    assert code == L.OK
+    sz = ctypes.c_size_t()
+    assert lib.lramm_workspace_bytes(h, ctypes.byref(sz)) == L.OK and sz.value > 512 * 512
+    lib.lramm_plan_destroy(h)
+    assert _create(lib, _desc(L, r=600, p=0))[0] == L.E_RANK          # l > min(m, k)
+    assert _create(lib, _desc(L, r=0, p=0))[0] == L.E_RANK            # l < 1
+    assert _create(lib, _desc(L, m=0))[0] == L.E_SHAPE
+    assert _create(lib, _desc(L, fmt_g2=7))[0] == L.E_UNSUPPORTED
+    assert _create(lib, _desc(L, flags=1))[0] == L.E_INVALID
+    assert _create(lib, _desc(L, k=200000))[0] == L.E_OVERFLOW        # K * 127^2 > 2^31
+    assert lib.lramm_plan_create(None, None) == L.E_INVALID
+
+
+def test_stage_argument_errors(lib):
+    import paper_2405_16917_amd._lib as L
+    # null device pointers / bad shapes are caught on the host
+    assert lib.lramm_quantize(4, 4, None, 4, L.F32, L.INT8, 0, None, 64, None, None, None) == L.E_INVALID
+    assert lib.lramm_quantize(4, 4, 1, 3, L.F32, L.INT8, 0, 16, 64, 1, None, None) == L.E_SHAPE
+    assert lib.lramm_quantize(4, 4, 1, 4, L.F32, L.INT8, 0, 16, 32, 1, None, None) == L.E_SHAPE
+    assert lib.lramm_gemm_nt(4, 4, 64, 9, 16, 64, 1, 16, 64, 1, 1.0, 0.0, 1, 4, 0, None, 0, None, 0,
+                             None) == L.E_UNSUPPORTED
+    assert lib.lramm_gemm_nt(4, 4, 64, L.INT8, 16, 32, 1, 16, 64, 1, 1.0, 0.0, 1, 4, 0, None, 0, None, 0,
+                             None) == L.E_SHAPE
+    assert lib.lramm_gemm_nt(4, 4, 200000, L.INT8, 16, 200064, 1, 16, 200064, 1, 1.0, 0.0, 1, 4, 0, None, 0,
+                             None, 0, None) == L.E_OVERFLOW
+    assert lib.lramm_cholqr2(10, 20, 1, 20, L.F32, 1, 32, 1, 1 << 30, None, None) == L.E_RANK
+    assert lib.lramm_cholqr2(100, 20, 1, 20, L.F32, 1, 20, 1, 1 << 30, None, None) == L.E_SHAPE
+    assert lib.lramm_cholqr2(100, 20, 1, 20, L.F32, 1, 32, 1, 10, None, None) == L.E_WORKSPACE
+    assert lib.lramm_dense_gemm_nt(64, 64, 60, L.BF16, 1, 64, 1, 64, 1, 64, None) == L.E_SHAPE
+    assert lib.lramm_omega(0, 10, 3, None, 10, None) == L.E_INVALID

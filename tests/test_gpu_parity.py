@@ -1,0 +1,373 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Integer work (quantiser codes, int32 accumulators, dequantised epilogue) is
+compared bit for bit; the end-to-end LRAMM output within relative Frobenius
+1e-5 of the oracle's own output at the same bit widths; Q within
+1e-13 * cond(Y) of the oracle's Householder Q.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from oracle import lramm as OL  # noqa: E402
+from oracle import philox as OP  # noqa: E402
+from oracle import qgemm as OG  # noqa: E402
+from oracle import quant as OQ  # noqa: E402
+from oracle.qr import householder_qr  # noqa: E402
+
+DEV = "cuda"
+
+
+def g(x, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV, dtype)
+
+
+def f32(x):
+    return np.asarray(x, np.float32).astype(np.float64)
+
+
+def bf16_round(x):
+    return synth.to_dtype(x, "bf16").astype(np.float64)
+
+
+def codes_from(Xq, fmt, K):
+    q = Xq.cpu().numpy()
+    if fmt == "int8":
+        return q.view(np.int8)[:, :K].astype(np.int64), q
+    if fmt == "int4":
+        return OQ.unpack_int4(q, K), q
+    if fmt == "bf16":
+        u = q.view(np.uint16)[:, :K].astype(np.uint32) << 16
+        return u.view(np.float32).astype(np.float64), q
+    raise ValueError(fmt)
+
+
+def pad_bytes(q, fmt, K):
+    used = {"int8": K, "int4": (K + 1) // 2, "bf16": 2 * K}[fmt]
+    return q[:, used:]
+
+
+# --------------------------------------------------------------- runtime --
+
+def test_single_hip_runtime_and_library_loaded(lib):
+    lib.lramm_init()
+    maps = open("/proc/self/maps").read()
+    hips = {l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l}
+    assert len(hips) == 1, hips
+    assert lib.LIB_PATH in maps
+
+
+# ------------------------------------------------------------- quantiser --
+
+@pytest.mark.parametrize("fmt", ["int8", "int4", "bf16"])
+@pytest.mark.parametrize("shape", [(1, 1), (37, 50), (130, 257), (512, 512), (64, 4099)])
+def test_quantize_rows_bit_exact(lib, fmt, shape):
+    rng = np.random.default_rng(shape[0] * 1000 + shape[1] + len(fmt))
+    X = f32(rng.standard_normal(shape) * np.exp(rng.uniform(-8, 8, (shape[0], 1))))
+    X[0, :] = 0.0                                   # all-zero vector -> codes 0, d 0
+    Xq, s = lib.lramm_quantize(g(X), fmt, transpose=False)
+    torch.cuda.synchronize()
+    codes, raw = codes_from(Xq, fmt, shape[1])
+    ref_c, ref_d = OQ.quantize_rows(X, fmt)
+    assert np.array_equal(codes, ref_c)
+    assert np.array_equal(s.cpu().numpy().astype(np.float64), ref_d)
+    assert not pad_bytes(raw, fmt, shape[1]).any()
+
+
+@pytest.mark.parametrize("fmt", ["int8", "int4", "bf16"])
+@pytest.mark.parametrize("shape", [(1, 1), (50, 37), (257, 130), (512, 512), (4099, 70)])
+def test_quantize_cols_bit_exact(lib, fmt, shape):
+    rng = np.random.default_rng(shape[0] * 1000 + shape[1] + len(fmt) + 1)
+    X = f32(rng.standard_normal(shape) * np.exp(rng.uniform(-8, 8, (1, shape[1]))))
+    X[:, 0] = 0.0
+    Xq, s = lib.lramm_quantize(g(X), fmt, transpose=True)
+    torch.cuda.synchronize()
+    codes, raw = codes_from(Xq, fmt, shape[0])
+    ref_c, ref_d = OQ.quantize_cols(X, fmt)
+    assert np.array_equal(codes, ref_c.T)
+    assert np.array_equal(s.cpu().numpy().astype(np.float64), ref_d)
+    assert not pad_bytes(raw, fmt, shape[0]).any()
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_quantize_bf16_and_f64_inputs(lib, transpose):
+    rng = np.random.default_rng(5)
+    Xb = bf16_round(rng.standard_normal((70, 90)))
+    Xq, s = lib.lramm_quantize(g(Xb, torch.bfloat16), "int8", transpose=transpose)
+    ref = OQ.quantize_cols(Xb, "int8") if transpose else OQ.quantize_rows(Xb, "int8")
+    codes, _ = codes_from(Xq, "int8", 70 if transpose else 90)
+    assert np.array_equal(codes, ref[0].T if transpose else ref[0])
+    assert np.array_equal(s.cpu().numpy().astype(np.float64), ref[1])
+    Xd = rng.standard_normal((70, 90))               # FP64 input is rounded once to binary32
+    Xq, s = lib.lramm_quantize(g(Xd, torch.float64), "int8", transpose=transpose)
+    ref = OQ.quantize_cols(f32(Xd), "int8") if transpose else OQ.quantize_rows(f32(Xd), "int8")
+    codes, _ = codes_from(Xq, "int8", 70 if transpose else 90)
+    assert np.array_equal(codes, ref[0].T if transpose else ref[0])
+
+
+def test_quantize_flags_nonfinite(lib):
+    X = torch.ones((8, 8), device=DEV)
+    X[3, 4] = float("nan")
+    flags = torch.zeros(1, dtype=torch.int32, device=DEV)
+    lib.lramm_quantize(X, "int8", transpose=False, flags=flags)
+    torch.cuda.synchronize()
+    assert int(flags.item()) & lib.FLAG_NONFINITE
+    flags.zero_()
+    X[3, 4] = float("inf")
+    lib.lramm_quantize(X, "int8", transpose=True, flags=flags)
+    torch.cuda.synchronize()
+    assert int(flags.item()) & lib.FLAG_NONFINITE
+
+
+# ------------------------------------------------------------------ GEMM --
+
+def _int_operands(rng, M, N, K, qmax):
+    L = rng.integers(-qmax, qmax + 1, (M, K))
+    R = rng.integers(-qmax, qmax + 1, (N, K))
+    return L, R
+
+
+def _pack(codes, fmt, K):
+    pitch = {"int8": (K + 63) // 64 * 64, "int4": ((K + 1) // 2 + 63) // 64 * 64}[fmt]
+    if fmt == "int8":
+        buf = np.zeros((codes.shape[0], pitch), np.int8)
+        buf[:, :K] = codes
+        return buf.view(np.uint8)
+    p = OQ.pack_int4(codes)
+    buf = np.zeros((codes.shape[0], pitch), np.uint8)
+    buf[:, :p.shape[1]] = p
+    return buf
+
+
+@pytest.mark.parametrize("fmt", ["int8", "int4"])
+@pytest.mark.parametrize("MNK", [(1, 1, 1), (37, 53, 100), (129, 65, 300), (64, 64, 64), (256, 320, 4096),
+                                 (300, 70, 8192), (512, 512, 512)])
+def test_gemm_int_bit_exact(lib, fmt, MNK):
+    M, N, K = MNK
+    rng = np.random.default_rng(M * 7 + N * 11 + K)
+    qmax = 127 if fmt == "int8" else 7
+    L, R = _int_operands(rng, M, N, K, qmax)
+    dL = f32(rng.uniform(1e-3, 1e-1, M))
+    dR = f32(rng.uniform(1e-3, 1e-1, N))
+    Lq, Rq = g(_pack(L, fmt, K), torch.uint8), g(_pack(R, fmt, K), torch.uint8)
+    acc = torch.empty((M, N), dtype=torch.int32, device=DEV)
+    ws = torch.empty(max(1, lib.lramm_gemm_nt_workspace(M, N, K, fmt)), dtype=torch.uint8, device=DEV)
+    C = lib.lramm_gemm_nt(M, N, K, fmt, Lq, g(dL), Rq, g(dR), acc_out=acc, ws=ws)
+    ref_acc = OG.int_gemm(L, R.T)
+    assert np.array_equal(acc.cpu().numpy().astype(np.int64), ref_acc)
+    assert np.array_equal(C.cpu().numpy().astype(np.float64), OG.epilogue(ref_acc, dL, dR))
+    # without split-K workspace: same bits
+    C2 = lib.lramm_gemm_nt(M, N, K, fmt, Lq, g(dL), Rq, g(dR))
+    assert torch.equal(C, C2)
+
+
+def test_gemm_alpha_beta_and_bf16_out(lib):
+    rng = np.random.default_rng(3)
+    M, N, K = 200, 150, 333
+    L, R = _int_operands(rng, M, N, K, 127)
+    dL = f32(rng.uniform(1e-3, 1e-1, M))
+    dR = f32(rng.uniform(1e-3, 1e-1, N))
+    Cin = f32(rng.standard_normal((M, N)))
+    Lq, Rq = g(_pack(L, "int8", K), torch.uint8), g(_pack(R, "int8", K), torch.uint8)
+    C = g(Cin)
+    lib.lramm_gemm_nt(M, N, K, "int8", Lq, g(dL), Rq, g(dR), alpha=0.5, beta=-1.5, C=C)
+    ref = OG.epilogue(OG.int_gemm(L, R.T), dL, dR, 0.5, -1.5, Cin)
+    assert np.array_equal(C.cpu().numpy().astype(np.float64), ref)
+    Cb = lib.lramm_gemm_nt(M, N, K, "int8", Lq, g(dL), Rq, g(dR), ctype=torch.bfloat16)
+    refb = bf16_round(OG.epilogue(OG.int_gemm(L, R.T), dL, dR))
+    assert np.array_equal(Cb.float().cpu().numpy().astype(np.float64), refb)
+
+
+@pytest.mark.parametrize("MNK", [(64, 64, 64), (100, 37, 257), (512, 512, 2048)])
+def test_gemm_bf16_operands(lib, MNK):
+    M, N, K = MNK
+    rng = np.random.default_rng(K)
+    L = bf16_round(rng.standard_normal((M, K)))
+    R = bf16_round(rng.standard_normal((N, K)))
+    Lq, dL = lib.lramm_quantize(g(L), "bf16")
+    Rq, dR = lib.lramm_quantize(g(R), "bf16")
+    C = lib.lramm_gemm_nt(M, N, K, "bf16", Lq, dL, Rq, dR).double().cpu().numpy()
+    ref = L @ R.T
+    assert OL.rel_fro(C, ref) <= 1e-6 * np.sqrt(K / 64) + 1e-7
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32])
+def test_dense_comparator(lib, dtype):
+    M, N, K = 256, 192, 512
+    rng = np.random.default_rng(11)
+    L = rng.standard_normal((M, K))
+    R = rng.standard_normal((N, K))
+    if dtype == torch.bfloat16:
+        L, R = bf16_round(L), bf16_round(R)
+    else:
+        L, R = f32(L), f32(R)
+    C = lib.lramm_dense_gemm_nt(g(L, dtype), g(R, dtype)).double().cpu().numpy()
+    assert OL.rel_fro(C, L @ R.T) <= 1e-5
+
+
+# ------------------------------------------------------------------ Omega --
+
+@pytest.mark.parametrize("kl", [(512, 74), (1001, 37), (4096, 272)])
+def test_omega_matches_oracle_philox(lib, kl):
+    k, l = kl
+    OmT = lib.lramm_omega(12345, k, l).cpu().numpy().astype(np.float64)
+    ref = OP.gaussian_omega(12345, k, l)
+    diff = OmT.T != ref
+    # Box-Muller in FP64 on both sides, rounded once: a mismatch needs an FP64
+    # result within a few ulps of a binary32 rounding boundary
+    assert diff.sum() <= max(2, ref.size // 10**6)
+    assert np.max(np.abs(OmT.T - ref)) <= 1e-6 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------- CholQR2 --
+
+@pytest.mark.parametrize("case", [(300, 40, 1.0), (512, 74, 1e3), (1000, 96, 1e6), (2048, 272, 30.0),
+                                  (700, 33, 10.0)])
+def test_cholqr2_matches_householder(lib, case):
+    rows, l, cond = case
+    rng = np.random.default_rng(rows + l)
+    U, _ = np.linalg.qr(rng.standard_normal((rows, l)))
+    V, _ = np.linalg.qr(rng.standard_normal((l, l)))
+    Y = f32((U * np.logspace(0, -np.log10(cond), l)) @ V.T)
+    flags = torch.zeros(1, dtype=torch.int32, device=DEV)
+    Q = lib.lramm_cholqr2(g(Y), l, flags=flags)
+    torch.cuda.synchronize()
+    Qg = Q.cpu().numpy()
+    assert not Qg[:, l:].any()
+    Qg = Qg[:, :l]
+    Qh, _ = householder_qr(Y)
+    assert np.max(np.abs(Qg.T @ Qg - np.eye(l))) <= 1e-13
+    assert np.max(np.abs(Qg - Qh)) <= 2e-14 * cond * np.sqrt(l)
+    assert int(flags.item()) == 0
+
+
+def test_cholqr2_f64_input_and_rank_deficiency(lib):
+    rng = np.random.default_rng(9)
+    Y = rng.standard_normal((400, 50))
+    Y[:, 7] = 0.0
+    flags = torch.zeros(1, dtype=torch.int32, device=DEV)
+    Q = lib.lramm_cholqr2(g(Y, torch.float64), 50, flags=flags)
+    torch.cuda.synchronize()
+    Qg = Q.cpu().numpy()[:, :50]
+    assert int(flags.item()) & lib.FLAG_BREAKDOWN
+    assert not Qg[:, 7].any()
+    keep = [j for j in range(50) if j != 7]
+    assert np.max(np.abs(Qg[:, keep].T @ Qg[:, keep] - np.eye(49))) <= 1e-13
+    # span is kept: Y = Q Q^T Y
+    assert np.linalg.norm(Y - Qg @ (Qg.T @ Y)) <= 1e-12 * np.linalg.norm(Y)
+
+
+# ------------------------------------------------------------- end to end --
+
+def _run_forward(lib, A, B, r, p, q, fmt, omega=None, seed=0, alpha=1.0, beta=0.0, Cin=None,
+                 a_type=torch.float32, c_type=torch.float32):
+    m, k = A.shape
+    n = B.shape[1]
+    plan = lib.LrammPlan(m, n, k, r, p, q, fmt, a_type, a_type, c_type, seed, alpha, beta)
+    ws = plan.workspace()
+    C = g(Cin, c_type) if Cin is not None else None
+    C = plan.forward(g(A, a_type), g(B, a_type), ws, C=C, omega=None if omega is None else g(omega))
+    flags = plan.status(ws)
+    return C.double().cpu().numpy(), plan, ws, flags
+
+
+CASES = [
+    # m, k, n, r, p, q, tau, fmt
+    (512, 512, 512, 64, 10, 1, 32.0, ("int8",) * 4),     # the small plain-LRAMM configuration
+    (512, 512, 512, 64, 10, 0, 32.0, ("int8",) * 4),
+    (512, 512, 512, 64, 10, 2, 32.0, ("int8",) * 4),
+    (300, 257, 190, 20, 5, 1, 12.0, ("int8",) * 4),      # ragged
+    (640, 384, 512, 100, 12, 1, 40.0, ("int8", "int8", "int4", "int4")),
+    (512, 512, 512, 64, 10, 1, 32.0, ("int4",) * 4),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_lramm_forward_matches_oracle(lib, case):
+    m, k, n, r, p, q, tau, fmt = case
+    A, s = synth.lowrank(m, k, synth.spectrum("exp", min(m, k), tau), 0)
+    B = synth.gaussian(k, n, 100)
+    om = synth.omega(k, r + p, 1)
+    C, plan, ws, flags = _run_forward(lib, A, B, r, p, q, fmt, omega=om)
+    ref = OL.lramm_forward(A.astype(np.float64), B.astype(np.float64), r, p, q, fmt, omega=om.astype(np.float64))
+    err = OL.rel_fro(C, ref["C"])
+    assert err <= 1e-5, err
+    assert flags == 0
+    Qg, Btg = plan.factors(ws)
+    Qg = Qg.cpu().numpy()
+    assert np.max(np.abs(Qg - ref["Q"])) <= 1e-11
+    assert OL.rel_fro(Btg.cpu().numpy(), ref["Bt"]) <= 1e-5
+
+
+def test_lramm_seeded_omega_and_alpha_beta(lib):
+    m = k = n = 384
+    A, _ = synth.lowrank(m, k, synth.spectrum("exp", 384, 24.0), 3)
+    B = synth.gaussian(k, n, 103)
+    Cin = synth.gaussian(m, n, 7)
+    C, _, _, _ = _run_forward(lib, A, B, 48, 8, 1, ("int8",) * 4, seed=77, alpha=0.75, beta=0.5, Cin=Cin)
+    ref = OL.lramm_forward(A.astype(np.float64), B.astype(np.float64), 48, 8, 1, seed=77, alpha=0.75, beta=0.5,
+                           Cin=Cin.astype(np.float64))
+    assert OL.rel_fro(C, ref["C"]) <= 1e-5
+
+
+def test_lramm_bf16_io(lib):
+    m = k = n = 512
+    A, _ = synth.lowrank(m, k, synth.spectrum("exp", 512, 32.0), 0, dtype="bf16")
+    B = synth.gaussian(k, n, 100, dtype="bf16")
+    om = synth.omega(k, 74, 1)
+    C, _, _, _ = _run_forward(lib, A, B, 64, 10, 1, ("int8",) * 4, omega=om, a_type=torch.bfloat16,
+                              c_type=torch.bfloat16)
+    ref = OL.lramm_forward(A.astype(np.float64), B.astype(np.float64), 64, 10, 1, omega=om.astype(np.float64))
+    assert OL.rel_fro(C, bf16_round(ref["C"])) <= 1e-5
+
+
+def test_lramm_deterministic(lib):
+    m = k = n = 512
+    A, _ = synth.lowrank(m, k, synth.spectrum("exp", 512, 32.0), 0)
+    B = synth.gaussian(k, n, 100)
+    C1, _, _, _ = _run_forward(lib, A, B, 64, 10, 1, ("int8",) * 4, seed=5)
+    C2, _, _, _ = _run_forward(lib, A, B, 64, 10, 1, ("int8",) * 4, seed=5)
+    assert np.array_equal(C1, C2)
+
+
+def test_lramm_nonfinite_input_flag(lib):
+    A = np.ones((128, 128), np.float32)
+    A[5, 6] = np.nan
+    B = np.ones((128, 64), np.float32)
+    plan = lib.LrammPlan(128, 64, 128, 16, 4, 0)
+    ws = plan.workspace()
+    plan.forward(g(A), g(B), ws)
+    with pytest.raises(lib.LrammError):
+        plan.status(ws)
+
+
+# ---------------------------------------------------------------- backward --
+
+def test_backward_matches_exact_gradient(lib):
+    m, k, n = 384, 320, 256
+    A, _ = synth.lowrank(m, k, synth.spectrum("exp", 320, 24.0), 0)
+    B = synth.gaussian(k, n, 100)
+    om = synth.omega(k, 48, 1)
+    At = g(A).requires_grad_(True)
+    Bt = g(B).requires_grad_(True)
+    cfg = lib.LRAMMConfig(r=40, p=8, q=1, omega=g(om))
+    C = lib.LRAMMFunction.apply(At, Bt, cfg)
+    dC = synth.gaussian(m, n, 9)
+    C.backward(g(dC))
+    ref = OL.lramm_forward(A.astype(np.float64), B.astype(np.float64), 40, 8, 1, omega=om.astype(np.float64))
+    dA, dB = OL.lramm_backward(ref["Q"], A, B, dC)
+    assert OL.rel_fro(At.grad.double().cpu().numpy(), dA) <= 1e-5
+    assert OL.rel_fro(Bt.grad.double().cpu().numpy(), dB) <= 1e-5
+    # recompute mode gives identical gradients
+    At2 = g(A).requires_grad_(True)
+    Bt2 = g(B).requires_grad_(True)
+    cfg2 = lib.LRAMMConfig(r=40, p=8, q=1, omega=g(om), recompute=True)
+    lib.LRAMMFunction.apply(At2, Bt2, cfg2).backward(g(dC))
+    assert torch.equal(At.grad, At2.grad) and torch.equal(Bt.grad, Bt2.grad)
