@@ -29,8 +29,10 @@ EXPORTS = (
     "lramm_workspace_bytes", "lramm_forward", "lramm_factors", "lramm_backward",
     "lramm_status_poll", "lramm_quantize", "lramm_pitch", "lramm_gemm_nt",
     "lramm_gemm_nt_workspace", "lramm_omega", "lramm_cholqr2",
-    "lramm_cholqr2_workspace", "lramm_dense_gemm_nt",
+    "lramm_cholqr2_workspace", "lramm_dense_gemm_nt", "lramm_plan_set_timing", "lramm_stage_times",
+    "lramm_stage_name",
 )
+NSTAGES = 17
 
 
 class LrammError(RuntimeError):
@@ -89,6 +91,9 @@ def load(path=LIB_PATH):
         "lramm_cholqr2": ([I64, I64, P, I64, I32, P, I64, P, SZ, P, P], I32),
         "lramm_cholqr2_workspace": ([I64, I64], SZ),
         "lramm_dense_gemm_nt": ([I64, I64, I64, I32, P, I64, P, I64, P, I64, P], I32),
+        "lramm_plan_set_timing": ([P, I32], I32),
+        "lramm_stage_times": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], I32),
+        "lramm_stage_name": ([I32], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -272,6 +277,18 @@ class LrammPlan:
                                      _ptr(dB) if need_dB else None, dB.stride(0) if need_dB else 0, _ptr(ws),
                                      ws.numel(), _stream()), "lramm_backward")
         return dA, dB
+
+    def set_timing(self, enable=True):
+        _check(load().lramm_plan_set_timing(self._h, 1 if enable else 0), "lramm_plan_set_timing")
+
+    def stage_times(self):
+        """{stage name: (total ms, launches)} recorded since the last call
+        (synchronises the recorded events)."""
+        lib = load()
+        ms = (ctypes.c_double * NSTAGES)()
+        cnt = (I64 * NSTAGES)()
+        _check(lib.lramm_stage_times(self._h, ms, cnt), "lramm_stage_times")
+        return {lib.lramm_stage_name(i).decode(): (ms[i], int(cnt[i])) for i in range(NSTAGES)}
 
     def status(self, ws):
         """Synchronise and return the device status flags (raises on NaN/Inf)."""
