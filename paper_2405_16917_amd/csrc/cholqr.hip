@@ -5,7 +5,7 @@
 //   pass(X):  G = X^T X (FP64)        Gram, split over row chunks, summed in
 //                                      a fixed order (deterministic)
 //             G = L L^T               blocked right-looking Cholesky, 32 x 32
-//                                      panels, one launch per panel
+//                                      tiles, one launch per panel
 //             Q = X L^-T              row-block forward substitution
 //   Q1 = pass(Y); Q = pass(Q1)        (the second pass restores
 //                                      orthogonality lost to cond(Y)^2 u)
@@ -94,8 +94,10 @@ __global__ __launch_bounds__(256) void gram_kernel(int64_t rows, int lw, int nco
 
 // G (lower tiles) = sum over chunks in order; diag0 = diag(G).
 __global__ __launch_bounds__(256) void gram_reduce_kernel(int lw, int nchunks, const double* __restrict__ part,
-                                                          double* __restrict__ G, double* __restrict__ diag0) {
+                                                          double* __restrict__ G, double* __restrict__ diag0,
+                                                          uint32_t* gate) {
   int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e == 0) *gate = 0u;   // second-pass gate of this orthonormalisation
   if (e >= (int64_t)lw * lw) return;
   int i = (int)(e / lw), j = (int)(e % lw);
   if ((i / NB) < (j / NB)) return;   // upper tiles are never read
@@ -106,132 +108,378 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int lw, int nchunks, c
 }
 
 // -------------------------------------------------------------- Cholesky --
-// Factor the 32 x 32 diagonal block held in sD (lower part) in place and
-// build its inverse in sI.  256 threads.
-__device__ void factor_diag(double (*sD)[NB + 1], double (*sI)[NB + 1], double* sPiv, const double* diag0, int col0,
-                            int l_true, double tol, uint32_t* flags, bool report) {
-  const int tid = threadIdx.x;
+// Blocked right-looking Cholesky with 32 x 32 tiles.  Launch p updates every
+// trailing tile (i, j), p < j <= i, with the panel p; the workgroup that
+// finishes tile (p+1, p+1) then factors it, so the next launch finds L and
+// its inverse for that diagonal block ready.  A diagonal block is factored by
+// one wavefront with rows in registers (lane i owns row i) and cross-lane
+// broadcasts by readlane, without barriers.
+
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Order LDS accesses of one wavefront (compiler barrier + LDS wait).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// One wavefront factors the 32 x 32 block S (LDS, pitch NB + 1) into L
+// (written to Lout, row pitch ldl, zeros above the diagonal) and writes the
+// inverse of L to Iout (32 x 32, row-major).  Lane i keeps row i in
+// registers; after each column is scaled it is published in LDS (scratch)
+// and read back by every lane as uniform-address (broadcast) loads.
+// scratch: NB * (NB + 1) + 2 NB doubles of LDS private to this wavefront.
+__device__ __attribute__((always_inline)) inline void factor_block_wave(const double* S, double* scratch,
+                                                                        const double* diag0, int col0, int l_true,
+                                                                        double tol, uint32_t* flags, double* Lout,
+                                                                        int64_t ldl, double* Iout) {
+  const int lane = threadIdx.x & 63;
+  const int row = lane & 31;
+  double* Ls = scratch;                      // L, pitch NB + 1
+  double* colbuf = scratch + NB * (NB + 1);  // two column slots (double-buffered)
+  // pivot thresholds, loaded once (lane j: column col0 + j; negative = padding column)
+  const double thr = col0 + row < l_true ? tol * diag0[col0 + row] : -1.0;
+  double a[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) a[k] = S[row * (NB + 1) + k];
+  double inv[NB];
+  uint32_t bad = 0;
+#pragma unroll
   for (int j = 0; j < NB; ++j) {
-    if (tid == 0) {
-      double a = sD[j][j];
-      int col = col0 + j;
-      double piv = 0.0;
-      if (col < l_true) {
-        double g0 = diag0[col];
-        if (a > tol * g0 && a > 0.0) {
-          piv = sqrt(a);
-        } else if (report && flags) {
-          atomicOr(flags, (a < -tol * g0 || a != a) ? (LRAMM_FLAG_BREAKDOWN | LRAMM_FLAG_SQRTNEG)
-                                                    : LRAMM_FLAG_BREAKDOWN);
-        }
+    const double d = lane_bcast(a[j], j);
+    const double tj = lane_bcast(thr, j);
+    double piv = 0.0, iv = 0.0;
+    if (tj >= 0.0) {
+      if (d > tj && d > 0.0) {
+        // 1/sqrt(d): hardware estimate refined by two Newton steps (quadratic
+        // convergence from ~2^-23 to full precision); piv = d / sqrt(d)
+        double y = __builtin_amdgcn_rsq(d);
+        y = y * fma(-0.5 * d * y, y, 1.5);
+        y = y * fma(-0.5 * d * y, y, 1.5);
+        iv = y;
+        piv = d * y;
+      } else {
+        bad |= (d < -tj || d != d) ? (LRAMM_FLAG_BREAKDOWN | LRAMM_FLAG_SQRTNEG) : LRAMM_FLAG_BREAKDOWN;
       }
-      *sPiv = piv;
     }
-    __syncthreads();
-    const double piv = *sPiv;
-    const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
-    if (tid > j && tid < NB) sD[tid][j] *= inv;
-    if (tid == j) sD[j][j] = piv;
-    __syncthreads();
-    for (int e = tid; e < NB * NB; e += 256) {
-      int i = e / NB, c = e % NB;
-      if (c > j && i >= c) sD[i][c] -= sD[i][j] * sD[c][j];
-    }
-    __syncthreads();
+    inv[j] = iv;
+    a[j] = row > j ? a[j] * iv : (row == j ? piv : a[j]);
+    double* col = colbuf + (j & 1) * NB;
+    if (lane < NB) col[lane] = a[j];
+    wave_lds_sync();
+#pragma unroll
+    for (int k = j + 1; k < NB; ++k) a[k] = fma(-a[j], col[k], a[k]);
   }
-  // inverse of the lower-triangular factor, one column per thread
-  if (tid < NB) {
-    const int c = tid;
-    for (int i = 0; i < NB; ++i) {
-      double v = 0.0;
-      if (i >= c) {
-        double s = (i == c) ? 1.0 : 0.0;
-        for (int t2 = c; t2 < i; ++t2) s -= sD[i][t2] * sI[t2][c];
-        double d = sD[i][i];
-        v = d > 0.0 ? s / d : 0.0;
-      }
-      sI[i][c] = v;
+  if (lane < NB) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const double v = k <= row ? a[k] : 0.0;
+      Ls[row * (NB + 1) + k] = v;
+      Lout[(int64_t)row * ldl + k] = v;
     }
   }
-  __syncthreads();
+  wave_lds_sync();
+  // inverse, one column per lane: X[i][c] = (delta_ic - sum_t L[i][t] X[t][c]) / L[i][i],
+  // the sum split over four independent partial sums
+  double x[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    double p0 = row == i ? 1.0 : 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+#pragma unroll
+    for (int t = 0; t < i; t += 4) {
+      p0 = fma(-Ls[i * (NB + 1) + t], x[t], p0);
+      if (t + 1 < i) p1 = fma(-Ls[i * (NB + 1) + t + 1], x[t + 1], p1);
+      if (t + 2 < i) p2 = fma(-Ls[i * (NB + 1) + t + 2], x[t + 2], p2);
+      if (t + 3 < i) p3 = fma(-Ls[i * (NB + 1) + t + 3], x[t + 3], p3);
+    }
+    x[i] = ((p0 + p1) + (p2 + p3)) * inv[i];
+  }
+  if (lane < NB) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) Iout[i * NB + row] = x[i];
+  }
+  if (lane == 0 && bad && flags) atomicOr(flags, bad);
 }
 
-// dst (32 x 32, LDS) = src (32 x 32, global rows of ld) * Inv^T
-__device__ __forceinline__ void times_inv_t(double (*dst)[NB + 1], const double* src, int64_t ld,
-                                            double (*sI)[NB + 1], double (*tmp)[NB + 1]) {
-  const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += 256) tmp[e / NB][e % NB] = src[(int64_t)(e / NB) * ld + (e % NB)];
-  __syncthreads();
-  for (int e = tid; e < NB * NB; e += 256) {
-    int i = e / NB, c = e % NB;
-    double s = 0.0;
-    for (int t = 0; t <= c; ++t) s += tmp[i][t] * sI[c][t];   // Inv is lower: Inv[c][t] = 0 for t > c
-    dst[i][c] = s;
-  }
-  __syncthreads();
-}
-
-// One panel step p of the right-looking blocked Cholesky on G (lw x lw, row
-// major, lower tiles).  Block b covers tile (i, j) with p <= j <= i < T.
-__global__ __launch_bounds__(256) void chol_step_kernel(int lw, int l_true, int p, double* __restrict__ G,
+// First diagonal block (one wavefront).
+__global__ __launch_bounds__(64) void chol_first_kernel(int lw, int l_true, const double* __restrict__ G,
                                                         double* __restrict__ L, double* __restrict__ Dinv,
                                                         const double* __restrict__ diag0, double tol,
                                                         uint32_t* flags) {
+  __shared__ double sS[NB * (NB + 1)];
+  __shared__ double scratch[NB * (NB + 1) + 2 * NB];
+  for (int e = threadIdx.x; e < NB * NB; e += 64) sS[(e / NB) * (NB + 1) + e % NB] = G[(int64_t)(e / NB) * lw + e % NB];
+  __syncthreads();
+  factor_block_wave(sS, scratch, diag0, 0, l_true, tol, flags, L, lw, Dinv);
+}
+
+// 32 x 32 tile product on 4 wavefronts: out = X Y^T (X, Y in LDS, pitch
+// NB + 1); wave w computes the 16 x 16 sub-tile (w / 2, w % 2).
+__device__ __forceinline__ v4d tile_xyt(const double (*X)[NB + 1], const double (*Y)[NB + 1], int wave, int li,
+                                        int lk) {
+  const int si = wave >> 1, sj = wave & 1;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < NB; kk += 4) acc = mfma_f64(X[16 * si + li][kk + lk], Y[16 * sj + li][kk + lk], acc);
+  return acc;
+}
+
+// Launch p (0 <= p < T - 1): workgroup b owns trailing tile (i, j),
+// p < j <= i < T.  It forms L_ip = G_ip Dinv_p^T and L_jp, writes L_ip when
+// j == p + 1, updates G_ij -= L_ip L_jp^T, and the owner of (p+1, p+1)
+// factors that block.
+__global__ __launch_bounds__(256) void chol_panel_kernel(int lw, int l_true, int p, double* __restrict__ G,
+                                                         double* __restrict__ L, double* __restrict__ Dinv,
+                                                         const double* __restrict__ diag0, double tol,
+                                                         uint32_t* flags) {
   __shared__ double sD[NB][NB + 1];
-  __shared__ double sI[NB][NB + 1];
-  __shared__ double sT[NB][NB + 1];
-  __shared__ double sLi[NB][NB + 1];
-  __shared__ double sLj[NB][NB + 1];
-  __shared__ double sPiv;
-  const int T = lw / NB;
+  __shared__ double sGi[NB][NB + 1], sGj[NB][NB + 1];
+  __shared__ double sLi[NB][NB + 1], sLj[NB][NB + 1];
+  __shared__ double sS[NB][NB + 1];
+  __shared__ double scratch[NB * (NB + 1) + 2 * NB];
   int t = blockIdx.x, di = 0;
   while (t > di) {
     t -= di + 1;
     ++di;
   }
-  const int i = p + di, j = p + t;   // p <= j <= i
-  const int tid = threadIdx.x;
-
-  const double* Gpp = G + (int64_t)p * NB * lw + p * NB;
-  for (int e = tid; e < NB * NB; e += 256) sD[e / NB][e % NB] = Gpp[(int64_t)(e / NB) * lw + (e % NB)];
-  __syncthreads();
-  factor_diag(sD, sI, &sPiv, diag0, p * NB, l_true, tol, flags, i == p && j == p);
-
-  if (i == p) {   // j == p: the diagonal block
-    double* Lpp = L + (int64_t)p * NB * lw + p * NB;
-    double* Dp = Dinv + (int64_t)p * NB * NB;
-    for (int e = tid; e < NB * NB; e += 256) {
-      int r = e / NB, c = e % NB;
-      Lpp[(int64_t)r * lw + c] = c <= r ? sD[r][c] : 0.0;
-      Dp[e] = sI[r][c];
-    }
-    // zero the strictly upper tiles of this block row of L
-    for (int64_t e = tid; e < (int64_t)NB * (T - 1 - p) * NB; e += 256) {
-      int r = (int)(e / ((T - 1 - p) * NB)), c = (int)(e % ((T - 1 - p) * NB));
-      L[(int64_t)(p * NB + r) * lw + (p + 1) * NB + c] = 0.0;
-    }
-    return;
-  }
-  // L_ip = G_ip * Inv^T
-  times_inv_t(sLi, G + (int64_t)i * NB * lw + p * NB, lw, sI, sT);
-  if (j == p) {
-    double* Lip = L + (int64_t)i * NB * lw + p * NB;
-    for (int e = tid; e < NB * NB; e += 256) Lip[(int64_t)(e / NB) * lw + (e % NB)] = sLi[e / NB][e % NB];
-    return;
-  }
-  // trailing update G_ij -= L_ip L_jp^T
-  if (j == i) {
-    for (int e = tid; e < NB * NB; e += 256) sLj[e / NB][e % NB] = sLi[e / NB][e % NB];
-    __syncthreads();
-  } else {
-    times_inv_t(sLj, G + (int64_t)j * NB * lw + p * NB, lw, sI, sT);
-  }
-  double* Gij = G + (int64_t)i * NB * lw + j * NB;
+  const int i = p + 1 + di, j = p + 1 + t;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const double* Dp = Dinv + (int64_t)p * NB * NB;
+  const double* Gip = G + (int64_t)i * NB * lw + p * NB;
+  const double* Gjp = G + (int64_t)j * NB * lw + p * NB;
   for (int e = tid; e < NB * NB; e += 256) {
-    int r = e / NB, c = e % NB;
-    double s = 0.0;
-    for (int k = 0; k < NB; ++k) s += sLi[r][k] * sLj[c][k];
-    Gij[(int64_t)r * lw + c] -= s;
+    const int r = e / NB, c = e % NB;
+    sD[r][c] = Dp[e];
+    sGi[r][c] = Gip[(int64_t)r * lw + c];
+    if (j != i) sGj[r][c] = Gjp[(int64_t)r * lw + c];
+  }
+  __syncthreads();
+  {
+    v4d li_acc = tile_xyt(sGi, sD, wave, li, lk);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sLi[16 * (wave >> 1) + 4 * r + lk][16 * (wave & 1) + li] = li_acc[r];
+    if (j != i) {
+      v4d lj_acc = tile_xyt(sGj, sD, wave, li, lk);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sLj[16 * (wave >> 1) + 4 * r + lk][16 * (wave & 1) + li] = lj_acc[r];
+    }
+  }
+  __syncthreads();
+  if (j == p + 1) {
+    double* Lip = L + (int64_t)i * NB * lw + p * NB;
+    for (int e = tid; e < NB * NB; e += 256) Lip[(int64_t)(e / NB) * lw + e % NB] = sLi[e / NB][e % NB];
+  }
+  const v4d upd = tile_xyt(sLi, j != i ? sLj : sLi, wave, li, lk);
+  double* Gij = G + (int64_t)i * NB * lw + j * NB;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int rr = 16 * (wave >> 1) + 4 * r + lk, cc = 16 * (wave & 1) + li;
+    const double v = Gij[(int64_t)rr * lw + cc] - upd[r];
+    Gij[(int64_t)rr * lw + cc] = v;
+    sS[rr][cc] = v;
+  }
+  if (i == p + 1 && j == p + 1) {
+    __syncthreads();
+    if (wave == 0)
+      factor_block_wave(&sS[0][0], scratch, diag0, (p + 1) * NB, l_true, tol, flags,
+                        L + (int64_t)(p + 1) * NB * lw + (p + 1) * NB, lw, Dinv + (int64_t)(p + 1) * NB * NB);
+  }
+}
+
+// One wavefront: acc[si][sj] (16 x 16 sub-tiles) += X[32 x 32] Y[32 x 32]^T,
+// X and Y row-major in global memory (L2-resident), K = 32.
+__device__ __forceinline__ void wave_tile_xyt(const double* X, int64_t ldx, const double* Y, int64_t ldy, int li,
+                                              int lk, v4d acc[2][2]) {
+  double xv[2][8], yv[2][8];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      xv[s][kk] = X[(int64_t)(16 * s + li) * ldx + 4 * kk + lk];
+      yv[s][kk] = Y[(int64_t)(16 * s + li) * ldy + 4 * kk + lk];
+    }
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+    for (int si = 0; si < 2; ++si)
+#pragma unroll
+      for (int sj = 0; sj < 2; ++sj) acc[si][sj] = mfma_f64(xv[si][kk], yv[sj][kk], acc[si][sj]);
+}
+
+// The whole blocked Cholesky in one workgroup (no launches between panels).
+// When gate is non-null the kernel does nothing unless (*gate & gate_mask).
+__global__ __launch_bounds__(256) void chol_fused_kernel(int lw, int l_true, double* __restrict__ G,
+                                                         double* __restrict__ L, double* __restrict__ Dinv,
+                                                         const double* __restrict__ diag0, double tol,
+                                                         uint32_t* flags, const uint32_t* gate, uint32_t gate_mask) {
+  if (gate && !(*gate & gate_mask)) return;
+  __shared__ double sS[NB][NB + 1];
+  __shared__ double scratch[NB * (NB + 1) + 2 * NB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int T = lw / NB;
+  for (int p = 0; p < T; ++p) {
+    const double* Gpp = G + (int64_t)p * NB * lw + p * NB;
+    for (int e = tid; e < NB * NB; e += 256) sS[e / NB][e % NB] = Gpp[(int64_t)(e / NB) * lw + e % NB];
+    __syncthreads();
+    double* Dp = Dinv + (int64_t)p * NB * NB;
+    if (wave == 0)
+      factor_block_wave(&sS[0][0], scratch, diag0, p * NB, l_true, tol, flags, L + (int64_t)p * NB * lw + p * NB,
+                        lw, Dp);
+    __syncthreads();
+    // panel: L_ip = G_ip Dinv_p^T, one 32 x 32 tile per wavefront
+    for (int i = p + 1 + wave; i < T; i += 4) {
+      v4d acc[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
+      wave_tile_xyt(G + (int64_t)i * NB * lw + p * NB, lw, Dp, NB, li, lk, acc);
+      double* Lip = L + (int64_t)i * NB * lw + p * NB;
+#pragma unroll
+      for (int si = 0; si < 2; ++si)
+#pragma unroll
+        for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Lip[(int64_t)(16 * si + 4 * r + lk) * lw + 16 * sj + li] = acc[si][sj][r];
+    }
+    __syncthreads();
+    // trailing update: G_ij -= L_ip L_jp^T for p < j <= i
+    const int nt = (T - p - 1) * (T - p) / 2;
+    for (int idx = wave; idx < nt; idx += 4) {
+      int t = idx, di = 0;
+      while (t > di) {
+        t -= di + 1;
+        ++di;
+      }
+      const int i = p + 1 + di, j = p + 1 + t;
+      v4d acc[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
+      wave_tile_xyt(L + (int64_t)i * NB * lw + p * NB, lw, L + (int64_t)j * NB * lw + p * NB, lw, li, lk, acc);
+      double* Gij = G + (int64_t)i * NB * lw + j * NB;
+#pragma unroll
+      for (int si = 0; si < 2; ++si)
+#pragma unroll
+        for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double* g = Gij + (int64_t)(16 * si + 4 * r + lk) * lw + 16 * sj + li;
+            *g -= acc[si][sj][r];
+          }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------ second pass series --
+// After the first pass, G2 = Q1^T Q1 = I + E with |E| of order cond(Y)^2 u.
+// Its Cholesky factor I + F (F lower triangular) and the solve factor
+// (I + F)^-T are expanded in E: with F0 = tril_half(E) (strict lower part of
+// E plus half its diagonal),
+//     (I + F)^-T - I = M = -F0^T + tril_half(F0 F0^T)^T + (F0 F0)^T + O(|E|^3),
+// so Q = Q1 (I + F)^-T = Q1 + Q1 M.  series_m_kernel builds M (upper
+// triangular, 32 x 32 tiles (a, b), a <= b) and raises gate_bit when some
+// |E_ij| exceeds tau, in which case the full second pass runs instead.
+
+__device__ __forceinline__ double f0_at(const double* G2, int lw, int l_true, int i, int t) {
+  // F0[i][t] for the lower triangle of E = G2 - I (zero outside l_true)
+  if (i >= l_true || t >= l_true || t > i) return 0.0;
+  const double g = G2[(int64_t)i * lw + t];
+  return i == t ? 0.5 * (g - 1.0) : g;
+}
+
+__global__ __launch_bounds__(256) void series_m_kernel(int lw, int l_true, const double* __restrict__ G2,
+                                                       double* __restrict__ M, uint32_t* gate, uint32_t gate_bit,
+                                                       double tau) {
+  __shared__ double sB[NB][NB + 1];   // F0 rows of block b, t-chunk
+  __shared__ double sA[NB][NB + 1];   // F0 rows of block a, t-chunk
+  __shared__ double sC[NB][NB + 1];   // F0 t-chunk rows, columns of block a
+  int t = blockIdx.x, bb = 0;
+  while (t > bb) {
+    t -= bb + 1;
+    ++bb;
+  }
+  const int ab = t;                   // tile (ab, bb) of M with ab <= bb
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int si = wave >> 1, sj = wave & 1;
+  // gate test on the E tile (bb, ab) this block owns
+  bool over = false;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = bb * NB + e / NB, j = ab * NB + e % NB;
+    if (i < l_true && j < l_true && j <= i) {
+      const double v = G2[(int64_t)i * lw + j] - (i == j ? 1.0 : 0.0);
+      if (!(fabs(v) <= tau)) over = true;
+    }
+  }
+  if (over) atomicOr(gate, gate_bit);
+  // out[r][c] = M[ab*NB + r][bb*NB + c]: transposed accumulation of
+  //   S1[b][a] = sum_t F0[b][t] F0[a][t]  (t <= a)  and  S2[b][a] = sum_t F0[b][t] F0[t][a]  (a <= t <= b)
+  // sub-tile (si, sj) of the (bb, ab) orientation: rows b, columns a
+  v4d s1 = {0, 0, 0, 0}, s2 = {0, 0, 0, 0};
+  for (int tb = 0; tb <= bb; ++tb) {
+    __syncthreads();
+    for (int e = tid; e < NB * NB; e += 256) {
+      const int r = e / NB, c = e % NB;
+      sB[r][c] = f0_at(G2, lw, l_true, bb * NB + r, tb * NB + c);
+      sA[r][c] = f0_at(G2, lw, l_true, ab * NB + r, tb * NB + c);
+      sC[r][c] = f0_at(G2, lw, l_true, tb * NB + r, ab * NB + c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < NB; kk += 4) {
+      const double x = sB[16 * si + li][kk + lk];
+      if (tb <= ab) s1 = mfma_f64(x, sA[16 * sj + li][kk + lk], s1);     // B[k][j] = F0[a j][t k]
+      if (tb >= ab) s2 = mfma_f64(x, sC[kk + lk][16 * sj + li], s2);     // B[k][j] = F0[t k][a j]
+    }
+  }
+  // write M[a][b] = -F0[b][a] + h(S1)[b][a] + S2[b][a]  (transpose of the (b, a) tile)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int bi = bb * NB + 16 * si + 4 * r + lk;     // row index in the (b, a) orientation
+    const int aj = ab * NB + 16 * sj + li;
+    double v = 0.0;
+    if (aj <= bi) {
+      const double h1 = (aj < bi) ? s1[r] : 0.5 * s1[r];
+      v = -f0_at(G2, lw, l_true, bi, aj) + h1 + s2[r];
+    }
+    M[(int64_t)aj * lw + bi] = v;
+  }
+}
+
+// Q = Q1 + Q1 M (M upper triangular); 16 rows x 64 columns per block.
+// Columns in [lw, zero_to) are written as zero.  Skipped when the gate is set.
+__global__ __launch_bounds__(256) void series_apply_kernel(int64_t rows, int lw, const double* __restrict__ Q1,
+                                                           const double* __restrict__ M, double* __restrict__ Q,
+                                                           int64_t ldq, int zero_to, const uint32_t* gate,
+                                                           uint32_t gate_bit) {
+  if (*gate & gate_bit) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * 16;
+  const int c0 = blockIdx.y * 64 + wave * 16;
+  if (c0 >= zero_to) return;
+  if (c0 >= lw) {
+    for (int e = lane; e < 256; e += 64) {
+      const int64_t r = r0 + e / 16;
+      const int c = c0 + e % 16;
+      if (r < rows && c < zero_to) Q[r * ldq + c] = 0.0;
+    }
+    return;
+  }
+  const int64_t ra = r0 + li < rows ? r0 + li : rows - 1;
+  v4d acc = {0, 0, 0, 0};
+  const int kend = c0 + 16;        // M[t][c] = 0 for t > c
+  for (int t0 = 0; t0 < kend; t0 += 4) {
+    const double a = Q1[ra * lw + t0 + lk];
+    const double b = M[(int64_t)(t0 + lk) * lw + c0 + li];
+    acc = mfma_f64(a, b, acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = r0 + 4 * r + lk;
+    const int c = c0 + li;
+    if (row < rows && c < zero_to) Q[row * ldq + c] = Q1[row * lw + c] + acc[r];
   }
 }
 
@@ -243,7 +491,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void trsm_kernel(int64_t rows, int lw, int ncols, const T* __restrict__ X,
                                                    int64_t ldx,
                                                    const double* __restrict__ L, const double* __restrict__ Dinv,
-                                                   double* __restrict__ Q, int64_t ldq, int zero_to) {
+                                                   double* __restrict__ Q, int64_t ldq, int zero_to,
+                                                   const uint32_t* gate, uint32_t gate_mask) {
+  if (gate && !(*gate & gate_mask)) return;
   extern __shared__ double smem[];
   double* sQ = smem;                          // 16 x lw
   double* sW = smem + 16 * lw;                // 4 waves x 16 x 32 partials
@@ -308,10 +558,14 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t rows, int lw, int nco
 // ------------------------------------------------------------------ host --
 
 struct CholWs {
-  double *G, *L, *Dinv, *diag0, *part, *Q1;
+  double *G, *L, *Dinv, *diag0, *part, *Q1, *M;
+  uint32_t* gate;
   int nchunks;
   int64_t rows_per_chunk;
 };
+
+constexpr uint32_t kGateFull = 1u;      // second pass needs the full Cholesky
+constexpr double kSeriesTau = 1e-5;     // |E| bound of the second-pass expansion (error O(tau^3))
 
 static void cholqr_layout(int64_t rows, int64_t l, int* lw_out, int* nchunks, int64_t* rpc) {
   int lw = (int)round_up(l, NB);
@@ -334,42 +588,72 @@ size_t cholqr2_workspace(int64_t rows, int64_t l) {
   int64_t rpc;
   cholqr_layout(rows, l, &lw, &nc, &rpc);
   size_t sq = (size_t)lw * lw;
-  size_t n = 2 * sq + (size_t)lw * NB + lw + (size_t)nc * sq + (size_t)rows * lw;
+  size_t n = 3 * sq + (size_t)lw * NB + lw + (size_t)nc * sq + (size_t)rows * lw + 32;
   return n * sizeof(double) + 256;
 }
 
-template <typename T>
-static lramm_status one_pass(int64_t rows, int lw, int l_true, const T* X, int64_t ldx, double* Qout, int64_t ldq,
-                             int zero_to, const CholWs& w, uint32_t* flags, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
+static lramm_status set_trsm_attr() {
+  static bool done = false;
+  if (!done) {
     LRAMM_HIP(hipFuncSetAttribute((const void*)trsm_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   160 * 1024));
     LRAMM_HIP(hipFuncSetAttribute((const void*)trsm_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   160 * 1024));
-    attr_set = true;
+    done = true;
   }
+  return LRAMM_OK;
+}
+
+template <typename T>
+static lramm_status gram(int64_t rows, int lw, int l_true, const T* X, int64_t ldx, const CholWs& w, hipStream_t s) {
   const int Tn = lw / NB;
   const int ntri = Tn * (Tn + 1) / 2;
   hipLaunchKernelGGL((gram_kernel<T>), dim3(ntri, w.nchunks), dim3(256), 0, s, rows, lw, l_true, X, ldx, w.part,
                      w.rows_per_chunk);
   LRAMM_HIP(hipGetLastError());
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)ceil_div((int64_t)lw * lw, 256)), dim3(256), 0, s, lw,
-                     w.nchunks, w.part, w.G, w.diag0);
-  LRAMM_HIP(hipGetLastError());
-  const double tol = 64.0 * (double)l_true * 0x1p-53;
-  for (int p = 0; p < Tn; ++p) {
-    int nb = (Tn - p) * (Tn - p + 1) / 2;
-    hipLaunchKernelGGL(chol_step_kernel, dim3(nb), dim3(256), 0, s, lw, l_true, p, w.G, w.L, w.Dinv, w.diag0, tol,
-                       flags);
-    LRAMM_HIP(hipGetLastError());
-  }
-  size_t shm = (size_t)(16 * lw + 4 * 16 * NB + 16 * NB) * sizeof(double);
-  hipLaunchKernelGGL((trsm_kernel<T>), dim3((unsigned)ceil_div(rows, 16)), dim3(256), shm, s, rows, lw, l_true, X,
-                     ldx, w.L, w.Dinv, Qout, ldq, zero_to);
+                     w.nchunks, w.part, w.G, w.diag0, w.gate);
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }
+
+// Cholesky of w.G into w.L / w.Dinv.  Multi-launch (one launch per panel)
+// unless fused; gated variants only run when (*gate & mask).
+static lramm_status cholesky(int lw, int l_true, const CholWs& w, uint32_t* flags, bool fused, const uint32_t* gate,
+                             uint32_t mask, hipStream_t s) {
+  const double tol = 64.0 * (double)l_true * 0x1p-53;
+  const int Tn = lw / NB;
+  if (fused || gate) {
+    hipLaunchKernelGGL(chol_fused_kernel, dim3(1), dim3(256), 0, s, lw, l_true, w.G, w.L, w.Dinv, w.diag0, tol, flags,
+                       gate, mask);
+    LRAMM_HIP(hipGetLastError());
+    return LRAMM_OK;
+  }
+  hipLaunchKernelGGL(chol_first_kernel, dim3(1), dim3(64), 0, s, lw, l_true, w.G, w.L, w.Dinv, w.diag0, tol, flags);
+  LRAMM_HIP(hipGetLastError());
+  for (int p = 0; p + 1 < Tn; ++p) {
+    int nb = (Tn - p - 1) * (Tn - p) / 2;
+    hipLaunchKernelGGL(chol_panel_kernel, dim3(nb), dim3(256), 0, s, lw, l_true, p, w.G, w.L, w.Dinv, w.diag0, tol,
+                       flags);
+    LRAMM_HIP(hipGetLastError());
+  }
+  return LRAMM_OK;
+}
+
+template <typename T>
+static lramm_status trsm(int64_t rows, int lw, int l_true, const T* X, int64_t ldx, double* Qout, int64_t ldq,
+                         int zero_to, const CholWs& w, const uint32_t* gate, uint32_t mask, hipStream_t s) {
+  LRAMM_TRY(set_trsm_attr());
+  size_t shm = (size_t)(16 * lw + 4 * 16 * NB + 16 * NB) * sizeof(double);
+  hipLaunchKernelGGL((trsm_kernel<T>), dim3((unsigned)ceil_div(rows, 16)), dim3(256), shm, s, rows, lw, l_true, X,
+                     ldx, w.L, w.Dinv, Qout, ldq, zero_to, gate, mask);
+  LRAMM_HIP(hipGetLastError());
+  return LRAMM_OK;
+}
+
+#ifndef LRAMM_CHOL_FUSED_PASS1
+#define LRAMM_CHOL_FUSED_PASS1 0
+#endif
 
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
                             int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s) {
@@ -387,6 +671,8 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   p += sq;
   w.L = p;
   p += sq;
+  w.M = p;
+  p += sq;
   w.Dinv = p;
   p += (size_t)lw * NB;
   w.diag0 = p;
@@ -394,18 +680,36 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   w.part = p;
   p += (size_t)nc * sq;
   w.Q1 = p;
+  p += (size_t)rows * lw;
+  w.gate = reinterpret_cast<uint32_t*>(p);
   w.nchunks = nc;
   w.rows_per_chunk = rpc;
-  // pass 1 on Y (columns at or past l are never read), pass 2 on Q1
+  const int lt = (int)l;
+  const bool fused1 = LRAMM_CHOL_FUSED_PASS1 != 0;
+  // pass 1 on Y (columns at or past l are never read): Q1 = Y L1^-T
   if (ytype == LRAMM_F32) {
-    LRAMM_TRY(one_pass<float>(rows, lw, (int)l, (const float*)Y, ldy, w.Q1, lw, lw, w, flags, s));
+    LRAMM_TRY(gram<float>(rows, lw, lt, (const float*)Y, ldy, w, s));
+    LRAMM_TRY(cholesky(lw, lt, w, flags, fused1, nullptr, 0, s));
+    LRAMM_TRY(trsm<float>(rows, lw, lt, (const float*)Y, ldy, w.Q1, lw, lw, w, nullptr, 0, s));
   } else if (ytype == LRAMM_F64) {
-    LRAMM_TRY(one_pass<double>(rows, lw, (int)l, (const double*)Y, ldy, w.Q1, lw, lw, w, flags, s));
+    LRAMM_TRY(gram<double>(rows, lw, lt, (const double*)Y, ldy, w, s));
+    LRAMM_TRY(cholesky(lw, lt, w, flags, fused1, nullptr, 0, s));
+    LRAMM_TRY(trsm<double>(rows, lw, lt, (const double*)Y, ldy, w.Q1, lw, lw, w, nullptr, 0, s));
   } else {
     return LRAMM_E_UNSUPPORTED;
   }
-  int zero_to = (int)ldq;
-  LRAMM_TRY(one_pass<double>(rows, lw, (int)l, w.Q1, lw, Q, ldq, zero_to, w, flags, s));
+  // pass 2 on Q1: expansion of the near-identity factor, or (gated) the full pass
+  const int zero_to = (int)ldq;
+  LRAMM_TRY(gram<double>(rows, lw, lt, w.Q1, lw, w, s));
+  const int Tn = lw / NB;
+  hipLaunchKernelGGL(series_m_kernel, dim3(Tn * (Tn + 1) / 2), dim3(256), 0, s, lw, lt, w.G, w.M, w.gate, kGateFull,
+                     kSeriesTau);
+  LRAMM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(series_apply_kernel, dim3((unsigned)ceil_div(rows, 16), (unsigned)ceil_div(zero_to, 64)),
+                     dim3(256), 0, s, rows, lw, w.Q1, w.M, Q, ldq, zero_to, w.gate, kGateFull);
+  LRAMM_HIP(hipGetLastError());
+  LRAMM_TRY(cholesky(lw, lt, w, flags, true, w.gate, kGateFull, s));
+  LRAMM_TRY(trsm<double>(rows, lw, lt, w.Q1, lw, Q, ldq, zero_to, w, w.gate, kGateFull, s));
   return LRAMM_OK;
 }
 
