@@ -2,13 +2,15 @@
 // Sec. 2.2: a matrix Q with orthonormal columns spanning the sketch).  For a
 // rows x l matrix Y (FP32 or FP64):
 //
-//   pass(X):  G = X^T X (FP64)        Gram, split over row chunks, summed in
+//   G1 = Y^T Y (FP64)                 Gram, split over row chunks, summed in
 //                                      a fixed order (deterministic)
-//             G = L L^T               blocked right-looking Cholesky, 32 x 32
-//                                      tiles, one launch per panel
-//             Q = X L^-T              row-block forward substitution
-//   Q1 = pass(Y); Q = pass(Q1)        (the second pass restores
-//                                      orthogonality lost to cond(Y)^2 u)
+//   G1 = L L^T, X = L^-1              blocked right-looking Cholesky, 32 x 32
+//                                      tiles, one launch per panel; the block
+//                                      inverse is formed in the same launches
+//   Q1 = Y X^T                         FP64 GEMM
+//   G2 = Q1^T Q1 = I + E,  Q = Q1 (chol(G2))^-T   second pass, restoring the
+//                                      orthogonality lost to cond(Y)^2 u (see
+//                                      the second-pass section)
 //
 // The thin QR factor with positive diagonal is unique, so Q equals the
 // Householder Q of any other stable method to about cond(Y) * 2^-53.
@@ -33,65 +35,6 @@ __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
 }
 
 // ------------------------------------------------------------------ Gram --
-// part[chunk] (lw x lw, lower 32x32 tiles only) = X[rows of chunk]^T X[...]
-template <typename T>
-__global__ __launch_bounds__(256) void gram_kernel(int64_t rows, int lw, int ncols, const T* __restrict__ X,
-                                                   int64_t ldx, double* __restrict__ part, int64_t rows_per_chunk) {
-  __shared__ double red[4][NB][NB + 1];
-  // lower-triangle tile index -> (ti, tj), ti >= tj
-  int t = blockIdx.x, ti = 0;
-  while (t > ti) {
-    t -= ti + 1;
-    ++ti;
-  }
-  const int tj = t;
-  const int chunk = blockIdx.y;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t r0 = (int64_t)chunk * rows_per_chunk;
-  int64_t r1 = r0 + rows_per_chunk;
-  r1 = r1 < rows ? r1 : rows;
-  const int a0 = ti * NB, b0 = tj * NB;
-  const int li = lane & 15, lk = lane >> 4;
-
-  v4d acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
-
-  for (int64_t rb = r0 + 4 * wave; rb < r1; rb += 16) {
-    int64_t r = rb + lk;
-    double xa0 = 0, xa1 = 0, xb0 = 0, xb1 = 0;
-    if (r < r1) {   // columns at or past ncols read as zero
-      const T* row = X + r * ldx;
-      if (a0 + li < ncols) xa0 = (double)row[a0 + li];
-      if (a0 + 16 + li < ncols) xa1 = (double)row[a0 + 16 + li];
-      if (b0 + li < ncols) xb0 = (double)row[b0 + li];
-      if (b0 + 16 + li < ncols) xb1 = (double)row[b0 + 16 + li];
-    }
-    acc[0][0] = mfma_f64(xa0, xb0, acc[0][0]);
-    acc[0][1] = mfma_f64(xa0, xb1, acc[0][1]);
-    acc[1][0] = mfma_f64(xa1, xb0, acc[1][0]);
-    acc[1][1] = mfma_f64(xa1, xb1, acc[1][1]);
-  }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) red[wave][16 * i + 4 * r + lk][16 * j + li] = acc[i][j][r];
-  __syncthreads();
-  double* out = part + (int64_t)chunk * lw * lw;
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {
-    int i = e / NB, j = e % NB;
-    double v = red[0][i][j];
-    v += red[1][i][j];
-    v += red[2][i][j];
-    v += red[3][i][j];
-    out[(int64_t)(a0 + i) * lw + b0 + j] = v;
-  }
-}
-
 // G (lower tiles) = sum over chunks in order; diag0 = diag(G).
 __global__ __launch_bounds__(256) void gram_reduce_kernel(int lw, int nchunks, const double* __restrict__ part,
                                                           double* __restrict__ G, double* __restrict__ diag0,
@@ -105,6 +48,186 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int lw, int nchunks, c
   for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * lw * lw + e];
   G[e] = s;
   if (i == j) diag0[i] = s;
+}
+
+// ---------------------------------------------------- FP64 tile GEMM engine --
+// A 64 x 64 output tile on 4 wavefronts (2 x 2, each 32 x 32 = 2 x 2 MFMA
+// 16 x 16 sub-tiles) accumulating sum_k A(k, m) B(k, n) over [kbeg, kend).
+// K advances in stages of 32, double-buffered in LDS, both operands stored
+// K-major ([k][m]) so that an MFMA operand read is 16 consecutive doubles.
+// Operands come from functors fa(k, m, valid), fb(k, n, valid) returning
+// doubles: they load unconditionally from an in-range address and return zero
+// when the element is outside the operand (no branches around the loads, so a
+// stage's loads are all in flight together).  AK / BK: the operand is
+// contiguous along k in memory (threads then walk k first, keeping global
+// loads coalesced).
+constexpr int FT = 64, FK = 32, FP = FT + 2;
+struct F64Smem {
+  double a[2][FK][FP];
+  double b[2][FK][FP];
+};
+
+template <bool AK, bool BK, class FA, class FB>
+__device__ __forceinline__ void f64_gemm_tile(const FA& fa, const FB& fb, int kbeg, int kend, v4d acc[2][2],
+                                              F64Smem& sm) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1, li = lane & 15, lk = lane >> 4;
+  double ra[8], rb[8];
+  auto gload = [&](int kb) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = tid + 256 * i;
+      const int ka = AK ? e % FK : e / FT, ma = AK ? e / FK : e % FT;
+      const int kbb = BK ? e % FK : e / FT, nb = BK ? e / FK : e % FT;
+      const bool va = kb + ka < kend, vb = kb + kbb < kend;
+      ra[i] = fa(va ? kb + ka : kbeg, ma, va);
+      rb[i] = fb(vb ? kb + kbb : kbeg, nb, vb);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = tid + 256 * i;
+      const int ka = AK ? e % FK : e / FT, ma = AK ? e / FK : e % FT;
+      const int kbb = BK ? e % FK : e / FT, nb = BK ? e / FK : e % FT;
+      sm.a[buf][ka][ma] = ra[i];
+      sm.b[buf][kbb][nb] = rb[i];
+    }
+  };
+  const int nst = kend > kbeg ? (kend - kbeg + FK - 1) / FK : 0;
+  if (nst == 0) return;
+  gload(kbeg);
+  sstore(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    const bool more = st + 1 < nst;
+    if (more) gload(kbeg + (st + 1) * FK);
+#pragma unroll
+    for (int kk = 0; kk < FK; kk += 4) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        av[q] = sm.a[buf][kk + lk][wm * 32 + 16 * q + li];
+        bv[q] = sm.b[buf][kk + lk][wn * 32 + 16 * q + li];
+      }
+#pragma unroll
+      for (int si = 0; si < 2; ++si)
+#pragma unroll
+        for (int sj = 0; sj < 2; ++sj) acc[si][sj] = mfma_f64(av[si], bv[sj], acc[si][sj]);
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+  }
+}
+
+// Output coordinates of accumulator element (si, sj, r) of this lane.
+__device__ __forceinline__ int f64_row(int si, int r) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  return (wave >> 1) * 32 + 16 * si + 4 * r + (lane >> 4);
+}
+__device__ __forceinline__ int f64_col(int sj) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  return (wave & 1) * 32 + 16 * sj + (lane & 15);
+}
+
+// Gram of a row chunk, 64 x 64 tiles (ta, tb), ta >= tb:
+// out[a][b] = sum_{r in chunk} X[r][a] X[r][b]; columns >= ncols read as zero.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void gram64_kernel(int64_t rows, int lw, int ncols, const T* __restrict__ X,
+                                                        int64_t ldx, double* __restrict__ part,
+                                                        int64_t rows_per_chunk) {
+  __shared__ F64Smem sm;
+  int t = blockIdx.x, ta = 0;
+  while (t > ta) {
+    t -= ta + 1;
+    ++ta;
+  }
+  const int tb = t, a0 = ta * FT, b0 = tb * FT;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_chunk;
+  const int64_t r1 = r0 + rows_per_chunk < rows ? r0 + rows_per_chunk : rows;
+  auto fa = [&](int k, int m, bool v) -> double {
+    const bool ok = v && a0 + m < ncols;
+    const double x = (double)X[(r0 + k) * ldx + (ok ? a0 + m : 0)];
+    return ok ? x : 0.0;
+  };
+  auto fb = [&](int k, int n, bool v) -> double {
+    const bool ok = v && b0 + n < ncols;
+    const double x = (double)X[(r0 + k) * ldx + (ok ? b0 + n : 0)];
+    return ok ? x : 0.0;
+  };
+  v4d acc[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
+  f64_gemm_tile<false, false>(fa, fb, 0, (int)(r1 - r0), acc, sm);
+  double* out = part + (int64_t)blockIdx.y * lw * lw;
+#pragma unroll
+  for (int si = 0; si < 2; ++si)
+#pragma unroll
+    for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = a0 + f64_row(si, r), j = b0 + f64_col(sj);
+        if (i < lw && j < lw) out[(int64_t)i * lw + j] = acc[si][sj][r];
+      }
+}
+
+// Q[r][c] = [Q1[r][c] +] sum_{k <= c} X[r][k] B(k, c) for the two solve
+// products of CholeskyQR, 64 x 64 output tiles over (rows, lw):
+//   APPLY == false:  B(k, c) = Linv[c][k]  (Q1 = X L^-T, X = Y in FP32/FP64)
+//   APPLY == true :  B(k, c) = M[k][c]     (Q = Q1 + Q1 M, X = Q1)
+// Columns in [lw, zero_to) of Q are written as zero.  When gate is non-null
+// the kernel is skipped if (*gate & gate_mask) is set.
+template <typename T, bool APPLY>
+__global__ __launch_bounds__(256, 2) void solve_gemm_kernel(int64_t rows, int lw, int ncols, const T* __restrict__ X,
+                                                            int64_t ldx, const double* __restrict__ B,
+                                                            double* __restrict__ Q, int64_t ldq, int zero_to,
+                                                            const uint32_t* gate, uint32_t gate_mask) {
+  if (gate && (*gate & gate_mask)) return;
+  __shared__ F64Smem sm;
+  const int64_t r0 = (int64_t)blockIdx.x * FT;
+  const int c0 = blockIdx.y * FT;
+  if (c0 >= lw) {
+    for (int e = threadIdx.x; e < FT * FT; e += 256) {
+      const int64_t r = r0 + e / FT;
+      const int c = c0 + e % FT;
+      if (r < rows && c < zero_to) Q[r * ldq + c] = 0.0;
+    }
+    return;
+  }
+  auto fa = [&](int k, int m, bool v) -> double {
+    const int64_t r = r0 + m;
+    const bool ok = v && r < rows && k < ncols;
+    const double x = (double)X[ok ? r * ldx + k : 0];
+    return ok ? x : 0.0;
+  };
+  auto fb = [&](int k, int n, bool v) -> double {
+    // both factors are triangular (Linv lower, M upper): B(k, c) = 0 for k > c,
+    // and the blocks beyond the diagonal are never written, so never read them
+    const int c = c0 + n;
+    const bool ok = v && c < lw && k <= c;
+    const double x = B[ok ? (APPLY ? (int64_t)k * lw + c : (int64_t)c * lw + k) : 0];
+    return ok ? x : 0.0;
+  };
+  v4d acc[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
+  const int kend = c0 + FT < lw ? c0 + FT : lw;      // triangular: terms with k > c vanish
+  if constexpr (APPLY) {
+    f64_gemm_tile<true, false>(fa, fb, 0, kend, acc, sm);
+  } else {
+    f64_gemm_tile<true, true>(fa, fb, 0, kend, acc, sm);
+  }
+#pragma unroll
+  for (int si = 0; si < 2; ++si)
+#pragma unroll
+    for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + f64_row(si, r);
+        const int c = c0 + f64_col(sj);
+        if (row < rows && c < zero_to) {
+          double v = acc[si][sj][r];
+          if constexpr (APPLY) v += (double)X[row * ldx + c];
+          Q[row * ldq + c] = c < lw ? v : 0.0;
+        }
+      }
 }
 
 // -------------------------------------------------------------- Cholesky --
@@ -228,19 +351,74 @@ __device__ __forceinline__ v4d tile_xyt(const double (*X)[NB + 1], const double 
   return acc;
 }
 
+// Block (p, j), j <= p, of X = L^-1 (lower triangular, 32 x 32 blocks):
+//   X_pp = Dinv_p;  X_pj = -Dinv_p sum_{t=j}^{p-1} L_pt X_tj  (j < p).
+// Needs row blocks 0..p-1 of X and row block p of L.  One workgroup.
+__device__ void inverse_block(int lw, int p, int j, const double* __restrict__ L, const double* __restrict__ Dinv,
+                              double* __restrict__ Xinv, double (*sS)[NB + 1]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4, si = wave >> 1, sj = wave & 1;
+  const double* Dp = Dinv + (int64_t)p * NB * NB;
+  double* Xpj = Xinv + (int64_t)p * NB * lw + j * NB;
+  if (j == p) {
+    for (int e = tid; e < NB * NB; e += 256) Xpj[(int64_t)(e / NB) * lw + e % NB] = Dp[e];
+    return;
+  }
+  // S = sum_t L_pt X_tj  (sub-tile (si, sj) per wave)
+  v4d acc = {0, 0, 0, 0};
+  for (int t = j; t < p; ++t) {
+    const double* Lpt = L + (int64_t)p * NB * lw + t * NB;
+    const double* Xtj = Xinv + (int64_t)t * NB * lw + j * NB;
+    double av[8], bv[8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      av[kk] = Lpt[(int64_t)(16 * si + li) * lw + 4 * kk + lk];
+      bv[kk] = Xtj[(int64_t)(4 * kk + lk) * lw + 16 * sj + li];
+    }
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) acc = mfma_f64(av[kk], bv[kk], acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) sS[16 * si + 4 * r + lk][16 * sj + li] = acc[r];
+  __syncthreads();
+  // X_pj = -Dinv_p S
+  v4d out = {0, 0, 0, 0};
+#pragma unroll
+  for (int kk = 0; kk < NB; kk += 4) out = mfma_f64(Dp[(16 * si + li) * NB + kk + lk], sS[kk + lk][16 * sj + li], out);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Xpj[(int64_t)(16 * si + 4 * r + lk) * lw + 16 * sj + li] = -out[r];
+}
+
+// Last row block of X = L^-1 (after the last panel launch).
+__global__ __launch_bounds__(256) void inverse_row_kernel(int lw, int p, const double* __restrict__ L,
+                                                          const double* __restrict__ Dinv, double* __restrict__ Xinv,
+                                                          const uint32_t* gate, uint32_t gate_mask) {
+  if (gate && !(*gate & gate_mask)) return;
+  __shared__ double sS[NB][NB + 1];
+  inverse_block(lw, p, blockIdx.x, L, Dinv, Xinv, sS);
+}
+
 // Launch p (0 <= p < T - 1): workgroup b owns trailing tile (i, j),
 // p < j <= i < T.  It forms L_ip = G_ip Dinv_p^T and L_jp, writes L_ip when
 // j == p + 1, updates G_ij -= L_ip L_jp^T, and the owner of (p+1, p+1)
-// factors that block.
+// factors that block.  p + 1 further workgroups form row block p of
+// X = L^-1, which is ready because row blocks < p of X and row block p of L
+// were finished by earlier launches.
 __global__ __launch_bounds__(256) void chol_panel_kernel(int lw, int l_true, int p, double* __restrict__ G,
                                                          double* __restrict__ L, double* __restrict__ Dinv,
-                                                         const double* __restrict__ diag0, double tol,
-                                                         uint32_t* flags) {
+                                                         double* __restrict__ Xinv, const double* __restrict__ diag0,
+                                                         double tol, uint32_t* flags) {
   __shared__ double sD[NB][NB + 1];
   __shared__ double sGi[NB][NB + 1], sGj[NB][NB + 1];
   __shared__ double sLi[NB][NB + 1], sLj[NB][NB + 1];
   __shared__ double sS[NB][NB + 1];
   __shared__ double scratch[NB * (NB + 1) + 2 * NB];
+  const int T = lw / NB;
+  const int ntrail = (T - p - 1) * (T - p) / 2;
+  if ((int)blockIdx.x >= ntrail) {   // inverse row block p (blocks past the trailing tiles)
+    inverse_block(lw, p, blockIdx.x - ntrail, L, Dinv, Xinv, sS);
+    return;
+  }
   int t = blockIdx.x, di = 0;
   while (t > di) {
     t -= di + 1;
@@ -447,42 +625,6 @@ __global__ __launch_bounds__(256) void series_m_kernel(int lw, int l_true, const
   }
 }
 
-// Q = Q1 + Q1 M (M upper triangular); 16 rows x 64 columns per block.
-// Columns in [lw, zero_to) are written as zero.  Skipped when the gate is set.
-__global__ __launch_bounds__(256) void series_apply_kernel(int64_t rows, int lw, const double* __restrict__ Q1,
-                                                           const double* __restrict__ M, double* __restrict__ Q,
-                                                           int64_t ldq, int zero_to, const uint32_t* gate,
-                                                           uint32_t gate_bit) {
-  if (*gate & gate_bit) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int64_t r0 = (int64_t)blockIdx.x * 16;
-  const int c0 = blockIdx.y * 64 + wave * 16;
-  if (c0 >= zero_to) return;
-  if (c0 >= lw) {
-    for (int e = lane; e < 256; e += 64) {
-      const int64_t r = r0 + e / 16;
-      const int c = c0 + e % 16;
-      if (r < rows && c < zero_to) Q[r * ldq + c] = 0.0;
-    }
-    return;
-  }
-  const int64_t ra = r0 + li < rows ? r0 + li : rows - 1;
-  v4d acc = {0, 0, 0, 0};
-  const int kend = c0 + 16;        // M[t][c] = 0 for t > c
-  for (int t0 = 0; t0 < kend; t0 += 4) {
-    const double a = Q1[ra * lw + t0 + lk];
-    const double b = M[(int64_t)(t0 + lk) * lw + c0 + li];
-    acc = mfma_f64(a, b, acc);
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int64_t row = r0 + 4 * r + lk;
-    const int c = c0 + li;
-    if (row < rows && c < zero_to) Q[row * ldq + c] = Q1[row * lw + c] + acc[r];
-  }
-}
-
 // ------------------------------------------------------------------ TRSM --
 // Q[rows x lw] = X L^-T, 16 rows per block.  For each 32-column panel c:
 //   W = X[:, c] - Q[:, <c] L[c, <c]^T      (K split over the 4 waves)
@@ -558,7 +700,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t rows, int lw, int nco
 // ------------------------------------------------------------------ host --
 
 struct CholWs {
-  double *G, *L, *Dinv, *diag0, *part, *Q1, *M;
+  double *G, *L, *Dinv, *diag0, *part, *Q1, *M, *X;
   uint32_t* gate;
   int nchunks;
   int64_t rows_per_chunk;
@@ -568,14 +710,14 @@ constexpr uint32_t kGateFull = 1u;      // second pass needs the full Cholesky
 constexpr double kSeriesTau = 1e-5;     // |E| bound of the second-pass expansion (error O(tau^3))
 
 static void cholqr_layout(int64_t rows, int64_t l, int* lw_out, int* nchunks, int64_t* rpc) {
-  int lw = (int)round_up(l, NB);
-  int T = lw / NB;
-  int ntri = T * (T + 1) / 2;
-  int64_t nc = 512 / ntri;
-  int64_t maxc = ceil_div(rows, 64);
+  const int lw = (int)round_up(l, NB);
+  const int t64 = (int)ceil_div(lw, FT);
+  const int ntri = t64 * (t64 + 1) / 2;
+  int64_t nc = 384 / ntri;
+  const int64_t maxc = ceil_div(rows, 64);
   if (nc > maxc) nc = maxc;
   if (nc < 1) nc = 1;
-  int64_t r = round_up(ceil_div(rows, nc), 16);
+  const int64_t r = round_up(ceil_div(rows, nc), FK);
   nc = ceil_div(rows, r);
   if (nc < 1) nc = 1;
   *lw_out = lw;
@@ -587,8 +729,8 @@ size_t cholqr2_workspace(int64_t rows, int64_t l) {
   int lw, nc;
   int64_t rpc;
   cholqr_layout(rows, l, &lw, &nc, &rpc);
-  size_t sq = (size_t)lw * lw;
-  size_t n = 3 * sq + (size_t)lw * NB + lw + (size_t)nc * sq + (size_t)rows * lw + 32;
+  const size_t sq = (size_t)lw * lw;
+  const size_t n = 4 * sq + (size_t)lw * NB + lw + (size_t)nc * sq + (size_t)rows * lw + 32;
   return n * sizeof(double) + 256;
 }
 
@@ -606,9 +748,9 @@ static lramm_status set_trsm_attr() {
 
 template <typename T>
 static lramm_status gram(int64_t rows, int lw, int l_true, const T* X, int64_t ldx, const CholWs& w, hipStream_t s) {
-  const int Tn = lw / NB;
-  const int ntri = Tn * (Tn + 1) / 2;
-  hipLaunchKernelGGL((gram_kernel<T>), dim3(ntri, w.nchunks), dim3(256), 0, s, rows, lw, l_true, X, ldx, w.part,
+  const int t64 = (int)ceil_div(lw, FT);
+  const int ntri = t64 * (t64 + 1) / 2;
+  hipLaunchKernelGGL((gram64_kernel<T>), dim3(ntri, w.nchunks), dim3(256), 0, s, rows, lw, l_true, X, ldx, w.part,
                      w.rows_per_chunk);
   LRAMM_HIP(hipGetLastError());
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)ceil_div((int64_t)lw * lw, 256)), dim3(256), 0, s, lw,
@@ -617,43 +759,32 @@ static lramm_status gram(int64_t rows, int lw, int l_true, const T* X, int64_t l
   return LRAMM_OK;
 }
 
-// Cholesky of w.G into w.L / w.Dinv.  Multi-launch (one launch per panel)
-// unless fused; gated variants only run when (*gate & mask).
-static lramm_status cholesky(int lw, int l_true, const CholWs& w, uint32_t* flags, bool fused, const uint32_t* gate,
-                             uint32_t mask, hipStream_t s) {
+// Cholesky of w.G into w.L, w.Dinv and X = L^-1 (one launch per panel).
+static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32_t* flags, hipStream_t s) {
   const double tol = 64.0 * (double)l_true * 0x1p-53;
   const int Tn = lw / NB;
-  if (fused || gate) {
-    hipLaunchKernelGGL(chol_fused_kernel, dim3(1), dim3(256), 0, s, lw, l_true, w.G, w.L, w.Dinv, w.diag0, tol, flags,
-                       gate, mask);
-    LRAMM_HIP(hipGetLastError());
-    return LRAMM_OK;
-  }
   hipLaunchKernelGGL(chol_first_kernel, dim3(1), dim3(64), 0, s, lw, l_true, w.G, w.L, w.Dinv, w.diag0, tol, flags);
   LRAMM_HIP(hipGetLastError());
   for (int p = 0; p + 1 < Tn; ++p) {
-    int nb = (Tn - p - 1) * (Tn - p) / 2;
-    hipLaunchKernelGGL(chol_panel_kernel, dim3(nb), dim3(256), 0, s, lw, l_true, p, w.G, w.L, w.Dinv, w.diag0, tol,
-                       flags);
+    const int nb = (Tn - p - 1) * (Tn - p) / 2 + p + 1;
+    hipLaunchKernelGGL(chol_panel_kernel, dim3(nb), dim3(256), 0, s, lw, l_true, p, w.G, w.L, w.Dinv, w.X, w.diag0,
+                       tol, flags);
     LRAMM_HIP(hipGetLastError());
   }
-  return LRAMM_OK;
-}
-
-template <typename T>
-static lramm_status trsm(int64_t rows, int lw, int l_true, const T* X, int64_t ldx, double* Qout, int64_t ldq,
-                         int zero_to, const CholWs& w, const uint32_t* gate, uint32_t mask, hipStream_t s) {
-  LRAMM_TRY(set_trsm_attr());
-  size_t shm = (size_t)(16 * lw + 4 * 16 * NB + 16 * NB) * sizeof(double);
-  hipLaunchKernelGGL((trsm_kernel<T>), dim3((unsigned)ceil_div(rows, 16)), dim3(256), shm, s, rows, lw, l_true, X,
-                     ldx, w.L, w.Dinv, Qout, ldq, zero_to, gate, mask);
+  hipLaunchKernelGGL(inverse_row_kernel, dim3(Tn), dim3(256), 0, s, lw, Tn - 1, w.L, w.Dinv, w.X, nullptr, 0u);
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }
 
-#ifndef LRAMM_CHOL_FUSED_PASS1
-#define LRAMM_CHOL_FUSED_PASS1 0
-#endif
+template <typename T, bool APPLY>
+static lramm_status solve_gemm(int64_t rows, int lw, int ncols, const T* X, int64_t ldx, const double* B, double* Q,
+                               int64_t ldq, int zero_to, const uint32_t* gate, uint32_t mask, hipStream_t s) {
+  dim3 grid((unsigned)ceil_div(rows, FT), (unsigned)ceil_div(zero_to, FT));
+  hipLaunchKernelGGL((solve_gemm_kernel<T, APPLY>), grid, dim3(256), 0, s, rows, lw, ncols, X, ldx, B, Q, ldq,
+                     zero_to, gate, mask);
+  LRAMM_HIP(hipGetLastError());
+  return LRAMM_OK;
+}
 
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
                             int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s) {
@@ -663,15 +794,18 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   cholqr_layout(rows, l, &lw, &nc, &rpc);
   if (ws_bytes < cholqr2_workspace(rows, l)) return LRAMM_E_WORKSPACE;
   if ((size_t)(16 * lw + 5 * 16 * NB) * sizeof(double) > 160 * 1024) return LRAMM_E_UNSUPPORTED;
+  LRAMM_TRY(set_trsm_attr());
   uintptr_t base = round_up((int64_t)(uintptr_t)ws, 256);
   double* p = reinterpret_cast<double*>(base);
-  size_t sq = (size_t)lw * lw;
+  const size_t sq = (size_t)lw * lw;
   CholWs w;
   w.G = p;
   p += sq;
   w.L = p;
   p += sq;
   w.M = p;
+  p += sq;
+  w.X = p;
   p += sq;
   w.Dinv = p;
   p += (size_t)lw * NB;
@@ -685,16 +819,15 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   w.nchunks = nc;
   w.rows_per_chunk = rpc;
   const int lt = (int)l;
-  const bool fused1 = LRAMM_CHOL_FUSED_PASS1 != 0;
   // pass 1 on Y (columns at or past l are never read): Q1 = Y L1^-T
   if (ytype == LRAMM_F32) {
     LRAMM_TRY(gram<float>(rows, lw, lt, (const float*)Y, ldy, w, s));
-    LRAMM_TRY(cholesky(lw, lt, w, flags, fused1, nullptr, 0, s));
-    LRAMM_TRY(trsm<float>(rows, lw, lt, (const float*)Y, ldy, w.Q1, lw, lw, w, nullptr, 0, s));
+    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s));
+    LRAMM_TRY((solve_gemm<float, false>(rows, lw, lt, (const float*)Y, ldy, w.X, w.Q1, lw, lw, nullptr, 0, s)));
   } else if (ytype == LRAMM_F64) {
     LRAMM_TRY(gram<double>(rows, lw, lt, (const double*)Y, ldy, w, s));
-    LRAMM_TRY(cholesky(lw, lt, w, flags, fused1, nullptr, 0, s));
-    LRAMM_TRY(trsm<double>(rows, lw, lt, (const double*)Y, ldy, w.Q1, lw, lw, w, nullptr, 0, s));
+    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s));
+    LRAMM_TRY((solve_gemm<double, false>(rows, lw, lt, (const double*)Y, ldy, w.X, w.Q1, lw, lw, nullptr, 0, s)));
   } else {
     return LRAMM_E_UNSUPPORTED;
   }
@@ -705,11 +838,16 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   hipLaunchKernelGGL(series_m_kernel, dim3(Tn * (Tn + 1) / 2), dim3(256), 0, s, lw, lt, w.G, w.M, w.gate, kGateFull,
                      kSeriesTau);
   LRAMM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(series_apply_kernel, dim3((unsigned)ceil_div(rows, 16), (unsigned)ceil_div(zero_to, 64)),
-                     dim3(256), 0, s, rows, lw, w.Q1, w.M, Q, ldq, zero_to, w.gate, kGateFull);
+  LRAMM_TRY((solve_gemm<double, true>(rows, lw, lw, w.Q1, lw, w.M, Q, ldq, zero_to, w.gate, kGateFull, s)));
+  // gated fallback: full Cholesky of G2 and triangular solve
+  const double tol = 64.0 * (double)lt * 0x1p-53;
+  hipLaunchKernelGGL(chol_fused_kernel, dim3(1), dim3(256), 0, s, lw, lt, w.G, w.L, w.Dinv, w.diag0, tol, flags,
+                     w.gate, kGateFull);
   LRAMM_HIP(hipGetLastError());
-  LRAMM_TRY(cholesky(lw, lt, w, flags, true, w.gate, kGateFull, s));
-  LRAMM_TRY(trsm<double>(rows, lw, lt, w.Q1, lw, Q, ldq, zero_to, w, w.gate, kGateFull, s));
+  const size_t shm = (size_t)(16 * lw + 4 * 16 * NB + 16 * NB) * sizeof(double);
+  hipLaunchKernelGGL((trsm_kernel<double>), dim3((unsigned)ceil_div(rows, 16)), dim3(256), shm, s, rows, lw, lt,
+                     w.Q1, (int64_t)lw, w.L, w.Dinv, Q, ldq, zero_to, w.gate, kGateFull);
+  LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }
 

@@ -6,12 +6,14 @@
 //
 // Tiling: 256 threads = 4 wavefronts in a 2 x 2 grid; a block tile is
 // BM x BN, each wavefront owns (BM/2) x (BN/2) as (BM/64) x (BN/64) tiles of
-// the 32 x 32 MFMA.  K advances in stages of 64 bytes of the widened operand
-// (64 int8 / int4 / fp8 elements, 32 bf16 elements), double-buffered in LDS
-// with a 16-byte row pad (80-byte pitch) so the 16-byte MFMA operand reads of
-// 8 consecutive rows fall in distinct banks.  Packed int4 rows are read as 32
-// bytes per stage and widened to int8 on the way into LDS (no int4 MFMA on
-// CDNA4), so the MFMA loop is the int8 one.
+// the 32 x 32 MFMA.  K advances in stages of 128 bytes of the widened operand
+// (128 int8 / int4 elements, 64 bf16 elements), double-buffered in LDS with a
+// 16-byte row pad (144-byte pitch) so the 16-byte MFMA operand reads of 8
+// consecutive rows fall in distinct banks; bytes past the padded K read as
+// zero.  Packed int4 rows are read as 64 bytes per stage and widened to int8
+// on the way into LDS (no int4 MFMA on CDNA4), so the MFMA loop is the int8
+// one.  The epilogue stages the accumulators in LDS and writes 4 consecutive
+// outputs per thread (16-byte stores), applying the dequantisation there.
 //
 // MFMA operand layout (v_mfma_*_32x32x*): lane l supplies row (l % 32) of its
 // operand and a 16-byte slice of K chosen by l / 32; both operands use the
@@ -29,8 +31,9 @@ enum { KIND_I8 = 0, KIND_I4 = 1, KIND_BF16 = 2 };
 
 struct GemmArgs {
   int M, N;
-  int nst;                 // K stages of 64 widened bytes
+  int nst;                 // K stages of 128 widened bytes
   int st_per_split;        // stages per split-K slice
+  int kw;                  // widened K bytes (multiple of 64); bytes past it read as zero
   const uint8_t* L;
   int64_t ldl;             // bytes
   const uint8_t* R;
@@ -41,13 +44,15 @@ struct GemmArgs {
   void* C;
   int64_t ldc;             // elements
   int ctype;
+  int c_vec;               // C rows 16-byte aligned (vector stores)
   int32_t* acc_out;
   int64_t ld_acc;
   int32_t* part;           // split-K partials [split][M][N] (int32 or float bits)
   int tiles_m, tiles_n;
 };
 
-constexpr int kLdsPitch = 80;   // bytes per LDS row (64 data + 16 pad)
+constexpr int kStage = 128;                 // widened bytes of K per stage
+constexpr int kLdsPitch = kStage + 16;      // LDS row pitch (16-byte pad: conflict-free 16 B reads)
 
 template <int KIND>
 struct Acc;
@@ -72,26 +77,33 @@ __device__ __forceinline__ uint2 widen_int4(uint32_t w) {
 }
 
 // Global -> registers for one operand tile of ROWS rows at stage st.
+//   int8 / bf16: a row holds 8 vectors of 16 B per stage;
+//   int4: 4 vectors of 16 B (packed), each widened to 32 B in LDS.
 template <int ROWS, int KIND>
 struct TileLoader {
-  // int8 / bf16: ROWS x 64 bytes = ROWS*4 vectors of 16 B.
-  // int4: ROWS x 32 bytes = ROWS*2 vectors of 16 B (widened to 32 B each).
-  static constexpr int kVecPerRow = KIND == KIND_I4 ? 2 : 4;
+  static constexpr int kVecPerRow = KIND == KIND_I4 ? 4 : 8;
+  static constexpr int kWPerVec = KIND == KIND_I4 ? 32 : 16;   // widened bytes per global vector
   static constexpr int kVecs = ROWS * kVecPerRow;
   static constexpr int kPerThread = (kVecs + 255) / 256;
   uint4 r[kPerThread];
 
-  __device__ __forceinline__ void load(const uint8_t* base, int64_t ld, int row0, int rows_total, int st, int tid) {
-    const int64_t kb = (int64_t)st * (KIND == KIND_I4 ? 32 : 64);
+  __device__ __forceinline__ void load(const uint8_t* base, int64_t ld, int row0, int rows_total, int st, int kw,
+                                       int tid) {
 #pragma unroll
     for (int i = 0; i < kPerThread; ++i) {
-      int v = tid + 256 * i;
+      const int v = tid + 256 * i;
       if (kVecs % 256 == 0 || v < kVecs) {
-        int row = v / kVecPerRow;
-        int c16 = v % kVecPerRow;
+        const int row = v / kVecPerRow;
+        const int c = v % kVecPerRow;
+        const int wofs = st * kStage + c * kWPerVec;          // widened byte offset of this vector
         int gr = row0 + row;
-        gr = gr < rows_total ? gr : rows_total - 1;     // clamp: results of such rows are discarded
-        r[i] = *reinterpret_cast<const uint4*>(base + (int64_t)gr * ld + kb + c16 * 16);
+        gr = gr < rows_total ? gr : rows_total - 1;           // clamp: results of such rows are discarded
+        if (wofs < kw) {
+          const int64_t gofs = KIND == KIND_I4 ? wofs / 2 : wofs;
+          r[i] = *reinterpret_cast<const uint4*>(base + (int64_t)gr * ld + gofs);
+        } else {
+          r[i] = make_uint4(0u, 0u, 0u, 0u);                  // past the padded K: zero
+        }
       }
     }
   }
@@ -99,18 +111,18 @@ struct TileLoader {
   __device__ __forceinline__ void store(uint8_t* lds, int tid) const {
 #pragma unroll
     for (int i = 0; i < kPerThread; ++i) {
-      int v = tid + 256 * i;
+      const int v = tid + 256 * i;
       if (kVecs % 256 == 0 || v < kVecs) {
-        int row = v / kVecPerRow;
-        int c16 = v % kVecPerRow;
+        const int row = v / kVecPerRow;
+        const int c = v % kVecPerRow;
         if constexpr (KIND == KIND_I4) {
           uint2 a = widen_int4(r[i].x), b = widen_int4(r[i].y);
-          uint2 c = widen_int4(r[i].z), d = widen_int4(r[i].w);
-          uint4* dst = reinterpret_cast<uint4*>(lds + row * kLdsPitch + c16 * 32);
+          uint2 cc = widen_int4(r[i].z), d = widen_int4(r[i].w);
+          uint4* dst = reinterpret_cast<uint4*>(lds + row * kLdsPitch + c * 32);
           dst[0] = make_uint4(a.x, a.y, b.x, b.y);
-          dst[1] = make_uint4(c.x, c.y, d.x, d.y);
+          dst[1] = make_uint4(cc.x, cc.y, d.x, d.y);
         } else {
-          *reinterpret_cast<uint4*>(lds + row * kLdsPitch + c16 * 16) = r[i];
+          *reinterpret_cast<uint4*>(lds + row * kLdsPitch + c * 16) = r[i];
         }
       }
     }
@@ -130,39 +142,90 @@ __device__ __forceinline__ void mfma_32x32(typename Acc<KIND>::T& acc, const uin
   }
 }
 
-__device__ __forceinline__ void store_out(void* C, int64_t idx, int ctype, float v) {
-  if (ctype == LRAMM_F32) {
-    reinterpret_cast<float*>(C)[idx] = v;
-  } else {
-    reinterpret_cast<uint16_t*>(C)[idx] = bf16_bits(v);
-  }
-}
-
 __device__ __forceinline__ float load_cin(const void* C, int64_t idx, int ctype) {
   return ctype == LRAMM_F32 ? reinterpret_cast<const float*>(C)[idx]
                             : bf16_to_float(reinterpret_cast<const uint16_t*>(C)[idx]);
 }
 
-// Dequantising epilogue: c = fl32(fl32(acc) * fl32(dL dR)); out = fl32(alpha c)
-// [+ fl32(beta Cin)].  For bf16 operands there are no scales (factor 1).
+// Dequantising epilogue of one element: c = fl32(fl32(acc) * fl32(dL dR));
+// out = fl32(alpha c) [+ fl32(beta Cin)].  bf16 operands have no scales.
 template <bool INT>
-__device__ __forceinline__ float epilogue_value(float accf, const GemmArgs& a, int gm, int gn, int64_t cidx) {
+__device__ __forceinline__ float epi_value(float accf, float dl, float dr, float alpha, float beta, float cin) {
   float c = accf;
-  if (INT) {
-    float s = __fmul_rn(a.dL[gm], a.dR[gn]);
-    c = __fmul_rn(c, s);
-  }
-  c = __fmul_rn(a.alpha, c);
-  if (a.beta != 0.0f) c = __fadd_rn(c, __fmul_rn(a.beta, load_cin(a.C, cidx, a.ctype)));
+  if (INT) c = __fmul_rn(c, __fmul_rn(dl, dr));
+  c = __fmul_rn(alpha, c);
+  if (beta != 0.0f) c = __fadd_rn(c, __fmul_rn(beta, cin));
   return c;
+}
+
+// Store phase for 4 consecutive columns gn..gn+3 of row gm: raw accumulator
+// bits v (int32 for integer kinds, float bits otherwise).
+template <bool INT, bool SPLIT>
+__device__ __forceinline__ void store4(const GemmArgs& a, int split, int gm, int gn, const int32_t v[4]) {
+  if constexpr (SPLIT) {
+    int32_t* dst = a.part + ((int64_t)split * a.M + gm) * a.N + gn;
+    if (gn + 3 < a.N && (a.N & 3) == 0) {
+      *reinterpret_cast<int4*>(dst) = make_int4(v[0], v[1], v[2], v[3]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (gn + q < a.N) dst[q] = v[q];
+    }
+    return;
+  }
+  if constexpr (INT) {
+    if (a.acc_out) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (gn + q < a.N) a.acc_out[(int64_t)gm * a.ld_acc + gn + q] = v[q];
+    }
+  }
+  const float dl = INT ? a.dL[gm] : 1.0f;
+  float out[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int n = gn + q < a.N ? gn + q : a.N - 1;
+    const float accf = INT ? (float)v[q] : __int_as_float(v[q]);   // v_cvt_f32_i32 rounds to nearest even
+    const float dr = INT ? a.dR[n] : 1.0f;
+    const float cin = a.beta != 0.0f ? load_cin(a.C, (int64_t)gm * a.ldc + n, a.ctype) : 0.0f;
+    out[q] = epi_value<INT>(accf, dl, dr, a.alpha, a.beta, cin);
+  }
+  const int64_t base = (int64_t)gm * a.ldc + gn;
+  const bool full = gn + 3 < a.N;
+  if (a.ctype == LRAMM_F32) {
+    float* C = reinterpret_cast<float*>(a.C) + base;
+    if (full && a.c_vec) {
+      *reinterpret_cast<float4*>(C) = make_float4(out[0], out[1], out[2], out[3]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (gn + q < a.N) C[q] = out[q];
+    }
+  } else {
+    uint16_t* C = reinterpret_cast<uint16_t*>(a.C) + base;
+    if (full && a.c_vec) {
+      uint2 w;
+      w.x = (uint32_t)bf16_bits(out[0]) | ((uint32_t)bf16_bits(out[1]) << 16);
+      w.y = (uint32_t)bf16_bits(out[2]) | ((uint32_t)bf16_bits(out[3]) << 16);
+      *reinterpret_cast<uint2*>(C) = w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (gn + q < a.N) C[q] = bf16_bits(out[q]);
+    }
+  }
 }
 
 template <int BM, int BN, int KIND, bool SPLIT>
 __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
   constexpr int RM = BM / 64;   // 32x32 MFMA tiles per wave along M
   constexpr int RN = BN / 64;
-  __shared__ __attribute__((aligned(16))) uint8_t sA[2][BM * kLdsPitch];
-  __shared__ __attribute__((aligned(16))) uint8_t sB[2][BN * kLdsPitch];
+  constexpr int kABytes = 2 * BM * kLdsPitch, kBBytes = 2 * BN * kLdsPitch;
+  constexpr int kCPitch = BN + 4;                       // floats per staged output row
+  constexpr int kLds = (kABytes + kBBytes) > BM * kCPitch * 4 ? (kABytes + kBBytes) : BM * kCPitch * 4;
+  __shared__ __attribute__((aligned(16))) uint8_t smem[kLds];
+  uint8_t* sA = smem;
+  uint8_t* sB = smem + kABytes;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -172,7 +235,7 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
   // XCD-aware tile order: consecutive workgroup ids land on different XCDs
   // (round robin over 8); remap so that each XCD walks a contiguous band of
   // tiles and shares operand rows in its own L2.
-  int ntiles = a.tiles_m * a.tiles_n;
+  const int ntiles = a.tiles_m * a.tiles_n;
   int bid = blockIdx.x;
   if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
   const int tm = bid / a.tiles_n;
@@ -194,10 +257,10 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
   TileLoader<BM, KIND> la;
   TileLoader<BN, KIND> lb;
   if (st0 < st1) {
-    la.load(a.L, a.ldl, row0, a.M, st0, tid);
-    lb.load(a.R, a.ldr, col0, a.N, st0, tid);
-    la.store(sA[0], tid);
-    lb.store(sB[0], tid);
+    la.load(a.L, a.ldl, row0, a.M, st0, a.kw, tid);
+    lb.load(a.R, a.ldr, col0, a.N, st0, a.kw, tid);
+    la.store(sA, tid);
+    lb.store(sB, tid);
   }
   __syncthreads();
 
@@ -209,59 +272,57 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
     const int buf = (st - st0) & 1;
     const bool more = st + 1 < st1;
     if (more) {
-      la.load(a.L, a.ldl, row0, a.M, st + 1, tid);
-      lb.load(a.R, a.ldr, col0, a.N, st + 1, tid);
+      la.load(a.L, a.ldl, row0, a.M, st + 1, a.kw, tid);
+      lb.load(a.R, a.ldr, col0, a.N, st + 1, a.kw, tid);
     }
+    const uint8_t* A = sA + buf * BM * kLdsPitch;
+    const uint8_t* B = sB + buf * BN * kLdsPitch;
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < kStage / 32; ++c) {
       uint4 av[RM], bv[RN];
 #pragma unroll
-      for (int i = 0; i < RM; ++i)
-        av[i] = *reinterpret_cast<const uint4*>(&sA[buf][(arow + 32 * i) * kLdsPitch + c * 32 + kofs]);
+      for (int i = 0; i < RM; ++i) av[i] = *reinterpret_cast<const uint4*>(A + (arow + 32 * i) * kLdsPitch + c * 32 + kofs);
 #pragma unroll
-      for (int j = 0; j < RN; ++j)
-        bv[j] = *reinterpret_cast<const uint4*>(&sB[buf][(brow + 32 * j) * kLdsPitch + c * 32 + kofs]);
+      for (int j = 0; j < RN; ++j) bv[j] = *reinterpret_cast<const uint4*>(B + (brow + 32 * j) * kLdsPitch + c * 32 + kofs);
 #pragma unroll
       for (int i = 0; i < RM; ++i)
 #pragma unroll
         for (int j = 0; j < RN; ++j) mfma_32x32<KIND>(acc[i][j], av[i], bv[j]);
     }
     if (more) {
-      la.store(sA[buf ^ 1], tid);
-      lb.store(sB[buf ^ 1], tid);
+      la.store(sA + (buf ^ 1) * BM * kLdsPitch, tid);
+      lb.store(sB + (buf ^ 1) * BN * kLdsPitch, tid);
     }
     __syncthreads();
   }
 
-  // ---- epilogue
-  constexpr bool INT = KIND != KIND_BF16;
+  // ---- epilogue: stage raw accumulators in LDS, then coalesced 4-wide stores
+  int32_t* sC = reinterpret_cast<int32_t*>(smem);
 #pragma unroll
-  for (int i = 0; i < RM; ++i) {
+  for (int i = 0; i < RM; ++i)
 #pragma unroll
     for (int j = 0; j < RN; ++j) {
-      const int gn = col0 + wn * (BN / 2) + 32 * j + (lane & 31);
+      const int cc = wn * (BN / 2) + 32 * j + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int gm = row0 + wm * (BM / 2) + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (gm < a.M && gn < a.N) {
-          if constexpr (SPLIT) {
-            int32_t bits;
-            if constexpr (INT) bits = acc[i][j][r];
-            else bits = __float_as_int(acc[i][j][r]);
-            a.part[((int64_t)split * a.M + gm) * a.N + gn] = bits;
-          } else {
-            float accf;
-            if constexpr (INT) {
-              accf = (float)acc[i][j][r];          // v_cvt_f32_i32: round to nearest even
-              if (a.acc_out) a.acc_out[(int64_t)gm * a.ld_acc + gn] = acc[i][j][r];
-            } else {
-              accf = acc[i][j][r];
-            }
-            const int64_t cidx = (int64_t)gm * a.ldc + gn;
-            store_out(a.C, cidx, a.ctype, epilogue_value<INT>(accf, a, gm, gn, cidx));
-          }
-        }
+        const int rr = wm * (BM / 2) + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        int32_t bits;
+        if constexpr (KIND == KIND_BF16) bits = __float_as_int(acc[i][j][r]);
+        else bits = acc[i][j][r];
+        sC[rr * kCPitch + cc] = bits;
       }
+    }
+  __syncthreads();
+  constexpr bool INT = KIND != KIND_BF16;
+  constexpr int kQuads = BM * BN / 4;
+#pragma unroll 4
+  for (int q = tid; q < kQuads; q += 256) {
+    const int rr = q / (BN / 4), cq = (q % (BN / 4)) * 4;
+    const int gm = row0 + rr, gn = col0 + cq;
+    if (gm < a.M && gn < a.N) {
+      const int4 w = *reinterpret_cast<const int4*>(sC + rr * kCPitch + cq);
+      const int32_t v[4] = {w.x, w.y, w.z, w.w};
+      store4<INT, SPLIT>(a, split, gm, gn, v);
     }
   }
 }
@@ -269,23 +330,38 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
 // Sum the split-K partials in split order and apply the epilogue.
 template <bool INT>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs a, int nsplit) {
-  int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  int64_t total = (int64_t)a.M * a.N;
-  if (idx >= total) return;
-  int gm = (int)(idx / a.N), gn = (int)(idx % a.N);
-  float accf;
-  if constexpr (INT) {
-    int32_t s = 0;
-    for (int k = 0; k < nsplit; ++k) s += a.part[(int64_t)k * total + idx];
-    if (a.acc_out) a.acc_out[(int64_t)gm * a.ld_acc + gn] = s;
-    accf = (float)s;
-  } else {
-    float s = 0.0f;
-    for (int k = 0; k < nsplit; ++k) s = __fadd_rn(s, __int_as_float(a.part[(int64_t)k * total + idx]));
-    accf = s;
+  const int64_t total = (int64_t)a.M * a.N;
+  const int64_t q = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (q >= total) return;
+  const int gm = (int)(q / a.N), gn = (int)(q % a.N);
+  int32_t v[4];
+  const bool vec = (a.N & 3) == 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (INT) {
+      int32_t s = 0;
+      if (q + j < total)
+        for (int k = 0; k < nsplit; ++k) s += a.part[(int64_t)k * total + q + j];
+      v[j] = s;
+    } else {
+      float s = 0.0f;
+      if (q + j < total)
+        for (int k = 0; k < nsplit; ++k) s = __fadd_rn(s, __int_as_float(a.part[(int64_t)k * total + q + j]));
+      v[j] = __float_as_int(s);
+    }
   }
-  const int64_t cidx = (int64_t)gm * a.ldc + gn;
-  store_out(a.C, cidx, a.ctype, epilogue_value<INT>(accf, a, gm, gn, cidx));
+  if (vec) {
+    store4<INT, false>(a, 0, gm, gn, v);
+  } else {
+    // row-crossing quad: store element by element
+    for (int j = 0; j < 4 && q + j < total; ++j) {
+      const int m2 = (int)((q + j) / a.N), n2 = (int)((q + j) % a.N);
+      int32_t one[4] = {v[j], 0, 0, 0};
+      GemmArgs b = a;
+      b.N = n2 + 1;   // limit the store to one column
+      store4<INT, false>(b, 0, m2, n2, one);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ host --
@@ -300,25 +376,27 @@ static int kind_of(int fmt) {
 }
 
 struct Plan {
-  int bm, bn, split, st_per_split, nst, tiles_m, tiles_n;
+  int bm, bn, split, st_per_split, nst, kw, tiles_m, tiles_n;
 };
 
 static Plan plan_gemm(int64_t M, int64_t N, int64_t K, int fmt, bool allow_split) {
   Plan p;
-  int epst = fmt == LRAMM_BF16F ? 32 : 64;      // elements per stage
-  p.nst = (int)ceil_div(K, epst);
+  const int64_t esz = fmt == LRAMM_BF16F ? 2 : 1;     // widened bytes per element
+  p.kw = (int)round_up(K * esz > 0 ? K * esz : 1, 64);
+  p.nst = (int)ceil_div(p.kw, kStage);
   p.bm = M >= 128 ? 128 : 64;
   p.bn = N >= 128 ? 128 : 64;
   // prefer the 64-wide N tile when it wastes noticeably less of a skinny N
   if (p.bn == 128 && (round_up(N, 128) - N) * 4 > N && (round_up(N, 64) - N) < (round_up(N, 128) - N)) p.bn = 64;
   p.tiles_m = (int)ceil_div(M, p.bm);
   p.tiles_n = (int)ceil_div(N, p.bn);
-  int tiles = p.tiles_m * p.tiles_n;
+  const int tiles = p.tiles_m * p.tiles_n;
   p.split = 1;
-  if (allow_split && tiles < 128) {
-    // too few tiles to occupy the 256 CUs and a long K: split K (each slice
-    // keeps at least 8 stages); partials are summed in a second pass.
-    while (tiles * p.split < 256 && p.nst / (p.split * 2) >= 8 && p.split < 16) p.split *= 2;
+  if (allow_split && tiles < 384) {
+    // too few tiles to keep 256 CUs busy (two workgroups each) and a long K:
+    // split K, each slice keeping at least 4 stages; the partials are summed
+    // in a second pass
+    while (tiles * p.split < 512 && p.nst / (p.split * 2) >= 4 && p.split < 16) p.split *= 2;
   }
   p.st_per_split = (int)ceil_div(p.nst, p.split);
   p.split = (int)ceil_div(p.nst, p.st_per_split);
@@ -378,6 +456,8 @@ lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void
   a.part = (int32_t*)ws;
   a.tiles_m = p.tiles_m;
   a.tiles_n = p.tiles_n;
+  a.kw = p.kw;
+  a.c_vec = (ldc % 4 == 0) && ((uintptr_t)C % (ctype == LRAMM_F32 ? 16 : 8) == 0);
   if (K == 0) p.nst = a.nst = 0;
   switch (kind) {
     case KIND_I8: launch_kind<KIND_I8>(a, p, s); break;
@@ -386,12 +466,12 @@ lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void
   }
   LRAMM_HIP(hipGetLastError());
   if (p.split > 1) {
-    int64_t total = M * N;
+    int64_t quads = ceil_div(M * N, 4);
     if (kind == KIND_BF16)
-      hipLaunchKernelGGL(splitk_reduce_kernel<false>, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, a,
+      hipLaunchKernelGGL(splitk_reduce_kernel<false>, dim3((unsigned)ceil_div(quads, 256)), dim3(256), 0, s, a,
                          p.split);
     else
-      hipLaunchKernelGGL(splitk_reduce_kernel<true>, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, a,
+      hipLaunchKernelGGL(splitk_reduce_kernel<true>, dim3((unsigned)ceil_div(quads, 256)), dim3(256), 0, s, a,
                          p.split);
     LRAMM_HIP(hipGetLastError());
   }
