@@ -172,7 +172,7 @@ LRAMM_API lramm_status lramm_status_poll(const lramm_plan* plan, const void* ws,
  * synchronises those events, adds their elapsed times to per-stage totals
  * (milliseconds, launch counts) and clears the record; entries beyond
  * LRAMM_NSTAGES are ignored.  Stage names: lramm_stage_name(). */
-#define LRAMM_NSTAGES 17
+#define LRAMM_NSTAGES 22
 LRAMM_API lramm_status lramm_plan_set_timing(lramm_plan* plan, int32_t enable);
 LRAMM_API lramm_status lramm_stage_times(lramm_plan* plan, double* ms,
                                          int64_t* counts);

@@ -32,7 +32,7 @@ EXPORTS = (
     "lramm_cholqr2_workspace", "lramm_dense_gemm_nt", "lramm_plan_set_timing", "lramm_stage_times",
     "lramm_stage_name",
 )
-NSTAGES = 17
+NSTAGES = 22
 
 
 class LrammError(RuntimeError):

@@ -746,12 +746,26 @@ static lramm_status set_trsm_attr() {
   return LRAMM_OK;
 }
 
+struct HookScope {
+  const TimingHook* h;
+  HookScope(const TimingHook* hook, int stage) : h(hook) {
+    if (h) h->begin(h->ctx, stage);
+  }
+  ~HookScope() {
+    if (h) h->end(h->ctx);
+  }
+};
+
 template <typename T>
-static lramm_status gram(int64_t rows, int lw, int l_true, const T* X, int64_t ldx, const CholWs& w, hipStream_t s) {
+static lramm_status gram(int64_t rows, int lw, int l_true, const T* X, int64_t ldx, const CholWs& w, hipStream_t s,
+                         const TimingHook* hook) {
   const int t64 = (int)ceil_div(lw, FT);
   const int ntri = t64 * (t64 + 1) / 2;
-  hipLaunchKernelGGL((gram64_kernel<T>), dim3(ntri, w.nchunks), dim3(256), 0, s, rows, lw, l_true, X, ldx, w.part,
-                     w.rows_per_chunk);
+  {
+    HookScope hs(hook, SUB_CHOL_GRAM);
+    hipLaunchKernelGGL((gram64_kernel<T>), dim3(ntri, w.nchunks), dim3(256), 0, s, rows, lw, l_true, X, ldx, w.part,
+                       w.rows_per_chunk);
+  }
   LRAMM_HIP(hipGetLastError());
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)ceil_div((int64_t)lw * lw, 256)), dim3(256), 0, s, lw,
                      w.nchunks, w.part, w.G, w.diag0, w.gate);
@@ -760,13 +774,15 @@ static lramm_status gram(int64_t rows, int lw, int l_true, const T* X, int64_t l
 }
 
 // Cholesky of w.G into w.L, w.Dinv and X = L^-1 (one launch per panel).
-static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32_t* flags, hipStream_t s) {
+static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32_t* flags, hipStream_t s,
+                                     const TimingHook* hook) {
   const double tol = 64.0 * (double)l_true * 0x1p-53;
   const int Tn = lw / NB;
   hipLaunchKernelGGL(chol_first_kernel, dim3(1), dim3(64), 0, s, lw, l_true, w.G, w.L, w.Dinv, w.diag0, tol, flags);
   LRAMM_HIP(hipGetLastError());
   for (int p = 0; p + 1 < Tn; ++p) {
     const int nb = (Tn - p - 1) * (Tn - p) / 2 + p + 1;
+    HookScope hs(hook, SUB_CHOL_PANEL);
     hipLaunchKernelGGL(chol_panel_kernel, dim3(nb), dim3(256), 0, s, lw, l_true, p, w.G, w.L, w.Dinv, w.X, w.diag0,
                        tol, flags);
     LRAMM_HIP(hipGetLastError());
@@ -778,7 +794,9 @@ static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32
 
 template <typename T, bool APPLY>
 static lramm_status solve_gemm(int64_t rows, int lw, int ncols, const T* X, int64_t ldx, const double* B, double* Q,
-                               int64_t ldq, int zero_to, const uint32_t* gate, uint32_t mask, hipStream_t s) {
+                               int64_t ldq, int zero_to, const uint32_t* gate, uint32_t mask, hipStream_t s,
+                               const TimingHook* hook) {
+  HookScope hs(hook, APPLY ? SUB_CHOL_APPLY : SUB_CHOL_SOLVE);
   dim3 grid((unsigned)ceil_div(rows, FT), (unsigned)ceil_div(zero_to, FT));
   hipLaunchKernelGGL((solve_gemm_kernel<T, APPLY>), grid, dim3(256), 0, s, rows, lw, ncols, X, ldx, B, Q, ldq,
                      zero_to, gate, mask);
@@ -787,7 +805,8 @@ static lramm_status solve_gemm(int64_t rows, int lw, int ncols, const T* X, int6
 }
 
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
-                            int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s) {
+                            int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s,
+                            const TimingHook* hook) {
   if (rows == 0 || l == 0) return LRAMM_OK;
   int lw, nc;
   int64_t rpc;
@@ -821,24 +840,27 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   const int lt = (int)l;
   // pass 1 on Y (columns at or past l are never read): Q1 = Y L1^-T
   if (ytype == LRAMM_F32) {
-    LRAMM_TRY(gram<float>(rows, lw, lt, (const float*)Y, ldy, w, s));
-    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s));
-    LRAMM_TRY((solve_gemm<float, false>(rows, lw, lt, (const float*)Y, ldy, w.X, w.Q1, lw, lw, nullptr, 0, s)));
+    LRAMM_TRY(gram<float>(rows, lw, lt, (const float*)Y, ldy, w, s, hook));
+    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook));
+    LRAMM_TRY((solve_gemm<float, false>(rows, lw, lt, (const float*)Y, ldy, w.X, w.Q1, lw, lw, nullptr, 0, s, hook)));
   } else if (ytype == LRAMM_F64) {
-    LRAMM_TRY(gram<double>(rows, lw, lt, (const double*)Y, ldy, w, s));
-    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s));
-    LRAMM_TRY((solve_gemm<double, false>(rows, lw, lt, (const double*)Y, ldy, w.X, w.Q1, lw, lw, nullptr, 0, s)));
+    LRAMM_TRY(gram<double>(rows, lw, lt, (const double*)Y, ldy, w, s, hook));
+    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook));
+    LRAMM_TRY((solve_gemm<double, false>(rows, lw, lt, (const double*)Y, ldy, w.X, w.Q1, lw, lw, nullptr, 0, s, hook)));
   } else {
     return LRAMM_E_UNSUPPORTED;
   }
   // pass 2 on Q1: expansion of the near-identity factor, or (gated) the full pass
   const int zero_to = (int)ldq;
-  LRAMM_TRY(gram<double>(rows, lw, lt, w.Q1, lw, w, s));
+  LRAMM_TRY(gram<double>(rows, lw, lt, w.Q1, lw, w, s, hook));
   const int Tn = lw / NB;
-  hipLaunchKernelGGL(series_m_kernel, dim3(Tn * (Tn + 1) / 2), dim3(256), 0, s, lw, lt, w.G, w.M, w.gate, kGateFull,
-                     kSeriesTau);
+  {
+    HookScope hs(hook, SUB_CHOL_SERIES);
+    hipLaunchKernelGGL(series_m_kernel, dim3(Tn * (Tn + 1) / 2), dim3(256), 0, s, lw, lt, w.G, w.M, w.gate,
+                       kGateFull, kSeriesTau);
+  }
   LRAMM_HIP(hipGetLastError());
-  LRAMM_TRY((solve_gemm<double, true>(rows, lw, lw, w.Q1, lw, w.M, Q, ldq, zero_to, w.gate, kGateFull, s)));
+  LRAMM_TRY((solve_gemm<double, true>(rows, lw, lw, w.Q1, lw, w.M, Q, ldq, zero_to, w.gate, kGateFull, s, hook)));
   // gated fallback: full Cholesky of G2 and triangular solve
   const double tol = 64.0 * (double)lt * 0x1p-53;
   hipLaunchKernelGGL(chol_fused_kernel, dim3(1), dim3(256), 0, s, lw, lt, w.G, w.L, w.Dinv, w.diag0, tol, flags,

@@ -165,8 +165,18 @@ size_t gemm_nt_workspace(int64_t M, int64_t N, int64_t K, int fmt);
 lramm_status launch_omega(uint64_t seed, int64_t k, int64_t l, int64_t lrows, float* OmegaT, int64_t ldo,
                           hipStream_t s);
 
+// Optional measurement hook: event pairs around individual launches.
+struct TimingHook {
+  void* ctx;
+  void (*begin)(void* ctx, int stage);
+  void (*end)(void* ctx);
+};
+// sub-stage ids inside the orthonormalisation (continuing the forward's list)
+enum { SUB_CHOL_GRAM = 17, SUB_CHOL_PANEL = 18, SUB_CHOL_SOLVE = 19, SUB_CHOL_SERIES = 20, SUB_CHOL_APPLY = 21 };
+
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
-                            int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s);
+                            int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s,
+                            const TimingHook* hook = nullptr);
 size_t cholqr2_workspace(int64_t rows, int64_t l);
 
 lramm_status launch_dense_gemm_nt(int64_t M, int64_t N, int64_t K, int dtype, const void* L, int64_t ldl,

@@ -35,6 +35,9 @@ struct lramm_plan {
   size_t off_W, off_Bte, off_V;
   size_t total;
   int64_t pAr, pAc, pBc, pOm, pQZc, pQc, pQr, pBtq, pTtq;
+  // side stream for the work independent of the orthonormalisation chain
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // stage timing (measurement only)
   bool timing = false;
   std::vector<hipEvent_t> events;     // pool, reused
@@ -69,7 +72,8 @@ enum Stage {
 const char* kStageNames[LRAMM_NSTAGES] = {
     "quant_A_rows", "quant_A_cols", "quant_B_cols", "omega", "quant_omega", "sketch_gemm", "cholqr2",
     "quant_Q_cols", "power_gemm_Z", "quant_QZ_cols", "power_gemm_Y", "proj_gemm", "quant_Bt_rows", "g1_gemm",
-    "quant_Q_rows", "quant_Tt_rows", "g2_gemm"};
+    "quant_Q_rows", "quant_Tt_rows", "g2_gemm", "cholqr2.gram", "cholqr2.chol_panel", "cholqr2.solve",
+    "cholqr2.series", "cholqr2.apply"};
 
 // Event pair around one stage when the plan measures (no-op otherwise).
 struct StageTimer {
@@ -97,6 +101,22 @@ struct StageTimer {
     if (stop) (void)hipEventRecord(stop, s);
   }
 };
+
+// Nested timers for launches inside a stage (TimingHook callbacks).
+struct HookCtx {
+  lramm_plan* p;
+  hipStream_t s;
+  std::vector<StageTimer*> open;
+};
+void hook_begin(void* c, int stage) {
+  HookCtx* h = static_cast<HookCtx*>(c);
+  h->open.push_back(new StageTimer(h->p, h->s, stage));
+}
+void hook_end(void* c) {
+  HookCtx* h = static_cast<HookCtx*>(c);
+  delete h->open.back();
+  h->open.pop_back();
+}
 
 int64_t qk_bound(int fmt) { return fmt == LRAMM_INT4 ? (int64_t)(2147483647LL / 49) : (int64_t)(2147483647LL / 16129); }
 
@@ -211,6 +231,14 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   p->off_Bte = carve(&c, (size_t)l * k * 4);
   p->off_V = carve(&c, (size_t)l * k * 4);
   p->total = c + 256;
+  // side stream (default priority) and fork/join events; without them the
+  // forward runs everything on the caller's stream
+  if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess) p->side = nullptr;
+  if (p->side && (hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                  hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess)) {
+    (void)hipStreamDestroy(p->side);
+    p->side = nullptr;
+  }
   *out = p;
   return LRAMM_OK;
 }
@@ -218,6 +246,9 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
 void lramm_plan_destroy(lramm_plan* plan) {
   if (!plan) return;
   for (hipEvent_t e : plan->events) (void)hipEventDestroy(e);
+  if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+  if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
+  if (plan->side) (void)hipStreamDestroy(plan->side);
   delete plan;
 }
 
@@ -288,14 +319,30 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
   void* cws = at<void>(W, P->off_chol);
 
   // operand quantisation
+  HookCtx hctx{P, s, {}};
+  TimingHook hook{&hctx, hook_begin, hook_end};
+  const TimingHook* hk = P->timing ? &hook : nullptr;
 #define TIMED(stage, expr)                \
   do {                                    \
     StageTimer _t(P, s, stage);           \
     LRAMM_TRY(expr);                      \
   } while (0)
+#define TIMED_ON(strm, stage, expr)       \
+  do {                                    \
+    StageTimer _t(P, strm, stage);        \
+    LRAMM_TRY(expr);                      \
+  } while (0)
+  // A's column codes and B's codes are first needed after the first
+  // orthonormalisation: produce them on the side stream meanwhile.
+  hipStream_t s2 = P->side ? P->side : s;
+  if (P->side) {
+    LRAMM_HIP(hipEventRecord(P->ev_fork, s));
+    LRAMM_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
+  }
+  TIMED_ON(s2, ST_QUANT_A_COLS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_proj, 1, Ac, P->pAc, sAc, flags, s2));
+  TIMED_ON(s2, ST_QUANT_B, launch_quantize(k, n, B, ldb, d.b_type, d.fmt_g1, 1, Bc, P->pBc, sBc, flags, s2));
+  if (P->side) LRAMM_HIP(hipEventRecord(P->ev_join, P->side));
   TIMED(ST_QUANT_A_ROWS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_sketch, 0, Ar, P->pAr, sAr, flags, s));
-  TIMED(ST_QUANT_A_COLS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_proj, 1, Ac, P->pAc, sAc, flags, s));
-  TIMED(ST_QUANT_B, launch_quantize(k, n, B, ldb, d.b_type, d.fmt_g1, 1, Bc, P->pBc, sBc, flags, s));
   if (omega) {
     TIMED(ST_QUANT_OMEGA, launch_quantize(k, l, omega, ldo, LRAMM_F32, d.fmt_sketch, 1, Om, P->pOm, sOm, flags, s));
   } else {
@@ -306,9 +353,10 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
   // sketch and orthonormalisation
   TIMED(ST_SKETCH, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, P->pAr, sAr, Om, P->pOm, sOm, 1.0f, 0.0f, Y, lp,
                                   LRAMM_F32, nullptr, 0, split, sb, s));
-  TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s));
+  TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk));
   uint8_t* Qc = at<uint8_t>(W, P->off_Qc);
   float* sQc = at<float>(W, P->off_sQc);
+  if (P->side) LRAMM_HIP(hipStreamWaitEvent(s, P->ev_join, 0));   // join: A_c and B_c ready
   for (int it = 0; it < d.q; ++it) {
     float* Z = at<float>(W, P->off_Z);
     double* QZ = at<double>(W, P->off_QZ);
@@ -317,11 +365,11 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
     TIMED(ST_QUANT_Q_COLS, launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s));
     TIMED(ST_POWER_Z, launch_gemm_nt(k, l, m, d.fmt_proj, Ac, P->pAc, sAc, Qc, P->pQc, sQc, 1.0f, 0.0f, Z, lp,
                                      LRAMM_F32, nullptr, 0, split, sb, s));
-    TIMED(ST_CHOLQR2, launch_cholqr2(k, l, Z, lp, LRAMM_F32, QZ, lp, cws, P->chol_bytes, flags, s));
+    TIMED(ST_CHOLQR2, launch_cholqr2(k, l, Z, lp, LRAMM_F32, QZ, lp, cws, P->chol_bytes, flags, s, hk));
     TIMED(ST_QUANT_QZ, launch_quantize(k, l, QZ, lp, LRAMM_F64, d.fmt_sketch, 1, QZc, P->pQZc, sQZc, flags, s));
     TIMED(ST_POWER_Y, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, P->pAr, sAr, QZc, P->pQZc, sQZc, 1.0f, 0.0f, Y, lp,
                                      LRAMM_F32, nullptr, 0, split, sb, s));
-    TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s));
+    TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk));
   }
   // projection Bt = Q^T A  (l x k)
   float* Bt = at<float>(W, P->off_Bt);
@@ -345,6 +393,7 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
   TIMED(ST_G2, launch_gemm_nt(m, n, l, d.fmt_g2, Qr, P->pQr, sQr, Ttq, P->pTtq, sTt, d.alpha, d.beta, C, ldc,
                               d.c_type, nullptr, 0, split, sb, s));
 #undef TIMED
+#undef TIMED_ON
   return LRAMM_OK;
 }
 
