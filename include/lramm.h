@@ -16,7 +16,9 @@
  * where every product is Alg. 2: the left operand is quantised per row, the
  * right operand per column, the integer (or low-precision) product is
  * accumulated exactly in int32 (FP32 for fp8/bf16), and the result is
- * dequantised as c = fl32(fl32(acc) * fl32(d_row * d_col)).
+ * dequantised by the row factor, then the column factor, each product
+ * rounded to binary32: c = fl32(fl32(fl32(acc) * d_row) * d_col).  (T is
+ * formed transposed; its epilogue still applies T's row factor first.)
  *
  * Quantiser (paper Sec. 3.1, eqs. Quantization / get_lambda /
  * Dequantization), per vector v of binary32 values, qmax = 2^(N-1) - 1:
@@ -146,6 +148,21 @@ LRAMM_API lramm_status lramm_factors(const lramm_plan* plan, const void* ws,
                            const double** Q, int64_t* ldq, const float** Bt,
                            int64_t* ldbt);
 
+/* Device view of one FP intermediate the last forward left in ws, for
+ * stage-by-stage replay against a reference (the FP32 values that feed each
+ * quantiser; formats with FP32 accumulation cannot be compared bit for bit):
+ *   LRAMM_VIEW_Y  (0): the last sketch Y = A Q_Z (or A Omega), m x l, FP32;
+ *   LRAMM_VIEW_Q  (1): Q, m x l, FP64 (as lramm_factors);
+ *   LRAMM_VIEW_BT (2): Bt = Q^T A, l x k, FP32;
+ *   LRAMM_VIEW_TT (3): T^T = (Bt B)^T, n x l, FP32.
+ * *ptr points into ws; *ld is the leading dimension in elements, *dtype an
+ * lramm_io value (LRAMM_F32 or LRAMM_F64).  Returns LRAMM_E_INVALID for an
+ * unknown view or NULL arguments. */
+enum { LRAMM_VIEW_Y = 0, LRAMM_VIEW_Q = 1, LRAMM_VIEW_BT = 2, LRAMM_VIEW_TT = 3 };
+LRAMM_API lramm_status lramm_intermediate(const lramm_plan* plan, const void* ws,
+                           int32_t which, const void** ptr, int64_t* rows,
+                           int64_t* cols, int64_t* ld, int32_t* dtype);
+
 /* Backward of C = Q Q^T A B with Q fixed and quantisation straight-through
  * (the gradient of the frozen-Q surrogate):
  *     W = Q^T dC,  dB = (Q^T A)^T W,  dA = Q (W B^T).
@@ -206,8 +223,12 @@ LRAMM_API int64_t lramm_pitch(int64_t K, int32_t fmt);
  *   Lq, Rq: quantised rows with byte pitches ldl, ldr >= lramm_pitch(K, fmt),
  *           zero past K (as lramm_quantize writes them).
  *   dL (M), dR (N): dequantisation factors (ignored for bf16).
- *   C: FP32 or BF16 (ctype), ldc >= N;  c = fl32(fl32(acc) fl32(dL dR));
+ *   C: FP32 or BF16 (ctype), ldc >= N;  c = fl32(fl32(fl32(acc) dL) dR);
  *      out = fl32(alpha c) [+ fl32(beta C_in)] (C_in read only if beta != 0).
+ *      fp8 codes are OCP e4m3 multiplied on the 32x32x64 fp8 MFMA with FP32
+ *      accumulation (each product is exact in FP32; the sums round in the
+ *      hardware's order, so fp8 results match an FP64 sum only to FP32
+ *      accumulation accuracy).
  *   acc_out: optional raw int32 accumulators (int8/int4 only), M x ld_acc.
  *   ws / ws_bytes: workspace for split-K partials (may be NULL / 0, then the
  *   library does not split K).  Returns LRAMM_E_OVERFLOW if K * qmax^2 could

@@ -9,10 +9,10 @@ returns alpha * D_F + beta * C.  The oracle writes those steps out:
      matrix product is exact for K < 2^53 / 127^2; the function asserts the
      bound and also that every result fits the int32 accumulator
      (K * 127^2 < 2^31, i.e. K <= 133144 for int8);
-  3. dequantisation, one binary32 product with the combined per-row/per-column
-     factor: c_ij = fl32(fl32(acc_ij) * fl32(d_i * d_j)).  The factor is a
-     single symmetric product, so computing the transposed product (as the
-     GPU does for T = B~ B) rounds identically;
+  3. dequantisation by the row factor of the left operand, then by the column
+     factor of the right operand, each product rounded to binary32:
+     c_ij = fl32(fl32(fl32(acc_ij) * d_i) * d_j).  Alg. 2 does not fix the
+     order; this is the reading the oracle takes (row factor first);
   4. alpha/beta: out = fl32(alpha * c) when beta == 0 (C is not read), else
      fl32(fl32(alpha * c) + fl32(beta * C)).
 
@@ -52,8 +52,8 @@ def int_gemm(Lq, Rq):
 
 def epilogue(acc, dL, dR, alpha=1.0, beta=0.0, Cin=None):
     """Dequantising epilogue with the alpha/beta update of Alg. 2."""
-    s = fl32(np.asarray(dL, np.float64)[:, None] * np.asarray(dR, np.float64)[None, :])
-    c = fl32(fl32(np.asarray(acc, np.float64)) * s)
+    c = fl32(fl32(np.asarray(acc, np.float64)) * np.asarray(dL, np.float64)[:, None])
+    c = fl32(c * np.asarray(dR, np.float64)[None, :])
     a = fl32(alpha)
     out = fl32(a * c)
     if beta != 0.0:

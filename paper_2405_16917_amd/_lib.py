@@ -30,7 +30,7 @@ EXPORTS = (
     "lramm_status_poll", "lramm_quantize", "lramm_pitch", "lramm_gemm_nt",
     "lramm_gemm_nt_workspace", "lramm_omega", "lramm_cholqr2",
     "lramm_cholqr2_workspace", "lramm_dense_gemm_nt", "lramm_plan_set_timing", "lramm_stage_times",
-    "lramm_stage_name",
+    "lramm_stage_name", "lramm_intermediate",
 )
 NSTAGES = 22
 
@@ -80,6 +80,8 @@ def load(path=LIB_PATH):
         "lramm_forward": ([P, P, I64, P, I64, P, I64, P, I64, P, SZ, P], I32),
         "lramm_factors": ([P, P, ctypes.POINTER(P), ctypes.POINTER(I64), ctypes.POINTER(P),
                            ctypes.POINTER(I64)], I32),
+        "lramm_intermediate": ([P, P, I32, ctypes.POINTER(P), ctypes.POINTER(I64), ctypes.POINTER(I64),
+                                ctypes.POINTER(I64), ctypes.POINTER(I32)], I32),
         "lramm_backward": ([P, P, I64, P, I64, P, I64, P, I64, P, I64, P, SZ, P], I32),
         "lramm_status_poll": ([P, P, P, ctypes.POINTER(ctypes.c_uint32)], I32),
         "lramm_quantize": ([I64, I64, P, I64, I32, I32, I32, P, I64, P, P, P], I32),
@@ -265,6 +267,18 @@ class LrammPlan:
         Q = ws[qo:qo + d.m * ldq.value * 8].view(torch.float64).view(d.m, ldq.value)[:, :self.l]
         Bt = ws[bo:bo + self.l * ldbt.value * 4].view(torch.float32).view(self.l, ldbt.value)
         return Q, Bt
+
+    VIEWS = {"Y": 0, "Q": 1, "Bt": 2, "Tt": 3}
+
+    def intermediate(self, ws, name):
+        """View of one FP intermediate ("Y", "Q", "Bt" or "Tt") inside ws."""
+        ptr, rows, cols, ld, dt = P(), I64(), I64(), I64(), I32()
+        _check(load().lramm_intermediate(self._h, _ptr(ws), self.VIEWS[name], ctypes.byref(ptr), ctypes.byref(rows),
+                                         ctypes.byref(cols), ctypes.byref(ld), ctypes.byref(dt)),
+               "lramm_intermediate")
+        esz, tdt = (8, torch.float64) if dt.value == F64 else (4, torch.float32)
+        off = ptr.value - ws.data_ptr()
+        return ws[off:off + rows.value * ld.value * esz].view(tdt).view(rows.value, ld.value)[:, :cols.value]
 
     def backward(self, dC, A, B, ws, dA=None, dB=None, need_dA=True, need_dB=True):
         d = self.desc

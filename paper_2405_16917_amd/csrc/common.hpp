@@ -159,7 +159,7 @@ lramm_status launch_quantize(int64_t rows, int64_t cols, const void* X, int64_t 
 lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void* Lq, int64_t ldl,
                             const float* dL, const void* Rq, int64_t ldr, const float* dR, float alpha,
                             float beta, void* C, int64_t ldc, int ctype, int32_t* acc_out, int64_t ld_acc,
-                            void* ws, size_t ws_bytes, hipStream_t s);
+                            void* ws, size_t ws_bytes, hipStream_t s, bool col_first = false);
 size_t gemm_nt_workspace(int64_t M, int64_t N, int64_t K, int fmt);
 
 lramm_status launch_omega(uint64_t seed, int64_t k, int64_t l, int64_t lrows, float* OmegaT, int64_t ldo,

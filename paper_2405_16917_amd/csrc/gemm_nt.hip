@@ -7,16 +7,18 @@
 // Tiling: 256 threads = 4 wavefronts in a 2 x 2 grid; a block tile is
 // BM x BN, each wavefront owns (BM/2) x (BN/2) as (BM/64) x (BN/64) tiles of
 // the 32 x 32 MFMA.  K advances in stages of 128 bytes of the widened operand
-// (128 int8 / int4 elements, 64 bf16 elements), double-buffered in LDS with a
+// (128 int8 / int4 / fp8 elements, 64 bf16 elements), double-buffered in LDS with a
 // 16-byte row pad (144-byte pitch) so the 16-byte MFMA operand reads of 8
 // consecutive rows fall in distinct banks; bytes past the padded K read as
 // zero.  Packed int4 rows are read as 64 bytes per stage and widened to int8
 // on the way into LDS (no int4 MFMA on CDNA4), so the MFMA loop is the int8
-// one.  The epilogue stages the accumulators in LDS and writes 4 consecutive
-// outputs per thread (16-byte stores), applying the dequantisation there.
+// one.  fp8 (OCP e4m3) runs on the 32 x 32 x 64 f8f6f4 MFMA with unit block
+// scales, 32 bytes of K per lane.  The epilogue stages the accumulators in
+// LDS and writes 4 consecutive outputs per thread (16-byte stores), applying
+// the dequantisation there.
 //
 // MFMA operand layout (v_mfma_*_32x32x*): lane l supplies row (l % 32) of its
-// operand and a 16-byte slice of K chosen by l / 32; both operands use the
+// operand and a 16-byte (fp8: 32-byte) slice of K chosen by l / 32; both operands use the
 // same slice mapping, so the K order inside a 32-byte chunk does not matter.
 // Result layout: lane l, accumulator r holds row 8(r/4) + 4(l/32) + r%4,
 // column l % 32 of the 32 x 32 tile.
@@ -27,7 +29,18 @@
 
 namespace lramm {
 
-enum { KIND_I8 = 0, KIND_I4 = 1, KIND_BF16 = 2 };
+enum { KIND_I8 = 0, KIND_I4 = 1, KIND_BF16 = 2, KIND_F8 = 3 };
+
+// integer accumulators (exact); otherwise FP32 accumulators
+template <int KIND>
+constexpr bool kIntAcc = KIND == KIND_I8 || KIND == KIND_I4;
+// per-row / per-column dequantisation factors (all but bf16)
+template <int KIND>
+constexpr bool kScaled = KIND != KIND_BF16;
+// K bytes one MFMA consumes: 32 for the 32x32x32 int8 and 32x32x16 bf16
+// forms, 64 for the 32x32x64 fp8 form
+template <int KIND>
+constexpr int kChunk = KIND == KIND_F8 ? 64 : 32;
 
 struct GemmArgs {
   int M, N;
@@ -45,6 +58,7 @@ struct GemmArgs {
   int64_t ldc;             // elements
   int ctype;
   int c_vec;               // C rows 16-byte aligned (vector stores)
+  int col_first;           // dequantise by dR before dL (the output is a transposed product)
   int32_t* acc_out;
   int64_t ld_acc;
   int32_t* part;           // split-K partials [split][M][N] (int32 or float bits)
@@ -62,6 +76,14 @@ template <>
 struct Acc<KIND_I4> { typedef v16i T; };
 template <>
 struct Acc<KIND_BF16> { typedef v16f T; };
+template <>
+struct Acc<KIND_F8> { typedef v16f T; };
+
+// One lane's operand fragment: 16 bytes, or 32 for fp8.
+template <int KIND>
+struct Frag {
+  uint4 x[kChunk<KIND> / 32];
+};
 
 // Sign-extend the 8 nibbles of w to 8 bytes in element order
 // (byte j of w holds element 2j in its low and 2j+1 in its high nibble).
@@ -130,14 +152,31 @@ struct TileLoader {
 };
 
 template <int KIND>
-__device__ __forceinline__ void mfma_32x32(typename Acc<KIND>::T& acc, const uint4& a, const uint4& b) {
+__device__ __forceinline__ Frag<KIND> load_frag(const uint8_t* p) {
+  Frag<KIND> f;
+#pragma unroll
+  for (int i = 0; i < kChunk<KIND> / 32; ++i) f.x[i] = *reinterpret_cast<const uint4*>(p + 16 * i);
+  return f;
+}
+
+// fp8 operands: format code 0 (OCP e4m3) for both; the block scales are
+// E8M0 127, i.e. 2^0, so the instruction is the plain fp8 product.
+constexpr int kFmtE4M3 = 0, kScaleOne = 127;
+
+template <int KIND>
+__device__ __forceinline__ void mfma_32x32(typename Acc<KIND>::T& acc, const Frag<KIND>& a, const Frag<KIND>& b) {
   if constexpr (KIND == KIND_BF16) {
-    v8bf av = __builtin_bit_cast(v8bf, a);
-    v8bf bv = __builtin_bit_cast(v8bf, b);
+    v8bf av = __builtin_bit_cast(v8bf, a.x[0]);
+    v8bf bv = __builtin_bit_cast(v8bf, b.x[0]);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+  } else if constexpr (KIND == KIND_F8) {
+    v8i av = __builtin_bit_cast(v8i, a);
+    v8i bv = __builtin_bit_cast(v8i, b);
+    acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, kFmtE4M3, kFmtE4M3, 0, kScaleOne, 0,
+                                                           kScaleOne);
   } else {
-    v4i av = __builtin_bit_cast(v4i, a);
-    v4i bv = __builtin_bit_cast(v4i, b);
+    v4i av = __builtin_bit_cast(v4i, a.x[0]);
+    v4i bv = __builtin_bit_cast(v4i, b.x[0]);
     acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv, acc, 0, 0, 0);
   }
 }
@@ -147,12 +186,21 @@ __device__ __forceinline__ float load_cin(const void* C, int64_t idx, int ctype)
                             : bf16_to_float(reinterpret_cast<const uint16_t*>(C)[idx]);
 }
 
-// Dequantising epilogue of one element: c = fl32(fl32(acc) * fl32(dL dR));
-// out = fl32(alpha c) [+ fl32(beta Cin)].  bf16 operands have no scales.
-template <bool INT>
-__device__ __forceinline__ float epi_value(float accf, float dl, float dr, float alpha, float beta, float cin) {
+// Dequantising epilogue of one element: c = fl32(fl32(fl32(acc) * d_i) * d_j)
+// with d_i the row factor of the left operand of the product and d_j the
+// column factor of the right one; out = fl32(alpha c) [+ fl32(beta Cin)].
+// When the kernel computes a transposed product (C^T = R L^T), the paper's
+// row factor is the kernel's column factor dR, so col_first swaps the order.
+// bf16 operands have no scales.
+template <bool SCALED>
+__device__ __forceinline__ float epi_value(float accf, float dl, float dr, int col_first, float alpha, float beta,
+                                           float cin) {
   float c = accf;
-  if (INT) c = __fmul_rn(c, __fmul_rn(dl, dr));
+  if (SCALED) {
+    const float f1 = col_first ? dr : dl;
+    const float f2 = col_first ? dl : dr;
+    c = __fmul_rn(__fmul_rn(c, f1), f2);
+  }
   c = __fmul_rn(alpha, c);
   if (beta != 0.0f) c = __fadd_rn(c, __fmul_rn(beta, cin));
   return c;
@@ -160,7 +208,7 @@ __device__ __forceinline__ float epi_value(float accf, float dl, float dr, float
 
 // Store phase for 4 consecutive columns gn..gn+3 of row gm: raw accumulator
 // bits v (int32 for integer kinds, float bits otherwise).
-template <bool INT, bool SPLIT>
+template <int KIND, bool SPLIT>
 __device__ __forceinline__ void store4(const GemmArgs& a, int split, int gm, int gn, const int32_t v[4]) {
   if constexpr (SPLIT) {
     int32_t* dst = a.part + ((int64_t)split * a.M + gm) * a.N + gn;
@@ -173,22 +221,24 @@ __device__ __forceinline__ void store4(const GemmArgs& a, int split, int gm, int
     }
     return;
   }
-  if constexpr (INT) {
+  if constexpr (kIntAcc<KIND>) {
     if (a.acc_out) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
         if (gn + q < a.N) a.acc_out[(int64_t)gm * a.ld_acc + gn + q] = v[q];
     }
   }
-  const float dl = INT ? a.dL[gm] : 1.0f;
+  constexpr bool SCALED = kScaled<KIND>;
+  const float dl = SCALED ? a.dL[gm] : 1.0f;
   float out[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int n = gn + q < a.N ? gn + q : a.N - 1;
-    const float accf = INT ? (float)v[q] : __int_as_float(v[q]);   // v_cvt_f32_i32 rounds to nearest even
-    const float dr = INT ? a.dR[n] : 1.0f;
+    // v_cvt_f32_i32 rounds to nearest even
+    const float accf = kIntAcc<KIND> ? (float)v[q] : __int_as_float(v[q]);
+    const float dr = SCALED ? a.dR[n] : 1.0f;
     const float cin = a.beta != 0.0f ? load_cin(a.C, (int64_t)gm * a.ldc + n, a.ctype) : 0.0f;
-    out[q] = epi_value<INT>(accf, dl, dr, a.alpha, a.beta, cin);
+    out[q] = epi_value<SCALED>(accf, dl, dr, a.col_first, a.alpha, a.beta, cin);
   }
   const int64_t base = (int64_t)gm * a.ldc + gn;
   const bool full = gn + 3 < a.N;
@@ -266,7 +316,8 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
 
   const int arow = wm * (BM / 2) + (lane & 31);
   const int brow = wn * (BN / 2) + (lane & 31);
-  const int kofs = (lane >> 5) * 16;
+  constexpr int CH = kChunk<KIND>;
+  const int kofs = (lane >> 5) * (CH / 2);
 
   for (int st = st0; st < st1; ++st) {
     const int buf = (st - st0) & 1;
@@ -278,12 +329,12 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
     const uint8_t* A = sA + buf * BM * kLdsPitch;
     const uint8_t* B = sB + buf * BN * kLdsPitch;
 #pragma unroll
-    for (int c = 0; c < kStage / 32; ++c) {
-      uint4 av[RM], bv[RN];
+    for (int c = 0; c < kStage / CH; ++c) {
+      Frag<KIND> av[RM], bv[RN];
 #pragma unroll
-      for (int i = 0; i < RM; ++i) av[i] = *reinterpret_cast<const uint4*>(A + (arow + 32 * i) * kLdsPitch + c * 32 + kofs);
+      for (int i = 0; i < RM; ++i) av[i] = load_frag<KIND>(A + (arow + 32 * i) * kLdsPitch + c * CH + kofs);
 #pragma unroll
-      for (int j = 0; j < RN; ++j) bv[j] = *reinterpret_cast<const uint4*>(B + (brow + 32 * j) * kLdsPitch + c * 32 + kofs);
+      for (int j = 0; j < RN; ++j) bv[j] = load_frag<KIND>(B + (brow + 32 * j) * kLdsPitch + c * CH + kofs);
 #pragma unroll
       for (int i = 0; i < RM; ++i)
 #pragma unroll
@@ -307,13 +358,12 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
       for (int r = 0; r < 16; ++r) {
         const int rr = wm * (BM / 2) + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         int32_t bits;
-        if constexpr (KIND == KIND_BF16) bits = __float_as_int(acc[i][j][r]);
-        else bits = acc[i][j][r];
+        if constexpr (kIntAcc<KIND>) bits = acc[i][j][r];
+        else bits = __float_as_int(acc[i][j][r]);
         sC[rr * kCPitch + cc] = bits;
       }
     }
   __syncthreads();
-  constexpr bool INT = KIND != KIND_BF16;
   constexpr int kQuads = BM * BN / 4;
 #pragma unroll 4
   for (int q = tid; q < kQuads; q += 256) {
@@ -322,13 +372,13 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
     if (gm < a.M && gn < a.N) {
       const int4 w = *reinterpret_cast<const int4*>(sC + rr * kCPitch + cq);
       const int32_t v[4] = {w.x, w.y, w.z, w.w};
-      store4<INT, SPLIT>(a, split, gm, gn, v);
+      store4<KIND, SPLIT>(a, split, gm, gn, v);
     }
   }
 }
 
 // Sum the split-K partials in split order and apply the epilogue.
-template <bool INT>
+template <int KIND>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs a, int nsplit) {
   const int64_t total = (int64_t)a.M * a.N;
   const int64_t q = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
@@ -338,7 +388,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs a, int nspl
   const bool vec = (a.N & 3) == 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    if (INT) {
+    if (kIntAcc<KIND>) {
       int32_t s = 0;
       if (q + j < total)
         for (int k = 0; k < nsplit; ++k) s += a.part[(int64_t)k * total + q + j];
@@ -351,7 +401,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs a, int nspl
     }
   }
   if (vec) {
-    store4<INT, false>(a, 0, gm, gn, v);
+    store4<KIND, false>(a, 0, gm, gn, v);
   } else {
     // row-crossing quad: store element by element
     for (int j = 0; j < 4 && q + j < total; ++j) {
@@ -359,7 +409,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs a, int nspl
       int32_t one[4] = {v[j], 0, 0, 0};
       GemmArgs b = a;
       b.N = n2 + 1;   // limit the store to one column
-      store4<INT, false>(b, 0, m2, n2, one);
+      store4<KIND, false>(b, 0, m2, n2, one);
     }
   }
 }
@@ -371,6 +421,7 @@ static int kind_of(int fmt) {
     case LRAMM_INT8: return KIND_I8;
     case LRAMM_INT4: return KIND_I4;
     case LRAMM_BF16F: return KIND_BF16;
+    case LRAMM_FP8: return KIND_F8;
     default: return -1;
   }
 }
@@ -428,7 +479,7 @@ static void launch_kind(const GemmArgs& a, const Plan& p, hipStream_t s) {
 lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void* Lq, int64_t ldl,
                             const float* dL, const void* Rq, int64_t ldr, const float* dR, float alpha,
                             float beta, void* C, int64_t ldc, int ctype, int32_t* acc_out, int64_t ld_acc,
-                            void* ws, size_t ws_bytes, hipStream_t s) {
+                            void* ws, size_t ws_bytes, hipStream_t s, bool col_first) {
   int kind = kind_of(fmt);
   if (kind < 0) return LRAMM_E_UNSUPPORTED;
   if (M == 0 || N == 0) return LRAMM_OK;
@@ -457,22 +508,25 @@ lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void
   a.tiles_m = p.tiles_m;
   a.tiles_n = p.tiles_n;
   a.kw = p.kw;
+  a.col_first = col_first ? 1 : 0;
   a.c_vec = (ldc % 4 == 0) && ((uintptr_t)C % (ctype == LRAMM_F32 ? 16 : 8) == 0);
   if (K == 0) p.nst = a.nst = 0;
   switch (kind) {
     case KIND_I8: launch_kind<KIND_I8>(a, p, s); break;
     case KIND_I4: launch_kind<KIND_I4>(a, p, s); break;
+    case KIND_F8: launch_kind<KIND_F8>(a, p, s); break;
     default: launch_kind<KIND_BF16>(a, p, s); break;
   }
   LRAMM_HIP(hipGetLastError());
   if (p.split > 1) {
     int64_t quads = ceil_div(M * N, 4);
-    if (kind == KIND_BF16)
-      hipLaunchKernelGGL(splitk_reduce_kernel<false>, dim3((unsigned)ceil_div(quads, 256)), dim3(256), 0, s, a,
-                         p.split);
-    else
-      hipLaunchKernelGGL(splitk_reduce_kernel<true>, dim3((unsigned)ceil_div(quads, 256)), dim3(256), 0, s, a,
-                         p.split);
+    const dim3 g((unsigned)ceil_div(quads, 256));
+    switch (kind) {
+      case KIND_I8: hipLaunchKernelGGL(splitk_reduce_kernel<KIND_I8>, g, dim3(256), 0, s, a, p.split); break;
+      case KIND_I4: hipLaunchKernelGGL(splitk_reduce_kernel<KIND_I4>, g, dim3(256), 0, s, a, p.split); break;
+      case KIND_F8: hipLaunchKernelGGL(splitk_reduce_kernel<KIND_F8>, g, dim3(256), 0, s, a, p.split); break;
+      default: hipLaunchKernelGGL(splitk_reduce_kernel<KIND_BF16>, g, dim3(256), 0, s, a, p.split); break;
+    }
     LRAMM_HIP(hipGetLastError());
   }
   return LRAMM_OK;

@@ -51,7 +51,7 @@ using namespace lramm;
 
 namespace {
 
-bool valid_fmt(int f) { return f == LRAMM_INT8 || f == LRAMM_INT4 || f == LRAMM_BF16F; }
+bool valid_fmt(int f) { return f == LRAMM_INT8 || f == LRAMM_INT4 || f == LRAMM_FP8 || f == LRAMM_BF16F; }
 bool valid_io(int t) { return t == LRAMM_F32 || t == LRAMM_BF16; }
 
 size_t carve(size_t* cur, size_t bytes) {
@@ -118,7 +118,14 @@ void hook_end(void* c) {
   h->open.pop_back();
 }
 
-int64_t qk_bound(int fmt) { return fmt == LRAMM_INT4 ? (int64_t)(2147483647LL / 49) : (int64_t)(2147483647LL / 16129); }
+// Longest K whose products cannot leave the accumulator's range: int32 for
+// the integer formats (K * qmax^2 < 2^31); fp8 and bf16 accumulate in FP32,
+// where K * 448^2 stays far below FLT_MAX for any supported K.
+int64_t qk_bound(int fmt) {
+  if (fmt == LRAMM_INT4) return (int64_t)(2147483647LL / 49);
+  if (fmt == LRAMM_INT8) return (int64_t)(2147483647LL / 16129);
+  return (int64_t)INT32_MAX;
+}
 
 }  // namespace
 
@@ -381,8 +388,10 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
   float* sBt = at<float>(W, P->off_sBt);
   float* Tt = at<float>(W, P->off_Tt);
   TIMED(ST_QUANT_BT, launch_quantize(l, k, Bt, k, LRAMM_F32, d.fmt_g1, 0, Btq, P->pBtq, sBt, flags, s));
+  // Tt is T transposed: the row factor of T (that of B~) is this product's
+  // column factor, so the epilogue applies it first
   TIMED(ST_G1, launch_gemm_nt(n, l, k, d.fmt_g1, Bc, P->pBc, sBc, Btq, P->pBtq, sBt, 1.0f, 0.0f, Tt, lp, LRAMM_F32,
-                              nullptr, 0, split, sb, s));
+                              nullptr, 0, split, sb, s, true));
   // G2: C = alpha Q_r . Tt_q^T + beta C  (m x n)
   uint8_t* Qr = at<uint8_t>(W, P->off_Qr);
   float* sQr = at<float>(W, P->off_sQr);
@@ -405,6 +414,29 @@ lramm_status lramm_factors(const lramm_plan* P, const void* ws, const double** Q
   if (ldq) *ldq = P->lp;
   if (Bt) *Bt = reinterpret_cast<const float*>(base + P->off_Bt);
   if (ldbt) *ldbt = P->d.k;
+  return LRAMM_OK;
+}
+
+lramm_status lramm_intermediate(const lramm_plan* P, const void* ws, int32_t which, const void** ptr,
+                                int64_t* rows, int64_t* cols, int64_t* ld, int32_t* dtype) {
+  if (!P || !ws || !ptr || !rows || !cols || !ld || !dtype) return LRAMM_E_INVALID;
+  const uint8_t* base = reinterpret_cast<const uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
+  const lramm_desc& d = P->d;
+  switch (which) {
+    case LRAMM_VIEW_Y:
+      *ptr = base + P->off_Y, *rows = d.m, *cols = P->l, *ld = P->lp, *dtype = LRAMM_F32;
+      break;
+    case LRAMM_VIEW_Q:
+      *ptr = base + P->off_Q, *rows = d.m, *cols = P->l, *ld = P->lp, *dtype = LRAMM_F64;
+      break;
+    case LRAMM_VIEW_BT:
+      *ptr = base + P->off_Bt, *rows = P->l, *cols = d.k, *ld = d.k, *dtype = LRAMM_F32;
+      break;
+    case LRAMM_VIEW_TT:
+      *ptr = base + P->off_Tt, *rows = d.n, *cols = P->l, *ld = P->lp, *dtype = LRAMM_F32;
+      break;
+    default: return LRAMM_E_INVALID;
+  }
   return LRAMM_OK;
 }
 
@@ -459,7 +491,7 @@ lramm_status lramm_quantize(int64_t rows, int64_t cols, const void* X, int64_t l
                             void* stream) {
   if (rows < 0 || cols < 0) return LRAMM_E_SHAPE;
   if ((rows > 0 && cols > 0) && (!X || !Xq || !scales)) return LRAMM_E_INVALID;
-  if (!valid_fmt(fmt) && fmt != LRAMM_FP8) return LRAMM_E_INVALID;
+  if (!valid_fmt(fmt)) return LRAMM_E_INVALID;
   if (xtype != LRAMM_F32 && xtype != LRAMM_BF16 && xtype != LRAMM_F64) return LRAMM_E_INVALID;
   if (transpose != 0 && transpose != 1) return LRAMM_E_INVALID;
   if (ldx < cols) return LRAMM_E_SHAPE;
@@ -486,7 +518,7 @@ lramm_status lramm_gemm_nt(int64_t M, int64_t N, int64_t K, int32_t fmt, const v
   if (ldl < pitch_bytes(K, fmt) || ldr < pitch_bytes(K, fmt) || ldl % 16 || ldr % 16) return LRAMM_E_SHAPE;
   if ((uintptr_t)Lq % 16 || (uintptr_t)Rq % 16) return LRAMM_E_INVALID;
   if (ldc < N) return LRAMM_E_SHAPE;
-  if (acc_out && (fmt == LRAMM_BF16F || ld_acc < N)) return LRAMM_E_INVALID;
+  if (acc_out && (fmt == LRAMM_BF16F || fmt == LRAMM_FP8 || ld_acc < N)) return LRAMM_E_INVALID;
   if (fmt != LRAMM_BF16F && K > qk_bound(fmt)) return LRAMM_E_OVERFLOW;
   return launch_gemm_nt(M, N, K, fmt, Lq, ldl, dL, Rq, ldr, dR, alpha, beta, C, ldc, ctype, acc_out, ld_acc, ws,
                         ws_bytes, (hipStream_t)stream);

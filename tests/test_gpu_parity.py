@@ -37,8 +37,22 @@ def bf16_round(x):
     return synth.to_dtype(x, "bf16").astype(np.float64)
 
 
+def e4m3_value(b):
+    """Value of OCP fp8 e4m3 bytes (sign, 4 exponent bits with bias 7, 3
+    mantissa bits; exponent field 0 is subnormal, 2^-6 * m/8)."""
+    b = np.asarray(b, np.int64)
+    sign = np.where(b & 0x80, -1.0, 1.0)
+    e = (b >> 3) & 0xF
+    m = (b & 7).astype(np.float64)
+    mag = np.where(e == 0, m / 8.0 * 2.0**-6, (1.0 + m / 8.0) * np.exp2(e - 7.0))
+    assert not np.any((b & 0x7F) == 0x7F), "NaN code"
+    return sign * mag
+
+
 def codes_from(Xq, fmt, K):
     q = Xq.cpu().numpy()
+    if fmt == "fp8":
+        return e4m3_value(q[:, :K]), q
     if fmt == "int8":
         return q.view(np.int8)[:, :K].astype(np.int64), q
     if fmt == "int4":
@@ -50,7 +64,7 @@ def codes_from(Xq, fmt, K):
 
 
 def pad_bytes(q, fmt, K):
-    used = {"int8": K, "int4": (K + 1) // 2, "bf16": 2 * K}[fmt]
+    used = {"int8": K, "int4": (K + 1) // 2, "bf16": 2 * K, "fp8": K}[fmt]
     return q[:, used:]
 
 
@@ -66,7 +80,7 @@ def test_single_hip_runtime_and_library_loaded(lib):
 
 # ------------------------------------------------------------- quantiser --
 
-@pytest.mark.parametrize("fmt", ["int8", "int4", "bf16"])
+@pytest.mark.parametrize("fmt", ["int8", "int4", "fp8", "bf16"])
 @pytest.mark.parametrize("shape", [(1, 1), (37, 50), (130, 257), (512, 512), (64, 4099)])
 def test_quantize_rows_bit_exact(lib, fmt, shape):
     rng = np.random.default_rng(shape[0] * 1000 + shape[1] + len(fmt))
@@ -81,7 +95,7 @@ def test_quantize_rows_bit_exact(lib, fmt, shape):
     assert not pad_bytes(raw, fmt, shape[1]).any()
 
 
-@pytest.mark.parametrize("fmt", ["int8", "int4", "bf16"])
+@pytest.mark.parametrize("fmt", ["int8", "int4", "fp8", "bf16"])
 @pytest.mark.parametrize("shape", [(1, 1), (50, 37), (257, 130), (512, 512), (4099, 70)])
 def test_quantize_cols_bit_exact(lib, fmt, shape):
     rng = np.random.default_rng(shape[0] * 1000 + shape[1] + len(fmt) + 1)
@@ -198,6 +212,35 @@ def test_gemm_bf16_operands(lib, MNK):
     assert OL.rel_fro(C, ref) <= 1e-6 * np.sqrt(K / 64) + 1e-7
 
 
+@pytest.mark.parametrize("MNK", [(1, 1, 1), (64, 64, 64), (100, 37, 257), (130, 200, 1000), (512, 512, 4096)])
+def test_gemm_fp8_operands(lib, MNK):
+    # fp8 products are exact in FP32, but the 32x32x64 MFMA adds the 64
+    # products of one instruction at reduced precision (measured: up to about
+    # 2^-16 of their absolute sum), then accumulates in FP32.  Bound: 2^-14 of
+    # sum|a b| (code units) for the in-instruction sums, K 2^-24 of it for the
+    # FP32 accumulation, plus the two roundings of the epilogue.
+    M, N, K = MNK
+    rng = np.random.default_rng(M + 3 * N + 5 * K)
+    L = f32(rng.standard_normal((M, K)) * np.exp(rng.uniform(-4, 4, (M, 1))))
+    R = f32(rng.standard_normal((N, K)) * np.exp(rng.uniform(-4, 4, (N, 1))))
+    Lq, dL = lib.lramm_quantize(g(L), "fp8")
+    Rq, dR = lib.lramm_quantize(g(R), "fp8")
+    Lc, dLr = OQ.quantize_rows(L, "fp8")
+    Rc, dRr = OQ.quantize_rows(R, "fp8")
+    assert np.array_equal(dL.cpu().numpy().astype(np.float64), dLr)
+    ref = OG.epilogue(Lc @ Rc.T, dLr, dRr)
+    S = np.abs(Lc) @ np.abs(Rc).T
+    bound = dLr[:, None] * dRr[None, :] * ((2.0**-14 + K * 2.0**-24) * S) + \
+        3 * np.spacing(np.abs(ref).astype(np.float32))
+    ws = torch.empty(max(1, lib.lramm_gemm_nt_workspace(M, N, K, "fp8")), dtype=torch.uint8, device=DEV)
+    for w in (ws, None):
+        C = lib.lramm_gemm_nt(M, N, K, "fp8", Lq, dL, Rq, dR, ws=w).double().cpu().numpy()
+        assert np.all(np.abs(C - ref) <= bound), np.max(np.abs(C - ref) - bound)
+    # the fp8 product approximates the exact one at e4m3 resolution
+    if K >= 64:
+        assert OL.rel_fro(C, L @ R.T) < 0.1
+
+
 @pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32])
 def test_dense_comparator(lib, dtype):
     M, N, K = 256, 192, 512
@@ -304,6 +347,59 @@ def test_lramm_forward_matches_oracle(lib, case):
     Qg = Qg.cpu().numpy()
     assert np.max(np.abs(Qg - ref["Q"])) <= 1e-11
     assert OL.rel_fro(Btg.cpu().numpy(), ref["Bt"]) <= 1e-5
+
+
+FP_CASES = [
+    (512, 512, 512, 64, 10, 1, 32.0, ("bf16",) * 4),
+    (512, 512, 512, 64, 10, 1, 32.0, ("fp8",) * 4),
+    (300, 257, 190, 20, 5, 1, 12.0, ("fp8",) * 4),
+    (640, 384, 512, 100, 12, 1, 40.0, ("int8", "int8", "fp8", "fp8")),
+    (640, 384, 512, 100, 12, 0, 40.0, ("bf16", "bf16", "int8", "int8")),
+]
+# rel-F of one replayed stage (FP32 accumulation in the MFMA's own order;
+# the fp8 MFMA adds within an instruction at reduced precision)
+STAGE_TOL = {"int8": 1e-6, "int4": 1e-6, "bf16": 1e-5, "fp8": 1e-4}
+# end to end against the independent oracle: the stage differences move
+# values across quantiser rounding boundaries (one code step each), and the
+# sketch directions that the quantisation noise dominates rotate with them;
+# measured 1.2e-3 (bf16 stages) and 2.5e-2 (fp8 in every stage)
+INDEP_TOL = {"int8": 1e-5, "int4": 1e-5, "bf16": 5e-3, "fp8": 6e-2}
+
+
+@pytest.mark.parametrize("case", FP_CASES)
+def test_lramm_forward_fp_formats(lib, case):
+    """Formats with FP32 accumulation: every stage is replayed from the GPU's
+    own input to that stage (the quantiser codes then agree bit for bit and
+    only the accumulation order differs), and the end result is compared
+    with the independent oracle at a looser tolerance."""
+    m, k, n, r, p, q, tau, fmt = case
+    A, s = synth.lowrank(m, k, synth.spectrum("exp", min(m, k), tau), 0)
+    B = synth.gaussian(k, n, 100)
+    om = synth.omega(k, r + p, 1)
+    C, plan, ws, flags = _run_forward(lib, A, B, r, p, q, fmt, omega=om)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    assert flags == 0
+    l = r + p
+    Y = plan.intermediate(ws, "Y").double().cpu().numpy()
+    Qg = plan.intermediate(ws, "Q").cpu().numpy()
+    Btg = plan.intermediate(ws, "Bt").double().cpu().numpy()
+    Tg = plan.intermediate(ws, "Tt").double().cpu().numpy().T
+    # orthonormalisation of the GPU's last sketch
+    Qh, _ = householder_qr(Y)
+    assert np.max(np.abs(Qg - Qh)) <= 1e-11
+    assert np.max(np.abs(Qg.T @ Qg - np.eye(l))) <= 1e-12
+    # the three products, each on the GPU's own operands
+    assert OL.rel_fro(Btg, OL._product(Qg.T, A64, fmt[1])) <= STAGE_TOL[fmt[1]]
+    assert OL.rel_fro(Tg, OL._product(Btg, B64, fmt[2])) <= STAGE_TOL[fmt[2]]
+    assert OL.rel_fro(C, OL._product(Qg, Tg, fmt[3])) <= STAGE_TOL[fmt[3]]
+    ref = OL.lramm_forward(A64, B64, r, p, q, fmt, omega=om.astype(np.float64))
+    err = OL.rel_fro(C, ref["C"])
+    print(f"fmt {fmt}: end-to-end rel-F vs oracle {err:.3e}")
+    assert err <= max(INDEP_TOL[f] for f in fmt)
+    # and the two are equally good approximations of the exact product
+    Cex = A64 @ B64
+    e_gpu, e_ref = OL.rel_fro(C, Cex), OL.rel_fro(ref["C"], Cex)
+    assert abs(e_gpu - e_ref) <= 0.05 * e_ref, (e_gpu, e_ref)
 
 
 def test_lramm_seeded_omega_and_alpha_beta(lib):

@@ -158,8 +158,7 @@ def _qmm(Lm, Rm):
         row = []
         for j in range(N):
             acc = sum(lq[i][0][t] * rq[j][0][t] for t in range(K))
-            s = _r32(lq[i][1] * rq[j][1])
-            row.append(_r32(_r32(float(acc)) * s))
+            row.append(_r32(_r32(_r32(float(acc)) * lq[i][1]) * rq[j][1]))
         out.append(row)
     return out
 
