@@ -1,13 +1,15 @@
 // CholeskyQR2 in FP64 for the range finder's orthonormalisation (paper
 // Sec. 2.2: a matrix Q with orthonormal columns spanning the sketch).  For a
-// rows x l matrix Y (FP32 or FP64):
+// rows x l matrix Y (FP32 or FP64), l' = l rounded up to 32:
 //
-//   G1 = Y^T Y (FP64)                 Gram, split over row chunks, summed in
-//                                      a fixed order (deterministic)
+//   G1 = Y^T Y (FP64)                 32 x 32 lower tiles x row chunks, the
+//                                      four wavefronts of a workgroup split
+//                                      the chunk; partials summed in a fixed
+//                                      order (deterministic)
 //   G1 = L L^T, X = L^-1              blocked right-looking Cholesky, 32 x 32
 //                                      tiles, one launch per panel; the block
 //                                      inverse is formed in the same launches
-//   Q1 = Y X^T                         FP64 GEMM
+//   Q1 = Y X^T                         tall-skinny FP64 product
 //   G2 = Q1^T Q1 = I + E,  Q = Q1 (chol(G2))^-T   second pass, restoring the
 //                                      orthogonality lost to cond(Y)^2 u (see
 //                                      the second-pass section)
@@ -18,7 +20,10 @@
 // FP64 matrix work uses v_mfma_f64_16x16x4.  Operand layout: lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; the 16 x 16 result puts
 // D[4 r + l / 16][l % 16] in accumulator r of lane l (rows interleaved across
-// the four lane groups, unlike the 32 x 32 MFMAs).
+// the four lane groups, unlike the 32 x 32 MFMAs).  The k index a lane feeds
+// may be permuted freely as long as A and B use the same permutation: the
+// tall-skinny kernels let lane group g feed k = k0 + 4 g + q in step q, so
+// that each lane reads 4 consecutive elements of a row with one vector load.
 //
 // Dependent columns (rank-deficient Y): a pivot whose square is at most
 // 64 l 2^-53 times the original Gram diagonal is dropped -- its column of L
@@ -34,200 +39,281 @@ __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Four consecutive elements x[0..3] of a row as doubles (one vector load).
+__device__ __forceinline__ void load4d(const float* p, double v[4]) {
+  const float4 f = *reinterpret_cast<const float4*>(p);
+  v[0] = f.x, v[1] = f.y, v[2] = f.z, v[3] = f.w;
+}
+__device__ __forceinline__ void load4d(const double* p, double v[4]) {
+  const double4 d = *reinterpret_cast<const double4*>(p);
+  v[0] = d.x, v[1] = d.y, v[2] = d.z, v[3] = d.w;
+}
+
+// v where ok, else zero, without letting the compiler move the load that
+// produced v under a branch (a select of a loaded value may be turned into a
+// conditional load followed by a full wait; a multiply keeps the load
+// unconditional).  Callers load from a valid address either way.
+__device__ __forceinline__ double keep_if(bool ok, double v) { return v * (ok ? 1.0 : 0.0); }
+
+// Lower 32 x 32 tile t (row-major over the lower triangle) -> (i, j), i >= j.
+__device__ __forceinline__ void lower_tile(int t, int& i, int& j) {
+  int di = 0;
+  while (t > di) {
+    t -= di + 1;
+    ++di;
+  }
+  i = di;
+  j = t;
+}
+
 // ------------------------------------------------------------------ Gram --
+// Partial Gram of one row chunk for one lower 32 x 32 tile (a, b), a >= b:
+//   part[chunk][32a + i][32b + j] = sum_{r in chunk} X[r][32a + i] X[r][32b + j],
+// columns >= ncols read as zero.  The four wavefronts take consecutive
+// quarters of the chunk; a wavefront computes the whole 32 x 32 tile (2 x 2
+// MFMA sub-tiles), four rows per step, each lane reading X[r][c..] of one
+// row (16 consecutive columns per lane group: coalesced).  The quarters are
+// summed in LDS in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void gram_kernel(int64_t rows, int lw, int ncols, const T* __restrict__ X,
+                                                   int64_t ldx, double* __restrict__ part, int64_t rows_per_chunk) {
+  __shared__ double red[4][NB][NB + 1];
+  int ta, tb;
+  lower_tile(blockIdx.x, ta, tb);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t c0 = (int64_t)blockIdx.y * rows_per_chunk;
+  const int64_t c1 = c0 + rows_per_chunk < rows ? c0 + rows_per_chunk : rows;
+  const int64_t per = ((c1 - c0 + 15) / 16) * 4;   // a quarter of the chunk, a multiple of 4 rows
+  const int64_t w0 = c0 + wave * per;
+  const int64_t w1 = w0 + per < c1 ? w0 + per : c1;
+  // columns past ncols are read from column 0 (valid data) and their Gram
+  // entries zeroed at the end, so the main loop needs no masks
+  int ca[2], cb[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    ca[s] = ta * NB + 16 * s + li;
+    cb[s] = tb * NB + 16 * s + li;
+    ca[s] = ca[s] < ncols ? ca[s] : 0;
+    cb[s] = cb[s] < ncols ? cb[s] : 0;
+  }
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+  auto mma = [&](const double (*a)[2], const double (*b)[2]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int si = 0; si < 2; ++si)
+#pragma unroll
+        for (int sj = 0; sj < 2; ++sj) acc[si][sj] = mfma_f64(a[q][si], b[q][sj], acc[si][sj]);
+  };
+  // full groups of 32 rows (8 MFMA steps); the next group is loaded while
+  // the current one is multiplied
+  const int64_t nfull = w1 > w0 ? (w1 - w0) / 32 : 0;
+  double av[8][2], bv[8][2];
+  auto fetch = [&](int64_t r, double (*a)[2], double (*b)[2]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const T* xr = X + (r + 4 * q + lk) * ldx;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        a[q][s] = (double)xr[ca[s]];
+        b[q][s] = (double)xr[cb[s]];
+      }
+    }
+  };
+  if (nfull > 0) fetch(w0, av, bv);
+  for (int64_t g = 0; g < nfull; ++g) {
+    double an[8][2], bn[8][2];
+    const bool more = g + 1 < nfull;
+    if (more) fetch(w0 + 32 * (g + 1), an, bn);
+    mma(av, bv);
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) av[q][u] = an[q][u], bv[q][u] = bn[q][u];
+    }
+  }
+  // the last partial group (rows past w1 contribute zero)
+  const int64_t rt = w0 + 32 * nfull;
+  if (rt < w1) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t rr = rt + 4 * q + lk;
+      const bool ok = rr < w1;
+      const T* xr = X + (ok ? rr : w0) * ldx;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        av[q][s] = keep_if(ok, (double)xr[ca[s]]);
+        bv[q][s] = keep_if(ok, (double)xr[cb[s]]);
+      }
+    }
+    mma(av, bv);
+  }
+#pragma unroll
+  for (int si = 0; si < 2; ++si)
+#pragma unroll
+    for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wave][16 * si + 4 * r + lk][16 * sj + li] = acc[si][sj][r];
+  __syncthreads();
+  double* out = part + (int64_t)blockIdx.y * lw * lw + (int64_t)ta * NB * lw + tb * NB;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e / NB, j = e % NB;
+    const bool in = ta * NB + i < ncols && tb * NB + j < ncols;
+    out[(int64_t)i * lw + j] = in ? (red[0][i][j] + red[1][i][j]) + (red[2][i][j] + red[3][i][j]) : 0.0;
+  }
+}
+
 // G (lower tiles) = sum over chunks in order; diag0 = diag(G).
-__global__ __launch_bounds__(256) void gram_reduce_kernel(int lw, int nchunks, const double* __restrict__ part,
-                                                          double* __restrict__ G, double* __restrict__ diag0,
-                                                          uint32_t* gate) {
-  int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e == 0) *gate = 0u;   // second-pass gate of this orthonormalisation
+//   mode 0 (first pass): clears the second-pass gate of this orthonormalisation;
+//   mode 1 (second pass): raises gate_bit when some |G_ij - delta_ij|, i, j < l_true,
+//   exceeds tau (or is NaN).
+__global__ __launch_bounds__(256) void gram_reduce_kernel(int lw, int l_true, int nchunks,
+                                                          const double* __restrict__ part, double* __restrict__ G,
+                                                          double* __restrict__ diag0, uint32_t* gate, int mode,
+                                                          uint32_t gate_bit, double tau) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (mode == 0 && e == 0) *gate = 0u;
   if (e >= (int64_t)lw * lw) return;
-  int i = (int)(e / lw), j = (int)(e % lw);
+  const int i = (int)(e / lw), j = (int)(e % lw);
   if ((i / NB) < (j / NB)) return;   // upper tiles are never read
   double s = 0.0;
   for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * lw * lw + e];
   G[e] = s;
   if (i == j) diag0[i] = s;
+  if (mode == 1 && i < l_true && j <= i) {
+    const double v = s - (i == j ? 1.0 : 0.0);
+    if (!(fabs(v) <= tau)) atomicOr(gate, gate_bit);
+  }
 }
 
-// ---------------------------------------------------- FP64 tile GEMM engine --
-// A 64 x 64 output tile on 4 wavefronts (2 x 2, each 32 x 32 = 2 x 2 MFMA
-// 16 x 16 sub-tiles) accumulating sum_k A(k, m) B(k, n) over [kbeg, kend).
-// K advances in stages of 32, double-buffered in LDS, both operands stored
-// K-major ([k][m]) so that an MFMA operand read is 16 consecutive doubles.
-// Operands come from functors fa(k, m, valid), fb(k, n, valid) returning
-// doubles: they load unconditionally from an in-range address and return zero
-// when the element is outside the operand (no branches around the loads, so a
-// stage's loads are all in flight together).  AK / BK: the operand is
-// contiguous along k in memory (threads then walk k first, keeping global
-// loads coalesced).
-constexpr int FT = 64, FK = 32, FP = FT + 2;
-struct F64Smem {
-  double a[2][FK][FP];
-  double b[2][FK][FP];
-};
+// ---------------------------------------------------- tall-skinny product --
+// Q[r][c] = (ADD ? X[r][c] : 0) + sum_{k < kend(c)} X[r][k] W[c][k]  for c < lw,
+// kend(c) = min(32 (c / 32 + 1), ncols): W is lower triangular by 32-blocks
+// (the blocks above its diagonal are never read).  Columns [lw, zero_to) of
+// Q are written as zero.
+//   solve: X = Y, W = L^-1                 (Q1 = Y L^-T)
+//   apply: X = Q1, W = M^T, ADD            (Q = Q1 + Q1 M)
+// A workgroup owns 16 rows, staged once in LDS as FP64 (zero past ncols and
+// past the last row).  Its eight wavefronts (two per SIMD) share the
+// 32-column blocks, block c costing c + 1 units of K, by longest-first
+// assignment to the least loaded wavefront (computed identically on every
+// lane).  A wavefront computes a 16 x 32 block (2 MFMA sub-tiles) per step of
+// 16 k: lane group g feeds k = 16 s + 4 g + q in MFMA q, reading its 4
+// values of X from LDS and of W with one vector load per sub-tile; W is
+// fetched four steps at a time, one group ahead of the MFMAs.
+constexpr int TS_ROWS = 16, TS_WAVES = 8;
 
-template <bool AK, bool BK, class FA, class FB>
-__device__ __forceinline__ void f64_gemm_tile(const FA& fa, const FB& fb, int kbeg, int kend, v4d acc[2][2],
-                                              F64Smem& sm) {
+__host__ __device__ constexpr int ts_pitch(int lw) { return lw + 4; }
+
+template <typename T, bool ADD>
+__global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int lw, int ncols,
+                                                              const T* __restrict__ X, int64_t ldx,
+                                                              const double* __restrict__ W, double* __restrict__ Q,
+                                                              int64_t ldq, int zero_to, int vec) {
+  extern __shared__ double sA[];   // TS_ROWS x ts_pitch(lw)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1, li = lane & 15, lk = lane >> 4;
-  double ra[8], rb[8];
-  auto gload = [&](int kb) {
+  const int li = lane & 15, lk = lane >> 4;
+  const int pitch = ts_pitch(lw);
+  const int64_t r0 = (int64_t)blockIdx.x * TS_ROWS;
+  // stage the row panel: 4 consecutive columns per thread
+  const int q4 = lw / 4;
+  for (int e = tid; e < TS_ROWS * q4; e += TS_WAVES * 64) {
+    const int rr = e / q4, c = (e % q4) * 4;
+    const int64_t gr = r0 + rr;
+    const bool rok = gr < rows;
+    const T* xr = X + (rok ? gr : rows - 1) * ldx;
+    double v[4];
+    if (vec && c + 4 <= ncols) {
+      load4d(xr + c, v);
+    } else {   // unaligned rows, or the row's last partial group: never read past column ncols
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int e = tid + 256 * i;
-      const int ka = AK ? e % FK : e / FT, ma = AK ? e / FK : e % FT;
-      const int kbb = BK ? e % FK : e / FT, nb = BK ? e / FK : e % FT;
-      const bool va = kb + ka < kend, vb = kb + kbb < kend;
-      ra[i] = fa(va ? kb + ka : kbeg, ma, va);
-      rb[i] = fb(vb ? kb + kbb : kbeg, nb, vb);
+      for (int q = 0; q < 4; ++q) v[q] = (double)xr[c + q < ncols ? c + q : 0];
     }
-  };
-  auto sstore = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int e = tid + 256 * i;
-      const int ka = AK ? e % FK : e / FT, ma = AK ? e / FK : e % FT;
-      const int kbb = BK ? e % FK : e / FT, nb = BK ? e / FK : e % FT;
-      sm.a[buf][ka][ma] = ra[i];
-      sm.b[buf][kbb][nb] = rb[i];
-    }
-  };
-  const int nst = kend > kbeg ? (kend - kbeg + FK - 1) / FK : 0;
-  if (nst == 0) return;
-  gload(kbeg);
-  sstore(0);
+    for (int q = 0; q < 4; ++q) sA[rr * pitch + c + q] = (rok && c + q < ncols) ? v[q] : 0.0;
+  }
   __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    const int buf = st & 1;
-    const bool more = st + 1 < nst;
-    if (more) gload(kbeg + (st + 1) * FK);
+  const int Tb = lw / NB;
+  int load[TS_WAVES];
 #pragma unroll
-    for (int kk = 0; kk < FK; kk += 4) {
-      double av[2], bv[2];
+  for (int u = 0; u < TS_WAVES; ++u) load[u] = 0;
+  for (int c = Tb - 1; c >= 0; --c) {
+    int w = 0;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        av[q] = sm.a[buf][kk + lk][wm * 32 + 16 * q + li];
-        bv[q] = sm.b[buf][kk + lk][wn * 32 + 16 * q + li];
-      }
+    for (int u = 1; u < TS_WAVES; ++u)
+      if (load[u] < load[w]) w = u;
+    load[w] += c + 1;
+    if (w != wave) continue;
+    const int cb0 = c * NB;
+    const int kend = cb0 + NB < ncols ? cb0 + NB : ncols;
+    const int ksteps = (kend + 15) / 16;
+    const int ngroups = (ksteps + 3) / 4;
+    const double* w0p = W + (int64_t)(cb0 + li) * lw + 4 * lk;
+    const double* w1p = W + (int64_t)(cb0 + 16 + li) * lw + 4 * lk;
+    const double* ap = sA + li * pitch + 4 * lk;
+    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+    double b[2][4][4];
+    auto fetch = [&](int g, double (*b0)[4], double (*b1)[4]) {
 #pragma unroll
-      for (int si = 0; si < 2; ++si)
-#pragma unroll
-        for (int sj = 0; sj < 2; ++sj) acc[si][sj] = mfma_f64(av[si], bv[sj], acc[si][sj]);
-    }
-    if (more) sstore(buf ^ 1);
-    __syncthreads();
-  }
-}
-
-// Output coordinates of accumulator element (si, sj, r) of this lane.
-__device__ __forceinline__ int f64_row(int si, int r) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave >> 1) * 32 + 16 * si + 4 * r + (lane >> 4);
-}
-__device__ __forceinline__ int f64_col(int sj) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave & 1) * 32 + 16 * sj + (lane & 15);
-}
-
-// Gram of a row chunk, 64 x 64 tiles (ta, tb), ta >= tb:
-// out[a][b] = sum_{r in chunk} X[r][a] X[r][b]; columns >= ncols read as zero.
-template <typename T>
-__global__ __launch_bounds__(256, 2) void gram64_kernel(int64_t rows, int lw, int ncols, const T* __restrict__ X,
-                                                        int64_t ldx, double* __restrict__ part,
-                                                        int64_t rows_per_chunk) {
-  __shared__ F64Smem sm;
-  int t = blockIdx.x, ta = 0;
-  while (t > ta) {
-    t -= ta + 1;
-    ++ta;
-  }
-  const int tb = t, a0 = ta * FT, b0 = tb * FT;
-  const int64_t r0 = (int64_t)blockIdx.y * rows_per_chunk;
-  const int64_t r1 = r0 + rows_per_chunk < rows ? r0 + rows_per_chunk : rows;
-  auto fa = [&](int k, int m, bool v) -> double {
-    const bool ok = v && a0 + m < ncols;
-    const double x = (double)X[(r0 + k) * ldx + (ok ? a0 + m : 0)];
-    return ok ? x : 0.0;
-  };
-  auto fb = [&](int k, int n, bool v) -> double {
-    const bool ok = v && b0 + n < ncols;
-    const double x = (double)X[(r0 + k) * ldx + (ok ? b0 + n : 0)];
-    return ok ? x : 0.0;
-  };
-  v4d acc[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
-  f64_gemm_tile<false, false>(fa, fb, 0, (int)(r1 - r0), acc, sm);
-  double* out = part + (int64_t)blockIdx.y * lw * lw;
-#pragma unroll
-  for (int si = 0; si < 2; ++si)
-#pragma unroll
-    for (int sj = 0; sj < 2; ++sj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = a0 + f64_row(si, r), j = b0 + f64_col(sj);
-        if (i < lw && j < lw) out[(int64_t)i * lw + j] = acc[si][sj][r];
-      }
-}
-
-// Q[r][c] = [Q1[r][c] +] sum_{k <= c} X[r][k] B(k, c) for the two solve
-// products of CholeskyQR, 64 x 64 output tiles over (rows, lw):
-//   APPLY == false:  B(k, c) = Linv[c][k]  (Q1 = X L^-T, X = Y in FP32/FP64)
-//   APPLY == true :  B(k, c) = M[k][c]     (Q = Q1 + Q1 M, X = Q1)
-// Columns in [lw, zero_to) of Q are written as zero.  When gate is non-null
-// the kernel is skipped if (*gate & gate_mask) is set.
-template <typename T, bool APPLY>
-__global__ __launch_bounds__(256, 2) void solve_gemm_kernel(int64_t rows, int lw, int ncols, const T* __restrict__ X,
-                                                            int64_t ldx, const double* __restrict__ B,
-                                                            double* __restrict__ Q, int64_t ldq, int zero_to,
-                                                            const uint32_t* gate, uint32_t gate_mask) {
-  if (gate && (*gate & gate_mask)) return;
-  __shared__ F64Smem sm;
-  const int64_t r0 = (int64_t)blockIdx.x * FT;
-  const int c0 = blockIdx.y * FT;
-  if (c0 >= lw) {
-    for (int e = threadIdx.x; e < FT * FT; e += 256) {
-      const int64_t r = r0 + e / FT;
-      const int c = c0 + e % FT;
-      if (r < rows && c < zero_to) Q[r * ldq + c] = 0.0;
-    }
-    return;
-  }
-  auto fa = [&](int k, int m, bool v) -> double {
-    const int64_t r = r0 + m;
-    const bool ok = v && r < rows && k < ncols;
-    const double x = (double)X[ok ? r * ldx + k : 0];
-    return ok ? x : 0.0;
-  };
-  auto fb = [&](int k, int n, bool v) -> double {
-    // both factors are triangular (Linv lower, M upper): B(k, c) = 0 for k > c,
-    // and the blocks beyond the diagonal are never written, so never read them
-    const int c = c0 + n;
-    const bool ok = v && c < lw && k <= c;
-    const double x = B[ok ? (APPLY ? (int64_t)k * lw + c : (int64_t)c * lw + k) : 0];
-    return ok ? x : 0.0;
-  };
-  v4d acc[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
-  const int kend = c0 + FT < lw ? c0 + FT : lw;      // triangular: terms with k > c vanish
-  if constexpr (APPLY) {
-    f64_gemm_tile<true, false>(fa, fb, 0, kend, acc, sm);
-  } else {
-    f64_gemm_tile<true, true>(fa, fb, 0, kend, acc, sm);
-  }
-#pragma unroll
-  for (int si = 0; si < 2; ++si)
-#pragma unroll
-    for (int sj = 0; sj < 2; ++sj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + f64_row(si, r);
-        const int c = c0 + f64_col(sj);
-        if (row < rows && c < zero_to) {
-          double v = acc[si][sj][r];
-          if constexpr (APPLY) v += (double)X[row * ldx + c];
-          Q[row * ldq + c] = c < lw ? v : 0.0;
+      for (int st = 0; st < 4; ++st) {
+        if (4 * g + st < ksteps) {   // uniform: never reads W past column 32 (c + 1)
+          load4d(w0p + 16 * (4 * g + st), b0[st]);
+          load4d(w1p + 16 * (4 * g + st), b1[st]);
         }
       }
+    };
+    fetch(0, b[0], b[1]);
+    for (int g = 0; g < ngroups; ++g) {
+      double bn[2][4][4];
+      const bool more = g + 1 < ngroups;
+      if (more) fetch(g + 1, bn[0], bn[1]);
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int ks = 4 * g + st;
+        if (ks < ksteps) {
+          double a[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) a[q] = ap[16 * ks + q];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            acc0 = mfma_f64(a[q], b[0][st][q], acc0);
+            acc1 = mfma_f64(a[q], b[1][st][q], acc1);
+          }
+        }
+      }
+      if (more) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) b[0][st][q] = bn[0][st][q], b[1][st][q] = bn[1][st][q];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = 4 * r + lk;
+      const int64_t row = r0 + rr;
+      if (row < rows) {
+        double v0 = acc0[r], v1 = acc1[r];
+        if constexpr (ADD) {
+          v0 += sA[rr * pitch + cb0 + li];
+          v1 += sA[rr * pitch + cb0 + 16 + li];
+        }
+        Q[row * ldq + cb0 + li] = v0;
+        Q[row * ldq + cb0 + 16 + li] = v1;
+      }
+    }
+  }
+  const int zc = zero_to - lw;
+  for (int e = tid; e < TS_ROWS * zc; e += TS_WAVES * 64) {
+    const int64_t row = r0 + e / zc;
+    if (row < rows) Q[row * ldq + lw + e % zc] = 0.0;
+  }
 }
 
 // -------------------------------------------------------------- Cholesky --
@@ -252,78 +338,65 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // One wavefront factors the 32 x 32 block S (LDS, pitch NB + 1) into L
 // (written to Lout, row pitch ldl, zeros above the diagonal) and writes the
-// inverse of L to Iout (32 x 32, row-major).  Lane i keeps row i in
-// registers; after each column is scaled it is published in LDS (scratch)
-// and read back by every lane as uniform-address (broadcast) loads.
-// scratch: NB * (NB + 1) + 2 NB doubles of LDS private to this wavefront.
+// inverse X = L^-1 to Iout (32 x 32, row-major), both in one right-looking
+// sweep over the columns.  Lanes 0..31 keep row i = lane of the block, lanes
+// 32..63 column c = lane - 32 of X (starting as the identity), in the same
+// registers v[].  Step j: the pivot v[j] of lane j is read by readlane, the
+// scaled column l_j = L[:, j] is published in LDS (scratch, one 32-slot row
+// per column), and every lane applies
+//   v[k] -= m l_kj   (k > j),   m = l_ij (row lanes) or X[j][c] = v[j] / l_jj (column lanes),
+// i.e. the Cholesky update of row i and the same elimination on column c of
+// X, reading l_kj from LDS (uniform-address loads).  Only the update of the
+// next column (k = j + 1) is on the critical path, and it takes l_{j+1,j}
+// from lane j + 1 by readlane, so the LDS loads of the other updates are
+// off the pivot chain.
+// scratch: NB * NB doubles of LDS private to this wavefront.
 __device__ __attribute__((always_inline)) inline void factor_block_wave(const double* S, double* scratch,
                                                                         const double* diag0, int col0, int l_true,
                                                                         double tol, uint32_t* flags, double* Lout,
                                                                         int64_t ldl, double* Iout) {
   const int lane = threadIdx.x & 63;
   const int row = lane & 31;
-  double* Ls = scratch;                      // L, pitch NB + 1
-  double* colbuf = scratch + NB * (NB + 1);  // two column slots (double-buffered)
+  const bool fac = lane < NB;
   // pivot thresholds, loaded once (lane j: column col0 + j; negative = padding column)
   const double thr = col0 + row < l_true ? tol * diag0[col0 + row] : -1.0;
-  double a[NB];
+  double v[NB];
 #pragma unroll
-  for (int k = 0; k < NB; ++k) a[k] = S[row * (NB + 1) + k];
-  double inv[NB];
+  for (int k = 0; k < NB; ++k) v[k] = fac ? S[row * (NB + 1) + k] : (k == row ? 1.0 : 0.0);
   uint32_t bad = 0;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    const double d = lane_bcast(a[j], j);
+    const double d = lane_bcast(v[j], j);
     const double tj = lane_bcast(thr, j);
-    double piv = 0.0, iv = 0.0;
-    if (tj >= 0.0) {
-      if (d > tj && d > 0.0) {
-        // 1/sqrt(d): hardware estimate refined by two Newton steps (quadratic
-        // convergence from ~2^-23 to full precision); piv = d / sqrt(d)
-        double y = __builtin_amdgcn_rsq(d);
-        y = y * fma(-0.5 * d * y, y, 1.5);
-        y = y * fma(-0.5 * d * y, y, 1.5);
-        iv = y;
-        piv = d * y;
-      } else {
-        bad |= (d < -tj || d != d) ? (LRAMM_FLAG_BREAKDOWN | LRAMM_FLAG_SQRTNEG) : LRAMM_FLAG_BREAKDOWN;
-      }
+    // 1/sqrt(d): hardware estimate refined by two Newton steps (quadratic
+    // convergence from ~2^-23 to full precision); piv = d / sqrt(d)
+    double y = __builtin_amdgcn_rsq(d);
+    y = y * fma(-0.5 * d * y, y, 1.5);
+    y = y * fma(-0.5 * d * y, y, 1.5);
+    const bool live = tj >= 0.0;
+    const bool ok = live && d > tj && d > 0.0;
+    const double iv = ok ? y : 0.0;
+    const double piv = ok ? d * y : 0.0;
+    if (live && !ok) bad |= (d < -tj || d != d) ? (LRAMM_FLAG_BREAKDOWN | LRAMM_FLAG_SQRTNEG) : LRAMM_FLAG_BREAKDOWN;
+    const double sc = v[j] * iv;
+    const double m = fac ? (row > j ? sc : (row == j ? piv : 0.0)) : sc;
+    v[j] = m;
+    double* col = scratch + j * NB;
+    if (fac) col[lane] = m;
+    wave_lds_sync();   // also keeps later columns' loads out of this step (register pressure)
+    if (j + 1 < NB) {
+      const double ln = lane_bcast(m, j + 1);       // l_{j+1, j}
+      v[j + 1] = fma(-m, ln, v[j + 1]);
     }
-    inv[j] = iv;
-    a[j] = row > j ? a[j] * iv : (row == j ? piv : a[j]);
-    double* col = colbuf + (j & 1) * NB;
-    if (lane < NB) col[lane] = a[j];
-    wave_lds_sync();
 #pragma unroll
-    for (int k = j + 1; k < NB; ++k) a[k] = fma(-a[j], col[k], a[k]);
+    for (int k = j + 2; k < NB; ++k) v[k] = fma(-m, col[k], v[k]);
   }
-  if (lane < NB) {
+  if (fac) {
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      const double v = k <= row ? a[k] : 0.0;
-      Ls[row * (NB + 1) + k] = v;
-      Lout[(int64_t)row * ldl + k] = v;
-    }
-  }
-  wave_lds_sync();
-  // inverse, one column per lane: X[i][c] = (delta_ic - sum_t L[i][t] X[t][c]) / L[i][i],
-  // the sum split over four independent partial sums
-  double x[NB];
+    for (int k = 0; k < NB; ++k) Lout[(int64_t)row * ldl + k] = k <= row ? v[k] : 0.0;
+  } else {
 #pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    double p0 = row == i ? 1.0 : 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-#pragma unroll
-    for (int t = 0; t < i; t += 4) {
-      p0 = fma(-Ls[i * (NB + 1) + t], x[t], p0);
-      if (t + 1 < i) p1 = fma(-Ls[i * (NB + 1) + t + 1], x[t + 1], p1);
-      if (t + 2 < i) p2 = fma(-Ls[i * (NB + 1) + t + 2], x[t + 2], p2);
-      if (t + 3 < i) p3 = fma(-Ls[i * (NB + 1) + t + 3], x[t + 3], p3);
-    }
-    x[i] = ((p0 + p1) + (p2 + p3)) * inv[i];
-  }
-  if (lane < NB) {
-#pragma unroll
-    for (int i = 0; i < NB; ++i) Iout[i * NB + row] = x[i];
+    for (int k = 0; k < NB; ++k) Iout[k * NB + row] = v[k];
   }
   if (lane == 0 && bad && flags) atomicOr(flags, bad);
 }
@@ -489,15 +562,12 @@ __device__ __forceinline__ void wave_tile_xyt(const double* X, int64_t ldx, cons
       for (int sj = 0; sj < 2; ++sj) acc[si][sj] = mfma_f64(xv[si][kk], yv[sj][kk], acc[si][sj]);
 }
 
-// The whole blocked Cholesky in one workgroup (no launches between panels).
-// When gate is non-null the kernel does nothing unless (*gate & gate_mask).
-__global__ __launch_bounds__(256) void chol_fused_kernel(int lw, int l_true, double* __restrict__ G,
-                                                         double* __restrict__ L, double* __restrict__ Dinv,
-                                                         const double* __restrict__ diag0, double tol,
-                                                         uint32_t* flags, const uint32_t* gate, uint32_t gate_mask) {
-  if (gate && !(*gate & gate_mask)) return;
-  __shared__ double sS[NB][NB + 1];
-  __shared__ double scratch[NB * (NB + 1) + 2 * NB];
+// The whole blocked Cholesky of G in one workgroup (no launches between
+// panels), used only by the gated fallback of the second pass.  sS and
+// scratch are LDS buffers of the caller.
+__device__ void chol_single_wg(int lw, int l_true, double* __restrict__ G, double* __restrict__ L,
+                               double* __restrict__ Dinv, const double* __restrict__ diag0, double tol,
+                               uint32_t* flags, double (*sS)[NB + 1], double* scratch) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int T = lw / NB;
@@ -555,152 +625,133 @@ __global__ __launch_bounds__(256) void chol_fused_kernel(int lw, int l_true, dou
 // (I + F)^-T are expanded in E: with F0 = tril_half(E) (strict lower part of
 // E plus half its diagonal),
 //     (I + F)^-T - I = M = -F0^T + tril_half(F0 F0^T)^T + (F0 F0)^T + O(|E|^3),
-// so Q = Q1 (I + F)^-T = Q1 + Q1 M.  series_m_kernel builds M (upper
-// triangular, 32 x 32 tiles (a, b), a <= b) and raises gate_bit when some
-// |E_ij| exceeds tau, in which case the full second pass runs instead.
+// so Q = Q1 (I + F)^-T = Q1 + Q1 M.  The kernel writes W = M^T (lower
+// triangular, the operand layout of tsmul_kernel) tile by tile:
+//     W[b][a] = -F0[b][a] + h(S1)[b][a] + S2[b][a],   a <= b,
+//     S1[b][a] = sum_{t <= a} F0[b][t] F0[a][t],  S2[b][a] = sum_{a <= t <= b} F0[b][t] F0[t][a],
+// h halving the diagonal.  The 32-wide t blocks of both sums are shared
+// round-robin by the four wavefronts and their partial tiles summed in LDS.
+// When the Gram reduction raised the gate (some |E_ij| > tau) the expansion
+// is not accurate enough: workgroup 0 then runs the full blocked Cholesky of
+// G2 and its inverse X2 in one workgroup and writes W = X2 - I (so that
+// Q1 + Q1 W^T = Q1 X2^T), and the other workgroups do nothing.
+
+// F0 elements (i, t..t+3) of row i: tril_half(G2 - I), zero outside l_true.
+__device__ __forceinline__ void f0_row4(const double* G2, int lw, int l_true, int i, int t, double v[4]) {
+  const int ic = i < lw ? i : lw - 1;
+  load4d(G2 + (int64_t)ic * lw + t, v);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int tq = t + q;
+    const bool in = i < l_true && tq < l_true && tq <= i;
+    const double g = tq == i ? 0.5 * (v[q] - 1.0) : v[q];
+    v[q] = keep_if(in, g);
+  }
+}
 
 __device__ __forceinline__ double f0_at(const double* G2, int lw, int l_true, int i, int t) {
-  // F0[i][t] for the lower triangle of E = G2 - I (zero outside l_true)
-  if (i >= l_true || t >= l_true || t > i) return 0.0;
-  const double g = G2[(int64_t)i * lw + t];
-  return i == t ? 0.5 * (g - 1.0) : g;
+  const bool in = i < l_true && t < l_true && t <= i;
+  const double g = G2[in ? (int64_t)i * lw + t : 0];
+  return keep_if(in, i == t ? 0.5 * (g - 1.0) : g);
 }
 
-__global__ __launch_bounds__(256) void series_m_kernel(int lw, int l_true, const double* __restrict__ G2,
-                                                       double* __restrict__ M, uint32_t* gate, uint32_t gate_bit,
-                                                       double tau) {
-  __shared__ double sB[NB][NB + 1];   // F0 rows of block b, t-chunk
-  __shared__ double sA[NB][NB + 1];   // F0 rows of block a, t-chunk
-  __shared__ double sC[NB][NB + 1];   // F0 t-chunk rows, columns of block a
-  int t = blockIdx.x, bb = 0;
-  while (t > bb) {
-    t -= bb + 1;
-    ++bb;
-  }
-  const int ab = t;                   // tile (ab, bb) of M with ab <= bb
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int si = wave >> 1, sj = wave & 1;
-  // gate test on the E tile (bb, ab) this block owns
-  bool over = false;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = bb * NB + e / NB, j = ab * NB + e % NB;
-    if (i < l_true && j < l_true && j <= i) {
-      const double v = G2[(int64_t)i * lw + j] - (i == j ? 1.0 : 0.0);
-      if (!(fabs(v) <= tau)) over = true;
+// Gated fallback of the second pass, in one workgroup: W = chol(G2)^-1 - I.
+// Kept out of line so that its register pressure does not spill the series
+// path of the kernel below.
+__device__ __noinline__ void series_fallback(int lw, int l_true, double* G2, double* Wout, double* L, double* Dinv,
+                                             const double* diag0, double tol, uint32_t* flags,
+                                             double (*sS)[NB + 1], double* scratch) {
+  const int tid = threadIdx.x;
+  chol_single_wg(lw, l_true, G2, L, Dinv, diag0, tol, flags, sS, scratch);
+  const int Tn = lw / NB;
+  for (int p = 0; p < Tn; ++p) {
+    for (int j = 0; j <= p; ++j) {
+      inverse_block(lw, p, j, L, Dinv, Wout, sS);
+      __syncthreads();
     }
   }
-  if (over) atomicOr(gate, gate_bit);
-  // out[r][c] = M[ab*NB + r][bb*NB + c]: transposed accumulation of
-  //   S1[b][a] = sum_t F0[b][t] F0[a][t]  (t <= a)  and  S2[b][a] = sum_t F0[b][t] F0[t][a]  (a <= t <= b)
-  // sub-tile (si, sj) of the (bb, ab) orientation: rows b, columns a
-  v4d s1 = {0, 0, 0, 0}, s2 = {0, 0, 0, 0};
-  for (int tb = 0; tb <= bb; ++tb) {
-    __syncthreads();
-    for (int e = tid; e < NB * NB; e += 256) {
-      const int r = e / NB, c = e % NB;
-      sB[r][c] = f0_at(G2, lw, l_true, bb * NB + r, tb * NB + c);
-      sA[r][c] = f0_at(G2, lw, l_true, ab * NB + r, tb * NB + c);
-      sC[r][c] = f0_at(G2, lw, l_true, tb * NB + r, ab * NB + c);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < NB; kk += 4) {
-      const double x = sB[16 * si + li][kk + lk];
-      if (tb <= ab) s1 = mfma_f64(x, sA[16 * sj + li][kk + lk], s1);     // B[k][j] = F0[a j][t k]
-      if (tb >= ab) s2 = mfma_f64(x, sC[kk + lk][16 * sj + li], s2);     // B[k][j] = F0[t k][a j]
-    }
-  }
-  // write M[a][b] = -F0[b][a] + h(S1)[b][a] + S2[b][a]  (transpose of the (b, a) tile)
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int bi = bb * NB + 16 * si + 4 * r + lk;     // row index in the (b, a) orientation
-    const int aj = ab * NB + 16 * sj + li;
-    double v = 0.0;
-    if (aj <= bi) {
-      const double h1 = (aj < bi) ? s1[r] : 0.5 * s1[r];
-      v = -f0_at(G2, lw, l_true, bi, aj) + h1 + s2[r];
-    }
-    M[(int64_t)aj * lw + bi] = v;
-  }
+  for (int i = tid; i < lw; i += 256) Wout[(int64_t)i * lw + i] -= 1.0;
 }
 
-// ------------------------------------------------------------------ TRSM --
-// Q[rows x lw] = X L^-T, 16 rows per block.  For each 32-column panel c:
-//   W = X[:, c] - Q[:, <c] L[c, <c]^T      (K split over the 4 waves)
-//   Q[:, c] = W Dinv_c^T
-template <typename T>
-__global__ __launch_bounds__(256) void trsm_kernel(int64_t rows, int lw, int ncols, const T* __restrict__ X,
-                                                   int64_t ldx,
-                                                   const double* __restrict__ L, const double* __restrict__ Dinv,
-                                                   double* __restrict__ Q, int64_t ldq, int zero_to,
-                                                   const uint32_t* gate, uint32_t gate_mask) {
-  if (gate && !(*gate & gate_mask)) return;
-  extern __shared__ double smem[];
-  double* sQ = smem;                          // 16 x lw
-  double* sW = smem + 16 * lw;                // 4 waves x 16 x 32 partials
-  double* sX = sW + 4 * 16 * NB;              // 16 x 32 (W)
+__global__ __launch_bounds__(256) void series_kernel(int lw, int l_true, double* __restrict__ G2,
+                                                     double* __restrict__ Wout, double* __restrict__ L,
+                                                     double* __restrict__ Dinv, const double* __restrict__ diag0,
+                                                     double tol, uint32_t* flags, const uint32_t* gate,
+                                                     uint32_t gate_bit) {
+  __shared__ double red[4][NB][NB + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int64_t row0 = (int64_t)blockIdx.x * 16;
-  const int npanel = lw / NB;
-
-  for (int c = 0; c < npanel; ++c) {
-    const int c0 = c * NB;
-    // partial products over t in [0, c0), K split across waves in steps of 4
-    v4d acc0 = (v4d){0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
-    for (int t0 = 4 * wave; t0 < c0; t0 += 16) {
-      double a = sQ[li * lw + t0 + lk];
-      double b0 = L[(int64_t)(c0 + li) * lw + t0 + lk];
-      double b1 = L[(int64_t)(c0 + 16 + li) * lw + t0 + lk];
-      acc0 = mfma_f64(a, b0, acc0);
-      acc1 = mfma_f64(a, b1, acc1);
-    }
+  if (*gate & gate_bit) {
+    // fallback: W = chol(G2)^-1 - I, all in workgroup 0
+    if (blockIdx.x != 0) return;
+    series_fallback(lw, l_true, G2, Wout, L, Dinv, diag0, tol, flags, red[0], &red[1][0][0]);
+    return;
+  }
+  int bb, ab;
+  lower_tile(blockIdx.x, bb, ab);     // tile (bb, ab) of W, ab <= bb
+  // tasks: S1 over t blocks 0..ab, S2 over ab..bb
+  const int n1 = ab + 1, n2 = bb - ab + 1;
+  v4d s1[2][2], s2[2][2];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      sW[(wave * 16 + 4 * r + lk) * NB + li] = acc0[r];
-      sW[(wave * 16 + 4 * r + lk) * NB + 16 + li] = acc1[r];
-    }
-    __syncthreads();
-    for (int e = tid; e < 16 * NB; e += 256) {
-      int r = e / NB, cc = e % NB;
-      int64_t gr = row0 + r;
-      double x = (gr < rows && c0 + cc < ncols) ? (double)X[gr * ldx + c0 + cc] : 0.0;
-      double s = sW[(0 * 16 + r) * NB + cc];
-      s += sW[(1 * 16 + r) * NB + cc];
-      s += sW[(2 * 16 + r) * NB + cc];
-      s += sW[(3 * 16 + r) * NB + cc];
-      sX[r * NB + cc] = x - s;
-    }
-    __syncthreads();
-    // Q[:, c] = W * Dinv_c^T  (waves 0, 1: one 16 x 16 output tile each)
-    if (wave < 2) {
-      const double* Dc = Dinv + (int64_t)c * NB * NB;
-      v4d acc = (v4d){0.0, 0.0, 0.0, 0.0};
-      for (int t0 = 0; t0 < NB; t0 += 4) {
-        double a = sX[li * NB + t0 + lk];
-        double b = Dc[(wave * 16 + li) * NB + t0 + lk];   // B[k][j] = Dinv[j][k]
-        acc = mfma_f64(a, b, acc);
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) s1[i][j] = s2[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int task = wave; task < n1 + n2; task += 4) {
+    const bool first = task < n1;
+    const int tb = first ? task : ab + (task - n1);
+#pragma unroll
+    for (int k0 = 0; k0 < NB; k0 += 16) {
+      const int t = tb * NB + k0 + 4 * lk;
+      double a[2][4], b[2][4];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) f0_row4(G2, lw, l_true, bb * NB + 16 * s + li, t, a[s]);
+      if (first) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) f0_row4(G2, lw, l_true, ab * NB + 16 * s + li, t, b[s]);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) b[s][q] = f0_at(G2, lw, l_true, t + q, ab * NB + 16 * s + li);
       }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int si = 0; si < 2; ++si)
+#pragma unroll
+          for (int sj = 0; sj < 2; ++sj) {
+            if (first) s1[si][sj] = mfma_f64(a[si][q], b[sj][q], s1[si][sj]);
+            else s2[si][sj] = mfma_f64(a[si][q], b[sj][q], s2[si][sj]);
+          }
+    }
+  }
+  // per-wave h(S1) + S2 at each element of the (b, a) tile, then the fixed-order sum
+#pragma unroll
+  for (int si = 0; si < 2; ++si)
+#pragma unroll
+    for (int sj = 0; sj < 2; ++sj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int rr = 4 * r + lk;
-        sQ[rr * lw + c0 + wave * 16 + li] = acc[r];
+        const int rb = 16 * si + 4 * r + lk, ca = 16 * sj + li;
+        const int bi = bb * NB + rb, aj = ab * NB + ca;
+        const double h1 = aj < bi ? s1[si][sj][r] : 0.5 * s1[si][sj][r];
+        red[wave][rb][ca] = h1 + s2[si][sj][r];
       }
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < 16 * zero_to; e += 256) {
-    int r = e / zero_to, cc = e % zero_to;
-    int64_t gr = row0 + r;
-    if (gr < rows) Q[gr * ldq + cc] = cc < lw ? sQ[r * lw + cc] : 0.0;
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int rb = e / NB, ca = e % NB;
+    const int bi = bb * NB + rb, aj = ab * NB + ca;
+    double v = 0.0;
+    if (aj <= bi)
+      v = -f0_at(G2, lw, l_true, bi, aj) + ((red[0][rb][ca] + red[1][rb][ca]) + (red[2][rb][ca] + red[3][rb][ca]));
+    Wout[(int64_t)bi * lw + aj] = v;
   }
 }
 
 // ------------------------------------------------------------------ host --
 
 struct CholWs {
-  double *G, *L, *Dinv, *diag0, *part, *Q1, *M, *X;
+  double *G, *L, *Dinv, *diag0, *part, *Q1, *W, *X;
   uint32_t* gate;
   int nchunks;
   int64_t rows_per_chunk;
@@ -709,15 +760,15 @@ struct CholWs {
 constexpr uint32_t kGateFull = 1u;      // second pass needs the full Cholesky
 constexpr double kSeriesTau = 1e-5;     // |E| bound of the second-pass expansion (error O(tau^3))
 
+// Row chunks of the Gram: about two workgroups per compute unit over the
+// lower 32 x 32 tiles, each wavefront at least 4 rows.
 static void cholqr_layout(int64_t rows, int64_t l, int* lw_out, int* nchunks, int64_t* rpc) {
   const int lw = (int)round_up(l, NB);
-  const int t64 = (int)ceil_div(lw, FT);
-  const int ntri = t64 * (t64 + 1) / 2;
-  int64_t nc = 384 / ntri;
-  const int64_t maxc = ceil_div(rows, 64);
-  if (nc > maxc) nc = maxc;
+  const int Tn = lw / NB;
+  const int ntri = Tn * (Tn + 1) / 2;
+  int64_t nc = 512 / ntri;
   if (nc < 1) nc = 1;
-  const int64_t r = round_up(ceil_div(rows, nc), FK);
+  int64_t r = round_up(ceil_div(rows, nc), (int64_t)16);
   nc = ceil_div(rows, r);
   if (nc < 1) nc = 1;
   *lw_out = lw;
@@ -734,18 +785,6 @@ size_t cholqr2_workspace(int64_t rows, int64_t l) {
   return n * sizeof(double) + 256;
 }
 
-static lramm_status set_trsm_attr() {
-  static bool done = false;
-  if (!done) {
-    LRAMM_HIP(hipFuncSetAttribute((const void*)trsm_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024));
-    LRAMM_HIP(hipFuncSetAttribute((const void*)trsm_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024));
-    done = true;
-  }
-  return LRAMM_OK;
-}
-
 struct HookScope {
   const TimingHook* h;
   HookScope(const TimingHook* hook, int stage) : h(hook) {
@@ -757,18 +796,18 @@ struct HookScope {
 };
 
 template <typename T>
-static lramm_status gram(int64_t rows, int lw, int l_true, const T* X, int64_t ldx, const CholWs& w, hipStream_t s,
-                         const TimingHook* hook) {
-  const int t64 = (int)ceil_div(lw, FT);
-  const int ntri = t64 * (t64 + 1) / 2;
+static lramm_status gram(int64_t rows, int lw, int l_true, const T* X, int64_t ldx, const CholWs& w, int mode,
+                         hipStream_t s, const TimingHook* hook) {
+  const int Tn = lw / NB;
+  const int ntri = Tn * (Tn + 1) / 2;
   {
     HookScope hs(hook, SUB_CHOL_GRAM);
-    hipLaunchKernelGGL((gram64_kernel<T>), dim3(ntri, w.nchunks), dim3(256), 0, s, rows, lw, l_true, X, ldx, w.part,
+    hipLaunchKernelGGL((gram_kernel<T>), dim3(ntri, w.nchunks), dim3(256), 0, s, rows, lw, l_true, X, ldx, w.part,
                        w.rows_per_chunk);
   }
   LRAMM_HIP(hipGetLastError());
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)ceil_div((int64_t)lw * lw, 256)), dim3(256), 0, s, lw,
-                     w.nchunks, w.part, w.G, w.diag0, w.gate);
+                     l_true, w.nchunks, w.part, w.G, w.diag0, w.gate, mode, kGateFull, kSeriesTau);
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }
@@ -792,14 +831,21 @@ static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32
   return LRAMM_OK;
 }
 
-template <typename T, bool APPLY>
-static lramm_status solve_gemm(int64_t rows, int lw, int ncols, const T* X, int64_t ldx, const double* B, double* Q,
-                               int64_t ldq, int zero_to, const uint32_t* gate, uint32_t mask, hipStream_t s,
-                               const TimingHook* hook) {
-  HookScope hs(hook, APPLY ? SUB_CHOL_APPLY : SUB_CHOL_SOLVE);
-  dim3 grid((unsigned)ceil_div(rows, FT), (unsigned)ceil_div(zero_to, FT));
-  hipLaunchKernelGGL((solve_gemm_kernel<T, APPLY>), grid, dim3(256), 0, s, rows, lw, ncols, X, ldx, B, Q, ldq,
-                     zero_to, gate, mask);
+template <typename T, bool ADD>
+static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t ldx, const double* W, double* Q,
+                          int64_t ldq, int zero_to, hipStream_t s, const TimingHook* hook) {
+  static bool attr_set = false;
+  if (!attr_set) {   // up to 16 x 1028 doubles of LDS
+    LRAMM_HIP(hipFuncSetAttribute((const void*)tsmul_kernel<T, ADD>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024));
+    attr_set = true;
+  }
+  HookScope hs(hook, ADD ? SUB_CHOL_APPLY : SUB_CHOL_SOLVE);
+  // 4-element vector loads need every row start aligned to 4 elements
+  const int vec = ((uintptr_t)X % (4 * sizeof(T)) == 0 && ldx % 4 == 0) ? 1 : 0;
+  const size_t shm = (size_t)TS_ROWS * ts_pitch(lw) * sizeof(double);
+  hipLaunchKernelGGL((tsmul_kernel<T, ADD>), dim3((unsigned)ceil_div(rows, (int64_t)TS_ROWS)), dim3(TS_WAVES * 64),
+                     shm, s, rows, lw, ncols, X, ldx, W, Q, ldq, zero_to, vec);
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }
@@ -812,8 +858,6 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   int64_t rpc;
   cholqr_layout(rows, l, &lw, &nc, &rpc);
   if (ws_bytes < cholqr2_workspace(rows, l)) return LRAMM_E_WORKSPACE;
-  if ((size_t)(16 * lw + 5 * 16 * NB) * sizeof(double) > 160 * 1024) return LRAMM_E_UNSUPPORTED;
-  LRAMM_TRY(set_trsm_attr());
   uintptr_t base = round_up((int64_t)(uintptr_t)ws, 256);
   double* p = reinterpret_cast<double*>(base);
   const size_t sq = (size_t)lw * lw;
@@ -822,7 +866,7 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   p += sq;
   w.L = p;
   p += sq;
-  w.M = p;
+  w.W = p;
   p += sq;
   w.X = p;
   p += sq;
@@ -840,36 +884,28 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   const int lt = (int)l;
   // pass 1 on Y (columns at or past l are never read): Q1 = Y L1^-T
   if (ytype == LRAMM_F32) {
-    LRAMM_TRY(gram<float>(rows, lw, lt, (const float*)Y, ldy, w, s, hook));
+    LRAMM_TRY(gram<float>(rows, lw, lt, (const float*)Y, ldy, w, 0, s, hook));
     LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook));
-    LRAMM_TRY((solve_gemm<float, false>(rows, lw, lt, (const float*)Y, ldy, w.X, w.Q1, lw, lw, nullptr, 0, s, hook)));
+    LRAMM_TRY((tsmul<float, false>(rows, lw, lt, (const float*)Y, ldy, w.X, w.Q1, lw, lw, s, hook)));
   } else if (ytype == LRAMM_F64) {
-    LRAMM_TRY(gram<double>(rows, lw, lt, (const double*)Y, ldy, w, s, hook));
+    LRAMM_TRY(gram<double>(rows, lw, lt, (const double*)Y, ldy, w, 0, s, hook));
     LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook));
-    LRAMM_TRY((solve_gemm<double, false>(rows, lw, lt, (const double*)Y, ldy, w.X, w.Q1, lw, lw, nullptr, 0, s, hook)));
+    LRAMM_TRY((tsmul<double, false>(rows, lw, lt, (const double*)Y, ldy, w.X, w.Q1, lw, lw, s, hook)));
   } else {
     return LRAMM_E_UNSUPPORTED;
   }
-  // pass 2 on Q1: expansion of the near-identity factor, or (gated) the full pass
+  // pass 2 on Q1: expansion of the near-identity factor, or (gated) the full factor
   const int zero_to = (int)ldq;
-  LRAMM_TRY(gram<double>(rows, lw, lt, w.Q1, lw, w, s, hook));
+  LRAMM_TRY(gram<double>(rows, lw, lt, w.Q1, lw, w, 1, s, hook));
   const int Tn = lw / NB;
+  const double tol = 64.0 * (double)lt * 0x1p-53;
   {
     HookScope hs(hook, SUB_CHOL_SERIES);
-    hipLaunchKernelGGL(series_m_kernel, dim3(Tn * (Tn + 1) / 2), dim3(256), 0, s, lw, lt, w.G, w.M, w.gate,
-                       kGateFull, kSeriesTau);
+    hipLaunchKernelGGL(series_kernel, dim3(Tn * (Tn + 1) / 2), dim3(256), 0, s, lw, lt, w.G, w.W, w.L, w.Dinv,
+                       w.diag0, tol, flags, w.gate, kGateFull);
   }
   LRAMM_HIP(hipGetLastError());
-  LRAMM_TRY((solve_gemm<double, true>(rows, lw, lw, w.Q1, lw, w.M, Q, ldq, zero_to, w.gate, kGateFull, s, hook)));
-  // gated fallback: full Cholesky of G2 and triangular solve
-  const double tol = 64.0 * (double)lt * 0x1p-53;
-  hipLaunchKernelGGL(chol_fused_kernel, dim3(1), dim3(256), 0, s, lw, lt, w.G, w.L, w.Dinv, w.diag0, tol, flags,
-                     w.gate, kGateFull);
-  LRAMM_HIP(hipGetLastError());
-  const size_t shm = (size_t)(16 * lw + 4 * 16 * NB + 16 * NB) * sizeof(double);
-  hipLaunchKernelGGL((trsm_kernel<double>), dim3((unsigned)ceil_div(rows, 16)), dim3(256), shm, s, rows, lw, lt,
-                     w.Q1, (int64_t)lw, w.L, w.Dinv, Q, ldq, zero_to, w.gate, kGateFull);
-  LRAMM_HIP(hipGetLastError());
+  LRAMM_TRY((tsmul<double, true>(rows, lw, lw, w.Q1, lw, w.W, Q, ldq, zero_to, s, hook)));
   return LRAMM_OK;
 }
 
