@@ -162,7 +162,9 @@ __global__ __launch_bounds__(256) void gram_kernel(int64_t rows, int lw, int nco
       for (int r = 0; r < 4; ++r) red[wave][16 * si + 4 * r + lk][16 * sj + li] = acc[si][sj][r];
   __syncthreads();
   double* out = part + (int64_t)blockIdx.y * lw * lw + (int64_t)ta * NB * lw + tb * NB;
-  for (int e = tid; e < NB * NB; e += 256) {
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = tid + 256 * u;
     const int i = e / NB, j = e % NB;
     const bool in = ta * NB + i < ncols && tb * NB + j < ncols;
     out[(int64_t)i * lw + j] = in ? (red[0][i][j] + red[1][i][j]) + (red[2][i][j] + red[3][i][j]) : 0.0;
@@ -348,9 +350,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // i.e. the Cholesky update of row i and the same elimination on column c of
 // X, reading l_kj from LDS (uniform-address loads).  Only the update of the
 // next column (k = j + 1) is on the critical path, and it takes l_{j+1,j}
-// from lane j + 1 by readlane, so the LDS loads of the other updates are
-// off the pivot chain.
-// scratch: NB * NB doubles of LDS private to this wavefront.
+// from lane j + 1 by readlane; the other updates of column j are applied
+// one step later, so their LDS loads are off the pivot chain.
+// scratch: NB * NB + NB doubles of LDS private to this wavefront.
 __device__ __attribute__((always_inline)) inline void factor_block_wave(const double* S, double* scratch,
                                                                         const double* diag0, int col0, int l_true,
                                                                         double tol, uint32_t* flags, double* Lout,
@@ -358,28 +360,38 @@ __device__ __attribute__((always_inline)) inline void factor_block_wave(const do
   const int lane = threadIdx.x & 63;
   const int row = lane & 31;
   const bool fac = lane < NB;
-  // pivot thresholds, loaded once (lane j: column col0 + j; negative = padding column)
-  const double thr = col0 + row < l_true ? tol * diag0[col0 + row] : -1.0;
+  double* sthr = scratch + NB * NB;   // pivot thresholds (negative: padding column)
+  if (fac) sthr[lane] = col0 + row < l_true ? tol * diag0[col0 + row] : -1.0;
   double v[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) v[k] = fac ? S[row * (NB + 1) + k] : (k == row ? 1.0 : 0.0);
+  wave_lds_sync();
   uint32_t bad = 0;
+  // the updates from column j - 1 (other than the next column's) are applied
+  // one step late, after the pivot of column j, so that the LDS loads of
+  // column j - 1 complete while that pivot is computed
+  double cprev[NB];
+  double mprev = 0.0;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) cprev[k] = 0.0;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
+    const double tj = sthr[j];
     const double d = lane_bcast(v[j], j);
-    const double tj = lane_bcast(thr, j);
     // 1/sqrt(d): hardware estimate refined by two Newton steps (quadratic
     // convergence from ~2^-23 to full precision); piv = d / sqrt(d)
+    const double hd = 0.5 * d;
     double y = __builtin_amdgcn_rsq(d);
-    y = y * fma(-0.5 * d * y, y, 1.5);
-    y = y * fma(-0.5 * d * y, y, 1.5);
+    y = y * fma(-hd * y, y, 1.5);
+    y = y * fma(-hd * y, y, 1.5);
     const bool live = tj >= 0.0;
     const bool ok = live && d > tj && d > 0.0;
     const double iv = ok ? y : 0.0;
-    const double piv = ok ? d * y : 0.0;
-    if (live && !ok) bad |= (d < -tj || d != d) ? (LRAMM_FLAG_BREAKDOWN | LRAMM_FLAG_SQRTNEG) : LRAMM_FLAG_BREAKDOWN;
-    const double sc = v[j] * iv;
-    const double m = fac ? (row > j ? sc : (row == j ? piv : 0.0)) : sc;
+    bad |= (live && !ok) ? ((d < -tj || d != d) ? (LRAMM_FLAG_BREAKDOWN | LRAMM_FLAG_SQRTNEG) : LRAMM_FLAG_BREAKDOWN)
+                         : 0u;
+    // row lanes: l_ij (0 above the diagonal, d / sqrt(d) on it); column lanes: X[j][c]
+    const double sc = v[j] * ((fac && row < j) ? 0.0 : iv);
+    const double m = (fac && row == j) ? d * iv : sc;
     v[j] = m;
     double* col = scratch + j * NB;
     if (fac) col[lane] = m;
@@ -388,8 +400,12 @@ __device__ __attribute__((always_inline)) inline void factor_block_wave(const do
       const double ln = lane_bcast(m, j + 1);       // l_{j+1, j}
       v[j + 1] = fma(-m, ln, v[j + 1]);
     }
+    // late updates of column j - 1 (k >= j + 1), then the loads for column j
 #pragma unroll
-    for (int k = j + 2; k < NB; ++k) v[k] = fma(-m, col[k], v[k]);
+    for (int k = j + 1; k < NB; ++k) v[k] = fma(-mprev, cprev[k], v[k]);
+#pragma unroll
+    for (int k = j + 2; k < NB; ++k) cprev[k] = col[k];
+    mprev = m;
   }
   if (fac) {
 #pragma unroll
@@ -408,7 +424,11 @@ __global__ __launch_bounds__(64) void chol_first_kernel(int lw, int l_true, cons
                                                         uint32_t* flags) {
   __shared__ double sS[NB * (NB + 1)];
   __shared__ double scratch[NB * (NB + 1) + 2 * NB];
-  for (int e = threadIdx.x; e < NB * NB; e += 64) sS[(e / NB) * (NB + 1) + e % NB] = G[(int64_t)(e / NB) * lw + e % NB];
+#pragma unroll
+  for (int u = 0; u < NB * NB / 64; ++u) {
+    const int e = threadIdx.x + 64 * u;
+    sS[(e / NB) * (NB + 1) + e % NB] = G[(int64_t)(e / NB) * lw + e % NB];
+  }
   __syncthreads();
   factor_block_wave(sS, scratch, diag0, 0, l_true, tol, flags, L, lw, Dinv);
 }
@@ -418,41 +438,75 @@ __global__ __launch_bounds__(64) void chol_first_kernel(int lw, int l_true, cons
 __device__ __forceinline__ v4d tile_xyt(const double (*X)[NB + 1], const double (*Y)[NB + 1], int wave, int li,
                                         int lk) {
   const int si = wave >> 1, sj = wave & 1;
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  v4d a0 = {0.0, 0.0, 0.0, 0.0}, a1 = a0;   // two chains: half the dependent MFMA latency
 #pragma unroll
-  for (int kk = 0; kk < NB; kk += 4) acc = mfma_f64(X[16 * si + li][kk + lk], Y[16 * sj + li][kk + lk], acc);
-  return acc;
+  for (int kk = 0; kk < NB; kk += 8) {
+    a0 = mfma_f64(X[16 * si + li][kk + lk], Y[16 * sj + li][kk + lk], a0);
+    a1 = mfma_f64(X[16 * si + li][kk + 4 + lk], Y[16 * sj + li][kk + 4 + lk], a1);
+  }
+  return a0 + a1;
 }
 
 // Block (p, j), j <= p, of X = L^-1 (lower triangular, 32 x 32 blocks):
 //   X_pp = Dinv_p;  X_pj = -Dinv_p sum_{t=j}^{p-1} L_pt X_tj  (j < p).
-// Needs row blocks 0..p-1 of X and row block p of L.  One workgroup.
+// Needs row blocks 0..p-1 of X and row block p of L.  One workgroup: the
+// four wavefronts share the terms of the sum (t = j + w, j + w + 4, ...),
+// each forming whole 32 x 32 products (2 x 2 MFMA sub-tiles) with all its
+// loads issued together; the partial sums meet in LDS (red0..red3) in a
+// fixed order, and each wavefront then forms one 16 x 16 sub-tile of the
+// product with Dinv_p.
 __device__ void inverse_block(int lw, int p, int j, const double* __restrict__ L, const double* __restrict__ Dinv,
-                              double* __restrict__ Xinv, double (*sS)[NB + 1]) {
+                              double* __restrict__ Xinv, double (*sS)[NB + 1], double (*red0)[NB + 1],
+                              double (*red1)[NB + 1], double (*red2)[NB + 1], double (*red3)[NB + 1]) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4, si = wave >> 1, sj = wave & 1;
   const double* Dp = Dinv + (int64_t)p * NB * NB;
   double* Xpj = Xinv + (int64_t)p * NB * lw + j * NB;
   if (j == p) {
-    for (int e = tid; e < NB * NB; e += 256) Xpj[(int64_t)(e / NB) * lw + e % NB] = Dp[e];
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+      const int e = tid + 256 * u;
+      Xpj[(int64_t)(e / NB) * lw + e % NB] = Dp[e];
+    }
     return;
   }
-  // S = sum_t L_pt X_tj  (sub-tile (si, sj) per wave)
-  v4d acc = {0, 0, 0, 0};
-  for (int t = j; t < p; ++t) {
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int t = j + wave; t < p; t += 4) {
     const double* Lpt = L + (int64_t)p * NB * lw + t * NB;
     const double* Xtj = Xinv + (int64_t)t * NB * lw + j * NB;
-    double av[8], bv[8];
+    double av[2][8], bv[2][8];
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      av[kk] = Lpt[(int64_t)(16 * si + li) * lw + 4 * kk + lk];
-      bv[kk] = Xtj[(int64_t)(4 * kk + lk) * lw + 16 * sj + li];
-    }
+    for (int kk = 0; kk < 8; ++kk)
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) acc = mfma_f64(av[kk], bv[kk], acc);
+      for (int u = 0; u < 2; ++u) {
+        av[u][kk] = Lpt[(int64_t)(16 * u + li) * lw + 4 * kk + lk];
+        bv[u][kk] = Xtj[(int64_t)(4 * kk + lk) * lw + 16 * u + li];
+      }
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma_f64(av[a][kk], bv[b][kk], acc[a][b]);
   }
+  double (*mine)[NB + 1] = wave == 0 ? red0 : (wave == 1 ? red1 : (wave == 2 ? red2 : red3));
 #pragma unroll
-  for (int r = 0; r < 4; ++r) sS[16 * si + 4 * r + lk][16 * sj + li] = acc[r];
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) mine[16 * a + 4 * r + lk][16 * b + li] = acc[a][b][r];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = tid + 256 * u;
+    const int r = e / NB, c = e % NB;
+    sS[r][c] = (red0[r][c] + red1[r][c]) + (red2[r][c] + red3[r][c]);
+  }
   __syncthreads();
   // X_pj = -Dinv_p S
   v4d out = {0, 0, 0, 0};
@@ -468,7 +522,8 @@ __global__ __launch_bounds__(256) void inverse_row_kernel(int lw, int p, const d
                                                           const uint32_t* gate, uint32_t gate_mask) {
   if (gate && !(*gate & gate_mask)) return;
   __shared__ double sS[NB][NB + 1];
-  inverse_block(lw, p, blockIdx.x, L, Dinv, Xinv, sS);
+  __shared__ double red[4][NB][NB + 1];
+  inverse_block(lw, p, blockIdx.x, L, Dinv, Xinv, sS, red[0], red[1], red[2], red[3]);
 }
 
 // Launch p (0 <= p < T - 1): workgroup b owns trailing tile (i, j),
@@ -489,7 +544,7 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int lw, int l_true, int
   const int T = lw / NB;
   const int ntrail = (T - p - 1) * (T - p) / 2;
   if ((int)blockIdx.x >= ntrail) {   // inverse row block p (blocks past the trailing tiles)
-    inverse_block(lw, p, blockIdx.x - ntrail, L, Dinv, Xinv, sS);
+    inverse_block(lw, p, blockIdx.x - ntrail, L, Dinv, Xinv, sS, sGi, sGj, sLi, sLj);
     return;
   }
   int t = blockIdx.x, di = 0;
@@ -503,11 +558,19 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int lw, int l_true, int
   const double* Dp = Dinv + (int64_t)p * NB * NB;
   const double* Gip = G + (int64_t)i * NB * lw + p * NB;
   const double* Gjp = G + (int64_t)j * NB * lw + p * NB;
-  for (int e = tid; e < NB * NB; e += 256) {
+  double* Gij = G + (int64_t)i * NB * lw + j * NB;
+  // every load of this launch is issued here: the panel tiles, Dinv_p and
+  // this thread's elements of the tile being updated
+  double gij[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) gij[r] = Gij[(int64_t)(16 * (wave >> 1) + 4 * r + lk) * lw + 16 * (wave & 1) + li];
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = tid + 256 * u;
     const int r = e / NB, c = e % NB;
     sD[r][c] = Dp[e];
     sGi[r][c] = Gip[(int64_t)r * lw + c];
-    if (j != i) sGj[r][c] = Gjp[(int64_t)r * lw + c];
+    sGj[r][c] = Gjp[(int64_t)r * lw + c];
   }
   __syncthreads();
   {
@@ -523,14 +586,17 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int lw, int l_true, int
   __syncthreads();
   if (j == p + 1) {
     double* Lip = L + (int64_t)i * NB * lw + p * NB;
-    for (int e = tid; e < NB * NB; e += 256) Lip[(int64_t)(e / NB) * lw + e % NB] = sLi[e / NB][e % NB];
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+      const int e = tid + 256 * u;
+      Lip[(int64_t)(e / NB) * lw + e % NB] = sLi[e / NB][e % NB];
+    }
   }
   const v4d upd = tile_xyt(sLi, j != i ? sLj : sLi, wave, li, lk);
-  double* Gij = G + (int64_t)i * NB * lw + j * NB;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int rr = 16 * (wave >> 1) + 4 * r + lk, cc = 16 * (wave & 1) + li;
-    const double v = Gij[(int64_t)rr * lw + cc] - upd[r];
+    const double v = gij[r] - upd[r];
     Gij[(int64_t)rr * lw + cc] = v;
     sS[rr][cc] = v;
   }
@@ -573,7 +639,11 @@ __device__ void chol_single_wg(int lw, int l_true, double* __restrict__ G, doubl
   const int T = lw / NB;
   for (int p = 0; p < T; ++p) {
     const double* Gpp = G + (int64_t)p * NB * lw + p * NB;
-    for (int e = tid; e < NB * NB; e += 256) sS[e / NB][e % NB] = Gpp[(int64_t)(e / NB) * lw + e % NB];
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+      const int e = tid + 256 * u;
+      sS[e / NB][e % NB] = Gpp[(int64_t)(e / NB) * lw + e % NB];
+    }
     __syncthreads();
     double* Dp = Dinv + (int64_t)p * NB * NB;
     if (wave == 0)
@@ -660,13 +730,14 @@ __device__ __forceinline__ double f0_at(const double* G2, int lw, int l_true, in
 // path of the kernel below.
 __device__ __noinline__ void series_fallback(int lw, int l_true, double* G2, double* Wout, double* L, double* Dinv,
                                              const double* diag0, double tol, uint32_t* flags,
-                                             double (*sS)[NB + 1], double* scratch) {
+                                             double (*red)[NB][NB + 1]) {
   const int tid = threadIdx.x;
-  chol_single_wg(lw, l_true, G2, L, Dinv, diag0, tol, flags, sS, scratch);
+  double (*sS)[NB + 1] = red[0];
+  chol_single_wg(lw, l_true, G2, L, Dinv, diag0, tol, flags, sS, &red[1][0][0]);
   const int Tn = lw / NB;
   for (int p = 0; p < Tn; ++p) {
     for (int j = 0; j <= p; ++j) {
-      inverse_block(lw, p, j, L, Dinv, Wout, sS);
+      inverse_block(lw, p, j, L, Dinv, Wout, sS, red[1], red[2], red[3], red[4]);
       __syncthreads();
     }
   }
@@ -678,13 +749,13 @@ __global__ __launch_bounds__(256) void series_kernel(int lw, int l_true, double*
                                                      double* __restrict__ Dinv, const double* __restrict__ diag0,
                                                      double tol, uint32_t* flags, const uint32_t* gate,
                                                      uint32_t gate_bit) {
-  __shared__ double red[4][NB][NB + 1];
+  __shared__ double red[5][NB][NB + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   if (*gate & gate_bit) {
     // fallback: W = chol(G2)^-1 - I, all in workgroup 0
     if (blockIdx.x != 0) return;
-    series_fallback(lw, l_true, G2, Wout, L, Dinv, diag0, tol, flags, red[0], &red[1][0][0]);
+    series_fallback(lw, l_true, G2, Wout, L, Dinv, diag0, tol, flags, red);
     return;
   }
   int bb, ab;
@@ -738,7 +809,9 @@ __global__ __launch_bounds__(256) void series_kernel(int lw, int l_true, double*
         red[wave][rb][ca] = h1 + s2[si][sj][r];
       }
   __syncthreads();
-  for (int e = tid; e < NB * NB; e += 256) {
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = tid + 256 * u;
     const int rb = e / NB, ca = e % NB;
     const int bi = bb * NB + rb, aj = ab * NB + ca;
     double v = 0.0;
