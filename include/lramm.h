@@ -183,6 +183,35 @@ LRAMM_API lramm_status lramm_backward(lramm_plan* plan, const float* dC, int64_t
 LRAMM_API lramm_status lramm_status_poll(const lramm_plan* plan, const void* ws,
                                void* stream, uint32_t* flags);
 
+/* ------------------------------------------------------------------------
+ * Uneven batch: many independent products C_i = alpha A_i B_i + beta C_i,
+ * each described by its own plan (shapes, rank and formats per product; the
+ * paper's rank rule r = ceil(min(M, K) / 10), Sec. 3.5, is one way to choose
+ * them).  The batch owns nstreams (1..16) internal streams of default
+ * priority; products are issued largest first, each to the least loaded
+ * stream, and joined back into the caller's stream.  LRAMM_BATCH_GRAPH
+ * (capture the sequence once and replay it as a HIP graph) is reserved and
+ * currently returns LRAMM_E_UNSUPPORTED.  The plans must outlive the batch
+ * and must not be used on other streams meanwhile.
+ */
+typedef struct lramm_batch lramm_batch;   /* opaque, host memory */
+#define LRAMM_BATCH_GRAPH 0x1u
+
+LRAMM_API lramm_status lramm_batch_create(int32_t count, lramm_plan* const* plans,
+                           int32_t nstreams, uint32_t flags, lramm_batch** out);
+LRAMM_API void lramm_batch_destroy(lramm_batch* batch);
+/* One device workspace for the whole batch (each product gets a slice). */
+LRAMM_API lramm_status lramm_batch_workspace_bytes(const lramm_batch* batch, size_t* bytes);
+/* count-long arrays (host memory) of device pointers and leading dimensions,
+ * in plan order; omega is always drawn from each plan's seed. */
+LRAMM_API lramm_status lramm_batched_forward(lramm_batch* batch, const void* const* A,
+                           const int64_t* lda, const void* const* B, const int64_t* ldb,
+                           void* const* C, const int64_t* ldc, void* ws, size_t ws_bytes,
+                           void* stream);
+/* Synchronise and OR the status words of every product. */
+LRAMM_API lramm_status lramm_batch_status_poll(const lramm_batch* batch, const void* ws,
+                           void* stream, uint32_t* flags);
+
 /* Stage timing, for measurement.  While enabled, lramm_forward records a
  * HIP event pair around every stage on the caller's stream (events are
  * created on the host at the first use and reused).  lramm_stage_times

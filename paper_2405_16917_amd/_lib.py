@@ -30,7 +30,8 @@ EXPORTS = (
     "lramm_status_poll", "lramm_quantize", "lramm_pitch", "lramm_gemm_nt",
     "lramm_gemm_nt_workspace", "lramm_omega", "lramm_cholqr2",
     "lramm_cholqr2_workspace", "lramm_dense_gemm_nt", "lramm_plan_set_timing", "lramm_stage_times",
-    "lramm_stage_name", "lramm_intermediate",
+    "lramm_stage_name", "lramm_intermediate", "lramm_batch_create", "lramm_batch_destroy",
+    "lramm_batch_workspace_bytes", "lramm_batched_forward", "lramm_batch_status_poll",
 )
 NSTAGES = 22
 
@@ -96,6 +97,12 @@ def load(path=LIB_PATH):
         "lramm_plan_set_timing": ([P, I32], I32),
         "lramm_stage_times": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], I32),
         "lramm_stage_name": ([I32], ctypes.c_char_p),
+        "lramm_batch_create": ([I32, ctypes.POINTER(P), I32, ctypes.c_uint32, ctypes.POINTER(P)], I32),
+        "lramm_batch_destroy": ([P], None),
+        "lramm_batch_workspace_bytes": ([P, ctypes.POINTER(SZ)], I32),
+        "lramm_batched_forward": ([P, ctypes.POINTER(P), ctypes.POINTER(I64), ctypes.POINTER(P),
+                                   ctypes.POINTER(I64), ctypes.POINTER(P), ctypes.POINTER(I64), P, SZ, P], I32),
+        "lramm_batch_status_poll": ([P, P, P, ctypes.POINTER(ctypes.c_uint32)], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -309,4 +316,53 @@ class LrammPlan:
         f = ctypes.c_uint32()
         code = load().lramm_status_poll(self._h, _ptr(ws), _stream(), ctypes.byref(f))
         _check(code, "lramm_status_poll")
+        return int(f.value)
+
+
+BATCH_GRAPH = 0x1
+
+
+def autotune_rank(m, k):
+    """The paper's rank rule (Sec. 3.5): about a tenth of the smaller dimension
+    of the sketched operand, r = ceil(min(m, k) / 10)."""
+    return max(1, -(-min(m, k) // 10))
+
+
+class LrammBatch:
+    """lramm_batch_create / lramm_batched_forward over a list of LrammPlan."""
+
+    def __init__(self, plans, nstreams=4, graph=False):
+        lib = load()
+        self.plans = list(plans)
+        arr = (P * len(self.plans))(*[pl._h for pl in self.plans])
+        h = P()
+        _check(lib.lramm_batch_create(len(self.plans), arr, nstreams, BATCH_GRAPH if graph else 0, ctypes.byref(h)),
+               "lramm_batch_create")
+        self._h = h
+        sz = SZ()
+        _check(lib.lramm_batch_workspace_bytes(h, ctypes.byref(sz)), "lramm_batch_workspace_bytes")
+        self.ws_bytes = int(sz.value)
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.lramm_batch_destroy(self._h)
+            self._h = None
+
+    def workspace(self, device="cuda"):
+        return torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+
+    def forward(self, As, Bs, Cs, ws):
+        n = len(self.plans)
+        assert len(As) == len(Bs) == len(Cs) == n
+        ptrs = lambda ts: (P * n)(*[t.data_ptr() for t in ts])
+        lds = lambda ts: (I64 * n)(*[t.stride(0) for t in ts])
+        _check(load().lramm_batched_forward(self._h, ptrs(As), lds(As), ptrs(Bs), lds(Bs), ptrs(Cs), lds(Cs),
+                                            _ptr(ws), ws.numel(), _stream()), "lramm_batched_forward")
+        return Cs
+
+    def status(self, ws):
+        f = ctypes.c_uint32(0)
+        code = load().lramm_batch_status_poll(self._h, _ptr(ws), _stream(), ctypes.byref(f))
+        if code not in (OK, E_NONFINITE):
+            _check(code, "lramm_batch_status_poll")
         return int(f.value)

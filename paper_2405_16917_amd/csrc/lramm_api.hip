@@ -13,9 +13,11 @@
 //   Bt   = quant_cols(Q)[fmt_proj] . A_c^T          (Q^T A, l x k)
 //   T^T  = B_c . quant_rows(Bt)[fmt_g1]^T           (n x l)
 //   C    = alpha quant_rows(Q)[fmt_g2] . quant_rows(T^T)[fmt_g2]^T + beta C
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -482,6 +484,150 @@ lramm_status lramm_status_poll(const lramm_plan* P, const void* ws, void* stream
   LRAMM_HIP(hipStreamSynchronize(s));
   if (flags) *flags = h;
   return (h & LRAMM_FLAG_NONFINITE) ? LRAMM_E_NONFINITE : LRAMM_OK;
+}
+
+// ----------------------------------------------------------- uneven batch --
+// Independent products, each with its own plan and workspace slice, spread
+// over a few streams (longest first, each to the least loaded stream) so that
+// small products overlap.  Capturing the sequence as a HIP graph
+// (LRAMM_BATCH_GRAPH) is not available: the first capture attempt crashed
+// inside the host runtime, so the flag is rejected.
+
+}  // extern "C"
+
+struct lramm_batch {
+  std::vector<lramm_plan*> plans;
+  std::vector<size_t> offs;           // workspace offset of each product
+  std::vector<int> order;             // issue order (largest first)
+  std::vector<int> stream_of;         // stream index of each product
+  size_t total = 0;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> done;       // one per stream
+  hipEvent_t fork = nullptr;
+};
+
+namespace {
+
+double product_work(const lramm_desc& d) {
+  const double l = (double)d.r + d.p;
+  return 2.0 * l * ((double)d.m * d.k * (2 + 2 * d.q) + (double)d.k * d.n + (double)d.m * d.n) +
+         4.0 * l * l * ((double)d.m * (d.q + 1) + (double)d.k * d.q);
+}
+
+void batch_free(lramm_batch* b) {
+  for (hipEvent_t e : b->done) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  delete b;
+}
+
+lramm_status batch_issue(lramm_batch* b, const void* const* A, const int64_t* lda, const void* const* B,
+                         const int64_t* ldb, void* const* C, const int64_t* ldc, uint8_t* ws, hipStream_t s) {
+  LRAMM_HIP(hipEventRecord(b->fork, s));
+  for (hipStream_t t : b->streams) LRAMM_HIP(hipStreamWaitEvent(t, b->fork, 0));
+  for (int i : b->order) {
+    lramm_plan* P = b->plans[i];
+    LRAMM_TRY(lramm_forward(P, A[i], lda[i], B[i], ldb[i], C[i], ldc[i], nullptr, 0, ws + b->offs[i], P->total,
+                            b->streams[b->stream_of[i]]));
+  }
+  for (size_t t = 0; t < b->streams.size(); ++t) {
+    LRAMM_HIP(hipEventRecord(b->done[t], b->streams[t]));
+    LRAMM_HIP(hipStreamWaitEvent(s, b->done[t], 0));
+  }
+  return LRAMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lramm_status lramm_batch_create(int32_t count, lramm_plan* const* plans, int32_t nstreams, uint32_t flags,
+                                lramm_batch** out) {
+  if (!out || count < 1 || !plans || nstreams < 1 || nstreams > 16) return LRAMM_E_INVALID;
+  if (flags & ~LRAMM_BATCH_GRAPH) return LRAMM_E_INVALID;
+  if (flags & LRAMM_BATCH_GRAPH) return LRAMM_E_UNSUPPORTED;
+  lramm_batch* b = new (std::nothrow) lramm_batch();
+  if (!b) return LRAMM_E_INVALID;
+  size_t c = 0;
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i]) {
+      delete b;
+      return LRAMM_E_INVALID;
+    }
+    if (plans[i]->timing) plans[i]->timing = false;   // no event timing inside a batch
+    b->plans.push_back(plans[i]);
+    b->offs.push_back(carve(&c, plans[i]->total));
+  }
+  b->total = c + 256;
+  for (int i = 0; i < count; ++i) b->order.push_back(i);
+  std::vector<double> work(count);
+  for (int i = 0; i < count; ++i) work[i] = product_work(plans[i]->d);
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) { return work[x] > work[y]; });
+  const int ns = nstreams < count ? nstreams : count;
+  std::vector<double> load(ns, 0.0);
+  b->stream_of.assign(count, 0);
+  for (int i : b->order) {
+    int t = 0;
+    for (int u = 1; u < ns; ++u)
+      if (load[u] < load[t]) t = u;
+    b->stream_of[i] = t;
+    load[t] += work[i];
+  }
+  bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+  for (int t = 0; ok && t < ns; ++t) {
+    hipStream_t st;
+    hipEvent_t ev;
+    ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;   // default priority
+    if (ok) b->streams.push_back(st);
+    ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+    if (ok) b->done.push_back(ev);
+  }
+  if (!ok) {
+    batch_free(b);
+    return LRAMM_E_HIP;
+  }
+  *out = b;
+  return LRAMM_OK;
+}
+
+lramm_status lramm_batch_workspace_bytes(const lramm_batch* b, size_t* bytes) {
+  if (!b || !bytes) return LRAMM_E_INVALID;
+  *bytes = b->total;
+  return LRAMM_OK;
+}
+
+void lramm_batch_destroy(lramm_batch* b) {
+  if (b) batch_free(b);
+}
+
+lramm_status lramm_batched_forward(lramm_batch* b, const void* const* A, const int64_t* lda, const void* const* B,
+                                   const int64_t* ldb, void* const* C, const int64_t* ldc, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  if (!b || !A || !lda || !B || !ldb || !C || !ldc) return LRAMM_E_INVALID;
+  if (!ws || ws_bytes < b->total) return LRAMM_E_WORKSPACE;
+  const int n = (int)b->plans.size();
+  for (int i = 0; i < n; ++i) {
+    const lramm_desc& d = b->plans[i]->d;
+    if (!A[i] || !B[i] || !C[i]) return LRAMM_E_INVALID;
+    if (lda[i] < d.k || ldb[i] < d.n || ldc[i] < d.n) return LRAMM_E_SHAPE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* base = reinterpret_cast<uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
+  return batch_issue(b, A, lda, B, ldb, C, ldc, base, s);
+}
+
+lramm_status lramm_batch_status_poll(const lramm_batch* b, const void* ws, void* stream, uint32_t* flags) {
+  if (!b || !ws) return LRAMM_E_INVALID;
+  const uint8_t* base = reinterpret_cast<const uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
+  uint32_t all = 0;
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    uint32_t f = 0;
+    lramm_status st = lramm_status_poll(b->plans[i], base + b->offs[i], stream, &f);
+    if (st != LRAMM_OK && st != LRAMM_E_NONFINITE) return st;
+    all |= f;
+  }
+  if (flags) *flags = all;
+  return (all & LRAMM_FLAG_NONFINITE) ? LRAMM_E_NONFINITE : LRAMM_OK;
 }
 
 // ------------------------------------------------------------ stage APIs --
