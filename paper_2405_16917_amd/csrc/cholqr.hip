@@ -319,12 +319,15 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
 }
 
 // -------------------------------------------------------------- Cholesky --
-// Blocked right-looking Cholesky with 32 x 32 tiles.  Launch p updates every
-// trailing tile (i, j), p < j <= i, with the panel p; the workgroup that
-// finishes tile (p+1, p+1) then factors it, so the next launch finds L and
-// its inverse for that diagonal block ready.  A diagonal block is factored by
-// one wavefront with rows in registers (lane i owns row i) and cross-lane
-// broadcasts by readlane, without barriers.
+// Blocked right-looking Cholesky with 32 x 32 tiles, two panels per launch.
+// Launch p (p even) finds L and Dinv for the diagonal blocks p and p + 1 (and
+// L_{p+1,p}) ready; every trailing tile (i, j), p + 2 <= j <= i, forms its own
+// panel tiles L_{i,p}, L_{i,p+1} (and L_{j,.}) and applies both panels; the
+// workgroup of tile (p+2, p+2) owns (p+3, p+2) and (p+3, p+3) too and
+// factors the diagonal blocks p + 2 and p + 3 one after the other, so the
+// next launch again finds two factored blocks.  Further workgroups form row
+// blocks p and p + 1 of X = L^-1.  A diagonal block is factored by one
+// wavefront with rows in registers (lane i owns row i).
 
 __device__ __forceinline__ double lane_bcast(double v, int lane) {
   int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
@@ -352,7 +355,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // next column (k = j + 1) is on the critical path, and it takes l_{j+1,j}
 // from lane j + 1 by readlane; the other updates of column j are applied
 // one step later, so their LDS loads are off the pivot chain.
-// scratch: NB * NB + NB doubles of LDS private to this wavefront.
+// scratch: NB * NB + 2 NB doubles of LDS private to this wavefront.
 __device__ __attribute__((always_inline)) inline void factor_block_wave(const double* S, double* scratch,
                                                                         const double* diag0, int col0, int l_true,
                                                                         double tol, uint32_t* flags, double* Lout,
@@ -360,13 +363,15 @@ __device__ __attribute__((always_inline)) inline void factor_block_wave(const do
   const int lane = threadIdx.x & 63;
   const int row = lane & 31;
   const bool fac = lane < NB;
-  double* sthr = scratch + NB * NB;   // pivot thresholds (negative: padding column)
-  if (fac) sthr[lane] = col0 + row < l_true ? tol * diag0[col0 + row] : -1.0;
+  double* sthr = scratch + NB * NB;        // pivot thresholds; +inf marks a padding column
+  double* spiv = scratch + NB * NB + NB;   // the pivots, for the breakdown flags
+  const bool live_col = col0 + row < l_true;
+  const double thr = live_col ? tol * diag0[col0 + row] : __builtin_inf();
+  if (fac) sthr[lane] = thr;
   double v[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) v[k] = fac ? S[row * (NB + 1) + k] : (k == row ? 1.0 : 0.0);
   wave_lds_sync();
-  uint32_t bad = 0;
   // the updates from column j - 1 (other than the next column's) are applied
   // one step late, after the pivot of column j, so that the LDS loads of
   // column j - 1 complete while that pivot is computed
@@ -378,20 +383,18 @@ __device__ __attribute__((always_inline)) inline void factor_block_wave(const do
   for (int j = 0; j < NB; ++j) {
     const double tj = sthr[j];
     const double d = lane_bcast(v[j], j);
+    if (lane == 0) spiv[j] = d;
     // 1/sqrt(d): hardware estimate refined by two Newton steps (quadratic
-    // convergence from ~2^-23 to full precision); piv = d / sqrt(d)
+    // convergence from ~2^-23 to full precision)
     const double hd = 0.5 * d;
     double y = __builtin_amdgcn_rsq(d);
     y = y * fma(-hd * y, y, 1.5);
     y = y * fma(-hd * y, y, 1.5);
-    const bool live = tj >= 0.0;
-    const bool ok = live && d > tj && d > 0.0;
-    const double iv = ok ? y : 0.0;
-    bad |= (live && !ok) ? ((d < -tj || d != d) ? (LRAMM_FLAG_BREAKDOWN | LRAMM_FLAG_SQRTNEG) : LRAMM_FLAG_BREAKDOWN)
-                         : 0u;
-    // row lanes: l_ij (0 above the diagonal, d / sqrt(d) on it); column lanes: X[j][c]
-    const double sc = v[j] * ((fac && row < j) ? 0.0 : iv);
-    const double m = (fac && row == j) ? d * iv : sc;
+    const double iv = d > tj ? y : 0.0;      // false for NaN, padding (+inf) and dropped pivots
+    // m = v[j] / l_jj on every lane: l_ij below the diagonal, l_jj = d / sqrt(d)
+    // on it (v[j] of lane j is d), X[j][c] on the column lanes; rows above j
+    // get values that are never read (their L entries are written as zero)
+    const double m = v[j] * iv;
     v[j] = m;
     double* col = scratch + j * NB;
     if (fac) col[lane] = m;
@@ -407,6 +410,13 @@ __device__ __attribute__((always_inline)) inline void factor_block_wave(const do
     for (int k = j + 2; k < NB; ++k) cprev[k] = col[k];
     mprev = m;
   }
+  // breakdown flags from the recorded pivots (row lane j checks column j)
+  wave_lds_sync();
+  uint32_t bad = 0;
+  if (fac && live_col) {
+    const double d = spiv[row];
+    if (!(d > thr)) bad = (d < -thr || d != d) ? (LRAMM_FLAG_BREAKDOWN | LRAMM_FLAG_SQRTNEG) : LRAMM_FLAG_BREAKDOWN;
+  }
   if (fac) {
 #pragma unroll
     for (int k = 0; k < NB; ++k) Lout[(int64_t)row * ldl + k] = k <= row ? v[k] : 0.0;
@@ -414,23 +424,7 @@ __device__ __attribute__((always_inline)) inline void factor_block_wave(const do
 #pragma unroll
     for (int k = 0; k < NB; ++k) Iout[k * NB + row] = v[k];
   }
-  if (lane == 0 && bad && flags) atomicOr(flags, bad);
-}
-
-// First diagonal block (one wavefront).
-__global__ __launch_bounds__(64) void chol_first_kernel(int lw, int l_true, const double* __restrict__ G,
-                                                        double* __restrict__ L, double* __restrict__ Dinv,
-                                                        const double* __restrict__ diag0, double tol,
-                                                        uint32_t* flags) {
-  __shared__ double sS[NB * (NB + 1)];
-  __shared__ double scratch[NB * (NB + 1) + 2 * NB];
-#pragma unroll
-  for (int u = 0; u < NB * NB / 64; ++u) {
-    const int e = threadIdx.x + 64 * u;
-    sS[(e / NB) * (NB + 1) + e % NB] = G[(int64_t)(e / NB) * lw + e % NB];
-  }
-  __syncthreads();
-  factor_block_wave(sS, scratch, diag0, 0, l_true, tol, flags, L, lw, Dinv);
+  if (bad && flags) atomicOr(flags, bad);
 }
 
 // 32 x 32 tile product on 4 wavefronts: out = X Y^T (X, Y in LDS, pitch
@@ -445,6 +439,58 @@ __device__ __forceinline__ v4d tile_xyt(const double (*X)[NB + 1], const double 
     a1 = mfma_f64(X[16 * si + li][kk + 4 + lk], Y[16 * sj + li][kk + 4 + lk], a1);
   }
   return a0 + a1;
+}
+
+typedef double Tile[NB][NB + 1];   // an LDS tile, padded rows
+
+// Global 32 x 32 tile (row stride ld) -> LDS, all loads issued first.
+__device__ __forceinline__ void tile_load(double (*dst)[NB + 1], const double* src, int64_t ld) {
+  const int tid = threadIdx.x;
+  double v[NB * NB / 256];
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = tid + 256 * u;
+    v[u] = src[(int64_t)(e / NB) * ld + e % NB];
+  }
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = tid + 256 * u;
+    dst[e / NB][e % NB] = v[u];
+  }
+}
+
+__device__ __forceinline__ void tile_store(double* dst, int64_t ld, const double (*src)[NB + 1]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = tid + 256 * u;
+    dst[(int64_t)(e / NB) * ld + e % NB] = src[e / NB][e % NB];
+  }
+}
+
+// This wavefront's 16 x 16 sub-tile of an LDS tile, in accumulator layout.
+__device__ __forceinline__ void sub_put(double (*T)[NB + 1], v4d v) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) T[16 * (wave >> 1) + 4 * r + (lane >> 4)][16 * (wave & 1) + (lane & 15)] = v[r];
+}
+__device__ __forceinline__ v4d sub_get(const double (*T)[NB + 1]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v4d v;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = T[16 * (wave >> 1) + 4 * r + (lane >> 4)][16 * (wave & 1) + (lane & 15)];
+  return v;
+}
+__device__ __forceinline__ v4d sub_xyt(const double (*X)[NB + 1], const double (*Y)[NB + 1]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  return tile_xyt(X, Y, wave, lane & 15, lane >> 4);
+}
+
+// In place: T <- T Y^T (a product of two LDS tiles written over its left factor).
+__device__ __forceinline__ void tile_mul_t_inplace(double (*T)[NB + 1], const double (*Y)[NB + 1]) {
+  const v4d v = sub_xyt(T, Y);
+  __syncthreads();
+  sub_put(T, v);
 }
 
 // Block (p, j), j <= p, of X = L^-1 (lower triangular, 32 x 32 blocks):
@@ -516,96 +562,168 @@ __device__ void inverse_block(int lw, int p, int j, const double* __restrict__ L
   for (int r = 0; r < 4; ++r) Xpj[(int64_t)(16 * si + 4 * r + lk) * lw + 16 * sj + li] = -out[r];
 }
 
-// Last row block of X = L^-1 (after the last panel launch).
-__global__ __launch_bounds__(256) void inverse_row_kernel(int lw, int p, const double* __restrict__ L,
-                                                          const double* __restrict__ Dinv, double* __restrict__ Xinv,
-                                                          const uint32_t* gate, uint32_t gate_mask) {
-  if (gate && !(*gate & gate_mask)) return;
-  __shared__ double sS[NB][NB + 1];
-  __shared__ double red[4][NB][NB + 1];
-  inverse_block(lw, p, blockIdx.x, L, Dinv, Xinv, sS, red[0], red[1], red[2], red[3]);
+// Row blocks r0 .. r0 + nrows - 1 of X = L^-1 (nrows 1 or 2); workgroup jc
+// forms the blocks of column block jc in row order, so a row sees the one
+// above it (same workgroup, after a barrier).
+__device__ void inverse_rows(int lw, int r0, int nrows, int jc, const double* __restrict__ L,
+                             const double* __restrict__ Dinv, double* __restrict__ Xinv, double (*sS)[NB + 1],
+                             double (*r0b)[NB + 1], double (*r1b)[NB + 1], double (*r2b)[NB + 1],
+                             double (*r3b)[NB + 1]) {
+  for (int rr = r0; rr < r0 + nrows; ++rr) {
+    if (jc <= rr) inverse_block(lw, rr, jc, L, Dinv, Xinv, sS, r0b, r1b, r2b, r3b);
+    __syncthreads();
+  }
 }
 
-// Launch p (0 <= p < T - 1): workgroup b owns trailing tile (i, j),
-// p < j <= i < T.  It forms L_ip = G_ip Dinv_p^T and L_jp, writes L_ip when
-// j == p + 1, updates G_ij -= L_ip L_jp^T, and the owner of (p+1, p+1)
-// factors that block.  p + 1 further workgroups form row block p of
-// X = L^-1, which is ready because row blocks < p of X and row block p of L
-// were finished by earlier launches.
-__global__ __launch_bounds__(256) void chol_panel_kernel(int lw, int l_true, int p, double* __restrict__ G,
-                                                         double* __restrict__ L, double* __restrict__ Dinv,
-                                                         double* __restrict__ Xinv, const double* __restrict__ diag0,
-                                                         double tol, uint32_t* flags) {
-  __shared__ double sD[NB][NB + 1];
-  __shared__ double sGi[NB][NB + 1], sGj[NB][NB + 1];
-  __shared__ double sLi[NB][NB + 1], sLj[NB][NB + 1];
+__global__ __launch_bounds__(256) void inverse_rows_kernel(int lw, int r0, int nrows, const double* __restrict__ L,
+                                                           const double* __restrict__ Dinv,
+                                                           double* __restrict__ Xinv) {
   __shared__ double sS[NB][NB + 1];
-  __shared__ double scratch[NB * (NB + 1) + 2 * NB];
+  __shared__ double red[4][NB][NB + 1];
+  inverse_rows(lw, r0, nrows, blockIdx.x, L, Dinv, Xinv, sS, red[0], red[1], red[2], red[3]);
+}
+
+// The first two diagonal blocks (one workgroup): factor G_00, form
+// L_10 = G_10 Dinv_0^T, update G_11 and factor it.
+__global__ __launch_bounds__(256) void chol_first2_kernel(int lw, int l_true, const double* __restrict__ G,
+                                                          double* __restrict__ L, double* __restrict__ Dinv,
+                                                          const double* __restrict__ diag0, double tol,
+                                                          uint32_t* flags) {
+  __shared__ Tile s00, s10, s11, sD;
+  __shared__ double scratch[NB * NB + 2 * NB];
   const int T = lw / NB;
-  const int ntrail = (T - p - 1) * (T - p) / 2;
-  if ((int)blockIdx.x >= ntrail) {   // inverse row block p (blocks past the trailing tiles)
-    inverse_block(lw, p, blockIdx.x - ntrail, L, Dinv, Xinv, sS, sGi, sGj, sLi, sLj);
+  const int wave = threadIdx.x >> 6;
+  tile_load(s00, G, lw);
+  if (T > 1) {
+    tile_load(s10, G + (int64_t)NB * lw, lw);
+    tile_load(s11, G + (int64_t)NB * lw + NB, lw);
+  }
+  __syncthreads();
+  if (wave == 0) factor_block_wave(&s00[0][0], scratch, diag0, 0, l_true, tol, flags, L, lw, Dinv);
+  __syncthreads();
+  if (T == 1) return;
+  tile_load(sD, Dinv, NB);
+  __syncthreads();
+  tile_mul_t_inplace(s10, sD);                 // L_10
+  __syncthreads();
+  tile_store(L + (int64_t)NB * lw, lw, s10);
+  sub_put(s11, sub_get(s11) - sub_xyt(s10, s10));
+  __syncthreads();
+  if (wave == 0)
+    factor_block_wave(&s11[0][0], scratch, diag0, NB, l_true, tol, flags, L + (int64_t)NB * lw + NB, lw,
+                      Dinv + NB * NB);
+}
+
+// Launch p (p even, p + 2 < T).  Blocks 0 .. nt-1: trailing tiles (i, j),
+// p + 2 <= j <= i < T, in lower-triangle order (tile 0 = (p+2, p+2) is the
+// diagonal workgroup, tiles 1 and 2 = (p+3, p+2), (p+3, p+3) belong to it);
+// blocks nt .. nt + p + 1: column block jc = b - nt of X row blocks p, p + 1.
+__global__ __launch_bounds__(256) void chol_panel2_kernel(int lw, int l_true, int p, double* __restrict__ G,
+                                                          double* __restrict__ L, double* __restrict__ Dinv,
+                                                          double* __restrict__ Xinv,
+                                                          const double* __restrict__ diag0, double tol,
+                                                          uint32_t* flags) {
+  __shared__ Tile sD0, sD1, sL10, sA0, sA1, sB0, sB1, sU, sV, sW;
+  __shared__ double scratch[NB * NB + 2 * NB];
+  const int T = lw / NB;
+  const int R = T - p - 2;
+  const int nt = R * (R + 1) / 2;
+  const int b = blockIdx.x;
+  if (b >= nt) {   // inverse row blocks p, p + 1
+    inverse_rows(lw, p, 2, b - nt, L, Dinv, Xinv, sU, sA0, sA1, sB0, sB1);
     return;
   }
-  int t = blockIdx.x, di = 0;
-  while (t > di) {
-    t -= di + 1;
-    ++di;
-  }
-  const int i = p + 1 + di, j = p + 1 + t;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
+  int di, dj;
+  lower_tile(b, di, dj);
+  if (b == 1 || b == 2) return;   // owned by the diagonal workgroup
+  const int i = p + 2 + di, j = p + 2 + dj;
+  const int wave = threadIdx.x >> 6;
   const double* Dp = Dinv + (int64_t)p * NB * NB;
-  const double* Gip = G + (int64_t)i * NB * lw + p * NB;
-  const double* Gjp = G + (int64_t)j * NB * lw + p * NB;
-  double* Gij = G + (int64_t)i * NB * lw + j * NB;
-  // every load of this launch is issued here: the panel tiles, Dinv_p and
-  // this thread's elements of the tile being updated
-  double gij[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) gij[r] = Gij[(int64_t)(16 * (wave >> 1) + 4 * r + lk) * lw + 16 * (wave & 1) + li];
-#pragma unroll
-  for (int u = 0; u < NB * NB / 256; ++u) {
-    const int e = tid + 256 * u;
-    const int r = e / NB, c = e % NB;
-    sD[r][c] = Dp[e];
-    sGi[r][c] = Gip[(int64_t)r * lw + c];
-    sGj[r][c] = Gjp[(int64_t)r * lw + c];
+  // every load first: Dinv_p, Dinv_{p+1}, L_{p+1,p}, the panel tiles of rows i (and j)
+  tile_load(sD0, Dp, NB);
+  tile_load(sD1, Dp + NB * NB, NB);
+  tile_load(sL10, L + (int64_t)(p + 1) * NB * lw + p * NB, lw);
+  tile_load(sA0, G + (int64_t)i * NB * lw + p * NB, lw);
+  tile_load(sA1, G + (int64_t)i * NB * lw + (p + 1) * NB, lw);
+  const bool diag = b == 0;
+  const bool two = diag && i + 1 < T;          // the diagonal workgroup also owns row i + 1
+  const bool other = !diag && j != i;          // a distinct row j
+  if (other || two) {
+    const int r = two ? i + 1 : j;
+    tile_load(sB0, G + (int64_t)r * NB * lw + p * NB, lw);
+    tile_load(sB1, G + (int64_t)r * NB * lw + (p + 1) * NB, lw);
   }
+  tile_load(sU, G + (int64_t)i * NB * lw + j * NB, lw);                  // G_ij (G_ii for the diagonal)
+  if (two) {
+    tile_load(sV, G + (int64_t)(i + 1) * NB * lw + i * NB, lw);          // G_{i+1,i}
+    tile_load(sW, G + (int64_t)(i + 1) * NB * lw + (i + 1) * NB, lw);    // G_{i+1,i+1}
+  }
+  __syncthreads();
+  const bool hasB = other || two;
+  // panel p: L_{r,p} = G_{r,p} Dinv_p^T
+  {
+    const v4d a = sub_xyt(sA0, sD0);
+    const v4d c = hasB ? sub_xyt(sB0, sD0) : a;
+    __syncthreads();
+    sub_put(sA0, a);
+    if (hasB) sub_put(sB0, c);
+  }
+  __syncthreads();
+  // panel p + 1: L_{r,p+1} = (G_{r,p+1} - L_{r,p} L_{p+1,p}^T) Dinv_{p+1}^T
+  sub_put(sA1, sub_get(sA1) - sub_xyt(sA0, sL10));
+  if (hasB) sub_put(sB1, sub_get(sB1) - sub_xyt(sB0, sL10));
   __syncthreads();
   {
-    v4d li_acc = tile_xyt(sGi, sD, wave, li, lk);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) sLi[16 * (wave >> 1) + 4 * r + lk][16 * (wave & 1) + li] = li_acc[r];
-    if (j != i) {
-      v4d lj_acc = tile_xyt(sGj, sD, wave, li, lk);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) sLj[16 * (wave >> 1) + 4 * r + lk][16 * (wave & 1) + li] = lj_acc[r];
-    }
+    const v4d a = sub_xyt(sA1, sD1);
+    const v4d c = hasB ? sub_xyt(sB1, sD1) : a;
+    __syncthreads();
+    sub_put(sA1, a);
+    if (hasB) sub_put(sB1, c);
   }
   __syncthreads();
-  if (j == p + 1) {
-    double* Lip = L + (int64_t)i * NB * lw + p * NB;
-#pragma unroll
-    for (int u = 0; u < NB * NB / 256; ++u) {
-      const int e = tid + 256 * u;
-      Lip[(int64_t)(e / NB) * lw + e % NB] = sLi[e / NB][e % NB];
-    }
-  }
-  const v4d upd = tile_xyt(sLi, j != i ? sLj : sLi, wave, li, lk);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int rr = 16 * (wave >> 1) + 4 * r + lk, cc = 16 * (wave & 1) + li;
-    const double v = gij[r] - upd[r];
-    Gij[(int64_t)rr * lw + cc] = v;
-    sS[rr][cc] = v;
-  }
-  if (i == p + 1 && j == p + 1) {
+  if (!diag) {
+    // G_ij -= L_{i,p} L_{j,p}^T + L_{i,p+1} L_{j,p+1}^T;  column p + 2 writes the panel tiles of row i
+    const double (*J0)[NB + 1] = other ? sB0 : sA0;
+    const double (*J1)[NB + 1] = other ? sB1 : sA1;
+    const v4d g = sub_get(sU) - (sub_xyt(sA0, J0) + sub_xyt(sA1, J1));
+    sub_put(sU, g);
     __syncthreads();
-    if (wave == 0)
-      factor_block_wave(&sS[0][0], scratch, diag0, (p + 1) * NB, l_true, tol, flags,
-                        L + (int64_t)(p + 1) * NB * lw + (p + 1) * NB, lw, Dinv + (int64_t)(p + 1) * NB * NB);
+    tile_store(G + (int64_t)i * NB * lw + j * NB, lw, sU);
+    if (j == p + 2) {
+      tile_store(L + (int64_t)i * NB * lw + p * NB, lw, sA0);
+      tile_store(L + (int64_t)i * NB * lw + (p + 1) * NB, lw, sA1);
+    }
+    return;
   }
+  // diagonal workgroup: rows i (= p + 2) and i + 1
+  tile_store(L + (int64_t)i * NB * lw + p * NB, lw, sA0);
+  tile_store(L + (int64_t)i * NB * lw + (p + 1) * NB, lw, sA1);
+  if (two) {
+    tile_store(L + (int64_t)(i + 1) * NB * lw + p * NB, lw, sB0);
+    tile_store(L + (int64_t)(i + 1) * NB * lw + (p + 1) * NB, lw, sB1);
+  }
+  sub_put(sU, sub_get(sU) - (sub_xyt(sA0, sA0) + sub_xyt(sA1, sA1)));
+  if (two) {
+    sub_put(sV, sub_get(sV) - (sub_xyt(sB0, sA0) + sub_xyt(sB1, sA1)));
+    sub_put(sW, sub_get(sW) - (sub_xyt(sB0, sB0) + sub_xyt(sB1, sB1)));
+  }
+  __syncthreads();
+  double* Di = Dinv + (int64_t)i * NB * NB;
+  if (wave == 0)
+    factor_block_wave(&sU[0][0], scratch, diag0, i * NB, l_true, tol, flags, L + (int64_t)i * NB * lw + i * NB,
+                      lw, Di);
+  if (!two) return;
+  __syncthreads();
+  tile_load(sD0, Di, NB);
+  __syncthreads();
+  tile_mul_t_inplace(sV, sD0);                 // L_{i+1,i}
+  __syncthreads();
+  tile_store(L + (int64_t)(i + 1) * NB * lw + i * NB, lw, sV);
+  sub_put(sW, sub_get(sW) - sub_xyt(sV, sV));
+  __syncthreads();
+  if (wave == 0)
+    factor_block_wave(&sW[0][0], scratch, diag0, (i + 1) * NB, l_true, tol, flags,
+                      L + (int64_t)(i + 1) * NB * lw + (i + 1) * NB, lw, Dinv + (int64_t)(i + 1) * NB * NB);
 }
 
 // One wavefront: acc[si][sj] (16 x 16 sub-tiles) += X[32 x 32] Y[32 x 32]^T,
@@ -885,21 +1003,27 @@ static lramm_status gram(int64_t rows, int lw, int l_true, const T* X, int64_t l
   return LRAMM_OK;
 }
 
-// Cholesky of w.G into w.L, w.Dinv and X = L^-1 (one launch per panel).
+// Cholesky of w.G into w.L, w.Dinv and X = L^-1 (one launch per two panels).
 static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32_t* flags, hipStream_t s,
                                      const TimingHook* hook) {
   const double tol = 64.0 * (double)l_true * 0x1p-53;
   const int Tn = lw / NB;
-  hipLaunchKernelGGL(chol_first_kernel, dim3(1), dim3(64), 0, s, lw, l_true, w.G, w.L, w.Dinv, w.diag0, tol, flags);
-  LRAMM_HIP(hipGetLastError());
-  for (int p = 0; p + 1 < Tn; ++p) {
-    const int nb = (Tn - p - 1) * (Tn - p) / 2 + p + 1;
+  {
     HookScope hs(hook, SUB_CHOL_PANEL);
-    hipLaunchKernelGGL(chol_panel_kernel, dim3(nb), dim3(256), 0, s, lw, l_true, p, w.G, w.L, w.Dinv, w.X, w.diag0,
-                       tol, flags);
+    hipLaunchKernelGGL(chol_first2_kernel, dim3(1), dim3(256), 0, s, lw, l_true, w.G, w.L, w.Dinv, w.diag0, tol,
+                       flags);
+  }
+  LRAMM_HIP(hipGetLastError());
+  int p = 0;
+  for (; p + 2 < Tn; p += 2) {
+    const int R = Tn - p - 2;
+    const int nb = R * (R + 1) / 2 + p + 2;
+    HookScope hs(hook, SUB_CHOL_PANEL);
+    hipLaunchKernelGGL(chol_panel2_kernel, dim3(nb), dim3(256), 0, s, lw, l_true, p, w.G, w.L, w.Dinv, w.X,
+                       w.diag0, tol, flags);
     LRAMM_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(inverse_row_kernel, dim3(Tn), dim3(256), 0, s, lw, Tn - 1, w.L, w.Dinv, w.X, nullptr, 0u);
+  hipLaunchKernelGGL(inverse_rows_kernel, dim3(Tn), dim3(256), 0, s, lw, p, Tn - p, w.L, w.Dinv, w.X);
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }
