@@ -217,7 +217,8 @@ template <typename T, bool ADD>
 __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int lw, int ncols,
                                                               const T* __restrict__ X, int64_t ldx,
                                                               const double* __restrict__ W, double* __restrict__ Q,
-                                                              int64_t ldq, int zero_to, int vec) {
+                                                              int64_t ldq, int zero_to, int vec,
+                                                              uint32_t* __restrict__ colmax) {
   extern __shared__ double sA[];   // TS_ROWS x ts_pitch(lw)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -296,6 +297,7 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
           for (int q = 0; q < 4; ++q) b[0][st][q] = bn[0][st][q], b[1][st][q] = bn[1][st][q];
       }
     }
+    uint32_t m0 = 0, m1 = 0;   // column maxima of fl32(|Q|) over this wavefront's rows
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int rr = 4 * r + lk;
@@ -308,6 +310,19 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
         }
         Q[row * ldq + cb0 + li] = v0;
         Q[row * ldq + cb0 + 16 + li] = v1;
+        m0 = max(m0, __float_as_uint(fabsf((float)v0)));
+        m1 = max(m1, __float_as_uint(fabsf((float)v1)));
+      }
+    }
+    if (colmax) {
+      // the four lane groups hold the same columns: combine, then one atomic per column
+      m0 = max(m0, (uint32_t)__shfl_xor((int)m0, 16));
+      m0 = max(m0, (uint32_t)__shfl_xor((int)m0, 32));
+      m1 = max(m1, (uint32_t)__shfl_xor((int)m1, 16));
+      m1 = max(m1, (uint32_t)__shfl_xor((int)m1, 32));
+      if (lk == 0) {
+        if (m0) atomicMax(colmax + cb0 + li, m0);
+        if (m1) atomicMax(colmax + cb0 + 16 + li, m1);
       }
     }
   }
@@ -1030,7 +1045,8 @@ static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32
 
 template <typename T, bool ADD>
 static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t ldx, const double* W, double* Q,
-                          int64_t ldq, int zero_to, hipStream_t s, const TimingHook* hook) {
+                          int64_t ldq, int zero_to, hipStream_t s, const TimingHook* hook,
+                          uint32_t* colmax = nullptr) {
   static bool attr_set = false;
   if (!attr_set) {   // up to 16 x 1028 doubles of LDS
     LRAMM_HIP(hipFuncSetAttribute((const void*)tsmul_kernel<T, ADD>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1042,14 +1058,14 @@ static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t l
   const int vec = ((uintptr_t)X % (4 * sizeof(T)) == 0 && ldx % 4 == 0) ? 1 : 0;
   const size_t shm = (size_t)TS_ROWS * ts_pitch(lw) * sizeof(double);
   hipLaunchKernelGGL((tsmul_kernel<T, ADD>), dim3((unsigned)ceil_div(rows, (int64_t)TS_ROWS)), dim3(TS_WAVES * 64),
-                     shm, s, rows, lw, ncols, X, ldx, W, Q, ldq, zero_to, vec);
+                     shm, s, rows, lw, ncols, X, ldx, W, Q, ldq, zero_to, vec, colmax);
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }
 
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
                             int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s,
-                            const TimingHook* hook) {
+                            const TimingHook* hook, uint32_t* colmax) {
   if (rows == 0 || l == 0) return LRAMM_OK;
   int lw, nc;
   int64_t rpc;
@@ -1102,7 +1118,7 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
                        w.diag0, tol, flags, w.gate, kGateFull);
   }
   LRAMM_HIP(hipGetLastError());
-  LRAMM_TRY((tsmul<double, true>(rows, lw, lw, w.Q1, lw, w.W, Q, ldq, zero_to, s, hook)));
+  LRAMM_TRY((tsmul<double, true>(rows, lw, lw, w.Q1, lw, w.W, Q, ldq, zero_to, s, hook, colmax)));
   return LRAMM_OK;
 }
 

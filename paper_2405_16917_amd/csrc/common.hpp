@@ -152,9 +152,13 @@ lramm_status fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 // Internal launchers (no argument validation beyond what the kernels need;
 // the C ABI layer validates).
 
+// Column form (transpose = 1) with amax_ws: the column maxima go to that
+// caller-zeroed buffer (abs bit patterns, cols entries) -- or are already
+// there when amax_ready -- and the quantise pass writes the scales, saving the
+// fill and scale launches.
 lramm_status launch_quantize(int64_t rows, int64_t cols, const void* X, int64_t ldx, int xtype, int fmt,
                              int transpose, void* Xq, int64_t pitch, float* scales, uint32_t* flags,
-                             hipStream_t s);
+                             hipStream_t s, uint32_t* amax_ws = nullptr, bool amax_ready = false);
 
 lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void* Lq, int64_t ldl,
                             const float* dL, const void* Rq, int64_t ldr, const float* dR, float alpha,
@@ -174,9 +178,11 @@ struct TimingHook {
 // sub-stage ids inside the orthonormalisation (continuing the forward's list)
 enum { SUB_CHOL_GRAM = 17, SUB_CHOL_PANEL = 18, SUB_CHOL_SOLVE = 19, SUB_CHOL_SERIES = 20, SUB_CHOL_APPLY = 21 };
 
+// colmax (nullable, caller-zeroed, ldq entries): column maxima of fl32(|Q|)
+// as bit patterns, accumulated while Q is written.
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
                             int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s,
-                            const TimingHook* hook = nullptr);
+                            const TimingHook* hook = nullptr, uint32_t* colmax = nullptr);
 size_t cholqr2_workspace(int64_t rows, int64_t l);
 
 lramm_status launch_dense_gemm_nt(int64_t M, int64_t N, int64_t K, int dtype, const void* L, int64_t ldl,

@@ -35,6 +35,10 @@ struct lramm_plan {
   size_t off_Bt, off_Btq, off_sBt, off_Tt, off_Ttq, off_sTt;
   size_t off_chol, chol_bytes, off_split, split_bytes;
   size_t off_W, off_Bte, off_V;
+  // zero-filled at the start of every forward: the status word, then the
+  // column-maxima buffers of every column quantisation of the pass
+  size_t off_zero, zero_words;
+  size_t mx_A, mx_B, mx_Om, mx_Q, mx_QZ;   // word offsets inside the zero region
   size_t total;
   int64_t pAr, pAc, pBc, pOm, pQZc, pQc, pQr, pBtq, pTtq;
   // side stream for the work independent of the orthonormalisation chain
@@ -197,7 +201,22 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   p->pTtq = pitch_bytes(l, d.fmt_g2);
 
   size_t c = 0;
-  p->off_flags = carve(&c, 256);
+  {
+    size_t w = 64;   // status word (first) and padding
+    auto seg = [&](size_t words) {
+      size_t o = w;
+      w += (words + 63) / 64 * 64;
+      return o;
+    };
+    p->mx_A = seg((size_t)k);
+    p->mx_B = seg((size_t)n);
+    p->mx_Om = seg((size_t)l);
+    p->mx_Q = seg((size_t)lp * (d.q + 1));
+    p->mx_QZ = seg((size_t)lp * (d.q > 0 ? d.q : 1));
+    p->zero_words = w;
+    p->off_zero = carve(&c, w * 4);
+    p->off_flags = p->off_zero;
+  }
   p->off_Ar = carve(&c, (size_t)m * p->pAr);
   p->off_sAr = carve(&c, (size_t)m * 4);
   p->off_Ac = carve(&c, (size_t)k * p->pAc);
@@ -311,7 +330,12 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
   uint8_t* base = reinterpret_cast<uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
   void* W = base;
   uint32_t* flags = at<uint32_t>(W, P->off_flags);
-  LRAMM_TRY(fill_u32(flags, 0u, 1, s));
+  uint32_t* zero = at<uint32_t>(W, P->off_zero);
+  LRAMM_TRY(fill_u32(zero, 0u, (int64_t)P->zero_words, s));
+  uint32_t* mxA = zero + P->mx_A;
+  uint32_t* mxB = zero + P->mx_B;
+  auto mxQ = [&](int c) { return zero + P->mx_Q + (size_t)c * lp; };
+  auto mxQZ = [&](int it) { return zero + P->mx_QZ + (size_t)it * lp; };
   void* split = P->split_bytes ? at<void>(W, P->off_split) : nullptr;
   const size_t sb = P->split_bytes;
 
@@ -348,12 +372,14 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
     LRAMM_HIP(hipEventRecord(P->ev_fork, s));
     LRAMM_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
   }
-  TIMED_ON(s2, ST_QUANT_A_COLS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_proj, 1, Ac, P->pAc, sAc, flags, s2));
-  TIMED_ON(s2, ST_QUANT_B, launch_quantize(k, n, B, ldb, d.b_type, d.fmt_g1, 1, Bc, P->pBc, sBc, flags, s2));
+  TIMED_ON(s2, ST_QUANT_A_COLS,
+           launch_quantize(m, k, A, lda, d.a_type, d.fmt_proj, 1, Ac, P->pAc, sAc, flags, s2, mxA));
+  TIMED_ON(s2, ST_QUANT_B, launch_quantize(k, n, B, ldb, d.b_type, d.fmt_g1, 1, Bc, P->pBc, sBc, flags, s2, mxB));
   if (P->side) LRAMM_HIP(hipEventRecord(P->ev_join, P->side));
   TIMED(ST_QUANT_A_ROWS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_sketch, 0, Ar, P->pAr, sAr, flags, s));
   if (omega) {
-    TIMED(ST_QUANT_OMEGA, launch_quantize(k, l, omega, ldo, LRAMM_F32, d.fmt_sketch, 1, Om, P->pOm, sOm, flags, s));
+    TIMED(ST_QUANT_OMEGA, launch_quantize(k, l, omega, ldo, LRAMM_F32, d.fmt_sketch, 1, Om, P->pOm, sOm, flags, s,
+                                          zero + P->mx_Om));
   } else {
     float* OmT = at<float>(W, P->off_OmT);
     TIMED(ST_OMEGA, launch_omega(d.seed, k, l, l, OmT, k, s));
@@ -362,7 +388,7 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
   // sketch and orthonormalisation
   TIMED(ST_SKETCH, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, P->pAr, sAr, Om, P->pOm, sOm, 1.0f, 0.0f, Y, lp,
                                   LRAMM_F32, nullptr, 0, split, sb, s));
-  TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk));
+  TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(0)));
   uint8_t* Qc = at<uint8_t>(W, P->off_Qc);
   float* sQc = at<float>(W, P->off_sQc);
   if (P->side) LRAMM_HIP(hipStreamWaitEvent(s, P->ev_join, 0));   // join: A_c and B_c ready
@@ -371,18 +397,22 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
     double* QZ = at<double>(W, P->off_QZ);
     uint8_t* QZc = at<uint8_t>(W, P->off_QZc);
     float* sQZc = at<float>(W, P->off_sQZc);
-    TIMED(ST_QUANT_Q_COLS, launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s));
+    TIMED(ST_QUANT_Q_COLS,
+          launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s, mxQ(it), true));
     TIMED(ST_POWER_Z, launch_gemm_nt(k, l, m, d.fmt_proj, Ac, P->pAc, sAc, Qc, P->pQc, sQc, 1.0f, 0.0f, Z, lp,
                                      LRAMM_F32, nullptr, 0, split, sb, s));
-    TIMED(ST_CHOLQR2, launch_cholqr2(k, l, Z, lp, LRAMM_F32, QZ, lp, cws, P->chol_bytes, flags, s, hk));
-    TIMED(ST_QUANT_QZ, launch_quantize(k, l, QZ, lp, LRAMM_F64, d.fmt_sketch, 1, QZc, P->pQZc, sQZc, flags, s));
+    TIMED(ST_CHOLQR2, launch_cholqr2(k, l, Z, lp, LRAMM_F32, QZ, lp, cws, P->chol_bytes, flags, s, hk, mxQZ(it)));
+    TIMED(ST_QUANT_QZ,
+          launch_quantize(k, l, QZ, lp, LRAMM_F64, d.fmt_sketch, 1, QZc, P->pQZc, sQZc, flags, s, mxQZ(it), true));
     TIMED(ST_POWER_Y, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, P->pAr, sAr, QZc, P->pQZc, sQZc, 1.0f, 0.0f, Y, lp,
                                      LRAMM_F32, nullptr, 0, split, sb, s));
-    TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk));
+    TIMED(ST_CHOLQR2,
+          launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(it + 1)));
   }
   // projection Bt = Q^T A  (l x k)
   float* Bt = at<float>(W, P->off_Bt);
-  TIMED(ST_QUANT_Q_COLS, launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s));
+  TIMED(ST_QUANT_Q_COLS,
+        launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s, mxQ(d.q), true));
   TIMED(ST_PROJ, launch_gemm_nt(l, k, m, d.fmt_proj, Qc, P->pQc, sQc, Ac, P->pAc, sAc, 1.0f, 0.0f, Bt, k, LRAMM_F32,
                                 nullptr, 0, split, sb, s));
   // G1: T^T = B_c . Bt_q^T  (n x l)

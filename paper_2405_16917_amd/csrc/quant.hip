@@ -167,7 +167,8 @@ __global__ __launch_bounds__(256) void colmax_kernel(int64_t rows, int64_t cols,
 template <typename T, int FMT>
 __global__ __launch_bounds__(256) void quant_cols_t_kernel(int64_t rows, int64_t cols, const T* __restrict__ X,
                                                            int64_t ldx, const uint32_t* __restrict__ amax_bits,
-                                                           uint8_t* __restrict__ Xq, int64_t pitch) {
+                                                           uint8_t* __restrict__ Xq, int64_t pitch,
+                                                           float* __restrict__ scales_out, uint32_t* flags) {
   // codes of the tile, transposed: sT[col][k]; 2 bytes per code for bf16
   __shared__ uint16_t sT[64][66];
   const int t = threadIdx.x;
@@ -179,8 +180,17 @@ __global__ __launch_bounds__(256) void quant_cols_t_kernel(int64_t rows, int64_t
   if (col < cols) {
     if constexpr (FMT == LRAMM_BF16F) {
       lam = 1.0f;
+      if (scales_out && blockIdx.y == 0 && t < 64) scales_out[col] = 1.0f;
     } else {
-      lam = qparams(__uint_as_float(amax_bits[col]), qmax).lam;
+      const uint32_t mb = amax_bits[col];
+      const QParams qp = qparams(__uint_as_float(mb), qmax);
+      lam = qp.lam;
+      // the first row of tiles also writes the scales (when the maxima live
+      // in a separate buffer) and reports non-finite columns
+      if (scales_out && blockIdx.y == 0 && t < 64) {
+        scales_out[col] = qp.d;
+        if (mb >= 0x7f800000u && flags) atomicOr(flags, LRAMM_FLAG_NONFINITE);
+      }
     }
   }
 #pragma unroll 4
@@ -260,7 +270,8 @@ __global__ void col_scales_kernel(int64_t cols, float* scales, uint32_t* flags) 
 
 template <typename T, int FMT>
 static lramm_status quantize_typed(int64_t rows, int64_t cols, const T* X, int64_t ldx, int transpose, uint8_t* Xq,
-                                   int64_t pitch, float* scales, uint32_t* flags, hipStream_t s) {
+                                   int64_t pitch, float* scales, uint32_t* flags, hipStream_t s, uint32_t* amax_ws,
+                                   bool amax_ready) {
   if (!transpose) {
     if (rows == 0) return LRAMM_OK;
     int64_t pe = pitch_elems(pitch, FMT);
@@ -273,6 +284,21 @@ static lramm_status quantize_typed(int64_t rows, int64_t cols, const T* X, int64
   }
   // column vectors, transposed output: cols x pitch
   if (cols == 0) return LRAMM_OK;
+  if (amax_ws) {
+    // maxima in a caller-zeroed buffer (or already there): no fill, and the
+    // quantise pass writes the scales itself
+    if (FMT != LRAMM_BF16F && rows > 0 && !amax_ready) {
+      dim3 g1((unsigned)ceil_div(cols, 256), (unsigned)ceil_div(rows, (int64_t)64));
+      hipLaunchKernelGGL((colmax_kernel<T>), g1, dim3(256), 0, s, rows, cols, X, ldx, amax_ws, (int64_t)64);
+      LRAMM_HIP(hipGetLastError());
+    }
+    int64_t pe = pitch_elems(pitch, FMT);
+    dim3 g2((unsigned)ceil_div(cols, 64), (unsigned)(pe / 64));
+    hipLaunchKernelGGL((quant_cols_t_kernel<T, FMT>), g2, dim3(256), 0, s, rows, cols, X, ldx, amax_ws, Xq, pitch,
+                       scales, flags);
+    LRAMM_HIP(hipGetLastError());
+    return LRAMM_OK;
+  }
   uint32_t* amax = reinterpret_cast<uint32_t*>(scales);
   LRAMM_TRY(fill_u32(amax, 0u, cols, s));
   if (FMT != LRAMM_BF16F && rows > 0) {
@@ -283,7 +309,8 @@ static lramm_status quantize_typed(int64_t rows, int64_t cols, const T* X, int64
   }
   int64_t pe = pitch_elems(pitch, FMT);
   dim3 g2((unsigned)ceil_div(cols, 64), (unsigned)(pe / 64));
-  hipLaunchKernelGGL((quant_cols_t_kernel<T, FMT>), g2, dim3(256), 0, s, rows, cols, X, ldx, amax, Xq, pitch);
+  hipLaunchKernelGGL((quant_cols_t_kernel<T, FMT>), g2, dim3(256), 0, s, rows, cols, X, ldx, amax, Xq, pitch,
+                     (float*)nullptr, (uint32_t*)nullptr);
   LRAMM_HIP(hipGetLastError());
   hipLaunchKernelGGL((col_scales_kernel<FMT>), dim3((unsigned)ceil_div(cols, 256)), dim3(256), 0, s, cols, scales,
                      flags);
@@ -293,27 +320,28 @@ static lramm_status quantize_typed(int64_t rows, int64_t cols, const T* X, int64
 
 template <typename T>
 static lramm_status quantize_fmt(int64_t rows, int64_t cols, const T* X, int64_t ldx, int fmt, int transpose,
-                                 uint8_t* Xq, int64_t pitch, float* scales, uint32_t* flags, hipStream_t s) {
+                                 uint8_t* Xq, int64_t pitch, float* scales, uint32_t* flags, hipStream_t s,
+                                 uint32_t* amax_ws, bool amax_ready) {
   switch (fmt) {
-    case LRAMM_INT8: return quantize_typed<T, LRAMM_INT8>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s);
-    case LRAMM_INT4: return quantize_typed<T, LRAMM_INT4>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s);
-    case LRAMM_FP8: return quantize_typed<T, LRAMM_FP8>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s);
-    case LRAMM_BF16F: return quantize_typed<T, LRAMM_BF16F>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s);
+    case LRAMM_INT8: return quantize_typed<T, LRAMM_INT8>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s, amax_ws, amax_ready);
+    case LRAMM_INT4: return quantize_typed<T, LRAMM_INT4>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s, amax_ws, amax_ready);
+    case LRAMM_FP8: return quantize_typed<T, LRAMM_FP8>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s, amax_ws, amax_ready);
+    case LRAMM_BF16F: return quantize_typed<T, LRAMM_BF16F>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s, amax_ws, amax_ready);
     default: return LRAMM_E_INVALID;
   }
 }
 
 lramm_status launch_quantize(int64_t rows, int64_t cols, const void* X, int64_t ldx, int xtype, int fmt,
                              int transpose, void* Xq, int64_t pitch, float* scales, uint32_t* flags,
-                             hipStream_t s) {
+                             hipStream_t s, uint32_t* amax_ws, bool amax_ready) {
   uint8_t* q = reinterpret_cast<uint8_t*>(Xq);
   switch (xtype) {
     case LRAMM_F32:
-      return quantize_fmt<float>(rows, cols, (const float*)X, ldx, fmt, transpose, q, pitch, scales, flags, s);
+      return quantize_fmt<float>(rows, cols, (const float*)X, ldx, fmt, transpose, q, pitch, scales, flags, s, amax_ws, amax_ready);
     case LRAMM_BF16:
-      return quantize_fmt<uint16_t>(rows, cols, (const uint16_t*)X, ldx, fmt, transpose, q, pitch, scales, flags, s);
+      return quantize_fmt<uint16_t>(rows, cols, (const uint16_t*)X, ldx, fmt, transpose, q, pitch, scales, flags, s, amax_ws, amax_ready);
     case LRAMM_F64:
-      return quantize_fmt<double>(rows, cols, (const double*)X, ldx, fmt, transpose, q, pitch, scales, flags, s);
+      return quantize_fmt<double>(rows, cols, (const double*)X, ldx, fmt, transpose, q, pitch, scales, flags, s, amax_ws, amax_ready);
     default:
       return LRAMM_E_INVALID;
   }
