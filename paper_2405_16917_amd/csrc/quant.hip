@@ -265,6 +265,54 @@ __global__ void col_scales_kernel(int64_t cols, float* scales, uint32_t* flags) 
     scales[c] = qparams(__uint_as_float(b), qmax).d;
   }
 }
+// Row vectors held in registers: one read of the row (all loads issued
+// together), the wavefront maximum, then the codes from the registers.  NV
+// groups of 4 elements per lane cover 256 NV elements of the padded row.
+template <typename T, int FMT, int NV>
+__global__ __launch_bounds__(256) void quant_rows_reg_kernel(int64_t rows, int64_t cols, const T* __restrict__ X,
+                                                             int64_t ldx, uint8_t* __restrict__ Xq, int64_t pitch,
+                                                             int64_t pelems, float* __restrict__ scales,
+                                                             uint32_t* flags, int vec) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const T* xr = X + row * ldx;
+  uint8_t* qr = Xq + row * pitch;
+  const float qmax = FMT == LRAMM_INT8 ? 127.0f : (FMT == LRAMM_INT4 ? 7.0f : 448.0f);
+  float v[NV][4];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    bool live[4];
+    load4<T>(xr, (int64_t)(c * 64 + lane) * 4, cols, vec != 0, v[c], live);
+  }
+  float lam = 1.0f;
+  if constexpr (FMT != LRAMM_BF16F) {
+    unsigned amax = 0;
+#pragma unroll
+    for (int c = 0; c < NV; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) amax = max(amax, abs_bits(v[c][j]));   // zero past cols
+    unsigned mb = wave_max_u32(amax);             // bit order == value order for |x|
+    if (mb >= 0x7f800000u) {
+      if (lane == 0 && flags) atomicOr(flags, LRAMM_FLAG_NONFINITE);
+    }
+    QParams qp = qparams(__uint_as_float(mb), qmax);
+    lam = qp.lam;
+    if (lane == 0) scales[row] = qp.d;
+  } else {
+    if (lane == 0) scales[row] = 1.0f;
+  }
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    const int64_t c0 = (int64_t)(c * 64 + lane) * 4;
+    if (c0 < pelems) {
+      bool live[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) live[j] = c0 + j < cols && (FMT == LRAMM_BF16F || lam != 0.0f);
+      store4<FMT>(qr, c0, v[c], live, lam);
+    }
+  }
+}
 
 // ---------------------------------------------------------------- launch --
 
@@ -277,8 +325,21 @@ static lramm_status quantize_typed(int64_t rows, int64_t cols, const T* X, int64
     int64_t pe = pitch_elems(pitch, FMT);
     bool vec = ((uintptr_t)X % (4 * sizeof(T)) == 0) && (ldx % 4 == 0);
     dim3 grid((unsigned)ceil_div(rows, 4));
-    hipLaunchKernelGGL((quant_rows_kernel<T, FMT>), grid, dim3(256), 0, s, rows, cols, X, ldx, Xq, pitch, pe, scales,
-                       flags, vec ? 1 : 0);
+    const int v = vec ? 1 : 0;
+    const int64_t groups = ceil_div(pe, (int64_t)256);   // 4-element groups per lane
+#define ROWS_REG(NV)                                                                                            \
+  hipLaunchKernelGGL((quant_rows_reg_kernel<T, FMT, NV>), grid, dim3(256), 0, s, rows, cols, X, ldx, Xq, pitch, pe, \
+                     scales, flags, v)
+    if (groups <= 1) ROWS_REG(1);
+    else if (groups <= 2) ROWS_REG(2);
+    else if (groups <= 4) ROWS_REG(4);
+    else if (groups <= 8) ROWS_REG(8);
+    else if (groups <= 16) ROWS_REG(16);
+    else if (groups <= 32 && sizeof(T) <= 4) ROWS_REG(32);
+    else
+      hipLaunchKernelGGL((quant_rows_kernel<T, FMT>), grid, dim3(256), 0, s, rows, cols, X, ldx, Xq, pitch, pe,
+                         scales, flags, v);
+#undef ROWS_REG
     LRAMM_HIP(hipGetLastError());
     return LRAMM_OK;
   }
