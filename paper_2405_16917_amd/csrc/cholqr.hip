@@ -368,9 +368,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // i.e. the Cholesky update of row i and the same elimination on column c of
 // X, reading l_kj from LDS (uniform-address loads).  Only the update of the
 // next column (k = j + 1) is on the critical path, and it takes l_{j+1,j}
-// from lane j + 1 by readlane; the other updates of column j are applied
-// one step later, so their LDS loads are off the pivot chain.
-// scratch: NB * NB + 2 NB doubles of LDS private to this wavefront.
+// from lane j + 1 by readlane.
+// scratch: NB * NB doubles of LDS private to this wavefront.
+template <int NEWTON = 2>
 __device__ __attribute__((always_inline)) inline void factor_block_wave(const double* S, double* scratch,
                                                                         const double* diag0, int col0, int l_true,
                                                                         double tol, uint32_t* flags, double* Lout,
@@ -378,34 +378,35 @@ __device__ __attribute__((always_inline)) inline void factor_block_wave(const do
   const int lane = threadIdx.x & 63;
   const int row = lane & 31;
   const bool fac = lane < NB;
-  double* sthr = scratch + NB * NB;        // pivot thresholds; +inf marks a padding column
-  double* spiv = scratch + NB * NB + NB;   // the pivots, for the breakdown flags
+  // lane j's pivot threshold for column j (+inf marks a padding column);
+  // lane j tests its own pivot and a ballot makes the outcome uniform
   const bool live_col = col0 + row < l_true;
   const double thr = live_col ? tol * diag0[col0 + row] : __builtin_inf();
-  if (fac) sthr[lane] = thr;
   double v[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) v[k] = fac ? S[row * (NB + 1) + k] : (k == row ? 1.0 : 0.0);
-  wave_lds_sync();
-  // the updates from column j - 1 (other than the next column's) are applied
-  // one step late, after the pivot of column j, so that the LDS loads of
-  // column j - 1 complete while that pivot is computed
+  uint64_t okbits = 0, negbits = 0;
+  // updates from column j - 1 other than the next column's are applied one
+  // step late, after pivot j, so that their LDS loads complete meanwhile
   double cprev[NB];
   double mprev = 0.0;
 #pragma unroll
   for (int k = 0; k < NB; ++k) cprev[k] = 0.0;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    const double tj = sthr[j];
     const double d = lane_bcast(v[j], j);
-    if (lane == 0) spiv[j] = d;
-    // 1/sqrt(d): hardware estimate refined by two Newton steps (quadratic
-    // convergence from ~2^-23 to full precision)
+    const uint64_t okm = __ballot(v[j] > thr);                       // bit j: pivot j accepted
+    const uint64_t ngm = __ballot(v[j] < -thr || v[j] != v[j]);      // bit j: negative or NaN
+    const bool ok = (okm >> j) & 1;
+    okbits |= okm & (1ull << j);
+    negbits |= ngm & (1ull << j);
+    // 1/sqrt(d): hardware estimate (about 2^-23) refined by NEWTON Newton
+    // steps, each squaring the relative error
     const double hd = 0.5 * d;
     double y = __builtin_amdgcn_rsq(d);
-    y = y * fma(-hd * y, y, 1.5);
-    y = y * fma(-hd * y, y, 1.5);
-    const double iv = d > tj ? y : 0.0;      // false for NaN, padding (+inf) and dropped pivots
+#pragma unroll
+    for (int it = 0; it < NEWTON; ++it) y = y * fma(-hd * y, y, 1.5);
+    const double iv = ok ? y : 0.0;      // zero for padding and dropped pivots
     // m = v[j] / l_jj on every lane: l_ij below the diagonal, l_jj = d / sqrt(d)
     // on it (v[j] of lane j is d), X[j][c] on the column lanes; rows above j
     // get values that are never read (their L entries are written as zero)
@@ -413,25 +414,23 @@ __device__ __attribute__((always_inline)) inline void factor_block_wave(const do
     v[j] = m;
     double* col = scratch + j * NB;
     if (fac) col[lane] = m;
-    wave_lds_sync();   // also keeps later columns' loads out of this step (register pressure)
+    // the store completes (and so do the previous column's loads, issued
+    // before this pivot); it also keeps the scheduler from overlapping
+    // steps, which would raise register pressure
+    wave_lds_sync();
     if (j + 1 < NB) {
       const double ln = lane_bcast(m, j + 1);       // l_{j+1, j}
       v[j + 1] = fma(-m, ln, v[j + 1]);
     }
-    // late updates of column j - 1 (k >= j + 1), then the loads for column j
 #pragma unroll
     for (int k = j + 1; k < NB; ++k) v[k] = fma(-mprev, cprev[k], v[k]);
 #pragma unroll
     for (int k = j + 2; k < NB; ++k) cprev[k] = col[k];
     mprev = m;
   }
-  // breakdown flags from the recorded pivots (row lane j checks column j)
-  wave_lds_sync();
   uint32_t bad = 0;
-  if (fac && live_col) {
-    const double d = spiv[row];
-    if (!(d > thr)) bad = (d < -thr || d != d) ? (LRAMM_FLAG_BREAKDOWN | LRAMM_FLAG_SQRTNEG) : LRAMM_FLAG_BREAKDOWN;
-  }
+  if (fac && live_col && !((okbits >> row) & 1))
+    bad = ((negbits >> row) & 1) ? (LRAMM_FLAG_BREAKDOWN | LRAMM_FLAG_SQRTNEG) : LRAMM_FLAG_BREAKDOWN;
   if (fac) {
 #pragma unroll
     for (int k = 0; k < NB; ++k) Lout[(int64_t)row * ldl + k] = k <= row ? v[k] : 0.0;
@@ -614,7 +613,7 @@ __global__ __launch_bounds__(256) void chol_first2_kernel(int lw, int l_true, co
     tile_load(s11, G + (int64_t)NB * lw + NB, lw);
   }
   __syncthreads();
-  if (wave == 0) factor_block_wave(&s00[0][0], scratch, diag0, 0, l_true, tol, flags, L, lw, Dinv);
+  if (wave == 0) factor_block_wave<1>(&s00[0][0], scratch, diag0, 0, l_true, tol, flags, L, lw, Dinv);
   __syncthreads();
   if (T == 1) return;
   tile_load(sD, Dinv, NB);
@@ -625,8 +624,8 @@ __global__ __launch_bounds__(256) void chol_first2_kernel(int lw, int l_true, co
   sub_put(s11, sub_get(s11) - sub_xyt(s10, s10));
   __syncthreads();
   if (wave == 0)
-    factor_block_wave(&s11[0][0], scratch, diag0, NB, l_true, tol, flags, L + (int64_t)NB * lw + NB, lw,
-                      Dinv + NB * NB);
+    factor_block_wave<1>(&s11[0][0], scratch, diag0, NB, l_true, tol, flags, L + (int64_t)NB * lw + NB, lw,
+                         Dinv + NB * NB);
 }
 
 // Launch p (p even, p + 2 < T).  Blocks 0 .. nt-1: trailing tiles (i, j),
@@ -725,8 +724,8 @@ __global__ __launch_bounds__(256) void chol_panel2_kernel(int lw, int l_true, in
   __syncthreads();
   double* Di = Dinv + (int64_t)i * NB * NB;
   if (wave == 0)
-    factor_block_wave(&sU[0][0], scratch, diag0, i * NB, l_true, tol, flags, L + (int64_t)i * NB * lw + i * NB,
-                      lw, Di);
+    factor_block_wave<1>(&sU[0][0], scratch, diag0, i * NB, l_true, tol, flags, L + (int64_t)i * NB * lw + i * NB,
+                         lw, Di);
   if (!two) return;
   __syncthreads();
   tile_load(sD0, Di, NB);
@@ -737,8 +736,8 @@ __global__ __launch_bounds__(256) void chol_panel2_kernel(int lw, int l_true, in
   sub_put(sW, sub_get(sW) - sub_xyt(sV, sV));
   __syncthreads();
   if (wave == 0)
-    factor_block_wave(&sW[0][0], scratch, diag0, (i + 1) * NB, l_true, tol, flags,
-                      L + (int64_t)(i + 1) * NB * lw + (i + 1) * NB, lw, Dinv + (int64_t)(i + 1) * NB * NB);
+    factor_block_wave<1>(&sW[0][0], scratch, diag0, (i + 1) * NB, l_true, tol, flags,
+                         L + (int64_t)(i + 1) * NB * lw + (i + 1) * NB, lw, Dinv + (int64_t)(i + 1) * NB * NB);
 }
 
 // One wavefront: acc[si][sj] (16 x 16 sub-tiles) += X[32 x 32] Y[32 x 32]^T,
