@@ -329,6 +329,7 @@ CASES = [
     (300, 257, 190, 20, 5, 1, 12.0, ("int8",) * 4),      # ragged
     (640, 384, 512, 100, 12, 1, 40.0, ("int8", "int8", "int4", "int4")),
     (512, 512, 512, 64, 10, 1, 32.0, ("int4",) * 4),
+    (2048, 4096, 512, 64, 16, 1, 64.0, ("int8",) * 4),   # long K: split-K products
 ]
 
 
