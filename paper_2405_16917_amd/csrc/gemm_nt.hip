@@ -109,6 +109,10 @@ struct TileLoader {
   static constexpr int kPerThread = (kVecs + 255) / 256;
   uint4 r[kPerThread];
 
+  // MASK: the stage may reach past the padded K (only the last one can);
+  // full stages load without a per-vector test, so their loads issue
+  // back to back instead of each behind its own branch.
+  template <bool MASK>
   __device__ __forceinline__ void load(const uint8_t* base, int64_t ld, int row0, int rows_total, int st, int kw,
                                        int tid) {
 #pragma unroll
@@ -120,7 +124,7 @@ struct TileLoader {
         const int wofs = st * kStage + c * kWPerVec;          // widened byte offset of this vector
         int gr = row0 + row;
         gr = gr < rows_total ? gr : rows_total - 1;           // clamp: results of such rows are discarded
-        if (wofs < kw) {
+        if (!MASK || wofs < kw) {
           const int64_t gofs = KIND == KIND_I4 ? wofs / 2 : wofs;
           r[i] = *reinterpret_cast<const uint4*>(base + (int64_t)gr * ld + gofs);
         } else {
@@ -306,9 +310,15 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
 
   TileLoader<BM, KIND> la;
   TileLoader<BN, KIND> lb;
+  const int full = a.kw / kStage;          // stages that lie wholly inside the padded K
   if (st0 < st1) {
-    la.load(a.L, a.ldl, row0, a.M, st0, a.kw, tid);
-    lb.load(a.R, a.ldr, col0, a.N, st0, a.kw, tid);
+    if (st0 < full) {
+      la.template load<false>(a.L, a.ldl, row0, a.M, st0, a.kw, tid);
+      lb.template load<false>(a.R, a.ldr, col0, a.N, st0, a.kw, tid);
+    } else {
+      la.template load<true>(a.L, a.ldl, row0, a.M, st0, a.kw, tid);
+      lb.template load<true>(a.R, a.ldr, col0, a.N, st0, a.kw, tid);
+    }
     la.store(sA, tid);
     lb.store(sB, tid);
   }
@@ -322,9 +332,12 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
   for (int st = st0; st < st1; ++st) {
     const int buf = (st - st0) & 1;
     const bool more = st + 1 < st1;
-    if (more) {
-      la.load(a.L, a.ldl, row0, a.M, st + 1, a.kw, tid);
-      lb.load(a.R, a.ldr, col0, a.N, st + 1, a.kw, tid);
+    if (st + 1 < full && more) {
+      la.template load<false>(a.L, a.ldl, row0, a.M, st + 1, a.kw, tid);
+      lb.template load<false>(a.R, a.ldr, col0, a.N, st + 1, a.kw, tid);
+    } else if (more) {
+      la.template load<true>(a.L, a.ldl, row0, a.M, st + 1, a.kw, tid);
+      lb.template load<true>(a.R, a.ldr, col0, a.N, st + 1, a.kw, tid);
     }
     const uint8_t* A = sA + buf * BM * kLdsPitch;
     const uint8_t* B = sB + buf * BN * kLdsPitch;

@@ -70,22 +70,28 @@ __device__ __forceinline__ void store4(uint8_t* row, int64_t c0, const float v[4
   }
 }
 
+// 4 consecutive elements (4-element aligned) as FP32, no bounds test.
+template <typename T>
+__device__ __forceinline__ void load4_full(const T* p, float v[4]) {
+  if constexpr (sizeof(T) == 4) {
+    float4 f = *reinterpret_cast<const float4*>(p);
+    v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+  } else if constexpr (sizeof(T) == 2) {
+    uint2 u = *reinterpret_cast<const uint2*>(p);
+    v[0] = __uint_as_float(u.x << 16);
+    v[1] = __uint_as_float(u.x & 0xffff0000u);
+    v[2] = __uint_as_float(u.y << 16);
+    v[3] = __uint_as_float(u.y & 0xffff0000u);
+  } else {
+    double4 d = *reinterpret_cast<const double4*>(p);
+    v[0] = (float)d.x; v[1] = (float)d.y; v[2] = (float)d.z; v[3] = (float)d.w;
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void load4(const T* row, int64_t c0, int64_t cols, bool vec, float v[4], bool live[4]) {
   if (vec && c0 + 3 < cols) {
-    if constexpr (sizeof(T) == 4) {
-      float4 f = *reinterpret_cast<const float4*>(row + c0);
-      v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
-    } else if constexpr (sizeof(T) == 2) {
-      uint2 u = *reinterpret_cast<const uint2*>(row + c0);
-      v[0] = __uint_as_float(u.x << 16);
-      v[1] = __uint_as_float(u.x & 0xffff0000u);
-      v[2] = __uint_as_float(u.y << 16);
-      v[3] = __uint_as_float(u.y & 0xffff0000u);
-    } else {
-      double4 d = *reinterpret_cast<const double4*>(row + c0);
-      v[0] = (float)d.x; v[1] = (float)d.y; v[2] = (float)d.z; v[3] = (float)d.w;
-    }
+    load4_full<T>(row + c0, v);
 #pragma unroll
     for (int j = 0; j < 4; ++j) live[j] = true;
   } else {
@@ -150,17 +156,48 @@ __global__ __launch_bounds__(256) void quant_rows_kernel(int64_t rows, int64_t c
 
 // --------------------------------------------------------- column kernels --
 
+// Column maxima of a band of rows: each lane owns 4 consecutive columns (a
+// wavefront spans 256), the 4 wavefronts take every 4th row; away from the
+// right edge the loads carry no test and 8 rows are in flight per wavefront.
+// The band's maxima meet in LDS and go out with one atomicMax per column.
+constexpr int kColmaxRows = 128;   // rows per column-max workgroup
+
 template <typename T>
 __global__ __launch_bounds__(256) void colmax_kernel(int64_t rows, int64_t cols, const T* __restrict__ X,
                                                      int64_t ldx, uint32_t* __restrict__ amax_bits,
-                                                     int64_t rows_per_block) {
-  int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (col >= cols) return;
-  int64_t r0 = (int64_t)blockIdx.y * rows_per_block;
-  int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
-  unsigned m = 0;
-  for (int64_t r = r0; r < r1; ++r) m = max(m, abs_bits(load_as_f32<T>(X + r * ldx + col)));
-  if (m) atomicMax(amax_bits + col, m);
+                                                     int64_t rows_per_block, int vec) {
+  __shared__ unsigned sm[4][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t cb = (int64_t)blockIdx.x * 256;
+  const int64_t c0 = cb + 4 * lane;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_block;
+  const int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
+  unsigned m[4] = {0u, 0u, 0u, 0u};
+  int64_t r = r0 + w;
+  if (vec && cb + 256 <= cols) {
+    for (; r + 28 < r1; r += 32) {
+      float v[8][4];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) load4_full<T>(X + (r + 4 * i) * ldx + c0, v[i]);
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) m[j] = max(m[j], abs_bits(v[i][j]));
+    }
+  }
+  for (; r < r1; r += 4) {
+    float v[4];
+    bool live[4];
+    load4<T>(X + r * ldx, c0, cols, vec != 0, v, live);   // zero past cols
+#pragma unroll
+    for (int j = 0; j < 4; ++j) m[j] = max(m[j], abs_bits(v[j]));
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) sm[w][4 * lane + j] = m[j];
+  __syncthreads();
+  const int t = threadIdx.x;
+  const unsigned mx = max(max(sm[0][t], sm[1][t]), max(sm[2][t], sm[3][t]));
+  if (cb + t < cols && mx) atomicMax(amax_bits + cb + t, mx);
 }
 
 // Quantise a 64 (K) x 64 (cols) tile and write it transposed.
@@ -168,50 +205,75 @@ template <typename T, int FMT>
 __global__ __launch_bounds__(256) void quant_cols_t_kernel(int64_t rows, int64_t cols, const T* __restrict__ X,
                                                            int64_t ldx, const uint32_t* __restrict__ amax_bits,
                                                            uint8_t* __restrict__ Xq, int64_t pitch,
-                                                           float* __restrict__ scales_out, uint32_t* flags) {
+                                                           float* __restrict__ scales_out, uint32_t* flags,
+                                                           int vec) {
   // codes of the tile, transposed: sT[col][k]; 2 bytes per code for bf16
   __shared__ uint16_t sT[64][66];
   const int t = threadIdx.x;
-  const int cl = t & 63;            // column within the tile
-  const int64_t col = (int64_t)blockIdx.x * 64 + cl;
+  const int64_t col0 = (int64_t)blockIdx.x * 64;
   const int64_t k0 = (int64_t)blockIdx.y * 64;
   const float qmax = FMT == LRAMM_INT8 ? 127.0f : (FMT == LRAMM_INT4 ? 7.0f : 448.0f);
-  float lam = 0.0f;
-  if (col < cols) {
+  // the first row of tiles also writes the scales (when the maxima live in a
+  // separate buffer) and reports non-finite columns
+  if (scales_out && blockIdx.y == 0 && t < 64 && col0 + t < cols) {
     if constexpr (FMT == LRAMM_BF16F) {
-      lam = 1.0f;
-      if (scales_out && blockIdx.y == 0 && t < 64) scales_out[col] = 1.0f;
+      scales_out[col0 + t] = 1.0f;
     } else {
-      const uint32_t mb = amax_bits[col];
-      const QParams qp = qparams(__uint_as_float(mb), qmax);
-      lam = qp.lam;
-      // the first row of tiles also writes the scales (when the maxima live
-      // in a separate buffer) and reports non-finite columns
-      if (scales_out && blockIdx.y == 0 && t < 64) {
-        scales_out[col] = qp.d;
-        if (mb >= 0x7f800000u && flags) atomicOr(flags, LRAMM_FLAG_NONFINITE);
-      }
+      const uint32_t mb = amax_bits[col0 + t];
+      scales_out[col0 + t] = qparams(__uint_as_float(mb), qmax).d;
+      if (mb >= 0x7f800000u && flags) atomicOr(flags, LRAMM_FLAG_NONFINITE);
     }
   }
-#pragma unroll 4
-  for (int i = 0; i < 16; ++i) {
-    int kr = (t >> 6) + 4 * i;       // row within the tile
-    int64_t r = k0 + kr;
-    uint16_t code = 0;
-    if (col < cols && r < rows && lam != 0.0f) {
-      float v = load_as_f32<T>(X + r * ldx + col);
-      if constexpr (FMT == LRAMM_INT8) {
-        code = (uint16_t)(qcode(v, lam, qmax) & 0xff);
-      } else if constexpr (FMT == LRAMM_INT4) {
-        code = (uint16_t)(qcode(v, lam, qmax) & 0xf);
-      } else if constexpr (FMT == LRAMM_FP8) {
-        code = (uint16_t)e4m3_bits(__fmul_rn(v, lam));
+  // reads: lane owns 4 consecutive columns (16 lanes span the tile's 64),
+  // rows sub, sub + 16, sub + 32, sub + 48
+  const int cg = t & 15, sub = t >> 4;
+  const int64_t c4 = col0 + 4 * cg;
+  float lam[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    lam[j] = 0.0f;
+    if (c4 + j < cols) {
+      if constexpr (FMT == LRAMM_BF16F) lam[j] = 1.0f;
+      else lam[j] = qparams(__uint_as_float(amax_bits[c4 + j]), qmax).lam;
+    }
+  }
+  float v[4][4];
+  if (vec && k0 + 64 <= rows && col0 + 64 <= cols) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) load4_full<T>(X + (k0 + sub + 16 * i) * ldx + c4, v[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = k0 + sub + 16 * i;
+      bool live[4];
+      if (r < rows) {
+        load4<T>(X + r * ldx, c4, cols, vec != 0, v[i], live);
       } else {
-        code = bf16_bits(v);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[i][j] = 0.0f;
       }
     }
-    sT[cl][kr] = code;
   }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      // rows past the end and columns with a zero lambda give code 0
+      const float x = v[i][j];
+      uint16_t code = 0;
+      if (lam[j] != 0.0f) {
+        if constexpr (FMT == LRAMM_INT8) {
+          code = (uint16_t)(qcode(x, lam[j], qmax) & 0xff);
+        } else if constexpr (FMT == LRAMM_INT4) {
+          code = (uint16_t)(qcode(x, lam[j], qmax) & 0xf);
+        } else if constexpr (FMT == LRAMM_FP8) {
+          code = (uint16_t)e4m3_bits(__fmul_rn(x, lam[j]));
+        } else {
+          code = bf16_bits(x);
+        }
+      }
+      sT[4 * cg + j][sub + 16 * i] = code;
+    }
   __syncthreads();
   // write: output row = column of X, 64 elements of K starting at k0
   const int orow = t >> 2;           // 0..63
@@ -345,33 +407,34 @@ static lramm_status quantize_typed(int64_t rows, int64_t cols, const T* X, int64
   }
   // column vectors, transposed output: cols x pitch
   if (cols == 0) return LRAMM_OK;
+  const int cvec = ((uintptr_t)X % (4 * sizeof(T)) == 0) && (ldx % 4 == 0) ? 1 : 0;
   if (amax_ws) {
     // maxima in a caller-zeroed buffer (or already there): no fill, and the
     // quantise pass writes the scales itself
     if (FMT != LRAMM_BF16F && rows > 0 && !amax_ready) {
-      dim3 g1((unsigned)ceil_div(cols, 256), (unsigned)ceil_div(rows, (int64_t)64));
-      hipLaunchKernelGGL((colmax_kernel<T>), g1, dim3(256), 0, s, rows, cols, X, ldx, amax_ws, (int64_t)64);
+      dim3 g1((unsigned)ceil_div(cols, 256), (unsigned)ceil_div(rows, (int64_t)kColmaxRows));
+      hipLaunchKernelGGL((colmax_kernel<T>), g1, dim3(256), 0, s, rows, cols, X, ldx, amax_ws, (int64_t)kColmaxRows,
+                         cvec);
       LRAMM_HIP(hipGetLastError());
     }
     int64_t pe = pitch_elems(pitch, FMT);
     dim3 g2((unsigned)ceil_div(cols, 64), (unsigned)(pe / 64));
     hipLaunchKernelGGL((quant_cols_t_kernel<T, FMT>), g2, dim3(256), 0, s, rows, cols, X, ldx, amax_ws, Xq, pitch,
-                       scales, flags);
+                       scales, flags, cvec);
     LRAMM_HIP(hipGetLastError());
     return LRAMM_OK;
   }
   uint32_t* amax = reinterpret_cast<uint32_t*>(scales);
   LRAMM_TRY(fill_u32(amax, 0u, cols, s));
   if (FMT != LRAMM_BF16F && rows > 0) {
-    int64_t rpb = 64;
-    dim3 g1((unsigned)ceil_div(cols, 256), (unsigned)ceil_div(rows, rpb));
-    hipLaunchKernelGGL((colmax_kernel<T>), g1, dim3(256), 0, s, rows, cols, X, ldx, amax, rpb);
+    dim3 g1((unsigned)ceil_div(cols, 256), (unsigned)ceil_div(rows, (int64_t)kColmaxRows));
+    hipLaunchKernelGGL((colmax_kernel<T>), g1, dim3(256), 0, s, rows, cols, X, ldx, amax, (int64_t)kColmaxRows, cvec);
     LRAMM_HIP(hipGetLastError());
   }
   int64_t pe = pitch_elems(pitch, FMT);
   dim3 g2((unsigned)ceil_div(cols, 64), (unsigned)(pe / 64));
   hipLaunchKernelGGL((quant_cols_t_kernel<T, FMT>), g2, dim3(256), 0, s, rows, cols, X, ldx, amax, Xq, pitch,
-                     (float*)nullptr, (uint32_t*)nullptr);
+                     (float*)nullptr, (uint32_t*)nullptr, cvec);
   LRAMM_HIP(hipGetLastError());
   hipLaunchKernelGGL((col_scales_kernel<FMT>), dim3((unsigned)ceil_div(cols, 256)), dim3(256), 0, s, cols, scales,
                      flags);
