@@ -261,7 +261,8 @@ LRAMM_API int64_t lramm_pitch(int64_t K, int32_t fmt);
  *   acc_out: optional raw int32 accumulators (int8/int4 only), M x ld_acc.
  *   ws / ws_bytes: workspace for split-K partials (may be NULL / 0, then the
  *   library does not split K).  Returns LRAMM_E_OVERFLOW if K * qmax^2 could
- *   exceed the int32 accumulator. */
+ *   exceed the int32 accumulator, LRAMM_E_UNSUPPORTED if M * ldl or N * ldr
+ *   reaches 2^31 bytes (operands are addressed with 32-bit offsets). */
 LRAMM_API lramm_status lramm_gemm_nt(int64_t M, int64_t N, int64_t K, int32_t fmt,
                            const void* Lq, int64_t ldl, const float* dL,
                            const void* Rq, int64_t ldr, const float* dR,

@@ -66,6 +66,11 @@ struct GemmArgs {
 };
 
 constexpr int kStage = 128;                 // widened bytes of K per stage
+// stages of K in flight in registers: as deep as the register file allows
+// at two workgroups per CU (the LDS limit of the 128-row tiles)
+template <int BM, int BN, int KIND>
+constexpr int kPrefetchOf = BM * BN >= 128 * 128 ? (KIND == KIND_F8 ? 1 : 2) : (KIND == KIND_F8 ? 2 : 3);
+constexpr int kBufferWord3 = 0x00020000;    // buffer resource word 3 (raw byte buffer) on gfx9-family parts
 constexpr int kLdsPitch = kStage + 16;      // LDS row pitch (16-byte pad: conflict-free 16 B reads)
 
 template <int KIND>
@@ -101,35 +106,65 @@ __device__ __forceinline__ uint2 widen_int4(uint32_t w) {
 // Global -> registers for one operand tile of ROWS rows at stage st.
 //   int8 / bf16: a row holds 8 vectors of 16 B per stage;
 //   int4: 4 vectors of 16 B (packed), each widened to 32 B in LDS.
+// Loads are buffer loads: the operand base lives in a scalar resource, each
+// lane keeps one 32-bit byte offset per vector (its row and its place in the
+// stage, fixed for the kernel) and the stage offset is a scalar, so prefetching
+// several stages costs no extra address registers.  The lane's place in the
+// stage (vector c) is the same for all of its vectors, since 256 lanes cover
+// whole rows.
 template <int ROWS, int KIND>
 struct TileLoader {
   static constexpr int kVecPerRow = KIND == KIND_I4 ? 4 : 8;
   static constexpr int kWPerVec = KIND == KIND_I4 ? 32 : 16;   // widened bytes per global vector
   static constexpr int kVecs = ROWS * kVecPerRow;
   static constexpr int kPerThread = (kVecs + 255) / 256;
+  static constexpr int kStageBytes = KIND == KIND_I4 ? kStage / 2 : kStage;   // global bytes per stage
   uint4 r[kPerThread];
 
+  // Per-lane offsets: row part (clamped row: results of rows past the end
+  // are discarded) and the vector's byte offset inside a stage.
+  struct Offsets {
+    int row[kPerThread];
+    int vec;      // global bytes
+    int wvec;     // widened bytes
+  };
+  static __device__ __forceinline__ Offsets offsets(int64_t ld, int row0, int rows_total, int tid) {
+    Offsets o;
+    const int c = tid % kVecPerRow;
+    o.vec = c * 16;
+    o.wvec = c * kWPerVec;
+#pragma unroll
+    for (int i = 0; i < kPerThread; ++i) {
+      const int v = tid + 256 * i;
+      int gr = row0 + v / kVecPerRow;
+      gr = gr < rows_total ? gr : rows_total - 1;
+      o.row[i] = (int)((int64_t)gr * ld);
+    }
+    return o;
+  }
+
   // MASK: the stage may reach past the padded K (only the last one can);
-  // full stages load without a per-vector test, so their loads issue
-  // back to back instead of each behind its own branch.
+  // those vectors are loaded from the stage's start in the row (in bounds)
+  // and zeroed.  Both forms are straight-line code.
   template <bool MASK>
-  __device__ __forceinline__ void load(const uint8_t* base, int64_t ld, int row0, int rows_total, int st, int kw,
-                                       int tid) {
+  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, const Offsets& o, int st, int kw, int tid) {
+    const int so = st * kStageBytes;
+    uint32_t m = 0xffffffffu;
+    int vec = o.vec;
+    if constexpr (MASK) {
+      const bool in = st * kStage + o.wvec < kw;
+      m = in ? 0xffffffffu : 0u;
+      vec = in ? vec : 0;
+      __asm__("" : "+v"(m));   // opaque: the and-with-mask must not become a branch around the load
+    }
 #pragma unroll
     for (int i = 0; i < kPerThread; ++i) {
       const int v = tid + 256 * i;
       if (kVecs % 256 == 0 || v < kVecs) {
-        const int row = v / kVecPerRow;
-        const int c = v % kVecPerRow;
-        const int wofs = st * kStage + c * kWPerVec;          // widened byte offset of this vector
-        int gr = row0 + row;
-        gr = gr < rows_total ? gr : rows_total - 1;           // clamp: results of such rows are discarded
-        if (!MASK || wofs < kw) {
-          const int64_t gofs = KIND == KIND_I4 ? wofs / 2 : wofs;
-          r[i] = *reinterpret_cast<const uint4*>(base + (int64_t)gr * ld + gofs);
-        } else {
-          r[i] = make_uint4(0u, 0u, 0u, 0u);                  // past the padded K: zero
-        }
+        typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+        const v4u x = __builtin_amdgcn_raw_buffer_load_b128(rs, o.row[i] + vec, so, 0);
+        if constexpr (MASK) r[i] = make_uint4(x[0] & m, x[1] & m, x[2] & m, x[3] & m);
+        else r[i] = make_uint4(x[0], x[1], x[2], x[3]);
       }
     }
   }
@@ -273,6 +308,7 @@ __device__ __forceinline__ void store4(const GemmArgs& a, int split, int gm, int
 template <int BM, int BN, int KIND, bool SPLIT>
 __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
   constexpr int RM = BM / 64;   // 32x32 MFMA tiles per wave along M
+  constexpr int kPrefetch = kPrefetchOf<BM, BN, KIND>;
   constexpr int RN = BN / 64;
   constexpr int kABytes = 2 * BM * kLdsPitch, kBBytes = 2 * BN * kLdsPitch;
   constexpr int kCPitch = BN + 4;                       // floats per staged output row
@@ -308,19 +344,33 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
 
-  TileLoader<BM, KIND> la;
-  TileLoader<BN, KIND> lb;
+  // Register prefetch kPrefetch stages deep: stage x sits in slot
+  // (x - st0) % kPrefetch from its load until it is written to LDS (double
+  // buffer) one iteration before its MFMAs, so every global load has about
+  // kPrefetch stages of MFMA work to arrive.
+  TileLoader<BM, KIND> la[kPrefetch];
+  TileLoader<BN, KIND> lb[kPrefetch];
+  // operand resources: base and byte extent (rows x pitch, below 2^31)
+  const __amdgpu_buffer_rsrc_t rsL =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.L, (short)0, (int)((int64_t)a.M * a.ldl), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t rsR =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.R, (short)0, (int)((int64_t)a.N * a.ldr), kBufferWord3);
+  const typename TileLoader<BM, KIND>::Offsets oa = TileLoader<BM, KIND>::offsets(a.ldl, row0, a.M, tid);
+  const typename TileLoader<BN, KIND>::Offsets ob = TileLoader<BN, KIND>::offsets(a.ldr, col0, a.N, tid);
   const int full = a.kw / kStage;          // stages that lie wholly inside the padded K
+  // prologue: the first kPrefetch stages (a short slice repeats its last
+  // stage; those copies are never stored)
   if (st0 < st1) {
-    if (st0 < full) {
-      la.template load<false>(a.L, a.ldl, row0, a.M, st0, a.kw, tid);
-      lb.template load<false>(a.R, a.ldr, col0, a.N, st0, a.kw, tid);
-    } else {
-      la.template load<true>(a.L, a.ldl, row0, a.M, st0, a.kw, tid);
-      lb.template load<true>(a.R, a.ldr, col0, a.N, st0, a.kw, tid);
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+      const int st = st0 + u < st1 ? st0 + u : st1 - 1;
+      la[u].template load<true>(rsL, oa, st, a.kw, tid);
+      lb[u].template load<true>(rsR, ob, st, a.kw, tid);
     }
-    la.store(sA, tid);
-    lb.store(sB, tid);
+  }
+  if (st0 < st1) {
+    la[0].store(sA, tid);
+    lb[0].store(sB, tid);
   }
   __syncthreads();
 
@@ -329,16 +379,17 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
   constexpr int CH = kChunk<KIND>;
   const int kofs = (lane >> 5) * (CH / 2);
 
-  for (int st = st0; st < st1; ++st) {
-    const int buf = (st - st0) & 1;
-    const bool more = st + 1 < st1;
-    if (st + 1 < full && more) {
-      la.template load<false>(a.L, a.ldl, row0, a.M, st + 1, a.kw, tid);
-      lb.template load<false>(a.R, a.ldr, col0, a.N, st + 1, a.kw, tid);
-    } else if (more) {
-      la.template load<true>(a.L, a.ldl, row0, a.M, st + 1, a.kw, tid);
-      lb.template load<true>(a.R, a.ldr, col0, a.N, st + 1, a.kw, tid);
+  // one stage: refill slot u (if asked), MFMAs on LDS buffer (st - st0) & 1,
+  // then the next stage's slot into the other buffer
+  // refill 0: none; 2: stage st + kPrefetch, which may reach past the padded
+  // K (clamped to the slice: a repeat of its last stage is never stored)
+  auto stage = [&](const int u, const int st, const int refill) {
+    const int nx = st + kPrefetch < st1 ? st + kPrefetch : st1 - 1;
+    if (refill == 2) {
+      la[u].template load<true>(rsL, oa, nx, a.kw, tid);
+      lb[u].template load<true>(rsR, ob, nx, a.kw, tid);
     }
+    const int buf = (st - st0) & 1;
     const uint8_t* A = sA + buf * BM * kLdsPitch;
     const uint8_t* B = sB + buf * BN * kLdsPitch;
 #pragma unroll
@@ -353,12 +404,26 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
 #pragma unroll
         for (int j = 0; j < RN; ++j) mfma_32x32<KIND>(acc[i][j], av[i], bv[j]);
     }
-    if (more) {
-      la.store(sA + (buf ^ 1) * BM * kLdsPitch, tid);
-      lb.store(sB + (buf ^ 1) * BN * kLdsPitch, tid);
+    if (st + 1 < st1) {
+      const int un = (u + 1) % kPrefetch;
+      la[un].store(sA + (buf ^ 1) * BM * kLdsPitch, tid);
+      lb[un].store(sB + (buf ^ 1) * BN * kLdsPitch, tid);
     }
     __syncthreads();
+  };
+
+  // whole groups of kPrefetch stages: every refill is issued (clamped to
+  // the slice, masked past the padded K), so the loop body is straight-line
+  // code and each LDS store waits only for its own stage's loads; then the
+  // last stages, with nothing left to load
+  int sb = st0;
+  for (; sb + kPrefetch <= st1; sb += kPrefetch) {
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) stage(u, sb + u, 2);
   }
+#pragma unroll
+  for (int u = 0; u < kPrefetch; ++u)
+    if (sb + u < st1) stage(u, sb + u, 0);
 
   // ---- epilogue: stage raw accumulators in LDS, then coalesced 4-wide stores
   int32_t* sC = reinterpret_cast<int32_t*>(smem);
@@ -399,6 +464,34 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs a, int nspl
   const int gm = (int)(q / a.N), gn = (int)(q % a.N);
   int32_t v[4];
   const bool vec = (a.N & 3) == 0;
+  if (vec) {
+    // whole quad inside a row: 16-byte loads, several slices in flight
+    const int4* p4 = reinterpret_cast<const int4*>(a.part + q);
+    const int64_t stride4 = total / 4;
+    if (kIntAcc<KIND>) {
+      int4 acc = make_int4(0, 0, 0, 0);
+#pragma unroll 4
+      for (int k = 0; k < nsplit; ++k) {
+        const int4 x = p4[(int64_t)k * stride4];
+        acc.x += x.x; acc.y += x.y; acc.z += x.z; acc.w += x.w;
+      }
+      v[0] = acc.x; v[1] = acc.y; v[2] = acc.z; v[3] = acc.w;
+    } else {
+      float f[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+      for (int k = 0; k < nsplit; ++k) {
+        const int4 x = p4[(int64_t)k * stride4];
+        f[0] = __fadd_rn(f[0], __int_as_float(x.x));
+        f[1] = __fadd_rn(f[1], __int_as_float(x.y));
+        f[2] = __fadd_rn(f[2], __int_as_float(x.z));
+        f[3] = __fadd_rn(f[3], __int_as_float(x.w));
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = __float_as_int(f[j]);
+    }
+    store4<KIND, false>(a, 0, gm, gn, v);
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     if (kIntAcc<KIND>) {
@@ -413,17 +506,13 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs a, int nspl
       v[j] = __float_as_int(s);
     }
   }
-  if (vec) {
-    store4<KIND, false>(a, 0, gm, gn, v);
-  } else {
-    // row-crossing quad: store element by element
-    for (int j = 0; j < 4 && q + j < total; ++j) {
-      const int m2 = (int)((q + j) / a.N), n2 = (int)((q + j) % a.N);
-      int32_t one[4] = {v[j], 0, 0, 0};
-      GemmArgs b = a;
-      b.N = n2 + 1;   // limit the store to one column
-      store4<KIND, false>(b, 0, m2, n2, one);
-    }
+  // a quad that may cross a row end: store element by element
+  for (int j = 0; j < 4 && q + j < total; ++j) {
+    const int m2 = (int)((q + j) / a.N), n2 = (int)((q + j) % a.N);
+    int32_t one[4] = {v[j], 0, 0, 0};
+    GemmArgs b = a;
+    b.N = n2 + 1;   // limit the store to one column
+    store4<KIND, false>(b, 0, m2, n2, one);
   }
 }
 
@@ -450,6 +539,8 @@ static Plan plan_gemm(int64_t M, int64_t N, int64_t K, int fmt, bool allow_split
   p.nst = (int)ceil_div(p.kw, kStage);
   p.bm = M >= 128 ? 128 : 64;
   p.bn = N >= 128 ? 128 : 64;
+  // prefer the 64-high M tile when it wastes noticeably less of a short M
+  if (p.bm == 128 && (round_up(M, 128) - M) * 4 > M && (round_up(M, 64) - M) < (round_up(M, 128) - M)) p.bm = 64;
   // prefer the 64-wide N tile when it wastes noticeably less of a skinny N
   if (p.bn == 128 && (round_up(N, 128) - N) * 4 > N && (round_up(N, 64) - N) < (round_up(N, 128) - N)) p.bn = 64;
   p.tiles_m = (int)ceil_div(M, p.bm);
@@ -458,9 +549,10 @@ static Plan plan_gemm(int64_t M, int64_t N, int64_t K, int fmt, bool allow_split
   p.split = 1;
   if (allow_split && tiles < 384) {
     // too few tiles to keep 256 CUs busy (two workgroups each) and a long K:
-    // split K, each slice keeping at least 4 stages; the partials are summed
-    // in a second pass
-    while (tiles * p.split < 512 && p.nst / (p.split * 2) >= 4 && p.split < 16) p.split *= 2;
+    // split K as far as one round of 512 workgroups allows, each slice
+    // keeping at least 4 stages; the partials are summed in a second pass
+    for (int sp = 2; sp <= 16; ++sp)
+      if (tiles * sp <= 512 && p.nst / sp >= 4) p.split = sp;
   }
   p.st_per_split = (int)ceil_div(p.nst, p.split);
   p.split = (int)ceil_div(p.nst, p.st_per_split);
@@ -496,6 +588,8 @@ lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void
   int kind = kind_of(fmt);
   if (kind < 0) return LRAMM_E_UNSUPPORTED;
   if (M == 0 || N == 0) return LRAMM_OK;
+  // the tile loads address each operand with 32-bit byte offsets
+  if (M * ldl >= (int64_t)1 << 31 || N * ldr >= (int64_t)1 << 31) return LRAMM_E_UNSUPPORTED;
   size_t need = gemm_nt_workspace(M, N, K, fmt);
   bool can_split = ws != nullptr && need > 0 && ws_bytes >= need;
   Plan p = plan_gemm(M, N, K, fmt, can_split);

@@ -57,6 +57,11 @@ using namespace lramm;
 
 namespace {
 
+// Events that only order streams of this device: no timing, and a
+// device-scope release instead of the default system-scope fence (nothing
+// on the host reads what they guard).
+constexpr unsigned kOrderEvent = hipEventDisableTiming | hipEventReleaseToDevice;
+
 bool valid_fmt(int f) { return f == LRAMM_INT8 || f == LRAMM_INT4 || f == LRAMM_FP8 || f == LRAMM_BF16F; }
 bool valid_io(int t) { return t == LRAMM_F32 || t == LRAMM_BF16; }
 
@@ -262,8 +267,8 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   // side stream (default priority) and fork/join events; without them the
   // forward runs everything on the caller's stream
   if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess) p->side = nullptr;
-  if (p->side && (hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
-                  hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess)) {
+  if (p->side && (hipEventCreateWithFlags(&p->ev_fork, kOrderEvent) != hipSuccess ||
+                  hipEventCreateWithFlags(&p->ev_join, kOrderEvent) != hipSuccess)) {
     (void)hipStreamDestroy(p->side);
     p->side = nullptr;
   }
@@ -603,13 +608,13 @@ lramm_status lramm_batch_create(int32_t count, lramm_plan* const* plans, int32_t
     b->stream_of[i] = t;
     load[t] += work[i];
   }
-  bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+  bool ok = hipEventCreateWithFlags(&b->fork, kOrderEvent) == hipSuccess;
   for (int t = 0; ok && t < ns; ++t) {
     hipStream_t st;
     hipEvent_t ev;
     ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;   // default priority
     if (ok) b->streams.push_back(st);
-    ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&ev, kOrderEvent) == hipSuccess;
     if (ok) b->done.push_back(ev);
   }
   if (!ok) {
