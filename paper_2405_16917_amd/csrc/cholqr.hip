@@ -171,26 +171,44 @@ __global__ __launch_bounds__(256) void gram_kernel(int64_t rows, int lw, int nco
   }
 }
 
+// Second-pass gate bits (one word per orthonormalisation).
+constexpr uint32_t kGateFull = 1u;    // |E| too large for the expansion: full Cholesky of G2
+constexpr uint32_t kGatePass2 = 2u;   // the first pass is not yet orthonormal to the second pass's accuracy
+
 // G (lower tiles) = sum over chunks in order; diag0 = diag(G).
-//   mode 0 (first pass): clears the second-pass gate of this orthonormalisation;
-//   mode 1 (second pass): raises gate_bit when some |G_ij - delta_ij|, i, j < l_true,
-//   exceeds tau (or is NaN).
+//   mode 0 (first pass): clears the gate word and the first-pass column
+//   maxima cm1 (lw words) of this orthonormalisation;
+//   mode 1 (second pass): with E = G - I over i, j < l_true, raises kGateFull
+//   when some |E_ij| exceeds tau (or is NaN) and kGatePass2 when some |E_ij|
+//   exceeds tau_skip (or is NaN); one atomic per wavefront at most.
 __global__ __launch_bounds__(256) void gram_reduce_kernel(int lw, int l_true, int nchunks,
                                                           const double* __restrict__ part, double* __restrict__ G,
-                                                          double* __restrict__ diag0, uint32_t* gate, int mode,
-                                                          uint32_t gate_bit, double tau) {
+                                                          double* __restrict__ diag0, uint32_t* gate,
+                                                          uint32_t* cm1, int mode, double tau, double tau_skip) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (mode == 0 && e == 0) *gate = 0u;
-  if (e >= (int64_t)lw * lw) return;
-  const int i = (int)(e / lw), j = (int)(e % lw);
-  if ((i / NB) < (j / NB)) return;   // upper tiles are never read
-  double s = 0.0;
-  for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * lw * lw + e];
-  G[e] = s;
-  if (i == j) diag0[i] = s;
-  if (mode == 1 && i < l_true && j <= i) {
-    const double v = s - (i == j ? 1.0 : 0.0);
-    if (!(fabs(v) <= tau)) atomicOr(gate, gate_bit);
+  if (mode == 0) {
+    if (e == 0) *gate = 0u;
+    if (cm1 && e < lw) cm1[e] = 0u;
+  }
+  uint32_t bits = 0;
+  if (e < (int64_t)lw * lw) {
+    const int i = (int)(e / lw), j = (int)(e % lw);
+    if ((i / NB) >= (j / NB)) {   // upper tiles are never read
+      double s = 0.0;
+      for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * lw * lw + e];
+      G[e] = s;
+      if (i == j) diag0[i] = s;
+      if (mode == 1 && i < l_true && j <= i) {
+        const double v = fabs(s - (i == j ? 1.0 : 0.0));
+        if (!(v <= tau)) bits |= kGateFull;
+        if (!(v <= tau_skip)) bits |= kGatePass2;
+      }
+    }
+  }
+  if (mode == 1) {
+    const uint64_t full = __ballot(bits & kGateFull), pass2 = __ballot(bits & kGatePass2);
+    const uint32_t wb = (full ? kGateFull : 0u) | (pass2 ? kGatePass2 : 0u);
+    if ((threadIdx.x & 63) == 0 && wb) atomicOr(gate, wb);
   }
 }
 
@@ -202,7 +220,9 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int lw, int l_true, in
 //   solve: X = Y, W = L^-1                 (Q1 = Y L^-T)
 //   apply: X = Q1, W = M^T, ADD            (Q = Q1 + Q1 M)
 // A workgroup owns 16 rows, staged once in LDS as FP64 (zero past ncols and
-// past the last row).  Its eight wavefronts (two per SIMD) share the
+// past the last row) before anything is written, so Q may be X itself (the
+// apply step runs in place).  With a gate word, the apply step does nothing
+// unless kGatePass2 is set.  Its eight wavefronts (two per SIMD) share the
 // 32-column blocks, block c costing c + 1 units of K, by longest-first
 // assignment to the least loaded wavefront (computed identically on every
 // lane).  A wavefront computes a 16 x 32 block (2 MFMA sub-tiles) per step of
@@ -214,12 +234,13 @@ constexpr int TS_ROWS = 16, TS_WAVES = 8;
 __host__ __device__ constexpr int ts_pitch(int lw) { return lw + 4; }
 
 template <typename T, bool ADD>
-__global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int lw, int ncols,
-                                                              const T* __restrict__ X, int64_t ldx,
-                                                              const double* __restrict__ W, double* __restrict__ Q,
+__global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int lw, int ncols, const T* X,
+                                                              int64_t ldx, const double* __restrict__ W, double* Q,
                                                               int64_t ldq, int zero_to, int vec,
-                                                              uint32_t* __restrict__ colmax) {
+                                                              uint32_t* __restrict__ colmax,
+                                                              const uint32_t* __restrict__ gate) {
   extern __shared__ double sA[];   // TS_ROWS x ts_pitch(lw)
+  if (ADD && gate && !(*gate & kGatePass2)) return;   // second pass skipped: Q already holds Q1
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int pitch = ts_pitch(lw);
@@ -880,11 +901,19 @@ __global__ __launch_bounds__(256) void series_kernel(int lw, int l_true, double*
                                                      double* __restrict__ Wout, double* __restrict__ L,
                                                      double* __restrict__ Dinv, const double* __restrict__ diag0,
                                                      double tol, uint32_t* flags, const uint32_t* gate,
-                                                     uint32_t gate_bit) {
+                                                     const uint32_t* __restrict__ cm1,
+                                                     uint32_t* __restrict__ colmax) {
   __shared__ double red[5][NB][NB + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  if (*gate & gate_bit) {
+  const uint32_t g = *gate;
+  if (!(g & kGatePass2)) {
+    // second pass skipped: Q is Q1, whose column maxima become the result's
+    if (blockIdx.x == 0 && cm1 && colmax)
+      for (int c = tid; c < l_true; c += 256) colmax[c] = cm1[c];
+    return;
+  }
+  if (g & kGateFull) {
     // fallback: W = chol(G2)^-1 - I, all in workgroup 0
     if (blockIdx.x != 0) return;
     series_fallback(lw, l_true, G2, Wout, L, Dinv, diag0, tol, flags, red);
@@ -956,14 +985,18 @@ __global__ __launch_bounds__(256) void series_kernel(int lw, int l_true, double*
 // ------------------------------------------------------------------ host --
 
 struct CholWs {
-  double *G, *L, *Dinv, *diag0, *part, *Q1, *W, *X;
+  double *G, *L, *Dinv, *diag0, *part, *W, *X;
   uint32_t* gate;
+  uint32_t* cm1;   // column maxima of fl32(|Q1|) (first pass)
   int nchunks;
   int64_t rows_per_chunk;
 };
 
-constexpr uint32_t kGateFull = 1u;      // second pass needs the full Cholesky
 constexpr double kSeriesTau = 1e-5;     // |E| bound of the second-pass expansion (error O(tau^3))
+// The second pass is skipped when every |E_ij| of the first pass is at most
+// 2^-44, about the orthonormality the second pass itself reaches (l u for
+// l of a few hundred): it would change Q by no more than its own rounding.
+constexpr double kSkipTau = 0x1p-44;
 
 // Row chunks of the Gram: about two workgroups per compute unit over the
 // lower 32 x 32 tiles, each wavefront at least 4 rows.
@@ -986,7 +1019,7 @@ size_t cholqr2_workspace(int64_t rows, int64_t l) {
   int64_t rpc;
   cholqr_layout(rows, l, &lw, &nc, &rpc);
   const size_t sq = (size_t)lw * lw;
-  const size_t n = 4 * sq + (size_t)lw * NB + lw + (size_t)nc * sq + (size_t)rows * lw + 32;
+  const size_t n = 4 * sq + (size_t)lw * NB + lw + (size_t)nc * sq + 32 + (size_t)lw / 2 + 1;
   return n * sizeof(double) + 256;
 }
 
@@ -1012,7 +1045,7 @@ static lramm_status gram(int64_t rows, int lw, int l_true, const T* X, int64_t l
   }
   LRAMM_HIP(hipGetLastError());
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)ceil_div((int64_t)lw * lw, 256)), dim3(256), 0, s, lw,
-                     l_true, w.nchunks, w.part, w.G, w.diag0, w.gate, mode, kGateFull, kSeriesTau);
+                     l_true, w.nchunks, w.part, w.G, w.diag0, w.gate, w.cm1, mode, kSeriesTau, kSkipTau);
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }
@@ -1045,7 +1078,7 @@ static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32
 template <typename T, bool ADD>
 static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t ldx, const double* W, double* Q,
                           int64_t ldq, int zero_to, hipStream_t s, const TimingHook* hook,
-                          uint32_t* colmax = nullptr) {
+                          uint32_t* colmax = nullptr, const uint32_t* gate = nullptr) {
   static bool attr_set = false;
   if (!attr_set) {   // up to 16 x 1028 doubles of LDS
     LRAMM_HIP(hipFuncSetAttribute((const void*)tsmul_kernel<T, ADD>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1057,7 +1090,7 @@ static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t l
   const int vec = ((uintptr_t)X % (4 * sizeof(T)) == 0 && ldx % 4 == 0) ? 1 : 0;
   const size_t shm = (size_t)TS_ROWS * ts_pitch(lw) * sizeof(double);
   hipLaunchKernelGGL((tsmul_kernel<T, ADD>), dim3((unsigned)ceil_div(rows, (int64_t)TS_ROWS)), dim3(TS_WAVES * 64),
-                     shm, s, rows, lw, ncols, X, ldx, W, Q, ldq, zero_to, vec, colmax);
+                     shm, s, rows, lw, ncols, X, ldx, W, Q, ldq, zero_to, vec, colmax, gate);
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }
@@ -1088,36 +1121,41 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   p += lw;
   w.part = p;
   p += (size_t)nc * sq;
-  w.Q1 = p;
-  p += (size_t)rows * lw;
   w.gate = reinterpret_cast<uint32_t*>(p);
+  p += 32;
+  w.cm1 = reinterpret_cast<uint32_t*>(p);
   w.nchunks = nc;
   w.rows_per_chunk = rpc;
   const int lt = (int)l;
-  // pass 1 on Y (columns at or past l are never read): Q1 = Y L1^-T
+  // pass 1 on Y (columns at or past l are never read): Q1 = Y L1^-T, written
+  // into Q (columns lw .. ldq-1 zero), with its column maxima when asked
+  const int zero_to = (int)ldq;
+  uint32_t* cm1 = colmax ? w.cm1 : nullptr;
   if (ytype == LRAMM_F32) {
     LRAMM_TRY(gram<float>(rows, lw, lt, (const float*)Y, ldy, w, 0, s, hook));
     LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook));
-    LRAMM_TRY((tsmul<float, false>(rows, lw, lt, (const float*)Y, ldy, w.X, w.Q1, lw, lw, s, hook)));
+    LRAMM_TRY((tsmul<float, false>(rows, lw, lt, (const float*)Y, ldy, w.X, Q, ldq, zero_to, s, hook, cm1)));
   } else if (ytype == LRAMM_F64) {
     LRAMM_TRY(gram<double>(rows, lw, lt, (const double*)Y, ldy, w, 0, s, hook));
     LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook));
-    LRAMM_TRY((tsmul<double, false>(rows, lw, lt, (const double*)Y, ldy, w.X, w.Q1, lw, lw, s, hook)));
+    LRAMM_TRY((tsmul<double, false>(rows, lw, lt, (const double*)Y, ldy, w.X, Q, ldq, zero_to, s, hook, cm1)));
   } else {
     return LRAMM_E_UNSUPPORTED;
   }
-  // pass 2 on Q1: expansion of the near-identity factor, or (gated) the full factor
-  const int zero_to = (int)ldq;
-  LRAMM_TRY(gram<double>(rows, lw, lt, w.Q1, lw, w, 1, s, hook));
+  // pass 2 on Q1 (in place in Q): expansion of the near-identity factor, or
+  // (gated) the full factor; skipped on the device when Q1 is already
+  // orthonormal to the second pass's own accuracy (then the expansion kernel
+  // hands the first pass's column maxima on)
+  LRAMM_TRY(gram<double>(rows, lw, lt, Q, ldq, w, 1, s, hook));
   const int Tn = lw / NB;
   const double tol = 64.0 * (double)lt * 0x1p-53;
   {
     HookScope hs(hook, SUB_CHOL_SERIES);
     hipLaunchKernelGGL(series_kernel, dim3(Tn * (Tn + 1) / 2), dim3(256), 0, s, lw, lt, w.G, w.W, w.L, w.Dinv,
-                       w.diag0, tol, flags, w.gate, kGateFull);
+                       w.diag0, tol, flags, w.gate, cm1, colmax);
   }
   LRAMM_HIP(hipGetLastError());
-  LRAMM_TRY((tsmul<double, true>(rows, lw, lw, w.Q1, lw, w.W, Q, ldq, zero_to, s, hook, colmax)));
+  LRAMM_TRY((tsmul<double, true>(rows, lw, lw, Q, ldq, w.W, Q, ldq, zero_to, s, hook, colmax, w.gate)));
   return LRAMM_OK;
 }
 

@@ -245,6 +245,34 @@ __device__ __forceinline__ float epi_value(float accf, float dl, float dr, int c
   return c;
 }
 
+// Write 4 finished outputs at columns gn..gn+3 of row gm (FP32 or BF16 C).
+__device__ __forceinline__ void store_out4(const GemmArgs& a, int gm, int gn, const float out[4]) {
+  const int64_t base = (int64_t)gm * a.ldc + gn;
+  const bool full = gn + 3 < a.N;
+  if (a.ctype == LRAMM_F32) {
+    float* C = reinterpret_cast<float*>(a.C) + base;
+    if (full && a.c_vec) {
+      *reinterpret_cast<float4*>(C) = make_float4(out[0], out[1], out[2], out[3]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (gn + q < a.N) C[q] = out[q];
+    }
+  } else {
+    uint16_t* C = reinterpret_cast<uint16_t*>(a.C) + base;
+    if (full && a.c_vec) {
+      uint2 w;
+      w.x = (uint32_t)bf16_bits(out[0]) | ((uint32_t)bf16_bits(out[1]) << 16);
+      w.y = (uint32_t)bf16_bits(out[2]) | ((uint32_t)bf16_bits(out[3]) << 16);
+      *reinterpret_cast<uint2*>(C) = w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (gn + q < a.N) C[q] = bf16_bits(out[q]);
+    }
+  }
+}
+
 // Store phase for 4 consecutive columns gn..gn+3 of row gm: raw accumulator
 // bits v (int32 for integer kinds, float bits otherwise).
 template <int KIND, bool SPLIT>
@@ -279,30 +307,30 @@ __device__ __forceinline__ void store4(const GemmArgs& a, int split, int gm, int
     const float cin = a.beta != 0.0f ? load_cin(a.C, (int64_t)gm * a.ldc + n, a.ctype) : 0.0f;
     out[q] = epi_value<SCALED>(accf, dl, dr, a.col_first, a.alpha, a.beta, cin);
   }
-  const int64_t base = (int64_t)gm * a.ldc + gn;
-  const bool full = gn + 3 < a.N;
-  if (a.ctype == LRAMM_F32) {
-    float* C = reinterpret_cast<float*>(a.C) + base;
-    if (full && a.c_vec) {
-      *reinterpret_cast<float4*>(C) = make_float4(out[0], out[1], out[2], out[3]);
-    } else {
+  store_out4(a, gm, gn, out);
+}
+
+// Final store of 4 consecutive columns gn..gn+3 of row gm with the
+// dequantisation factors already at hand (scaled kinds, no split).
+template <int KIND>
+__device__ __forceinline__ void store4_scaled(const GemmArgs& a, int gm, int gn, const int32_t v[4], float dl,
+                                              const float dr[4]) {
+  if constexpr (kIntAcc<KIND>) {
+    if (a.acc_out) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (gn + q < a.N) C[q] = out[q];
-    }
-  } else {
-    uint16_t* C = reinterpret_cast<uint16_t*>(a.C) + base;
-    if (full && a.c_vec) {
-      uint2 w;
-      w.x = (uint32_t)bf16_bits(out[0]) | ((uint32_t)bf16_bits(out[1]) << 16);
-      w.y = (uint32_t)bf16_bits(out[2]) | ((uint32_t)bf16_bits(out[3]) << 16);
-      *reinterpret_cast<uint2*>(C) = w;
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (gn + q < a.N) C[q] = bf16_bits(out[q]);
+        if (gn + q < a.N) a.acc_out[(int64_t)gm * a.ld_acc + gn + q] = v[q];
     }
   }
+  float out[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int n = gn + q < a.N ? gn + q : a.N - 1;
+    const float accf = kIntAcc<KIND> ? (float)v[q] : __int_as_float(v[q]);
+    const float cin = a.beta != 0.0f ? load_cin(a.C, (int64_t)gm * a.ldc + n, a.ctype) : 0.0f;
+    out[q] = epi_value<true>(accf, dl, dr[q], a.col_first, a.alpha, a.beta, cin);
+  }
+  store_out4(a, gm, gn, out);
 }
 
 template <int BM, int BN, int KIND, bool SPLIT>
@@ -443,14 +471,41 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
     }
   __syncthreads();
   constexpr int kQuads = BM * BN / 4;
+  constexpr int kIters = kQuads / 256;
+  static_assert(256 % (BN / 4) == 0, "a thread's quads share their columns");
+  // a thread's quads all sit in columns cq..cq+3 and in rows rq + (256 / (BN / 4)) it
+  const int cq = (tid % (BN / 4)) * 4, rq = tid / (BN / 4);
+  const int gn = col0 + cq;
+  if constexpr (SPLIT || !kScaled<KIND>) {
 #pragma unroll 4
-  for (int q = tid; q < kQuads; q += 256) {
-    const int rr = q / (BN / 4), cq = (q % (BN / 4)) * 4;
-    const int gm = row0 + rr, gn = col0 + cq;
-    if (gm < a.M && gn < a.N) {
-      const int4 w = *reinterpret_cast<const int4*>(sC + rr * kCPitch + cq);
-      const int32_t v[4] = {w.x, w.y, w.z, w.w};
-      store4<KIND, SPLIT>(a, split, gm, gn, v);
+    for (int it = 0; it < kIters; ++it) {
+      const int rr = rq + (256 / (BN / 4)) * it;
+      const int gm = row0 + rr;
+      if (gm < a.M && gn < a.N) {
+        const int4 w = *reinterpret_cast<const int4*>(sC + rr * kCPitch + cq);
+        const int32_t v[4] = {w.x, w.y, w.z, w.w};
+        store4<KIND, SPLIT>(a, split, gm, gn, v);
+      }
+    }
+  } else {
+    // dequantisation factors gathered once, all loads issued together
+    float dr[4], dl[kIters];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dr[q] = a.dR[gn + q < a.N ? gn + q : a.N - 1];
+#pragma unroll
+    for (int it = 0; it < kIters; ++it) {
+      const int gm = row0 + rq + (256 / (BN / 4)) * it;
+      dl[it] = a.dL[gm < a.M ? gm : a.M - 1];
+    }
+#pragma unroll 4
+    for (int it = 0; it < kIters; ++it) {
+      const int rr = rq + (256 / (BN / 4)) * it;
+      const int gm = row0 + rr;
+      if (gm < a.M && gn < a.N) {
+        const int4 w = *reinterpret_cast<const int4*>(sC + rr * kCPitch + cq);
+        const int32_t v[4] = {w.x, w.y, w.z, w.w};
+        store4_scaled<KIND>(a, gm, gn, v, dl[it], dr);
+      }
     }
   }
 }

@@ -249,7 +249,12 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   p->off_Tt = carve(&c, (size_t)n * lp * 4);
   p->off_Ttq = carve(&c, (size_t)n * p->pTtq);
   p->off_sTt = carve(&c, (size_t)n * 4);
-  p->chol_bytes = cholqr2_workspace(m > k ? m : k, l);
+  {
+    // the orthonormalisations run on m rows (sketches) and k rows (power
+    // iterations); the workspace is not monotone in the row count
+    const size_t wm = cholqr2_workspace(m, l), wk = cholqr2_workspace(k, l);
+    p->chol_bytes = wm > wk ? wm : wk;
+  }
   p->off_chol = carve(&c, p->chol_bytes);
   size_t sb = 0, t;
   t = gemm_nt_workspace(m, l, k, d.fmt_sketch); sb = t > sb ? t : sb;
