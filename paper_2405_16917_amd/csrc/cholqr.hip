@@ -195,7 +195,8 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int lw, int l_true, in
     const int i = (int)(e / lw), j = (int)(e % lw);
     if ((i / NB) >= (j / NB)) {   // upper tiles are never read
       double s = 0.0;
-      for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * lw * lw + e];
+#pragma unroll 8
+      for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * lw * lw + e];   // loads batched, sum in order
       G[e] = s;
       if (i == j) diag0[i] = s;
       if (mode == 1 && i < l_true && j <= i) {
