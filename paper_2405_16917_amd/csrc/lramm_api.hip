@@ -43,7 +43,7 @@ struct lramm_plan {
   int64_t pAr, pAc, pBc, pOm, pQZc, pQc, pQr, pBtq, pTtq;
   // side stream for the work independent of the orthonormalisation chain
   hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_omega = nullptr;
   // stage timing (measurement only)
   bool timing = false;
   std::vector<hipEvent_t> events;     // pool, reused
@@ -273,7 +273,8 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   // forward runs everything on the caller's stream
   if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess) p->side = nullptr;
   if (p->side && (hipEventCreateWithFlags(&p->ev_fork, kOrderEvent) != hipSuccess ||
-                  hipEventCreateWithFlags(&p->ev_join, kOrderEvent) != hipSuccess)) {
+                  hipEventCreateWithFlags(&p->ev_join, kOrderEvent) != hipSuccess ||
+                  hipEventCreateWithFlags(&p->ev_omega, kOrderEvent) != hipSuccess)) {
     (void)hipStreamDestroy(p->side);
     p->side = nullptr;
   }
@@ -286,6 +287,7 @@ void lramm_plan_destroy(lramm_plan* plan) {
   for (hipEvent_t e : plan->events) (void)hipEventDestroy(e);
   if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
   if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
+  if (plan->ev_omega) (void)hipEventDestroy(plan->ev_omega);
   if (plan->side) (void)hipStreamDestroy(plan->side);
   delete plan;
 }
@@ -375,25 +377,33 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
     StageTimer _t(P, strm, stage);        \
     LRAMM_TRY(expr);                      \
   } while (0)
-  // A's column codes and B's codes are first needed after the first
-  // orthonormalisation: produce them on the side stream meanwhile.
+  // The side stream first generates and quantises Omega (arithmetic bound)
+  // while the main stream quantises A's rows (bandwidth bound); then A's
+  // column codes and B's codes, first needed after the first
+  // orthonormalisation.
   hipStream_t s2 = P->side ? P->side : s;
   if (P->side) {
     LRAMM_HIP(hipEventRecord(P->ev_fork, s));
     LRAMM_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
   }
+  if (!omega) {
+    float* OmT = at<float>(W, P->off_OmT);
+    TIMED_ON(s2, ST_OMEGA, launch_omega(d.seed, k, l, l, OmT, k, s2));
+    TIMED_ON(s2, ST_QUANT_OMEGA,
+             launch_quantize(l, k, OmT, k, LRAMM_F32, d.fmt_sketch, 0, Om, P->pOm, sOm, flags, s2));
+    if (P->side) LRAMM_HIP(hipEventRecord(P->ev_omega, P->side));
+  }
+  // queued before the side stream's column work so that it starts at once
+  TIMED(ST_QUANT_A_ROWS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_sketch, 0, Ar, P->pAr, sAr, flags, s));
   TIMED_ON(s2, ST_QUANT_A_COLS,
            launch_quantize(m, k, A, lda, d.a_type, d.fmt_proj, 1, Ac, P->pAc, sAc, flags, s2, mxA));
   TIMED_ON(s2, ST_QUANT_B, launch_quantize(k, n, B, ldb, d.b_type, d.fmt_g1, 1, Bc, P->pBc, sBc, flags, s2, mxB));
   if (P->side) LRAMM_HIP(hipEventRecord(P->ev_join, P->side));
-  TIMED(ST_QUANT_A_ROWS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_sketch, 0, Ar, P->pAr, sAr, flags, s));
   if (omega) {
     TIMED(ST_QUANT_OMEGA, launch_quantize(k, l, omega, ldo, LRAMM_F32, d.fmt_sketch, 1, Om, P->pOm, sOm, flags, s,
                                           zero + P->mx_Om));
-  } else {
-    float* OmT = at<float>(W, P->off_OmT);
-    TIMED(ST_OMEGA, launch_omega(d.seed, k, l, l, OmT, k, s));
-    TIMED(ST_QUANT_OMEGA, launch_quantize(l, k, OmT, k, LRAMM_F32, d.fmt_sketch, 0, Om, P->pOm, sOm, flags, s));
+  } else if (P->side) {
+    LRAMM_HIP(hipStreamWaitEvent(s, P->ev_omega, 0));   // Omega's codes ready
   }
   // sketch and orthonormalisation
   TIMED(ST_SKETCH, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, P->pAr, sAr, Om, P->pOm, sOm, 1.0f, 0.0f, Y, lp,
