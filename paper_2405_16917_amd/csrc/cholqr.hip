@@ -233,14 +233,21 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int lw, int l_true, in
 constexpr int TS_ROWS = 16, TS_WAVES = 8;
 
 __host__ __device__ constexpr int ts_pitch(int lw) { return lw + 4; }
+// LDS bytes of the solve with its last block formed from the others:
+// staged rows, the other blocks' results, eight partial sums and the residual.
+__host__ __device__ constexpr size_t ts_solve_last_lds(int lw) {
+  return (size_t)(2 * TS_ROWS * ts_pitch(lw) + (TS_WAVES + 1) * TS_ROWS * NB) * sizeof(double);
+}
 
 template <typename T, bool ADD>
 __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int lw, int ncols, const T* X,
                                                               int64_t ldx, const double* __restrict__ W, double* Q,
                                                               int64_t ldq, int zero_to, int vec,
                                                               uint32_t* __restrict__ colmax,
-                                                              const uint32_t* __restrict__ gate) {
-  extern __shared__ double sA[];   // TS_ROWS x ts_pitch(lw)
+                                                              const uint32_t* __restrict__ gate,
+                                                              const double* __restrict__ Ltri,
+                                                              const double* __restrict__ Dlast) {
+  extern __shared__ double sA[];   // TS_ROWS x ts_pitch(lw) [+ the last-block solve's buffers]
   if (ADD && gate && !(*gate & kGatePass2)) return;   // second pass skipped: Q already holds Q1
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -265,10 +272,14 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
   }
   __syncthreads();
   const int Tb = lw / NB;
+  // last-block solve: block Tb - 1 of Q1 from the other blocks (below), so
+  // row block Tb - 1 of W = L^-1 is never needed
+  const bool solve_last = !ADD && Ltri != nullptr;
+  double* sQ = sA + TS_ROWS * pitch;              // the other blocks' results, same layout as sA
   int load[TS_WAVES];
 #pragma unroll
   for (int u = 0; u < TS_WAVES; ++u) load[u] = 0;
-  for (int c = Tb - 1; c >= 0; --c) {
+  for (int c = (solve_last ? Tb - 2 : Tb - 1); c >= 0; --c) {
     int w = 0;
 #pragma unroll
     for (int u = 1; u < TS_WAVES; ++u)
@@ -320,6 +331,13 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
       }
     }
     uint32_t m0 = 0, m1 = 0;   // column maxima of fl32(|Q|) over this wavefront's rows
+    if (solve_last) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        sQ[(4 * r + lk) * pitch + cb0 + li] = acc0[r];
+        sQ[(4 * r + lk) * pitch + cb0 + 16 + li] = acc1[r];
+      }
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int rr = 4 * r + lk;
@@ -345,6 +363,84 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
       if (lk == 0) {
         if (m0) atomicMax(colmax + cb0 + li, m0);
         if (m1) atomicMax(colmax + cb0 + 16 + li, m1);
+      }
+    }
+  }
+  if (solve_last) {
+    // Q1_c = (Y_c - sum_{t<c} Q1_t L_{c,t}^T) Dinv_c^T, c = Tb - 1: wavefront w
+    // takes the terms t = w, w + 8, ...; the partial sums meet in LDS in a
+    // fixed order, then one wavefront applies Dinv_c
+    double* red = sQ + TS_ROWS * pitch;             // TS_WAVES x 16 x 32
+    double* sR = red + TS_WAVES * TS_ROWS * NB;     // 16 x 32
+    __syncthreads();                                // every other block is in sQ
+    const int c = Tb - 1, cb0 = c * NB;
+    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+    for (int t = wave; t < c; t += TS_WAVES) {
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+        const int k0 = t * NB + 16 * st + 4 * lk;
+        double a[4], b0[4], b1[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = sQ[li * pitch + k0 + q];
+        load4d(Ltri + (int64_t)(cb0 + li) * lw + k0, b0);
+        load4d(Ltri + (int64_t)(cb0 + 16 + li) * lw + k0, b1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc0 = mfma_f64(a[q], b0[q], acc0);
+          acc1 = mfma_f64(a[q], b1[q], acc1);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      red[(wave * TS_ROWS + 4 * r + lk) * NB + li] = acc0[r];
+      red[(wave * TS_ROWS + 4 * r + lk) * NB + 16 + li] = acc1[r];
+    }
+    __syncthreads();
+    for (int e = tid; e < TS_ROWS * NB; e += TS_WAVES * 64) {
+      const int i = e / NB, j = e % NB;
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < TS_WAVES; ++w) v += red[(w * TS_ROWS + i) * NB + j];
+      sR[i * NB + j] = sA[i * pitch + cb0 + j] - v;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      v4d o0 = {0.0, 0.0, 0.0, 0.0}, o1 = o0;
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+        const int k0 = 16 * st + 4 * lk;
+        double a[4], b0[4], b1[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = sR[li * NB + k0 + q];
+        load4d(Dlast + (int64_t)li * NB + k0, b0);
+        load4d(Dlast + (int64_t)(16 + li) * NB + k0, b1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          o0 = mfma_f64(a[q], b0[q], o0);
+          o1 = mfma_f64(a[q], b1[q], o1);
+        }
+      }
+      uint32_t m0 = 0, m1 = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + 4 * r + lk;
+        if (row < rows) {
+          Q[row * ldq + cb0 + li] = o0[r];
+          Q[row * ldq + cb0 + 16 + li] = o1[r];
+          m0 = max(m0, __float_as_uint(fabsf((float)o0[r])));
+          m1 = max(m1, __float_as_uint(fabsf((float)o1[r])));
+        }
+      }
+      if (colmax) {
+        m0 = max(m0, (uint32_t)__shfl_xor((int)m0, 16));
+        m0 = max(m0, (uint32_t)__shfl_xor((int)m0, 32));
+        m1 = max(m1, (uint32_t)__shfl_xor((int)m1, 16));
+        m1 = max(m1, (uint32_t)__shfl_xor((int)m1, 32));
+        if (lk == 0) {
+          if (m0) atomicMax(colmax + cb0 + li, m0);
+          if (m1) atomicMax(colmax + cb0 + 16 + li, m1);
+        }
       }
     }
   }
@@ -1052,8 +1148,11 @@ static lramm_status gram(int64_t rows, int lw, int l_true, const T* X, int64_t l
 }
 
 // Cholesky of w.G into w.L, w.Dinv and X = L^-1 (one launch per two panels).
+// With skip_last_row (an odd block count whose last row block of X would
+// need a launch of its own) that row block is left out: the solve forms the
+// last block of Q1 from the others instead.
 static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32_t* flags, hipStream_t s,
-                                     const TimingHook* hook) {
+                                     const TimingHook* hook, bool skip_last_row) {
   const double tol = 64.0 * (double)l_true * 0x1p-53;
   const int Tn = lw / NB;
   {
@@ -1071,6 +1170,7 @@ static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32
                        w.diag0, tol, flags);
     LRAMM_HIP(hipGetLastError());
   }
+  if (skip_last_row && Tn - p == 1) return LRAMM_OK;
   hipLaunchKernelGGL(inverse_rows_kernel, dim3(Tn), dim3(256), 0, s, lw, p, Tn - p, w.L, w.Dinv, w.X);
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
@@ -1079,7 +1179,8 @@ static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32
 template <typename T, bool ADD>
 static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t ldx, const double* W, double* Q,
                           int64_t ldq, int zero_to, hipStream_t s, const TimingHook* hook,
-                          uint32_t* colmax = nullptr, const uint32_t* gate = nullptr) {
+                          uint32_t* colmax = nullptr, const uint32_t* gate = nullptr,
+                          const double* Ltri = nullptr, const double* Dlast = nullptr) {
   static bool attr_set = false;
   if (!attr_set) {   // up to 16 x 1028 doubles of LDS
     LRAMM_HIP(hipFuncSetAttribute((const void*)tsmul_kernel<T, ADD>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1089,9 +1190,10 @@ static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t l
   HookScope hs(hook, ADD ? SUB_CHOL_APPLY : SUB_CHOL_SOLVE);
   // 4-element vector loads need every row start aligned to 4 elements
   const int vec = ((uintptr_t)X % (4 * sizeof(T)) == 0 && ldx % 4 == 0) ? 1 : 0;
-  const size_t shm = (size_t)TS_ROWS * ts_pitch(lw) * sizeof(double);
+  size_t shm = (size_t)TS_ROWS * ts_pitch(lw) * sizeof(double);
+  if (Ltri) shm = ts_solve_last_lds(lw);
   hipLaunchKernelGGL((tsmul_kernel<T, ADD>), dim3((unsigned)ceil_div(rows, (int64_t)TS_ROWS)), dim3(TS_WAVES * 64),
-                     shm, s, rows, lw, ncols, X, ldx, W, Q, ldq, zero_to, vec, colmax, gate);
+                     shm, s, rows, lw, ncols, X, ldx, W, Q, ldq, zero_to, vec, colmax, gate, Ltri, Dlast);
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }
@@ -1132,14 +1234,21 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   // into Q (columns lw .. ldq-1 zero), with its column maxima when asked
   const int zero_to = (int)ldq;
   uint32_t* cm1 = colmax ? w.cm1 : nullptr;
+  // an odd block count leaves X's last row block to the solve, when its LDS fits
+  const int Tn1 = lw / NB;
+  const bool solve_last = (Tn1 % 2 == 1) && ts_solve_last_lds(lw) <= 160 * 1024;
+  const double* Ltri = solve_last ? w.L : nullptr;
+  const double* Dlast = solve_last ? w.Dinv + (size_t)(Tn1 - 1) * NB * NB : nullptr;
   if (ytype == LRAMM_F32) {
     LRAMM_TRY(gram<float>(rows, lw, lt, (const float*)Y, ldy, w, 0, s, hook));
-    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook));
-    LRAMM_TRY((tsmul<float, false>(rows, lw, lt, (const float*)Y, ldy, w.X, Q, ldq, zero_to, s, hook, cm1)));
+    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last));
+    LRAMM_TRY((tsmul<float, false>(rows, lw, lt, (const float*)Y, ldy, w.X, Q, ldq, zero_to, s, hook, cm1, nullptr,
+                                   Ltri, Dlast)));
   } else if (ytype == LRAMM_F64) {
     LRAMM_TRY(gram<double>(rows, lw, lt, (const double*)Y, ldy, w, 0, s, hook));
-    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook));
-    LRAMM_TRY((tsmul<double, false>(rows, lw, lt, (const double*)Y, ldy, w.X, Q, ldq, zero_to, s, hook, cm1)));
+    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last));
+    LRAMM_TRY((tsmul<double, false>(rows, lw, lt, (const double*)Y, ldy, w.X, Q, ldq, zero_to, s, hook, cm1,
+                                    nullptr, Ltri, Dlast)));
   } else {
     return LRAMM_E_UNSUPPORTED;
   }
