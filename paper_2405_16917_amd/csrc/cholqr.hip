@@ -1122,8 +1122,8 @@ size_t cholqr2_workspace(int64_t rows, int64_t l) {
 
 struct HookScope {
   const TimingHook* h;
-  HookScope(const TimingHook* hook, int stage) : h(hook) {
-    if (h) h->begin(h->ctx, stage);
+  HookScope(const TimingHook* hook, int stage, int launches = 1) : h(hook) {
+    if (h) h->begin(h->ctx, stage | (launches << 16));
   }
   ~HookScope() {
     if (h) h->end(h->ctx);
@@ -1155,20 +1155,20 @@ static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32
                                      const TimingHook* hook, bool skip_last_row) {
   const double tol = 64.0 * (double)l_true * 0x1p-53;
   const int Tn = lw / NB;
+  int p = 0;
   {
-    HookScope hs(hook, SUB_CHOL_PANEL);
+    // one timing pair over the whole chain of dependent launches
+    HookScope hs(hook, SUB_CHOL_PANEL, 1 + (Tn - 1) / 2);
     hipLaunchKernelGGL(chol_first2_kernel, dim3(1), dim3(256), 0, s, lw, l_true, w.G, w.L, w.Dinv, w.diag0, tol,
                        flags);
-  }
-  LRAMM_HIP(hipGetLastError());
-  int p = 0;
-  for (; p + 2 < Tn; p += 2) {
-    const int R = Tn - p - 2;
-    const int nb = R * (R + 1) / 2 + p + 2;
-    HookScope hs(hook, SUB_CHOL_PANEL);
-    hipLaunchKernelGGL(chol_panel2_kernel, dim3(nb), dim3(256), 0, s, lw, l_true, p, w.G, w.L, w.Dinv, w.X,
-                       w.diag0, tol, flags);
     LRAMM_HIP(hipGetLastError());
+    for (; p + 2 < Tn; p += 2) {
+      const int R = Tn - p - 2;
+      const int nb = R * (R + 1) / 2 + p + 2;
+      hipLaunchKernelGGL(chol_panel2_kernel, dim3(nb), dim3(256), 0, s, lw, l_true, p, w.G, w.L, w.Dinv, w.X,
+                         w.diag0, tol, flags);
+      LRAMM_HIP(hipGetLastError());
+    }
   }
   if (skip_last_row && Tn - p == 1) return LRAMM_OK;
   hipLaunchKernelGGL(inverse_rows_kernel, dim3(Tn), dim3(256), 0, s, lw, p, Tn - p, w.L, w.Dinv, w.X);

@@ -172,7 +172,7 @@ lramm_status launch_omega(uint64_t seed, int64_t k, int64_t l, int64_t lrows, fl
 // Optional measurement hook: event pairs around individual launches.
 struct TimingHook {
   void* ctx;
-  void (*begin)(void* ctx, int stage);
+  void (*begin)(void* ctx, int stage);   // stage | (launches << 16): one event pair over that many launches
   void (*end)(void* ctx);
 };
 // sub-stage ids inside the orthonormalisation (continuing the forward's list)

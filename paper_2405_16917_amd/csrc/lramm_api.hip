@@ -48,6 +48,7 @@ struct lramm_plan {
   bool timing = false;
   std::vector<hipEvent_t> events;     // pool, reused
   std::vector<int> rec_stage;         // stage of each recorded pair
+  std::vector<int> rec_weight;        // kernel launches inside each recorded pair
   size_t next_event = 0;
   double stage_ms[LRAMM_NSTAGES] = {0};
   int64_t stage_n[LRAMM_NSTAGES] = {0};
@@ -92,7 +93,7 @@ struct StageTimer {
   hipStream_t s;
   int stage;
   hipEvent_t stop = nullptr;
-  StageTimer(lramm_plan* p_, hipStream_t s_, int st) : p(p_), s(s_), stage(st) {
+  StageTimer(lramm_plan* p_, hipStream_t s_, int st, int weight = 1) : p(p_), s(s_), stage(st) {
     if (!p->timing) return;
     while (p->events.size() < p->next_event + 2) {
       hipEvent_t e;
@@ -106,6 +107,7 @@ struct StageTimer {
     stop = p->events[p->next_event + 1];
     p->next_event += 2;
     p->rec_stage.push_back(stage);
+    p->rec_weight.push_back(weight);
     (void)hipEventRecord(start, s);
   }
   ~StageTimer() {
@@ -121,7 +123,8 @@ struct HookCtx {
 };
 void hook_begin(void* c, int stage) {
   HookCtx* h = static_cast<HookCtx*>(c);
-  h->open.push_back(new StageTimer(h->p, h->s, stage));
+  const int launches = stage >> 16;
+  h->open.push_back(new StageTimer(h->p, h->s, stage & 0xffff, launches > 0 ? launches : 1));
 }
 void hook_end(void* c) {
   HookCtx* h = static_cast<HookCtx*>(c);
@@ -307,9 +310,10 @@ lramm_status lramm_stage_times(lramm_plan* plan, double* ms, int64_t* counts) {
     LRAMM_HIP(hipEventElapsedTime(&t, a, b));
     int st = plan->rec_stage[i];
     plan->stage_ms[st] += t;
-    plan->stage_n[st] += 1;
+    plan->stage_n[st] += plan->rec_weight[i];
   }
   plan->rec_stage.clear();
+  plan->rec_weight.clear();
   plan->next_event = 0;
   for (int i = 0; i < LRAMM_NSTAGES; ++i) {
     if (ms) ms[i] = plan->stage_ms[i];
