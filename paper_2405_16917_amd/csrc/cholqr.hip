@@ -110,11 +110,12 @@ __global__ __launch_bounds__(256) void gram_kernel(int64_t rows, int lw, int nco
 #pragma unroll
         for (int sj = 0; sj < 2; ++sj) acc[si][sj] = mfma_f64(a[q][si], b[q][sj], acc[si][sj]);
   };
-  // full groups of 32 rows (8 MFMA steps); the next group is loaded while
-  // the current one is multiplied
+  // full groups of 32 rows (8 MFMA steps) in three register buffers, loads
+  // two groups ahead of the MFMAs; fetches past the last group re-read group
+  // 0 (valid rows, unused) so that no load sits under a branch
   const int64_t nfull = w1 > w0 ? (w1 - w0) / 32 : 0;
-  double av[8][2], bv[8][2];
-  auto fetch = [&](int64_t r, double (*a)[2], double (*b)[2]) {
+  auto fetch = [&](int64_t g, double (*a)[2], double (*b)[2]) {
+    const int64_t r = w0 + 32 * (g < nfull ? g : 0);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const T* xr = X + (r + 4 * q + lk) * ldx;
@@ -125,22 +126,25 @@ __global__ __launch_bounds__(256) void gram_kernel(int64_t rows, int lw, int nco
       }
     }
   };
-  if (nfull > 0) fetch(w0, av, bv);
-  for (int64_t g = 0; g < nfull; ++g) {
-    double an[8][2], bn[8][2];
-    const bool more = g + 1 < nfull;
-    if (more) fetch(w0 + 32 * (g + 1), an, bn);
-    mma(av, bv);
-    if (more) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-#pragma unroll
-        for (int u = 0; u < 2; ++u) av[q][u] = an[q][u], bv[q][u] = bn[q][u];
+  if (nfull > 0) {
+    double a0[8][2], b0[8][2], a1[8][2], b1[8][2], a2[8][2], b2[8][2];
+    fetch(0, a0, b0);
+    fetch(1, a1, b1);
+    for (int64_t g = 0; g < nfull; g += 3) {
+      fetch(g + 2, a2, b2);
+      mma(a0, b0);
+      if (g + 1 >= nfull) break;
+      fetch(g + 3, a0, b0);
+      mma(a1, b1);
+      if (g + 2 >= nfull) break;
+      fetch(g + 4, a1, b1);
+      mma(a2, b2);
     }
   }
   // the last partial group (rows past w1 contribute zero)
   const int64_t rt = w0 + 32 * nfull;
   if (rt < w1) {
+    double av[8][2], bv[8][2];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int64_t rr = rt + 4 * q + lk;
@@ -194,9 +198,17 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int lw, int l_true, in
   if (e < (int64_t)lw * lw) {
     const int i = (int)(e / lw), j = (int)(e % lw);
     if ((i / NB) >= (j / NB)) {   // upper tiles are never read
+      // the chunks in order, sixteen loads in flight (clamped, unused past the last chunk)
       double s = 0.0;
-#pragma unroll 8
-      for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * lw * lw + e];   // loads batched, sum in order
+      const int64_t sq = (int64_t)lw * lw;
+      for (int c0 = 0; c0 < nchunks; c0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = part[(int64_t)(c0 + u < nchunks ? c0 + u : nchunks - 1) * sq + e];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (c0 + u < nchunks) s += v[u];
+      }
       G[e] = s;
       if (i == j) diag0[i] = s;
       if (mode == 1 && i < l_true && j <= i) {
@@ -468,44 +480,47 @@ __device__ __forceinline__ double lane_bcast(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// Order LDS accesses of one wavefront (compiler barrier + LDS wait).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-}
+// LDS of one wavefront's block factorisation (doubles, 16-byte aligned):
+// the published columns of L (one 64-slot row per column) and the pivot
+// thresholds.
+constexpr int kFactorScratch = NB * 64 + NB;
 
-// One wavefront factors the 32 x 32 block S (LDS, pitch NB + 1) into L
-// (written to Lout, row pitch ldl, zeros above the diagonal) and writes the
-// inverse X = L^-1 to Iout (32 x 32, row-major), both in one right-looking
-// sweep over the columns.  Lanes 0..31 keep row i = lane of the block, lanes
+// One wavefront factors the 32 x 32 block S (LDS, pitch NB + 1) in place
+// into L (the entries above the diagonal are left undefined: store the tile
+// with tile_store_lower) and writes the inverse X = L^-1 to the LDS tile Xo
+// (pitch NB + 1), both in one right-looking sweep over the columns.  Lanes 0..31 keep row i = lane of the block, lanes
 // 32..63 column c = lane - 32 of X (starting as the identity), in the same
-// registers v[].  Step j: the pivot v[j] of lane j is read by readlane, the
-// scaled column l_j = L[:, j] is published in LDS (scratch, one 32-slot row
-// per column), and every lane applies
-//   v[k] -= m l_kj   (k > j),   m = l_ij (row lanes) or X[j][c] = v[j] / l_jj (column lanes),
+// registers v[].  Step j: the pivot v[j] of lane j is read by readlane, every
+// lane scales its v[j] by 1 / l_jj (giving l_ij on the row lanes and X[j][c]
+// on the column lanes), the scaled column is published in LDS, and every
+// lane applies
+//   v[k] -= m l_kj   (k > j),   m = the scaled v[j] of the lane,
 // i.e. the Cholesky update of row i and the same elimination on column c of
 // X, reading l_kj from LDS (uniform-address loads).  Only the update of the
-// next column (k = j + 1) is on the critical path, and it takes l_{j+1,j}
-// from lane j + 1 by readlane.
-// scratch: NB * NB doubles of LDS private to this wavefront.
+// next column (k = j + 1) is on the critical path; it takes l_{j+1,j} from
+// lane j + 1 by readlane, and the other updates of column j are applied one
+// step later, once their LDS loads have returned.  The LDS column is read
+// back by the wavefront that wrote it, so LDS keeps the order without a wait.
+// A pivot is accepted when it exceeds its threshold (tol times the original
+// Gram diagonal, +inf for padding columns); otherwise 1 / l_jj is taken as
+// zero and column j of L and row j of X vanish.  Dropped live pivots are
+// classified after the sweep: the pivot is recomputed on its lane with the
+// same operations in the same order (so it is bit-identical) and flags
+// breakdown, plus a negative or NaN pivot.
+// scratch: kFactorScratch doubles of LDS private to this wavefront.
 template <int NEWTON = 2>
-__device__ __attribute__((always_inline)) inline void factor_block_wave(const double* S, double* scratch,
+__device__ __attribute__((always_inline)) inline void factor_block_wave(double* S, double* Xo, double* scratch,
                                                                         const double* diag0, int col0, int l_true,
-                                                                        double tol, uint32_t* flags, double* Lout,
-                                                                        int64_t ldl, double* Iout) {
+                                                                        double tol, uint32_t* flags) {
   const int lane = threadIdx.x & 63;
   const int row = lane & 31;
   const bool fac = lane < NB;
-  // lane j's pivot threshold for column j (+inf marks a padding column);
-  // lane j tests its own pivot and a ballot makes the outcome uniform
+  double* thr_s = scratch + NB * 64;
   const bool live_col = col0 + row < l_true;
-  const double thr = live_col ? tol * diag0[col0 + row] : __builtin_inf();
+  if (fac) thr_s[lane] = live_col ? tol * diag0[col0 + row] : __builtin_inf();
   double v[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) v[k] = fac ? S[row * (NB + 1) + k] : (k == row ? 1.0 : 0.0);
-  uint64_t okbits = 0, negbits = 0;
-  // updates from column j - 1 other than the next column's are applied one
-  // step late, after pivot j, so that their LDS loads complete meanwhile
   double cprev[NB];
   double mprev = 0.0;
 #pragma unroll
@@ -513,11 +528,7 @@ __device__ __attribute__((always_inline)) inline void factor_block_wave(const do
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const double d = lane_bcast(v[j], j);
-    const uint64_t okm = __ballot(v[j] > thr);                       // bit j: pivot j accepted
-    const uint64_t ngm = __ballot(v[j] < -thr || v[j] != v[j]);      // bit j: negative or NaN
-    const bool ok = (okm >> j) & 1;
-    okbits |= okm & (1ull << j);
-    negbits |= ngm & (1ull << j);
+    const bool ok = d > thr_s[j];
     // 1/sqrt(d): hardware estimate (about 2^-23) refined by NEWTON Newton
     // steps, each squaring the relative error
     const double hd = 0.5 * d;
@@ -530,33 +541,49 @@ __device__ __attribute__((always_inline)) inline void factor_block_wave(const do
     // get values that are never read (their L entries are written as zero)
     const double m = v[j] * iv;
     v[j] = m;
-    double* col = scratch + j * NB;
-    if (fac) col[lane] = m;
-    // the store completes (and so do the previous column's loads, issued
-    // before this pivot); it also keeps the scheduler from overlapping
-    // steps, which would raise register pressure
-    wave_lds_sync();
+    double* col = scratch + j * 64;
+    col[lane] = m;                       // slots 32..63 are never read
     if (j + 1 < NB) {
       const double ln = lane_bcast(m, j + 1);       // l_{j+1, j}
       v[j + 1] = fma(-m, ln, v[j + 1]);
     }
 #pragma unroll
     for (int k = j + 1; k < NB; ++k) v[k] = fma(-mprev, cprev[k], v[k]);
+    // l_kj, k >= j + 2, for the delayed updates: 16-byte loads of aligned pairs
+    int k0 = j + 2;
+    if ((k0 & 1) && k0 < NB) cprev[k0++] = col[k0];
 #pragma unroll
-    for (int k = j + 2; k < NB; ++k) cprev[k] = col[k];
+    for (int k = k0; k < NB; k += 2) {
+      const double2 t = *reinterpret_cast<const double2*>(col + k);
+      cprev[k] = t.x;
+      cprev[k + 1] = t.y;
+    }
     mprev = m;
   }
-  uint32_t bad = 0;
-  if (fac && live_col && !((okbits >> row) & 1))
-    bad = ((negbits >> row) & 1) ? (LRAMM_FLAG_BREAKDOWN | LRAMM_FLAG_SQRTNEG) : LRAMM_FLAG_BREAKDOWN;
+  // a dropped pivot leaves l_jj = 0 (or NaN for a non-finite pivot)
+  const bool suspect = fac && live_col && !(scratch[row * 64 + row] > 0.0);
+  if (__ballot(suspect)) {
+    uint32_t bad = 0;
+    if (suspect) {
+      // the pivot of column r = row as the sweep formed it: the updates of
+      // columns 0 .. r-3 in order, then column r-1, then column r-2
+      const double* Lc = scratch + row;    // L[row][k] = Lc[64 k]
+      double d = S[row * (NB + 1) + row];
+      for (int k = 0; k + 2 < row; ++k) d = fma(-Lc[64 * k], Lc[64 * k], d);
+      if (row >= 1) d = fma(-Lc[64 * (row - 1)], Lc[64 * (row - 1)], d);
+      if (row >= 2) d = fma(-Lc[64 * (row - 2)], Lc[64 * (row - 2)], d);
+      const double thr = thr_s[row];
+      if (!(d > thr)) bad = (d < -thr || d != d) ? (LRAMM_FLAG_BREAKDOWN | LRAMM_FLAG_SQRTNEG) : LRAMM_FLAG_BREAKDOWN;
+    }
+    if (bad && flags) atomicOr(flags, bad);
+  }
   if (fac) {
 #pragma unroll
-    for (int k = 0; k < NB; ++k) Lout[(int64_t)row * ldl + k] = k <= row ? v[k] : 0.0;
+    for (int k = 0; k < NB; ++k) S[row * (NB + 1) + k] = v[k];
   } else {
 #pragma unroll
-    for (int k = 0; k < NB; ++k) Iout[k * NB + row] = v[k];
+    for (int k = 0; k < NB; ++k) Xo[k * (NB + 1) + row] = v[k];
   }
-  if (bad && flags) atomicOr(flags, bad);
 }
 
 // 32 x 32 tile product on 4 wavefronts: out = X Y^T (X, Y in LDS, pitch
@@ -600,22 +627,41 @@ __device__ __forceinline__ void tile_store(double* dst, int64_t ld, const double
   }
 }
 
-// This wavefront's 16 x 16 sub-tile of an LDS tile, in accumulator layout.
-__device__ __forceinline__ void sub_put(double (*T)[NB + 1], v4d v) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// The lower triangle of an LDS tile, zeros above the diagonal.
+__device__ __forceinline__ void tile_store_lower(double* dst, int64_t ld, const double (*src)[NB + 1]) {
+  const int tid = threadIdx.x;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) T[16 * (wave >> 1) + 4 * r + (lane >> 4)][16 * (wave & 1) + (lane & 15)] = v[r];
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = tid + 256 * u;
+    const int r = e / NB, c = e % NB;
+    dst[(int64_t)r * ld + c] = c <= r ? src[r][c] : 0.0;
+  }
 }
-__device__ __forceinline__ v4d sub_get(const double (*T)[NB + 1]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+// The 16 x 16 sub-tile st = 2 (row half) + (column half) of an LDS tile, in
+// accumulator layout, and the same sub-tile of a product X Y^T.
+__device__ __forceinline__ void sub_put_at(double (*T)[NB + 1], int st, v4d v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) T[16 * (st >> 1) + 4 * r + (lane >> 4)][16 * (st & 1) + (lane & 15)] = v[r];
+}
+__device__ __forceinline__ v4d sub_get_at(const double (*T)[NB + 1], int st) {
+  const int lane = threadIdx.x & 63;
   v4d v;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) v[r] = T[16 * (wave >> 1) + 4 * r + (lane >> 4)][16 * (wave & 1) + (lane & 15)];
+  for (int r = 0; r < 4; ++r) v[r] = T[16 * (st >> 1) + 4 * r + (lane >> 4)][16 * (st & 1) + (lane & 15)];
   return v;
 }
+__device__ __forceinline__ v4d sub_xyt_at(const double (*X)[NB + 1], const double (*Y)[NB + 1], int st) {
+  const int lane = threadIdx.x & 63;
+  return tile_xyt(X, Y, st, lane & 15, lane >> 4);
+}
+
+// This wavefront's sub-tile (st = wave index).
+__device__ __forceinline__ void sub_put(double (*T)[NB + 1], v4d v) { sub_put_at(T, threadIdx.x >> 6, v); }
+__device__ __forceinline__ v4d sub_get(const double (*T)[NB + 1]) { return sub_get_at(T, threadIdx.x >> 6); }
 __device__ __forceinline__ v4d sub_xyt(const double (*X)[NB + 1], const double (*Y)[NB + 1]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return tile_xyt(X, Y, wave, lane & 15, lane >> 4);
+  return sub_xyt_at(X, Y, threadIdx.x >> 6);
 }
 
 // In place: T <- T Y^T (a product of two LDS tiles written over its left factor).
@@ -722,7 +768,7 @@ __global__ __launch_bounds__(256) void chol_first2_kernel(int lw, int l_true, co
                                                           const double* __restrict__ diag0, double tol,
                                                           uint32_t* flags) {
   __shared__ Tile s00, s10, s11, sD;
-  __shared__ double scratch[NB * NB + 2 * NB];
+  __shared__ __align__(16) double scratch[kFactorScratch];
   const int T = lw / NB;
   const int wave = threadIdx.x >> 6;
   tile_load(s00, G, lw);
@@ -731,19 +777,20 @@ __global__ __launch_bounds__(256) void chol_first2_kernel(int lw, int l_true, co
     tile_load(s11, G + (int64_t)NB * lw + NB, lw);
   }
   __syncthreads();
-  if (wave == 0) factor_block_wave<1>(&s00[0][0], scratch, diag0, 0, l_true, tol, flags, L, lw, Dinv);
+  if (wave == 0) factor_block_wave<1>(&s00[0][0], &sD[0][0], scratch, diag0, 0, l_true, tol, flags);
   __syncthreads();
+  tile_store_lower(L, lw, s00);
+  tile_store(Dinv, NB, sD);
   if (T == 1) return;
-  tile_load(sD, Dinv, NB);
-  __syncthreads();
   tile_mul_t_inplace(s10, sD);                 // L_10
   __syncthreads();
   tile_store(L + (int64_t)NB * lw, lw, s10);
   sub_put(s11, sub_get(s11) - sub_xyt(s10, s10));
   __syncthreads();
-  if (wave == 0)
-    factor_block_wave<1>(&s11[0][0], scratch, diag0, NB, l_true, tol, flags, L + (int64_t)NB * lw + NB, lw,
-                         Dinv + NB * NB);
+  if (wave == 0) factor_block_wave<1>(&s11[0][0], &sD[0][0], scratch, diag0, NB, l_true, tol, flags);
+  __syncthreads();
+  tile_store_lower(L + (int64_t)NB * lw + NB, lw, s11);
+  tile_store(Dinv + NB * NB, NB, sD);
 }
 
 // Launch p (p even, p + 2 < T).  Blocks 0 .. nt-1: trailing tiles (i, j),
@@ -755,8 +802,9 @@ __global__ __launch_bounds__(256) void chol_panel2_kernel(int lw, int l_true, in
                                                           double* __restrict__ Xinv,
                                                           const double* __restrict__ diag0, double tol,
                                                           uint32_t* flags) {
-  __shared__ Tile sD0, sD1, sL10, sA0, sA1, sB0, sB1, sU, sV, sW;
-  __shared__ double scratch[NB * NB + 2 * NB];
+  __shared__ Tile sD0, sD1, sL10, sA0, sA1, sB0, sB1, sU, sV, sW, sX;
+  __shared__ __align__(16) double scratch[kFactorScratch];
+  __shared__ int s_cnt;   // wavefronts 1 and 2 of the diagonal workgroup meet on it
   const int T = lw / NB;
   const int R = T - p - 2;
   const int nt = R * (R + 1) / 2;
@@ -790,72 +838,112 @@ __global__ __launch_bounds__(256) void chol_panel2_kernel(int lw, int l_true, in
     tile_load(sV, G + (int64_t)(i + 1) * NB * lw + i * NB, lw);          // G_{i+1,i}
     tile_load(sW, G + (int64_t)(i + 1) * NB * lw + (i + 1) * NB, lw);    // G_{i+1,i+1}
   }
+  if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
-  const bool hasB = other || two;
-  // panel p: L_{r,p} = G_{r,p} Dinv_p^T
+  if (diag) {
+    // Row i: panel tiles and the update of G_ii, one 16 x 16 sub-tile per wavefront.
+    {
+      const v4d a = sub_xyt(sA0, sD0);
+      __syncthreads();
+      sub_put(sA0, a);
+    }
+    __syncthreads();
+    sub_put(sA1, sub_get(sA1) - sub_xyt(sA0, sL10));
+    __syncthreads();
+    {
+      const v4d a = sub_xyt(sA1, sD1);
+      __syncthreads();
+      sub_put(sA1, a);
+    }
+    __syncthreads();
+    tile_store(L + (int64_t)i * NB * lw + p * NB, lw, sA0);
+    tile_store(L + (int64_t)i * NB * lw + (p + 1) * NB, lw, sA1);
+    sub_put(sU, sub_get(sU) - (sub_xyt(sA0, sA0) + sub_xyt(sA1, sA1)));
+    __syncthreads();
+    if (wave == 0) {
+      factor_block_wave<1>(&sU[0][0], &sX[0][0], scratch, diag0, i * NB, l_true, tol, flags);
+    } else if (two && wave <= 2) {
+      // Meanwhile wavefronts 1 and 2 take row i + 1, rows 16 h .. 16 h + 15 each
+      // (h = wave - 1): its panel tiles and G_{i+1,i} need only these rows and
+      // the finished tiles of row i, so each wavefront updates its rows in
+      // place with no barrier; G_{i+1,i+1} needs both halves of the panel
+      // tiles and waits for the other wavefront on an LDS counter.  Wavefront
+      // 3 has no part in it.
+      const int h = wave - 1;
+      v4d c0 = sub_xyt_at(sB0, sD0, 2 * h), c1 = sub_xyt_at(sB0, sD0, 2 * h + 1);
+      sub_put_at(sB0, 2 * h, c0);
+      sub_put_at(sB0, 2 * h + 1, c1);
+      c0 = sub_get_at(sB1, 2 * h) - sub_xyt_at(sB0, sL10, 2 * h);
+      c1 = sub_get_at(sB1, 2 * h + 1) - sub_xyt_at(sB0, sL10, 2 * h + 1);
+      sub_put_at(sB1, 2 * h, c0);
+      sub_put_at(sB1, 2 * h + 1, c1);
+      c0 = sub_xyt_at(sB1, sD1, 2 * h);
+      c1 = sub_xyt_at(sB1, sD1, 2 * h + 1);
+      sub_put_at(sB1, 2 * h, c0);
+      sub_put_at(sB1, 2 * h + 1, c1);
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        sub_put_at(sV, 2 * h + c,
+                   sub_get_at(sV, 2 * h + c) - (sub_xyt_at(sB0, sA0, 2 * h + c) + sub_xyt_at(sB1, sA1, 2 * h + c)));
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_add(&s_cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      while (__hip_atomic_load(&s_cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < 2) __builtin_amdgcn_s_sleep(1);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      // the lower sub-tiles of G_{i+1,i+1} (the factor reads no entry above the diagonal)
+      const int st0 = h == 0 ? 0 : 2;
+      sub_put_at(sW, st0, sub_get_at(sW, st0) - (sub_xyt_at(sB0, sB0, st0) + sub_xyt_at(sB1, sB1, st0)));
+      if (h == 0) sub_put_at(sW, 3, sub_get_at(sW, 3) - (sub_xyt_at(sB0, sB0, 3) + sub_xyt_at(sB1, sB1, 3)));
+    }
+    __syncthreads();
+    tile_store_lower(L + (int64_t)i * NB * lw + i * NB, lw, sU);
+    tile_store(Dinv + (int64_t)i * NB * NB, NB, sX);
+    if (!two) return;
+    tile_store(L + (int64_t)(i + 1) * NB * lw + p * NB, lw, sB0);
+    tile_store(L + (int64_t)(i + 1) * NB * lw + (p + 1) * NB, lw, sB1);
+    tile_mul_t_inplace(sV, sX);                  // L_{i+1,i}
+    __syncthreads();
+    tile_store(L + (int64_t)(i + 1) * NB * lw + i * NB, lw, sV);
+    sub_put(sW, sub_get(sW) - sub_xyt(sV, sV));
+    __syncthreads();
+    // the Dinv tile of panel p is no longer read: it receives the inverse of block i + 1
+    if (wave == 0) factor_block_wave<1>(&sW[0][0], &sD0[0][0], scratch, diag0, (i + 1) * NB, l_true, tol, flags);
+    __syncthreads();
+    tile_store_lower(L + (int64_t)(i + 1) * NB * lw + (i + 1) * NB, lw, sW);
+    tile_store(Dinv + (int64_t)(i + 1) * NB * NB, NB, sD0);
+    return;
+  }
+  // trailing tile (i, j): panel p: L_{r,p} = G_{r,p} Dinv_p^T for r = i (and j)
   {
     const v4d a = sub_xyt(sA0, sD0);
-    const v4d c = hasB ? sub_xyt(sB0, sD0) : a;
+    const v4d c = other ? sub_xyt(sB0, sD0) : a;
     __syncthreads();
     sub_put(sA0, a);
-    if (hasB) sub_put(sB0, c);
+    if (other) sub_put(sB0, c);
   }
   __syncthreads();
   // panel p + 1: L_{r,p+1} = (G_{r,p+1} - L_{r,p} L_{p+1,p}^T) Dinv_{p+1}^T
   sub_put(sA1, sub_get(sA1) - sub_xyt(sA0, sL10));
-  if (hasB) sub_put(sB1, sub_get(sB1) - sub_xyt(sB0, sL10));
+  if (other) sub_put(sB1, sub_get(sB1) - sub_xyt(sB0, sL10));
   __syncthreads();
   {
     const v4d a = sub_xyt(sA1, sD1);
-    const v4d c = hasB ? sub_xyt(sB1, sD1) : a;
+    const v4d c = other ? sub_xyt(sB1, sD1) : a;
     __syncthreads();
     sub_put(sA1, a);
-    if (hasB) sub_put(sB1, c);
+    if (other) sub_put(sB1, c);
   }
   __syncthreads();
-  if (!diag) {
-    // G_ij -= L_{i,p} L_{j,p}^T + L_{i,p+1} L_{j,p+1}^T;  column p + 2 writes the panel tiles of row i
-    const double (*J0)[NB + 1] = other ? sB0 : sA0;
-    const double (*J1)[NB + 1] = other ? sB1 : sA1;
-    const v4d g = sub_get(sU) - (sub_xyt(sA0, J0) + sub_xyt(sA1, J1));
-    sub_put(sU, g);
-    __syncthreads();
-    tile_store(G + (int64_t)i * NB * lw + j * NB, lw, sU);
-    if (j == p + 2) {
-      tile_store(L + (int64_t)i * NB * lw + p * NB, lw, sA0);
-      tile_store(L + (int64_t)i * NB * lw + (p + 1) * NB, lw, sA1);
-    }
-    return;
+  // G_ij -= L_{i,p} L_{j,p}^T + L_{i,p+1} L_{j,p+1}^T;  column p + 2 writes the panel tiles of row i
+  const double (*J0)[NB + 1] = other ? sB0 : sA0;
+  const double (*J1)[NB + 1] = other ? sB1 : sA1;
+  const v4d g = sub_get(sU) - (sub_xyt(sA0, J0) + sub_xyt(sA1, J1));
+  sub_put(sU, g);
+  __syncthreads();
+  tile_store(G + (int64_t)i * NB * lw + j * NB, lw, sU);
+  if (j == p + 2) {
+    tile_store(L + (int64_t)i * NB * lw + p * NB, lw, sA0);
+    tile_store(L + (int64_t)i * NB * lw + (p + 1) * NB, lw, sA1);
   }
-  // diagonal workgroup: rows i (= p + 2) and i + 1
-  tile_store(L + (int64_t)i * NB * lw + p * NB, lw, sA0);
-  tile_store(L + (int64_t)i * NB * lw + (p + 1) * NB, lw, sA1);
-  if (two) {
-    tile_store(L + (int64_t)(i + 1) * NB * lw + p * NB, lw, sB0);
-    tile_store(L + (int64_t)(i + 1) * NB * lw + (p + 1) * NB, lw, sB1);
-  }
-  sub_put(sU, sub_get(sU) - (sub_xyt(sA0, sA0) + sub_xyt(sA1, sA1)));
-  if (two) {
-    sub_put(sV, sub_get(sV) - (sub_xyt(sB0, sA0) + sub_xyt(sB1, sA1)));
-    sub_put(sW, sub_get(sW) - (sub_xyt(sB0, sB0) + sub_xyt(sB1, sB1)));
-  }
-  __syncthreads();
-  double* Di = Dinv + (int64_t)i * NB * NB;
-  if (wave == 0)
-    factor_block_wave<1>(&sU[0][0], scratch, diag0, i * NB, l_true, tol, flags, L + (int64_t)i * NB * lw + i * NB,
-                         lw, Di);
-  if (!two) return;
-  __syncthreads();
-  tile_load(sD0, Di, NB);
-  __syncthreads();
-  tile_mul_t_inplace(sV, sD0);                 // L_{i+1,i}
-  __syncthreads();
-  tile_store(L + (int64_t)(i + 1) * NB * lw + i * NB, lw, sV);
-  sub_put(sW, sub_get(sW) - sub_xyt(sV, sV));
-  __syncthreads();
-  if (wave == 0)
-    factor_block_wave<1>(&sW[0][0], scratch, diag0, (i + 1) * NB, l_true, tol, flags,
-                         L + (int64_t)(i + 1) * NB * lw + (i + 1) * NB, lw, Dinv + (int64_t)(i + 1) * NB * NB);
 }
 
 // One wavefront: acc[si][sj] (16 x 16 sub-tiles) += X[32 x 32] Y[32 x 32]^T,
@@ -879,11 +967,12 @@ __device__ __forceinline__ void wave_tile_xyt(const double* X, int64_t ldx, cons
 }
 
 // The whole blocked Cholesky of G in one workgroup (no launches between
-// panels), used only by the gated fallback of the second pass.  sS and
-// scratch are LDS buffers of the caller.
+// panels), used only by the gated fallback of the second pass.  sS, sX (one
+// tile each) and scratch (kFactorScratch doubles, 16-byte aligned) are LDS
+// buffers of the caller.
 __device__ void chol_single_wg(int lw, int l_true, double* __restrict__ G, double* __restrict__ L,
                                double* __restrict__ Dinv, const double* __restrict__ diag0, double tol,
-                               uint32_t* flags, double (*sS)[NB + 1], double* scratch) {
+                               uint32_t* flags, double (*sS)[NB + 1], double (*sX)[NB + 1], double* scratch) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int T = lw / NB;
@@ -896,9 +985,10 @@ __device__ void chol_single_wg(int lw, int l_true, double* __restrict__ G, doubl
     }
     __syncthreads();
     double* Dp = Dinv + (int64_t)p * NB * NB;
-    if (wave == 0)
-      factor_block_wave(&sS[0][0], scratch, diag0, p * NB, l_true, tol, flags, L + (int64_t)p * NB * lw + p * NB,
-                        lw, Dp);
+    if (wave == 0) factor_block_wave(&sS[0][0], &sX[0][0], scratch, diag0, p * NB, l_true, tol, flags);
+    __syncthreads();
+    tile_store_lower(L + (int64_t)p * NB * lw + p * NB, lw, sS);
+    tile_store(Dp, NB, sX);
     __syncthreads();
     // panel: L_ip = G_ip Dinv_p^T, one 32 x 32 tile per wavefront
     for (int i = p + 1 + wave; i < T; i += 4) {
@@ -983,7 +1073,8 @@ __device__ __noinline__ void series_fallback(int lw, int l_true, double* G2, dou
                                              double (*red)[NB][NB + 1]) {
   const int tid = threadIdx.x;
   double (*sS)[NB + 1] = red[0];
-  chol_single_wg(lw, l_true, G2, L, Dinv, diag0, tol, flags, sS, &red[1][0][0]);
+  static_assert(kFactorScratch <= 2 * NB * (NB + 1), "factor scratch spans red[1] and red[2]");
+  chol_single_wg(lw, l_true, G2, L, Dinv, diag0, tol, flags, sS, red[3], &red[1][0][0]);
   const int Tn = lw / NB;
   for (int p = 0; p < Tn; ++p) {
     for (int j = 0; j <= p; ++j) {
@@ -1000,7 +1091,7 @@ __global__ __launch_bounds__(256) void series_kernel(int lw, int l_true, double*
                                                      double tol, uint32_t* flags, const uint32_t* gate,
                                                      const uint32_t* __restrict__ cm1,
                                                      uint32_t* __restrict__ colmax) {
-  __shared__ double red[5][NB][NB + 1];
+  __shared__ __align__(16) double red[5][NB][NB + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const uint32_t g = *gate;
