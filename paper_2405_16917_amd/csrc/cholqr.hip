@@ -481,9 +481,16 @@ __device__ __forceinline__ double lane_bcast(double v, int lane) {
 }
 
 // LDS of one wavefront's block factorisation (doubles, 16-byte aligned):
-// the published columns of L (one 64-slot row per column) and the pivot
-// thresholds.
-constexpr int kFactorScratch = NB * 64 + NB;
+// the published columns of L, one 64-slot row per column.
+constexpr int kFactorScratch = NB * 64;
+
+// Pivot threshold of column col: tol times its original Gram diagonal, +inf
+// for padding columns (col >= l_true; diag0 is not read there).  Callers load
+// the thresholds of a block into LDS at kernel start, so that the global
+// load's latency overlaps the tile loads instead of the factorisation.
+__device__ __forceinline__ double pivot_thr(const double* diag0, int col, int l_true, double tol) {
+  return col < l_true ? tol * diag0[col] : __builtin_inf();
+}
 
 // One wavefront factors the 32 x 32 block S (LDS, pitch NB + 1) in place
 // into L (the entries above the diagonal are left undefined: store the tile
@@ -501,23 +508,21 @@ constexpr int kFactorScratch = NB * 64 + NB;
 // lane j + 1 by readlane, and the other updates of column j are applied one
 // step later, once their LDS loads have returned.  The LDS column is read
 // back by the wavefront that wrote it, so LDS keeps the order without a wait.
-// A pivot is accepted when it exceeds its threshold (tol times the original
-// Gram diagonal, +inf for padding columns); otherwise 1 / l_jj is taken as
-// zero and column j of L and row j of X vanish.  Dropped live pivots are
+// A pivot is accepted when it exceeds its threshold thr[j] (LDS, see
+// pivot_thr); otherwise 1 / l_jj is taken as zero and column j of L and row j
+// of X vanish.  Dropped live pivots are
 // classified after the sweep: the pivot is recomputed on its lane with the
 // same operations in the same order (so it is bit-identical) and flags
 // breakdown, plus a negative or NaN pivot.
 // scratch: kFactorScratch doubles of LDS private to this wavefront.
 template <int NEWTON = 2>
 __device__ __attribute__((always_inline)) inline void factor_block_wave(double* S, double* Xo, double* scratch,
-                                                                        const double* diag0, int col0, int l_true,
-                                                                        double tol, uint32_t* flags) {
+                                                                        const double* thr_s, int col0, int l_true,
+                                                                        uint32_t* flags) {
   const int lane = threadIdx.x & 63;
   const int row = lane & 31;
   const bool fac = lane < NB;
-  double* thr_s = scratch + NB * 64;
   const bool live_col = col0 + row < l_true;
-  if (fac) thr_s[lane] = live_col ? tol * diag0[col0 + row] : __builtin_inf();
   double v[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) v[k] = fac ? S[row * (NB + 1) + k] : (k == row ? 1.0 : 0.0);
@@ -769,15 +774,18 @@ __global__ __launch_bounds__(256) void chol_first2_kernel(int lw, int l_true, co
                                                           uint32_t* flags) {
   __shared__ Tile s00, s10, s11, sD;
   __shared__ __align__(16) double scratch[kFactorScratch];
+  __shared__ double s_thr[2 * NB];   // pivot thresholds of blocks 0 and 1
   const int T = lw / NB;
   const int wave = threadIdx.x >> 6;
+  const double thr = threadIdx.x < 2 * NB ? pivot_thr(diag0, threadIdx.x, l_true, tol) : 0.0;
   tile_load(s00, G, lw);
   if (T > 1) {
     tile_load(s10, G + (int64_t)NB * lw, lw);
     tile_load(s11, G + (int64_t)NB * lw + NB, lw);
   }
+  if (threadIdx.x < 2 * NB) s_thr[threadIdx.x] = thr;
   __syncthreads();
-  if (wave == 0) factor_block_wave<1>(&s00[0][0], &sD[0][0], scratch, diag0, 0, l_true, tol, flags);
+  if (wave == 0) factor_block_wave<1>(&s00[0][0], &sD[0][0], scratch, s_thr, 0, l_true, flags);
   __syncthreads();
   tile_store_lower(L, lw, s00);
   tile_store(Dinv, NB, sD);
@@ -787,7 +795,7 @@ __global__ __launch_bounds__(256) void chol_first2_kernel(int lw, int l_true, co
   tile_store(L + (int64_t)NB * lw, lw, s10);
   sub_put(s11, sub_get(s11) - sub_xyt(s10, s10));
   __syncthreads();
-  if (wave == 0) factor_block_wave<1>(&s11[0][0], &sD[0][0], scratch, diag0, NB, l_true, tol, flags);
+  if (wave == 0) factor_block_wave<1>(&s11[0][0], &sD[0][0], scratch, s_thr + NB, NB, l_true, flags);
   __syncthreads();
   tile_store_lower(L + (int64_t)NB * lw + NB, lw, s11);
   tile_store(Dinv + NB * NB, NB, sD);
@@ -805,6 +813,7 @@ __global__ __launch_bounds__(256) void chol_panel2_kernel(int lw, int l_true, in
   __shared__ Tile sD0, sD1, sL10, sA0, sA1, sB0, sB1, sU, sV, sW, sX;
   __shared__ __align__(16) double scratch[kFactorScratch];
   __shared__ int s_cnt;   // wavefronts 1 and 2 of the diagonal workgroup meet on it
+  __shared__ double s_thr[2 * NB];   // pivot thresholds of the diagonal workgroup's blocks
   const int T = lw / NB;
   const int R = T - p - 2;
   const int nt = R * (R + 1) / 2;
@@ -819,13 +828,14 @@ __global__ __launch_bounds__(256) void chol_panel2_kernel(int lw, int l_true, in
   const int i = p + 2 + di, j = p + 2 + dj;
   const int wave = threadIdx.x >> 6;
   const double* Dp = Dinv + (int64_t)p * NB * NB;
+  const bool diag = b == 0;
+  const double thr = diag && threadIdx.x < 2 * NB ? pivot_thr(diag0, i * NB + threadIdx.x, l_true, tol) : 0.0;
   // every load first: Dinv_p, Dinv_{p+1}, L_{p+1,p}, the panel tiles of rows i (and j)
   tile_load(sD0, Dp, NB);
   tile_load(sD1, Dp + NB * NB, NB);
   tile_load(sL10, L + (int64_t)(p + 1) * NB * lw + p * NB, lw);
   tile_load(sA0, G + (int64_t)i * NB * lw + p * NB, lw);
   tile_load(sA1, G + (int64_t)i * NB * lw + (p + 1) * NB, lw);
-  const bool diag = b == 0;
   const bool two = diag && i + 1 < T;          // the diagonal workgroup also owns row i + 1
   const bool other = !diag && j != i;          // a distinct row j
   if (other || two) {
@@ -839,6 +849,7 @@ __global__ __launch_bounds__(256) void chol_panel2_kernel(int lw, int l_true, in
     tile_load(sW, G + (int64_t)(i + 1) * NB * lw + (i + 1) * NB, lw);    // G_{i+1,i+1}
   }
   if (threadIdx.x == 0) s_cnt = 0;
+  if (diag && threadIdx.x < 2 * NB) s_thr[threadIdx.x] = thr;
   __syncthreads();
   if (diag) {
     // Row i: panel tiles and the update of G_ii, one 16 x 16 sub-tile per wavefront.
@@ -861,7 +872,7 @@ __global__ __launch_bounds__(256) void chol_panel2_kernel(int lw, int l_true, in
     sub_put(sU, sub_get(sU) - (sub_xyt(sA0, sA0) + sub_xyt(sA1, sA1)));
     __syncthreads();
     if (wave == 0) {
-      factor_block_wave<1>(&sU[0][0], &sX[0][0], scratch, diag0, i * NB, l_true, tol, flags);
+      factor_block_wave<1>(&sU[0][0], &sX[0][0], scratch, s_thr, i * NB, l_true, flags);
     } else if (two && wave <= 2) {
       // Meanwhile wavefronts 1 and 2 take row i + 1, rows 16 h .. 16 h + 15 each
       // (h = wave - 1): its panel tiles and G_{i+1,i} need only these rows and
@@ -906,7 +917,7 @@ __global__ __launch_bounds__(256) void chol_panel2_kernel(int lw, int l_true, in
     sub_put(sW, sub_get(sW) - sub_xyt(sV, sV));
     __syncthreads();
     // the Dinv tile of panel p is no longer read: it receives the inverse of block i + 1
-    if (wave == 0) factor_block_wave<1>(&sW[0][0], &sD0[0][0], scratch, diag0, (i + 1) * NB, l_true, tol, flags);
+    if (wave == 0) factor_block_wave<1>(&sW[0][0], &sD0[0][0], scratch, s_thr + NB, (i + 1) * NB, l_true, flags);
     __syncthreads();
     tile_store_lower(L + (int64_t)(i + 1) * NB * lw + (i + 1) * NB, lw, sW);
     tile_store(Dinv + (int64_t)(i + 1) * NB * NB, NB, sD0);
@@ -968,8 +979,9 @@ __device__ __forceinline__ void wave_tile_xyt(const double* X, int64_t ldx, cons
 
 // The whole blocked Cholesky of G in one workgroup (no launches between
 // panels), used only by the gated fallback of the second pass.  sS, sX (one
-// tile each) and scratch (kFactorScratch doubles, 16-byte aligned) are LDS
-// buffers of the caller.
+// tile each) and scratch (kFactorScratch + NB doubles, 16-byte aligned: the
+// factor's columns and the block's pivot thresholds) are LDS buffers of the
+// caller.
 __device__ void chol_single_wg(int lw, int l_true, double* __restrict__ G, double* __restrict__ L,
                                double* __restrict__ Dinv, const double* __restrict__ diag0, double tol,
                                uint32_t* flags, double (*sS)[NB + 1], double (*sX)[NB + 1], double* scratch) {
@@ -983,9 +995,11 @@ __device__ void chol_single_wg(int lw, int l_true, double* __restrict__ G, doubl
       const int e = tid + 256 * u;
       sS[e / NB][e % NB] = Gpp[(int64_t)(e / NB) * lw + e % NB];
     }
+    double* thr = scratch + kFactorScratch;
+    if (tid < NB) thr[tid] = pivot_thr(diag0, p * NB + tid, l_true, tol);
     __syncthreads();
     double* Dp = Dinv + (int64_t)p * NB * NB;
-    if (wave == 0) factor_block_wave(&sS[0][0], &sX[0][0], scratch, diag0, p * NB, l_true, tol, flags);
+    if (wave == 0) factor_block_wave(&sS[0][0], &sX[0][0], scratch, thr, p * NB, l_true, flags);
     __syncthreads();
     tile_store_lower(L + (int64_t)p * NB * lw + p * NB, lw, sS);
     tile_store(Dp, NB, sX);
@@ -1073,7 +1087,7 @@ __device__ __noinline__ void series_fallback(int lw, int l_true, double* G2, dou
                                              double (*red)[NB][NB + 1]) {
   const int tid = threadIdx.x;
   double (*sS)[NB + 1] = red[0];
-  static_assert(kFactorScratch <= 2 * NB * (NB + 1), "factor scratch spans red[1] and red[2]");
+  static_assert(kFactorScratch + NB <= 2 * NB * (NB + 1), "factor scratch and thresholds span red[1] and red[2]");
   chol_single_wg(lw, l_true, G2, L, Dinv, diag0, tol, flags, sS, red[3], &red[1][0][0]);
   const int Tn = lw / NB;
   for (int p = 0; p < Tn; ++p) {
