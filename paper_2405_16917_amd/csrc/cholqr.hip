@@ -514,8 +514,12 @@ __device__ __forceinline__ double pivot_thr(const double* diag0, int col, int l_
 // classified after the sweep: the pivot is recomputed on its lane with the
 // same operations in the same order (so it is bit-identical) and flags
 // breakdown, plus a negative or NaN pivot.
+// With NS < NB only the first NS columns are swept and the last NB - NS are
+// taken as dropped (their columns of L and rows of X are zero), which is
+// what the full sweep gives when those columns are padding (their
+// thresholds are +inf).
 // scratch: kFactorScratch doubles of LDS private to this wavefront.
-template <int NEWTON = 2>
+template <int NEWTON = 2, int NS = NB>
 __device__ __attribute__((always_inline)) inline void factor_block_wave(double* S, double* Xo, double* scratch,
                                                                         const double* thr_s, int col0, int l_true,
                                                                         uint32_t* flags) {
@@ -531,7 +535,7 @@ __device__ __attribute__((always_inline)) inline void factor_block_wave(double* 
 #pragma unroll
   for (int k = 0; k < NB; ++k) cprev[k] = 0.0;
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
+  for (int j = 0; j < NS; ++j) {
     const double d = lane_bcast(v[j], j);
     const bool ok = d > thr_s[j];
     // 1/sqrt(d): hardware estimate (about 2^-23) refined by NEWTON Newton
@@ -548,23 +552,25 @@ __device__ __attribute__((always_inline)) inline void factor_block_wave(double* 
     v[j] = m;
     double* col = scratch + j * 64;
     col[lane] = m;                       // slots 32..63 are never read
-    if (j + 1 < NB) {
+    if (j + 1 < NS) {
       const double ln = lane_bcast(m, j + 1);       // l_{j+1, j}
       v[j + 1] = fma(-m, ln, v[j + 1]);
     }
 #pragma unroll
-    for (int k = j + 1; k < NB; ++k) v[k] = fma(-mprev, cprev[k], v[k]);
+    for (int k = j + 1; k < NS; ++k) v[k] = fma(-mprev, cprev[k], v[k]);
     // l_kj, k >= j + 2, for the delayed updates: 16-byte loads of aligned pairs
     int k0 = j + 2;
-    if ((k0 & 1) && k0 < NB) cprev[k0++] = col[k0];
+    if ((k0 & 1) && k0 < NS) cprev[k0++] = col[k0];
 #pragma unroll
-    for (int k = k0; k < NB; k += 2) {
+    for (int k = k0; k < NS; k += 2) {
       const double2 t = *reinterpret_cast<const double2*>(col + k);
       cprev[k] = t.x;
       cprev[k + 1] = t.y;
     }
     mprev = m;
   }
+#pragma unroll
+  for (int k = NS; k < NB; ++k) v[k] = 0.0;   // padding columns: dropped
   // a dropped pivot leaves l_jj = 0 (or NaN for a non-finite pivot)
   const bool suspect = fac && live_col && !(scratch[row * 64 + row] > 0.0);
   if (__ballot(suspect)) {
@@ -589,6 +595,18 @@ __device__ __attribute__((always_inline)) inline void factor_block_wave(double* 
 #pragma unroll
     for (int k = 0; k < NB; ++k) Xo[k * (NB + 1) + row] = v[k];
   }
+}
+
+// The diagonal block at column col0, swept over its first half only when
+// its second half is padding (the last block of l' = l rounded up to 32).
+template <int NEWTON = 2>
+__device__ __attribute__((always_inline)) inline void factor_block(double* S, double* Xo, double* scratch,
+                                                                   const double* thr_s, int col0, int l_true,
+                                                                   uint32_t* flags) {
+  if (l_true - col0 <= NB / 2)
+    factor_block_wave<NEWTON, NB / 2>(S, Xo, scratch, thr_s, col0, l_true, flags);
+  else
+    factor_block_wave<NEWTON, NB>(S, Xo, scratch, thr_s, col0, l_true, flags);
 }
 
 // 32 x 32 tile product on 4 wavefronts: out = X Y^T (X, Y in LDS, pitch
@@ -785,7 +803,7 @@ __global__ __launch_bounds__(256) void chol_first2_kernel(int lw, int l_true, co
   }
   if (threadIdx.x < 2 * NB) s_thr[threadIdx.x] = thr;
   __syncthreads();
-  if (wave == 0) factor_block_wave<1>(&s00[0][0], &sD[0][0], scratch, s_thr, 0, l_true, flags);
+  if (wave == 0) factor_block<1>(&s00[0][0], &sD[0][0], scratch, s_thr, 0, l_true, flags);
   __syncthreads();
   tile_store_lower(L, lw, s00);
   tile_store(Dinv, NB, sD);
@@ -795,7 +813,7 @@ __global__ __launch_bounds__(256) void chol_first2_kernel(int lw, int l_true, co
   tile_store(L + (int64_t)NB * lw, lw, s10);
   sub_put(s11, sub_get(s11) - sub_xyt(s10, s10));
   __syncthreads();
-  if (wave == 0) factor_block_wave<1>(&s11[0][0], &sD[0][0], scratch, s_thr + NB, NB, l_true, flags);
+  if (wave == 0) factor_block<1>(&s11[0][0], &sD[0][0], scratch, s_thr + NB, NB, l_true, flags);
   __syncthreads();
   tile_store_lower(L + (int64_t)NB * lw + NB, lw, s11);
   tile_store(Dinv + NB * NB, NB, sD);
@@ -872,7 +890,7 @@ __global__ __launch_bounds__(256) void chol_panel2_kernel(int lw, int l_true, in
     sub_put(sU, sub_get(sU) - (sub_xyt(sA0, sA0) + sub_xyt(sA1, sA1)));
     __syncthreads();
     if (wave == 0) {
-      factor_block_wave<1>(&sU[0][0], &sX[0][0], scratch, s_thr, i * NB, l_true, flags);
+      factor_block<1>(&sU[0][0], &sX[0][0], scratch, s_thr, i * NB, l_true, flags);
     } else if (two && wave <= 2) {
       // Meanwhile wavefronts 1 and 2 take row i + 1, rows 16 h .. 16 h + 15 each
       // (h = wave - 1): its panel tiles and G_{i+1,i} need only these rows and
@@ -917,7 +935,7 @@ __global__ __launch_bounds__(256) void chol_panel2_kernel(int lw, int l_true, in
     sub_put(sW, sub_get(sW) - sub_xyt(sV, sV));
     __syncthreads();
     // the Dinv tile of panel p is no longer read: it receives the inverse of block i + 1
-    if (wave == 0) factor_block_wave<1>(&sW[0][0], &sD0[0][0], scratch, s_thr + NB, (i + 1) * NB, l_true, flags);
+    if (wave == 0) factor_block<1>(&sW[0][0], &sD0[0][0], scratch, s_thr + NB, (i + 1) * NB, l_true, flags);
     __syncthreads();
     tile_store_lower(L + (int64_t)(i + 1) * NB * lw + (i + 1) * NB, lw, sW);
     tile_store(Dinv + (int64_t)(i + 1) * NB * NB, NB, sD0);
@@ -999,7 +1017,7 @@ __device__ void chol_single_wg(int lw, int l_true, double* __restrict__ G, doubl
     if (tid < NB) thr[tid] = pivot_thr(diag0, p * NB + tid, l_true, tol);
     __syncthreads();
     double* Dp = Dinv + (int64_t)p * NB * NB;
-    if (wave == 0) factor_block_wave(&sS[0][0], &sX[0][0], scratch, thr, p * NB, l_true, flags);
+    if (wave == 0) factor_block(&sS[0][0], &sX[0][0], scratch, thr, p * NB, l_true, flags);
     __syncthreads();
     tile_store_lower(L + (int64_t)p * NB * lw + p * NB, lw, sS);
     tile_store(Dp, NB, sX);

@@ -291,18 +291,21 @@ def test_cholqr2_matches_householder(lib, case):
     assert int(flags.item()) == 0
 
 
-def test_cholqr2_f64_input_and_rank_deficiency(lib):
+# (l, dependent column): a full sweep of block 0, and the half sweep of a last
+# block whose second half is padding (l = 40: columns 32..39 live)
+@pytest.mark.parametrize("l,dead", [(50, 7), (40, 35)])
+def test_cholqr2_f64_input_and_rank_deficiency(lib, l, dead):
     rng = np.random.default_rng(9)
-    Y = rng.standard_normal((400, 50))
-    Y[:, 7] = 0.0
+    Y = rng.standard_normal((400, l))
+    Y[:, dead] = 0.0
     flags = torch.zeros(1, dtype=torch.int32, device=DEV)
-    Q = lib.lramm_cholqr2(g(Y, torch.float64), 50, flags=flags)
+    Q = lib.lramm_cholqr2(g(Y, torch.float64), l, flags=flags)
     torch.cuda.synchronize()
-    Qg = Q.cpu().numpy()[:, :50]
+    Qg = Q.cpu().numpy()[:, :l]
     assert int(flags.item()) & lib.FLAG_BREAKDOWN
-    assert not Qg[:, 7].any()
-    keep = [j for j in range(50) if j != 7]
-    assert np.max(np.abs(Qg[:, keep].T @ Qg[:, keep] - np.eye(49))) <= 1e-13
+    assert not Qg[:, dead].any()
+    keep = [j for j in range(l) if j != dead]
+    assert np.max(np.abs(Qg[:, keep].T @ Qg[:, keep] - np.eye(l - 1))) <= 1e-13
     # span is kept: Y = Q Q^T Y
     assert np.linalg.norm(Y - Qg @ (Qg.T @ Y)) <= 1e-12 * np.linalg.norm(Y)
 
