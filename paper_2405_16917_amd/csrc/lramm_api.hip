@@ -43,7 +43,7 @@ struct lramm_plan {
   int64_t pAr, pAc, pBc, pOm, pQZc, pQc, pQr, pBtq, pTtq;
   // side stream for the work independent of the orthonormalisation chain
   hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_omega = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_omega = nullptr, ev_sketch = nullptr;
   // stage timing (measurement only)
   bool timing = false;
   std::vector<hipEvent_t> events;     // pool, reused
@@ -277,7 +277,8 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess) p->side = nullptr;
   if (p->side && (hipEventCreateWithFlags(&p->ev_fork, kOrderEvent) != hipSuccess ||
                   hipEventCreateWithFlags(&p->ev_join, kOrderEvent) != hipSuccess ||
-                  hipEventCreateWithFlags(&p->ev_omega, kOrderEvent) != hipSuccess)) {
+                  hipEventCreateWithFlags(&p->ev_omega, kOrderEvent) != hipSuccess ||
+                  hipEventCreateWithFlags(&p->ev_sketch, kOrderEvent) != hipSuccess)) {
     (void)hipStreamDestroy(p->side);
     p->side = nullptr;
   }
@@ -291,6 +292,7 @@ void lramm_plan_destroy(lramm_plan* plan) {
   if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
   if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
   if (plan->ev_omega) (void)hipEventDestroy(plan->ev_omega);
+  if (plan->ev_sketch) (void)hipEventDestroy(plan->ev_sketch);
   if (plan->side) (void)hipStreamDestroy(plan->side);
   delete plan;
 }
@@ -382,9 +384,10 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
     LRAMM_TRY(expr);                      \
   } while (0)
   // The side stream first generates and quantises Omega (arithmetic bound)
-  // while the main stream quantises A's rows (bandwidth bound); then A's
-  // column codes and B's codes, first needed after the first
-  // orthonormalisation.
+  // while the main stream quantises A's rows (bandwidth bound).  A's column
+  // codes and B's codes, first needed after the first orthonormalisation,
+  // wait for the sketch: started earlier they take CUs and bandwidth from
+  // it, while the orthonormalisation's launches leave most CUs idle.
   hipStream_t s2 = P->side ? P->side : s;
   if (P->side) {
     LRAMM_HIP(hipEventRecord(P->ev_fork, s));
@@ -397,21 +400,24 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
              launch_quantize(l, k, OmT, k, LRAMM_F32, d.fmt_sketch, 0, Om, P->pOm, sOm, flags, s2));
     if (P->side) LRAMM_HIP(hipEventRecord(P->ev_omega, P->side));
   }
-  // queued before the side stream's column work so that it starts at once
   TIMED(ST_QUANT_A_ROWS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_sketch, 0, Ar, P->pAr, sAr, flags, s));
-  TIMED_ON(s2, ST_QUANT_A_COLS,
-           launch_quantize(m, k, A, lda, d.a_type, d.fmt_proj, 1, Ac, P->pAc, sAc, flags, s2, mxA));
-  TIMED_ON(s2, ST_QUANT_B, launch_quantize(k, n, B, ldb, d.b_type, d.fmt_g1, 1, Bc, P->pBc, sBc, flags, s2, mxB));
-  if (P->side) LRAMM_HIP(hipEventRecord(P->ev_join, P->side));
   if (omega) {
     TIMED(ST_QUANT_OMEGA, launch_quantize(k, l, omega, ldo, LRAMM_F32, d.fmt_sketch, 1, Om, P->pOm, sOm, flags, s,
                                           zero + P->mx_Om));
   } else if (P->side) {
     LRAMM_HIP(hipStreamWaitEvent(s, P->ev_omega, 0));   // Omega's codes ready
   }
-  // sketch and orthonormalisation
+  // sketch, then the side stream's column codes, then the orthonormalisation
   TIMED(ST_SKETCH, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, P->pAr, sAr, Om, P->pOm, sOm, 1.0f, 0.0f, Y, lp,
                                   LRAMM_F32, nullptr, 0, split, sb, s));
+  if (P->side) {
+    LRAMM_HIP(hipEventRecord(P->ev_sketch, s));
+    LRAMM_HIP(hipStreamWaitEvent(P->side, P->ev_sketch, 0));
+  }
+  TIMED_ON(s2, ST_QUANT_A_COLS,
+           launch_quantize(m, k, A, lda, d.a_type, d.fmt_proj, 1, Ac, P->pAc, sAc, flags, s2, mxA));
+  TIMED_ON(s2, ST_QUANT_B, launch_quantize(k, n, B, ldb, d.b_type, d.fmt_g1, 1, Bc, P->pBc, sBc, flags, s2, mxB));
+  if (P->side) LRAMM_HIP(hipEventRecord(P->ev_join, P->side));
   TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(0)));
   uint8_t* Qc = at<uint8_t>(W, P->off_Qc);
   float* sQc = at<float>(W, P->off_sQc);
