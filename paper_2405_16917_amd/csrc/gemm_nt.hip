@@ -352,12 +352,15 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
 
   // XCD-aware tile order: consecutive workgroup ids land on different XCDs
   // (round robin over 8); remap so that each XCD walks a contiguous band of
-  // tiles and shares operand rows in its own L2.
+  // tiles and shares operand rows in its own L2.  Within the band the short
+  // side's tile index varies fastest, so that the workgroups reading one tile
+  // of the long (larger) operand sit in the same XCD.
   const int ntiles = a.tiles_m * a.tiles_n;
   int bid = blockIdx.x;
   if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
-  const int tm = bid / a.tiles_n;
-  const int tn = bid % a.tiles_n;
+  const bool m_fast = a.tiles_m < a.tiles_n;
+  const int tm = m_fast ? bid % a.tiles_m : bid / a.tiles_n;
+  const int tn = m_fast ? bid / a.tiles_m : bid % a.tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
   const int split = blockIdx.y;
   const int st0 = split * a.st_per_split;
@@ -602,10 +605,13 @@ static Plan plan_gemm(int64_t M, int64_t N, int64_t K, int fmt, bool allow_split
   p.tiles_n = (int)ceil_div(N, p.bn);
   const int tiles = p.tiles_m * p.tiles_n;
   p.split = 1;
-  if (allow_split && tiles < 384) {
-    // too few tiles to keep 256 CUs busy (two workgroups each) and a long K:
-    // split K as far as one round of 512 workgroups allows, each slice
-    // keeping at least 4 stages; the partials are summed in a second pass
+  if (allow_split && tiles < 128) {
+    // too few tiles to occupy half of the 256 CUs and a long K: split K as
+    // far as one round of 512 workgroups allows, each slice keeping at least
+    // 4 stages; the partials are summed in a second pass.  From 128 tiles on
+    // one workgroup per tile is faster: the partial sums' traffic and the
+    // extra launch cost more than the idle CUs (measured at 160 tiles,
+    // K = 4096: 21 us unsplit against 23 us split in three)
     for (int sp = 2; sp <= 16; ++sp)
       if (tiles * sp <= 512 && p.nst / sp >= 4) p.split = sp;
   }
