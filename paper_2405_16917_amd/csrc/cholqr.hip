@@ -250,8 +250,13 @@ __host__ __device__ constexpr int ts_pitch(int lw) { return lw + 4; }
 __host__ __device__ constexpr size_t ts_solve_last_lds(int lw) {
   return (size_t)(2 * TS_ROWS * ts_pitch(lw) + (TS_WAVES + 1) * TS_ROWS * NB) * sizeof(double);
 }
+// With STAGED, each wavefront passes its W rows through an LDS tile of 32
+// rows x 16 k (pitch 18 doubles: the 16-byte reads of 8 consecutive rows hit
+// distinct banks), so that the global loads read whole 128-byte rows.
+constexpr int TS_WST = 32 * 18;
+constexpr size_t ts_stage_lds() { return (size_t)TS_WAVES * TS_WST * sizeof(double); }
 
-template <typename T, bool ADD>
+template <typename T, bool ADD, bool STAGED>
 __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int lw, int ncols, const T* X,
                                                               int64_t ldx, const double* __restrict__ W, double* Q,
                                                               int64_t ldq, int zero_to, int vec,
@@ -306,6 +311,59 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
     const double* w1p = W + (int64_t)(cb0 + 16 + li) * lw + 4 * lk;
     const double* ap = sA + li * pitch + 4 * lk;
     v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+    if constexpr (STAGED) {
+      // 8 rows of 16 k (128 bytes each) per load instruction; a kstep's 32 x 16
+      // tile goes through the wavefront's LDS tile into the MFMA layout.  The
+      // next group of four ksteps is loaded while this one is multiplied
+      // (past the last kstep the loads repeat it, unused).
+      double* wst = sA + (solve_last ? 2 * TS_ROWS * pitch + (TS_WAVES + 1) * TS_ROWS * NB : TS_ROWS * pitch) +
+                    wave * TS_WST;
+      typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+      const int lr = lane >> 3, lj = lane & 7;
+      const double* wg = W + (int64_t)(cb0 + lr) * lw + 2 * lj;
+      auto fetchg = [&](int g, v4u (*r)[4]) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int ks = min(4 * g + st, ksteps - 1);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) r[st][i] = *reinterpret_cast<const v4u*>(wg + (int64_t)(8 * i) * lw + 16 * ks);
+        }
+      };
+      v4u rc[4][4], rn[4][4];
+      fetchg(0, rc);
+      for (int g = 0; g < ngroups; ++g) {
+        fetchg(g + 1 < ngroups ? g + 1 : g, rn);
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int ks = 4 * g + st;
+          if (ks < ksteps) {
+            // the wavefront rewrites its tile only after reading the previous
+            // kstep from it (LDS keeps one wavefront's accesses in order)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) *reinterpret_cast<v4u*>(wst + (8 * i + lr) * 18 + 2 * lj) = rc[st][i];
+            double b0[4], b1[4];
+            const double2 x0 = *reinterpret_cast<const double2*>(wst + li * 18 + 4 * lk);
+            const double2 x1 = *reinterpret_cast<const double2*>(wst + li * 18 + 4 * lk + 2);
+            const double2 y0 = *reinterpret_cast<const double2*>(wst + (16 + li) * 18 + 4 * lk);
+            const double2 y1 = *reinterpret_cast<const double2*>(wst + (16 + li) * 18 + 4 * lk + 2);
+            b0[0] = x0.x, b0[1] = x0.y, b0[2] = x1.x, b0[3] = x1.y;
+            b1[0] = y0.x, b1[1] = y0.y, b1[2] = y1.x, b1[3] = y1.y;
+            double a[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[q] = ap[16 * ks + q];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              acc0 = mfma_f64(a[q], b0[q], acc0);
+              acc1 = mfma_f64(a[q], b1[q], acc1);
+            }
+          }
+        }
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) rc[st][i] = rn[st][i];
+      }
+    } else {
     double b[2][4][4];
     auto fetch = [&](int g, double (*b0)[4], double (*b1)[4]) {
 #pragma unroll
@@ -341,6 +399,7 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
 #pragma unroll
           for (int q = 0; q < 4; ++q) b[0][st][q] = bn[0][st][q], b[1][st][q] = bn[1][st][q];
       }
+    }
     }
     uint32_t m0 = 0, m1 = 0;   // column maxima of fl32(|Q|) over this wavefront's rows
     if (solve_last) {
@@ -1304,10 +1363,13 @@ static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t l
                           int64_t ldq, int zero_to, hipStream_t s, const TimingHook* hook,
                           uint32_t* colmax = nullptr, const uint32_t* gate = nullptr,
                           const double* Ltri = nullptr, const double* Dlast = nullptr) {
+  constexpr size_t kMaxLds = 160 * 1024;
   static bool attr_set = false;
-  if (!attr_set) {   // up to 16 x 1028 doubles of LDS
-    LRAMM_HIP(hipFuncSetAttribute((const void*)tsmul_kernel<T, ADD>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024));
+  if (!attr_set) {   // up to 160 KiB of LDS
+    LRAMM_HIP(hipFuncSetAttribute((const void*)tsmul_kernel<T, ADD, false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds));
+    LRAMM_HIP(hipFuncSetAttribute((const void*)tsmul_kernel<T, ADD, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds));
     attr_set = true;
   }
   HookScope hs(hook, ADD ? SUB_CHOL_APPLY : SUB_CHOL_SOLVE);
@@ -1315,8 +1377,14 @@ static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t l
   const int vec = ((uintptr_t)X % (4 * sizeof(T)) == 0 && ldx % 4 == 0) ? 1 : 0;
   size_t shm = (size_t)TS_ROWS * ts_pitch(lw) * sizeof(double);
   if (Ltri) shm = ts_solve_last_lds(lw);
-  hipLaunchKernelGGL((tsmul_kernel<T, ADD>), dim3((unsigned)ceil_div(rows, (int64_t)TS_ROWS)), dim3(TS_WAVES * 64),
-                     shm, s, rows, lw, ncols, X, ldx, W, Q, ldq, zero_to, vec, colmax, gate, Ltri, Dlast);
+  const dim3 grid((unsigned)ceil_div(rows, (int64_t)TS_ROWS)), block(TS_WAVES * 64);
+  // W staged through LDS when the tiles fit beside the row panel
+  if (shm + ts_stage_lds() <= kMaxLds)
+    hipLaunchKernelGGL((tsmul_kernel<T, ADD, true>), grid, block, shm + ts_stage_lds(), s, rows, lw, ncols, X, ldx, W,
+                       Q, ldq, zero_to, vec, colmax, gate, Ltri, Dlast);
+  else
+    hipLaunchKernelGGL((tsmul_kernel<T, ADD, false>), grid, block, shm, s, rows, lw, ncols, X, ldx, W, Q, ldq,
+                       zero_to, vec, colmax, gate, Ltri, Dlast);
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }
