@@ -34,6 +34,11 @@
 namespace lramm {
 
 constexpr int NB = 32;   // panel width
+// The first pass's column maxima of |Q1| are kept in kCmSlices copies, one
+// per group of workgroups (the solve's workgroup index mod kCmSlices), so
+// that a column's atomics spread over several words; readers take the
+// maximum over the copies.
+constexpr int kCmSlices = 8;
 
 __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -181,7 +186,7 @@ constexpr uint32_t kGatePass2 = 2u;   // the first pass is not yet orthonormal t
 
 // G (lower tiles) = sum over chunks in order; diag0 = diag(G).
 //   mode 0 (first pass): clears the gate word and the first-pass column
-//   maxima cm1 (lw words) of this orthonormalisation;
+//   maxima cm1 (kCmSlices x lw words) of this orthonormalisation;
 //   mode 1 (second pass): with E = G - I over i, j < l_true, raises kGateFull
 //   when some |E_ij| exceeds tau (or is NaN) and kGatePass2 when some |E_ij|
 //   exceeds tau_skip (or is NaN); one atomic per wavefront at most.
@@ -192,7 +197,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int lw, int l_true, in
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (mode == 0) {
     if (e == 0) *gate = 0u;
-    if (cm1 && e < lw) cm1[e] = 0u;
+    if (cm1 && e < (int64_t)kCmSlices * lw) cm1[e] = 0u;
   }
   uint32_t bits = 0;
   if (e < (int64_t)lw * lw) {
@@ -260,12 +265,13 @@ template <typename T, bool ADD, bool STAGED>
 __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int lw, int ncols, const T* X,
                                                               int64_t ldx, const double* __restrict__ W, double* Q,
                                                               int64_t ldq, int zero_to, int vec,
-                                                              uint32_t* __restrict__ colmax,
+                                                              uint32_t* __restrict__ colmax, int cm_stride,
                                                               const uint32_t* __restrict__ gate,
                                                               const double* __restrict__ Ltri,
                                                               const double* __restrict__ Dlast) {
   extern __shared__ double sA[];   // TS_ROWS x ts_pitch(lw) [+ the last-block solve's buffers]
   if (ADD && gate && !(*gate & kGatePass2)) return;   // second pass skipped: Q already holds Q1
+  if (colmax) colmax += (blockIdx.x % kCmSlices) * cm_stride;   // this workgroup's copy (cm_stride 0: one copy)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int pitch = ts_pitch(lw);
@@ -1189,7 +1195,12 @@ __global__ __launch_bounds__(256) void series_kernel(int lw, int l_true, double*
   if (!(g & kGatePass2)) {
     // second pass skipped: Q is Q1, whose column maxima become the result's
     if (blockIdx.x == 0 && cm1 && colmax)
-      for (int c = tid; c < l_true; c += 256) colmax[c] = cm1[c];
+      for (int c = tid; c < l_true; c += 256) {
+        uint32_t m = cm1[c];
+#pragma unroll
+        for (int q = 1; q < kCmSlices; ++q) m = max(m, cm1[(int64_t)q * lw + c]);
+        colmax[c] = m;
+      }
     return;
   }
   if (g & kGateFull) {
@@ -1266,7 +1277,7 @@ __global__ __launch_bounds__(256) void series_kernel(int lw, int l_true, double*
 struct CholWs {
   double *G, *L, *Dinv, *diag0, *part, *W, *X;
   uint32_t* gate;
-  uint32_t* cm1;   // column maxima of fl32(|Q1|) (first pass)
+  uint32_t* cm1;   // column maxima of fl32(|Q1|) (first pass), kCmSlices copies of lw words
   int nchunks;
   int64_t rows_per_chunk;
 };
@@ -1298,7 +1309,7 @@ size_t cholqr2_workspace(int64_t rows, int64_t l) {
   int64_t rpc;
   cholqr_layout(rows, l, &lw, &nc, &rpc);
   const size_t sq = (size_t)lw * lw;
-  const size_t n = 4 * sq + (size_t)lw * NB + lw + (size_t)nc * sq + 32 + (size_t)lw / 2 + 1;
+  const size_t n = 4 * sq + (size_t)lw * NB + lw + (size_t)nc * sq + 32 + (size_t)kCmSlices * lw / 2 + 1;
   return n * sizeof(double) + 256;
 }
 
@@ -1362,7 +1373,7 @@ template <typename T, bool ADD>
 static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t ldx, const double* W, double* Q,
                           int64_t ldq, int zero_to, hipStream_t s, const TimingHook* hook,
                           uint32_t* colmax = nullptr, const uint32_t* gate = nullptr,
-                          const double* Ltri = nullptr, const double* Dlast = nullptr) {
+                          const double* Ltri = nullptr, const double* Dlast = nullptr, int cm_stride = 0) {
   constexpr size_t kMaxLds = 160 * 1024;
   static bool attr_set = false;
   if (!attr_set) {   // up to 160 KiB of LDS
@@ -1381,10 +1392,10 @@ static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t l
   // W staged through LDS when the tiles fit beside the row panel
   if (shm + ts_stage_lds() <= kMaxLds)
     hipLaunchKernelGGL((tsmul_kernel<T, ADD, true>), grid, block, shm + ts_stage_lds(), s, rows, lw, ncols, X, ldx, W,
-                       Q, ldq, zero_to, vec, colmax, gate, Ltri, Dlast);
+                       Q, ldq, zero_to, vec, colmax, cm_stride, gate, Ltri, Dlast);
   else
     hipLaunchKernelGGL((tsmul_kernel<T, ADD, false>), grid, block, shm, s, rows, lw, ncols, X, ldx, W, Q, ldq,
-                       zero_to, vec, colmax, gate, Ltri, Dlast);
+                       zero_to, vec, colmax, cm_stride, gate, Ltri, Dlast);
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }
@@ -1434,12 +1445,12 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
     LRAMM_TRY(gram<float>(rows, lw, lt, (const float*)Y, ldy, w, 0, s, hook));
     LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last));
     LRAMM_TRY((tsmul<float, false>(rows, lw, lt, (const float*)Y, ldy, w.X, Q, ldq, zero_to, s, hook, cm1, nullptr,
-                                   Ltri, Dlast)));
+                                   Ltri, Dlast, lw)));
   } else if (ytype == LRAMM_F64) {
     LRAMM_TRY(gram<double>(rows, lw, lt, (const double*)Y, ldy, w, 0, s, hook));
     LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last));
     LRAMM_TRY((tsmul<double, false>(rows, lw, lt, (const double*)Y, ldy, w.X, Q, ldq, zero_to, s, hook, cm1,
-                                    nullptr, Ltri, Dlast)));
+                                    nullptr, Ltri, Dlast, lw)));
   } else {
     return LRAMM_E_UNSUPPORTED;
   }
