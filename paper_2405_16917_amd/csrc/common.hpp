@@ -155,10 +155,12 @@ lramm_status fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 // Column form (transpose = 1) with amax_ws: the column maxima go to that
 // caller-zeroed buffer (abs bit patterns, cols entries) -- or are already
 // there when amax_ready -- and the quantise pass writes the scales, saving the
-// fill and scale launches.
+// fill and scale launches.  With zero, zero_words words there are cleared
+// too, by the row kernels themselves (one launch fewer for the caller).
 lramm_status launch_quantize(int64_t rows, int64_t cols, const void* X, int64_t ldx, int xtype, int fmt,
                              int transpose, void* Xq, int64_t pitch, float* scales, uint32_t* flags,
-                             hipStream_t s, uint32_t* amax_ws = nullptr, bool amax_ready = false);
+                             hipStream_t s, uint32_t* amax_ws = nullptr, bool amax_ready = false,
+                             uint32_t* zero = nullptr, int64_t zero_words = 0);
 
 lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void* Lq, int64_t ldl,
                             const float* dL, const void* Rq, int64_t ldr, const float* dR, float alpha,

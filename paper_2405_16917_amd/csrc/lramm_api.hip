@@ -349,7 +349,8 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
   void* W = base;
   uint32_t* flags = at<uint32_t>(W, P->off_flags);
   uint32_t* zero = at<uint32_t>(W, P->off_zero);
-  LRAMM_TRY(fill_u32(zero, 0u, (int64_t)P->zero_words, s));
+  // the zero region (column-maxima accumulators) is cleared by the first
+  // kernel on s, A's row quantiser; its users all run after it
   uint32_t* mxA = zero + P->mx_A;
   uint32_t* mxB = zero + P->mx_B;
   auto mxQ = [&](int c) { return zero + P->mx_Q + (size_t)c * lp; };
@@ -400,7 +401,8 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
              launch_quantize(l, k, OmT, k, LRAMM_F32, d.fmt_sketch, 0, Om, P->pOm, sOm, flags, s2));
     if (P->side) LRAMM_HIP(hipEventRecord(P->ev_omega, P->side));
   }
-  TIMED(ST_QUANT_A_ROWS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_sketch, 0, Ar, P->pAr, sAr, flags, s));
+  TIMED(ST_QUANT_A_ROWS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_sketch, 0, Ar, P->pAr, sAr, flags, s,
+                                         nullptr, false, zero, (int64_t)P->zero_words));
   if (omega) {
     TIMED(ST_QUANT_OMEGA, launch_quantize(k, l, omega, ldo, LRAMM_F32, d.fmt_sketch, 1, Om, P->pOm, sOm, flags, s,
                                           zero + P->mx_Om));

@@ -109,7 +109,10 @@ template <typename T, int FMT>
 __global__ __launch_bounds__(256) void quant_rows_kernel(int64_t rows, int64_t cols, const T* __restrict__ X,
                                                          int64_t ldx, uint8_t* __restrict__ Xq, int64_t pitch,
                                                          int64_t pelems, float* __restrict__ scales,
-                                                         uint32_t* flags, int vec) {
+                                                         uint32_t* flags, int vec, uint32_t* zero,
+                                                             int64_t zero_words) {
+  // a buffer of zero_words words cleared on the way (saves the caller a launch)
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < zero_words; e += (int64_t)gridDim.x * 256) zero[e] = 0u;
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
@@ -334,7 +337,10 @@ template <typename T, int FMT, int NV>
 __global__ __launch_bounds__(256) void quant_rows_reg_kernel(int64_t rows, int64_t cols, const T* __restrict__ X,
                                                              int64_t ldx, uint8_t* __restrict__ Xq, int64_t pitch,
                                                              int64_t pelems, float* __restrict__ scales,
-                                                             uint32_t* flags, int vec) {
+                                                             uint32_t* flags, int vec, uint32_t* zero,
+                                                             int64_t zero_words) {
+  // a buffer of zero_words words cleared on the way (saves the caller a launch)
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < zero_words; e += (int64_t)gridDim.x * 256) zero[e] = 0u;
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
@@ -381,9 +387,9 @@ __global__ __launch_bounds__(256) void quant_rows_reg_kernel(int64_t rows, int64
 template <typename T, int FMT>
 static lramm_status quantize_typed(int64_t rows, int64_t cols, const T* X, int64_t ldx, int transpose, uint8_t* Xq,
                                    int64_t pitch, float* scales, uint32_t* flags, hipStream_t s, uint32_t* amax_ws,
-                                   bool amax_ready) {
+                                   bool amax_ready, uint32_t* zero, int64_t zero_words) {
   if (!transpose) {
-    if (rows == 0) return LRAMM_OK;
+    if (rows == 0) return zero_words > 0 ? fill_u32(zero, 0u, zero_words, s) : LRAMM_OK;
     int64_t pe = pitch_elems(pitch, FMT);
     bool vec = ((uintptr_t)X % (4 * sizeof(T)) == 0) && (ldx % 4 == 0);
     dim3 grid((unsigned)ceil_div(rows, 4));
@@ -391,7 +397,7 @@ static lramm_status quantize_typed(int64_t rows, int64_t cols, const T* X, int64
     const int64_t groups = ceil_div(pe, (int64_t)256);   // 4-element groups per lane
 #define ROWS_REG(NV)                                                                                            \
   hipLaunchKernelGGL((quant_rows_reg_kernel<T, FMT, NV>), grid, dim3(256), 0, s, rows, cols, X, ldx, Xq, pitch, pe, \
-                     scales, flags, v)
+                     scales, flags, v, zero, zero_words)
     if (groups <= 1) ROWS_REG(1);
     else if (groups <= 2) ROWS_REG(2);
     else if (groups <= 4) ROWS_REG(4);
@@ -400,12 +406,13 @@ static lramm_status quantize_typed(int64_t rows, int64_t cols, const T* X, int64
     else if (groups <= 32 && sizeof(T) <= 4) ROWS_REG(32);
     else
       hipLaunchKernelGGL((quant_rows_kernel<T, FMT>), grid, dim3(256), 0, s, rows, cols, X, ldx, Xq, pitch, pe,
-                         scales, flags, v);
+                         scales, flags, v, zero, zero_words);
 #undef ROWS_REG
     LRAMM_HIP(hipGetLastError());
     return LRAMM_OK;
   }
   // column vectors, transposed output: cols x pitch
+  if (zero_words > 0) LRAMM_TRY(fill_u32(zero, 0u, zero_words, s));
   if (cols == 0) return LRAMM_OK;
   const int cvec = ((uintptr_t)X % (4 * sizeof(T)) == 0) && (ldx % 4 == 0) ? 1 : 0;
   if (amax_ws) {
@@ -445,27 +452,28 @@ static lramm_status quantize_typed(int64_t rows, int64_t cols, const T* X, int64
 template <typename T>
 static lramm_status quantize_fmt(int64_t rows, int64_t cols, const T* X, int64_t ldx, int fmt, int transpose,
                                  uint8_t* Xq, int64_t pitch, float* scales, uint32_t* flags, hipStream_t s,
-                                 uint32_t* amax_ws, bool amax_ready) {
+                                 uint32_t* amax_ws, bool amax_ready, uint32_t* zero, int64_t zero_words) {
   switch (fmt) {
-    case LRAMM_INT8: return quantize_typed<T, LRAMM_INT8>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s, amax_ws, amax_ready);
-    case LRAMM_INT4: return quantize_typed<T, LRAMM_INT4>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s, amax_ws, amax_ready);
-    case LRAMM_FP8: return quantize_typed<T, LRAMM_FP8>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s, amax_ws, amax_ready);
-    case LRAMM_BF16F: return quantize_typed<T, LRAMM_BF16F>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s, amax_ws, amax_ready);
+    case LRAMM_INT8: return quantize_typed<T, LRAMM_INT8>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s, amax_ws, amax_ready, zero, zero_words);
+    case LRAMM_INT4: return quantize_typed<T, LRAMM_INT4>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s, amax_ws, amax_ready, zero, zero_words);
+    case LRAMM_FP8: return quantize_typed<T, LRAMM_FP8>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s, amax_ws, amax_ready, zero, zero_words);
+    case LRAMM_BF16F: return quantize_typed<T, LRAMM_BF16F>(rows, cols, X, ldx, transpose, Xq, pitch, scales, flags, s, amax_ws, amax_ready, zero, zero_words);
     default: return LRAMM_E_INVALID;
   }
 }
 
 lramm_status launch_quantize(int64_t rows, int64_t cols, const void* X, int64_t ldx, int xtype, int fmt,
                              int transpose, void* Xq, int64_t pitch, float* scales, uint32_t* flags,
-                             hipStream_t s, uint32_t* amax_ws, bool amax_ready) {
+                             hipStream_t s, uint32_t* amax_ws, bool amax_ready, uint32_t* zero,
+                             int64_t zero_words) {
   uint8_t* q = reinterpret_cast<uint8_t*>(Xq);
   switch (xtype) {
     case LRAMM_F32:
-      return quantize_fmt<float>(rows, cols, (const float*)X, ldx, fmt, transpose, q, pitch, scales, flags, s, amax_ws, amax_ready);
+      return quantize_fmt<float>(rows, cols, (const float*)X, ldx, fmt, transpose, q, pitch, scales, flags, s, amax_ws, amax_ready, zero, zero_words);
     case LRAMM_BF16:
-      return quantize_fmt<uint16_t>(rows, cols, (const uint16_t*)X, ldx, fmt, transpose, q, pitch, scales, flags, s, amax_ws, amax_ready);
+      return quantize_fmt<uint16_t>(rows, cols, (const uint16_t*)X, ldx, fmt, transpose, q, pitch, scales, flags, s, amax_ws, amax_ready, zero, zero_words);
     case LRAMM_F64:
-      return quantize_fmt<double>(rows, cols, (const double*)X, ldx, fmt, transpose, q, pitch, scales, flags, s, amax_ws, amax_ready);
+      return quantize_fmt<double>(rows, cols, (const double*)X, ldx, fmt, transpose, q, pitch, scales, flags, s, amax_ws, amax_ready, zero, zero_words);
     default:
       return LRAMM_E_INVALID;
   }
