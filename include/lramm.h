@@ -87,6 +87,8 @@ typedef enum {
 #define LRAMM_FLAG_NONFINITE 0x1u  /* a quantiser input held NaN or Inf       */
 #define LRAMM_FLAG_BREAKDOWN 0x2u  /* CholeskyQR dropped a dependent column    */
 #define LRAMM_FLAG_SQRTNEG   0x4u  /* a Cholesky pivot was negative / NaN      */
+#define LRAMM_FLAG_STALL     0x8u  /* a wait inside the one-launch Cholesky ran
+                                      past its bound: that factor is not valid */
 
 /*
  * Problem description (paper Alg. 3 inputs A, B, C, r and the bit budgets;
@@ -178,8 +180,8 @@ LRAMM_API lramm_status lramm_backward(lramm_plan* plan, const float* dC, int64_t
 
 /* Synchronise the stream and read the device status word of ws.
  * *flags (nullable) receives the LRAMM_FLAG_* bits; the return value is
- * LRAMM_E_NONFINITE if that bit is set, else LRAMM_OK (breakdown is
- * reported only through *flags). */
+ * LRAMM_E_NONFINITE if that bit is set, else LRAMM_OK (breakdown and
+ * stall are reported only through *flags). */
 LRAMM_API lramm_status lramm_status_poll(const lramm_plan* plan, const void* ws,
                                void* stream, uint32_t* flags);
 

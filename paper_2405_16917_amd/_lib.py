@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "liblramm.so")
 OK, E_INVALID, E_SHAPE, E_RANK, E_WORKSPACE, E_NONFINITE, E_BREAKDOWN, E_OVERFLOW, E_HIP, E_UNSUPPORTED = range(10)
 F32, BF16, F64 = 0, 1, 2
 INT8, INT4, FP8, BF16F = 0, 1, 2, 3
-FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_SQRTNEG = 0x1, 0x2, 0x4
+FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_SQRTNEG, FLAG_STALL = 0x1, 0x2, 0x4, 0x8
 
 FMT = {"int8": INT8, "int4": INT4, "fp8": FP8, "bf16": BF16F}
 DTYPE = {torch.float32: F32, torch.bfloat16: BF16, torch.float64: F64}

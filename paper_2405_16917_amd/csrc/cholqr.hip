@@ -39,6 +39,10 @@ constexpr int NB = 32;   // panel width
 // that a column's atomics spread over several words; readers take the
 // maximum over the copies.
 constexpr int kCmSlices = 8;
+// The workspace's gate area (64 words): word 0 the second pass's gate, words
+// kProgWord .. kProgWord + 2 the progress counters of the one-launch
+// Cholesky, all cleared by the first pass's Gram reduction.
+constexpr int kProgWord = 8;
 
 __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -69,6 +73,16 @@ __device__ __forceinline__ void lower_tile(int t, int& i, int& j) {
   }
   i = di;
   j = t;
+}
+
+// threadIdx.x as a value the compiler may not reuse or move: index
+// arithmetic of the LDS tile helpers then stays where it is used, instead of
+// being hoisted out of the long loops of the one-launch Cholesky and held in
+// registers across them.
+__device__ __forceinline__ int tid_x() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
 }
 
 // ------------------------------------------------------------------ Gram --
@@ -197,6 +211,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int lw, int l_true, in
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (mode == 0) {
     if (e == 0) *gate = 0u;
+    if (e < 3) gate[kProgWord + e] = 0u;   // the Cholesky chain's progress counters
     if (cm1 && e < (int64_t)kCmSlices * lw) cm1[e] = 0u;
   }
   uint32_t bits = 0;
@@ -588,7 +603,7 @@ template <int NEWTON = 2, int NS = NB>
 __device__ __attribute__((always_inline)) inline void factor_block_wave(double* S, double* Xo, double* scratch,
                                                                         const double* thr_s, int col0, int l_true,
                                                                         uint32_t* flags) {
-  const int lane = threadIdx.x & 63;
+  const int lane = tid_x() & 63;
   const int row = lane & 31;
   const bool fac = lane < NB;
   const bool live_col = col0 + row < l_true;
@@ -692,7 +707,7 @@ typedef double Tile[NB][NB + 1];   // an LDS tile, padded rows
 
 // Global 32 x 32 tile (row stride ld) -> LDS, all loads issued first.
 __device__ __forceinline__ void tile_load(double (*dst)[NB + 1], const double* src, int64_t ld) {
-  const int tid = threadIdx.x;
+  const int tid = tid_x();
   double v[NB * NB / 256];
 #pragma unroll
   for (int u = 0; u < NB * NB / 256; ++u) {
@@ -707,7 +722,7 @@ __device__ __forceinline__ void tile_load(double (*dst)[NB + 1], const double* s
 }
 
 __device__ __forceinline__ void tile_store(double* dst, int64_t ld, const double (*src)[NB + 1]) {
-  const int tid = threadIdx.x;
+  const int tid = tid_x();
 #pragma unroll
   for (int u = 0; u < NB * NB / 256; ++u) {
     const int e = tid + 256 * u;
@@ -717,7 +732,7 @@ __device__ __forceinline__ void tile_store(double* dst, int64_t ld, const double
 
 // The lower triangle of an LDS tile, zeros above the diagonal.
 __device__ __forceinline__ void tile_store_lower(double* dst, int64_t ld, const double (*src)[NB + 1]) {
-  const int tid = threadIdx.x;
+  const int tid = tid_x();
 #pragma unroll
   for (int u = 0; u < NB * NB / 256; ++u) {
     const int e = tid + 256 * u;
@@ -729,27 +744,27 @@ __device__ __forceinline__ void tile_store_lower(double* dst, int64_t ld, const 
 // The 16 x 16 sub-tile st = 2 (row half) + (column half) of an LDS tile, in
 // accumulator layout, and the same sub-tile of a product X Y^T.
 __device__ __forceinline__ void sub_put_at(double (*T)[NB + 1], int st, v4d v) {
-  const int lane = threadIdx.x & 63;
+  const int lane = tid_x() & 63;
 #pragma unroll
   for (int r = 0; r < 4; ++r) T[16 * (st >> 1) + 4 * r + (lane >> 4)][16 * (st & 1) + (lane & 15)] = v[r];
 }
 __device__ __forceinline__ v4d sub_get_at(const double (*T)[NB + 1], int st) {
-  const int lane = threadIdx.x & 63;
+  const int lane = tid_x() & 63;
   v4d v;
 #pragma unroll
   for (int r = 0; r < 4; ++r) v[r] = T[16 * (st >> 1) + 4 * r + (lane >> 4)][16 * (st & 1) + (lane & 15)];
   return v;
 }
 __device__ __forceinline__ v4d sub_xyt_at(const double (*X)[NB + 1], const double (*Y)[NB + 1], int st) {
-  const int lane = threadIdx.x & 63;
+  const int lane = tid_x() & 63;
   return tile_xyt(X, Y, st, lane & 15, lane >> 4);
 }
 
 // This wavefront's sub-tile (st = wave index).
-__device__ __forceinline__ void sub_put(double (*T)[NB + 1], v4d v) { sub_put_at(T, threadIdx.x >> 6, v); }
-__device__ __forceinline__ v4d sub_get(const double (*T)[NB + 1]) { return sub_get_at(T, threadIdx.x >> 6); }
+__device__ __forceinline__ void sub_put(double (*T)[NB + 1], v4d v) { sub_put_at(T, tid_x() >> 6, v); }
+__device__ __forceinline__ v4d sub_get(const double (*T)[NB + 1]) { return sub_get_at(T, tid_x() >> 6); }
 __device__ __forceinline__ v4d sub_xyt(const double (*X)[NB + 1], const double (*Y)[NB + 1]) {
-  return sub_xyt_at(X, Y, threadIdx.x >> 6);
+  return sub_xyt_at(X, Y, tid_x() >> 6);
 }
 
 // In place: T <- T Y^T (a product of two LDS tiles written over its left factor).
@@ -1040,6 +1055,416 @@ __global__ __launch_bounds__(256) void chol_panel2_kernel(int lw, int l_true, in
   }
 }
 
+// ------------------------------------------------ one-launch Cholesky chain --
+// The schedule of the launches above as one grid whose workgroups keep a
+// role for the whole factorisation and wait for each other on three
+// progress counters in global memory (prog[0..2]) instead of launch
+// boundaries:
+//   workgroup 0      the diagonal chain: blocks 0 and 1, then for p = 0, 2, ...
+//                    the panel rows i = p + 2, p + 3 and their diagonal blocks
+//                    (the diagonal workgroup's part of launch p); prog[0]
+//                    counts its finished steps, prog[2] the steps whose Dinv_i
+//                    and L_{i+1,i} are out (before block i + 1 is factored);
+//   1 .. ntr         one trailing tile (i, j), 2 <= j <= i, each: the update
+//                    of the tile by panels p, p + 1 for every p it trails
+//                    (the tile stays in LDS between steps); prog[1] counts
+//                    finished (tile, step) pairs;
+//   ntr + 1 ..       one column block jc of X = L^-1, each: row blocks p and
+//                    p + 1 once the diagonal blocks p, p + 1 are factored.
+// Step p of a trailing tile needs diagonal step p - 2 (Dinv_p and L_{p+1,p}
+// for its first half, Dinv_{p+1} for the rest) and trailing step p - 2 (the
+// final panel tiles of its rows).  Diagonal step p + 2 needs trailing step
+// p: wavefronts 1 - 3 of workgroup 0 wait for it and fetch that step's
+// tiles while wavefront 0 factors the second block of step p.  Every
+// workgroup must be resident at once: the host launches it only when the
+// grid fits the compute units (one workgroup per CU by its LDS).  Every wait
+// is bounded; an overrun raises LRAMM_FLAG_STALL (the factor is then not
+// valid) instead of hanging.
+constexpr uint32_t kChainSpin = 1u << 18;
+
+__device__ __forceinline__ void chain_wait(const uint32_t* ctr, uint32_t target, uint32_t* flags) {
+  uint32_t n = 0;
+  while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (++n > kChainSpin) {
+      if (flags && (threadIdx.x & 63) == 0) atomicOr(flags, LRAMM_FLAG_STALL);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// This workgroup's global writes so far made visible, then *ctr += 1.
+__device__ __forceinline__ void chain_signal(uint32_t* ctr) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Trailing tiles of step p (p even): (i, j), p + 2 <= j <= i < T, less the
+// ones the diagonal workgroup owns, (p+2, p+2) and, when p + 3 < T,
+// (p+3, p+2), (p+3, p+3).  chain_done(p) = those of steps 0, 2, .., p.
+__device__ __forceinline__ uint32_t chain_done(int T, int p) {
+  uint32_t s = 0;
+  for (int q = 0; q <= p; q += 2) {
+    const int R = T - q - 2;
+    if (R >= 1) s += (uint32_t)(R * (R + 1) / 2 - (R >= 2 ? 3 : 1));
+  }
+  return s;
+}
+
+// Global 32 x 32 tiles -> LDS by one wavefront: rows 2u, 2u + 1 per step,
+// every load of the NT tiles issued before the first LDS write.
+template <int NT>
+__device__ __forceinline__ void tiles_load_wave(double (*d0)[NB + 1], const double* s0, double (*d1)[NB + 1],
+                                                const double* s1, double (*d2)[NB + 1], const double* s2,
+                                                int64_t ld) {
+  const int lane = tid_x() & 63;
+  const int r = lane >> 5, c = lane & 31;
+  double v[NT][16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int64_t o = (int64_t)(2 * u + r) * ld + c;
+    v[0][u] = s0[o];
+    if (NT > 1) v[NT > 1 ? 1 : 0][u] = s1[o];
+    if (NT > 2) v[NT > 2 ? 2 : 0][u] = s2[o];
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    d0[2 * u + r][c] = v[0][u];
+    if (NT > 1) d1[2 * u + r][c] = v[NT > 1 ? 1 : 0][u];
+    if (NT > 2) d2[2 * u + r][c] = v[NT > 2 ? 2 : 0][u];
+  }
+}
+
+// LDS tile -> global by one wavefront (LOWER: zeros above the diagonal).
+template <bool LOWER>
+__device__ __forceinline__ void tile_store_wave(double* dst, int64_t ld, const double (*src)[NB + 1]) {
+  const int lane = tid_x() & 63;
+  const int r = lane >> 5, c = lane & 31;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int row = 2 * u + r;
+    const double v = src[row][c];
+    dst[(int64_t)row * ld + c] = (!LOWER || c <= row) ? v : 0.0;
+  }
+}
+
+// T[st] -= (X Y^T)[st] for one 16 x 16 sub-tile, by one wavefront.
+__device__ __forceinline__ void sub_sub_xyt(double (*T)[NB + 1], const double (*X)[NB + 1],
+                                            const double (*Y)[NB + 1], int st) {
+  sub_put_at(T, st, sub_get_at(T, st) - sub_xyt_at(X, Y, st));
+}
+
+// Wavefronts 1 - 3 of a workgroup meet: each adds one to *cnt and waits
+// for target (3, 6, .. for the first, second, .. meeting since *cnt was 0).
+__device__ __forceinline__ void meet3(int* cnt, int target) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if ((tid_x() & 63) == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < target) __builtin_amdgcn_s_sleep(1);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// inv_end: X row blocks 0 .. inv_end - 1 are formed (T, or T - 1 when the
+// solve forms the last block of Q1 itself).  prog[0..2] must be zero at the
+// launch.
+//
+// A step of the diagonal workgroup (rows i = p + 2, i + 1; p = -2 for the
+// first two blocks) finds in LDS what the previous step prepared on its idle
+// wavefronts: L_{i,p}, L_{i+1,p} (final), A1' = G_{i,p+1} - L_{i,p} L_{p+1,p}^T,
+// U' = G_ii - L_{i,p} L_{i,p}^T, B1' (the same for row i + 1), V' = G_{i+1,i}
+// - L_{i+1,p} L_{i,p}^T, W' = G_{i+1,i+1} - L_{i+1,p} L_{i+1,p}^T and
+// Dinv_{p+1}.  On the critical path it forms only L_{i,p+1} = A1' Dinv_{p+1}^T
+// and U' - L_{i,p+1} L_{i,p+1}^T, factors block i (wavefront 0; meanwhile
+// wavefronts 1 - 2 finish row i + 1 with Dinv_{p+1} and wavefront 3 writes the
+// finished panel tiles), forms L_{i+1,i} and W, and factors block i + 1; during
+// that factorisation wavefronts 1 - 3 write this step's tiles, wait for
+// trailing step p, fetch the next step's G tiles and apply to them everything
+// that needs only Dinv_i and L_{i+1,i}.
+__global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, double* __restrict__ G,
+                                                         double* __restrict__ L, double* __restrict__ Dinv,
+                                                         double* __restrict__ Xinv,
+                                                         const double* __restrict__ diag0, double tol,
+                                                         uint32_t* flags, uint32_t* prog, int inv_end) {
+  __shared__ Tile pool[12];
+  __shared__ __align__(16) double lscratch[kFactorScratch];
+  __shared__ int s_cnt, s_cnt3, s_item;
+  __shared__ double lthr[2][2 * NB];
+  const int T = lw / NB;
+  const int ntr = T > 2 ? (T - 2) * (T - 1) / 2 : 0;
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6;
+
+  if (b > ntr) {
+    // ---- column block jc of X
+    const int jc = b - 1 - ntr;
+    for (int p = 0; p < inv_end; p += 2) {
+      // z = 0 opaque to the compiler (as in the diagonal chain below)
+      int z = 0;
+      asm volatile("" : "+s"(z));
+      Tile* P = pool + z;
+      const int lwz = lw + z;
+      const int nrows = inv_end - p < 2 ? inv_end - p : 2;
+      if (jc > p + nrows - 1) continue;
+      chain_wait(&prog[0], (uint32_t)(p / 2 + 1), flags);
+      inverse_rows(lwz, p, nrows, jc, L, Dinv, Xinv, P[7], P[3], P[4], P[5], P[6]);
+    }
+    return;
+  }
+
+  if (b > 0) {
+    // ---- trailing tile (i, j)
+    int di, dj;
+    lower_tile(b - 1, di, dj);
+    const int i = 2 + di, j = 2 + dj;
+    const int p_last = ((j - 2) / 2) * 2;
+    const bool owned_last = (j % 2 == 0) ? (i == j || i == j + 1) : (i == j);
+    const int last = owned_last ? p_last - 2 : p_last;
+    const bool other = j != i;
+    for (int p = 0; p <= last; p += 2) {
+      // z = 0 opaque to the compiler (as in the diagonal chain below)
+      int z = 0;
+      asm volatile("" : "+s"(z));
+      Tile* P = pool + z;
+      double (*sD0)[NB + 1] = P[0], (*sD1)[NB + 1] = P[1], (*sL10)[NB + 1] = P[2];
+      double (*sA0)[NB + 1] = P[3], (*sA1)[NB + 1] = P[4], (*sB0)[NB + 1] = P[5];
+      double (*sB1)[NB + 1] = P[6], (*sU)[NB + 1] = P[7];
+      const int lwz = lw + z;
+      // first half: Dinv_p and L_{p+1,p} (published before the diagonal
+      // workgroup factors block p + 1), then Dinv_{p+1}
+      chain_wait(&prog[2], (uint32_t)(p / 2 + 1), flags);
+      if (p >= 2) chain_wait(&prog[1], chain_done(T, p - 2), flags);
+      const double* Dp = Dinv + (int64_t)p * NB * NB;
+      tile_load(sD0, Dp, NB);
+      tile_load(sL10, L + (int64_t)(p + 1) * NB * lwz + p * NB, lwz);
+      tile_load(sA0, G + (int64_t)i * NB * lwz + p * NB, lwz);
+      tile_load(sA1, G + (int64_t)i * NB * lwz + (p + 1) * NB, lwz);
+      if (other) {
+        tile_load(sB0, G + (int64_t)j * NB * lwz + p * NB, lwz);
+        tile_load(sB1, G + (int64_t)j * NB * lwz + (p + 1) * NB, lwz);
+      }
+      if (p == 0) tile_load(sU, G + (int64_t)i * NB * lwz + j * NB, lwz);
+      __syncthreads();
+      {
+        const v4d a = sub_xyt(sA0, sD0);
+        const v4d c = other ? sub_xyt(sB0, sD0) : a;
+        __syncthreads();
+        sub_put(sA0, a);
+        if (other) sub_put(sB0, c);
+      }
+      __syncthreads();
+      sub_put(sA1, sub_get(sA1) - sub_xyt(sA0, sL10));
+      if (other) sub_put(sB1, sub_get(sB1) - sub_xyt(sB0, sL10));
+      chain_wait(&prog[0], (uint32_t)(p / 2 + 1), flags);
+      tile_load(sD1, Dp + NB * NB, NB);
+      __syncthreads();
+      {
+        const v4d a = sub_xyt(sA1, sD1);
+        const v4d c = other ? sub_xyt(sB1, sD1) : a;
+        __syncthreads();
+        sub_put(sA1, a);
+        if (other) sub_put(sB1, c);
+      }
+      __syncthreads();
+      const double (*J0)[NB + 1] = other ? sB0 : sA0;
+      const double (*J1)[NB + 1] = other ? sB1 : sA1;
+      sub_put(sU, sub_get(sU) - (sub_xyt(sA0, J0) + sub_xyt(sA1, J1)));
+      __syncthreads();
+      if (j == p + 2) {
+        tile_store(L + (int64_t)i * NB * lwz + p * NB, lwz, sA0);
+        tile_store(L + (int64_t)i * NB * lwz + (p + 1) * NB, lwz, sA1);
+      }
+      if (p == last) tile_store(G + (int64_t)i * NB * lwz + j * NB, lwz, sU);
+      chain_signal(&prog[1]);
+    }
+    return;
+  }
+
+  // ---- the diagonal chain.  Slots A0 .. U keep their role; the others
+  // change role between steps (Dinv_{i+1} becomes the next Dinv_{p+1}, the
+  // next row pair's G_{in+1,in} and G_{in+1,in+1} the next V and W).
+  enum { kA0 = 0, kA1 = 1, kB0 = 2, kB1 = 3, kU = 4 };
+  int rD1 = 5, rD0 = 6, rX = 7, rV = 8, rW = 9, rPV = 10, rPW = 11, cur = 0;
+  if (tid < 2 * NB) lthr[0][tid] = pivot_thr(diag0, tid, l_true, tol);
+  tile_load(pool[kU], G, lw);
+  if (T > 1) {
+    tile_load(pool[rV], G + (int64_t)NB * lw, lw);
+    tile_load(pool[rW], G + (int64_t)NB * lw + NB, lw);
+  }
+  for (int p = -2;; p += 2) {
+    // z = 0, opaque to the compiler: the LDS tile addresses and row strides
+    // below are then formed inside the loop instead of hundreds of address
+    // values being hoisted out of it and held in registers across the chain
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    Tile* P = pool + z;
+    double (*A0)[NB + 1] = P[kA0], (*A1)[NB + 1] = P[kA1], (*B0)[NB + 1] = P[kB0], (*B1)[NB + 1] = P[kB1];
+    double (*U)[NB + 1] = P[kU], (*D1)[NB + 1] = P[rD1], (*D0)[NB + 1] = P[rD0], (*X)[NB + 1] = P[rX];
+    double (*V)[NB + 1] = P[rV], (*W)[NB + 1] = P[rW], (*PV)[NB + 1] = P[rPV], (*PW)[NB + 1] = P[rPW];
+    double* scratch = lscratch + z;
+    double* thr = &lthr[cur][0] + z;
+    double* thrn = &lthr[cur ^ 1][0] + z;
+    const int lwz = lw + z;
+    const int i = p + 2;
+    const bool two = i + 1 < T;
+    if (tid == 0) {
+      s_cnt = 0;
+      s_cnt3 = 0;
+      s_item = 0;
+    }
+    __syncthreads();
+    if (p >= 0) {
+      // L_{i,p+1} = A1' Dinv_{p+1}^T, then U = U' - L_{i,p+1} L_{i,p+1}^T
+      {
+        const v4d a = sub_xyt(A1, D1);
+        __syncthreads();
+        sub_put(A1, a);
+      }
+      __syncthreads();
+      sub_put(U, sub_get(U) - sub_xyt(A1, A1));
+      __syncthreads();
+    }
+    if (wave == 0) {
+      factor_block<1>(&U[0][0], &X[0][0], scratch, thr, i * NB, l_true, flags);
+    } else if (p >= 0 && wave == 3) {
+      // the finished panel tiles of rows i and i + 1
+      tile_store_wave<false>(L + (int64_t)i * NB * lwz + p * NB, lwz, A0);
+      tile_store_wave<false>(L + (int64_t)i * NB * lwz + (p + 1) * NB, lwz, A1);
+      if (two) tile_store_wave<false>(L + (int64_t)(i + 1) * NB * lwz + p * NB, lwz, B0);
+    } else if (p >= 0 && two) {
+      // wavefronts 1 and 2: row i + 1, rows 16 h .. 16 h + 15 each (h = wave
+      // - 1): L_{i+1,p+1} = B1' Dinv_{p+1}^T and V' - L_{i+1,p+1} L_{i,p+1}^T
+      // need only these rows; W needs both halves and waits for the other
+      const int h = wave - 1;
+      const v4d c0 = sub_xyt_at(B1, D1, 2 * h), c1 = sub_xyt_at(B1, D1, 2 * h + 1);
+      sub_put_at(B1, 2 * h, c0);
+      sub_put_at(B1, 2 * h + 1, c1);
+      sub_sub_xyt(V, B1, A1, 2 * h);
+      sub_sub_xyt(V, B1, A1, 2 * h + 1);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if ((tid & 63) == 0) __hip_atomic_fetch_add(&s_cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      while (__hip_atomic_load(&s_cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < 2) __builtin_amdgcn_s_sleep(1);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      // the lower sub-tiles of W (the factor reads no entry above the diagonal)
+      sub_sub_xyt(W, B1, B1, h == 0 ? 0 : 2);
+      if (h == 0) sub_sub_xyt(W, B1, B1, 3);
+    }
+    __syncthreads();
+    if (!two) {
+      tile_store_lower(L + (int64_t)i * NB * lwz + i * NB, lwz, U);
+      tile_store(Dinv + (int64_t)i * NB * NB, NB, X);
+      chain_signal(&prog[0]);
+      return;
+    }
+    tile_mul_t_inplace(V, X);                    // L_{i+1,i}
+    __syncthreads();
+    sub_put(W, sub_get(W) - sub_xyt(V, V));
+    __syncthreads();
+    const int in = i + 2;                        // the next step's first row
+    const bool two_n = in + 1 < T;
+    // the updates by the panel column i (V = L_{i+1,i}) of the next row pair:
+    // A1', U', and for row in + 1 B1', V', W' (lower sub-tiles of U' and W'
+    // only), one 16 x 16 sub-tile per item, items claimed by the wavefronts
+    // in turn (wavefront 0 joins once its factorisation is done)
+    auto stage2 = [&]() {
+      const int n2 = two_n ? 18 : 7;
+      for (;;) {
+        int q = 0;
+        if ((tid & 63) == 0) q = __hip_atomic_fetch_add(&s_item, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        q = __builtin_amdgcn_readfirstlane(q);
+        if (q >= n2) break;
+        if (q < 4)
+          sub_sub_xyt(A1, A0, V, q);
+        else if (q < 7)
+          sub_sub_xyt(U, A0, A0, q == 4 ? 0 : q - 3);
+        else if (q < 11)
+          sub_sub_xyt(B1, B0, V, q - 7);
+        else if (q < 15)
+          sub_sub_xyt(PV, B0, A0, q - 11);
+        else
+          sub_sub_xyt(PW, B0, B0, q == 15 ? 0 : q - 14);
+      }
+    };
+    if (wave == 0) {
+      factor_block<1>(&W[0][0], &D0[0][0], scratch, thr + NB, (i + 1) * NB, l_true, flags);
+      if (in < T) {
+        while (__hip_atomic_load(&s_cnt3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < 9)
+          __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        stage2();
+      }
+    } else {
+      // this step's finished tiles, each written by the wavefront that
+      // refills its slot below; wavefront 1 publishes Dinv_i and L_{i+1,i}
+      // at once (the first half of trailing step p + 2 needs only these)
+      const int pn = i;
+      const double* Gi = G + (int64_t)in * NB * lwz;
+      const double* Gn = Gi + (int64_t)NB * lwz;
+      if (wave == 1) {
+        tile_store_wave<false>(Dinv + (int64_t)i * NB * NB, NB, X);
+        tile_store_wave<false>(L + (int64_t)(i + 1) * NB * lwz + i * NB, lwz, V);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if ((tid & 63) == 0) __hip_atomic_fetch_add(&prog[2], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else if (wave == 2) {
+        tile_store_wave<true>(L + (int64_t)i * NB * lwz + i * NB, lwz, U);
+        if (p >= 0) tile_store_wave<false>(L + (int64_t)(i + 1) * NB * lwz + (p + 1) * NB, lwz, B1);
+      }
+      if (in < T) {
+        // the next step's G tiles, final once trailing step p is done
+        if (p >= 0) chain_wait(&prog[1], chain_done(T, p), flags);
+        if (wave == 3) {
+          tiles_load_wave<2>(A0, Gi + pn * NB, A1, Gi + (pn + 1) * NB, A1, nullptr, lwz);
+          thrn[tid - 192] = pivot_thr(diag0, in * NB + (tid - 192), l_true, tol);
+        } else if (wave == 2) {
+          if (two_n)
+            tiles_load_wave<3>(U, Gi + in * NB, B0, Gn + pn * NB, B1, Gn + (pn + 1) * NB, lwz);
+          else
+            tiles_load_wave<1>(U, Gi + in * NB, U, nullptr, U, nullptr, lwz);
+        } else if (two_n) {
+          tiles_load_wave<2>(PV, Gn + in * NB, PW, Gn + (in + 1) * NB, PW, nullptr, lwz);
+        }
+        meet3(&s_cnt3, 3);
+        // L_{in,pn} = G_{in,pn} Dinv_pn^T (and row in + 1), in place: every
+        // product first, then the writes
+        const int n1 = two_n ? 8 : 4;
+        v4d r1[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          const int q = wave - 1 + 3 * u;
+          if (q < n1) r1[u] = sub_xyt_at(q < 4 ? A0 : B0, X, q & 3);
+        }
+        meet3(&s_cnt3, 6);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          const int q = wave - 1 + 3 * u;
+          if (q < n1) sub_put_at(q < 4 ? A0 : B0, q & 3, r1[u]);
+        }
+        meet3(&s_cnt3, 9);
+        stage2();
+      }
+    }
+    __syncthreads();
+    tile_store_lower(L + (int64_t)(i + 1) * NB * lwz + (i + 1) * NB, lwz, W);
+    tile_store(Dinv + (int64_t)(i + 1) * NB * NB, NB, D0);
+    if (in >= T) {
+      chain_signal(&prog[0]);
+      return;
+    }
+    // Dinv_{i+1} is the next step's Dinv_{p+1}; G_{in+1,in}', G_{in+1,in+1}' its V, W
+    int t = rD1;
+    rD1 = rD0;
+    rD0 = t;
+    t = rV;
+    rV = rPV;
+    rPV = t;
+    t = rW;
+    rW = rPW;
+    rPW = t;
+    cur ^= 1;
+    chain_signal(&prog[0]);
+  }
+}
+
 // One wavefront: acc[si][sj] (16 x 16 sub-tiles) += X[32 x 32] Y[32 x 32]^T,
 // X and Y row-major in global memory (L2-resident), K = 32.
 __device__ __forceinline__ void wave_tile_xyt(const double* X, int64_t ldx, const double* Y, int64_t ldy, int li,
@@ -1277,6 +1702,7 @@ __global__ __launch_bounds__(256) void series_kernel(int lw, int l_true, double*
 struct CholWs {
   double *G, *L, *Dinv, *diag0, *part, *W, *X;
   uint32_t* gate;
+  uint32_t* prog;  // the chain kernel's three progress counters (gate + kProgWord)
   uint32_t* cm1;   // column maxima of fl32(|Q1|) (first pass), kCmSlices copies of lw words
   int nchunks;
   int64_t rows_per_chunk;
@@ -1340,7 +1766,20 @@ static lramm_status gram(int64_t rows, int lw, int l_true, const T* X, int64_t l
   return LRAMM_OK;
 }
 
-// Cholesky of w.G into w.L, w.Dinv and X = L^-1 (one launch per two panels).
+// Workgroups the chain kernel may use: the compute units less a margin, so
+// that all of them are resident at once (its LDS allows one per CU).
+static int chain_grid_limit() {
+  static const int lim = [] {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cus - 16;
+  }();
+  return lim;
+}
+
+// Cholesky of w.G into w.L, w.Dinv and X = L^-1: the one-launch chain, or
+// (a grid too large to be resident at once) one launch per two panels.
 // With skip_last_row (an odd block count whose last row block of X would
 // need a launch of its own) that row block is left out: the solve forms the
 // last block of Q1 from the others instead.
@@ -1348,6 +1787,18 @@ static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32
                                      const TimingHook* hook, bool skip_last_row) {
   const double tol = 64.0 * (double)l_true * 0x1p-53;
   const int Tn = lw / NB;
+  // one launch when every workgroup of the chain can be resident at once
+  const int chain_grid = 1 + (Tn > 2 ? (Tn - 2) * (Tn - 1) / 2 : 0) + Tn;
+  if (chain_grid <= chain_grid_limit()) {
+    const int inv_end = (skip_last_row && Tn % 2 == 1) ? Tn - 1 : Tn;
+    {
+      HookScope hs(hook, SUB_CHOL_PANEL, 1);
+      hipLaunchKernelGGL(chol_chain_kernel, dim3(chain_grid), dim3(256), 0, s, lw, l_true, w.G, w.L, w.Dinv, w.X,
+                         w.diag0, tol, flags, w.prog, inv_end);
+    }
+    LRAMM_HIP(hipGetLastError());
+    return LRAMM_OK;
+  }
   int p = 0;
   {
     // one timing pair over the whole chain of dependent launches
@@ -1427,6 +1878,7 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   w.part = p;
   p += (size_t)nc * sq;
   w.gate = reinterpret_cast<uint32_t*>(p);
+  w.prog = w.gate + kProgWord;
   p += 32;
   w.cm1 = reinterpret_cast<uint32_t*>(p);
   w.nchunks = nc;
