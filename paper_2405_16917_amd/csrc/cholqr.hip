@@ -1307,6 +1307,10 @@ __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, dou
     const int lwz = lw + z;
     const int i = p + 2;
     const bool two = i + 1 < T;
+    const int in = i + 2;                        // the next step's first row
+    const bool two_n = in + 1 < T;
+    const double* Gi = G + (int64_t)in * NB * lwz;
+    const double* Gn = Gi + (int64_t)NB * lwz;
     if (tid == 0) {
       s_cnt = 0;
       s_cnt3 = 0;
@@ -1326,11 +1330,20 @@ __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, dou
     }
     if (wave == 0) {
       factor_block<1>(&U[0][0], &X[0][0], scratch, thr, i * NB, l_true, flags);
-    } else if (p >= 0 && wave == 3) {
-      // the finished panel tiles of rows i and i + 1
-      tile_store_wave<false>(L + (int64_t)i * NB * lwz + p * NB, lwz, A0);
-      tile_store_wave<false>(L + (int64_t)i * NB * lwz + (p + 1) * NB, lwz, A1);
-      if (two) tile_store_wave<false>(L + (int64_t)(i + 1) * NB * lwz + p * NB, lwz, B0);
+    } else if (wave == 3) {
+      // the finished panel tiles of rows i and i + 1; then, once trailing
+      // step p is done, the next row pair's G tiles that go to free slots
+      // (the barrier after this factorisation passes the wait on to the
+      // other wavefronts)
+      if (p >= 0) {
+        tile_store_wave<false>(L + (int64_t)i * NB * lwz + p * NB, lwz, A0);
+        tile_store_wave<false>(L + (int64_t)i * NB * lwz + (p + 1) * NB, lwz, A1);
+        if (two) tile_store_wave<false>(L + (int64_t)(i + 1) * NB * lwz + p * NB, lwz, B0);
+      }
+      if (two && in < T) {
+        if (p >= 0) chain_wait(&prog[1], chain_done(T, p), flags);
+        if (two_n) tiles_load_wave<2>(PV, Gn + in * NB, PW, Gn + (in + 1) * NB, PW, nullptr, lwz);
+      }
     } else if (p >= 0 && two) {
       // wavefronts 1 and 2: row i + 1, rows 16 h .. 16 h + 15 each (h = wave
       // - 1): L_{i+1,p+1} = B1' Dinv_{p+1}^T and V' - L_{i+1,p+1} L_{i,p+1}^T
@@ -1360,8 +1373,6 @@ __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, dou
     __syncthreads();
     sub_put(W, sub_get(W) - sub_xyt(V, V));
     __syncthreads();
-    const int in = i + 2;                        // the next step's first row
-    const bool two_n = in + 1 < T;
     // the updates by the panel column i (V = L_{i+1,i}) of the next row pair:
     // A1', U', and for row in + 1 B1', V', W' (lower sub-tiles of U' and W'
     // only), one 16 x 16 sub-tile per item, items claimed by the wavefronts
@@ -1387,6 +1398,8 @@ __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, dou
     };
     if (wave == 0) {
       factor_block<1>(&W[0][0], &D0[0][0], scratch, thr + NB, (i + 1) * NB, l_true, flags);
+      tile_store_wave<true>(L + (int64_t)(i + 1) * NB * lwz + (i + 1) * NB, lwz, W);
+      tile_store_wave<false>(Dinv + (int64_t)(i + 1) * NB * NB, NB, D0);
       if (in < T) {
         while (__hip_atomic_load(&s_cnt3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < 9)
           __builtin_amdgcn_s_sleep(1);
@@ -1398,8 +1411,6 @@ __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, dou
       // refills its slot below; wavefront 1 publishes Dinv_i and L_{i+1,i}
       // at once (the first half of trailing step p + 2 needs only these)
       const int pn = i;
-      const double* Gi = G + (int64_t)in * NB * lwz;
-      const double* Gn = Gi + (int64_t)NB * lwz;
       if (wave == 1) {
         tile_store_wave<false>(Dinv + (int64_t)i * NB * NB, NB, X);
         tile_store_wave<false>(L + (int64_t)(i + 1) * NB * lwz + i * NB, lwz, V);
@@ -1410,8 +1421,8 @@ __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, dou
         if (p >= 0) tile_store_wave<false>(L + (int64_t)(i + 1) * NB * lwz + (p + 1) * NB, lwz, B1);
       }
       if (in < T) {
-        // the next step's G tiles, final once trailing step p is done
-        if (p >= 0) chain_wait(&prog[1], chain_done(T, p), flags);
+        // the rest of the next step's G tiles (trailing step p was waited
+        // for by wavefront 3 before the last barrier)
         if (wave == 3) {
           tiles_load_wave<2>(A0, Gi + pn * NB, A1, Gi + (pn + 1) * NB, A1, nullptr, lwz);
           thrn[tid - 192] = pivot_thr(diag0, in * NB + (tid - 192), l_true, tol);
@@ -1420,8 +1431,6 @@ __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, dou
             tiles_load_wave<3>(U, Gi + in * NB, B0, Gn + pn * NB, B1, Gn + (pn + 1) * NB, lwz);
           else
             tiles_load_wave<1>(U, Gi + in * NB, U, nullptr, U, nullptr, lwz);
-        } else if (two_n) {
-          tiles_load_wave<2>(PV, Gn + in * NB, PW, Gn + (in + 1) * NB, PW, nullptr, lwz);
         }
         meet3(&s_cnt3, 3);
         // L_{in,pn} = G_{in,pn} Dinv_pn^T (and row in + 1), in place: every
@@ -1444,8 +1453,6 @@ __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, dou
       }
     }
     __syncthreads();
-    tile_store_lower(L + (int64_t)(i + 1) * NB * lwz + (i + 1) * NB, lwz, W);
-    tile_store(Dinv + (int64_t)(i + 1) * NB * NB, NB, D0);
     if (in >= T) {
       chain_signal(&prog[0]);
       return;
