@@ -1094,11 +1094,13 @@ __device__ __forceinline__ void chain_wait(const uint32_t* ctr, uint32_t target,
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
-// This workgroup's global writes so far made visible, then *ctr += 1.
+// This workgroup's global writes so far made visible, then *ctr += 1: every
+// wavefront's agent-scope release (its stores written back and complete)
+// comes before the barrier, so the counter moves only after all of them.
 __device__ __forceinline__ void chain_signal(uint32_t* ctr) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Trailing tiles of step p (p even): (i, j), p + 2 <= j <= i < T, less the
@@ -1415,7 +1417,7 @@ __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, dou
         tile_store_wave<false>(Dinv + (int64_t)i * NB * NB, NB, X);
         tile_store_wave<false>(L + (int64_t)(i + 1) * NB * lwz + i * NB, lwz, V);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if ((tid & 63) == 0) __hip_atomic_fetch_add(&prog[2], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if ((tid & 63) == 0) __hip_atomic_fetch_add(&prog[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else if (wave == 2) {
         tile_store_wave<true>(L + (int64_t)i * NB * lwz + i * NB, lwz, U);
         if (p >= 0) tile_store_wave<false>(L + (int64_t)(i + 1) * NB * lwz + (p + 1) * NB, lwz, B1);
