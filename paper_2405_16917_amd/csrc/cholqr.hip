@@ -7,8 +7,10 @@
 //                                      the chunk; partials summed in a fixed
 //                                      order (deterministic)
 //   G1 = L L^T, X = L^-1              blocked right-looking Cholesky, 32 x 32
-//                                      tiles, one launch per panel; the block
-//                                      inverse is formed in the same launches
+//                                      tiles, with the block inverse, in one
+//                                      launch whose workgroups wait on progress
+//                                      counters (one launch per two panels
+//                                      when its grid cannot be resident)
 //   Q1 = Y X^T                         tall-skinny FP64 product
 //   G2 = Q1^T Q1 = I + E,  Q = Q1 (chol(G2))^-T   second pass, restoring the
 //                                      orthogonality lost to cond(Y)^2 u (see
