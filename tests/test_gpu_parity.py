@@ -294,9 +294,10 @@ def test_cholqr2_matches_householder(lib, case):
     assert int(flags.item()) == 0
 
 
-# (l, dependent column): a full sweep of block 0, and the half sweep of a last
-# block whose second half is padding (l = 40: columns 32..39 live)
-@pytest.mark.parametrize("l,dead", [(50, 7), (40, 35)])
+# (l, dependent column): the first half of block 0, the half sweep of a last
+# block whose second half is padding (l = 40: columns 32..39 live), and the
+# second half of a block in the first, second and a later diagonal step
+@pytest.mark.parametrize("l,dead", [(50, 7), (40, 35), (64, 20), (90, 52), (130, 115)])
 def test_cholqr2_f64_input_and_rank_deficiency(lib, l, dead):
     rng = np.random.default_rng(9)
     Y = rng.standard_normal((400, l))
