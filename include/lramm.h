@@ -42,6 +42,13 @@
  *   - No exception or abort crosses this ABI.  A plan is not re-entrant on
  *     concurrent streams.  Identical inputs, seed and plan give bit-identical
  *     results.
+ *   - The Cholesky inside CholeskyQR2 (lramm_forward, lramm_cholqr2) runs
+ *     as one launch whose workgroups wait on one another, and needs all of
+ *     them on the GPU at once.  Calls whose such launches overlap on
+ *     several streams can keep each other's workgroups waiting: the waits
+ *     are bounded, and an overrun sets LRAMM_FLAG_STALL (that result is not
+ *     valid).  lramm_batched_forward on more than one stream uses launches
+ *     whose workgroups never wait instead.
  */
 #ifndef LRAMM_H
 #define LRAMM_H

@@ -969,7 +969,9 @@ __global__ __launch_bounds__(256) void chol_panel2_kernel(int lw, int l_true, in
     __syncthreads();
     tile_store(L + (int64_t)i * NB * lw + p * NB, lw, sA0);
     tile_store(L + (int64_t)i * NB * lw + (p + 1) * NB, lw, sA1);
-    sub_put(sU, sub_get(sU) - (sub_xyt(sA0, sA0) + sub_xyt(sA1, sA1)));
+    // (G_ii - L_{i,p} L_{i,p}^T) - L_{i,p+1} L_{i,p+1}^T: the one-launch chain's
+    // order, so that both schedules give the same factor bit for bit
+    sub_put(sU, (sub_get(sU) - sub_xyt(sA0, sA0)) - sub_xyt(sA1, sA1));
     __syncthreads();
     if (wave == 0) {
       factor_block<1>(&sU[0][0], &sX[0][0], scratch, s_thr, i * NB, l_true, flags);
@@ -995,15 +997,15 @@ __global__ __launch_bounds__(256) void chol_panel2_kernel(int lw, int l_true, in
 #pragma unroll
       for (int c = 0; c < 2; ++c)
         sub_put_at(sV, 2 * h + c,
-                   sub_get_at(sV, 2 * h + c) - (sub_xyt_at(sB0, sA0, 2 * h + c) + sub_xyt_at(sB1, sA1, 2 * h + c)));
+                   (sub_get_at(sV, 2 * h + c) - sub_xyt_at(sB0, sA0, 2 * h + c)) - sub_xyt_at(sB1, sA1, 2 * h + c));
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_add(&s_cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       while (__hip_atomic_load(&s_cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < 2) __builtin_amdgcn_s_sleep(1);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       // the lower sub-tiles of G_{i+1,i+1} (the factor reads no entry above the diagonal)
       const int st0 = h == 0 ? 0 : 2;
-      sub_put_at(sW, st0, sub_get_at(sW, st0) - (sub_xyt_at(sB0, sB0, st0) + sub_xyt_at(sB1, sB1, st0)));
-      if (h == 0) sub_put_at(sW, 3, sub_get_at(sW, 3) - (sub_xyt_at(sB0, sB0, 3) + sub_xyt_at(sB1, sB1, 3)));
+      sub_put_at(sW, st0, (sub_get_at(sW, st0) - sub_xyt_at(sB0, sB0, st0)) - sub_xyt_at(sB1, sB1, st0));
+      if (h == 0) sub_put_at(sW, 3, (sub_get_at(sW, 3) - sub_xyt_at(sB0, sB0, 3)) - sub_xyt_at(sB1, sB1, 3));
     }
     __syncthreads();
     tile_store_lower(L + (int64_t)i * NB * lw + i * NB, lw, sU);
@@ -1795,12 +1797,12 @@ static int chain_grid_limit() {
 // need a launch of its own) that row block is left out: the solve forms the
 // last block of Q1 from the others instead.
 static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32_t* flags, hipStream_t s,
-                                     const TimingHook* hook, bool skip_last_row) {
+                                     const TimingHook* hook, bool skip_last_row, bool one_launch) {
   const double tol = 64.0 * (double)l_true * 0x1p-53;
   const int Tn = lw / NB;
   // one launch when every workgroup of the chain can be resident at once
   const int chain_grid = 1 + (Tn > 2 ? (Tn - 2) * (Tn - 1) / 2 : 0) + Tn;
-  if (chain_grid <= chain_grid_limit()) {
+  if (one_launch && chain_grid <= chain_grid_limit()) {
     const int inv_end = (skip_last_row && Tn % 2 == 1) ? Tn - 1 : Tn;
     {
       HookScope hs(hook, SUB_CHOL_PANEL, 1);
@@ -1864,7 +1866,7 @@ static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t l
 
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
                             int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s,
-                            const TimingHook* hook, uint32_t* colmax) {
+                            const TimingHook* hook, uint32_t* colmax, bool one_launch) {
   if (rows == 0 || l == 0) return LRAMM_OK;
   int lw, nc;
   int64_t rpc;
@@ -1906,12 +1908,12 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   const double* Dlast = solve_last ? w.Dinv + (size_t)(Tn1 - 1) * NB * NB : nullptr;
   if (ytype == LRAMM_F32) {
     LRAMM_TRY(gram<float>(rows, lw, lt, (const float*)Y, ldy, w, 0, s, hook));
-    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last));
+    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last, one_launch));
     LRAMM_TRY((tsmul<float, false>(rows, lw, lt, (const float*)Y, ldy, w.X, Q, ldq, zero_to, s, hook, cm1, nullptr,
                                    Ltri, Dlast, lw)));
   } else if (ytype == LRAMM_F64) {
     LRAMM_TRY(gram<double>(rows, lw, lt, (const double*)Y, ldy, w, 0, s, hook));
-    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last));
+    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last, one_launch));
     LRAMM_TRY((tsmul<double, false>(rows, lw, lt, (const double*)Y, ldy, w.X, Q, ldq, zero_to, s, hook, cm1,
                                     nullptr, Ltri, Dlast, lw)));
   } else {

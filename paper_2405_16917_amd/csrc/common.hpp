@@ -181,10 +181,13 @@ struct TimingHook {
 enum { SUB_CHOL_GRAM = 17, SUB_CHOL_PANEL = 18, SUB_CHOL_SOLVE = 19, SUB_CHOL_SERIES = 20, SUB_CHOL_APPLY = 21 };
 
 // colmax (nullable, caller-zeroed, ldq entries): column maxima of fl32(|Q|)
-// as bit patterns, accumulated while Q is written.
+// as bit patterns, accumulated while Q is written.  one_launch: the Cholesky
+// may run as one launch whose workgroups wait on each other (false where
+// several such launches may overlap, as in a batch on several streams).
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
                             int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s,
-                            const TimingHook* hook = nullptr, uint32_t* colmax = nullptr);
+                            const TimingHook* hook = nullptr, uint32_t* colmax = nullptr,
+                            bool one_launch = true);
 size_t cholqr2_workspace(int64_t rows, int64_t l);
 
 lramm_status launch_dense_gemm_nt(int64_t M, int64_t N, int64_t K, int dtype, const void* L, int64_t ldl,

@@ -25,6 +25,7 @@
 
 struct lramm_plan {
   lramm_desc d;
+  bool one_launch_chol = true;   // cleared while a batch issues the plan on one of several streams
   int64_t l, lp;            // sketch width and its 32-padded leading dimension
   // workspace offsets (bytes)
   size_t off_flags;
@@ -420,7 +421,8 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
            launch_quantize(m, k, A, lda, d.a_type, d.fmt_proj, 1, Ac, P->pAc, sAc, flags, s2, mxA));
   TIMED_ON(s2, ST_QUANT_B, launch_quantize(k, n, B, ldb, d.b_type, d.fmt_g1, 1, Bc, P->pBc, sBc, flags, s2, mxB));
   if (P->side) LRAMM_HIP(hipEventRecord(P->ev_join, P->side));
-  TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(0)));
+  TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(0),
+                                   P->one_launch_chol));
   uint8_t* Qc = at<uint8_t>(W, P->off_Qc);
   float* sQc = at<float>(W, P->off_sQc);
   if (P->side) LRAMM_HIP(hipStreamWaitEvent(s, P->ev_join, 0));   // join: A_c and B_c ready
@@ -433,13 +435,15 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
           launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s, mxQ(it), true));
     TIMED(ST_POWER_Z, launch_gemm_nt(k, l, m, d.fmt_proj, Ac, P->pAc, sAc, Qc, P->pQc, sQc, 1.0f, 0.0f, Z, lp,
                                      LRAMM_F32, nullptr, 0, split, sb, s));
-    TIMED(ST_CHOLQR2, launch_cholqr2(k, l, Z, lp, LRAMM_F32, QZ, lp, cws, P->chol_bytes, flags, s, hk, mxQZ(it)));
+    TIMED(ST_CHOLQR2, launch_cholqr2(k, l, Z, lp, LRAMM_F32, QZ, lp, cws, P->chol_bytes, flags, s, hk, mxQZ(it),
+                                     P->one_launch_chol));
     TIMED(ST_QUANT_QZ,
           launch_quantize(k, l, QZ, lp, LRAMM_F64, d.fmt_sketch, 1, QZc, P->pQZc, sQZc, flags, s, mxQZ(it), true));
     TIMED(ST_POWER_Y, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, P->pAr, sAr, QZc, P->pQZc, sQZc, 1.0f, 0.0f, Y, lp,
                                      LRAMM_F32, nullptr, 0, split, sb, s));
     TIMED(ST_CHOLQR2,
-          launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(it + 1)));
+          launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(it + 1),
+                         P->one_launch_chol));
   }
   // projection Bt = Q^T A  (l x k)
   float* Bt = at<float>(W, P->off_Bt);
@@ -587,10 +591,18 @@ lramm_status batch_issue(lramm_batch* b, const void* const* A, const int64_t* ld
                          const int64_t* ldb, void* const* C, const int64_t* ldc, uint8_t* ws, hipStream_t s) {
   LRAMM_HIP(hipEventRecord(b->fork, s));
   for (hipStream_t t : b->streams) LRAMM_HIP(hipStreamWaitEvent(t, b->fork, 0));
+  // Products on several streams may run their Cholesky launches at the same
+  // time: each then uses the per-panel launches, whose workgroups never wait
+  // for one another (one-launch Cholesky grids could keep each other's
+  // workgroups off the CUs).
+  const bool one_launch = b->streams.size() == 1;
   for (int i : b->order) {
     lramm_plan* P = b->plans[i];
-    LRAMM_TRY(lramm_forward(P, A[i], lda[i], B[i], ldb[i], C[i], ldc[i], nullptr, 0, ws + b->offs[i], P->total,
-                            b->streams[b->stream_of[i]]));
+    P->one_launch_chol = one_launch;
+    const lramm_status st = lramm_forward(P, A[i], lda[i], B[i], ldb[i], C[i], ldc[i], nullptr, 0, ws + b->offs[i],
+                                          P->total, b->streams[b->stream_of[i]]);
+    P->one_launch_chol = true;
+    if (st != LRAMM_OK) return st;
   }
   for (size_t t = 0; t < b->streams.size(); ++t) {
     LRAMM_HIP(hipEventRecord(b->done[t], b->streams[t]));
