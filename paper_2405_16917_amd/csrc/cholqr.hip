@@ -1182,11 +1182,13 @@ __device__ __forceinline__ void meet3(int* cnt, int target) {
 // - L_{i+1,p} L_{i,p}^T, W' = G_{i+1,i+1} - L_{i+1,p} L_{i+1,p}^T and
 // Dinv_{p+1}.  On the critical path it forms only L_{i,p+1} = A1' Dinv_{p+1}^T
 // and U' - L_{i,p+1} L_{i,p+1}^T, factors block i (wavefront 0; meanwhile
-// wavefronts 1 - 2 finish row i + 1 with Dinv_{p+1} and wavefront 3 writes the
-// finished panel tiles), forms L_{i+1,i} and W, and factors block i + 1; during
-// that factorisation wavefronts 1 - 3 write this step's tiles, wait for
-// trailing step p, fetch the next step's G tiles and apply to them everything
-// that needs only Dinv_i and L_{i+1,i}.
+// wavefronts 1 - 2 finish row i + 1 with Dinv_{p+1}, and wavefront 3 writes the
+// finished panel tiles, waits for trailing step p and fetches the next
+// G_{in+1,in}, G_{in+1,in+1}), forms L_{i+1,i} and W, and factors block i + 1;
+// during that factorisation wavefronts 1 - 3 write this step's tiles
+// (wavefront 1 publishes Dinv_i and L_{i+1,i}), fetch the rest of the next
+// row pair's G tiles and apply to them everything that needs only Dinv_i and
+// L_{i+1,i}, and wavefront 0 joins in once its factorisation is done.
 __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, double* __restrict__ G,
                                                          double* __restrict__ L, double* __restrict__ Dinv,
                                                          double* __restrict__ Xinv,
