@@ -76,7 +76,9 @@ typedef enum {
   LRAMM_E_BREAKDOWN = 6,   /* Cholesky pivot dropped (device flag, non-fatal) */
   LRAMM_E_OVERFLOW = 7,    /* K too large for the int32 accumulator       */
   LRAMM_E_HIP = 8,         /* a HIP runtime call failed                   */
-  LRAMM_E_UNSUPPORTED = 9  /* format / type combination not implemented   */
+  LRAMM_E_UNSUPPORTED = 9, /* format / type combination not implemented   */
+  LRAMM_E_STALL = 10       /* a Cholesky wait ran past its bound (device
+                              flag): the result is not valid             */
 } lramm_status;
 
 /* element types of A, B, C and of stage inputs */
@@ -187,8 +189,8 @@ LRAMM_API lramm_status lramm_backward(lramm_plan* plan, const float* dC, int64_t
 
 /* Synchronise the stream and read the device status word of ws.
  * *flags (nullable) receives the LRAMM_FLAG_* bits; the return value is
- * LRAMM_E_NONFINITE if that bit is set, else LRAMM_OK (breakdown and
- * stall are reported only through *flags). */
+ * LRAMM_E_STALL if that bit is set, else LRAMM_E_NONFINITE if that bit is
+ * set, else LRAMM_OK (breakdown is reported only through *flags). */
 LRAMM_API lramm_status lramm_status_poll(const lramm_plan* plan, const void* ws,
                                void* stream, uint32_t* flags);
 

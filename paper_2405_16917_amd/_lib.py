@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblramm.so")
 
 # enums of include/lramm.h
-OK, E_INVALID, E_SHAPE, E_RANK, E_WORKSPACE, E_NONFINITE, E_BREAKDOWN, E_OVERFLOW, E_HIP, E_UNSUPPORTED = range(10)
+OK, E_INVALID, E_SHAPE, E_RANK, E_WORKSPACE, E_NONFINITE, E_BREAKDOWN, E_OVERFLOW, E_HIP, E_UNSUPPORTED, E_STALL = range(11)
 F32, BF16, F64 = 0, 1, 2
 INT8, INT4, FP8, BF16F = 0, 1, 2, 3
 FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_SQRTNEG, FLAG_STALL = 0x1, 0x2, 0x4, 0x8

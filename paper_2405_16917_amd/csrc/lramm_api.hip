@@ -158,6 +158,7 @@ const char* lramm_status_string(lramm_status s) {
     case LRAMM_E_OVERFLOW: return "K too large for the int32 accumulator";
     case LRAMM_E_HIP: return "HIP runtime error";
     case LRAMM_E_UNSUPPORTED: return "unsupported format, type or device";
+    case LRAMM_E_STALL: return "a Cholesky wait ran past its bound (result not valid)";
     default: return "unknown status";
   }
 }
@@ -549,6 +550,7 @@ lramm_status lramm_status_poll(const lramm_plan* P, const void* ws, void* stream
   LRAMM_HIP(hipMemcpyAsync(&h, base + P->off_flags, sizeof(h), hipMemcpyDeviceToHost, s));
   LRAMM_HIP(hipStreamSynchronize(s));
   if (flags) *flags = h;
+  if (h & LRAMM_FLAG_STALL) return LRAMM_E_STALL;
   return (h & LRAMM_FLAG_NONFINITE) ? LRAMM_E_NONFINITE : LRAMM_OK;
 }
 
@@ -701,6 +703,7 @@ lramm_status lramm_batch_status_poll(const lramm_batch* b, const void* ws, void*
     all |= f;
   }
   if (flags) *flags = all;
+  if (all & LRAMM_FLAG_STALL) return LRAMM_E_STALL;
   return (all & LRAMM_FLAG_NONFINITE) ? LRAMM_E_NONFINITE : LRAMM_OK;
 }
 

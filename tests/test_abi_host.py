@@ -37,8 +37,11 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_status_strings_and_pitch(lib):
+    import paper_2405_16917_amd._lib as L
     assert lib.lramm_status_string(0) == b"ok"
     assert lib.lramm_status_string(3).startswith(b"sketch width")
+    assert lib.lramm_status_string(L.E_STALL).startswith(b"a Cholesky wait")
+    assert L.FLAG_STALL == 0x8
     assert lib.lramm_pitch(272, 0) == 320      # int8: 272 bytes -> 64-byte multiple
     assert lib.lramm_pitch(272, 1) == 192      # int4: 136 bytes -> 192
     assert lib.lramm_pitch(100, 3) == 256      # bf16: 200 bytes -> 128-byte multiple
