@@ -1162,6 +1162,23 @@ __device__ __forceinline__ void sub_sub_xyt(double (*T)[NB + 1], const double (*
   sub_put_at(T, st, sub_get_at(T, st) - sub_xyt_at(X, Y, st));
 }
 
+// Spin (LDS) until *cnt >= target; workgroup-scope acquire.
+__device__ __forceinline__ void lds_wait(const int* cnt, int target) {
+  while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < target) __builtin_amdgcn_s_sleep(1);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+// Workgroup-scope release, then *cnt += 1 (one lane).
+__device__ __forceinline__ void lds_post(int* cnt) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if ((tid_x() & 63) == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// The next item of a work queue in LDS (the same value on every lane).
+__device__ __forceinline__ int lds_claim(int* cnt) {
+  int q = 0;
+  if ((tid_x() & 63) == 0) q = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return __builtin_amdgcn_readfirstlane(q);
+}
+
 // Wavefronts 1 - 3 of a workgroup meet: each adds one to *cnt and waits
 // for target (3, 6, .. for the first, second, .. meeting since *cnt was 0).
 __device__ __forceinline__ void meet3(int* cnt, int target) {
@@ -1178,17 +1195,17 @@ __device__ __forceinline__ void meet3(int* cnt, int target) {
 // A step of the diagonal workgroup (rows i = p + 2, i + 1; p = -2 for the
 // first two blocks) finds in LDS what the previous step prepared on its idle
 // wavefronts: L_{i,p}, L_{i+1,p} (final), A1' = G_{i,p+1} - L_{i,p} L_{p+1,p}^T,
-// U' = G_ii - L_{i,p} L_{i,p}^T, B1' (the same for row i + 1), V' = G_{i+1,i}
-// - L_{i+1,p} L_{i,p}^T, W' = G_{i+1,i+1} - L_{i+1,p} L_{i+1,p}^T and
+// U' = G_ii - L_{i,p} L_{i,p}^T, the raw G tiles of row i + 1, L_{p+1,p} and
 // Dinv_{p+1}.  On the critical path it forms only L_{i,p+1} = A1' Dinv_{p+1}^T
-// and U' - L_{i,p+1} L_{i,p+1}^T, factors block i (wavefront 0; meanwhile
-// wavefronts 1 - 2 finish row i + 1 with Dinv_{p+1}, and wavefront 3 writes the
-// finished panel tiles, waits for trailing step p and fetches the next
-// G_{in+1,in}, G_{in+1,in+1}), forms L_{i+1,i} and W, and factors block i + 1;
-// during that factorisation wavefronts 1 - 3 write this step's tiles
+// and U' - L_{i,p+1} L_{i,p+1}^T, and factors block i on wavefront 0;
+// meanwhile wavefronts 1 - 3 apply panel column p to row i + 1 (B1', V', W'),
+// wavefronts 1 - 2 finish that row with Dinv_{p+1}, and wavefront 3 writes
+// the finished panel tiles, waits for trailing step p and fetches the next
+// G_{in+1,in}, G_{in+1,in+1}.  It then forms L_{i+1,i} and W and factors block
+// i + 1; during that factorisation wavefronts 1 - 3 write this step's tiles
 // (wavefront 1 publishes Dinv_i and L_{i+1,i}), fetch the rest of the next
-// row pair's G tiles and apply to them everything that needs only Dinv_i and
-// L_{i+1,i}, and wavefront 0 joins in once its factorisation is done.
+// row pair's G tiles, form L_{in,i} (and L_{in+1,i}) and apply column i to
+// the next row's A1' and U'.
 __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, double* __restrict__ G,
                                                          double* __restrict__ L, double* __restrict__ Dinv,
                                                          double* __restrict__ Xinv,
@@ -1196,7 +1213,7 @@ __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, dou
                                                          uint32_t* flags, uint32_t* prog, int inv_end) {
   __shared__ Tile pool[12];
   __shared__ __align__(16) double lscratch[kFactorScratch];
-  __shared__ int s_cnt, s_cnt3, s_item;
+  __shared__ int s_cnt, s_cnt3, s_item, s_itemd, s_find;
   __shared__ double lthr[2][2 * NB];
   const int T = lw / NB;
   const int ntr = T > 2 ? (T - 2) * (T - 1) / 2 : 0;
@@ -1323,6 +1340,8 @@ __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, dou
       s_cnt = 0;
       s_cnt3 = 0;
       s_item = 0;
+      s_itemd = 0;
+      s_find = 0;
     }
     __syncthreads();
     if (p >= 0) {
@@ -1338,37 +1357,56 @@ __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, dou
     }
     if (wave == 0) {
       factor_block<1>(&U[0][0], &X[0][0], scratch, thr, i * NB, l_true, flags);
-    } else if (wave == 3) {
-      // the finished panel tiles of rows i and i + 1; then, once trailing
-      // step p is done, the next row pair's G tiles that go to free slots
-      // (the barrier after this factorisation passes the wait on to the
-      // other wavefronts)
-      if (p >= 0) {
+    } else {
+      // Wavefronts 1 - 3 first finish what the previous step left of row
+      // i + 1 (PV still holds L_{p+1,p}): B1' = G_{i+1,p+1} - L_{i+1,p} L_{p+1,p}^T,
+      // V' = G_{i+1,i} - L_{i+1,p} L_{i,p}^T, W' = G_{i+1,i+1} - L_{i+1,p} L_{i+1,p}^T
+      // (lower sub-tiles), one 16 x 16 sub-tile per item claimed in turn;
+      // wavefront 3 writes the finished panel tiles of rows i, i + 1 first.
+      if (wave == 3 && p >= 0) {
         tile_store_wave<false>(L + (int64_t)i * NB * lwz + p * NB, lwz, A0);
         tile_store_wave<false>(L + (int64_t)i * NB * lwz + (p + 1) * NB, lwz, A1);
         if (two) tile_store_wave<false>(L + (int64_t)(i + 1) * NB * lwz + p * NB, lwz, B0);
       }
-      if (two && in < T) {
-        if (p >= 0) chain_wait(&prog[1], chain_done(T, p), flags);
-        if (two_n) tiles_load_wave<2>(PV, Gn + in * NB, PW, Gn + (in + 1) * NB, PW, nullptr, lwz);
+      const int ndef = (p >= 0 && two) ? 11 : 0;
+      for (;;) {
+        const int q = lds_claim(&s_itemd);
+        if (q >= ndef) break;
+        if (q < 4)
+          sub_sub_xyt(B1, B0, PV, q);
+        else if (q < 8)
+          sub_sub_xyt(V, B0, A0, q - 4);
+        else
+          sub_sub_xyt(W, B0, B0, q == 8 ? 0 : q - 7);
+        lds_post(&s_find);
       }
-    } else if (p >= 0 && two) {
-      // wavefronts 1 and 2: row i + 1, rows 16 h .. 16 h + 15 each (h = wave
-      // - 1): L_{i+1,p+1} = B1' Dinv_{p+1}^T and V' - L_{i+1,p+1} L_{i,p+1}^T
-      // need only these rows; W needs both halves and waits for the other
-      const int h = wave - 1;
-      const v4d c0 = sub_xyt_at(B1, D1, 2 * h), c1 = sub_xyt_at(B1, D1, 2 * h + 1);
-      sub_put_at(B1, 2 * h, c0);
-      sub_put_at(B1, 2 * h + 1, c1);
-      sub_sub_xyt(V, B1, A1, 2 * h);
-      sub_sub_xyt(V, B1, A1, 2 * h + 1);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      if ((tid & 63) == 0) __hip_atomic_fetch_add(&s_cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      while (__hip_atomic_load(&s_cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < 2) __builtin_amdgcn_s_sleep(1);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      // the lower sub-tiles of W (the factor reads no entry above the diagonal)
-      sub_sub_xyt(W, B1, B1, h == 0 ? 0 : 2);
-      if (h == 0) sub_sub_xyt(W, B1, B1, 3);
+      lds_wait(&s_find, ndef);
+      if (wave == 3) {
+        // once trailing step p is done, the next row pair's G tiles that go to
+        // free slots (the barrier after this factorisation passes the wait on
+        // to the other wavefronts)
+        if (two && in < T) {
+          if (p >= 0) chain_wait(&prog[1], chain_done(T, p), flags);
+          if (two_n) tiles_load_wave<2>(PV, Gn + in * NB, PW, Gn + (in + 1) * NB, PW, nullptr, lwz);
+        }
+      } else if (p >= 0 && two) {
+        // wavefronts 1 and 2: row i + 1, rows 16 h .. 16 h + 15 each (h = wave
+        // - 1): L_{i+1,p+1} = B1' Dinv_{p+1}^T and V' - L_{i+1,p+1} L_{i,p+1}^T
+        // need only these rows; W needs both halves and waits for the other
+        const int h = wave - 1;
+        const v4d c0 = sub_xyt_at(B1, D1, 2 * h), c1 = sub_xyt_at(B1, D1, 2 * h + 1);
+        sub_put_at(B1, 2 * h, c0);
+        sub_put_at(B1, 2 * h + 1, c1);
+        sub_sub_xyt(V, B1, A1, 2 * h);
+        sub_sub_xyt(V, B1, A1, 2 * h + 1);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if ((tid & 63) == 0) __hip_atomic_fetch_add(&s_cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        while (__hip_atomic_load(&s_cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < 2) __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        // the lower sub-tiles of W (the factor reads no entry above the diagonal)
+        sub_sub_xyt(W, B1, B1, h == 0 ? 0 : 2);
+        if (h == 0) sub_sub_xyt(W, B1, B1, 3);
+      }
     }
     __syncthreads();
     if (!two) {
@@ -1381,39 +1419,25 @@ __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, dou
     __syncthreads();
     sub_put(W, sub_get(W) - sub_xyt(V, V));
     __syncthreads();
-    // the updates by the panel column i (V = L_{i+1,i}) of the next row pair:
-    // A1', U', and for row in + 1 B1', V', W' (lower sub-tiles of U' and W'
-    // only), one 16 x 16 sub-tile per item, items claimed by the wavefronts
-    // in turn (wavefront 0 joins once its factorisation is done)
+    // the updates by the panel column i (V = L_{i+1,i}) of the next row that
+    // its first products need: A1' and U' (lower sub-tiles), one 16 x 16
+    // sub-tile per item, claimed by wavefronts 1 - 3 in turn; row in + 1's
+    // share waits for the next step's first factorisation (V stays in the
+    // slot that becomes its PV)
     auto stage2 = [&]() {
-      const int n2 = two_n ? 18 : 7;
       for (;;) {
-        int q = 0;
-        if ((tid & 63) == 0) q = __hip_atomic_fetch_add(&s_item, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        q = __builtin_amdgcn_readfirstlane(q);
-        if (q >= n2) break;
+        const int q = lds_claim(&s_item);
+        if (q >= 7) break;
         if (q < 4)
           sub_sub_xyt(A1, A0, V, q);
-        else if (q < 7)
-          sub_sub_xyt(U, A0, A0, q == 4 ? 0 : q - 3);
-        else if (q < 11)
-          sub_sub_xyt(B1, B0, V, q - 7);
-        else if (q < 15)
-          sub_sub_xyt(PV, B0, A0, q - 11);
         else
-          sub_sub_xyt(PW, B0, B0, q == 15 ? 0 : q - 14);
+          sub_sub_xyt(U, A0, A0, q == 4 ? 0 : q - 3);
       }
     };
     if (wave == 0) {
       factor_block<1>(&W[0][0], &D0[0][0], scratch, thr + NB, (i + 1) * NB, l_true, flags);
       tile_store_wave<true>(L + (int64_t)(i + 1) * NB * lwz + (i + 1) * NB, lwz, W);
       tile_store_wave<false>(Dinv + (int64_t)(i + 1) * NB * NB, NB, D0);
-      if (in < T) {
-        while (__hip_atomic_load(&s_cnt3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < 9)
-          __builtin_amdgcn_s_sleep(1);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        stage2();
-      }
     } else {
       // this step's finished tiles, each written by the wavefront that
       // refills its slot below; wavefront 1 publishes Dinv_i and L_{i+1,i}
@@ -1465,7 +1489,8 @@ __global__ __launch_bounds__(256) void chol_chain_kernel(int lw, int l_true, dou
       chain_signal(&prog[0]);
       return;
     }
-    // Dinv_{i+1} is the next step's Dinv_{p+1}; G_{in+1,in}', G_{in+1,in+1}' its V, W
+    // Dinv_{i+1} is the next step's Dinv_{p+1}; G_{in+1,in}, G_{in+1,in+1} its
+    // V, W (their updates by panel column i still to come) and L_{i+1,i} its PV
     int t = rD1;
     rD1 = rD0;
     rD0 = t;
