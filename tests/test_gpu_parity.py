@@ -294,6 +294,32 @@ def test_cholqr2_matches_householder(lib, case):
     assert int(flags.item()) == 0
 
 
+def test_cholqr2_two_streams_at_once(lib):
+    """Two one-launch Cholesky grids that fit the GPU together (l = 200 and
+    272 on 2048 rows, on two streams): each result equals its single-stream
+    result bit for bit and no flag (stall, breakdown) is raised."""
+    rng = np.random.default_rng(77)
+    Ys = [g(f32(rng.standard_normal((2048, l)))) for l in (200, 272)]
+    single = []
+    for Y in Ys:
+        flags = torch.zeros(1, dtype=torch.int32, device=DEV)
+        single.append(lib.lramm_cholqr2(Y, Y.shape[1], flags=flags))
+        torch.cuda.synchronize()
+        assert int(flags.item()) == 0
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs, flags = [], []
+    for Y, st in zip(Ys, streams):
+        f = torch.zeros(1, dtype=torch.int32, device=DEV)
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            outs.append(lib.lramm_cholqr2(Y, Y.shape[1], flags=f))
+        flags.append(f)
+    torch.cuda.synchronize()
+    for Q, Q1, f in zip(outs, single, flags):
+        assert int(f.item()) == 0
+        assert torch.equal(Q, Q1)
+
+
 # (l, dependent column): the first half of block 0, the half sweep of a last
 # block whose second half is padding (l = 40: columns 32..39 live), and the
 # second half of a block in the first, second and a later diagonal step
