@@ -271,9 +271,10 @@ def test_omega_matches_oracle_philox(lib, kl):
 
 # ---------------------------------------------------------------- CholQR2 --
 
-# l' / 32 = 2 .. 23 blocks: odd and even block counts, the one-launch chain
+# l' / 32 = 1 .. 23 blocks: odd and even block counts, the one-launch chain
 # up to l' = 704 and the launch-per-two-panels schedule past it (l' = 736)
-@pytest.mark.parametrize("case", [(300, 40, 1.0), (512, 74, 1e3), (1000, 96, 1e6), (2048, 272, 30.0),
+@pytest.mark.parametrize("case", [(100, 5, 10.0), (64, 32, 10.0),
+                                  (300, 40, 1.0), (512, 74, 1e3), (1000, 96, 1e6), (2048, 272, 30.0),
                                   (700, 33, 10.0), (800, 128, 100.0), (2000, 200, 1e4), (4096, 528, 30.0),
                                   (2500, 700, 10.0), (1500, 736, 10.0)])
 def test_cholqr2_matches_householder(lib, case):
