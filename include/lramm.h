@@ -77,8 +77,10 @@ typedef enum {
   LRAMM_E_OVERFLOW = 7,    /* K too large for the int32 accumulator       */
   LRAMM_E_HIP = 8,         /* a HIP runtime call failed                   */
   LRAMM_E_UNSUPPORTED = 9, /* format / type combination not implemented   */
-  LRAMM_E_STALL = 10       /* a Cholesky wait ran past its bound (device
+  LRAMM_E_STALL = 10,      /* a Cholesky wait ran past its bound (device
                               flag): the result is not valid             */
+  LRAMM_E_SCRATCH = 11     /* problem larger than the fixed scratch of the
+                              no-allocation entry point                  */
 } lramm_status;
 
 /* element types of A, B, C and of stage inputs */
@@ -122,8 +124,10 @@ typedef struct {
 
 typedef struct lramm_plan lramm_plan;   /* opaque, host memory */
 
-/* Library set-up on the current device: checks the device is gfx950.  Safe
- * to call more than once.  Returns LRAMM_E_UNSUPPORTED on other devices. */
+/* Library set-up on the current device: checks the device is gfx950 and
+ * looks up that device's address of the lramm_cholqr2_noalloc scratch.
+ * Safe to call more than once.  Returns LRAMM_E_UNSUPPORTED on other
+ * devices. */
 LRAMM_API lramm_status lramm_init(void);
 
 LRAMM_API const char* lramm_status_string(lramm_status s);
@@ -306,6 +310,26 @@ LRAMM_API lramm_status lramm_cholqr2(int64_t rows, int64_t l, const void* Y, int
                            int32_t ytype, double* Q, int64_t ldq, void* ws,
                            size_t ws_bytes, uint32_t* flags, void* stream);
 LRAMM_API size_t lramm_cholqr2_workspace(int64_t rows, int64_t l);
+
+/* CholeskyQR2 that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments, results and error codes are
+ * those of lramm_cholqr2 (the same kernels: Q is bit-identical), without ws:
+ * the scratch is one fixed buffer of LRAMM_NOALLOC_SCRATCH_BYTES inside the
+ * library, one per GPU, held until the process ends and looked up by
+ * lramm_init() (or by the first call on a device).  It runs on the current
+ * device; stream must belong to it.
+ *   - Returns LRAMM_E_SCRATCH when lramm_cholqr2_workspace(rows, l) exceeds
+ *     LRAMM_NOALLOC_SCRATCH_BYTES (every l <= 768 fits at any row count).
+ *   - Calls no hipMalloc / hipFree or other allocating routine.
+ *   - All calls on one GPU share its buffer: calls that overlap in time on
+ *     that GPU (several streams, several host threads) race and give wrong
+ *     results; serialise them.  The buffer keeps the last call's contents;
+ *     every word a call reads is written earlier in that call. */
+#define LRAMM_NOALLOC_SCRATCH_BYTES (24u << 20)
+LRAMM_API lramm_status lramm_cholqr2_noalloc(int64_t rows, int64_t l, const void* Y, int64_t ldy,
+                           int32_t ytype, double* Q, int64_t ldq, uint32_t* flags,
+                           void* stream);
 
 /* Dense comparator GEMM (no quantisation, no vendor library):
  * C[M x N] = L[M x K] . R[N x K]^T with both operands K-contiguous.

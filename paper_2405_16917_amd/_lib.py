@@ -16,7 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblramm.so")
 
 # enums of include/lramm.h
-OK, E_INVALID, E_SHAPE, E_RANK, E_WORKSPACE, E_NONFINITE, E_BREAKDOWN, E_OVERFLOW, E_HIP, E_UNSUPPORTED, E_STALL = range(11)
+(OK, E_INVALID, E_SHAPE, E_RANK, E_WORKSPACE, E_NONFINITE, E_BREAKDOWN, E_OVERFLOW, E_HIP, E_UNSUPPORTED, E_STALL,
+ E_SCRATCH) = range(12)
+NOALLOC_SCRATCH_BYTES = 24 << 20
 F32, BF16, F64 = 0, 1, 2
 INT8, INT4, FP8, BF16F = 0, 1, 2, 3
 FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_SQRTNEG, FLAG_STALL = 0x1, 0x2, 0x4, 0x8
@@ -32,6 +34,7 @@ EXPORTS = (
     "lramm_cholqr2_workspace", "lramm_dense_gemm_nt", "lramm_plan_set_timing", "lramm_stage_times",
     "lramm_stage_name", "lramm_intermediate", "lramm_batch_create", "lramm_batch_destroy",
     "lramm_batch_workspace_bytes", "lramm_batched_forward", "lramm_batch_status_poll",
+    "lramm_cholqr2_noalloc",
 )
 NSTAGES = 22
 
@@ -93,6 +96,7 @@ def load(path=LIB_PATH):
         "lramm_omega": ([ctypes.c_uint64, I64, I64, P, I64, P], I32),
         "lramm_cholqr2": ([I64, I64, P, I64, I32, P, I64, P, SZ, P, P], I32),
         "lramm_cholqr2_workspace": ([I64, I64], SZ),
+        "lramm_cholqr2_noalloc": ([I64, I64, P, I64, I32, P, I64, P, P], I32),
         "lramm_dense_gemm_nt": ([I64, I64, I64, I32, P, I64, P, I64, P, I64, P], I32),
         "lramm_plan_set_timing": ([P, I32], I32),
         "lramm_stage_times": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], I32),
@@ -206,6 +210,20 @@ def lramm_cholqr2(Y, l=None, Q=None, ws=None, flags=None):
         ws = torch.empty(need, dtype=torch.uint8, device=Y.device)
     _check(lib.lramm_cholqr2(rows, l, _ptr(Y), Y.stride(0), DTYPE[Y.dtype], _ptr(Q), Q.stride(0), _ptr(ws),
                              ws.numel(), _ptr(flags), _stream()), "lramm_cholqr2")
+    return Q
+
+
+def lramm_cholqr2_noalloc(Y, l=None, Q=None, flags=None):
+    """lramm_cholqr2 on the library's fixed scratch (no workspace argument;
+    the library allocates nothing).  Q must be given by callers that cannot
+    allocate; it is created here only for convenience."""
+    lib = load()
+    rows = Y.shape[0]
+    l = Y.shape[1] if l is None else l
+    if Q is None:
+        Q = torch.empty((rows, (l + 31) // 32 * 32), dtype=torch.float64, device=Y.device)
+    _check(lib.lramm_cholqr2_noalloc(rows, l, _ptr(Y), Y.stride(0), DTYPE[Y.dtype], _ptr(Q), Q.stride(0),
+                                     _ptr(flags), _stream()), "lramm_cholqr2_noalloc")
     return Q
 
 

@@ -18,6 +18,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -57,12 +58,40 @@ struct lramm_plan {
 
 using namespace lramm;
 
+// Scratch of the no-allocation CholeskyQR2 (see lramm_cholqr2_noalloc).
+static __device__ __align__(256) uint8_t scratch[LRAMM_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 // Events that only order streams of this device: no timing, and a
 // device-scope release instead of the default system-scope fence (nothing
 // on the host reads what they guard).
 constexpr unsigned kOrderEvent = hipEventDisableTiming | hipEventReleaseToDevice;
+
+// Fixed device scratch of lramm_cholqr2_noalloc (callers that cannot
+// allocate).  Each GPU holds its own copy of this array for the life of the
+// process; host code reaches it only through the address
+// hipGetSymbolAddress returns with that GPU current (the array's name in
+// host code is a host-side stand-in, not a device address).
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of this GPU's scratch array: looked up once per device
+// (with that device current) and kept.
+lramm_status scratch_address(void** out) {
+  int dev = 0;
+  LRAMM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) return LRAMM_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LRAMM_E_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LRAMM_OK;
+}
 
 bool valid_fmt(int f) { return f == LRAMM_INT8 || f == LRAMM_INT4 || f == LRAMM_FP8 || f == LRAMM_BF16F; }
 bool valid_io(int t) { return t == LRAMM_F32 || t == LRAMM_BF16; }
@@ -159,6 +188,7 @@ const char* lramm_status_string(lramm_status s) {
     case LRAMM_E_HIP: return "HIP runtime error";
     case LRAMM_E_UNSUPPORTED: return "unsupported format, type or device";
     case LRAMM_E_STALL: return "a Cholesky wait ran past its bound (result not valid)";
+    case LRAMM_E_SCRATCH: return "problem needs more scratch than the no-allocation buffer holds";
     default: return "unknown status";
   }
 }
@@ -169,7 +199,8 @@ lramm_status lramm_init(void) {
   hipDeviceProp_t prop;
   LRAMM_HIP(hipGetDeviceProperties(&prop, dev));
   if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LRAMM_E_UNSUPPORTED;
-  return LRAMM_OK;
+  void* sp = nullptr;   // this GPU's no-allocation scratch, looked up once
+  return scratch_address(&sp);
 }
 
 int64_t lramm_pitch(int64_t K, int32_t fmt) { return pitch_bytes(K, fmt); }
@@ -768,6 +799,27 @@ lramm_status lramm_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, 
   if (ytype != LRAMM_F32 && ytype != LRAMM_F64) return LRAMM_E_UNSUPPORTED;
   if (!ws || ws_bytes < cholqr2_workspace(rows, l)) return LRAMM_E_WORKSPACE;
   return launch_cholqr2(rows, l, Y, ldy, ytype, Q, ldq, ws, ws_bytes, flags, (hipStream_t)stream);
+}
+
+lramm_status lramm_cholqr2_noalloc(int64_t rows, int64_t l, const void* Y, int64_t ldy, int32_t ytype, double* Q,
+                                   int64_t ldq, uint32_t* flags, void* stream) {
+  if (rows < 0 || l < 0) return LRAMM_E_SHAPE;
+  if (rows == 0 || l == 0) return LRAMM_OK;
+  if (!Y || !Q) return LRAMM_E_INVALID;
+  if (l > rows) return LRAMM_E_RANK;
+  if (ldy < l || ldq < round_up(l, 32)) return LRAMM_E_SHAPE;
+  if (round_up(l, 32) > 1024) return LRAMM_E_UNSUPPORTED;
+  if (ytype != LRAMM_F32 && ytype != LRAMM_F64) return LRAMM_E_UNSUPPORTED;
+  const size_t need = cholqr2_workspace(rows, l);
+  if (need > (size_t)LRAMM_NOALLOC_SCRATCH_BYTES) return LRAMM_E_SCRATCH;
+  void* ws = nullptr;
+  LRAMM_TRY(scratch_address(&ws));
+  // every scratch word the kernels read is written earlier in the same call
+  // (partial Grams, factors, and the gate word and progress counters that
+  // the first Gram reduction clears), so the previous call's contents need
+  // no clearing
+  return launch_cholqr2(rows, l, Y, ldy, ytype, Q, ldq, ws, (size_t)LRAMM_NOALLOC_SCRATCH_BYTES, flags,
+                        (hipStream_t)stream);
 }
 
 lramm_status lramm_dense_gemm_nt(int64_t M, int64_t N, int64_t K, int32_t dtype, const void* L, int64_t ldl,

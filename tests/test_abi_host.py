@@ -98,3 +98,21 @@ def test_stage_argument_errors(lib):
     assert lib.lramm_cholqr2(100, 20, 1, 20, L.F32, 1, 32, 1, 10, None, None) == L.E_WORKSPACE
     assert lib.lramm_dense_gemm_nt(64, 64, 60, L.BF16, 1, 64, 1, 64, 1, 64, None) == L.E_SHAPE
     assert lib.lramm_omega(0, 10, 3, None, 10, None) == L.E_INVALID
+
+
+def test_noalloc_cholqr2_host_checks(lib):
+    """The no-allocation CholeskyQR2 rejects, on the host, problems whose
+    workspace exceeds its fixed scratch (every l <= 768 fits at any row
+    count, l = 800 does not at large row counts), and the usual argument
+    errors, without touching the GPU."""
+    import paper_2405_16917_amd._lib as L
+    cap = L.NOALLOC_SCRATCH_BYTES
+    for rows in (768, 4096, 65536, 1 << 22):
+        assert lib.lramm_cholqr2_workspace(rows, 768) <= cap
+    assert lib.lramm_cholqr2_workspace(1 << 20, 800) > cap
+    assert lib.lramm_cholqr2_noalloc(1 << 20, 800, 1, 800, L.F32, 1, 800, None, None) == L.E_SCRATCH
+    assert lib.lramm_cholqr2_noalloc(10, 20, 1, 20, L.F32, 1, 32, None, None) == L.E_RANK
+    assert lib.lramm_cholqr2_noalloc(100, 20, 1, 20, L.F32, 1, 20, None, None) == L.E_SHAPE
+    assert lib.lramm_cholqr2_noalloc(100, 20, None, 20, L.F32, 1, 32, None, None) == L.E_INVALID
+    assert lib.lramm_cholqr2_noalloc(0, 20, None, 20, L.F32, None, 32, None, None) == L.OK
+    assert lib.lramm_status_string(L.E_SCRATCH).startswith(b"problem needs more scratch")
