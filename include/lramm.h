@@ -44,11 +44,14 @@
  *     results.
  *   - The Cholesky inside CholeskyQR2 (lramm_forward, lramm_cholqr2) runs
  *     as one launch whose workgroups wait on one another, and needs all of
- *     them on the GPU at once.  Calls whose such launches overlap on
- *     several streams can keep each other's workgroups waiting: the waits
- *     are bounded, and an overrun sets LRAMM_FLAG_STALL (that result is not
- *     valid).  lramm_batched_forward on more than one stream uses launches
- *     whose workgroups never wait instead.
+ *     them on the GPU at once.  By default that launch is used only when its
+ *     grid fits half of the compute units (less a margin), so two such calls
+ *     overlapping on different streams are resident together; a plan with
+ *     LRAMM_PLAN_EXCLUSIVE may use all of them.  More overlapping calls (or
+ *     exclusive plans overlapping others) can keep each other's workgroups
+ *     waiting: the waits are bounded, and an overrun sets LRAMM_FLAG_STALL
+ *     (that result is not valid).  lramm_batched_forward on more than one
+ *     stream uses launches whose workgroups never wait instead.
  */
 #ifndef LRAMM_H
 #define LRAMM_H
@@ -118,9 +121,17 @@ typedef struct {
   int32_t reserved0;
   uint64_t seed;        /* Philox key when the caller passes no Omega      */
   float alpha, beta;
-  uint32_t flags;       /* reserved, must be 0                             */
+  uint32_t flags;       /* 0 or LRAMM_PLAN_EXCLUSIVE                       */
   uint32_t reserved1;
 } lramm_desc;
+
+/* desc.flags: the caller runs no other CholeskyQR2 of this library on the
+ * GPU while this plan's forward runs, so its one-launch Cholesky may use all
+ * compute units (less a margin).  Without it the one-launch form is used
+ * only when its grid fits half of them, so that two forwards on different
+ * streams are always resident together; larger grids then use per-panel
+ * launches whose workgroups never wait on each other. */
+#define LRAMM_PLAN_EXCLUSIVE 0x1u
 
 typedef struct lramm_plan lramm_plan;   /* opaque, host memory */
 
@@ -310,6 +321,14 @@ LRAMM_API lramm_status lramm_cholqr2(int64_t rows, int64_t l, const void* Y, int
                            int32_t ytype, double* Q, int64_t ldq, void* ws,
                            size_t ws_bytes, uint32_t* flags, void* stream);
 LRAMM_API size_t lramm_cholqr2_workspace(int64_t rows, int64_t l);
+
+/* Host-only query of the schedule rule above: 1 when the Cholesky of an
+ * l-column CholeskyQR2 runs as one launch on a GPU with compute_units CUs
+ * (plan_flags 0 -- as for lramm_cholqr2 -- or LRAMM_PLAN_EXCLUSIVE), 0 when
+ * it runs as per-panel launches.  The grid has 1 + (T-2)(T-1)/2 + T
+ * workgroups for T = ceil(l / 32) blocks and is admitted when it is at most
+ * compute_units - 16, or half of that without LRAMM_PLAN_EXCLUSIVE. */
+LRAMM_API int32_t lramm_chol_one_launch(int64_t l, int32_t compute_units, uint32_t plan_flags);
 
 /* CholeskyQR2 that allocates nothing, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops,

@@ -19,23 +19,34 @@ from ._lib import (  # noqa: F401
 
 
 def matmul(A, B, r, p=16, q=1, fmt=("int8",) * 4, seed=0, omega=None, alpha=1.0, beta=0.0, out=None,
-           out_dtype=None, return_plan=False):
-    """C ~ alpha A B + beta out by LRAMM (one-sided, rank l = r + p)."""
+           out_dtype=None, return_plan=False, check=True):
+    """C ~ alpha A B + beta out by LRAMM (one-sided, rank l = r + p).
+
+    With ``check`` (the default) the device status word is read after the
+    forward (this synchronises the stream): a non-finite input or a Cholesky
+    wait past its bound raises LrammError instead of returning an invalid C."""
     m, k = A.shape
     n = B.shape[1]
     c_type = out.dtype if out is not None else (out_dtype or A.dtype)
     plan = LrammPlan(m, n, k, r, p, q, fmt, A.dtype, B.dtype, c_type, seed, alpha, beta)
     ws = plan.workspace(A.device)
     C = plan.forward(A, B, ws, C=out, omega=omega)
+    if check:
+        plan.status(ws)
     if return_plan:
         return C, plan, ws
     return C
 
 
 class LRAMMConfig:
-    def __init__(self, r, p=16, q=1, fmt=("int8",) * 4, seed=0, omega=None, recompute=False):
+    """Settings of LRAMMFunction.  ``check``: read the device status word
+    after each forward (synchronises the stream) and raise LrammError on a
+    non-finite input or an invalid Cholesky factor."""
+
+    def __init__(self, r, p=16, q=1, fmt=("int8",) * 4, seed=0, omega=None, recompute=False, check=True):
         self.r, self.p, self.q, self.fmt, self.seed, self.omega = r, p, q, fmt, seed, omega
         self.recompute = recompute
+        self.check = check
 
 
 class LRAMMFunction(torch.autograd.Function):
@@ -52,6 +63,8 @@ class LRAMMFunction(torch.autograd.Function):
         plan = LrammPlan(m, n, k, cfg.r, cfg.p, cfg.q, cfg.fmt, A.dtype, B.dtype, A.dtype, cfg.seed)
         ws = plan.workspace(A.device)
         C = plan.forward(A, B, ws, omega=cfg.omega)
+        if cfg.check:
+            plan.status(ws)
         ctx.plan, ctx.cfg = plan, cfg
         ctx.ws = None if cfg.recompute else ws
         ctx.save_for_backward(A, B)

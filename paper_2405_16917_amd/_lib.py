@@ -22,6 +22,7 @@ NOALLOC_SCRATCH_BYTES = 24 << 20
 F32, BF16, F64 = 0, 1, 2
 INT8, INT4, FP8, BF16F = 0, 1, 2, 3
 FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_SQRTNEG, FLAG_STALL = 0x1, 0x2, 0x4, 0x8
+PLAN_EXCLUSIVE = 0x1
 
 FMT = {"int8": INT8, "int4": INT4, "fp8": FP8, "bf16": BF16F}
 DTYPE = {torch.float32: F32, torch.bfloat16: BF16, torch.float64: F64}
@@ -34,7 +35,7 @@ EXPORTS = (
     "lramm_cholqr2_workspace", "lramm_dense_gemm_nt", "lramm_plan_set_timing", "lramm_stage_times",
     "lramm_stage_name", "lramm_intermediate", "lramm_batch_create", "lramm_batch_destroy",
     "lramm_batch_workspace_bytes", "lramm_batched_forward", "lramm_batch_status_poll",
-    "lramm_cholqr2_noalloc",
+    "lramm_cholqr2_noalloc", "lramm_chol_one_launch",
 )
 NSTAGES = 22
 
@@ -97,6 +98,7 @@ def load(path=LIB_PATH):
         "lramm_cholqr2": ([I64, I64, P, I64, I32, P, I64, P, SZ, P, P], I32),
         "lramm_cholqr2_workspace": ([I64, I64], SZ),
         "lramm_cholqr2_noalloc": ([I64, I64, P, I64, I32, P, I64, P, P], I32),
+        "lramm_chol_one_launch": ([I64, I32, ctypes.c_uint32], I32),
         "lramm_dense_gemm_nt": ([I64, I64, I64, I32, P, I64, P, I64, P, I64, P], I32),
         "lramm_plan_set_timing": ([P, I32], I32),
         "lramm_stage_times": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], I32),
@@ -247,13 +249,13 @@ class LrammPlan:
     lramm_status_poll on one problem description."""
 
     def __init__(self, m, n, k, r, p=16, q=1, fmt=("int8",) * 4, a_type=torch.float32,
-                 b_type=torch.float32, c_type=torch.float32, seed=0, alpha=1.0, beta=0.0):
+                 b_type=torch.float32, c_type=torch.float32, seed=0, alpha=1.0, beta=0.0, exclusive=False):
         lib = load()
         d = Desc()
         d.m, d.n, d.k, d.r, d.p, d.q = m, n, k, r, p, q
         d.fmt_sketch, d.fmt_proj, d.fmt_g1, d.fmt_g2 = (_fmt(f) for f in fmt)
         d.a_type, d.b_type, d.c_type = DTYPE[a_type], DTYPE[b_type], DTYPE[c_type]
-        d.seed, d.alpha, d.beta, d.flags = seed, alpha, beta, 0
+        d.seed, d.alpha, d.beta, d.flags = seed, alpha, beta, PLAN_EXCLUSIVE if exclusive else 0
         self.desc = d
         self.c_type = c_type
         h = P()
@@ -330,7 +332,8 @@ class LrammPlan:
         return {lib.lramm_stage_name(i).decode(): (ms[i], int(cnt[i])) for i in range(NSTAGES)}
 
     def status(self, ws):
-        """Synchronise and return the device status flags (raises on NaN/Inf)."""
+        """Synchronise and return the device status flags (raises LrammError
+        on a non-finite input or a Cholesky wait past its bound)."""
         f = ctypes.c_uint32()
         code = load().lramm_status_poll(self._h, _ptr(ws), _stream(), ctypes.byref(f))
         _check(code, "lramm_status_poll")

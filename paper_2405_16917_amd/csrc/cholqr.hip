@@ -1806,16 +1806,29 @@ static lramm_status gram(int64_t rows, int lw, int l_true, const T* X, int64_t l
   return LRAMM_OK;
 }
 
-// Workgroups the chain kernel may use: the compute units less a margin, so
-// that all of them are resident at once (its LDS allows one per CU).
-static int chain_grid_limit() {
-  static const int lim = [] {
-    int dev = 0, cus = 0;
+// Workgroups of the one-launch chain for Tn diagonal blocks: the diagonal
+// chain, one per trailing tile (i, j), j >= 2, one per column block of L^-1.
+static int chain_grid_of(int Tn) { return 1 + (Tn > 2 ? (Tn - 2) * (Tn - 1) / 2 : 0) + Tn; }
+
+// Whether the chain's grid may be used: it must fit the compute units less a
+// margin (its LDS allows one workgroup per CU), or half of that when two such
+// grids may run at the same time.
+bool chain_admits(int64_t l, int compute_units, int chain_mode) {
+  const int Tn = (int)(round_up(l, NB) / NB);
+  const int lim = compute_units - 16;
+  if (chain_mode == CHAIN_EXCLUSIVE) return chain_grid_of(Tn) <= lim;
+  if (chain_mode == CHAIN_SHARED) return chain_grid_of(Tn) <= lim / 2;
+  return false;
+}
+
+static int device_compute_units() {
+  static const int cus = [] {
+    int dev = 0, n = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    return cus - 16;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return n;
   }();
-  return lim;
+  return cus;
 }
 
 // Cholesky of w.G into w.L, w.Dinv and X = L^-1: the one-launch chain, or
@@ -1824,12 +1837,12 @@ static int chain_grid_limit() {
 // need a launch of its own) that row block is left out: the solve forms the
 // last block of Q1 from the others instead.
 static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32_t* flags, hipStream_t s,
-                                     const TimingHook* hook, bool skip_last_row, bool one_launch) {
+                                     const TimingHook* hook, bool skip_last_row, int chain_mode) {
   const double tol = 64.0 * (double)l_true * 0x1p-53;
   const int Tn = lw / NB;
   // one launch when every workgroup of the chain can be resident at once
-  const int chain_grid = 1 + (Tn > 2 ? (Tn - 2) * (Tn - 1) / 2 : 0) + Tn;
-  if (one_launch && chain_grid <= chain_grid_limit()) {
+  const int chain_grid = chain_grid_of(Tn);
+  if (chain_admits(lw, device_compute_units(), chain_mode)) {
     const int inv_end = (skip_last_row && Tn % 2 == 1) ? Tn - 1 : Tn;
     {
       HookScope hs(hook, SUB_CHOL_PANEL, 1);
@@ -1893,7 +1906,7 @@ static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t l
 
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
                             int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s,
-                            const TimingHook* hook, uint32_t* colmax, bool one_launch) {
+                            const TimingHook* hook, uint32_t* colmax, int chain_mode) {
   if (rows == 0 || l == 0) return LRAMM_OK;
   int lw, nc;
   int64_t rpc;
@@ -1935,12 +1948,12 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   const double* Dlast = solve_last ? w.Dinv + (size_t)(Tn1 - 1) * NB * NB : nullptr;
   if (ytype == LRAMM_F32) {
     LRAMM_TRY(gram<float>(rows, lw, lt, (const float*)Y, ldy, w, 0, s, hook));
-    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last, one_launch));
+    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last, chain_mode));
     LRAMM_TRY((tsmul<float, false>(rows, lw, lt, (const float*)Y, ldy, w.X, Q, ldq, zero_to, s, hook, cm1, nullptr,
                                    Ltri, Dlast, lw)));
   } else if (ytype == LRAMM_F64) {
     LRAMM_TRY(gram<double>(rows, lw, lt, (const double*)Y, ldy, w, 0, s, hook));
-    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last, one_launch));
+    LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last, chain_mode));
     LRAMM_TRY((tsmul<double, false>(rows, lw, lt, (const double*)Y, ldy, w.X, Q, ldq, zero_to, s, hook, cm1,
                                     nullptr, Ltri, Dlast, lw)));
   } else {

@@ -180,14 +180,28 @@ struct TimingHook {
 // sub-stage ids inside the orthonormalisation (continuing the forward's list)
 enum { SUB_CHOL_GRAM = 17, SUB_CHOL_PANEL = 18, SUB_CHOL_SOLVE = 19, SUB_CHOL_SERIES = 20, SUB_CHOL_APPLY = 21 };
 
+// How the Cholesky inside CholeskyQR2 may run.  Its one-launch form needs
+// every workgroup of its grid resident at once, since they wait on each
+// other:
+//   CHAIN_OFF:       per-panel launches only (workgroups never wait), for
+//                    callers that run several orthonormalisations at once;
+//   CHAIN_SHARED:    one launch when its grid fits half of the compute units
+//                    less a margin, so that two such grids issued on
+//                    different streams are still resident together;
+//   CHAIN_EXCLUSIVE: one launch when its grid fits all compute units less a
+//                    margin; the caller runs no other one-launch Cholesky on
+//                    the GPU meanwhile.
+enum ChainMode { CHAIN_OFF = 0, CHAIN_SHARED = 1, CHAIN_EXCLUSIVE = 2 };
+// The rule itself (host only): an l-column orthonormalisation on a GPU with
+// compute_units CUs.
+bool chain_admits(int64_t l, int compute_units, int chain_mode);
+
 // colmax (nullable, caller-zeroed, ldq entries): column maxima of fl32(|Q|)
-// as bit patterns, accumulated while Q is written.  one_launch: the Cholesky
-// may run as one launch whose workgroups wait on each other (false where
-// several such launches may overlap, as in a batch on several streams).
+// as bit patterns, accumulated while Q is written.
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
                             int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s,
                             const TimingHook* hook = nullptr, uint32_t* colmax = nullptr,
-                            bool one_launch = true);
+                            int chain_mode = CHAIN_SHARED);
 size_t cholqr2_workspace(int64_t rows, int64_t l);
 
 lramm_status launch_dense_gemm_nt(int64_t M, int64_t N, int64_t K, int dtype, const void* L, int64_t ldl,

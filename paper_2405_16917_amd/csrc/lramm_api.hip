@@ -26,7 +26,7 @@
 
 struct lramm_plan {
   lramm_desc d;
-  bool one_launch_chol = true;   // cleared while a batch issues the plan on one of several streams
+  int chain_mode = lramm::CHAIN_SHARED;   // CHAIN_OFF while a batch issues the plan on one of several streams
   int64_t l, lp;            // sketch width and its 32-padded leading dimension
   // workspace offsets (bytes)
   size_t off_flags;
@@ -216,7 +216,7 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   if (!valid_fmt(d.fmt_sketch) || !valid_fmt(d.fmt_proj) || !valid_fmt(d.fmt_g1) || !valid_fmt(d.fmt_g2))
     return LRAMM_E_UNSUPPORTED;
   if (!valid_io(d.a_type) || !valid_io(d.b_type) || !valid_io(d.c_type)) return LRAMM_E_UNSUPPORTED;
-  if (d.flags != 0) return LRAMM_E_INVALID;
+  if (d.flags & ~(uint32_t)LRAMM_PLAN_EXCLUSIVE) return LRAMM_E_INVALID;
   // int32 accumulator bound of every integer product
   if ((d.fmt_sketch != LRAMM_BF16F && d.k > qk_bound(d.fmt_sketch)) ||
       (d.fmt_proj != LRAMM_BF16F && d.m > qk_bound(d.fmt_proj)) ||
@@ -228,6 +228,7 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   lramm_plan* p = new (std::nothrow) lramm_plan();
   if (!p) return LRAMM_E_INVALID;
   p->d = d;
+  p->chain_mode = (d.flags & LRAMM_PLAN_EXCLUSIVE) ? CHAIN_EXCLUSIVE : CHAIN_SHARED;
   p->l = l;
   p->lp = lp;
   const int64_t m = d.m, n = d.n, k = d.k;
@@ -382,8 +383,6 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
   void* W = base;
   uint32_t* flags = at<uint32_t>(W, P->off_flags);
   uint32_t* zero = at<uint32_t>(W, P->off_zero);
-  // the zero region (column-maxima accumulators) is cleared by the first
-  // kernel on s, A's row quantiser; its users all run after it
   uint32_t* mxA = zero + P->mx_A;
   uint32_t* mxB = zero + P->mx_B;
   auto mxQ = [&](int c) { return zero + P->mx_Q + (size_t)c * lp; };
@@ -423,6 +422,10 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
   // wait for the sketch: started earlier they take CUs and bandwidth from
   // it, while the orthonormalisation's launches leave most CUs idle.
   hipStream_t s2 = P->side ? P->side : s;
+  // the status word and the column-maxima accumulators start at zero: one
+  // fill on s before any kernel that may set a flag (the side stream forks
+  // after it)
+  LRAMM_TRY(fill_u32(zero, 0u, (int64_t)P->zero_words, s));
   if (P->side) {
     LRAMM_HIP(hipEventRecord(P->ev_fork, s));
     LRAMM_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
@@ -434,8 +437,7 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
              launch_quantize(l, k, OmT, k, LRAMM_F32, d.fmt_sketch, 0, Om, P->pOm, sOm, flags, s2));
     if (P->side) LRAMM_HIP(hipEventRecord(P->ev_omega, P->side));
   }
-  TIMED(ST_QUANT_A_ROWS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_sketch, 0, Ar, P->pAr, sAr, flags, s,
-                                         nullptr, false, zero, (int64_t)P->zero_words));
+  TIMED(ST_QUANT_A_ROWS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_sketch, 0, Ar, P->pAr, sAr, flags, s));
   if (omega) {
     TIMED(ST_QUANT_OMEGA, launch_quantize(k, l, omega, ldo, LRAMM_F32, d.fmt_sketch, 1, Om, P->pOm, sOm, flags, s,
                                           zero + P->mx_Om));
@@ -454,7 +456,7 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
   TIMED_ON(s2, ST_QUANT_B, launch_quantize(k, n, B, ldb, d.b_type, d.fmt_g1, 1, Bc, P->pBc, sBc, flags, s2, mxB));
   if (P->side) LRAMM_HIP(hipEventRecord(P->ev_join, P->side));
   TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(0),
-                                   P->one_launch_chol));
+                                   P->chain_mode));
   uint8_t* Qc = at<uint8_t>(W, P->off_Qc);
   float* sQc = at<float>(W, P->off_sQc);
   if (P->side) LRAMM_HIP(hipStreamWaitEvent(s, P->ev_join, 0));   // join: A_c and B_c ready
@@ -468,14 +470,14 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
     TIMED(ST_POWER_Z, launch_gemm_nt(k, l, m, d.fmt_proj, Ac, P->pAc, sAc, Qc, P->pQc, sQc, 1.0f, 0.0f, Z, lp,
                                      LRAMM_F32, nullptr, 0, split, sb, s));
     TIMED(ST_CHOLQR2, launch_cholqr2(k, l, Z, lp, LRAMM_F32, QZ, lp, cws, P->chol_bytes, flags, s, hk, mxQZ(it),
-                                     P->one_launch_chol));
+                                     P->chain_mode));
     TIMED(ST_QUANT_QZ,
           launch_quantize(k, l, QZ, lp, LRAMM_F64, d.fmt_sketch, 1, QZc, P->pQZc, sQZc, flags, s, mxQZ(it), true));
     TIMED(ST_POWER_Y, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, P->pAr, sAr, QZc, P->pQZc, sQZc, 1.0f, 0.0f, Y, lp,
                                      LRAMM_F32, nullptr, 0, split, sb, s));
     TIMED(ST_CHOLQR2,
           launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(it + 1),
-                         P->one_launch_chol));
+                         P->chain_mode));
   }
   // projection Bt = Q^T A  (l x k)
   float* Bt = at<float>(W, P->off_Bt);
@@ -628,13 +630,14 @@ lramm_status batch_issue(lramm_batch* b, const void* const* A, const int64_t* ld
   // time: each then uses the per-panel launches, whose workgroups never wait
   // for one another (one-launch Cholesky grids could keep each other's
   // workgroups off the CUs).
-  const bool one_launch = b->streams.size() == 1;
+  const bool one_stream = b->streams.size() == 1;
   for (int i : b->order) {
     lramm_plan* P = b->plans[i];
-    P->one_launch_chol = one_launch;
+    const int mode = P->chain_mode;
+    if (!one_stream) P->chain_mode = CHAIN_OFF;
     const lramm_status st = lramm_forward(P, A[i], lda[i], B[i], ldb[i], C[i], ldc[i], nullptr, 0, ws + b->offs[i],
                                           P->total, b->streams[b->stream_of[i]]);
-    P->one_launch_chol = true;
+    P->chain_mode = mode;
     if (st != LRAMM_OK) return st;
   }
   for (size_t t = 0; t < b->streams.size(); ++t) {
@@ -787,6 +790,12 @@ lramm_status lramm_omega(uint64_t seed, int64_t k, int64_t l, float* OmegaT, int
 }
 
 size_t lramm_cholqr2_workspace(int64_t rows, int64_t l) { return cholqr2_workspace(rows, l); }
+
+int32_t lramm_chol_one_launch(int64_t l, int32_t compute_units, uint32_t plan_flags) {
+  if (l < 1 || round_up(l, 32) > 1024 || compute_units < 1) return 0;
+  return chain_admits(l, compute_units, (plan_flags & LRAMM_PLAN_EXCLUSIVE) ? CHAIN_EXCLUSIVE : CHAIN_SHARED) ? 1
+                                                                                                             : 0;
+}
 
 lramm_status lramm_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int32_t ytype, double* Q,
                            int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, void* stream) {

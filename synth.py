@@ -50,8 +50,14 @@ def to_dtype(X, dtype):
     raise ValueError(dtype)
 
 
-def lowrank(m, k, sigma, seed, noise_var=0.0, dtype="fp32"):
-    """Return (A, sigma) with A = U diag(sigma) V^T (+ noise) as float32 data."""
+def lowrank(m, k, sigma, seed, noise_var=0.0, dtype="fp32", info=None):
+    """Return (A, sigma) with A = U diag(sigma) V^T (+ noise) as float32 data.
+
+    With noise the low-rank part is first scaled to unit RMS entry; the
+    returned sigma is scaled by the same factor, so it holds the singular
+    values of the low-rank part of the returned A.  ``info`` (a dict, when
+    given) receives that factor ("scale") and the Frobenius norm of the noise
+    actually added ("noise_fro", 0 without noise)."""
     sigma = np.asarray(sigma, np.float64)
     c = int(np.sum(sigma >= 1e-9 * sigma[0]))
     c = max(1, min(c, m, k))
@@ -59,10 +65,16 @@ def lowrank(m, k, sigma, seed, noise_var=0.0, dtype="fp32"):
     U = haar(m, c, rng)
     V = haar(k, c, rng)
     A = (U * sigma[:c][None, :]) @ V.T
+    scale, noise_fro = 1.0, 0.0
     if noise_var > 0.0:
-        A = A / np.sqrt(np.mean(A * A))
-        A = A + np.sqrt(noise_var) * np.random.default_rng(seed + 200).standard_normal((m, k))
-    return to_dtype(A, dtype), sigma
+        scale = 1.0 / np.sqrt(np.mean(A * A))
+        N = np.sqrt(noise_var) * np.random.default_rng(seed + 200).standard_normal((m, k))
+        noise_fro = float(np.linalg.norm(N))
+        A = A * scale + N
+    if info is not None:
+        info["scale"] = float(scale)
+        info["noise_fro"] = noise_fro
+    return to_dtype(A, dtype), sigma * scale
 
 
 def gaussian(rows, cols, seed, dtype="fp32"):

@@ -76,7 +76,7 @@ def test_plan_validation(lib):
     assert _create(lib, _desc(L, r=0, p=0))[0] == L.E_RANK            # l < 1
     assert _create(lib, _desc(L, m=0))[0] == L.E_SHAPE
     assert _create(lib, _desc(L, fmt_g2=7))[0] == L.E_UNSUPPORTED
-    assert _create(lib, _desc(L, flags=1))[0] == L.E_INVALID
+    assert _create(lib, _desc(L, flags=2))[0] == L.E_INVALID
     assert _create(lib, _desc(L, k=200000))[0] == L.E_OVERFLOW        # K * 127^2 > 2^31
     assert lib.lramm_plan_create(None, None) == L.E_INVALID
 
@@ -116,3 +116,25 @@ def test_noalloc_cholqr2_host_checks(lib):
     assert lib.lramm_cholqr2_noalloc(100, 20, None, 20, L.F32, 1, 32, None, None) == L.E_INVALID
     assert lib.lramm_cholqr2_noalloc(0, 20, None, 20, L.F32, None, 32, None, None) == L.OK
     assert lib.lramm_status_string(L.E_SCRATCH).startswith(b"problem needs more scratch")
+
+
+def test_one_launch_cholesky_admission(lib):
+    """The one-launch Cholesky's grid (1 + (T-2)(T-1)/2 + T workgroups, T =
+    ceil(l/32)) must fit the CUs less 16, or half of that unless the plan is
+    exclusive, so that two default calls on different streams are resident
+    together."""
+    import paper_2405_16917_amd._lib as L
+    grid = lambda T: 1 + (T - 2) * (T - 1) // 2 + T
+    for l in range(1, 1025, 7):
+        T = (l + 31) // 32
+        for cus in (80, 256, 304):
+            assert lib.lramm_chol_one_launch(l, cus, 0) == int(grid(T) <= (cus - 16) // 2)
+            assert lib.lramm_chol_one_launch(l, cus, L.PLAN_EXCLUSIVE) == int(grid(T) <= cus - 16)
+    # MI355X (256 CUs): shared up to l' = 480 (107 workgroups), exclusive up to 704 (233)
+    assert lib.lramm_chol_one_launch(480, 256, 0) == 1 and lib.lramm_chol_one_launch(481, 256, 0) == 0
+    assert lib.lramm_chol_one_launch(704, 256, L.PLAN_EXCLUSIVE) == 1
+    assert lib.lramm_chol_one_launch(705, 256, L.PLAN_EXCLUSIVE) == 0
+    assert lib.lramm_chol_one_launch(2000, 256, 0) == 0
+    # the plan accepts the exclusive flag and nothing else
+    assert _create(lib, _desc(L, flags=L.PLAN_EXCLUSIVE))[0] == L.OK
+    assert _create(lib, _desc(L, flags=2))[0] == L.E_INVALID

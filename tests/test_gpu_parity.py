@@ -162,7 +162,9 @@ def _pack(codes, fmt, K):
 
 @pytest.mark.parametrize("fmt", ["int8", "int4"])
 @pytest.mark.parametrize("MNK", [(1, 1, 1), (37, 53, 100), (129, 65, 300), (64, 64, 64), (256, 320, 4096),
-                                 (300, 70, 8192), (512, 512, 512)])
+                                 (300, 70, 8192), (512, 512, 512),
+                                 # 128 x 64 and 64 x 128 tiles (skinny products at l = 272)
+                                 (8192, 272, 1024), (272, 8192, 1024), (8192, 448, 640), (448, 8192, 520)])
 def test_gemm_int_bit_exact(lib, fmt, MNK):
     M, N, K = MNK
     rng = np.random.default_rng(M * 7 + N * 11 + K)
@@ -477,6 +479,31 @@ def test_lramm_nonfinite_input_flag(lib):
     plan.forward(g(A), g(B), ws)
     with pytest.raises(lib.LrammError):
         plan.status(ws)
+
+
+@pytest.mark.parametrize("where", ["A_late_row", "B_late_col"])
+def test_lramm_nonfinite_in_late_workgroup(lib, where):
+    """A NaN in the last rows of A (quantised by the last workgroups of the
+    row pass) or the last column of B is reported: the status word is cleared
+    before any kernel that may set it.  matmul() raises on it by default."""
+    m, k, n = 4096, 256, 192
+    A = np.ones((m, k), np.float32)
+    B = np.ones((k, n), np.float32)
+    if where == "A_late_row":
+        A[m - 3, k - 1] = np.nan
+    else:
+        B[k - 2, n - 1] = np.inf
+    plan = lib.LrammPlan(m, n, k, 16, 4, 0)
+    ws = plan.workspace()
+    plan.forward(g(A), g(B), ws)
+    with pytest.raises(lib.LrammError) as e:
+        plan.status(ws)
+    assert e.value.code == 5
+    with pytest.raises(lib.LrammError):
+        lib.matmul(g(A), g(B), 16, 4, 0)
+    # a clean input on the same workspace reports nothing
+    plan.forward(g(np.ones((m, k), np.float32)), g(np.ones((k, n), np.float32)), ws)
+    assert plan.status(ws) & lib.FLAG_NONFINITE == 0
 
 
 # ---------------------------------------------------------------- backward --
