@@ -42,7 +42,7 @@ import numpy as np
 
 from .quant import fl32
 from .qgemm import qgemm
-from .qr import householder_qr
+from .qr import householder_qr, householder_qr_dropping
 from .philox import gaussian_omega
 
 FORMATS = ("int8", "int4", "fp8", "bf16", "fp64")
@@ -62,10 +62,18 @@ def _q_operand(Q, fmt):
 
 
 def lramm_forward(A, B, r, p, q, fmt=("int8",) * 4, omega=None, seed=None,
-                  alpha=1.0, beta=0.0, Cin=None, keep=True):
+                  alpha=1.0, beta=0.0, Cin=None, keep=True, drop_dependent=False):
     """One-sided LRAMM.  A: m x k, B: k x n (binary32 values unless every
     stage is fp64).  Returns a dict with C and, with ``keep``, every
-    intermediate (Omega, Y, Q, B~, T, and the power-iteration Z / Q_Z)."""
+    intermediate (Omega, Y, Q, B~, T, and the power-iteration Z / Q_Z).
+
+    ``drop_dependent``: orthonormalise with ``householder_qr_dropping`` at
+    tolerance 64 l 2^-53 (a sketch column that the earlier ones already span
+    to that accuracy gets a zero Q column instead of a completion vector);
+    the basis then spans exactly the kept sketch columns.  This is the reading
+    used for rank(A) < l, where the completion vectors of a plain Householder
+    QR are arbitrary directions outside range(A) and would change the row
+    scales of Q."""
     A = np.asarray(A, np.float64)
     B = np.asarray(B, np.float64)
     m, k = A.shape
@@ -88,15 +96,24 @@ def lramm_forward(A, B, r, p, q, fmt=("int8",) * 4, omega=None, seed=None,
         raise ValueError("omega must be k x l")
 
     out = {"l": l}
+    tol = 64.0 * l * 2.0**-53
+
+    def orth(X):
+        if drop_dependent:
+            Qd, Rd, dropped = householder_qr_dropping(X, tol)
+            out.setdefault("dropped", []).append(dropped)
+            return Qd, Rd
+        return householder_qr(X)
+
     Y = _product(A, omega, fs)
-    Q, R = householder_qr(Y)
+    Q, R = orth(Y)
     if keep:
         out.update(omega=omega, Y0=Y, Q0=Q)
     for it in range(q):
         Z = _product(A.T, _q_operand(Q, fp), fp)
-        QZ, _ = householder_qr(Z)
+        QZ, _ = orth(Z)
         Y = _product(A, _q_operand(QZ, fs), fs)
-        Q, R = householder_qr(Y)
+        Q, R = orth(Y)
         if keep:
             out[f"Z{it + 1}"] = Z
             out[f"QZ{it + 1}"] = QZ

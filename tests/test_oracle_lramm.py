@@ -207,3 +207,23 @@ def test_tiny_chain_against_pure_python():
     assert np.array_equal(out["Bt"], np.array(Bt))
     assert np.array_equal(out["T"], np.array(T))
     assert np.array_equal(out["C"], np.array(C))
+
+
+def test_exact_recovery_with_dropped_sketch_columns():
+    """rank(A) = 40 < l = 74: with the dropping orthonormalisation the sketch
+    columns past the rank are dropped (zero Q columns, l - 40 of them in
+    every orthonormalisation), Q still spans range(A), and the unquantised
+    product recovers A B to 1e-12 (exact recovery)."""
+    m = k = n = 256
+    rng = np.random.default_rng(8)
+    U, V = synth.haar(m, 40, rng), synth.haar(k, 40, rng)
+    A = (U * synth.spectrum("exp", 40, 10.0)[None, :]) @ V.T      # rank 40 exactly, kept in FP64
+    B = synth.gaussian(k, n, 108).astype(np.float64)
+    om = synth.omega(k, 74, 9).astype(np.float64)
+    ref = L.lramm_forward(A, B, 64, 10, 1, ("fp64",) * 4, omega=om, drop_dependent=True)
+    assert all(len(d) == 74 - 40 for d in ref["dropped"])
+    assert all(d == list(range(40, 74)) for d in ref["dropped"])
+    Q = ref["Q"]
+    assert not Q[:, 40:].any()
+    assert L.rel_fro(Q @ (Q.T @ A), A) <= 1e-12
+    assert L.rel_fro(ref["C"], A @ B) <= 1e-12
