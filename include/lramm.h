@@ -189,6 +189,30 @@ LRAMM_API lramm_status lramm_intermediate(const lramm_plan* plan, const void* ws
                            int32_t which, const void** ptr, int64_t* rows,
                            int64_t* cols, int64_t* ld, int32_t* dtype);
 
+/* Device view of the quantised operands of one product of the last forward
+ * on ws, for checking every product on its own operands:
+ *   LRAMM_CODES_A_ROWS   (0): A by rows (sketch format), m x k -- A itself
+ *                             when a bf16 A fed a bf16 sketch directly;
+ *   LRAMM_CODES_SKETCH_R (1): right operand of the last sketch (Omega^T, or
+ *                             Q_Z^T after power iterations), l x k;
+ *   LRAMM_CODES_Q_COLS   (2): Q^T by rows (= Q by columns, proj format), l x m;
+ *   LRAMM_CODES_A_COLS   (3): A^T by rows (proj format), k x m;
+ *   LRAMM_CODES_BT_ROWS  (4): Bt by rows (g1 format), l x k;
+ *   LRAMM_CODES_B_COLS   (5): B^T by rows (g1 format), n x k;
+ *   LRAMM_CODES_Q_ROWS   (6): Q by rows (g2 format), m x l;
+ *   LRAMM_CODES_TT_ROWS  (7): T^T by rows (g2 format), n x l.
+ * Each is rows x pitch BYTES of codes in the layout lramm_quantize writes
+ * (K codes per row, *fmt the lramm_fmt), with one FP32 scale per row (1 for
+ * bf16; the A_ROWS scales are not written on the direct path).  Pointers
+ * point into ws (or A). */
+enum {
+  LRAMM_CODES_A_ROWS = 0, LRAMM_CODES_SKETCH_R = 1, LRAMM_CODES_Q_COLS = 2, LRAMM_CODES_A_COLS = 3,
+  LRAMM_CODES_BT_ROWS = 4, LRAMM_CODES_B_COLS = 5, LRAMM_CODES_Q_ROWS = 6, LRAMM_CODES_TT_ROWS = 7
+};
+LRAMM_API lramm_status lramm_codes(const lramm_plan* plan, const void* ws, int32_t which,
+                           const void** codes, int64_t* rows, int64_t* K, int64_t* pitch,
+                           const float** scales, int32_t* fmt);
+
 /* Backward of C = Q Q^T A B with Q fixed and quantisation straight-through
  * (the gradient of the frozen-Q surrogate):
  *     W = Q^T dC,  dB = (Q^T A)^T W,  dA = Q (W B^T).

@@ -35,7 +35,7 @@ EXPORTS = (
     "lramm_cholqr2_workspace", "lramm_dense_gemm_nt", "lramm_plan_set_timing", "lramm_stage_times",
     "lramm_stage_name", "lramm_intermediate", "lramm_batch_create", "lramm_batch_destroy",
     "lramm_batch_workspace_bytes", "lramm_batched_forward", "lramm_batch_status_poll",
-    "lramm_cholqr2_noalloc", "lramm_chol_one_launch",
+    "lramm_cholqr2_noalloc", "lramm_chol_one_launch", "lramm_codes",
 )
 NSTAGES = 22
 
@@ -99,6 +99,8 @@ def load(path=LIB_PATH):
         "lramm_cholqr2_workspace": ([I64, I64], SZ),
         "lramm_cholqr2_noalloc": ([I64, I64, P, I64, I32, P, I64, P, P], I32),
         "lramm_chol_one_launch": ([I64, I32, ctypes.c_uint32], I32),
+        "lramm_codes": ([P, P, I32, ctypes.POINTER(P), ctypes.POINTER(I64), ctypes.POINTER(I64),
+                         ctypes.POINTER(I64), ctypes.POINTER(P), ctypes.POINTER(I32)], I32),
         "lramm_dense_gemm_nt": ([I64, I64, I64, I32, P, I64, P, I64, P, I64, P], I32),
         "lramm_plan_set_timing": ([P, I32], I32),
         "lramm_stage_times": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], I32),
@@ -306,6 +308,31 @@ class LrammPlan:
         esz, tdt = (8, torch.float64) if dt.value == F64 else (4, torch.float32)
         off = ptr.value - ws.data_ptr()
         return ws[off:off + rows.value * ld.value * esz].view(tdt).view(rows.value, ld.value)[:, :cols.value]
+
+    CODES = {"A_rows": 0, "sketch_R": 1, "Q_cols": 2, "A_cols": 3, "Bt_rows": 4, "B_cols": 5, "Q_rows": 6,
+             "Tt_rows": 7}
+
+    def codes(self, ws, name, A=None):
+        """(codes uint8 [rows x pitch], scales float32 [rows], K, fmt name) of
+        one quantised operand of the last forward (views into ws; "A_rows"
+        on the direct bf16 path views A, which must then be passed)."""
+        ptr, rows, K, pitch, sc, f = P(), I64(), I64(), I64(), P(), I32()
+        _check(load().lramm_codes(self._h, _ptr(ws), self.CODES[name], ctypes.byref(ptr), ctypes.byref(rows),
+                                  ctypes.byref(K), ctypes.byref(pitch), ctypes.byref(sc), ctypes.byref(f)),
+               "lramm_codes")
+        fname = {v: k for k, v in FMT.items()}[f.value]
+        base = ws.data_ptr()
+        nbytes = rows.value * pitch.value
+        if base <= ptr.value < base + ws.numel():
+            off = ptr.value - base
+            codes = ws[off:off + nbytes].view(rows.value, pitch.value)
+        else:
+            if A is None or A.data_ptr() != ptr.value:
+                raise ValueError("these codes are the input A itself: pass A")
+            codes = A.view(torch.uint8).view(rows.value, -1)[:, :pitch.value]
+        so = sc.value - base
+        scales = ws[so:so + 4 * rows.value].view(torch.float32)
+        return codes, scales, K.value, fname
 
     def backward(self, dC, A, B, ws, dA=None, dB=None, need_dA=True, need_dB=True):
         d = self.desc

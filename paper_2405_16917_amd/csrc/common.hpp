@@ -133,6 +133,44 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) {
 
 __device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
+// Encode 4 consecutive values (elements c0..c0+3, c0 % 4 == 0) of one vector
+// and store them at element offset c0 of the output row.
+template <int FMT>
+__device__ __forceinline__ void encode4(uint8_t* row, int64_t c0, const float v[4], bool live[4], float lam) {
+  if constexpr (FMT == LRAMM_INT8) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int q = live[j] ? qcode(v[j], lam, 127.0f) : 0;
+      w |= ((uint32_t)(q & 0xff)) << (8 * j);
+    }
+    *reinterpret_cast<uint32_t*>(row + c0) = w;
+  } else if constexpr (FMT == LRAMM_INT4) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int q = live[j] ? qcode(v[j], lam, 7.0f) : 0;
+      w |= ((uint32_t)(q & 0xf)) << (4 * j);
+    }
+    *reinterpret_cast<uint16_t*>(row + c0 / 2) = (uint16_t)w;
+  } else if constexpr (FMT == LRAMM_FP8) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint32_t b = live[j] ? e4m3_bits(__fmul_rn(v[j], lam)) : 0u;
+      w |= b << (8 * j);
+    }
+    *reinterpret_cast<uint32_t*>(row + c0) = w;
+  } else {  // bf16
+    uint32_t lo = (live[0] ? bf16_bits(v[0]) : 0u) | ((uint32_t)(live[1] ? bf16_bits(v[1]) : 0u) << 16);
+    uint32_t hi = (live[2] ? bf16_bits(v[2]) : 0u) | ((uint32_t)(live[3] ? bf16_bits(v[3]) : 0u) << 16);
+    uint2 w;
+    w.x = lo;
+    w.y = hi;
+    *reinterpret_cast<uint2*>(row + 2 * c0) = w;
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ float load_as_f32(const T* p);
 template <>
@@ -170,6 +208,11 @@ size_t gemm_nt_workspace(int64_t M, int64_t N, int64_t K, int fmt);
 
 lramm_status launch_omega(uint64_t seed, int64_t k, int64_t l, int64_t lrows, float* OmegaT, int64_t ldo,
                           hipStream_t s);
+// Omega generated and quantised by rows of Omega^T in one launch (codes l x
+// pitch, l scales), for k up to omega_quant_max_k(); LRAMM_E_UNSUPPORTED past it.
+lramm_status launch_omega_quant(uint64_t seed, int64_t k, int64_t l, int fmt, uint8_t* Oq, int64_t pitch,
+                                float* scales, hipStream_t s);
+int64_t omega_quant_max_k();
 
 // Optional measurement hook: event pairs around individual launches.
 struct TimingHook {

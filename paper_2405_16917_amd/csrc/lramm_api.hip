@@ -43,6 +43,10 @@ struct lramm_plan {
   size_t mx_A, mx_B, mx_Om, mx_Q, mx_QZ;   // word offsets inside the zero region
   size_t total;
   int64_t pAr, pAc, pBc, pOm, pQZc, pQc, pQr, pBtq, pTtq;
+  // A's row codes of the last forward: the workspace copy, or A itself when
+  // the bf16 input fed the bf16 sketch directly
+  const void* last_Ar = nullptr;
+  int64_t last_pAr = 0;
   // side stream for the work independent of the orthonormalisation chain
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_omega = nullptr, ev_sketch = nullptr;
@@ -431,13 +435,29 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
     LRAMM_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
   }
   if (!omega) {
-    float* OmT = at<float>(W, P->off_OmT);
-    TIMED_ON(s2, ST_OMEGA, launch_omega(d.seed, k, l, l, OmT, k, s2));
-    TIMED_ON(s2, ST_QUANT_OMEGA,
-             launch_quantize(l, k, OmT, k, LRAMM_F32, d.fmt_sketch, 0, Om, P->pOm, sOm, flags, s2));
+    if (d.fmt_sketch == LRAMM_BF16F || k <= omega_quant_max_k()) {
+      // generated and quantised in one pass
+      TIMED_ON(s2, ST_OMEGA, launch_omega_quant(d.seed, k, l, d.fmt_sketch, Om, P->pOm, sOm, s2));
+    } else {
+      float* OmT = at<float>(W, P->off_OmT);
+      TIMED_ON(s2, ST_OMEGA, launch_omega(d.seed, k, l, l, OmT, k, s2));
+      TIMED_ON(s2, ST_QUANT_OMEGA,
+               launch_quantize(l, k, OmT, k, LRAMM_F32, d.fmt_sketch, 0, Om, P->pOm, sOm, flags, s2));
+    }
     if (P->side) LRAMM_HIP(hipEventRecord(P->ev_omega, P->side));
   }
-  TIMED(ST_QUANT_A_ROWS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_sketch, 0, Ar, P->pAr, sAr, flags, s));
+  // bf16 A in a bf16 sketch: the codes are A itself (rows of whole 64-element
+  // tiles, 16-byte aligned), no pass over A
+  const bool a_direct = d.fmt_sketch == LRAMM_BF16F && d.a_type == LRAMM_BF16 && k % 64 == 0 &&
+                        (lda * 2) % 16 == 0 && (uintptr_t)A % 16 == 0;
+  if (a_direct) {
+    Ar = reinterpret_cast<uint8_t*>(const_cast<void*>(A));
+  } else {
+    TIMED(ST_QUANT_A_ROWS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_sketch, 0, Ar, P->pAr, sAr, flags, s));
+  }
+  const int64_t pAr = a_direct ? lda * 2 : P->pAr;
+  P->last_Ar = Ar;
+  P->last_pAr = pAr;
   if (omega) {
     TIMED(ST_QUANT_OMEGA, launch_quantize(k, l, omega, ldo, LRAMM_F32, d.fmt_sketch, 1, Om, P->pOm, sOm, flags, s,
                                           zero + P->mx_Om));
@@ -445,7 +465,7 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
     LRAMM_HIP(hipStreamWaitEvent(s, P->ev_omega, 0));   // Omega's codes ready
   }
   // sketch, then the side stream's column codes, then the orthonormalisation
-  TIMED(ST_SKETCH, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, P->pAr, sAr, Om, P->pOm, sOm, 1.0f, 0.0f, Y, lp,
+  TIMED(ST_SKETCH, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, pAr, sAr, Om, P->pOm, sOm, 1.0f, 0.0f, Y, lp,
                                   LRAMM_F32, nullptr, 0, split, sb, s));
   if (P->side) {
     LRAMM_HIP(hipEventRecord(P->ev_sketch, s));
@@ -473,7 +493,7 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
                                      P->chain_mode));
     TIMED(ST_QUANT_QZ,
           launch_quantize(k, l, QZ, lp, LRAMM_F64, d.fmt_sketch, 1, QZc, P->pQZc, sQZc, flags, s, mxQZ(it), true));
-    TIMED(ST_POWER_Y, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, P->pAr, sAr, QZc, P->pQZc, sQZc, 1.0f, 0.0f, Y, lp,
+    TIMED(ST_POWER_Y, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, pAr, sAr, QZc, P->pQZc, sQZc, 1.0f, 0.0f, Y, lp,
                                      LRAMM_F32, nullptr, 0, split, sb, s));
     TIMED(ST_CHOLQR2,
           launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(it + 1),
@@ -537,6 +557,37 @@ lramm_status lramm_intermediate(const lramm_plan* P, const void* ws, int32_t whi
     case LRAMM_VIEW_TT:
       *ptr = base + P->off_Tt, *rows = d.n, *cols = P->l, *ld = P->lp, *dtype = LRAMM_F32;
       break;
+    default: return LRAMM_E_INVALID;
+  }
+  return LRAMM_OK;
+}
+
+lramm_status lramm_codes(const lramm_plan* P, const void* ws, int32_t which, const void** codes, int64_t* rows,
+                         int64_t* K, int64_t* pitch, const float** scales, int32_t* fmt) {
+  if (!P || !ws || !codes || !rows || !K || !pitch || !scales || !fmt) return LRAMM_E_INVALID;
+  const uint8_t* base = reinterpret_cast<const uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
+  const lramm_desc& d = P->d;
+  const int64_t m = d.m, n = d.n, k = d.k, l = P->l;
+  auto set = [&](size_t off_codes, size_t off_scales, int64_t r, int64_t kk, int64_t pt, int f) {
+    *codes = base + off_codes, *rows = r, *K = kk, *pitch = pt, *fmt = f;
+    *scales = reinterpret_cast<const float*>(base + off_scales);
+  };
+  switch (which) {
+    case LRAMM_CODES_A_ROWS:
+      if (!P->last_Ar) return LRAMM_E_INVALID;
+      set(P->off_Ar, P->off_sAr, m, k, P->last_pAr, d.fmt_sketch);
+      *codes = P->last_Ar;
+      break;
+    case LRAMM_CODES_SKETCH_R:
+      if (d.q > 0) set(P->off_QZc, P->off_sQZc, l, k, P->pQZc, d.fmt_sketch);
+      else set(P->off_Om, P->off_sOm, l, k, P->pOm, d.fmt_sketch);
+      break;
+    case LRAMM_CODES_Q_COLS: set(P->off_Qc, P->off_sQc, l, m, P->pQc, d.fmt_proj); break;
+    case LRAMM_CODES_A_COLS: set(P->off_Ac, P->off_sAc, k, m, P->pAc, d.fmt_proj); break;
+    case LRAMM_CODES_BT_ROWS: set(P->off_Btq, P->off_sBt, l, k, P->pBtq, d.fmt_g1); break;
+    case LRAMM_CODES_B_COLS: set(P->off_Bc, P->off_sBc, n, k, P->pBc, d.fmt_g1); break;
+    case LRAMM_CODES_Q_ROWS: set(P->off_Qr, P->off_sQr, m, l, P->pQr, d.fmt_g2); break;
+    case LRAMM_CODES_TT_ROWS: set(P->off_Ttq, P->off_sTt, n, l, P->pTtq, d.fmt_g2); break;
     default: return LRAMM_E_INVALID;
   }
   return LRAMM_OK;

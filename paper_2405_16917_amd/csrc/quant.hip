@@ -32,44 +32,6 @@ lramm_status fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
 
 // ------------------------------------------------------------------ codes --
 
-// Encode 4 consecutive values (elements c0..c0+3, c0 % 4 == 0) of one vector
-// and store them at element offset c0 of the output row.
-template <int FMT>
-__device__ __forceinline__ void store4(uint8_t* row, int64_t c0, const float v[4], bool live[4], float lam) {
-  if constexpr (FMT == LRAMM_INT8) {
-    uint32_t w = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      int q = live[j] ? qcode(v[j], lam, 127.0f) : 0;
-      w |= ((uint32_t)(q & 0xff)) << (8 * j);
-    }
-    *reinterpret_cast<uint32_t*>(row + c0) = w;
-  } else if constexpr (FMT == LRAMM_INT4) {
-    uint32_t w = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      int q = live[j] ? qcode(v[j], lam, 7.0f) : 0;
-      w |= ((uint32_t)(q & 0xf)) << (4 * j);
-    }
-    *reinterpret_cast<uint16_t*>(row + c0 / 2) = (uint16_t)w;
-  } else if constexpr (FMT == LRAMM_FP8) {
-    uint32_t w = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      uint32_t b = live[j] ? e4m3_bits(__fmul_rn(v[j], lam)) : 0u;
-      w |= b << (8 * j);
-    }
-    *reinterpret_cast<uint32_t*>(row + c0) = w;
-  } else {  // bf16
-    uint32_t lo = (live[0] ? bf16_bits(v[0]) : 0u) | ((uint32_t)(live[1] ? bf16_bits(v[1]) : 0u) << 16);
-    uint32_t hi = (live[2] ? bf16_bits(v[2]) : 0u) | ((uint32_t)(live[3] ? bf16_bits(v[3]) : 0u) << 16);
-    uint2 w;
-    w.x = lo;
-    w.y = hi;
-    *reinterpret_cast<uint2*>(row + 2 * c0) = w;
-  }
-}
-
 // 4 consecutive elements (4-element aligned) as FP32, no bounds test.
 template <typename T>
 __device__ __forceinline__ void load4_full(const T* p, float v[4]) {
@@ -153,7 +115,7 @@ __global__ __launch_bounds__(256) void quant_rows_kernel(int64_t rows, int64_t c
         for (int j = 0; j < 4; ++j) live[j] = false;
       }
     }
-    store4<FMT>(qr, c0, v, live, lam);
+    encode4<FMT>(qr, c0, v, live, lam);
   }
 }
 
@@ -377,7 +339,7 @@ __global__ __launch_bounds__(256) void quant_rows_reg_kernel(int64_t rows, int64
       bool live[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) live[j] = c0 + j < cols && (FMT == LRAMM_BF16F || lam != 0.0f);
-      store4<FMT>(qr, c0, v[c], live, lam);
+      encode4<FMT>(qr, c0, v[c], live, lam);
     }
   }
 }

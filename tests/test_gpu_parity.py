@@ -50,7 +50,7 @@ def e4m3_value(b):
 
 
 def codes_from(Xq, fmt, K):
-    q = Xq.cpu().numpy()
+    q = Xq.cpu().numpy() if hasattr(Xq, "cpu") else np.asarray(Xq)
     if fmt == "fp8":
         return e4m3_value(q[:, :K]), q
     if fmt == "int8":
@@ -354,13 +354,128 @@ def _run_forward(lib, A, B, r, p, q, fmt, omega=None, seed=0, alpha=1.0, beta=0.
     plan = lib.LrammPlan(m, n, k, r, p, q, fmt, a_type, a_type, c_type, seed, alpha, beta)
     ws = plan.workspace()
     C = g(Cin, c_type) if Cin is not None else None
-    C = plan.forward(g(A, a_type), g(B, a_type), ws, C=C, omega=None if omega is None else g(omega))
+    Ad, Bd = g(A, a_type), g(B, a_type)
+    C = plan.forward(Ad, Bd, ws, C=C, omega=None if omega is None else g(omega))
     flags = plan.status(ws)
-    return C.double().cpu().numpy(), plan, ws, flags
+    return C.double().cpu().numpy(), plan, ws, flags, Ad
+
+
+# Accumulation error of one product of codes, per element, in code units:
+#   int8 / int4: none (exact integer sums);
+#   bf16: products exact in FP32, K - 1 FP32 additions in any order:
+#         |err| <= K 2^-24 sum|a b|;
+#   fp8:  the same, plus the gfx950 32x32x64 f8f6f4 MFMA's own addition of the
+#         64 products of one instruction, which is not IEEE-exact: 2^-14 of
+#         their absolute sum (a hardware constant, 4x the largest deviation
+#         seen on random operands by test_gemm_fp8_operands).
+ACC_REL = {"int8": 0.0, "int4": 0.0, "bf16": 1.0, "fp8": 1.0}
+
+
+def _check_product(name, out, Lc, dL, Rc, dR, fmt, col_first=False, alpha=1.0, c_bf16=False):
+    """GPU output of one product against its own codes: bit-exact for the
+    integer formats, within the accumulation bound (and two roundings of
+    the epilogue) for bf16 / fp8.  c_bf16: the output was rounded to bf16."""
+    acc = Lc @ Rc.T
+    if fmt == "bf16":   # no scales (the product ignores them)
+        dL, dR = np.ones(Lc.shape[0]), np.ones(Rc.shape[0])
+    f1, f2 = (dR[None, :], dL[:, None]) if col_first else (dL[:, None], dR[None, :])
+    ref = OQ.fl32(OQ.fl32(OQ.fl32(acc) * f1) * f2)
+    if alpha != 1.0:
+        ref = OQ.fl32(OQ.fl32(alpha) * ref)
+    if c_bf16:
+        ref = bf16_round(ref)
+    if fmt in ("int8", "int4") and not c_bf16:
+        assert np.array_equal(out, ref), f"{name}: {np.max(np.abs(out - ref))}"
+        return
+    K = Lc.shape[1]
+    S = np.abs(Lc) @ np.abs(Rc).T
+    eacc = ACC_REL[fmt] * (K * 2.0**-24 + (2.0**-14 if fmt == "fp8" else 0.0)) * S
+    ulps = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+    bound = eacc * np.abs(f1) * np.abs(f2) * abs(alpha) * (1 + 2.0**-22) + 3 * ulps
+    if c_bf16:
+        # the GPU rounds its own FP32 value to bf16: one bf16 ulp (at most
+        # 2^-7 of the magnitude) apart when the two straddle a rounding point
+        bound = bound + (np.abs(ref) + bound) * 2.0**-7
+    bad = np.abs(out - ref) > bound
+    assert not bad.any(), f"{name}: {bad.sum()} elements past the bound, worst {np.max(np.abs(out - ref) - bound)}"
+
+
+def _raw(plan, ws, name, A=None, rows=None):
+    """Codes (bytes, on the host; only the given rows), scales, K, format of
+    one quantised operand of the last forward."""
+    c, sc, K, f = plan.codes(ws, name, A)
+    if rows is not None:
+        c, sc = c[torch.as_tensor(rows, device=c.device)], sc[torch.as_tensor(rows, device=c.device)]
+    return c.cpu().numpy(), sc.cpu().numpy().astype(np.float64), K, f
+
+
+def _check_codes(name, raw, K, fmt, X_rows, mismatch=0):
+    """Codes the GPU wrote for the vectors that are the rows of X_rows
+    (binary32 values) equal the oracle quantiser's, bit for bit (up to
+    ``mismatch`` codes, for inputs that the two sides compute independently)."""
+    ref_c, ref_d = OQ.quantize_rows(X_rows, fmt)
+    got = codes_from(raw, fmt, K)[0]
+    assert np.sum(got != ref_c) <= mismatch, name
+    assert not pad_bytes(raw, fmt, K).any(), name
+    return got.astype(np.float64)
+
+
+def check_stages(lib, plan, ws, A, B, C, fmt, q, Ad=None, omega=None, omega_mismatch=0, alpha=1.0, sample=None,
+                 c_bf16=False):
+    """Every stage of the last forward on its own inputs (binary32 values as
+    float64 arrays A, B; C the GPU output): the codes of each quantised
+    operand against the oracle quantiser applied to the GPU's own input to
+    that quantiser, each product against the exact product of those codes,
+    and Q against Householder QR of the GPU's last sketch -- or, with
+    ``sample`` (row / column indices), every product on those rows or columns
+    of its output and Q's orthonormality and span at full size."""
+    fs, fp, f1, f2 = fmt
+    Y = plan.intermediate(ws, "Y").double().cpu().numpy()
+    Qg = plan.intermediate(ws, "Q").cpu().numpy()
+    Bt = plan.intermediate(ws, "Bt").double().cpu().numpy()
+    Tt = plan.intermediate(ws, "Tt").double().cpu().numpy()
+    l = Y.shape[1]
+    rows = np.arange(A.shape[0]) if sample is None else sample
+    cols = np.arange(A.shape[1]) if sample is None else sample
+    ncols = np.arange(B.shape[1]) if sample is None else sample
+    dec = lambda raw, f, K: codes_from(raw, f, K)[0].astype(np.float64)
+    # sketch: A by rows x (Omega or Q_Z) by columns -> Y
+    rawA, dLa, K, _ = _raw(plan, ws, "A_rows", Ad, rows)
+    La = _check_codes("A rows", rawA, K, fs, A[rows])
+    rawS, dRs, _, _ = _raw(plan, ws, "sketch_R")
+    Rs = dec(rawS, fs, K)
+    if q == 0 and omega is not None:
+        _check_codes("Omega", rawS, K, fs, omega.T, omega_mismatch)
+    _check_product("sketch", Y[rows], La, dLa, Rs, dRs, fs)
+    # orthonormalisation of the GPU's own last sketch
+    assert np.max(np.abs(Qg.T @ Qg - np.eye(l))) <= 1e-12
+    if sample is None:
+        Qh, _ = householder_qr(Y)
+        assert np.max(np.abs(Qg - Qh)) <= 1e-11
+    else:
+        assert np.linalg.norm(Y - Qg @ (Qg.T @ Y)) <= 1e-12 * np.linalg.norm(Y)
+    # projection: Q by columns x A by columns -> Bt (l x k)
+    rawQc, dLq, Kq, _ = _raw(plan, ws, "Q_cols")
+    Lq = _check_codes("Q cols", rawQc, Kq, fp, OQ.fl32(Qg).T)
+    rawAc, dRa, _, _ = _raw(plan, ws, "A_cols", rows=cols)
+    Ra = _check_codes("A cols", rawAc, Kq, fp, A.T[cols])
+    _check_product("projection", Bt[:, cols], Lq, dLq, Ra, dRa, fp)
+    # G1: B by columns x Bt by rows -> T^T (n x l), T's row factor first
+    rawBc, dLb, Kb, _ = _raw(plan, ws, "B_cols", rows=ncols)
+    Lb = _check_codes("B cols", rawBc, Kb, f1, B.T[ncols])
+    rawBt, dRb, _, _ = _raw(plan, ws, "Bt_rows")
+    Rb = _check_codes("Bt rows", rawBt, Kb, f1, Bt)
+    _check_product("G1", Tt[ncols], Lb, dLb, Rb, dRb, f1, col_first=True)
+    # G2: Q by rows x T^T by rows -> C
+    rawQr, dLr, Kl, _ = _raw(plan, ws, "Q_rows", rows=rows)
+    Lr = _check_codes("Q rows", rawQr, Kl, f2, OQ.fl32(Qg)[rows])
+    rawTt, dRt, _, _ = _raw(plan, ws, "Tt_rows")
+    Rt = _check_codes("Tt rows", rawTt, Kl, f2, Tt)
+    _check_product("G2", C[rows], Lr, dLr, Rt, dRt, f2, alpha=alpha, c_bf16=c_bf16)
 
 
 CASES = [
-    # m, k, n, r, p, q, tau, fmt
+    # m, k, n, r, p, q, tau, fmt[, noise]
     (512, 512, 512, 64, 10, 1, 32.0, ("int8",) * 4),     # the small plain-LRAMM configuration
     (512, 512, 512, 64, 10, 0, 32.0, ("int8",) * 4),
     (512, 512, 512, 64, 10, 2, 32.0, ("int8",) * 4),
@@ -368,77 +483,145 @@ CASES = [
     (640, 384, 512, 100, 12, 1, 40.0, ("int8", "int8", "int4", "int4")),
     (512, 512, 512, 64, 10, 1, 32.0, ("int4",) * 4),
     (2048, 4096, 512, 64, 16, 1, 64.0, ("int8",) * 4),   # long K: split-K products
+    # the at-scale workload (4096^3, l = 272 on 128 x 64 tiles and the
+    # one-launch Cholesky at l' = 288, entrywise noise)
+    (4096, 4096, 4096, 256, 16, 1, 128.0, ("int8",) * 4, 1e-4),
 ]
 
 
 @pytest.mark.parametrize("case", CASES)
 def test_lramm_forward_matches_oracle(lib, case):
-    m, k, n, r, p, q, tau, fmt = case
-    A, s = synth.lowrank(m, k, synth.spectrum("exp", min(m, k), tau), 0)
+    m, k, n, r, p, q, tau, fmt = case[:8]
+    noise = case[8] if len(case) > 8 else 0.0
+    print(f"forward case {m}x{k}x{n} r={r} p={p} q={q} {fmt}", flush=True)
+    A, s = synth.lowrank(m, k, synth.spectrum("exp", min(m, k), tau), 0, noise_var=noise)
     B = synth.gaussian(k, n, 100)
     om = synth.omega(k, r + p, 1)
-    C, plan, ws, flags = _run_forward(lib, A, B, r, p, q, fmt, omega=om)
-    ref = OL.lramm_forward(A.astype(np.float64), B.astype(np.float64), r, p, q, fmt, omega=om.astype(np.float64))
+    C, plan, ws, flags, Ad = _run_forward(lib, A, B, r, p, q, fmt, omega=om)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    check_stages(lib, plan, ws, A64, B64, C, fmt, q, Ad=Ad, omega=om.astype(np.float64))
+    ref = OL.lramm_forward(A64, B64, r, p, q, fmt, omega=om.astype(np.float64))
     err = OL.rel_fro(C, ref["C"])
     assert err <= 1e-5, err
     assert flags == 0
     Qg, Btg = plan.factors(ws)
-    Qg = Qg.cpu().numpy()
-    assert np.max(np.abs(Qg - ref["Q"])) <= 1e-11
+    assert np.max(np.abs(Qg.cpu().numpy() - ref["Q"])) <= 1e-11
     assert OL.rel_fro(Btg.cpu().numpy(), ref["Bt"]) <= 1e-5
 
 
+def test_lramm_bf16_input_l400_long_k(lib):
+    """bf16 inputs, l = 400 (the one-launch Cholesky at l' = 416), K = 8192,
+    int8 stages: against the independent oracle at 1e-5."""
+    m, k, n, r, p, q = 2048, 8192, 1024, 384, 16, 0
+    A, _ = synth.lowrank(m, k, synth.spectrum("exp", m, 64.0), 0, dtype="bf16")
+    B = synth.gaussian(k, n, 100, dtype="bf16")
+    om = synth.omega(k, r + p, 1)
+    C, plan, ws, flags, Ad = _run_forward(lib, A, B, r, p, q, ("int8",) * 4, omega=om, a_type=torch.bfloat16)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    check_stages(lib, plan, ws, A64, B64, C, ("int8",) * 4, q, Ad=Ad, omega=om.astype(np.float64))
+    ref = OL.lramm_forward(A64, B64, r, p, q, ("int8",) * 4, omega=om.astype(np.float64))
+    assert OL.rel_fro(C, ref["C"]) <= 1e-5
+    assert flags == 0
+
+
+@pytest.mark.parametrize("shape", ["rows", "block"])
+def test_lramm_rank_below_l(lib, shape):
+    """rank(A) = 40 < l = 74, with the dependence exact in every sketch: A has
+    40 nonzero rows ("rows", q = 0: each column of Y = A Omega lies in those
+    40 coordinates, so rounding cannot lift the rank), or a nonzero 40 x 40
+    block ("block", q = 1: Z = A^T Q as well).  CholeskyQR drops l - 40
+    columns of every orthonormalisation (zero Q columns, breakdown flag), and
+    the result equals the oracle that leaves dependent sketch columns out
+    the same way (not the completion vectors of a plain Householder QR, which
+    would change Q's row scales)."""
+    m = k = n = 512
+    rng = np.random.default_rng(12)
+    A = np.zeros((m, k), np.float32)
+    if shape == "rows":
+        A[:40, :] = rng.standard_normal((40, k)).astype(np.float32)
+        q = 0
+    else:
+        A[:40, :40] = rng.standard_normal((40, 40)).astype(np.float32)
+        q = 1
+    B = synth.gaussian(k, n, 112)
+    om = synth.omega(k, 74, 13)
+    fmt = ("int8",) * 4
+    C, plan, ws, flags, Ad = _run_forward(lib, A, B, 64, 10, q, fmt, omega=om)
+    assert flags & lib.FLAG_BREAKDOWN
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    ref = OL.lramm_forward(A64, B64, 64, 10, q, fmt, omega=om.astype(np.float64), drop_dependent=True)
+    assert all(len(d) == 74 - 40 for d in ref["dropped"])
+    Qg = plan.factors(ws)[0].cpu().numpy()
+    dead = ref["dropped"][-1]
+    assert not Qg[:, dead].any()
+    assert np.max(np.abs(Qg - ref["Q"])) <= 1e-11
+    assert OL.rel_fro(C, ref["C"]) <= 1e-5
+    keep = [j for j in range(74) if j not in dead]
+    assert np.max(np.abs(Qg[:, keep].T @ Qg[:, keep] - np.eye(len(keep)))) <= 1e-12
+
+
 FP_CASES = [
-    (512, 512, 512, 64, 10, 1, 32.0, ("bf16",) * 4),
-    (512, 512, 512, 64, 10, 1, 32.0, ("fp8",) * 4),
-    (300, 257, 190, 20, 5, 1, 12.0, ("fp8",) * 4),
-    (640, 384, 512, 100, 12, 1, 40.0, ("int8", "int8", "fp8", "fp8")),
-    (640, 384, 512, 100, 12, 0, 40.0, ("bf16", "bf16", "int8", "int8")),
+    # m, k, n, r, p, q, tau, fmt, io dtype, seeded Omega
+    (512, 512, 512, 64, 10, 1, 32.0, ("bf16",) * 4, torch.float32, False),
+    (512, 512, 512, 64, 10, 1, 32.0, ("fp8",) * 4, torch.float32, False),
+    (300, 257, 190, 20, 5, 1, 12.0, ("fp8",) * 4, torch.float32, False),
+    (640, 384, 512, 100, 12, 1, 40.0, ("int8", "int8", "fp8", "fp8"), torch.float32, False),
+    (640, 384, 512, 100, 12, 0, 40.0, ("bf16", "bf16", "int8", "int8"), torch.float32, False),
+    # bf16 inputs straight into the bf16 sketch, Omega generated on the GPU
+    (1024, 2048, 512, 200, 16, 0, 48.0, ("bf16",) * 4, torch.bfloat16, True),
+    (1024, 2048, 512, 120, 16, 1, 48.0, ("bf16",) * 4, torch.bfloat16, True),
+    (700, 1536, 300, 90, 10, 0, 32.0, ("int8", "bf16", "bf16", "bf16"), torch.bfloat16, True),
 ]
-# rel-F of one replayed stage (FP32 accumulation in the MFMA's own order;
-# the fp8 MFMA adds within an instruction at reduced precision)
-STAGE_TOL = {"int8": 1e-6, "int4": 1e-6, "bf16": 1e-5, "fp8": 1e-4}
-# end to end against the independent oracle: the stage differences move
-# values across quantiser rounding boundaries (one code step each), and the
-# sketch directions that the quantisation noise dominates rotate with them;
-# measured 1.2e-3 (bf16 stages) and 2.5e-2 (fp8 in every stage)
-INDEP_TOL = {"int8": 1e-5, "int4": 1e-5, "bf16": 5e-3, "fp8": 6e-2}
 
 
 @pytest.mark.parametrize("case", FP_CASES)
 def test_lramm_forward_fp_formats(lib, case):
-    """Formats with FP32 accumulation: every stage is replayed from the GPU's
-    own input to that stage (the quantiser codes then agree bit for bit and
-    only the accumulation order differs), and the end result is compared
-    with the independent oracle at a looser tolerance."""
-    m, k, n, r, p, q, tau, fmt = case
-    A, s = synth.lowrank(m, k, synth.spectrum("exp", min(m, k), tau), 0)
-    B = synth.gaussian(k, n, 100)
-    om = synth.omega(k, r + p, 1)
-    C, plan, ws, flags = _run_forward(lib, A, B, r, p, q, fmt, omega=om)
-    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    """Formats with FP32 accumulation: the MFMA's order of FP32 additions
+    cannot be replayed, so every stage is checked on the GPU's own inputs
+    (codes bit-exact, each product within its accumulation bound).  The end
+    result against the independent oracle is reported, and both must be
+    equally good approximations of the exact product (within a factor 2)."""
+    m, k, n, r, p, q, tau, fmt, io, seeded = case
+    dt = "bf16" if io == torch.bfloat16 else "fp32"
+    A, s = synth.lowrank(m, k, synth.spectrum("exp", min(m, k), tau), 0, dtype=dt)
+    B = synth.gaussian(k, n, 100, dtype=dt)
+    om = None if seeded else synth.omega(k, r + p, 1)
+    C, plan, ws, flags, Ad = _run_forward(lib, A, B, r, p, q, fmt, omega=om, seed=3, a_type=io)
     assert flags == 0
-    l = r + p
-    Y = plan.intermediate(ws, "Y").double().cpu().numpy()
-    Qg = plan.intermediate(ws, "Q").cpu().numpy()
-    Btg = plan.intermediate(ws, "Bt").double().cpu().numpy()
-    Tg = plan.intermediate(ws, "Tt").double().cpu().numpy().T
-    # orthonormalisation of the GPU's last sketch
-    Qh, _ = householder_qr(Y)
-    assert np.max(np.abs(Qg - Qh)) <= 1e-11
-    assert np.max(np.abs(Qg.T @ Qg - np.eye(l))) <= 1e-12
-    # the three products, each on the GPU's own operands
-    assert OL.rel_fro(Btg, OL._product(Qg.T, A64, fmt[1])) <= STAGE_TOL[fmt[1]]
-    assert OL.rel_fro(Tg, OL._product(Btg, B64, fmt[2])) <= STAGE_TOL[fmt[2]]
-    assert OL.rel_fro(C, OL._product(Qg, Tg, fmt[3])) <= STAGE_TOL[fmt[3]]
-    ref = OL.lramm_forward(A64, B64, r, p, q, fmt, omega=om.astype(np.float64))
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    om64 = OP.gaussian_omega(3, k, r + p).astype(np.float32).astype(np.float64) if seeded else \
+        om.astype(np.float64)
+    check_stages(lib, plan, ws, A64, B64, C, fmt, q, Ad=Ad, omega=om64, omega_mismatch=2 if seeded else 0)
+    ref = OL.lramm_forward(A64, B64, r, p, q, fmt, omega=om64)
     err = OL.rel_fro(C, ref["C"])
-    print(f"fmt {fmt}: end-to-end rel-F vs oracle {err:.3e}")
-    assert err <= max(INDEP_TOL[f] for f in fmt)
-    # and the two are equally good approximations of the exact product
     Cex = A64 @ B64
     e_gpu, e_ref = OL.rel_fro(C, Cex), OL.rel_fro(ref["C"], Cex)
-    assert abs(e_gpu - e_ref) <= 0.05 * e_ref, (e_gpu, e_ref)
+    print(f"fmt {fmt}: end-to-end rel-F vs oracle {err:.3e}; vs exact gpu {e_gpu:.3e} oracle {e_ref:.3e}")
+    assert e_gpu <= 2.0 * e_ref and e_ref <= 2.0 * e_gpu, (e_gpu, e_ref)
+
+
+def test_target_workload_sampled_stages(lib):
+    """The headline workload at full size (8192^3 bf16, sigma_i = exp(-i/64),
+    l = 448, q = 0, bf16 in every stage, Omega from the seed), in the launch
+    configuration the bench times: every stage checked on 96 sampled rows /
+    columns of its output against its own codes, and Q's orthonormality and
+    span at full size."""
+    m = k = n = 8192
+    A, _ = synth.lowrank(m, k, synth.spectrum("exp", m, 64.0), 0, dtype="bf16")
+    B = synth.gaussian(k, n, 100, dtype="bf16")
+    fmt = ("bf16",) * 4
+    plan = lib.LrammPlan(m, n, k, 416, 32, 0, fmt, torch.bfloat16, torch.bfloat16, torch.bfloat16, 1,
+                         exclusive=True)
+    ws = plan.workspace()
+    Ad, Bd = g(A, torch.bfloat16), g(B, torch.bfloat16)
+    C = plan.forward(Ad, Bd, ws)
+    assert plan.status(ws) == 0
+    rng = np.random.default_rng(5)
+    sample = np.sort(rng.choice(8192, 96, replace=False))
+    om = OP.gaussian_omega(1, k, 448).astype(np.float32).astype(np.float64)
+    Cs = C.float().cpu().numpy().astype(np.float64)
+    check_stages(lib, plan, ws, A.astype(np.float64), B.astype(np.float64), Cs, fmt, 0, Ad=Ad, omega=om,
+                 omega_mismatch=3, sample=sample, c_bf16=True)
 
 
 def test_lramm_seeded_omega_and_alpha_beta(lib):
@@ -446,7 +629,7 @@ def test_lramm_seeded_omega_and_alpha_beta(lib):
     A, _ = synth.lowrank(m, k, synth.spectrum("exp", 384, 24.0), 3)
     B = synth.gaussian(k, n, 103)
     Cin = synth.gaussian(m, n, 7)
-    C, _, _, _ = _run_forward(lib, A, B, 48, 8, 1, ("int8",) * 4, seed=77, alpha=0.75, beta=0.5, Cin=Cin)
+    C, *_ = _run_forward(lib, A, B, 48, 8, 1, ("int8",) * 4, seed=77, alpha=0.75, beta=0.5, Cin=Cin)
     ref = OL.lramm_forward(A.astype(np.float64), B.astype(np.float64), 48, 8, 1, seed=77, alpha=0.75, beta=0.5,
                            Cin=Cin.astype(np.float64))
     assert OL.rel_fro(C, ref["C"]) <= 1e-5
@@ -457,7 +640,7 @@ def test_lramm_bf16_io(lib):
     A, _ = synth.lowrank(m, k, synth.spectrum("exp", 512, 32.0), 0, dtype="bf16")
     B = synth.gaussian(k, n, 100, dtype="bf16")
     om = synth.omega(k, 74, 1)
-    C, _, _, _ = _run_forward(lib, A, B, 64, 10, 1, ("int8",) * 4, omega=om, a_type=torch.bfloat16,
+    C, *_ = _run_forward(lib, A, B, 64, 10, 1, ("int8",) * 4, omega=om, a_type=torch.bfloat16,
                               c_type=torch.bfloat16)
     ref = OL.lramm_forward(A.astype(np.float64), B.astype(np.float64), 64, 10, 1, omega=om.astype(np.float64))
     assert OL.rel_fro(C, bf16_round(ref["C"])) <= 1e-5
@@ -467,8 +650,8 @@ def test_lramm_deterministic(lib):
     m = k = n = 512
     A, _ = synth.lowrank(m, k, synth.spectrum("exp", 512, 32.0), 0)
     B = synth.gaussian(k, n, 100)
-    C1, _, _, _ = _run_forward(lib, A, B, 64, 10, 1, ("int8",) * 4, seed=5)
-    C2, _, _, _ = _run_forward(lib, A, B, 64, 10, 1, ("int8",) * 4, seed=5)
+    C1, *_ = _run_forward(lib, A, B, 64, 10, 1, ("int8",) * 4, seed=5)
+    C2, *_ = _run_forward(lib, A, B, 64, 10, 1, ("int8",) * 4, seed=5)
     assert np.array_equal(C1, C2)
 
 
