@@ -1,24 +1,33 @@
 #!/usr/bin/env python3
-"""Throughput of the LRAMM hot path on one MI355X.
+"""Throughput of the LRAMM hot path on one MI355X, at fixed accuracy.
 
 A step is one full forward pass of the method over one batch of synthetic
-input that is already resident in HBM: quantisation of A and B, the seeded
-Gaussian test matrix, the sketch, CholeskyQR2, the power iterations, the
-projection and the two quantised products (all stages of the library's
-lramm_forward).  Default workload: A, B 4096 x 4096 FP32, A with singular
-values exp(-i/128) plus entrywise noise of variance 1e-4 (relative to unit-RMS
-entries), B ~ N(0, 1); r = 256, p = 16, q = 1, int8 in every stage.
+input already resident in HBM: the seeded Gaussian test matrix and its codes,
+the sketch, CholeskyQR2, the power iterations, the projection, every
+quantisation (or bf16 rounding) and the two chained products (all stages of
+the library's lramm_forward).
 
-Prints ONE JSON line: effective 2 m n k / s, per-stage times (HIP events on
-the launch stream inside the timed region), the roofline of the dominant
-kernel, the dense bf16 / fp32 comparators on the same GPU, the error against
-the exact FP64 product and against the FP64 oracle, and the oracle's own
-time on the host cores (cpu_baseline).
+Default workload (the headline): A, B 8192 x 8192 bf16, A = U diag(sigma) V^T
+with Haar U, V and sigma_i = exp(-i/64), B ~ N(0, 1); the fastest setting
+(sketch width l = r + p, power iterations q, per-stage formats) whose
+relative Frobenius error against the exact product of the bf16 inputs is at
+most 1e-2, as found by ``--sweep``.  The same is reported for decay rates 128
+and 256 (``other_decays``), next to the hand-written dense bf16 GEMM on the
+same inputs and the dense bf16 roofline.
 
-    python bench.py [--steps K] [--warmup W] [--r 256] [--q 1] [--fmt int8]
+Prints ONE JSON line: effective 2 m n k / s, speedups, per-stage times (HIP
+events on the launch stream in a second, instrumented region), the roofline
+of the kernel with the largest share of the step, the error against the
+exact FP64 product and against the FP64 oracle with the Eckart-Young floor,
+and the oracle's own time on the host cores (cpu_baseline).
+
+    python bench.py [--steps K] [--warmup W] [--tau 64] [--l 448 --q 0 --fmt bf16]
+    python bench.py --sweep [--taus 64,128,256]     # the setting search
+    python bench.py --workload at-scale             # 4096^3 FP32 int8 (throughput / parity workload)
 """
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -29,8 +38,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "effective 2MNK/s + speedup vs dense GEMM at fixed rel-Frobenius error (1 GPU)"
-PEAK = {"int8": 5.03e15, "int4": 5.03e15, "bf16": 2.52e15, "fp32": 157.3e12, "fp64": 78.6e12}
+PEAK = {"int8": 5.03e15, "int4": 5.03e15, "fp8": 5.03e15, "bf16": 2.52e15, "fp32": 157.3e12, "fp64": 78.6e12}
 HBM = 8.0e12
+TARGET_RELF = 1e-2
+
+# Fastest setting per decay rate with rel-F <= 1e-2 on 8192^3 bf16, from
+# ``bench.py --sweep`` (summary: profiles/target_8192_setting_sweep.md):
+# (l, p, q, formats).  None: no setting within l <= 1024 reaches 1e-2; the
+# closest one is reported instead.
+BEST = {
+    64.0: (448, 32, 0, ("bf16",) * 4),
+    128.0: (896, 32, 0, ("bf16",) * 4),
+    256.0: None,
+}
+CLOSEST = {256.0: (1024, 32, 1, ("bf16",) * 4)}
+
+SWEEP = {
+    64.0: [256, 320, 384, 416, 448, 480, 512],
+    128.0: [512, 640, 768, 896, 1024],
+    256.0: [768, 896, 1024],
+}
+SWEEP_FMTS = {"bf16": ("bf16",) * 4, "int8_sketch": ("int8", "bf16", "bf16", "bf16"),
+              "fp8": ("fp8",) * 4, "int8": ("int8",) * 4}
 
 
 def parse():
@@ -38,18 +67,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--m", type=int, default=4096)
-    ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--k", type=int, default=4096)
-    ap.add_argument("--r", type=int, default=256)
-    ap.add_argument("--p", type=int, default=16)
-    ap.add_argument("--q", type=int, default=1)
-    ap.add_argument("--tau", type=float, default=128.0)
-    ap.add_argument("--noise", type=float, default=1e-4)
-    ap.add_argument("--fmt", default="int8", help="one format for every stage, or four comma-separated")
+    ap.add_argument("--workload", default="target", choices=["target", "at-scale"])
+    ap.add_argument("--tau", type=float, default=None, help="decay rate of sigma_i = exp(-i/tau)")
+    ap.add_argument("--l", type=int, default=None, help="sketch width l = r + p (with --q and --fmt)")
+    ap.add_argument("--p", type=int, default=None)
+    ap.add_argument("--q", type=int, default=None)
+    ap.add_argument("--fmt", default=None, help="one format for every stage, or four comma-separated")
+    ap.add_argument("--sweep", action="store_true", help="search (l, q, formats) per decay rate")
+    ap.add_argument("--taus", default="64,128,256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--no-other-decays", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="finish with one plain device copy of MIB MiB (reference for HBM byte counters)")
     return ap.parse_args()
@@ -59,55 +88,103 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# Stages whose timed region is one kernel launch (the roofline is reported
-# for the dominant one); composite stages (the whole orthonormalisation,
-# column quantisers with their max / quantise / scale kernels) are excluded.
-SINGLE_KERNEL = ("sketch_gemm", "power_gemm_Z", "power_gemm_Y", "proj_gemm", "g1_gemm", "g2_gemm",
-                 "quant_A_rows", "quant_Bt_rows", "quant_Q_rows", "quant_Tt_rows", "cholqr2.gram",
-                 "cholqr2.chol_panel", "cholqr2.solve", "cholqr2.series", "cholqr2.apply")
+# ------------------------------------------------------------ workloads --
+
+def make_inputs(workload, tau, dev):
+    """(A, B on the GPU, A and B as float64 host arrays, info) for a workload.
+    info holds the spectrum of A's low-rank part in the units of A, the
+    Frobenius norm of A and of the rounding or noise added to it."""
+    import numpy as np
+    import torch
+
+    import synth
+    t = time.time()
+    if workload == "target":
+        m = n = k = 8192
+        A32, sigma = synth.lowrank(m, k, synth.spectrum("exp", min(m, k), tau), 0, dtype="fp32")
+        A_np = synth.to_dtype(A32, "bf16")
+        B_np = synth.gaussian(k, n, 100, dtype="bf16")
+        dt = torch.bfloat16
+        pert = float(np.linalg.norm(A_np.astype(np.float64) - A32.astype(np.float64)))
+        del A32
+    else:
+        m = n = k = 4096
+        info0 = {}
+        A_np, sigma = synth.lowrank(m, k, synth.spectrum("exp", min(m, k), tau), 0, noise_var=1e-4, info=info0)
+        B_np = synth.gaussian(k, n, 100)
+        dt = torch.float32
+        pert = info0["noise_fro"]
+    log(f"inputs ({workload}, tau {tau:g}) generated in {time.time() - t:.1f}s")
+    A = torch.from_numpy(A_np).to(dev).to(dt)
+    B = torch.from_numpy(B_np).to(dev).to(dt)
+    A64, B64 = A_np.astype(np.float64), B_np.astype(np.float64)
+    info = {"sigma": sigma, "A_fro": float(np.linalg.norm(A64)), "perturbation_fro": pert, "dtype": dt}
+    return A, B, A64, B64, info
 
 
-# HBM bytes per launch of the dominant kernel, from two rocprofv3 counter
-# passes (FETCH_SIZE, WRITE_SIZE) of this bench's default workload, scaled by
-# the same counters on a plain device copy; recorded with a hash of the
-# kernel's source file and reported only while that file is unchanged.
-TRAFFIC = {"cholqr2.chol_panel": ("profiles/chol_panel_4096_r256_q1_int8_hbm_traffic.md",
-                                  "paper_2405_16917_amd/csrc/cholqr.hip")}
+def exact_product(A64, B64):
+    t = time.time()
+    C = A64 @ B64
+    log(f"exact FP64 product in {time.time() - t:.1f}s")
+    return C
 
 
-def measured_traffic(stage):
-    if stage not in TRAFFIC:
-        return None
-    summary, src = (os.path.join(ROOT, x) for x in TRAFFIC[stage])
-    try:
-        import hashlib
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        fields = {}
-        for line in open(summary):
-            if ":" in line and line.strip().startswith(("source_sha256", "traffic_bytes_per_launch")):
-                key, val = line.split(":", 1)
-                fields[key.strip()] = val.strip().strip("`")
-        if fields.get("source_sha256") != digest:
-            return None
-        return float(fields["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
-        return None
+def run_setting(lramm, A, B, setting, steps, warmup, seed=1, timing=False):
+    """Time `steps` forwards of one setting; returns (ms per step, C, plan, ws)."""
+    import torch
+    l, p, q, fmt = setting
+    m, k = A.shape
+    n = B.shape[1]
+    plan = lramm.LrammPlan(m, n, k, l - p, p, q, fmt, A.dtype, B.dtype, A.dtype, seed, exclusive=True)
+    ws = plan.workspace(A.device)
+    C = torch.empty((m, n), dtype=A.dtype, device=A.device)
+    for _ in range(warmup):
+        plan.forward(A, B, ws, C=C)
+    torch.cuda.synchronize()
+    plan.status(ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.forward(A, B, ws, C=C)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    plan.status(ws)
+    return ms, C, plan, ws
 
 
-def stage_work(name, m, n, k, l, fmt, q):
-    """Algorithmic work of ONE launch of a stage: (ops, bytes, peak key).
+def rel_errors(C, Cex, nrm):
+    import numpy as np
+    Cg = C.double().cpu().numpy()
+    d = Cg - Cex
+    return float(np.linalg.norm(d) / nrm), float(np.max(np.abs(d))), Cg
 
-    GEMM ops count 2 M N K; bytes count each operand read once and the
-    output written once.  Quantiser bytes count the FP input read once and
-    the codes written.  FP64 orthonormalisation (rows = m = k here, l' = l
-    rounded up to 32): Gram rows * l * (l + 1) flops (symmetric) reading X
-    once; Cholesky plus block inverse 2 l'^3 / 3 flops per factorisation
-    (split over its launches by the caller); the two solve products rows * l^2 flops (triangular factor)
-    reading X and writing Q; the expansion 2 l^3 flops."""
+
+def floors(info, r, l):
+    """Eckart-Young floors of the low-rank part of A (relative to ||A||_F):
+    sigma_{r+1}, the rank-r and rank-l tails; and the size of what was added
+    to it (bf16 rounding or entrywise noise)."""
+    import numpy as np
+    s = np.sort(np.asarray(info["sigma"], np.float64))[::-1]
+    a = info["A_fro"]
+    return {"sigma_r1_rel": float(s[r] / a) if r < len(s) else 0.0,
+            "tail_rank_r_rel": float(math.sqrt(float(np.sum(s[r:] ** 2))) / a),
+            "tail_rank_l_rel": float(math.sqrt(float(np.sum(s[l:] ** 2))) / a),
+            "perturbation_rel": info["perturbation_fro"] / a}
+
+
+# ----------------------------------------------------- measurement work --
+
+def stage_work(name, m, n, k, l, fmt, c_bytes):
+    """Algorithmic work of ONE launch of a stage: (flops, bytes, peak key).
+
+    GEMM: 2 M N K flops; bytes = each operand read once (1 byte per int8 /
+    fp8 code, 1/2 for int4, 2 for bf16) and the output written once.
+    Quantisers: the input read once and the codes written.  FP64
+    orthonormalisation: the Gram rows * l * (l + 1) flops over its lower
+    half; the Cholesky l^3 / 3 per factorisation (the unpadded l, no inverse);
+    the solve and the second-pass product rows * l^2."""
     fs, fp, f1, f2 = fmt
-    cb = {"int8": 1.0, "int4": 0.5, "bf16": 2.0}
-    lw = (l + 31) // 32 * 32
-    rows = m
+    cb = {"int8": 1.0, "int4": 0.5, "fp8": 1.0, "bf16": 2.0}
     if name in ("sketch_gemm", "power_gemm_Y"):
         return 2.0 * m * l * k, m * k * cb[fs] + l * k * cb[fs] + m * l * 4, fs
     if name == "power_gemm_Z":
@@ -117,28 +194,137 @@ def stage_work(name, m, n, k, l, fmt, q):
     if name == "g1_gemm":
         return 2.0 * n * l * k, n * k * cb[f1] + l * k * cb[f1] + n * l * 4, f1
     if name == "g2_gemm":
-        return 2.0 * m * n * l, m * l * cb[f2] + n * l * cb[f2] + m * n * 4, f2
-    if name == "quant_A_rows":
-        return 0.0, m * k * 4 + m * k * cb[fs], None
-    if name == "quant_Bt_rows":
-        return 0.0, l * k * 4 + l * k * cb[f1], None
-    if name == "quant_Q_rows":
-        return 0.0, m * l * 8 + m * l * cb[f2], None
-    if name == "quant_Tt_rows":
-        return 0.0, n * l * 4 + n * l * cb[f2], None
-    if name == "cholqr2.gram":          # average over the FP32 (Y) and FP64 (Q1) inputs
-        return rows * l * (l + 1.0), rows * l * 6.0, "fp64"
+        return 2.0 * m * n * l, m * l * cb[f2] + n * l * cb[f2] + m * n * c_bytes, f2
+    if name == "cholqr2.gram":
+        return m * l * (l + 1.0), m * l * 6.0, "fp64"
     if name == "cholqr2.chol_panel":
-        # one Cholesky + block inverse (l'^3/3 + l'^3/3 flops; G's lower half
-        # read once, L's and L^-1's lower halves written once); the caller
-        # divides by the launches per Cholesky it measured (one for the
-        # one-launch chain)
-        return 2.0 * lw ** 3 / 3.0, 1.5 * lw * lw * 8, "fp64"
+        return l ** 3 / 3.0, l * l * 8.0, "fp64"
     if name in ("cholqr2.solve", "cholqr2.apply"):
-        return rows * l * float(l), rows * l * (4.0 + 8.0), "fp64"
-    if name == "cholqr2.series":
-        return 2.0 * l ** 3, 2.0 * lw * lw * 8, "fp64"
+        return m * l * float(l), m * l * (4.0 + 8.0), "fp64"
     return 0.0, 0.0, None
+
+
+KERNEL_OF = {"sketch_gemm": "gemm_nt_kernel", "power_gemm_Z": "gemm_nt_kernel", "power_gemm_Y": "gemm_nt_kernel",
+             "proj_gemm": "gemm_nt_kernel", "g1_gemm": "gemm_nt_kernel", "g2_gemm": "gemm_nt_kernel",
+             "cholqr2.gram": "gram_kernel", "cholqr2.chol_panel": "chol_chain_kernel",
+             "cholqr2.solve": "tsmul_kernel", "cholqr2.apply": "tsmul_kernel"}
+
+# HBM bytes per launch of a kernel at the headline setting, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes scaled by the same counters on a plain
+# device copy; reported only while the kernel's source is unchanged.
+TRAFFIC = {"gemm_nt_kernel": ("profiles/target_8192_l448_bf16_hbm_traffic.md",
+                              "paper_2405_16917_amd/csrc/gemm_nt.hip"),
+           "chol_chain_kernel": ("profiles/target_8192_l448_bf16_hbm_traffic.md",
+                                 "paper_2405_16917_amd/csrc/cholqr.hip")}
+
+
+def measured_traffic(kernel):
+    if kernel not in TRAFFIC:
+        return None
+    summary, src = (os.path.join(ROOT, x) for x in TRAFFIC[kernel])
+    try:
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        fields = {}
+        for line in open(summary):
+            if ":" in line and line.strip().startswith((kernel + ".",)):
+                key, val = line.split(":", 1)
+                fields[key.strip()] = val.strip().strip("`")
+        if fields.get(kernel + ".source_sha256") != digest:
+            return None
+        return float(fields[kernel + ".traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def roofline(stage_ms, m, n, k, l, fmt, c_bytes):
+    """Roofline of the kernel with the largest time per step: its algorithmic
+    work per launch over its average event-measured launch duration, against
+    the MI355X peak of its bound (intensity against the ridge point of its
+    dtype)."""
+    per_kernel = {}
+    for st, (ms, cnt) in stage_ms.items():
+        kern = KERNEL_OF.get(st)
+        if kern is None or cnt <= 0:
+            continue
+        fl, by, pk = stage_work(st, m, n, k, l, fmt, c_bytes)
+        e = per_kernel.setdefault(kern, {"ms": 0.0, "launches": 0.0, "flops": 0.0, "bytes": 0.0, "peak": pk})
+        e["ms"] += ms
+        e["launches"] += cnt
+        e["flops"] += fl * cnt
+        e["bytes"] += by * cnt
+    out = {}
+    for kern, e in per_kernel.items():
+        launch_ms = e["ms"] / e["launches"]
+        fl, by = e["flops"] / e["launches"], e["bytes"] / e["launches"]
+        pk = e["peak"]
+        if fl > 0 and fl / by >= PEAK[pk] / HBM:
+            r = {"bound": "mfma", "achieved": fl / (launch_ms * 1e-3) / 1e12, "peak": PEAK[pk] / 1e12,
+                 "unit": "TFLOP/s"}
+        else:
+            r = {"bound": "hbm", "achieved": by / (launch_ms * 1e-3) / 1e9, "peak": HBM / 1e9, "unit": "GB/s"}
+        r["frac"] = r["achieved"] / r["peak"]
+        r.update(kernel=kern, peak_dtype=pk, launch_ms=launch_ms, launches_per_step=e["launches"],
+                 ms_per_step=e["ms"], flops_per_launch=fl, bytes_per_launch=by)
+        out[kern] = r
+    dom = max(out, key=lambda kk: out[kk]["ms_per_step"])
+    top = dict(out[dom])
+    tb = measured_traffic(dom)
+    top["traffic"] = tb
+    return top, out
+
+
+# ------------------------------------------------------------- the runs --
+
+def dense_bf16(lramm, A, B, reps=10):
+    """The hand-written dense bf16 NT-GEMM on the same inputs (B transposed
+    beforehand, outside the timing): ms per product and its C (FP32)."""
+    import torch
+    Bt = B.t().contiguous()
+    m, n = A.shape[0], B.shape[1]
+    Cd = torch.empty((m, n), dtype=torch.float32, device=A.device)
+    for _ in range(2):
+        lramm.lramm_dense_gemm_nt(A, Bt, Cd)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        lramm.lramm_dense_gemm_nt(A, Bt, Cd)
+    e1.record()
+    torch.cuda.synchronize()
+    del Bt
+    return e0.elapsed_time(e1) / reps, Cd
+
+
+def sweep(args, lramm, dev):
+    import torch
+    taus = [float(x) for x in args.taus.split(",")]
+    best = {}
+    for tau in taus:
+        A, B, A64, B64, info = make_inputs("target", tau, dev)
+        Cex = exact_product(A64, B64)
+        import numpy as np
+        nrm = float(np.linalg.norm(Cex))
+        cands = []
+        for l in SWEEP.get(tau, SWEEP[64.0]):
+            for q in (0, 1):
+                for fname, fmt in SWEEP_FMTS.items():
+                    setting = (l, 32, q, fmt)
+                    try:
+                        ms, C, plan, ws = run_setting(lramm, A, B, setting, 5, 2)
+                    except lramm.LrammError as e:
+                        print(json.dumps({"tau": tau, "l": l, "q": q, "fmt": fname, "error": str(e)}), flush=True)
+                        continue
+                    e, mx, _ = rel_errors(C, Cex, nrm)
+                    row = {"tau": tau, "l": l, "q": q, "fmt": fname, "ms": round(ms, 4), "rel_fro": e, "max_abs": mx}
+                    print(json.dumps(row), flush=True)
+                    cands.append(row)
+                    del plan, ws, C
+                    torch.cuda.empty_cache()
+        ok = [c for c in cands if c["rel_fro"] <= TARGET_RELF]
+        pick = min(ok, key=lambda c: c["ms"]) if ok else min(cands, key=lambda c: c["rel_fro"])
+        best[tau] = dict(pick, reaches_target=bool(ok))
+        del A, B, A64, B64, Cex
+    print(json.dumps({"sweep_best": best}), flush=True)
 
 
 def main():
@@ -151,136 +337,114 @@ def main():
     import torch
 
     import paper_2405_16917_amd as lramm
-    import synth
 
     lramm.load()
     lramm.lramm_init()
-    m, n, k, r, p, q = args.m, args.n, args.k, args.r, args.p, args.q
-    l = r + p
-    fmt = tuple(args.fmt.split(",")) if "," in args.fmt else (args.fmt,) * 4
     dev = torch.device("cuda:0")
+    if args.sweep:
+        sweep(args, lramm, dev)
+        return
 
-    t = time.time()
-    A_np, sigma = synth.lowrank(m, k, synth.spectrum("exp", min(m, k), args.tau), 0, noise_var=args.noise)
-    B_np = synth.gaussian(k, n, 100)
-    log(f"inputs generated in {time.time() - t:.1f}s")
-    A = torch.from_numpy(A_np).to(dev)
-    B = torch.from_numpy(B_np).to(dev)
+    if args.workload == "target":
+        tau = 64.0 if args.tau is None else args.tau
+        setting = BEST.get(tau) or CLOSEST.get(tau) or BEST[64.0]
+    else:
+        tau = 128.0 if args.tau is None else args.tau
+        setting = (272, 16, 1, ("int8",) * 4)
+    if args.l is not None:
+        p = args.p if args.p is not None else setting[1]
+        fmt = tuple(args.fmt.split(",")) if args.fmt and "," in args.fmt else ((args.fmt,) * 4 if args.fmt
+                                                                                else setting[3])
+        setting = (args.l, p, args.q if args.q is not None else setting[2], fmt)
+    l, p, q, fmt = setting
+    r = l - p
+
+    A, B, A64, B64, info = make_inputs(args.workload, tau, dev)
+    m, k = A.shape
+    n = B.shape[1]
+    c_bytes = 2 if A.dtype == torch.bfloat16 else 4
     seed = 1
-
-    plan = lramm.LrammPlan(m, n, k, r, p, q, fmt, torch.float32, torch.float32, torch.float32, seed)
-    ws = plan.workspace(dev)
-    C = torch.empty((m, n), dtype=torch.float32, device=dev)
-    for _ in range(args.warmup):
-        plan.forward(A, B, ws, C=C)
-    torch.cuda.synchronize()
-    plan.status(ws)
     # timed region: K whole forward passes, no instrumentation
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.forward(A, B, ws, C=C)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    flags = plan.status(ws)
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_step, C, plan, ws = run_setting(lramm, A, B, setting, args.steps, args.warmup, seed)
     value = 2.0 * m * n * k / (ms_step * 1e-3) / 1e12
-    log(f"LRAMM {ms_step:.3f} ms/step, effective {value:.1f} TFLOP/s, flags {flags}")
-    # second timed region of K passes with HIP events around every stage and
-    # every launch of the orthonormalisation, recorded on the launch stream
-    plan.stage_times()                          # clear anything recorded so far
+    log(f"LRAMM {ms_step:.3f} ms/step, effective {value:.1f} TFLOP/s")
+    # second region with HIP events around every stage and every launch of
+    # the orthonormalisation, recorded on the stream that launches them
+    plan.stage_times()
     plan.set_timing(True)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for _ in range(args.steps):
         plan.forward(A, B, ws, C=C)
     torch.cuda.synchronize()
-    t3 = time.perf_counter()
+    ms_instr = (time.perf_counter() - t2) * 1e3 / args.steps
     plan.set_timing(False)
     stages = plan.stage_times()
-    ms_step_instr = (t3 - t2) * 1e3 / args.steps
-
     stage_ms = {kk: (v[0] / args.steps, v[1] / args.steps) for kk, v in stages.items() if v[1]}
-    # roofline of the dominant single-kernel stage
-    cand = [st for st in stage_ms if st in SINGLE_KERNEL]
-    dom = max(cand, key=lambda st: stage_ms[st][0])
-    ops, byt, pk = stage_work(dom, m, n, k, l, fmt, q)
-    per_launch_ms = stage_ms[dom][0] / max(1e-9, stage_ms[dom][1])
-    if dom == "cholqr2.chol_panel":
-        # work per Cholesky -> per launch: 1 + 2q Cholesky factorisations per forward
-        per_chol = stage_ms[dom][1] / (1 + 2 * q)
-        ops, byt = ops / per_chol, byt / per_chol
-    if pk is not None and ops > 0 and (ops / byt) >= PEAK[pk] / HBM:
-        roof = {"bound": "mfma", "achieved": ops / (per_launch_ms * 1e-3) / 1e12, "peak": PEAK[pk] / 1e12,
-                "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": byt / (per_launch_ms * 1e-3) / 1e9, "peak": HBM / 1e9, "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dom)
-    roof["kernel"] = dom
-    roof["peak_dtype"] = pk
-    roof["launch_ms"] = per_launch_ms
-    roof["launches_per_step"] = stage_ms[dom][1]
+    top, kernels = roofline(stage_ms, m, n, k, l, fmt, c_bytes)
 
+    dtype = fmt[0] if len(set(fmt)) == 1 else "+".join(fmt)
+    wl = (f"{'target' if args.workload == 'target' else 'at-scale'}: A,B {m}x{k}x{n} "
+          f"{'bf16' if c_bytes == 2 else 'fp32'}, A = U diag(sigma) V^T, sigma_i = exp(-i/{tau:g})"
+          f"{' + entrywise noise var 1e-4' if args.workload != 'target' else ''}, B ~ N(0,1); "
+          f"l = {l} (r = {r}, p = {p}), q = {q}, formats {','.join(fmt)}, Omega from Philox seed {seed}")
     out = {
         "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "ms_per_step_instrumented": ms_step_instr,
-        "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": fmt[0] if len(set(fmt)) == 1 else "+".join(fmt), "data": "synthetic",
-        "config": {"workload": f"plain LRAMM at scale: A,B {m}x{k}x{n} FP32, sigma_i=exp(-i/{args.tau:g}) + "
-                               f"noise var {args.noise:g}, B~N(0,1); r={r} p={p} q={q}, formats {','.join(fmt)}, "
-                               "seeded Philox Omega",
-                   "m": m, "n": n, "k": k, "r": r, "p": p, "q": q, "l": l, "formats": list(fmt)},
+        "warmup": args.warmup, "ms_per_step": ms_step, "ms_per_step_instrumented": ms_instr,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic (seeded low-rank A with exponential singular-value decay, Gaussian B)",
+        "config": {"workload": wl, "m": m, "n": n, "k": k, "tau": tau, "r": r, "p": p, "q": q, "l": l,
+                   "formats": list(fmt), "io": "bf16" if c_bytes == 2 else "fp32"},
         "stages_ms": {st: round(v[0], 5) for st, v in stage_ms.items()},
-        "roofline": roof,
+        "roofline": top,
+        "kernels": kernels,
     }
 
-    if not args.no_dense:
-        Ab, Btb = A.to(torch.bfloat16), B.t().contiguous().to(torch.bfloat16)
-        Bt32 = B.t().contiguous()
-        Cd = torch.empty((m, n), dtype=torch.float32, device=dev)
-        dense = {}
-        for name, (L, R) in {"bf16": (Ab, Btb), "fp32": (A, Bt32)}.items():
-            for _ in range(2):
-                lramm.lramm_dense_gemm_nt(L, R, Cd)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            reps = 10
-            e0.record()
-            for _ in range(reps):
-                lramm.lramm_dense_gemm_nt(L, R, Cd)
-            e1.record()
-            torch.cuda.synchronize()
-            dms = e0.elapsed_time(e1) / reps
-            entry = {"ms": dms, "tflops": 2.0 * m * n * k / (dms * 1e-3) / 1e12}
-            entry["frac_peak"] = entry["tflops"] * 1e12 / PEAK[name]
-            if not args.no_error:
-                entry["Cd"] = Cd.double().cpu().numpy()
-            dense[name] = entry
-        out["dense"] = dense
-        out["speedup_vs_dense_bf16"] = dense["bf16"]["ms"] / ms_step
-        out["speedup_vs_dense_fp32"] = dense["fp32"]["ms"] / ms_step
-        out["speedup_vs_bf16_roofline"] = (2.0 * m * n * k / PEAK["bf16"] * 1e3) / ms_step
-
-    Cg = C.double().cpu().numpy()
+    Cex = None
+    if not args.no_error or not args.no_dense:
+        Cex = exact_product(A64, B64)
+    nrm = float(np.linalg.norm(Cex)) if Cex is not None else 1.0
     if not args.no_error:
-        t = time.time()
-        A64 = A_np.astype(np.float64)
-        B64 = B_np.astype(np.float64)
-        Cex = A64 @ B64
-        nrm = np.linalg.norm(Cex)
-        err = {"rel_fro_vs_exact": float(np.linalg.norm(Cg - Cex) / nrm),
-               "max_abs_vs_exact": float(np.max(np.abs(Cg - Cex))),
-               "sigma_next": float(sigma[l]) if l < len(sigma) else 0.0,
-               "tail_rank_l": float(math.sqrt(float(np.sum(sigma[l:] ** 2))))}
-        if "dense" in out:
-            for name in ("bf16", "fp32"):
-                Cd = out["dense"][name].pop("Cd")
-                out["dense"][name]["rel_fro_vs_exact"] = float(np.linalg.norm(Cd - Cex) / nrm)
-        out["error"] = err
-        log(f"errors computed in {time.time() - t:.1f}s")
-    elif "dense" in out:
-        for name in ("bf16", "fp32"):
-            out["dense"][name].pop("Cd", None)
+        e, mx, Cg = rel_errors(C, Cex, nrm)
+        out["error"] = {"rel_fro_vs_exact": e, "max_abs_vs_exact": mx, "max_abs_exact": float(np.max(np.abs(Cex))),
+                        "target_rel_fro": TARGET_RELF, "meets_target": e <= TARGET_RELF}
+        out["error"].update(floors(info, r, l))
+    del C, plan, ws
+    torch.cuda.empty_cache()
+
+    if not args.no_dense:
+        dms, Cd = dense_bf16(lramm, A if A.dtype == torch.bfloat16 else A.to(torch.bfloat16),
+                             B if B.dtype == torch.bfloat16 else B.to(torch.bfloat16))
+        ed, _, _ = rel_errors(Cd, Cex, nrm)
+        del Cd
+        roof_ms = 2.0 * m * n * k / PEAK["bf16"] * 1e3
+        out["dense_bf16"] = {"ms": dms, "tflops": 2.0 * m * n * k / (dms * 1e-3) / 1e12,
+                             "frac_peak": 2.0 * m * n * k / (dms * 1e-3) / PEAK["bf16"], "rel_fro_vs_exact": ed,
+                             "roofline_ms": roof_ms}
+        out["speedup_vs_dense_bf16"] = dms / ms_step
+        out["speedup_vs_dense_bf16_roofline"] = roof_ms / ms_step
+
+    if args.workload == "target" and not args.no_other_decays and args.tau is None and args.l is None:
+        others = {}
+        for t2_ in (128.0, 256.0):
+            st = BEST.get(t2_)
+            reach = st is not None
+            st = st or CLOSEST[t2_]
+            A2, B2, A2_64, B2_64, info2 = make_inputs("target", t2_, dev)
+            ms2, C2, plan2, ws2 = run_setting(lramm, A2, B2, st, max(5, args.steps // 4), 2, seed)
+            Cex2 = exact_product(A2_64, B2_64)
+            e2, mx2, _ = rel_errors(C2, Cex2, float(np.linalg.norm(Cex2)))
+            row = {"l": st[0], "p": st[1], "q": st[2], "formats": list(st[3]), "ms_per_step": ms2,
+                   "value": 2.0 * m * n * k / (ms2 * 1e-3) / 1e12, "rel_fro_vs_exact": e2, "max_abs_vs_exact": mx2,
+                   "reaches_target": reach and e2 <= TARGET_RELF}
+            row.update(floors(info2, st[0] - st[1], st[0]))
+            if "dense_bf16" in out:
+                row["speedup_vs_dense_bf16"] = out["dense_bf16"]["ms"] / ms2
+                row["speedup_vs_dense_bf16_roofline"] = out["dense_bf16"]["roofline_ms"] / ms2
+            others[f"tau={t2_:g}"] = row
+            del A2, B2, A2_64, B2_64, C2, plan2, ws2, Cex2
+            torch.cuda.empty_cache()
+        out["other_decays"] = others
 
     if not args.no_cpu_baseline:
         from threadpoolctl import threadpool_info, threadpool_limits
@@ -290,15 +454,19 @@ def main():
         with threadpool_limits(limits=cores):
             used = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
             t = time.time()
-            ref = OL.lramm_forward(A_np.astype(np.float64), B_np.astype(np.float64), r, p, q, fmt, seed=seed,
-                                   keep=False)
+            ref = OL.lramm_forward(A64, B64, r, p, q, fmt, seed=seed, keep=False)
             dt = time.time() - t
         out["cpu_baseline"] = {"value": 2.0 * m * n * k / dt / 1e12, "unit": "TFLOP/s", "cores": used,
                                "kind": "oracle", "seconds": dt,
-                               "sample": f"one full oracle forward of the same workload ({m}x{k}x{n}, r={r}, "
-                                         f"p={p}, q={q}, {','.join(fmt)}) in FP64 numpy"}
-        out.setdefault("error", {})["rel_fro_vs_oracle"] = float(OL.rel_fro(Cg, ref["C"]))
-        log(f"oracle {dt:.1f}s on {used} threads; GPU vs oracle rel-F {out['error']['rel_fro_vs_oracle']:.2e}")
+                               "sample": f"one whole oracle forward of the same workload and setting "
+                                         f"({m}x{k}x{n}, l={l}, q={q}, {','.join(fmt)}) in FP64 numpy"}
+        if "error" in out:
+            Cg32 = Cg.astype(np.float32).astype(np.float64) if c_bytes == 4 else Cg
+            refC = ref["C"] if c_bytes == 4 else synth_bf16(ref["C"])
+            d = Cg32 - refC
+            out["error"]["rel_fro_vs_oracle"] = float(np.linalg.norm(d) / np.linalg.norm(refC))
+            out["error"]["max_abs_vs_oracle"] = float(np.max(np.abs(d)))
+        log(f"oracle {dt:.1f}s on {used} threads")
 
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
@@ -309,6 +477,11 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = nbytes
     print(json.dumps(out), flush=True)
+
+
+def synth_bf16(X):
+    import synth
+    return synth.to_dtype(X, "bf16").astype("float64")
 
 
 if __name__ == "__main__":
