@@ -123,6 +123,15 @@ typedef struct {
   float alpha, beta;
   uint32_t flags;       /* 0 or LRAMM_PLAN_EXCLUSIVE                       */
   uint32_t reserved1;
+  /* Storage of A and B: 0 row-major as m x k (k x n), 1 stored as the
+   * transpose, k x m (n x k) row-major.  C is always m x n row-major. */
+  int32_t trans_a, trans_b;
+  /* Which operand is sketched (paper Alg. 3 approximates either one):
+   * 0 the left one, A (the formulas above); 1 the right one, B: the library
+   * runs them on C^T = B^T A^T, i.e. with A := B^T, B := A^T, m <-> n, and
+   * writes C (not C^T).  Q is then n x l and spans the row space of B. */
+  int32_t side;
+  int32_t reserved2;
 } lramm_desc;
 
 /* desc.flags: the caller runs no other CholeskyQR2 of this library on the
@@ -156,7 +165,8 @@ LRAMM_API void lramm_plan_destroy(lramm_plan* plan);
 LRAMM_API lramm_status lramm_workspace_bytes(const lramm_plan* plan, size_t* bytes);
 
 /* Forward pass (paper Alg. 3 in the one-sided form above).
- *   A: m x k (desc.a_type), lda >= k.   B: k x n (desc.b_type), ldb >= n.
+ *   A: m x k (desc.a_type), lda >= k (trans_a: stored k x m, lda >= m).
+ *   B: k x n (desc.b_type), ldb >= n (trans_b: stored n x k, ldb >= k).
  *   C: m x n (desc.c_type), ldc >= n; read when beta != 0.
  *   omega: optional k x l FP32 test matrix (ldo >= l); NULL draws it from
  *          Philox4x32-10 with key desc.seed (see lramm_omega).
@@ -169,7 +179,8 @@ LRAMM_API lramm_status lramm_forward(lramm_plan* plan, const void* A, int64_t ld
 
 /* Device views of the factors the last forward left in ws:
  *   Q: m x l FP64 with leading dimension *ldq (columns >= l are zero);
- *   Bt: l x k FP32 (the dequantised projection Q^T A), leading dim *ldbt. */
+ *   Bt: l x k FP32 (the dequantised projection Q^T A), leading dim *ldbt.
+ * With side 1 these are the factors of B^T: Q is n x l, Bt = Q^T B^T. */
 LRAMM_API lramm_status lramm_factors(const lramm_plan* plan, const void* ws,
                            const double** Q, int64_t* ldq, const float** Bt,
                            int64_t* ldbt);
@@ -215,16 +226,18 @@ LRAMM_API lramm_status lramm_codes(const lramm_plan* plan, const void* ws, int32
 
 /* Backward of C = Q Q^T A B with Q fixed and quantisation straight-through
  * (the gradient of the frozen-Q surrogate):
- *     W = Q^T dC,  dB = (Q^T A)^T W,  dA = Q (W B^T).
- * Uses the Q of the preceding lramm_forward on the same ws; all products in
- * FP32 with FP32 accumulation.  dC: m x n FP32 (lddc); A, B as in forward
- * (FP32); dA: m x k FP32 (ldda) and dB: k x n FP32 (lddb), each may be NULL
- * to skip it. */
-LRAMM_API lramm_status lramm_backward(lramm_plan* plan, const float* dC, int64_t lddc,
-                            const float* A, int64_t lda, const float* B,
-                            int64_t ldb, float* dA, int64_t ldda, float* dB,
-                            int64_t lddb, void* ws, size_t ws_bytes,
-                            void* stream);
+ *     W = Q^T dC,  dB = (Q^T A)^T W,  dA = Q (W B^T);
+ * with side 1 the surrogate is C = A B Q Q^T, and the same formulas run on
+ * the transposed problem (dA = dC Q Q^T B^T, dB = A^T dC Q Q^T).  Uses the Q
+ * of the preceding lramm_forward on the same ws; all products on the FP32
+ * MFMA with FP32 accumulation.  dC: m x n in desc.c_type (lddc); A, B as in
+ * the forward (their types and storage); dA and dB are written in the type
+ * and storage of A and B (leading dimensions ldda, lddb; bf16 rounded to
+ * nearest even); either may be NULL to skip it. */
+LRAMM_API lramm_status lramm_backward(lramm_plan* plan, const void* dC, int64_t lddc,
+                            const void* A, int64_t lda, const void* B, int64_t ldb,
+                            void* dA, int64_t ldda, void* dB, int64_t lddb, void* ws,
+                            size_t ws_bytes, void* stream);
 
 /* Synchronise the stream and read the device status word of ws.
  * *flags (nullable) receives the LRAMM_FLAG_* bits; the return value is

@@ -11,7 +11,7 @@ package only marshals torch tensors, sizes and the current stream.
 import torch
 
 from ._lib import (  # noqa: F401
-    EXPORTS, LIB_PATH, LrammBatch, LrammError, LrammPlan, autotune_rank, load, lramm_cholqr2,
+    EXPORTS, LIB_PATH, LrammBatch, LrammError, LrammPlan, autotune_rank, load, lramm_cholqr2, storage,
     lramm_cholqr2_workspace, lramm_cholqr2_noalloc, NOALLOC_SCRATCH_BYTES, E_SCRATCH,
     lramm_dense_gemm_nt, lramm_gemm_nt, lramm_gemm_nt_workspace, lramm_init, lramm_omega,
     lramm_pitch, lramm_quantize, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_SQRTNEG, FLAG_STALL,
@@ -19,18 +19,23 @@ from ._lib import (  # noqa: F401
 
 
 def matmul(A, B, r, p=16, q=1, fmt=("int8",) * 4, seed=0, omega=None, alpha=1.0, beta=0.0, out=None,
-           out_dtype=None, return_plan=False, check=True):
+           out_dtype=None, return_plan=False, check=True, side="left"):
     """C ~ alpha A B + beta out by LRAMM (one-sided, rank l = r + p).
+    ``side="right"`` sketches B instead of A.  A or B may be transposed views
+    (e.g. ``W.t()``): they are passed as transposed storage, not copied.
 
     With ``check`` (the default) the device status word is read after the
     forward (this synchronises the stream): a non-finite input or a Cholesky
     wait past its bound raises LrammError instead of returning an invalid C."""
     m, k = A.shape
     n = B.shape[1]
+    As, ta = storage(A)
+    Bs, tb = storage(B)
     c_type = out.dtype if out is not None else (out_dtype or A.dtype)
-    plan = LrammPlan(m, n, k, r, p, q, fmt, A.dtype, B.dtype, c_type, seed, alpha, beta)
+    plan = LrammPlan(m, n, k, r, p, q, fmt, A.dtype, B.dtype, c_type, seed, alpha, beta, trans_a=ta, trans_b=tb,
+                     side=side)
     ws = plan.workspace(A.device)
-    C = plan.forward(A, B, ws, C=out, omega=omega)
+    C = plan.forward(As, Bs, ws, C=out, omega=omega)
     if check:
         plan.status(ws)
     if return_plan:
@@ -39,14 +44,17 @@ def matmul(A, B, r, p=16, q=1, fmt=("int8",) * 4, seed=0, omega=None, alpha=1.0,
 
 
 class LRAMMConfig:
-    """Settings of LRAMMFunction.  ``check``: read the device status word
-    after each forward (synchronises the stream) and raise LrammError on a
-    non-finite input or an invalid Cholesky factor."""
+    """Settings of LRAMMFunction.  ``side``: "left" sketches A, "right"
+    sketches B (a low-rank weight on the right of activations).  ``check``:
+    read the device status word after each forward (synchronises the stream)
+    and raise LrammError on a non-finite input or an invalid Cholesky factor."""
 
-    def __init__(self, r, p=16, q=1, fmt=("int8",) * 4, seed=0, omega=None, recompute=False, check=True):
+    def __init__(self, r, p=16, q=1, fmt=("int8",) * 4, seed=0, omega=None, recompute=False, check=True,
+                 side="left"):
         self.r, self.p, self.q, self.fmt, self.seed, self.omega = r, p, q, fmt, seed, omega
         self.recompute = recompute
         self.check = check
+        self.side = side
 
 
 class LRAMMFunction(torch.autograd.Function):
@@ -60,24 +68,31 @@ class LRAMMFunction(torch.autograd.Function):
     def forward(ctx, A, B, cfg):
         m, k = A.shape
         n = B.shape[1]
-        plan = LrammPlan(m, n, k, cfg.r, cfg.p, cfg.q, cfg.fmt, A.dtype, B.dtype, A.dtype, cfg.seed)
+        As, ta = storage(A)
+        Bs, tb = storage(B)
+        plan = LrammPlan(m, n, k, cfg.r, cfg.p, cfg.q, cfg.fmt, A.dtype, B.dtype, A.dtype, cfg.seed,
+                         trans_a=ta, trans_b=tb, side=cfg.side)
         ws = plan.workspace(A.device)
-        C = plan.forward(A, B, ws, omega=cfg.omega)
+        C = plan.forward(As, Bs, ws, omega=cfg.omega)
         if cfg.check:
             plan.status(ws)
-        ctx.plan, ctx.cfg = plan, cfg
+        ctx.plan, ctx.cfg, ctx.trans = plan, cfg, (ta, tb)
         ctx.ws = None if cfg.recompute else ws
-        ctx.save_for_backward(A, B)
+        ctx.save_for_backward(As, Bs)
         return C
 
     @staticmethod
     def backward(ctx, dC):
-        A, B = ctx.saved_tensors
+        As, Bs = ctx.saved_tensors
         plan, ws = ctx.plan, ctx.ws
         if ws is None:
-            ws = plan.workspace(A.device)
-            plan.forward(A, B, ws, omega=ctx.cfg.omega)
-        dA, dB = plan.backward(dC.contiguous().to(torch.float32), A, B, ws,
-                               need_dA=ctx.needs_input_grad[0], need_dB=ctx.needs_input_grad[1])
+            ws = plan.workspace(As.device)
+            plan.forward(As, Bs, ws, omega=ctx.cfg.omega)
+        dCs = dC.contiguous()
+        if dCs.dtype != plan.c_type:
+            dCs = dCs.to(plan.c_type)
+        dA, dB = plan.backward(dCs, As, Bs, ws, need_dA=ctx.needs_input_grad[0], need_dB=ctx.needs_input_grad[1])
+        ta, tb = ctx.trans
         ctx.ws = None
-        return dA, dB, None
+        # gradients in the layout of the inputs (transposed storage -> .t() view)
+        return (dA.t() if (dA is not None and ta) else dA), (dB.t() if (dB is not None and tb) else dB), None

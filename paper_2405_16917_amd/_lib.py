@@ -57,6 +57,8 @@ class Desc(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("alpha", ctypes.c_float), ("beta", ctypes.c_float),
         ("flags", ctypes.c_uint32), ("reserved1", ctypes.c_uint32),
+        ("trans_a", ctypes.c_int32), ("trans_b", ctypes.c_int32), ("side", ctypes.c_int32),
+        ("reserved2", ctypes.c_int32),
     ]
 
 
@@ -246,18 +248,37 @@ def lramm_dense_gemm_nt(L, R, C=None):
 
 # ------------------------------------------------------------------- plan --
 
+def storage(X):
+    """(tensor whose rows are stored contiguously, transposed flag) for a 2-D
+    tensor or a transposed view of one: X itself when its rows are
+    contiguous, else X.t() when that is (the ABI's transposed storage), else
+    a contiguous copy."""
+    if X.stride(1) == 1 and X.stride(0) >= X.shape[1]:
+        return X, 0
+    if X.stride(0) == 1 and X.stride(1) >= X.shape[0]:
+        return X.t(), 1
+    return X.contiguous(), 0
+
+
+SIDES = {"left": 0, "right": 1, 0: 0, 1: 1}
+
+
 class LrammPlan:
     """lramm_plan_create / lramm_forward / lramm_backward / lramm_factors /
-    lramm_status_poll on one problem description."""
+    lramm_status_poll on one problem description.  A and B are passed as
+    their storage: A row-major m x k (or k x m with trans_a), B k x n (or
+    n x k with trans_b); ``side`` "right" sketches B instead of A."""
 
     def __init__(self, m, n, k, r, p=16, q=1, fmt=("int8",) * 4, a_type=torch.float32,
-                 b_type=torch.float32, c_type=torch.float32, seed=0, alpha=1.0, beta=0.0, exclusive=False):
+                 b_type=torch.float32, c_type=torch.float32, seed=0, alpha=1.0, beta=0.0, exclusive=False,
+                 trans_a=False, trans_b=False, side="left"):
         lib = load()
         d = Desc()
         d.m, d.n, d.k, d.r, d.p, d.q = m, n, k, r, p, q
         d.fmt_sketch, d.fmt_proj, d.fmt_g1, d.fmt_g2 = (_fmt(f) for f in fmt)
         d.a_type, d.b_type, d.c_type = DTYPE[a_type], DTYPE[b_type], DTYPE[c_type]
         d.seed, d.alpha, d.beta, d.flags = seed, alpha, beta, PLAN_EXCLUSIVE if exclusive else 0
+        d.trans_a, d.trans_b, d.side = int(bool(trans_a)), int(bool(trans_b)), SIDES[side]
         self.desc = d
         self.c_type = c_type
         h = P()
@@ -267,6 +288,7 @@ class LrammPlan:
         _check(lib.lramm_workspace_bytes(h, ctypes.byref(sz)), "lramm_workspace_bytes")
         self.ws_bytes = int(sz.value)
         self.l = r + p
+        self.a_type, self.b_type = a_type, b_type
 
     def __del__(self):
         if getattr(self, "_h", None) is not None and _lib is not None:
@@ -275,6 +297,12 @@ class LrammPlan:
 
     def workspace(self, device="cuda"):
         return torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+
+    def _fdims(self):
+        """(rows, cols) of the factor Q and of Bt: Q spans the sketched
+        operand (m rows, or n with side 1)."""
+        d = self.desc
+        return (d.n, d.m) if d.side else (d.m, d.n)
 
     def forward(self, A, B, ws, C=None, omega=None):
         d = self.desc
@@ -291,9 +319,10 @@ class LrammPlan:
         _check(load().lramm_factors(self._h, _ptr(ws), ctypes.byref(q), ctypes.byref(ldq), ctypes.byref(bt),
                                     ctypes.byref(ldbt)), "lramm_factors")
         d = self.desc
+        rows = self._fdims()[0]
         base = ws.data_ptr()
         qo, bo = q.value - base, bt.value - base
-        Q = ws[qo:qo + d.m * ldq.value * 8].view(torch.float64).view(d.m, ldq.value)[:, :self.l]
+        Q = ws[qo:qo + rows * ldq.value * 8].view(torch.float64).view(rows, ldq.value)[:, :self.l]
         Bt = ws[bo:bo + self.l * ldbt.value * 4].view(torch.float32).view(self.l, ldbt.value)
         return Q, Bt
 
@@ -335,11 +364,12 @@ class LrammPlan:
         return codes, scales, K.value, fname
 
     def backward(self, dC, A, B, ws, dA=None, dB=None, need_dA=True, need_dB=True):
-        d = self.desc
+        """Gradients of the frozen-Q surrogate; A, B, dA, dB are storage
+        tensors (shapes and types as A and B are stored)."""
         if need_dA and dA is None:
-            dA = torch.empty((d.m, d.k), dtype=torch.float32, device=dC.device)
+            dA = torch.empty(A.shape, dtype=A.dtype, device=dC.device)
         if need_dB and dB is None:
-            dB = torch.empty((d.k, d.n), dtype=torch.float32, device=dC.device)
+            dB = torch.empty(B.shape, dtype=B.dtype, device=dC.device)
         _check(load().lramm_backward(self._h, _ptr(dC), dC.stride(0), _ptr(A), A.stride(0), _ptr(B),
                                      B.stride(0), _ptr(dA) if need_dA else None, dA.stride(0) if need_dA else 0,
                                      _ptr(dB) if need_dB else None, dB.stride(0) if need_dB else 0, _ptr(ws),

@@ -251,14 +251,15 @@ lramm_status launch_dense_gemm_nt(int64_t M, int64_t N, int64_t K, int dtype, co
                                   const void* R, int64_t ldr, float* C, int64_t ldc, hipStream_t s);
 
 // FP32 GEMM with either operand stored K-contiguous ("t" = transposed
-// storage) or M/N-contiguous: C[M x N] = op(A) op(B) (+ C if accumulate).
+// storage) or M/N-contiguous: C[M x N] = op(A) op(B), FP32 accumulation.
 //   a_kmajor == 0: A stored M x K (lda, K contiguous)  -- A[i][k] = A[i*lda+k]
 //   a_kmajor == 1: A stored K x M (lda, M contiguous)  -- A[i][k] = A[k*lda+i]
 //   b_kmajor == 0: B stored N x K (ldb, K contiguous)  -- B[k][j] = B[j*ldb+k]
 //   b_kmajor == 1: B stored K x N (ldb, N contiguous)  -- B[k][j] = B[k*ldb+j]
-// A and B element type: float or double (converted to float).
+// a_type, b_type: LRAMM_F32, LRAMM_F64 or LRAMM_BF16 (converted to binary32
+// on load); c_type: LRAMM_F32 or LRAMM_BF16 (rounded to nearest even).
 lramm_status launch_gemm_f32(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, int a_kmajor,
-                             int a_f64, const float* B, int64_t ldb, int b_kmajor, float* C, int64_t ldc,
-                             hipStream_t s);
+                             int a_type, const void* B, int64_t ldb, int b_kmajor, int b_type, void* C,
+                             int64_t ldc, int c_type, hipStream_t s);
 
 }  // namespace lramm

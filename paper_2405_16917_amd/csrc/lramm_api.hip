@@ -19,13 +19,18 @@
 
 #include <algorithm>
 #include <mutex>
+#include <utility>
 #include <new>
 #include <vector>
 
 #include "common.hpp"
 
 struct lramm_plan {
+  lramm_desc user;   // as the caller described it
+  // the problem the library runs: the caller's A, B, C (side 0) or B^T, A^T,
+  // C^T (side 1), with m, n, k and the element types mapped accordingly
   lramm_desc d;
+  int at = 0, bt = 0, ct = 0;   // A', B', C' stored transposed
   int chain_mode = lramm::CHAIN_SHARED;   // CHAIN_OFF while a batch issues the plan on one of several streams
   int64_t l, lp;            // sketch width and its 32-padded leading dimension
   // workspace offsets (bytes)
@@ -211,7 +216,15 @@ int64_t lramm_pitch(int64_t K, int32_t fmt) { return pitch_bytes(K, fmt); }
 
 lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   if (!desc || !out) return LRAMM_E_INVALID;
-  const lramm_desc& d = *desc;
+  if ((desc->trans_a | desc->trans_b) & ~1 || (desc->side & ~1)) return LRAMM_E_INVALID;
+  // side 1 sketches the right operand: C^T = B^T A^T with B^T as the left one
+  lramm_desc d = *desc;
+  if (desc->side) {
+    d.m = desc->n;
+    d.n = desc->m;
+    d.a_type = desc->b_type;
+    d.b_type = desc->a_type;
+  }
   if (d.m <= 0 || d.n <= 0 || d.k <= 0) return LRAMM_E_SHAPE;
   if (d.m > INT32_MAX || d.n > INT32_MAX || d.k > INT32_MAX) return LRAMM_E_SHAPE;
   if (d.r < 0 || d.p < 0 || d.q < 0 || d.q > 16) return LRAMM_E_INVALID;
@@ -231,7 +244,13 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
 
   lramm_plan* p = new (std::nothrow) lramm_plan();
   if (!p) return LRAMM_E_INVALID;
+  p->user = *desc;
   p->d = d;
+  // storage of the operands the library runs on: A' = B^T is stored
+  // transposed when B is stored as is, and so on
+  p->at = desc->side ? 1 - desc->trans_b : desc->trans_a;
+  p->bt = desc->side ? 1 - desc->trans_a : desc->trans_b;
+  p->ct = desc->side;
   p->chain_mode = (d.flags & LRAMM_PLAN_EXCLUSIVE) ? CHAIN_EXCLUSIVE : CHAIN_SHARED;
   p->l = l;
   p->lp = lp;
@@ -303,6 +322,7 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   t = gemm_nt_workspace(l, k, m, d.fmt_proj); sb = t > sb ? t : sb;
   t = gemm_nt_workspace(n, l, k, d.fmt_g1); sb = t > sb ? t : sb;
   t = gemm_nt_workspace(m, n, l, d.fmt_g2); sb = t > sb ? t : sb;
+  t = gemm_nt_workspace(n, m, l, d.fmt_g2); sb = t > sb ? t : sb;   // C' written transposed
   p->split_bytes = sb;
   p->off_split = carve(&c, sb);
   // backward scratch
@@ -378,9 +398,16 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
                            int64_t ldc, const float* omega, int64_t ldo, void* ws, size_t ws_bytes, void* stream) {
   if (!P || !A || !B || !C) return LRAMM_E_INVALID;
   if (!ws || ws_bytes < P->total) return LRAMM_E_WORKSPACE;
+  {
+    const lramm_desc& u = P->user;
+    if (lda < (u.trans_a ? u.m : u.k) || ldb < (u.trans_b ? u.k : u.n) || ldc < u.n) return LRAMM_E_SHAPE;
+  }
+  if (P->user.side) {   // run on A' = B^T, B' = A^T
+    std::swap(A, B);
+    std::swap(lda, ldb);
+  }
   const lramm_desc& d = P->d;
   const int64_t m = d.m, n = d.n, k = d.k, l = P->l, lp = P->lp;
-  if (lda < k || ldb < n || ldc < n) return LRAMM_E_SHAPE;
   if (omega && ldo < l) return LRAMM_E_SHAPE;
   hipStream_t s = (hipStream_t)stream;
   uint8_t* base = reinterpret_cast<uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
@@ -448,12 +475,14 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
   }
   // bf16 A in a bf16 sketch: the codes are A itself (rows of whole 64-element
   // tiles, 16-byte aligned), no pass over A
-  const bool a_direct = d.fmt_sketch == LRAMM_BF16F && d.a_type == LRAMM_BF16 && k % 64 == 0 &&
+  const bool a_direct = d.fmt_sketch == LRAMM_BF16F && d.a_type == LRAMM_BF16 && !P->at && k % 64 == 0 &&
                         (lda * 2) % 16 == 0 && (uintptr_t)A % 16 == 0;
   if (a_direct) {
     Ar = reinterpret_cast<uint8_t*>(const_cast<void*>(A));
-  } else {
+  } else if (!P->at) {
     TIMED(ST_QUANT_A_ROWS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_sketch, 0, Ar, P->pAr, sAr, flags, s));
+  } else {   // A' stored k x m: its rows are the stored columns
+    TIMED(ST_QUANT_A_ROWS, launch_quantize(k, m, A, lda, d.a_type, d.fmt_sketch, 1, Ar, P->pAr, sAr, flags, s));
   }
   const int64_t pAr = a_direct ? lda * 2 : P->pAr;
   P->last_Ar = Ar;
@@ -471,9 +500,15 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
     LRAMM_HIP(hipEventRecord(P->ev_sketch, s));
     LRAMM_HIP(hipStreamWaitEvent(P->side, P->ev_sketch, 0));
   }
-  TIMED_ON(s2, ST_QUANT_A_COLS,
-           launch_quantize(m, k, A, lda, d.a_type, d.fmt_proj, 1, Ac, P->pAc, sAc, flags, s2, mxA));
-  TIMED_ON(s2, ST_QUANT_B, launch_quantize(k, n, B, ldb, d.b_type, d.fmt_g1, 1, Bc, P->pBc, sBc, flags, s2, mxB));
+  if (!P->at)
+    TIMED_ON(s2, ST_QUANT_A_COLS,
+             launch_quantize(m, k, A, lda, d.a_type, d.fmt_proj, 1, Ac, P->pAc, sAc, flags, s2, mxA));
+  else   // the columns of A' are the stored rows
+    TIMED_ON(s2, ST_QUANT_A_COLS, launch_quantize(k, m, A, lda, d.a_type, d.fmt_proj, 0, Ac, P->pAc, sAc, flags, s2));
+  if (!P->bt)
+    TIMED_ON(s2, ST_QUANT_B, launch_quantize(k, n, B, ldb, d.b_type, d.fmt_g1, 1, Bc, P->pBc, sBc, flags, s2, mxB));
+  else
+    TIMED_ON(s2, ST_QUANT_B, launch_quantize(n, k, B, ldb, d.b_type, d.fmt_g1, 0, Bc, P->pBc, sBc, flags, s2));
   if (P->side) LRAMM_HIP(hipEventRecord(P->ev_join, P->side));
   TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(0),
                                    P->chain_mode));
@@ -521,8 +556,15 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
   float* sTt = at<float>(W, P->off_sTt);
   TIMED(ST_QUANT_Q_ROWS, launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_g2, 0, Qr, P->pQr, sQr, flags, s));
   TIMED(ST_QUANT_TT, launch_quantize(n, l, Tt, lp, LRAMM_F32, d.fmt_g2, 0, Ttq, P->pTtq, sTt, flags, s));
-  TIMED(ST_G2, launch_gemm_nt(m, n, l, d.fmt_g2, Qr, P->pQr, sQr, Ttq, P->pTtq, sTt, d.alpha, d.beta, C, ldc,
-                              d.c_type, nullptr, 0, split, sb, s));
+  if (!P->ct) {
+    TIMED(ST_G2, launch_gemm_nt(m, n, l, d.fmt_g2, Qr, P->pQr, sQr, Ttq, P->pTtq, sTt, d.alpha, d.beta, C, ldc,
+                                d.c_type, nullptr, 0, split, sb, s));
+  } else {
+    // C = C'^T written directly: C = T'^T Q'^T, Q's row factor (now the
+    // column factor) applied first
+    TIMED(ST_G2, launch_gemm_nt(n, m, l, d.fmt_g2, Ttq, P->pTtq, sTt, Qr, P->pQr, sQr, d.alpha, d.beta, C, ldc,
+                                d.c_type, nullptr, 0, split, sb, s, true));
+  }
 #undef TIMED
 #undef TIMED_ON
   return LRAMM_OK;
@@ -593,35 +635,65 @@ lramm_status lramm_codes(const lramm_plan* P, const void* ws, int32_t which, con
   return LRAMM_OK;
 }
 
-lramm_status lramm_backward(lramm_plan* P, const float* dC, int64_t lddc, const float* A, int64_t lda,
-                            const float* B, int64_t ldb, float* dA, int64_t ldda, float* dB, int64_t lddb, void* ws,
-                            size_t ws_bytes, void* stream) {
+namespace {
+// A logical R x C matrix in memory: t == 0 row-major (element (i, j) at
+// p[i*ld + j]), t == 1 stored as its transpose (at p[j*ld + i]).
+struct MatV {
+  const void* p;
+  int64_t ld;
+  int t;
+  int type;
+};
+
+// C[M x N] = L[M x K] R[K x N] on the FP32 MFMA GEMM, C stored row-major
+// (ct == 0) or transposed (ct == 1: then C^T = R^T L^T is formed).
+lramm_status mm(int64_t M, int64_t N, int64_t K, MatV L, MatV R, void* C, int64_t ldc, int ct, int ctype,
+                hipStream_t s) {
+  if (!ct) return launch_gemm_f32(M, N, K, L.p, L.ld, L.t, L.type, R.p, R.ld, 1 - R.t, R.type, C, ldc, ctype, s);
+  return launch_gemm_f32(N, M, K, R.p, R.ld, 1 - R.t, R.type, L.p, L.ld, L.t, L.type, C, ldc, ctype, s);
+}
+}  // namespace
+
+lramm_status lramm_backward(lramm_plan* P, const void* dC, int64_t lddc, const void* A, int64_t lda, const void* B,
+                            int64_t ldb, void* dA, int64_t ldda, void* dB, int64_t lddb, void* ws, size_t ws_bytes,
+                            void* stream) {
   if (!P || !dC) return LRAMM_E_INVALID;
   if (!ws || ws_bytes < P->total) return LRAMM_E_WORKSPACE;
+  const lramm_desc& u = P->user;
+  if (lddc < u.n) return LRAMM_E_SHAPE;
+  const int64_t wa = u.trans_a ? u.m : u.k, wb = u.trans_b ? u.k : u.n;   // stored row lengths of A and B
+  if (dA && (!B || ldb < wb || ldda < wa)) return LRAMM_E_SHAPE;
+  if (dB && (!A || lda < wa || lddb < wb)) return LRAMM_E_SHAPE;
+  // the problem the library ran: A' = side ? B^T : A, B' = side ? A^T : B,
+  // dC' = side ? dC^T : dC; the gradient of A' is that of B (transposed) and so on
+  const bool sd = u.side != 0;
   const lramm_desc& d = P->d;
-  if (d.a_type != LRAMM_F32 || d.b_type != LRAMM_F32) return LRAMM_E_UNSUPPORTED;
   const int64_t m = d.m, n = d.n, k = d.k, l = P->l, lp = P->lp;
-  if (lddc < n) return LRAMM_E_SHAPE;
-  if (dA && (!B || ldb < n || ldda < k)) return LRAMM_E_SHAPE;
-  if (dB && (!A || lda < k || lddb < n)) return LRAMM_E_SHAPE;
+  const MatV Ap{sd ? B : A, sd ? ldb : lda, P->at, d.a_type};
+  const MatV Bp{sd ? A : B, sd ? lda : ldb, P->bt, d.b_type};
+  const MatV dCp{dC, lddc, sd ? 1 : 0, d.c_type};
+  void* dAp = sd ? dB : dA;
+  void* dBp = sd ? dA : dB;
+  const int64_t lddap = sd ? lddb : ldda, lddbp = sd ? ldda : lddb;
   hipStream_t s = (hipStream_t)stream;
   void* W = reinterpret_cast<uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
   const double* Q = at<double>(W, P->off_Q);
   float* Wm = at<float>(W, P->off_W);      // l x n
   float* Bte = at<float>(W, P->off_Bte);   // l x k
   float* V = at<float>(W, P->off_V);       // l x k
-  // W = Q^T dC: A-operand Q^T stored K x M (Q is m x lp), B-operand dC stored K x N
-  LRAMM_TRY(launch_gemm_f32(l, n, m, Q, lp, 1, 1, dC, lddc, 1, Wm, n, s));
-  if (dB) {
-    // Bte = Q^T A (l x k), dB = Bte^T W (k x n)
-    LRAMM_TRY(launch_gemm_f32(l, k, m, Q, lp, 1, 1, A, lda, 1, Bte, k, s));
-    LRAMM_TRY(launch_gemm_f32(k, n, l, Bte, k, 1, 0, Wm, n, 1, dB, lddb, s));
+  const MatV Qv{Q, lp, 0, LRAMM_F64}, QTv{Q, lp, 1, LRAMM_F64};
+  // W = Q^T dC'  (l x n)
+  LRAMM_TRY(mm(l, n, m, QTv, dCp, Wm, n, 0, LRAMM_F32, s));
+  const MatV Wv{Wm, n, 0, LRAMM_F32};
+  if (dBp) {
+    // Bte = Q^T A' (l x k); dB' = Bte^T W (k x n), stored like B'
+    LRAMM_TRY(mm(l, k, m, QTv, Ap, Bte, k, 0, LRAMM_F32, s));
+    LRAMM_TRY(mm(k, n, l, MatV{Bte, k, 1, LRAMM_F32}, Wv, dBp, lddbp, P->bt, d.b_type, s));
   }
-  if (dA) {
-    // V = W B^T (l x k): B-operand B^T, i.e. B stored N(=k) x K(=n) K-contiguous
-    LRAMM_TRY(launch_gemm_f32(l, k, n, Wm, n, 0, 0, B, ldb, 0, V, k, s));
-    // dA = Q V (m x k): A-operand Q stored M x K (f64), B-operand V stored K x N
-    LRAMM_TRY(launch_gemm_f32(m, k, l, Q, lp, 0, 1, V, k, 1, dA, ldda, s));
+  if (dAp) {
+    // V = W B'^T (l x k); dA' = Q V (m x k), stored like A'
+    LRAMM_TRY(mm(l, k, n, Wv, MatV{Bp.p, Bp.ld, 1 - Bp.t, Bp.type}, V, k, 0, LRAMM_F32, s));
+    LRAMM_TRY(mm(m, k, l, Qv, MatV{V, k, 0, LRAMM_F32}, dAp, lddap, P->at, d.a_type, s));
   }
   return LRAMM_OK;
 }
@@ -770,7 +842,9 @@ lramm_status lramm_batched_forward(lramm_batch* b, const void* const* A, const i
   for (int i = 0; i < n; ++i) {
     const lramm_desc& d = b->plans[i]->d;
     if (!A[i] || !B[i] || !C[i]) return LRAMM_E_INVALID;
-    if (lda[i] < d.k || ldb[i] < d.n || ldc[i] < d.n) return LRAMM_E_SHAPE;
+    const lramm_desc& u = b->plans[i]->user;
+    if (lda[i] < (u.trans_a ? u.m : u.k) || ldb[i] < (u.trans_b ? u.k : u.n) || ldc[i] < u.n) return LRAMM_E_SHAPE;
+    (void)d;
   }
   hipStream_t s = (hipStream_t)stream;
   uint8_t* base = reinterpret_cast<uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));

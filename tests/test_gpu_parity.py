@@ -714,3 +714,91 @@ def test_backward_matches_exact_gradient(lib):
     cfg2 = lib.LRAMMConfig(r=40, p=8, q=1, omega=g(om), recompute=True)
     lib.LRAMMFunction.apply(At2, Bt2, cfg2).backward(g(dC))
     assert torch.equal(At.grad, At2.grad) and torch.equal(Bt.grad, Bt2.grad)
+
+
+# ------------------------------------------------- side / transposed storage --
+
+def test_transposed_storage_gives_identical_results(lib):
+    """A and B passed as transposed storage (torch .t() views of their
+    transposes) give the same C bit for bit: the quantisers read the stored
+    rows or columns that hold the same vectors."""
+    m, k, n = 384, 320, 256
+    A, _ = synth.lowrank(m, k, synth.spectrum("exp", k, 24.0), 4)
+    B = synth.gaussian(k, n, 104)
+    om = g(synth.omega(k, 56, 5))
+    Ad, Bd = g(A), g(B)
+    C0 = lib.matmul(Ad, Bd, 48, 8, 1, omega=om)
+    C1 = lib.matmul(g(A.T.copy()).t(), g(B.T.copy()).t(), 48, 8, 1, omega=om)
+    assert torch.equal(C0, C1)
+
+
+@pytest.mark.parametrize("trans", [(False, False), (True, True)])
+def test_side_right_matches_oracle_on_transposed_problem(lib, trans):
+    """side = right sketches B: the result is the one-sided method on
+    C^T = B^T A^T (oracle run on (B^T, A^T), transposed back), bit for bit
+    for int8 stages, with A and B given either way."""
+    m, k, n = 512, 320, 384
+    X = synth.gaussian(m, k, 6)
+    W, _ = synth.lowrank(k, n, synth.spectrum("exp", min(k, n), 20.0), 7)
+    ta, tb = trans
+    Xd = g(X.T.copy()).t() if ta else g(X)
+    Wd = g(W.T.copy()).t() if tb else g(W)
+    # the transposed problem C^T = W^T X^T keeps the inner dimension k: Omega is k x l
+    C = lib.matmul(Xd, Wd, 50, 8, 1, omega=g(synth.omega(k, 58, 8)), side="right").double().cpu().numpy()
+    ref = OL.lramm_forward(W.T.astype(np.float64), X.T.astype(np.float64), 50, 8, 1,
+                           omega=synth.omega(k, 58, 8).astype(np.float64))
+    assert OL.rel_fro(C, ref["C"].T) <= 1e-5
+
+
+def test_backward_side_right_bf16(lib):
+    """side = right with bf16 activations and weight: the gradients of the
+    frozen-Q surrogate C = A B Q Q^T, written in bf16, within half a bf16
+    ulp per element (rel-F <= 2^-8) of the exact FP64 gradient taken with
+    the oracle's Q (equal to the GPU's to 1e-11)."""
+    m, k, n = 512, 256, 384
+    X = synth.gaussian(m, k, 9, dtype="bf16")
+    W, _ = synth.lowrank(k, n, synth.spectrum("exp", min(k, n), 16.0), 10, dtype="bf16")
+    om = synth.omega(k, 40, 11)
+    Xd = g(X, torch.bfloat16).requires_grad_(True)
+    Wd = g(W, torch.bfloat16).requires_grad_(True)
+    cfg = lib.LRAMMConfig(r=32, p=8, q=1, omega=g(om), side="right")
+    C = lib.LRAMMFunction.apply(Xd, Wd, cfg)
+    assert C.dtype == torch.bfloat16
+    dC = synth.gaussian(m, n, 12, dtype="bf16")
+    C.backward(g(dC, torch.bfloat16))
+    X64, W64, dC64 = X.astype(np.float64), W.astype(np.float64), dC.astype(np.float64)
+    ref = OL.lramm_forward(W64.T, X64.T, 32, 8, 1, omega=om.astype(np.float64))
+    # the transposed problem's gradients: dA' = grad of W^T, dB' = grad of X^T
+    dWt, dXt = OL.lramm_backward(ref["Q"], W64.T, X64.T, dC64.T)
+    eX = OL.rel_fro(Xd.grad.double().cpu().numpy(), dXt.T)
+    eW = OL.rel_fro(Wd.grad.double().cpu().numpy(), dWt.T)
+    assert Xd.grad.dtype == torch.bfloat16 and Wd.grad.dtype == torch.bfloat16
+    assert eX <= 2.0**-8 and eW <= 2.0**-8, (eX, eW)
+
+
+def test_differentiable_layer_workload(lib):
+    """The differentiable-layer workload: X 16384 x 4096 bf16 ~ N(0, 1) times
+    W 4096 x 4096 = rank-256 part (sigma_i = exp(-i/64), unit-RMS entries) +
+    entrywise noise of variance 1e-3, W sketched (side = right), r = 256,
+    p = 16, q = 1, int8.  Forward against the oracle on the transposed
+    problem (1e-5), backward against the exact frozen-Q gradient (bf16
+    output: rel-F <= 2^-8)."""
+    m, k, n = 16384, 4096, 4096
+    X = synth.gaussian(m, k, 21, dtype="bf16")
+    W, _ = synth.lowrank(k, n, synth.spectrum("exp", 256, 64.0), 22, noise_var=1e-3, dtype="bf16")
+    om = synth.omega(k, 272, 23)
+    Xd = g(X, torch.bfloat16).requires_grad_(True)
+    Wd = g(W, torch.bfloat16).requires_grad_(True)
+    cfg = lib.LRAMMConfig(r=256, p=16, q=1, omega=g(om), side="right")
+    C = lib.LRAMMFunction.apply(Xd, Wd, cfg)
+    dC = synth.gaussian(m, n, 24, dtype="bf16")
+    C.backward(g(dC, torch.bfloat16))
+    Cg = C.detach().double().cpu().numpy()
+    del C
+    X64, W64 = X.astype(np.float64), W.astype(np.float64)
+    ref = OL.lramm_forward(W64.T, X64.T, 256, 16, 1, omega=om.astype(np.float64))
+    assert OL.rel_fro(Cg, bf16_round(ref["C"].T)) <= 1e-5
+    dWt, dXt = OL.lramm_backward(ref["Q"], W64.T, X64.T, dC.astype(np.float64).T)
+    eX = OL.rel_fro(Xd.grad.double().cpu().numpy(), dXt.T)
+    eW = OL.rel_fro(Wd.grad.double().cpu().numpy(), dWt.T)
+    assert eX <= 2.0**-8 and eW <= 2.0**-8, (eX, eW)
