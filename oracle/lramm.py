@@ -61,6 +61,41 @@ def _q_operand(Q, fmt):
     return Q if fmt == "fp64" else fl32(Q)
 
 
+def range_finder(A, l, q, fs, fp, omega, drop_dependent=False, out=None, keep=True):
+    """Q with l orthonormal columns spanning the sketch of A (Sec. 2.2,
+    first stage): Y = A Omega in format fs, Q = qr(Y), then q subspace
+    iterations Z = A^T Q (format fp), Q_Z = qr(Z), Y = A Q_Z (fs), Q = qr(Y).
+    Intermediates go into ``out`` (when given, with ``keep``).  Returns
+    (Q, R) of the last orthonormalisation."""
+    if out is None:
+        out = {}
+    tol = 64.0 * l * 2.0**-53
+
+    def orth(X):
+        if drop_dependent:
+            Qd, Rd, dropped = householder_qr_dropping(X, tol)
+            out.setdefault("dropped", []).append(dropped)
+            return Qd, Rd
+        return householder_qr(X)
+
+    Y = _product(A, omega, fs)
+    Q, R = orth(Y)
+    if keep:
+        out.update(omega=omega, Y0=Y, Q0=Q)
+    for it in range(q):
+        Z = _product(A.T, _q_operand(Q, fp), fp)
+        QZ, _ = orth(Z)
+        Y = _product(A, _q_operand(QZ, fs), fs)
+        Q, R = orth(Y)
+        if keep:
+            out[f"Z{it + 1}"] = Z
+            out[f"QZ{it + 1}"] = QZ
+            out[f"Y{it + 1}"] = Y
+            out[f"Q{it + 1}"] = Q
+    out["Y"] = Y
+    return Q, R
+
+
 def lramm_forward(A, B, r, p, q, fmt=("int8",) * 4, omega=None, seed=None,
                   alpha=1.0, beta=0.0, Cin=None, keep=True, drop_dependent=False):
     """One-sided LRAMM.  A: m x k, B: k x n (binary32 values unless every
@@ -96,29 +131,7 @@ def lramm_forward(A, B, r, p, q, fmt=("int8",) * 4, omega=None, seed=None,
         raise ValueError("omega must be k x l")
 
     out = {"l": l}
-    tol = 64.0 * l * 2.0**-53
-
-    def orth(X):
-        if drop_dependent:
-            Qd, Rd, dropped = householder_qr_dropping(X, tol)
-            out.setdefault("dropped", []).append(dropped)
-            return Qd, Rd
-        return householder_qr(X)
-
-    Y = _product(A, omega, fs)
-    Q, R = orth(Y)
-    if keep:
-        out.update(omega=omega, Y0=Y, Q0=Q)
-    for it in range(q):
-        Z = _product(A.T, _q_operand(Q, fp), fp)
-        QZ, _ = orth(Z)
-        Y = _product(A, _q_operand(QZ, fs), fs)
-        Q, R = orth(Y)
-        if keep:
-            out[f"Z{it + 1}"] = Z
-            out[f"QZ{it + 1}"] = QZ
-            out[f"Y{it + 1}"] = Y
-            out[f"Q{it + 1}"] = Q
+    Q, R = range_finder(A, l, q, fs, fp, omega, drop_dependent, out, keep)
     Bt = _product(_q_operand(Q, fp).T, A, fp)
     T = _product(Bt, B, f1)
     C = _product(_q_operand(Q, f2), T, f2)
@@ -129,7 +142,7 @@ def lramm_forward(A, B, r, p, q, fmt=("int8",) * 4, omega=None, seed=None,
             C = fl32(C + fl32(fl32(beta) * np.asarray(Cin, np.float64)))
     else:
         C = alpha * C + (beta * np.asarray(Cin, np.float64) if beta != 0.0 else 0.0)
-    out.update(Y=Y, Q=Q, R=R, Bt=Bt, T=T, C=C)
+    out.update(Q=Q, R=R, Bt=Bt, T=T, C=C)
     return out
 
 
