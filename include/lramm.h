@@ -387,6 +387,54 @@ LRAMM_API lramm_status lramm_cholqr2_noalloc(int64_t rows, int64_t l, const void
                            int32_t ytype, double* Q, int64_t ldq, uint32_t* flags,
                            void* stream);
 
+/* ------------------------------------------------------------------------
+ * Two-sided form, the paper's Alg. 3 (Sec. 3.2):
+ *   rank-r RSVD of A and of B (Alg. 1 after the range finder above: Q from a
+ *   sketch of l = r + p columns with q power iterations, Bt = Q^T A, small
+ *   SVD Bt = U' S V^T, U = Q U', first r triplets kept), signs fixed so that
+ *   the largest-magnitude entry of each column of U' is positive;
+ *   U~ = U_A S_A (m x r), Z~ = G_B Z_B^T (r x n), computed in FP64 and
+ *   rounded once to binary32, as are V_A^T (r x k) and W_B (k x r);
+ *   E1 = QM(V_A^T W_B, d1), E2 = QM(E1 Z~, d2), D = alpha QM(U~ E2, d3) + beta C,
+ * each QM the quantised product of Alg. 2.  The small SVD is the
+ * eigen-decomposition of the FP64 Gram Bt Bt^T by Jacobi rotations, for
+ * round_up(l, 2) <= 128 (else LRAMM_E_UNSUPPORTED).  A: m x k (a_type,
+ * lda >= k), B: k x n (b_type, ldb >= n), C: m x n (c_type, ldc >= n);
+ * omega_a (k x l, ldoa) and omega_b (n x l, ldob) may be NULL: then they
+ * come from Philox with keys seed and seed + 1. */
+typedef struct {
+  int64_t m, n, k;
+  int32_t r, p, q;
+  int32_t fmt_sketch, fmt_proj;     /* lramm_fmt of both RSVDs' sketch / projection */
+  int32_t fmt_e1, fmt_e2, fmt_e3;   /* the paper's bit budgets d1, d2, d3           */
+  int32_t a_type, b_type, c_type;
+  uint64_t seed;
+  float alpha, beta;
+  uint32_t flags;                   /* must be 0 */
+  int32_t reserved;
+} lramm_ts_desc;
+typedef struct lramm_ts_plan lramm_ts_plan;
+LRAMM_API lramm_status lramm_ts_plan_create(const lramm_ts_desc* desc, lramm_ts_plan** out);
+LRAMM_API void lramm_ts_plan_destroy(lramm_ts_plan* plan);
+LRAMM_API lramm_status lramm_ts_workspace_bytes(const lramm_ts_plan* plan, size_t* bytes);
+LRAMM_API lramm_status lramm_ts_forward(lramm_ts_plan* plan, const void* A, int64_t lda, const void* B,
+                           int64_t ldb, void* C, int64_t ldc, const float* omega_a, int64_t ldoa,
+                           const float* omega_b, int64_t ldob, void* ws, size_t ws_bytes, void* stream);
+/* Views of the two-sided intermediates (FP32 unless noted):
+ *   LRAMM_TS_UT U~ (m x r), LRAMM_TS_VT V_A^T (r x k), LRAMM_TS_W W_B (k x r),
+ *   LRAMM_TS_ZS Z~ (r x n), LRAMM_TS_E1 (r x r), LRAMM_TS_E2 (r x n),
+ *   LRAMM_TS_SA / LRAMM_TS_SB singular values (r, FP64),
+ *   LRAMM_TS_UPA / LRAMM_TS_UPB U' (l x r, FP64). */
+enum { LRAMM_TS_UT = 0, LRAMM_TS_VT = 1, LRAMM_TS_W = 2, LRAMM_TS_ZS = 3, LRAMM_TS_E1 = 4, LRAMM_TS_E2 = 5,
+       LRAMM_TS_SA = 6, LRAMM_TS_SB = 7, LRAMM_TS_UPA = 8, LRAMM_TS_UPB = 9 };
+LRAMM_API lramm_status lramm_ts_intermediate(const lramm_ts_plan* plan, const void* ws, int32_t which,
+                           const void** ptr, int64_t* rows, int64_t* cols, int64_t* ld,
+                           int32_t* dtype);
+/* Synchronise and OR the status words of both RSVDs and of the chain
+ * (LRAMM_FLAG_BREAKDOWN also when Jacobi did not converge in 60 sweeps). */
+LRAMM_API lramm_status lramm_ts_status_poll(const lramm_ts_plan* plan, const void* ws, void* stream,
+                           uint32_t* flags);
+
 /* Dense comparator GEMM (no quantisation, no vendor library):
  * C[M x N] = L[M x K] . R[N x K]^T with both operands K-contiguous.
  * dtype BF16: bf16 inputs (uint16 storage), FP32 accumulation, FP32 output.

@@ -11,7 +11,7 @@ package only marshals torch tensors, sizes and the current stream.
 import torch
 
 from ._lib import (  # noqa: F401
-    EXPORTS, LIB_PATH, LrammBatch, LrammError, LrammPlan, autotune_rank, load, lramm_cholqr2, storage,
+    EXPORTS, LIB_PATH, LrammBatch, LrammError, LrammPlan, LrammTsPlan, autotune_rank, load, lramm_cholqr2, storage,
     lramm_cholqr2_workspace, lramm_cholqr2_noalloc, NOALLOC_SCRATCH_BYTES, E_SCRATCH,
     lramm_dense_gemm_nt, lramm_gemm_nt, lramm_gemm_nt_workspace, lramm_init, lramm_omega,
     lramm_pitch, lramm_quantize, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_SQRTNEG, FLAG_STALL,

@@ -36,6 +36,8 @@ EXPORTS = (
     "lramm_stage_name", "lramm_intermediate", "lramm_batch_create", "lramm_batch_destroy",
     "lramm_batch_workspace_bytes", "lramm_batched_forward", "lramm_batch_status_poll",
     "lramm_cholqr2_noalloc", "lramm_chol_one_launch", "lramm_codes",
+    "lramm_ts_plan_create", "lramm_ts_plan_destroy", "lramm_ts_workspace_bytes", "lramm_ts_forward",
+    "lramm_ts_intermediate", "lramm_ts_status_poll",
 )
 NSTAGES = 22
 
@@ -44,6 +46,19 @@ class LrammError(RuntimeError):
     def __init__(self, code, where):
         self.code = code
         super().__init__(f"{where}: {_status_string(code)} (status {code})")
+
+
+class TsDesc(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+        ("r", ctypes.c_int32), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
+        ("fmt_sketch", ctypes.c_int32), ("fmt_proj", ctypes.c_int32),
+        ("fmt_e1", ctypes.c_int32), ("fmt_e2", ctypes.c_int32), ("fmt_e3", ctypes.c_int32),
+        ("a_type", ctypes.c_int32), ("b_type", ctypes.c_int32), ("c_type", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("alpha", ctypes.c_float), ("beta", ctypes.c_float),
+        ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+    ]
 
 
 class Desc(ctypes.Structure):
@@ -103,6 +118,13 @@ def load(path=LIB_PATH):
         "lramm_chol_one_launch": ([I64, I32, ctypes.c_uint32], I32),
         "lramm_codes": ([P, P, I32, ctypes.POINTER(P), ctypes.POINTER(I64), ctypes.POINTER(I64),
                          ctypes.POINTER(I64), ctypes.POINTER(P), ctypes.POINTER(I32)], I32),
+        "lramm_ts_plan_create": ([ctypes.POINTER(TsDesc), ctypes.POINTER(P)], I32),
+        "lramm_ts_plan_destroy": ([P], None),
+        "lramm_ts_workspace_bytes": ([P, ctypes.POINTER(SZ)], I32),
+        "lramm_ts_forward": ([P, P, I64, P, I64, P, I64, P, I64, P, I64, P, SZ, P], I32),
+        "lramm_ts_intermediate": ([P, P, I32, ctypes.POINTER(P), ctypes.POINTER(I64), ctypes.POINTER(I64),
+                                   ctypes.POINTER(I64), ctypes.POINTER(I32)], I32),
+        "lramm_ts_status_poll": ([P, P, P, ctypes.POINTER(ctypes.c_uint32)], I32),
         "lramm_dense_gemm_nt": ([I64, I64, I64, I32, P, I64, P, I64, P, I64, P], I32),
         "lramm_plan_set_timing": ([P, I32], I32),
         "lramm_stage_times": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], I32),
@@ -394,6 +416,64 @@ class LrammPlan:
         f = ctypes.c_uint32()
         code = load().lramm_status_poll(self._h, _ptr(ws), _stream(), ctypes.byref(f))
         _check(code, "lramm_status_poll")
+        return int(f.value)
+
+
+class LrammTsPlan:
+    """Two-sided LRAMM (the paper's Alg. 3): lramm_ts_plan_create /
+    lramm_ts_forward / lramm_ts_intermediate / lramm_ts_status_poll.
+    ``rsvd_fmt`` = formats of both RSVDs' sketch and projection, ``d`` =
+    the budgets (d1, d2, d3) of E1, E2, E3."""
+
+    VIEWS = {"Ut": 0, "Vt": 1, "W": 2, "Zs": 3, "E1": 4, "E2": 5, "SA": 6, "SB": 7, "UpA": 8, "UpB": 9}
+
+    def __init__(self, m, n, k, r, p=8, q=1, rsvd_fmt=("int8", "int8"), d=("int8",) * 3, a_type=torch.float32,
+                 b_type=torch.float32, c_type=torch.float32, seed=0, alpha=1.0, beta=0.0):
+        lib = load()
+        t = TsDesc()
+        t.m, t.n, t.k, t.r, t.p, t.q = m, n, k, r, p, q
+        t.fmt_sketch, t.fmt_proj = (_fmt(f) for f in rsvd_fmt)
+        t.fmt_e1, t.fmt_e2, t.fmt_e3 = (_fmt(f) for f in d)
+        t.a_type, t.b_type, t.c_type = DTYPE[a_type], DTYPE[b_type], DTYPE[c_type]
+        t.seed, t.alpha, t.beta, t.flags = seed, alpha, beta, 0
+        self.desc, self.c_type = t, c_type
+        h = P()
+        _check(lib.lramm_ts_plan_create(ctypes.byref(t), ctypes.byref(h)), "lramm_ts_plan_create")
+        self._h = h
+        sz = SZ()
+        _check(lib.lramm_ts_workspace_bytes(h, ctypes.byref(sz)), "lramm_ts_workspace_bytes")
+        self.ws_bytes = int(sz.value)
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.lramm_ts_plan_destroy(self._h)
+            self._h = None
+
+    def workspace(self, device="cuda"):
+        return torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+
+    def forward(self, A, B, ws, C=None, omega_a=None, omega_b=None):
+        t = self.desc
+        if C is None:
+            C = torch.empty((t.m, t.n), dtype=self.c_type, device=A.device)
+        _check(load().lramm_ts_forward(self._h, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(C), C.stride(0),
+                                       _ptr(omega_a), 0 if omega_a is None else omega_a.stride(0), _ptr(omega_b),
+                                       0 if omega_b is None else omega_b.stride(0), _ptr(ws), ws.numel(), _stream()),
+               "lramm_ts_forward")
+        return C
+
+    def intermediate(self, ws, name):
+        ptr, rows, cols, ld, dt = P(), I64(), I64(), I64(), I32()
+        _check(load().lramm_ts_intermediate(self._h, _ptr(ws), self.VIEWS[name], ctypes.byref(ptr),
+                                            ctypes.byref(rows), ctypes.byref(cols), ctypes.byref(ld),
+                                            ctypes.byref(dt)), "lramm_ts_intermediate")
+        esz, tdt = (8, torch.float64) if dt.value == F64 else (4, torch.float32)
+        off = ptr.value - ws.data_ptr()
+        return ws[off:off + rows.value * ld.value * esz].view(tdt).view(rows.value, ld.value)[:, :cols.value]
+
+    def status(self, ws):
+        f = ctypes.c_uint32()
+        _check(load().lramm_ts_status_poll(self._h, _ptr(ws), _stream(), ctypes.byref(f)), "lramm_ts_status_poll")
         return int(f.value)
 
 

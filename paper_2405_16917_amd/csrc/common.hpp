@@ -262,4 +262,17 @@ lramm_status launch_gemm_f32(int64_t M, int64_t N, int64_t K, const void* A, int
                              int a_type, const void* B, int64_t ldb, int b_kmajor, int b_type, void* C,
                              int64_t ldc, int c_type, hipStream_t s);
 
+// Two-sided form: FP64 Gram of the rows of X (n x n, zero past rows), the
+// small SVD from it by Jacobi (n even, <= jacobi_max_order()), and FP32
+// results of FP64-accumulated products (operands FP32 or FP64, layouts as
+// launch_gemm_f32).
+lramm_status launch_rowgram(int rows, int cols, const void* X, int64_t ldx, int xtype, double* G, int n,
+                            hipStream_t s);
+int jacobi_max_order();
+lramm_status launch_jacobi_svd(int n, int r, const double* G, double* V, double* Up, double* S, double* UpS,
+                               double* UpSinv, uint32_t* flags, hipStream_t s);
+lramm_status launch_gemm_f64acc(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, int a_kmajor,
+                                int a_type, const void* B, int64_t ldb, int b_kmajor, int b_type, float* C,
+                                int64_t ldc, hipStream_t s);
+
 }  // namespace lramm

@@ -394,13 +394,20 @@ lramm_status lramm_workspace_bytes(const lramm_plan* plan, size_t* bytes) {
   return LRAMM_OK;
 }
 
-lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
-                           int64_t ldc, const float* omega, int64_t ldo, void* ws, size_t ws_bytes, void* stream) {
-  if (!P || !A || !B || !C) return LRAMM_E_INVALID;
+}  // extern "C"
+
+namespace {
+// The forward; with range_only (B and C unused, may be null) it stops after
+// the projection Bt = Q^T A, leaving Q and Bt in the workspace.
+lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                          int64_t ldc, const float* omega, int64_t ldo, void* ws, size_t ws_bytes, void* stream,
+                          bool range_only) {
+  if (!P || !A || (!range_only && (!B || !C))) return LRAMM_E_INVALID;
   if (!ws || ws_bytes < P->total) return LRAMM_E_WORKSPACE;
   {
     const lramm_desc& u = P->user;
-    if (lda < (u.trans_a ? u.m : u.k) || ldb < (u.trans_b ? u.k : u.n) || ldc < u.n) return LRAMM_E_SHAPE;
+    if (lda < (u.trans_a ? u.m : u.k)) return LRAMM_E_SHAPE;
+    if (!range_only && (ldb < (u.trans_b ? u.k : u.n) || ldc < u.n)) return LRAMM_E_SHAPE;
   }
   if (P->user.side) {   // run on A' = B^T, B' = A^T
     std::swap(A, B);
@@ -505,10 +512,12 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
              launch_quantize(m, k, A, lda, d.a_type, d.fmt_proj, 1, Ac, P->pAc, sAc, flags, s2, mxA));
   else   // the columns of A' are the stored rows
     TIMED_ON(s2, ST_QUANT_A_COLS, launch_quantize(k, m, A, lda, d.a_type, d.fmt_proj, 0, Ac, P->pAc, sAc, flags, s2));
-  if (!P->bt)
+  if (range_only) {
+  } else if (!P->bt) {
     TIMED_ON(s2, ST_QUANT_B, launch_quantize(k, n, B, ldb, d.b_type, d.fmt_g1, 1, Bc, P->pBc, sBc, flags, s2, mxB));
-  else
+  } else {
     TIMED_ON(s2, ST_QUANT_B, launch_quantize(n, k, B, ldb, d.b_type, d.fmt_g1, 0, Bc, P->pBc, sBc, flags, s2));
+  }
   if (P->side) LRAMM_HIP(hipEventRecord(P->ev_join, P->side));
   TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(0),
                                    P->chain_mode));
@@ -540,6 +549,7 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
         launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s, mxQ(d.q), true));
   TIMED(ST_PROJ, launch_gemm_nt(l, k, m, d.fmt_proj, Qc, P->pQc, sQc, Ac, P->pAc, sAc, 1.0f, 0.0f, Bt, k, LRAMM_F32,
                                 nullptr, 0, split, sb, s));
+  if (range_only) return LRAMM_OK;
   // G1: T^T = B_c . Bt_q^T  (n x l)
   uint8_t* Btq = at<uint8_t>(W, P->off_Btq);
   float* sBt = at<float>(W, P->off_sBt);
@@ -568,6 +578,14 @@ lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void
 #undef TIMED
 #undef TIMED_ON
   return LRAMM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lramm_status lramm_forward(lramm_plan* P, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                           int64_t ldc, const float* omega, int64_t ldo, void* ws, size_t ws_bytes, void* stream) {
+  return forward_impl(P, A, lda, B, ldb, C, ldc, omega, ldo, ws, ws_bytes, stream, false);
 }
 
 lramm_status lramm_factors(const lramm_plan* P, const void* ws, const double** Q, int64_t* ldq, const float** Bt,
@@ -954,6 +972,231 @@ lramm_status lramm_cholqr2_noalloc(int64_t rows, int64_t l, const void* Y, int64
   // no clearing
   return launch_cholqr2(rows, l, Y, ldy, ytype, Q, ldq, ws, (size_t)LRAMM_NOALLOC_SCRATCH_BYTES, flags,
                         (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------ two-sided --
+// Alg. 3: rank-r RSVD of A and of B (each the one-sided range finder and
+// projection, then the small SVD of the l x k projection through its Gram
+// matrix), Sigma and Gamma absorbed into U~ = Q_A U'_A S_A and
+// Z~ = U'_B^T (Q_B^T B) = G_B Z_B^T, and the chain E1 = QM(V^T W, d1),
+// E2 = QM(E1 Z~, d2), D = alpha QM(U~ E2, d3) + beta C.
+
+}  // extern "C"
+
+struct lramm_ts_plan {
+  lramm_ts_desc d;
+  lramm_plan* pa = nullptr;   // RSVD of A: one-sided plan run up to its projection
+  lramm_plan* pb = nullptr;   // RSVD of B: B as the left operand (k x n)
+  int64_t l = 0, n2 = 0;      // sketch width and its even padding (Jacobi order)
+  size_t off_wa = 0, off_wb = 0, off_flags = 0;
+  size_t off_GA, off_GB, off_VA, off_VB, off_UpA, off_SA, off_UpSA, off_UpSiA, off_UpB, off_SB, off_UpSB, off_UpSiB;
+  size_t off_Ut, off_Vt, off_W, off_Zs, off_E1, off_E2;
+  size_t off_Vtq, off_sVt, off_Wq, off_sW, off_E1q, off_sE1, off_Zsq, off_sZs, off_Utq, off_sUt, off_E2q, off_sE2;
+  size_t off_split = 0, split_bytes = 0;
+  int64_t pVt, pW, pE1, pZs, pUt, pE2;
+  size_t total = 0;
+};
+
+extern "C" {
+
+lramm_status lramm_ts_plan_create(const lramm_ts_desc* desc, lramm_ts_plan** out) {
+  if (!desc || !out) return LRAMM_E_INVALID;
+  const lramm_ts_desc& d = *desc;
+  if (d.m <= 0 || d.n <= 0 || d.k <= 0 || d.m > INT32_MAX || d.n > INT32_MAX || d.k > INT32_MAX)
+    return LRAMM_E_SHAPE;
+  if (d.r < 1 || d.p < 0 || d.q < 0 || d.q > 16 || d.flags != 0) return LRAMM_E_INVALID;
+  const int64_t l = (int64_t)d.r + d.p;
+  if (l > d.m || l > d.k || l > d.n) return LRAMM_E_RANK;
+  const int64_t n2 = round_up(l, 2);
+  if (n2 > jacobi_max_order()) return LRAMM_E_UNSUPPORTED;
+  if (!valid_fmt(d.fmt_e1) || !valid_fmt(d.fmt_e2) || !valid_fmt(d.fmt_e3)) return LRAMM_E_UNSUPPORTED;
+  if ((d.fmt_e1 != LRAMM_BF16F && d.k > qk_bound(d.fmt_e1)) ||
+      (d.fmt_e2 != LRAMM_BF16F && d.r > qk_bound(d.fmt_e2)) || (d.fmt_e3 != LRAMM_BF16F && d.r > qk_bound(d.fmt_e3)))
+    return LRAMM_E_OVERFLOW;
+  if (!valid_io(d.c_type)) return LRAMM_E_UNSUPPORTED;
+  lramm_desc da{};
+  da.m = d.m, da.n = 1, da.k = d.k, da.r = d.r, da.p = d.p, da.q = d.q;
+  da.fmt_sketch = d.fmt_sketch, da.fmt_proj = d.fmt_proj, da.fmt_g1 = LRAMM_INT8, da.fmt_g2 = LRAMM_INT8;
+  da.a_type = d.a_type, da.b_type = LRAMM_F32, da.c_type = LRAMM_F32, da.seed = d.seed;
+  da.alpha = 1.0f, da.beta = 0.0f;
+  lramm_desc db = da;
+  db.m = d.k, db.k = d.n, db.a_type = d.b_type, db.seed = d.seed + 1;
+  lramm_ts_plan* p = new (std::nothrow) lramm_ts_plan();
+  if (!p) return LRAMM_E_INVALID;
+  p->d = d;
+  p->l = l;
+  p->n2 = n2;
+  lramm_status st = lramm_plan_create(&da, &p->pa);
+  if (st == LRAMM_OK) st = lramm_plan_create(&db, &p->pb);
+  if (st != LRAMM_OK) {
+    lramm_ts_plan_destroy(p);
+    return st;
+  }
+  const int64_t m = d.m, n = d.n, k = d.k, r = d.r;
+  size_t c = 0;
+  p->off_flags = carve(&c, 256);
+  p->off_wa = carve(&c, p->pa->total);
+  p->off_wb = carve(&c, p->pb->total);
+  const size_t sq = (size_t)n2 * n2 * 8, fr = (size_t)n2 * r * 8;
+  p->off_GA = carve(&c, sq), p->off_GB = carve(&c, sq), p->off_VA = carve(&c, sq), p->off_VB = carve(&c, sq);
+  p->off_UpA = carve(&c, fr), p->off_UpSA = carve(&c, fr), p->off_UpSiA = carve(&c, fr), p->off_SA = carve(&c, r * 8);
+  p->off_UpB = carve(&c, fr), p->off_UpSB = carve(&c, fr), p->off_UpSiB = carve(&c, fr), p->off_SB = carve(&c, r * 8);
+  p->off_Ut = carve(&c, (size_t)m * r * 4), p->off_Vt = carve(&c, (size_t)r * k * 4);
+  p->off_W = carve(&c, (size_t)k * r * 4), p->off_Zs = carve(&c, (size_t)r * n * 4);
+  p->off_E1 = carve(&c, (size_t)r * r * 4), p->off_E2 = carve(&c, (size_t)r * n * 4);
+  p->pVt = pitch_bytes(k, d.fmt_e1), p->pW = pitch_bytes(k, d.fmt_e1);
+  p->pE1 = pitch_bytes(r, d.fmt_e2), p->pZs = pitch_bytes(r, d.fmt_e2);
+  p->pUt = pitch_bytes(r, d.fmt_e3), p->pE2 = pitch_bytes(r, d.fmt_e3);
+  p->off_Vtq = carve(&c, (size_t)r * p->pVt), p->off_sVt = carve(&c, r * 4);
+  p->off_Wq = carve(&c, (size_t)r * p->pW), p->off_sW = carve(&c, r * 4);
+  p->off_E1q = carve(&c, (size_t)r * p->pE1), p->off_sE1 = carve(&c, r * 4);
+  p->off_Zsq = carve(&c, (size_t)n * p->pZs), p->off_sZs = carve(&c, n * 4);
+  p->off_Utq = carve(&c, (size_t)m * p->pUt), p->off_sUt = carve(&c, m * 4);
+  p->off_E2q = carve(&c, (size_t)n * p->pE2), p->off_sE2 = carve(&c, n * 4);
+  size_t sb = 0, t;
+  t = gemm_nt_workspace(r, r, k, d.fmt_e1); sb = t > sb ? t : sb;
+  t = gemm_nt_workspace(r, n, r, d.fmt_e2); sb = t > sb ? t : sb;
+  t = gemm_nt_workspace(m, n, r, d.fmt_e3); sb = t > sb ? t : sb;
+  p->split_bytes = sb;
+  p->off_split = carve(&c, sb);
+  p->total = c + 256;
+  *out = p;
+  return LRAMM_OK;
+}
+
+void lramm_ts_plan_destroy(lramm_ts_plan* p) {
+  if (!p) return;
+  lramm_plan_destroy(p->pa);
+  lramm_plan_destroy(p->pb);
+  delete p;
+}
+
+lramm_status lramm_ts_workspace_bytes(const lramm_ts_plan* p, size_t* bytes) {
+  if (!p || !bytes) return LRAMM_E_INVALID;
+  *bytes = p->total;
+  return LRAMM_OK;
+}
+
+lramm_status lramm_ts_forward(lramm_ts_plan* P, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                              int64_t ldc, const float* omega_a, int64_t ldoa, const float* omega_b, int64_t ldob,
+                              void* ws, size_t ws_bytes, void* stream) {
+  if (!P || !A || !B || !C) return LRAMM_E_INVALID;
+  if (!ws || ws_bytes < P->total) return LRAMM_E_WORKSPACE;
+  const lramm_ts_desc& d = P->d;
+  const int64_t m = d.m, n = d.n, k = d.k, r = d.r, l = P->l, n2 = P->n2;
+  if (lda < k || ldb < n || ldc < n) return LRAMM_E_SHAPE;
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* W = reinterpret_cast<uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
+  uint32_t* flags = at<uint32_t>(W, P->off_flags);
+  LRAMM_TRY(fill_u32(flags, 0u, 1, s));
+  // 1. RSVD range finders and projections: Q_A (m x l), Bt_A = Q_A^T A
+  //    (l x k); Q_B (k x l), Bt_B = Q_B^T B (l x n)
+  void* wa = W + P->off_wa;
+  void* wb = W + P->off_wb;
+  LRAMM_TRY(forward_impl(P->pa, A, lda, nullptr, 0, nullptr, 0, omega_a, ldoa, wa, P->pa->total, stream, true));
+  LRAMM_TRY(forward_impl(P->pb, B, ldb, nullptr, 0, nullptr, 0, omega_b, ldob, wb, P->pb->total, stream, true));
+  const uint8_t* ba = reinterpret_cast<const uint8_t*>(round_up((int64_t)(uintptr_t)wa, 256));
+  const uint8_t* bb = reinterpret_cast<const uint8_t*>(round_up((int64_t)(uintptr_t)wb, 256));
+  const double* QA = reinterpret_cast<const double*>(ba + P->pa->off_Q);
+  const float* BtA = reinterpret_cast<const float*>(ba + P->pa->off_Bt);
+  const double* QB = reinterpret_cast<const double*>(bb + P->pb->off_Q);
+  const float* BtB = reinterpret_cast<const float*>(bb + P->pb->off_Bt);
+  const int64_t lpA = P->pa->lp, lpB = P->pb->lp;
+  // 2. small SVDs: Gram of the projections' rows, Jacobi, rank-r factors
+  double* GA = at<double>(W, P->off_GA);
+  double* GB = at<double>(W, P->off_GB);
+  LRAMM_TRY(launch_rowgram((int)l, (int)k, BtA, k, LRAMM_F32, GA, (int)n2, s));
+  LRAMM_TRY(launch_rowgram((int)l, (int)n, BtB, n, LRAMM_F32, GB, (int)n2, s));
+  double* UpA = at<double>(W, P->off_UpA);
+  double* UpSA = at<double>(W, P->off_UpSA);
+  double* UpSiA = at<double>(W, P->off_UpSiA);
+  double* UpB = at<double>(W, P->off_UpB);
+  LRAMM_TRY(launch_jacobi_svd((int)n2, (int)r, GA, at<double>(W, P->off_VA), UpA, at<double>(W, P->off_SA), UpSA,
+                              UpSiA, flags, s));
+  LRAMM_TRY(launch_jacobi_svd((int)n2, (int)r, GB, at<double>(W, P->off_VB), UpB, at<double>(W, P->off_SB),
+                              at<double>(W, P->off_UpSB), at<double>(W, P->off_UpSiB), flags, s));
+  // 3. factors in FP64 (rounded once to binary32): U~ = Q_A U'_A S_A (m x r),
+  //    V^T = S_A^-1 U'_A^T Bt_A (r x k), W = Q_B U'_B (k x r),
+  //    Z~ = U'_B^T Bt_B (r x n); rows of U' past l are zero
+  float* Ut = at<float>(W, P->off_Ut);
+  float* Vt = at<float>(W, P->off_Vt);
+  float* Wf = at<float>(W, P->off_W);
+  float* Zs = at<float>(W, P->off_Zs);
+  LRAMM_TRY(launch_gemm_f64acc(m, r, l, QA, lpA, 0, LRAMM_F64, UpSA, r, 1, LRAMM_F64, Ut, r, s));
+  LRAMM_TRY(launch_gemm_f64acc(r, k, l, UpSiA, r, 1, LRAMM_F64, BtA, k, 1, LRAMM_F32, Vt, k, s));
+  LRAMM_TRY(launch_gemm_f64acc(k, r, l, QB, lpB, 0, LRAMM_F64, UpB, r, 1, LRAMM_F64, Wf, r, s));
+  LRAMM_TRY(launch_gemm_f64acc(r, n, l, UpB, r, 1, LRAMM_F64, BtB, n, 1, LRAMM_F32, Zs, n, s));
+  // 4. the chain of quantised products (Alg. 2 each)
+  void* split = P->split_bytes ? at<void>(W, P->off_split) : nullptr;
+  const size_t sb = P->split_bytes;
+  uint8_t* Vtq = at<uint8_t>(W, P->off_Vtq);
+  float* sVt = at<float>(W, P->off_sVt);
+  uint8_t* Wq = at<uint8_t>(W, P->off_Wq);
+  float* sW = at<float>(W, P->off_sW);
+  float* E1 = at<float>(W, P->off_E1);
+  LRAMM_TRY(launch_quantize(r, k, Vt, k, LRAMM_F32, d.fmt_e1, 0, Vtq, P->pVt, sVt, flags, s));
+  LRAMM_TRY(launch_quantize(k, r, Wf, r, LRAMM_F32, d.fmt_e1, 1, Wq, P->pW, sW, flags, s));
+  LRAMM_TRY(launch_gemm_nt(r, r, k, d.fmt_e1, Vtq, P->pVt, sVt, Wq, P->pW, sW, 1.0f, 0.0f, E1, r, LRAMM_F32, nullptr,
+                           0, split, sb, s));
+  uint8_t* E1q = at<uint8_t>(W, P->off_E1q);
+  float* sE1 = at<float>(W, P->off_sE1);
+  uint8_t* Zsq = at<uint8_t>(W, P->off_Zsq);
+  float* sZs = at<float>(W, P->off_sZs);
+  float* E2 = at<float>(W, P->off_E2);
+  LRAMM_TRY(launch_quantize(r, r, E1, r, LRAMM_F32, d.fmt_e2, 0, E1q, P->pE1, sE1, flags, s));
+  LRAMM_TRY(launch_quantize(r, n, Zs, n, LRAMM_F32, d.fmt_e2, 1, Zsq, P->pZs, sZs, flags, s));
+  LRAMM_TRY(launch_gemm_nt(r, n, r, d.fmt_e2, E1q, P->pE1, sE1, Zsq, P->pZs, sZs, 1.0f, 0.0f, E2, n, LRAMM_F32,
+                           nullptr, 0, split, sb, s));
+  uint8_t* Utq = at<uint8_t>(W, P->off_Utq);
+  float* sUt = at<float>(W, P->off_sUt);
+  uint8_t* E2q = at<uint8_t>(W, P->off_E2q);
+  float* sE2 = at<float>(W, P->off_sE2);
+  LRAMM_TRY(launch_quantize(m, r, Ut, r, LRAMM_F32, d.fmt_e3, 0, Utq, P->pUt, sUt, flags, s));
+  LRAMM_TRY(launch_quantize(r, n, E2, n, LRAMM_F32, d.fmt_e3, 1, E2q, P->pE2, sE2, flags, s));
+  LRAMM_TRY(launch_gemm_nt(m, n, r, d.fmt_e3, Utq, P->pUt, sUt, E2q, P->pE2, sE2, d.alpha, d.beta, C, ldc, d.c_type,
+                           nullptr, 0, split, sb, s));
+  return LRAMM_OK;
+}
+
+lramm_status lramm_ts_intermediate(const lramm_ts_plan* P, const void* ws, int32_t which, const void** ptr,
+                                   int64_t* rows, int64_t* cols, int64_t* ld, int32_t* dtype) {
+  if (!P || !ws || !ptr || !rows || !cols || !ld || !dtype) return LRAMM_E_INVALID;
+  const uint8_t* base = reinterpret_cast<const uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
+  const lramm_ts_desc& d = P->d;
+  const int64_t m = d.m, n = d.n, k = d.k, r = d.r;
+  auto set = [&](size_t off, int64_t rr, int64_t cc, int64_t ll, int32_t t) {
+    *ptr = base + off, *rows = rr, *cols = cc, *ld = ll, *dtype = t;
+  };
+  switch (which) {
+    case LRAMM_TS_UT: set(P->off_Ut, m, r, r, LRAMM_F32); break;
+    case LRAMM_TS_VT: set(P->off_Vt, r, k, k, LRAMM_F32); break;
+    case LRAMM_TS_W: set(P->off_W, k, r, r, LRAMM_F32); break;
+    case LRAMM_TS_ZS: set(P->off_Zs, r, n, n, LRAMM_F32); break;
+    case LRAMM_TS_E1: set(P->off_E1, r, r, r, LRAMM_F32); break;
+    case LRAMM_TS_E2: set(P->off_E2, r, n, n, LRAMM_F32); break;
+    case LRAMM_TS_SA: set(P->off_SA, r, 1, 1, LRAMM_F64); break;
+    case LRAMM_TS_SB: set(P->off_SB, r, 1, 1, LRAMM_F64); break;
+    case LRAMM_TS_UPA: set(P->off_UpA, P->l, r, r, LRAMM_F64); break;
+    case LRAMM_TS_UPB: set(P->off_UpB, P->l, r, r, LRAMM_F64); break;
+    default: return LRAMM_E_INVALID;
+  }
+  return LRAMM_OK;
+}
+
+lramm_status lramm_ts_status_poll(const lramm_ts_plan* P, const void* ws, void* stream, uint32_t* flags) {
+  if (!P || !ws) return LRAMM_E_INVALID;
+  const uint8_t* base = reinterpret_cast<const uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
+  uint32_t fa = 0, fb = 0, own = 0;
+  lramm_status sa = lramm_status_poll(P->pa, base + P->off_wa, stream, &fa);
+  lramm_status sbs = lramm_status_poll(P->pb, base + P->off_wb, stream, &fb);
+  if (sa == LRAMM_E_HIP || sbs == LRAMM_E_HIP) return LRAMM_E_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  LRAMM_HIP(hipMemcpyAsync(&own, base + P->off_flags, sizeof(own), hipMemcpyDeviceToHost, s));
+  LRAMM_HIP(hipStreamSynchronize(s));
+  const uint32_t all = fa | fb | own;
+  if (flags) *flags = all;
+  if (all & LRAMM_FLAG_STALL) return LRAMM_E_STALL;
+  return (all & LRAMM_FLAG_NONFINITE) ? LRAMM_E_NONFINITE : LRAMM_OK;
 }
 
 lramm_status lramm_dense_gemm_nt(int64_t M, int64_t N, int64_t K, int32_t dtype, const void* L, int64_t ldl,

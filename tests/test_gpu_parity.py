@@ -802,3 +802,46 @@ def test_differentiable_layer_workload(lib):
     eX = OL.rel_fro(Xd.grad.double().cpu().numpy(), dXt.T)
     eW = OL.rel_fro(Wd.grad.double().cpu().numpy(), dWt.T)
     assert eX <= 2.0**-8 and eW <= 2.0**-8, (eX, eW)
+
+
+# -------------------------------------------------------- two-sided Alg. 3 --
+
+@pytest.mark.parametrize("d", [("int8", "int8", "int8"), ("int8", "int8", "int4"), ("int8", "int4", "int4"),
+                               ("int4", "int4", "int4")])
+def test_two_sided_matches_oracle(lib, d):
+    """Alg. 3 on the GPU against the oracle's two-sided LRAMM: the small SVDs
+    (singular values, signed U'), the FP64 factor products, and each of the
+    three quantised products bit for bit on the GPU's own inputs; the end
+    result against the independent oracle is reported."""
+    from oracle import two_sided as TS
+    m, k, n, r, p, q = 512, 384, 448, 40, 8, 1
+    A, _ = synth.lowrank(m, k, synth.spectrum("exp", k, 12.0), 31)
+    B, _ = synth.lowrank(k, n, synth.spectrum("exp", k, 14.0), 32)
+    oa, ob = synth.omega(k, r + p, 33), synth.omega(n, r + p, 34)
+    plan = lib.LrammTsPlan(m, n, k, r, p, q, ("int8", "int8"), d)
+    ws = plan.workspace()
+    D = plan.forward(g(A), g(B), ws, omega_a=g(oa), omega_b=g(ob)).double().cpu().numpy()
+    assert plan.status(ws) == 0
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    ref = TS.lramm_two_sided(A64, B64, r, p, q, ("int8", "int8"), d, omega_a=oa.astype(np.float64),
+                             omega_b=ob.astype(np.float64))
+    v = {kk: plan.intermediate(ws, kk).double().cpu().numpy() for kk in
+         ("Ut", "Vt", "W", "Zs", "E1", "E2", "SA", "SB", "UpA", "UpB")}
+    assert np.max(np.abs(v["SA"][:, 0] - ref["S"]) / ref["S"][0]) <= 1e-12
+    assert np.max(np.abs(v["SB"][:, 0] - ref["G"]) / ref["G"][0]) <= 1e-12
+    Up_ref = np.linalg.svd(ref["BtA"], full_matrices=False)[0]
+    Up_ref = TS.sign_fix(Up_ref, np.eye(Up_ref.shape[1]))[0][:, :r]
+    assert np.max(np.abs(v["UpA"] - Up_ref)) <= 1e-9
+    # factors: FP64 products rounded once to binary32
+    for name, refv in (("Ut", ref["Ut"]), ("Vt", ref["Vt"]), ("W", ref["W"]), ("Zs", ref["Zs"])):
+        assert OL.rel_fro(v[name], OQ.fl32(refv)) <= 1e-6, name
+    # the chain, each product on the GPU's own operands: bit for bit
+    from oracle.qgemm import qgemm
+    assert np.array_equal(v["E1"], qgemm(v["Vt"], v["W"], d[0]))
+    assert np.array_equal(v["E2"], qgemm(v["E1"], v["Zs"], d[1]))
+    assert np.array_equal(D, qgemm(v["Ut"], v["E2"], d[2]))
+    err = OL.rel_fro(D, ref["D"])
+    Cex = A64 @ B64
+    print(f"two-sided {d}: rel-F vs oracle {err:.2e}, vs exact gpu {OL.rel_fro(D, Cex):.3e} "
+          f"oracle {OL.rel_fro(ref['D'], Cex):.3e}")
+    assert err <= 1e-3
