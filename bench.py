@@ -75,6 +75,10 @@ def parse():
     ap.add_argument("--fmt", default=None, help="one format for every stage, or four comma-separated")
     ap.add_argument("--sweep", action="store_true", help="search (l, q, formats) per decay rate")
     ap.add_argument("--taus", default="64,128,256")
+    ap.add_argument("--precision-sweep", action="store_true",
+                    help="two-sided Alg. 3 budgets 888/884/844/444 against DQ8/DQ4 on uniform, exponential and "
+                         "normal matrices (the paper's precision test)")
+    ap.add_argument("--size", type=int, default=1024, help="matrix size of --precision-sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-error", action="store_true")
@@ -327,6 +331,51 @@ def sweep(args, lramm, dev):
     print(json.dumps({"sweep_best": best}), flush=True)
 
 
+def precision_sweep(args, lramm, dev):
+    """The paper's precision test (Sec. 4, its Fig. 3) on seeded synthetic
+    inputs: N x N matrices with i.i.d. entries U(0, 1), Exp(1) or N(0, 1);
+    relative Frobenius error against the exact FP64 product of the two-sided
+    method (RSVD in bf16, q = 0 as the paper chooses, p = 8) for each budget
+    d1 d2 d3 and rank r, and of the direct quantised products DQ8 and DQ4."""
+    import numpy as np
+    import torch
+    N = args.size
+    rng_draw = {"uniform": lambda g, s: g.uniform(0.0, 1.0, s), "exponential": lambda g, s: g.exponential(1.0, s),
+                "normal": lambda g, s: g.standard_normal(s)}
+    budgets = {"888": ("int8", "int8", "int8"), "884": ("int8", "int8", "int4"), "844": ("int8", "int4", "int4"),
+               "444": ("int4", "int4", "int4"), "bf16": ("bf16", "bf16", "bf16")}
+    ranks = [r for r in (8, 16, 32, 48, 64, 96, 120) if r + 8 <= min(N, 128)]
+    summary = {}
+    for dist, draw in rng_draw.items():
+        g0 = np.random.default_rng(1000 + len(dist))
+        A_np = draw(g0, (N, N)).astype(np.float32)
+        B_np = draw(g0, (N, N)).astype(np.float32)
+        A, B = torch.from_numpy(A_np).to(dev), torch.from_numpy(B_np).to(dev)
+        Cex = A_np.astype(np.float64) @ B_np.astype(np.float64)
+        nrm = float(np.linalg.norm(Cex))
+        row = {"dist": dist, "N": N}
+        for name, fmt in (("DQ8", "int8"), ("DQ4", "int4")):
+            Lq, dL = lramm.lramm_quantize(A, fmt)
+            Rq, dR = lramm.lramm_quantize(B, fmt, transpose=True)
+            C = lramm.lramm_gemm_nt(N, N, N, fmt, Lq, dL, Rq, dR)
+            row[name] = float(np.linalg.norm(C.double().cpu().numpy() - Cex) / nrm)
+        for r in ranks:
+            for bname, d in budgets.items():
+                plan = lramm.LrammTsPlan(N, N, N, r, 8, 0, ("bf16", "bf16"), d, seed=5)
+                ws = plan.workspace(dev)
+                C = plan.forward(A, B, ws)
+                plan.status(ws)
+                row[f"r{r}_{bname}"] = float(np.linalg.norm(C.double().cpu().numpy() - Cex) / nrm)
+                del plan, ws, C
+        print(json.dumps(row), flush=True)
+        first = {}
+        for bname in budgets:
+            beat = [r for r in ranks if row[f"r{r}_{bname}"] < row["DQ4"]]
+            first[bname] = beat[0] if beat else None
+        summary[dist] = {"DQ8": row["DQ8"], "DQ4": row["DQ4"], "smallest_r_beating_DQ4": first}
+    print(json.dumps({"precision_sweep_summary": summary, "ranks": ranks}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -343,6 +392,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.sweep:
         sweep(args, lramm, dev)
+        return
+    if args.precision_sweep:
+        precision_sweep(args, lramm, dev)
         return
 
     if args.workload == "target":
