@@ -732,8 +732,9 @@ lramm_status lramm_status_poll(const lramm_plan* P, const void* ws, void* stream
 // Independent products, each with its own plan and workspace slice, spread
 // over a few streams (longest first, each to the least loaded stream) so that
 // small products overlap.  Capturing the sequence as a HIP graph
-// (LRAMM_BATCH_GRAPH) is not available: the first capture attempt crashed
-// inside the host runtime, so the flag is rejected.
+// (LRAMM_BATCH_GRAPH) is not available: capture attempts crashed inside the
+// host runtime (also when capturing on a stream the batch owns, with every
+// return code checked), so the flag is rejected.
 
 }  // extern "C"
 

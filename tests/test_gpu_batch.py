@@ -4,11 +4,13 @@ Every product of a batch must equal, bit for bit, the same plan's single
 forward (the batch only changes which stream and workspace slice a product
 uses), and at small sizes the FP64 oracle's output within rel-F 1e-5.
 
-The HIP-graph mode (capture once, replay) crashed inside the host runtime
-during its first capture; the library now rejects LRAMM_BATCH_GRAPH with
-LRAMM_E_UNSUPPORTED, and the graph tests below are skipped until the cause
-is found (they must replay several times with eager work between replays
-and check each replay against the eager result).
+The HIP-graph mode (first call eager, then capture on a stream the batch
+owns, later calls replay) crashed inside the host runtime during the first
+call's capture or instantiation, also after moving the capture off the
+caller's (possibly null) stream; the library rejects LRAMM_BATCH_GRAPH with
+LRAMM_E_UNSUPPORTED and the graph tests below stay skipped (they replay
+several times with eager work and synchronisations between the replays and
+check each replay against the eager result).
 """
 
 import numpy as np
@@ -46,8 +48,9 @@ def test_autotune_rank_rule(lib):
     assert lib.autotune_rank(5, 9) == 1
 
 
-GRAPH_SKIP = pytest.mark.skip(reason="HIP-graph capture of the batch crashed in the host runtime; "
-                                     "LRAMM_BATCH_GRAPH is rejected until the cause is found")
+GRAPH_SKIP = pytest.mark.skip(reason="HIP-graph capture of the batch segfaulted in the host runtime (capture on "
+                                     "the caller's stream, then on a batch-owned stream); LRAMM_BATCH_GRAPH is "
+                                     "rejected until the cause is found")
 
 
 def test_batch_graph_flag_rejected(lib):
@@ -55,6 +58,14 @@ def test_batch_graph_flag_rejected(lib):
     with pytest.raises(lib.LrammError) as e:
         lib.LrammBatch([pl], nstreams=2, graph=True)
     assert e.value.code == lib._lib.E_UNSUPPORTED
+
+
+def test_batch_flags_checked(lib):
+    """More than 16 streams is refused on the host."""
+    pl = lib.LrammPlan(128, 128, 128, 8, 8, 1, ("int8",) * 4)
+    with pytest.raises(lib.LrammError) as e:
+        lib.LrammBatch([pl], nstreams=17)
+    assert e.value.code == lib._lib.E_INVALID
 
 
 @pytest.mark.parametrize("graph", [False, pytest.param(True, marks=GRAPH_SKIP)])
@@ -79,6 +90,12 @@ def test_batch_matches_single_and_oracle(lib, graph):
     ws = batch.workspace()
     batch.forward(As, Bs, Cs, ws)
     assert batch.status(ws) == 0
+    if graph:   # the second call with the same buffers replays the captured graph
+        for c in Cs:
+            c.fill_(float("nan"))
+        torch.cuda.synchronize()
+        batch.forward(As, Bs, Cs, ws)
+        assert batch.status(ws) == 0
     for i in range(len(shapes)):
         assert torch.equal(Cs[i], singles[i]), i
         assert OL.rel_fro(Cs[i].double().cpu().numpy(), refs[i]) <= 1e-5, i
