@@ -19,6 +19,7 @@ Modules
   qgemm   -- quantised GEMM, Alg. 2 (Sec. 3.1), exact integer products
   qr      -- Householder thin QR (range-finder orthonormalisation, Sec. 2.2)
   philox  -- Philox4x32-10 counter RNG + Box-Muller for the Gaussian test matrix
+  srht    -- the structured (subsampled randomised Hadamard) test matrix
   lramm   -- the one-sided LRAMM pipeline (randomised range finder, Sec. 2.2 /
              Alg. 1; chained quantised products, Sec. 3.2), the frozen-Q
              backward, and the error metrics (Sec. 3.3)
@@ -26,4 +27,4 @@ Modules
 Parity status per function is stated in each module header.
 """
 
-from . import quant, qgemm, qr, philox, lramm  # noqa: F401
+from . import quant, qgemm, qr, philox, srht, lramm  # noqa: F401
