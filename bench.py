@@ -59,7 +59,8 @@ SWEEP = {
     256.0: [768, 896, 1024],
 }
 SWEEP_FMTS = {"bf16": ("bf16",) * 4, "int8_sketch": ("int8", "bf16", "bf16", "bf16"),
-              "fp8": ("fp8",) * 4, "int8": ("int8",) * 4}
+              "fp8": ("fp8",) * 4, "int8": ("int8",) * 4, "srht+bf16": (("bf16",) * 4, "srht"),
+              "srht+fp8": (("fp8",) * 4, "srht")}
 
 
 def parse():
@@ -73,6 +74,8 @@ def parse():
     ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--q", type=int, default=None)
     ap.add_argument("--fmt", default=None, help="one format for every stage, or four comma-separated")
+    ap.add_argument("--sketch", default=None, choices=["gaussian", "srht"],
+                    help="test matrix of the first sketch (default: the setting's)")
     ap.add_argument("--sweep", action="store_true", help="search (l, q, formats) per decay rate")
     ap.add_argument("--taus", default="64,128,256")
     ap.add_argument("--precision-sweep", action="store_true",
@@ -136,10 +139,12 @@ def exact_product(A64, B64):
 def run_setting(lramm, A, B, setting, steps, warmup, seed=1, timing=False):
     """Time `steps` forwards of one setting; returns (ms per step, C, plan, ws)."""
     import torch
-    l, p, q, fmt = setting
+    l, p, q, fmt = setting[:4]
+    sketch = setting[4] if len(setting) > 4 else "gaussian"
     m, k = A.shape
     n = B.shape[1]
-    plan = lramm.LrammPlan(m, n, k, l - p, p, q, fmt, A.dtype, B.dtype, A.dtype, seed, exclusive=True)
+    plan = lramm.LrammPlan(m, n, k, l - p, p, q, fmt, A.dtype, B.dtype, A.dtype, seed, exclusive=True,
+                           sketch=sketch)
     ws = plan.workspace(A.device)
     C = torch.empty((m, n), dtype=A.dtype, device=A.device)
     for _ in range(warmup):
@@ -178,7 +183,7 @@ def floors(info, r, l):
 
 # ----------------------------------------------------- measurement work --
 
-def stage_work(name, m, n, k, l, fmt, c_bytes):
+def stage_work(name, m, n, k, l, fmt, c_bytes, sketch="gaussian"):
     """Algorithmic work of ONE launch of a stage: (flops, bytes, peak key).
 
     GEMM: 2 M N K flops; bytes = each operand read once (1 byte per int8 /
@@ -189,6 +194,11 @@ def stage_work(name, m, n, k, l, fmt, c_bytes):
     the solve and the second-pass product rows * l^2."""
     fs, fp, f1, f2 = fmt
     cb = {"int8": 1.0, "int4": 0.5, "fp8": 1.0, "bf16": 2.0}
+    if name == "sketch_gemm" and sketch == "srht":
+        # structured sketch: A read once (input dtype, c_bytes per element),
+        # Y written; k' log2 k' additions per row
+        kp = 1 << max(1, (k - 1).bit_length())
+        return m * kp * math.log2(kp), m * k * c_bytes + m * l * 4.0, "fp32"
     if name in ("sketch_gemm", "power_gemm_Y"):
         return 2.0 * m * l * k, m * k * cb[fs] + l * k * cb[fs] + m * l * 4, fs
     if name == "power_gemm_Z":
@@ -240,17 +250,17 @@ def measured_traffic(kernel):
         return None
 
 
-def roofline(stage_ms, m, n, k, l, fmt, c_bytes):
+def roofline(stage_ms, m, n, k, l, fmt, c_bytes, sketch="gaussian"):
     """Roofline of the kernel with the largest time per step: its algorithmic
     work per launch over its average event-measured launch duration, against
     the MI355X peak of its bound (intensity against the ridge point of its
     dtype)."""
     per_kernel = {}
     for st, (ms, cnt) in stage_ms.items():
-        kern = KERNEL_OF.get(st)
+        kern = "srht_kernel" if (st == "sketch_gemm" and sketch == "srht") else KERNEL_OF.get(st)
         if kern is None or cnt <= 0:
             continue
-        fl, by, pk = stage_work(st, m, n, k, l, fmt, c_bytes)
+        fl, by, pk = stage_work(st, m, n, k, l, fmt, c_bytes, sketch)
         e = per_kernel.setdefault(kern, {"ms": 0.0, "launches": 0.0, "flops": 0.0, "bytes": 0.0, "peak": pk})
         e["ms"] += ms
         e["launches"] += cnt
@@ -312,7 +322,10 @@ def sweep(args, lramm, dev):
         for l in SWEEP.get(tau, SWEEP[64.0]):
             for q in (0, 1):
                 for fname, fmt in SWEEP_FMTS.items():
-                    setting = (l, 32, q, fmt)
+                    sk = "gaussian"
+                    if isinstance(fmt[1], tuple) or fmt[-1] == "srht":
+                        fmt, sk = fmt
+                    setting = (l, 32, q, fmt, sk)
                     try:
                         ms, C, plan, ws = run_setting(lramm, A, B, setting, 5, 2)
                     except lramm.LrammError as e:
@@ -407,8 +420,12 @@ def main():
         p = args.p if args.p is not None else setting[1]
         fmt = tuple(args.fmt.split(",")) if args.fmt and "," in args.fmt else ((args.fmt,) * 4 if args.fmt
                                                                                 else setting[3])
-        setting = (args.l, p, args.q if args.q is not None else setting[2], fmt)
-    l, p, q, fmt = setting
+        setting = (args.l, p, args.q if args.q is not None else setting[2], fmt,
+                   args.sketch or (setting[4] if len(setting) > 4 else "gaussian"))
+    elif args.sketch:
+        setting = tuple(setting[:4]) + (args.sketch,)
+    l, p, q, fmt = setting[:4]
+    sketch = setting[4] if len(setting) > 4 else "gaussian"
     r = l - p
 
     A, B, A64, B64, info = make_inputs(args.workload, tau, dev)
@@ -433,20 +450,21 @@ def main():
     plan.set_timing(False)
     stages = plan.stage_times()
     stage_ms = {kk: (v[0] / args.steps, v[1] / args.steps) for kk, v in stages.items() if v[1]}
-    top, kernels = roofline(stage_ms, m, n, k, l, fmt, c_bytes)
+    top, kernels = roofline(stage_ms, m, n, k, l, fmt, c_bytes, sketch)
 
     dtype = fmt[0] if len(set(fmt)) == 1 else "+".join(fmt)
     wl = (f"{'target' if args.workload == 'target' else 'at-scale'}: A,B {m}x{k}x{n} "
           f"{'bf16' if c_bytes == 2 else 'fp32'}, A = U diag(sigma) V^T, sigma_i = exp(-i/{tau:g})"
           f"{' + entrywise noise var 1e-4' if args.workload != 'target' else ''}, B ~ N(0,1); "
-          f"l = {l} (r = {r}, p = {p}), q = {q}, formats {','.join(fmt)}, Omega from Philox seed {seed}")
+          f"l = {l} (r = {r}, p = {p}), q = {q}, formats {','.join(fmt)}, "
+          f"{'structured (SRHT)' if sketch == 'srht' else 'Gaussian'} test matrix from Philox seed {seed}")
     out = {
         "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "ms_per_step_instrumented": ms_instr,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
         "data": "synthetic (seeded low-rank A with exponential singular-value decay, Gaussian B)",
         "config": {"workload": wl, "m": m, "n": n, "k": k, "tau": tau, "r": r, "p": p, "q": q, "l": l,
-                   "formats": list(fmt), "io": "bf16" if c_bytes == 2 else "fp32"},
+                   "formats": list(fmt), "sketch": sketch, "io": "bf16" if c_bytes == 2 else "fp32"},
         "stages_ms": {st: round(v[0], 5) for st, v in stage_ms.items()},
         "roofline": top,
         "kernels": kernels,
@@ -486,7 +504,8 @@ def main():
             ms2, C2, plan2, ws2 = run_setting(lramm, A2, B2, st, max(5, args.steps // 4), 2, seed)
             Cex2 = exact_product(A2_64, B2_64)
             e2, mx2, _ = rel_errors(C2, Cex2, float(np.linalg.norm(Cex2)))
-            row = {"l": st[0], "p": st[1], "q": st[2], "formats": list(st[3]), "ms_per_step": ms2,
+            row = {"l": st[0], "p": st[1], "q": st[2], "formats": list(st[3]),
+                   "sketch": st[4] if len(st) > 4 else "gaussian", "ms_per_step": ms2,
                    "value": 2.0 * m * n * k / (ms2 * 1e-3) / 1e12, "rel_fro_vs_exact": e2, "max_abs_vs_exact": mx2,
                    "reaches_target": reach and e2 <= TARGET_RELF}
             row.update(floors(info2, st[0] - st[1], st[0]))
@@ -506,7 +525,7 @@ def main():
         with threadpool_limits(limits=cores):
             used = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
             t = time.time()
-            ref = OL.lramm_forward(A64, B64, r, p, q, fmt, seed=seed, keep=False)
+            ref = OL.lramm_forward(A64, B64, r, p, q, fmt, seed=seed, keep=False, sketch=sketch)
             dt = time.time() - t
         out["cpu_baseline"] = {"value": 2.0 * m * n * k / dt / 1e12, "unit": "TFLOP/s", "cores": used,
                                "kind": "oracle", "seconds": dt,

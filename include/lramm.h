@@ -121,7 +121,7 @@ typedef struct {
   int32_t reserved0;
   uint64_t seed;        /* Philox key when the caller passes no Omega      */
   float alpha, beta;
-  uint32_t flags;       /* 0 or LRAMM_PLAN_EXCLUSIVE                       */
+  uint32_t flags;       /* LRAMM_PLAN_EXCLUSIVE | LRAMM_PLAN_SRHT          */
   uint32_t reserved1;
   /* Storage of A and B: 0 row-major as m x k (k x n), 1 stored as the
    * transpose, k x m (n x k) row-major.  C is always m x n row-major. */
@@ -141,6 +141,15 @@ typedef struct {
  * streams are always resident together; larger grids then use per-panel
  * launches whose workgroups never wait on each other. */
 #define LRAMM_PLAN_EXCLUSIVE 0x1u
+/* desc.flags: the first sketch Y = A Omega uses the structured test matrix
+ * of lramm_srht_sketch (the subsampled randomised Hadamard transform; paper
+ * Sec. 2.2, the O(mn log r) RSVD cost) instead of the Gaussian one: one pass
+ * over A, no operand codes, FP32 arithmetic.  fmt_sketch then applies only
+ * to the power iterations' Y = A Q_Z.  Needs A' (the sketched operand as the
+ * library runs it) stored row-major (trans_a = 0, or side = 1 with
+ * trans_b = 1), 2 <= k and k' <= 32768; lramm_forward's omega must be null.
+ * Otherwise LRAMM_E_UNSUPPORTED (LRAMM_E_INVALID for a non-null omega). */
+#define LRAMM_PLAN_SRHT 0x2u
 
 typedef struct lramm_plan lramm_plan;   /* opaque, host memory */
 
@@ -346,6 +355,33 @@ LRAMM_API size_t lramm_gemm_nt_workspace(int64_t M, int64_t N, int64_t K, int32_
  * for (x2, x3) -> (z2, z3) -- and rounded once to binary32. */
 LRAMM_API lramm_status lramm_omega(uint64_t seed, int64_t k, int64_t l, float* OmegaT,
                          int64_t ldo, void* stream);
+
+/* Structured test matrix (Halko, Martinsson & Tropp 2011, Sec. 4.6, real
+ * form; paper Sec. 2.2, the O(mn log r) RSVD cost): with k' the smallest
+ * power of two >= k,
+ *     Omega = (D H)[0:k, S] / sqrt(l)     (k x l),
+ * H the k' x k' Sylvester-Hadamard matrix, H[i][j] = (-1)^popcount(i & j),
+ * D = diag(d_i), d_i = -1 when bit 0 of word x0 of Philox4x32-10 at counter
+ * (i, 0, 1, 0) is set (else +1), and S the indices of the l smallest pairs
+ * (x0 at counter (i, 0, 2, 0), i), in increasing order; key (seed mod 2^32,
+ * seed >> 32) as for lramm_omega.
+ * lramm_srht_padded: k' (0 for k < 1).
+ * lramm_srht_samples: S (l int32, device) and the sign mask sign_bits
+ * (ceil(k' / 32) uint32 words, device; bit i % 32 of word i / 32 set when
+ * d_i = -1).  One workgroup.  Needs 2 <= k, k' <= 32768 (else
+ * LRAMM_E_UNSUPPORTED) and 1 <= l <= k' (else LRAMM_E_RANK).
+ * lramm_srht_sketch: Y (m x l FP32, ldy >= l, device) = A Omega for A m x k
+ * row-major (a_type F32 or BF16, lda >= k, device) from S and sign_bits as
+ * lramm_srht_samples writes them: the fast Walsh-Hadamard transform of each
+ * signed row in binary32, the sampled entries multiplied by fl32(1/sqrt(l)).
+ * Each entry is within (log2 k' + 3) 2^-24 sum_i |A[r][i]| / sqrt(l) of the
+ * exact value.  Same limits on k and l. */
+LRAMM_API int64_t lramm_srht_padded(int64_t k);
+LRAMM_API lramm_status lramm_srht_samples(uint64_t seed, int64_t k, int64_t l, int32_t* S,
+                         uint32_t* sign_bits, void* stream);
+LRAMM_API lramm_status lramm_srht_sketch(int64_t m, int64_t k, int64_t l, const void* A,
+                         int64_t lda, int32_t a_type, const int32_t* S,
+                         const uint32_t* sign_bits, float* Y, int64_t ldy, void* stream);
 
 /* CholeskyQR2 of a rows x l matrix Y (ytype F32 or F64, ldy >= l):
  * Q (rows x l FP64, ldq >= round_up(l, 32)) with orthonormal columns spanning

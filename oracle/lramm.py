@@ -44,7 +44,7 @@ from .quant import fl32
 from .qgemm import qgemm
 from .qr import householder_qr, householder_qr_dropping
 from .philox import gaussian_omega
-from .srht import srht_omega
+from .srht import srht_omega, srht_sketch
 
 FORMATS = ("int8", "int4", "fp8", "bf16", "fp64")
 
@@ -62,13 +62,13 @@ def _q_operand(Q, fmt):
     return Q if fmt == "fp64" else fl32(Q)
 
 
-def range_finder(A, l, q, fs, fp, omega, drop_dependent=False, out=None, keep=True, fs0=None):
+def range_finder(A, l, q, fs, fp, omega, drop_dependent=False, out=None, keep=True, y0=None):
     """Q with l orthonormal columns spanning the sketch of A (Sec. 2.2,
-    first stage): Y = A Omega in format fs (fs0 when given: "fp64" for the
-    structured test matrix, whose sketch takes no operand codes), Q = qr(Y),
-    then q subspace iterations Z = A^T Q (format fp), Q_Z = qr(Z),
-    Y = A Q_Z (fs), Q = qr(Y).  Intermediates go into ``out`` (when given,
-    with ``keep``).  Returns (Q, R) of the last orthonormalisation."""
+    first stage): Y = A Omega in format fs (or y0 when given: the structured
+    sketch, formed without operand codes), Q = qr(Y), then q subspace
+    iterations Z = A^T Q (format fp), Q_Z = qr(Z), Y = A Q_Z (fs), Q = qr(Y).
+    Intermediates go into ``out`` (when given, with ``keep``).  Returns
+    (Q, R) of the last orthonormalisation."""
     if out is None:
         out = {}
     tol = 64.0 * l * 2.0**-53
@@ -80,7 +80,7 @@ def range_finder(A, l, q, fs, fp, omega, drop_dependent=False, out=None, keep=Tr
             return Qd, Rd
         return householder_qr(X)
 
-    Y = _product(A, omega, fs if fs0 is None else fs0)
+    Y = _product(A, omega, fs) if y0 is None else y0
     Q, R = orth(Y)
     if keep:
         out.update(omega=omega, Y0=Y, Q0=Q)
@@ -106,7 +106,8 @@ def lramm_forward(A, B, r, p, q, fmt=("int8",) * 4, omega=None, seed=None,
 
     ``sketch``: "gaussian" (Omega given or drawn from the seed, the first
     sketch in the sketch format) or "srht" (the structured test matrix of
-    srht.py drawn from the seed, the first sketch in FP64).
+    srht.py drawn from the seed: the first sketch is its FP64 product when the
+    sketch format is "fp64", else its binary32 transform).
 
     ``drop_dependent``: orthonormalise with ``householder_qr_dropping`` at
     tolerance 64 l 2^-53 (a sketch column that the earlier ones already span
@@ -128,12 +129,12 @@ def lramm_forward(A, B, r, p, q, fmt=("int8",) * 4, omega=None, seed=None,
     for f in fmt:
         if f not in FORMATS:
             raise ValueError(f"unknown format {f!r}")
-    fs0 = None
+    y0 = None
     if sketch == "srht":
         if omega is not None or seed is None:
             raise ValueError("the structured sketch is drawn from the seed")
         omega = srht_omega(seed, k, l)
-        fs0 = "fp64"
+        y0 = srht_sketch(A, seed, l, "fp64" if fs == "fp64" else "fp32")
     elif sketch != "gaussian":
         raise ValueError(f"unknown sketch {sketch!r}")
     if omega is None:
@@ -145,7 +146,7 @@ def lramm_forward(A, B, r, p, q, fmt=("int8",) * 4, omega=None, seed=None,
         raise ValueError("omega must be k x l")
 
     out = {"l": l}
-    Q, R = range_finder(A, l, q, fs, fp, omega, drop_dependent, out, keep, fs0)
+    Q, R = range_finder(A, l, q, fs, fp, omega, drop_dependent, out, keep, y0)
     Bt = _product(_q_operand(Q, fp).T, A, fp)
     T = _product(Bt, B, f1)
     C = _product(_q_operand(Q, f2), T, f2)

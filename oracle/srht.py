@@ -21,14 +21,24 @@ Definition (shared with the C ABI, both sides implementing it from here):
 so that Y = A Omega = (A_pad D H)[:, S] / sqrt(l).  Over the full padded
 height Omega^T Omega = (k' / l) I.
 
-The sketch is formed in FP64 (no quantisation: the transform needs no
-operand codes).  Power iterations, when asked for, run as in lramm.py.
+The sketch takes no operand codes.  In FP64 (the unquantised mode) it is
+the product A Omega.  Otherwise, like every other stage output that feeds a
+quantiser, it is a binary32 quantity, and its rounding is fixed here: the
+radix-2 Walsh-Hadamard butterflies (u, w) -> (fl32(u + w), fl32(u - w)) on
+index pairs (i, i + 2^s), i without bit s, for s = 0, 1, .., log2 k' - 1 in
+that order, applied to the binary32 row of A times d; then each sampled
+entry is multiplied by fl32(1 / sqrt(l)) with one rounding.  Power
+iterations, when asked for, run as in lramm.py.
 
 Pins (tests/test_oracle_srht.py): H against scipy.linalg.hadamard, the
 identity Omega^T Omega = (k / l) I for k a power of two, S a set of l
 distinct sorted indices whose selection frequencies and signs match their
 probabilities over many seeds, ||A Omega||_F = ||A||_F when l = k = k', and
-exact recovery of a rank-deficient A through the range finder.
+exact recovery of a rank-deficient A through the range finder; the binary32
+transform equal to the FP64 product on integer inputs (every partial sum
+exact) and within (log2 k' + 3) 2^-24 sum_i |a_i| / sqrt(l) of it on random
+ones, and applying the binary32 butterflies twice giving k' times the input
+on integers.
 """
 
 import numpy as np
@@ -82,3 +92,37 @@ def srht_omega(seed, k, l):
     S = srht_samples(seed, k, l)
     H = hadamard_entry(np.arange(k)[:, None], S[None, :])
     return d[:, None] * H / np.sqrt(l)
+
+
+def fwht_fp32(X):
+    """Radix-2 Walsh-Hadamard transform of every row of X (k' columns, a
+    power of two) in binary32, butterflies of bit s = 0, 1, .. in order."""
+    Y = np.array(X, dtype=np.float32)
+    kp = Y.shape[1]
+    h = 1
+    while h < kp:
+        Y = Y.reshape(Y.shape[0], kp // (2 * h), 2, h)
+        u = Y[:, :, 0, :].copy()
+        w = Y[:, :, 1, :].copy()
+        Y[:, :, 0, :] = u + w           # float32 + float32: one IEEE rounding
+        Y[:, :, 1, :] = u - w
+        Y = Y.reshape(-1, kp)
+        h *= 2
+    return Y
+
+
+def srht_sketch(A, seed, l, precision="fp32"):
+    """Y = A Omega: the FP64 product ("fp64") or the binary32 transform
+    ("fp32", values returned as float64)."""
+    A = np.asarray(A, np.float64)
+    m, k = A.shape
+    if precision == "fp64":
+        return A @ srht_omega(seed, k, l)
+    kp = next_pow2(k)
+    X = np.zeros((m, kp), np.float32)
+    X[:, :k] = A.astype(np.float32)
+    X = X * srht_signs(seed, k).astype(np.float32)[None, :]   # exact sign flips
+    T = fwht_fp32(X)
+    S = srht_samples(seed, k, l)
+    scale = np.float32(1.0 / np.sqrt(np.float64(l)))
+    return (T[:, S] * scale).astype(np.float64)

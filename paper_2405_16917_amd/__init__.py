@@ -14,15 +14,17 @@ from ._lib import (  # noqa: F401
     EXPORTS, LIB_PATH, LrammBatch, LrammError, LrammPlan, LrammTsPlan, autotune_rank, load, lramm_cholqr2, storage,
     lramm_cholqr2_workspace, lramm_cholqr2_noalloc, NOALLOC_SCRATCH_BYTES, E_SCRATCH,
     lramm_dense_gemm_nt, lramm_gemm_nt, lramm_gemm_nt_workspace, lramm_init, lramm_omega,
-    lramm_pitch, lramm_quantize, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_SQRTNEG, FLAG_STALL,
+    lramm_pitch, lramm_quantize, lramm_srht_padded, lramm_srht_samples, lramm_srht_sketch, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_SQRTNEG, FLAG_STALL,
 )
 
 
 def matmul(A, B, r, p=16, q=1, fmt=("int8",) * 4, seed=0, omega=None, alpha=1.0, beta=0.0, out=None,
-           out_dtype=None, return_plan=False, check=True, side="left"):
+           out_dtype=None, return_plan=False, check=True, side="left", sketch="gaussian"):
     """C ~ alpha A B + beta out by LRAMM (one-sided, rank l = r + p).
     ``side="right"`` sketches B instead of A.  A or B may be transposed views
     (e.g. ``W.t()``): they are passed as transposed storage, not copied.
+    ``sketch="srht"``: the first sketch uses the structured (subsampled
+    randomised Hadamard) test matrix drawn from ``seed``.
 
     With ``check`` (the default) the device status word is read after the
     forward (this synchronises the stream): a non-finite input or a Cholesky
@@ -33,7 +35,7 @@ def matmul(A, B, r, p=16, q=1, fmt=("int8",) * 4, seed=0, omega=None, alpha=1.0,
     Bs, tb = storage(B)
     c_type = out.dtype if out is not None else (out_dtype or A.dtype)
     plan = LrammPlan(m, n, k, r, p, q, fmt, A.dtype, B.dtype, c_type, seed, alpha, beta, trans_a=ta, trans_b=tb,
-                     side=side)
+                     side=side, sketch=sketch)
     ws = plan.workspace(A.device)
     C = plan.forward(As, Bs, ws, C=out, omega=omega)
     if check:
@@ -50,11 +52,12 @@ class LRAMMConfig:
     and raise LrammError on a non-finite input or an invalid Cholesky factor."""
 
     def __init__(self, r, p=16, q=1, fmt=("int8",) * 4, seed=0, omega=None, recompute=False, check=True,
-                 side="left"):
+                 side="left", sketch="gaussian"):
         self.r, self.p, self.q, self.fmt, self.seed, self.omega = r, p, q, fmt, seed, omega
         self.recompute = recompute
         self.check = check
         self.side = side
+        self.sketch = sketch
 
 
 class LRAMMFunction(torch.autograd.Function):
@@ -71,7 +74,7 @@ class LRAMMFunction(torch.autograd.Function):
         As, ta = storage(A)
         Bs, tb = storage(B)
         plan = LrammPlan(m, n, k, cfg.r, cfg.p, cfg.q, cfg.fmt, A.dtype, B.dtype, A.dtype, cfg.seed,
-                         trans_a=ta, trans_b=tb, side=cfg.side)
+                         trans_a=ta, trans_b=tb, side=cfg.side, sketch=cfg.sketch)
         ws = plan.workspace(A.device)
         C = plan.forward(As, Bs, ws, omega=cfg.omega)
         if cfg.check:

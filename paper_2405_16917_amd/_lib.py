@@ -23,6 +23,8 @@ F32, BF16, F64 = 0, 1, 2
 INT8, INT4, FP8, BF16F = 0, 1, 2, 3
 FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_SQRTNEG, FLAG_STALL = 0x1, 0x2, 0x4, 0x8
 PLAN_EXCLUSIVE = 0x1
+PLAN_SRHT = 0x2
+SKETCHES = {"gaussian": 0, "srht": PLAN_SRHT}
 
 FMT = {"int8": INT8, "int4": INT4, "fp8": FP8, "bf16": BF16F}
 DTYPE = {torch.float32: F32, torch.bfloat16: BF16, torch.float64: F64}
@@ -37,7 +39,8 @@ EXPORTS = (
     "lramm_batch_workspace_bytes", "lramm_batched_forward", "lramm_batch_status_poll",
     "lramm_cholqr2_noalloc", "lramm_chol_one_launch", "lramm_codes",
     "lramm_ts_plan_create", "lramm_ts_plan_destroy", "lramm_ts_workspace_bytes", "lramm_ts_forward",
-    "lramm_ts_intermediate", "lramm_ts_status_poll",
+    "lramm_ts_intermediate", "lramm_ts_status_poll", "lramm_srht_padded", "lramm_srht_samples",
+    "lramm_srht_sketch",
 )
 NSTAGES = 22
 
@@ -112,6 +115,9 @@ def load(path=LIB_PATH):
                            P, I64, I32, P, I64, P, SZ, P], I32),
         "lramm_gemm_nt_workspace": ([I64, I64, I64, I32], SZ),
         "lramm_omega": ([ctypes.c_uint64, I64, I64, P, I64, P], I32),
+        "lramm_srht_padded": ([I64], I64),
+        "lramm_srht_samples": ([ctypes.c_uint64, I64, I64, P, P, P], I32),
+        "lramm_srht_sketch": ([I64, I64, I64, P, I64, I32, P, P, P, I64, P], I32),
         "lramm_cholqr2": ([I64, I64, P, I64, I32, P, I64, P, SZ, P, P], I32),
         "lramm_cholqr2_workspace": ([I64, I64], SZ),
         "lramm_cholqr2_noalloc": ([I64, I64, P, I64, I32, P, I64, P, P], I32),
@@ -220,6 +226,31 @@ def lramm_omega(seed, k, l, device="cuda"):
     return out
 
 
+def lramm_srht_padded(k):
+    return int(load().lramm_srht_padded(k))
+
+
+def lramm_srht_samples(seed, k, l, device="cuda"):
+    """(S [l int32], sign_bits [ceil(k'/32) int32 views of the uint32 words])
+    of the structured test matrix."""
+    kp = lramm_srht_padded(k)
+    S = torch.empty(l, dtype=torch.int32, device=device)
+    bits = torch.empty((kp + 31) // 32, dtype=torch.int32, device=device)
+    _check(load().lramm_srht_samples(seed, k, l, _ptr(S), _ptr(bits), _stream()), "lramm_srht_samples")
+    return S, bits
+
+
+def lramm_srht_sketch(A, l, S, sign_bits, Y=None):
+    """Y = A Omega (m x l FP32) with the structured test matrix given by
+    (S, sign_bits) as lramm_srht_samples writes them."""
+    m, k = A.shape
+    if Y is None:
+        Y = torch.empty((m, l), dtype=torch.float32, device=A.device)
+    _check(load().lramm_srht_sketch(m, k, l, _ptr(A), A.stride(0), DTYPE[A.dtype], _ptr(S), _ptr(sign_bits),
+                                    _ptr(Y), Y.stride(0), _stream()), "lramm_srht_sketch")
+    return Y
+
+
 def lramm_cholqr2_workspace(rows, l):
     return int(load().lramm_cholqr2_workspace(rows, l))
 
@@ -293,13 +324,14 @@ class LrammPlan:
 
     def __init__(self, m, n, k, r, p=16, q=1, fmt=("int8",) * 4, a_type=torch.float32,
                  b_type=torch.float32, c_type=torch.float32, seed=0, alpha=1.0, beta=0.0, exclusive=False,
-                 trans_a=False, trans_b=False, side="left"):
+                 trans_a=False, trans_b=False, side="left", sketch="gaussian"):
         lib = load()
         d = Desc()
         d.m, d.n, d.k, d.r, d.p, d.q = m, n, k, r, p, q
         d.fmt_sketch, d.fmt_proj, d.fmt_g1, d.fmt_g2 = (_fmt(f) for f in fmt)
         d.a_type, d.b_type, d.c_type = DTYPE[a_type], DTYPE[b_type], DTYPE[c_type]
-        d.seed, d.alpha, d.beta, d.flags = seed, alpha, beta, PLAN_EXCLUSIVE if exclusive else 0
+        d.seed, d.alpha, d.beta = seed, alpha, beta
+        d.flags = (PLAN_EXCLUSIVE if exclusive else 0) | SKETCHES[sketch]
         d.trans_a, d.trans_b, d.side = int(bool(trans_a)), int(bool(trans_b)), SIDES[side]
         self.desc = d
         self.c_type = c_type

@@ -171,6 +171,30 @@ __device__ __forceinline__ void encode4(uint8_t* row, int64_t c0, const float v[
   }
 }
 
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds of
+// (hi(M1 x2) ^ x1 ^ k0, lo(M1 x2), hi(M0 x0) ^ x3 ^ k1, lo(M0 x0)), the key
+// bumped by the Weyl constants after every round.
+__device__ __forceinline__ void philox_round(uint32_t& x0, uint32_t& x1, uint32_t& x2, uint32_t& x3, uint32_t k0,
+                                             uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  uint32_t hi0 = __umulhi(M0, x0), lo0 = M0 * x0;
+  uint32_t hi1 = __umulhi(M1, x2), lo1 = M1 * x2;
+  uint32_t n0 = hi1 ^ x1 ^ k0, n2 = hi0 ^ x3 ^ k1;
+  x0 = n0;
+  x1 = lo1;
+  x2 = n2;
+  x3 = lo0;
+}
+
+__device__ __forceinline__ void philox4x32_10(uint32_t ctr[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    philox_round(ctr[0], ctr[1], ctr[2], ctr[3], k0, k1);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ float load_as_f32(const T* p);
 template <>
@@ -213,6 +237,17 @@ lramm_status launch_omega(uint64_t seed, int64_t k, int64_t l, int64_t lrows, fl
 lramm_status launch_omega_quant(uint64_t seed, int64_t k, int64_t l, int fmt, uint8_t* Oq, int64_t pitch,
                                 float* scales, hipStream_t s);
 int64_t omega_quant_max_k();
+
+// Structured test matrix (subsampled randomised Hadamard transform): k' =
+// srht_padded(k) <= 32768 and k >= 2.  The sample set S (l int32, increasing)
+// and the sign mask (ceil(k' / 32) words) from the seed, one workgroup; then
+// Y (m x l, ldy) = (A_pad D H)[:, S] / sqrt(l) from A (m x k row-major, FP32
+// or BF16), one workgroup per row.
+int64_t srht_padded(int64_t k);
+lramm_status launch_srht_samples(uint64_t seed, int64_t k, int64_t l, int32_t* S, uint32_t* sign_bits,
+                                 hipStream_t s);
+lramm_status launch_srht(int64_t m, int64_t k, int64_t l, const void* A, int64_t lda, int a_type,
+                         const uint32_t* sign_bits, const int32_t* S, float* Y, int64_t ldy, hipStream_t s);
 
 // Optional measurement hook: event pairs around individual launches.
 struct TimingHook {

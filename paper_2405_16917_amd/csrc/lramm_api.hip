@@ -42,6 +42,8 @@ struct lramm_plan {
   size_t off_Bt, off_Btq, off_sBt, off_Tt, off_Ttq, off_sTt;
   size_t off_chol, chol_bytes, off_split, split_bytes;
   size_t off_W, off_Bte, off_V;
+  bool srht = false;        // structured first sketch (LRAMM_PLAN_SRHT)
+  size_t off_srS = 0, off_srD = 0;
   // zero-filled at the start of every forward: the status word, then the
   // column-maxima buffers of every column quantisation of the pass
   size_t off_zero, zero_words;
@@ -233,7 +235,12 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   if (!valid_fmt(d.fmt_sketch) || !valid_fmt(d.fmt_proj) || !valid_fmt(d.fmt_g1) || !valid_fmt(d.fmt_g2))
     return LRAMM_E_UNSUPPORTED;
   if (!valid_io(d.a_type) || !valid_io(d.b_type) || !valid_io(d.c_type)) return LRAMM_E_UNSUPPORTED;
-  if (d.flags & ~(uint32_t)LRAMM_PLAN_EXCLUSIVE) return LRAMM_E_INVALID;
+  if (d.flags & ~(uint32_t)(LRAMM_PLAN_EXCLUSIVE | LRAMM_PLAN_SRHT)) return LRAMM_E_INVALID;
+  if (d.flags & LRAMM_PLAN_SRHT) {
+    // the transform runs along rows of A' stored row-major, k' <= 32768
+    const int at0 = desc->side ? 1 - desc->trans_b : desc->trans_a;
+    if (at0 || d.k < 2 || srht_padded(d.k) > 32768) return LRAMM_E_UNSUPPORTED;
+  }
   // int32 accumulator bound of every integer product
   if ((d.fmt_sketch != LRAMM_BF16F && d.k > qk_bound(d.fmt_sketch)) ||
       (d.fmt_proj != LRAMM_BF16F && d.m > qk_bound(d.fmt_proj)) ||
@@ -252,6 +259,7 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   p->bt = desc->side ? 1 - desc->trans_a : desc->trans_b;
   p->ct = desc->side;
   p->chain_mode = (d.flags & LRAMM_PLAN_EXCLUSIVE) ? CHAIN_EXCLUSIVE : CHAIN_SHARED;
+  p->srht = (d.flags & LRAMM_PLAN_SRHT) != 0;
   p->l = l;
   p->lp = lp;
   const int64_t m = d.m, n = d.n, k = d.k;
@@ -291,6 +299,10 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   p->off_OmT = carve(&c, (size_t)l * k * 4);
   p->off_Om = carve(&c, (size_t)l * p->pOm);
   p->off_sOm = carve(&c, (size_t)l * 4);
+  if (p->srht) {
+    p->off_srS = carve(&c, (size_t)l * 4);
+    p->off_srD = carve(&c, (size_t)(srht_padded(k) + 31) / 32 * 4);
+  }
   p->off_Y = carve(&c, (size_t)m * lp * 4);
   p->off_Q = carve(&c, (size_t)m * lp * 8);
   if (d.q > 0) {
@@ -416,6 +428,7 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   const lramm_desc& d = P->d;
   const int64_t m = d.m, n = d.n, k = d.k, l = P->l, lp = P->lp;
   if (omega && ldo < l) return LRAMM_E_SHAPE;
+  if (omega && P->srht) return LRAMM_E_INVALID;   // the structured sketch is drawn from the seed
   hipStream_t s = (hipStream_t)stream;
   uint8_t* base = reinterpret_cast<uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
   void* W = base;
@@ -468,7 +481,13 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
     LRAMM_HIP(hipEventRecord(P->ev_fork, s));
     LRAMM_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
   }
-  if (!omega) {
+  int32_t* srS = P->srht ? at<int32_t>(W, P->off_srS) : nullptr;
+  uint32_t* srD = P->srht ? at<uint32_t>(W, P->off_srD) : nullptr;
+  if (P->srht) {
+    // the sample set and the sign mask (one workgroup)
+    TIMED_ON(s2, ST_OMEGA, launch_srht_samples(d.seed, k, l, srS, srD, s2));
+    if (P->side) LRAMM_HIP(hipEventRecord(P->ev_omega, P->side));
+  } else if (!omega) {
     if (d.fmt_sketch == LRAMM_BF16F || k <= omega_quant_max_k()) {
       // generated and quantised in one pass
       TIMED_ON(s2, ST_OMEGA, launch_omega_quant(d.seed, k, l, d.fmt_sketch, Om, P->pOm, sOm, s2));
@@ -484,7 +503,9 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   // tiles, 16-byte aligned), no pass over A
   const bool a_direct = d.fmt_sketch == LRAMM_BF16F && d.a_type == LRAMM_BF16 && !P->at && k % 64 == 0 &&
                         (lda * 2) % 16 == 0 && (uintptr_t)A % 16 == 0;
-  if (a_direct) {
+  if (P->srht && d.q == 0) {
+    Ar = nullptr;   // the structured sketch reads A itself; no sketch-format codes
+  } else if (a_direct) {
     Ar = reinterpret_cast<uint8_t*>(const_cast<void*>(A));
   } else if (!P->at) {
     TIMED(ST_QUANT_A_ROWS, launch_quantize(m, k, A, lda, d.a_type, d.fmt_sketch, 0, Ar, P->pAr, sAr, flags, s));
@@ -501,8 +522,11 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
     LRAMM_HIP(hipStreamWaitEvent(s, P->ev_omega, 0));   // Omega's codes ready
   }
   // sketch, then the side stream's column codes, then the orthonormalisation
-  TIMED(ST_SKETCH, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, pAr, sAr, Om, P->pOm, sOm, 1.0f, 0.0f, Y, lp,
-                                  LRAMM_F32, nullptr, 0, split, sb, s));
+  if (P->srht)
+    TIMED(ST_SKETCH, launch_srht(m, k, l, A, lda, d.a_type, srD, srS, Y, lp, s));
+  else
+    TIMED(ST_SKETCH, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, pAr, sAr, Om, P->pOm, sOm, 1.0f, 0.0f, Y, lp,
+                                    LRAMM_F32, nullptr, 0, split, sb, s));
   if (P->side) {
     LRAMM_HIP(hipEventRecord(P->ev_sketch, s));
     LRAMM_HIP(hipStreamWaitEvent(P->side, P->ev_sketch, 0));
@@ -639,6 +663,7 @@ lramm_status lramm_codes(const lramm_plan* P, const void* ws, int32_t which, con
       *codes = P->last_Ar;
       break;
     case LRAMM_CODES_SKETCH_R:
+      if (P->srht && d.q == 0) return LRAMM_E_INVALID;   // the structured sketch takes no codes
       if (d.q > 0) set(P->off_QZc, P->off_sQZc, l, k, P->pQZc, d.fmt_sketch);
       else set(P->off_Om, P->off_sOm, l, k, P->pOm, d.fmt_sketch);
       break;
@@ -932,6 +957,24 @@ lramm_status lramm_omega(uint64_t seed, int64_t k, int64_t l, float* OmegaT, int
   if (ldo < k) return LRAMM_E_SHAPE;
   return launch_omega(seed, k, l, l, OmegaT, ldo, (hipStream_t)stream);
 }
+
+lramm_status lramm_srht_samples(uint64_t seed, int64_t k, int64_t l, int32_t* S, uint32_t* sign_bits,
+                                void* stream) {
+  if (k < 2 || l < 1) return l < 1 ? LRAMM_E_RANK : LRAMM_E_UNSUPPORTED;
+  if (!S || !sign_bits) return LRAMM_E_INVALID;
+  return launch_srht_samples(seed, k, l, S, sign_bits, (hipStream_t)stream);
+}
+
+lramm_status lramm_srht_sketch(int64_t m, int64_t k, int64_t l, const void* A, int64_t lda, int32_t a_type,
+                               const int32_t* S, const uint32_t* sign_bits, float* Y, int64_t ldy, void* stream) {
+  if (m < 0 || k < 2 || l < 1) return m < 0 ? LRAMM_E_SHAPE : (l < 1 ? LRAMM_E_RANK : LRAMM_E_UNSUPPORTED);
+  if (lda < k || ldy < l) return LRAMM_E_SHAPE;
+  if (m > 0 && (!A || !S || !sign_bits || !Y)) return LRAMM_E_INVALID;
+  if (a_type != LRAMM_F32 && a_type != LRAMM_BF16) return LRAMM_E_UNSUPPORTED;
+  return launch_srht(m, k, l, A, lda, a_type, sign_bits, S, Y, ldy, (hipStream_t)stream);
+}
+
+int64_t lramm_srht_padded(int64_t k) { return k < 1 ? 0 : srht_padded(k); }
 
 size_t lramm_cholqr2_workspace(int64_t rows, int64_t l) { return cholqr2_workspace(rows, l); }
 

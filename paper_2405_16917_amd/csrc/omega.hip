@@ -13,27 +13,6 @@
 
 namespace lramm {
 
-__device__ __forceinline__ void philox_round(uint32_t& x0, uint32_t& x1, uint32_t& x2, uint32_t& x3, uint32_t k0,
-                                             uint32_t k1) {
-  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
-  uint32_t hi0 = __umulhi(M0, x0), lo0 = M0 * x0;
-  uint32_t hi1 = __umulhi(M1, x2), lo1 = M1 * x2;
-  uint32_t n0 = hi1 ^ x1 ^ k0, n2 = hi0 ^ x3 ^ k1;
-  x0 = n0;
-  x1 = lo1;
-  x2 = n2;
-  x3 = lo0;
-}
-
-__device__ __forceinline__ void philox4x32_10(uint32_t ctr[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    philox_round(ctr[0], ctr[1], ctr[2], ctr[3], k0, k1);
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-}
-
 // Words (x0, x1), (x2, x3) of one Philox output -> four normals in FP64:
 // u1 = (x0 + 1) 2^-32, u2 = x1 2^-32, r = sqrt(-2 ln u1), t = 2 pi u2,
 // (r cos t, r sin t), and the same for (x2, x3).

@@ -76,7 +76,12 @@ def test_plan_validation(lib):
     assert _create(lib, _desc(L, r=0, p=0))[0] == L.E_RANK            # l < 1
     assert _create(lib, _desc(L, m=0))[0] == L.E_SHAPE
     assert _create(lib, _desc(L, fmt_g2=7))[0] == L.E_UNSUPPORTED
-    assert _create(lib, _desc(L, flags=2))[0] == L.E_INVALID
+    assert _create(lib, _desc(L, flags=4))[0] == L.E_INVALID
+    # the structured sketch: A' row-major and k' <= 32768 only
+    code, h = _create(lib, _desc(L, flags=L.PLAN_SRHT))
+    assert code == L.OK
+    lib.lramm_plan_destroy(h)
+    assert _create(lib, _desc(L, flags=L.PLAN_SRHT, trans_a=1))[0] == L.E_UNSUPPORTED
     assert _create(lib, _desc(L, k=200000))[0] == L.E_OVERFLOW        # K * 127^2 > 2^31
     assert lib.lramm_plan_create(None, None) == L.E_INVALID
 
@@ -137,4 +142,25 @@ def test_one_launch_cholesky_admission(lib):
     assert lib.lramm_chol_one_launch(2000, 256, 0) == 0
     # the plan accepts the exclusive flag and nothing else
     assert _create(lib, _desc(L, flags=L.PLAN_EXCLUSIVE))[0] == L.OK
-    assert _create(lib, _desc(L, flags=2))[0] == L.E_INVALID
+    assert _create(lib, _desc(L, flags=4))[0] == L.E_INVALID
+    # the structured sketch: A' row-major and k' <= 32768 only
+    code, h = _create(lib, _desc(L, flags=L.PLAN_SRHT))
+    assert code == L.OK
+    lib.lramm_plan_destroy(h)
+    assert _create(lib, _desc(L, flags=L.PLAN_SRHT, trans_a=1))[0] == L.E_UNSUPPORTED
+
+
+def test_srht_host_checks(lib):
+    """Sizes of the structured test matrix and the errors its entry points
+    return before any launch."""
+    import paper_2405_16917_amd._lib as L
+    assert [lib.lramm_srht_padded(k) for k in (0, 1, 2, 3, 512, 513, 32768)] == [0, 1, 2, 4, 512, 1024, 32768]
+    dummy = ctypes.c_void_p(16)
+    assert lib.lramm_srht_samples(1, 1, 1, dummy, dummy, None) == L.E_UNSUPPORTED       # k < 2
+    assert lib.lramm_srht_samples(1, 40000, 8, dummy, dummy, None) == L.E_UNSUPPORTED   # k' > 32768
+    assert lib.lramm_srht_samples(1, 100, 0, dummy, dummy, None) == L.E_RANK
+    assert lib.lramm_srht_samples(1, 100, 129, dummy, dummy, None) == L.E_RANK          # l > k'
+    assert lib.lramm_srht_samples(1, 100, 8, None, dummy, None) == L.E_INVALID
+    assert lib.lramm_srht_sketch(4, 100, 8, dummy, 99, L.F32, dummy, dummy, dummy, 8, None) == L.E_SHAPE
+    assert lib.lramm_srht_sketch(4, 100, 8, dummy, 100, L.F32, dummy, dummy, dummy, 7, None) == L.E_SHAPE
+    assert lib.lramm_srht_sketch(4, 100, 8, dummy, 100, L.F64, dummy, dummy, dummy, 8, None) == L.E_UNSUPPORTED

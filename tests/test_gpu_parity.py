@@ -20,6 +20,7 @@ from oracle import lramm as OL  # noqa: E402
 from oracle import philox as OP  # noqa: E402
 from oracle import qgemm as OG  # noqa: E402
 from oracle import quant as OQ  # noqa: E402
+from oracle import srht as OS  # noqa: E402
 from oracle.qr import householder_qr  # noqa: E402
 
 DEV = "cuda"
@@ -348,10 +349,10 @@ def test_cholqr2_f64_input_and_rank_deficiency(lib, l, dead):
 # ------------------------------------------------------------- end to end --
 
 def _run_forward(lib, A, B, r, p, q, fmt, omega=None, seed=0, alpha=1.0, beta=0.0, Cin=None,
-                 a_type=torch.float32, c_type=torch.float32):
+                 a_type=torch.float32, c_type=torch.float32, sketch="gaussian"):
     m, k = A.shape
     n = B.shape[1]
-    plan = lib.LrammPlan(m, n, k, r, p, q, fmt, a_type, a_type, c_type, seed, alpha, beta)
+    plan = lib.LrammPlan(m, n, k, r, p, q, fmt, a_type, a_type, c_type, seed, alpha, beta, sketch=sketch)
     ws = plan.workspace()
     C = g(Cin, c_type) if Cin is not None else None
     Ad, Bd = g(A, a_type), g(B, a_type)
@@ -421,7 +422,7 @@ def _check_codes(name, raw, K, fmt, X_rows, mismatch=0):
 
 
 def check_stages(lib, plan, ws, A, B, C, fmt, q, Ad=None, omega=None, omega_mismatch=0, alpha=1.0, sample=None,
-                 c_bf16=False):
+                 c_bf16=False, srht_seed=None):
     """Every stage of the last forward on its own inputs (binary32 values as
     float64 arrays A, B; C the GPU output): the codes of each quantised
     operand against the oracle quantiser applied to the GPU's own input to
@@ -439,14 +440,19 @@ def check_stages(lib, plan, ws, A, B, C, fmt, q, Ad=None, omega=None, omega_mism
     cols = np.arange(A.shape[1]) if sample is None else sample
     ncols = np.arange(B.shape[1]) if sample is None else sample
     dec = lambda raw, f, K: codes_from(raw, f, K)[0].astype(np.float64)
-    # sketch: A by rows x (Omega or Q_Z) by columns -> Y
-    rawA, dLa, K, _ = _raw(plan, ws, "A_rows", Ad, rows)
-    La = _check_codes("A rows", rawA, K, fs, A[rows])
-    rawS, dRs, _, _ = _raw(plan, ws, "sketch_R")
-    Rs = dec(rawS, fs, K)
-    if q == 0 and omega is not None:
-        _check_codes("Omega", rawS, K, fs, omega.T, omega_mismatch)
-    _check_product("sketch", Y[rows], La, dLa, Rs, dRs, fs)
+    if srht_seed is not None and q == 0:
+        # the structured sketch: bit for bit the binary32 transform
+        ref = OS.srht_sketch(A[rows], srht_seed, l, "fp32")
+        assert np.array_equal(Y[rows], ref), f"srht sketch: {np.sum(Y[rows] != ref)} entries differ"
+    else:
+        # sketch: A by rows x (Omega or Q_Z) by columns -> Y
+        rawA, dLa, K, _ = _raw(plan, ws, "A_rows", Ad, rows)
+        La = _check_codes("A rows", rawA, K, fs, A[rows])
+        rawS, dRs, _, _ = _raw(plan, ws, "sketch_R")
+        Rs = dec(rawS, fs, K)
+        if q == 0 and omega is not None:
+            _check_codes("Omega", rawS, K, fs, omega.T, omega_mismatch)
+        _check_product("sketch", Y[rows], La, dLa, Rs, dRs, fs)
     # orthonormalisation of the GPU's own last sketch
     assert np.max(np.abs(Qg.T @ Qg - np.eye(l))) <= 1e-12
     if sample is None:

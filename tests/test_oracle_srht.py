@@ -96,3 +96,37 @@ def test_srht_range_finder_close_to_gaussian():
     for e in errs.values():
         assert floor <= e <= 30 * floor
     assert errs["srht"] <= 5 * errs["gaussian"]
+
+
+def test_fp32_transform_exact_on_integers():
+    # small integers: every partial sum of the butterflies is exact in binary32
+    rng = np.random.default_rng(4)
+    for k, l in ((7, 5), (100, 16), (1024, 64)):
+        A = rng.integers(-50, 51, size=(9, k)).astype(np.float64)
+        y32 = S.srht_sketch(A, 3, l, "fp32")
+        y64 = S.srht_sketch(A, 3, l, "fp64")
+        # both sides scale by 1/sqrt(l); compare before the (different) scalings
+        sc = np.float32(1.0 / np.sqrt(np.float64(l)))
+        assert np.array_equal(np.rint(y32 / np.float64(sc)), np.rint(y64 * np.sqrt(l)))
+
+
+def test_fp32_transform_twice_is_kprime_times_input():
+    rng = np.random.default_rng(5)
+    X = rng.integers(-100, 101, size=(6, 256)).astype(np.float32)
+    assert np.array_equal(S.fwht_fp32(S.fwht_fp32(X)), 256 * X)
+
+
+def test_fp32_transform_within_rounding_bound():
+    rng = np.random.default_rng(6)
+    worst = 0.0
+    for k, l in ((300, 40), (2048, 100), (5000, 272)):
+        A = rng.standard_normal((12, k))
+        A32 = A.astype(np.float32).astype(np.float64)
+        y32 = S.srht_sketch(A32, 7, l, "fp32")
+        y64 = S.srht_sketch(A32, 7, l, "fp64")
+        p = int(np.log2(S.next_pow2(k)))
+        bound = (p + 3) * 2.0**-24 * np.sum(np.abs(A32), axis=1)[:, None] / np.sqrt(l)
+        err = np.abs(y32 - y64)
+        assert np.all(err <= bound)
+        worst = max(worst, float(np.max(err / bound)))
+    assert worst > 1e-3          # binary32 rounding is really there
