@@ -121,7 +121,7 @@ typedef struct {
   int32_t reserved0;
   uint64_t seed;        /* Philox key when the caller passes no Omega      */
   float alpha, beta;
-  uint32_t flags;       /* LRAMM_PLAN_EXCLUSIVE | LRAMM_PLAN_SRHT          */
+  uint32_t flags;       /* LRAMM_PLAN_EXCLUSIVE | _SRHT | _ESTIMATE        */
   uint32_t reserved1;
   /* Storage of A and B: 0 row-major as m x k (k x n), 1 stored as the
    * transpose, k x m (n x k) row-major.  C is always m x n row-major. */
@@ -150,6 +150,11 @@ typedef struct {
  * trans_b = 1), 2 <= k and k' <= 32768; lramm_forward's omega must be null.
  * Otherwise LRAMM_E_UNSUPPORTED (LRAMM_E_INVALID for a non-null omega). */
 #define LRAMM_PLAN_SRHT 0x2u
+/* desc.flags: the forward also forms ||A'||_F^2 (one more read of the
+ * sketched operand, beside the orthonormalisation) and ||Bt||_F^2 (after
+ * the projection), both in FP64 and deterministic, for
+ * lramm_error_estimate. */
+#define LRAMM_PLAN_ESTIMATE 0x4u
 
 typedef struct lramm_plan lramm_plan;   /* opaque, host memory */
 
@@ -376,6 +381,18 @@ LRAMM_API lramm_status lramm_omega(uint64_t seed, int64_t k, int64_t l, float* O
  * signed row in binary32, the sampled entries multiplied by fl32(1/sqrt(l)).
  * Each entry is within (log2 k' + 3) 2^-24 sum_i |A[r][i]| / sqrt(l) of the
  * exact value.  Same limits on k and l. */
+/* A-posteriori error of the range finder after a forward of a plan created
+ * with LRAMM_PLAN_ESTIMATE (else LRAMM_E_INVALID): with Q orthonormal,
+ * ||A' - Q Q^T A'||_F^2 = ||A'||_F^2 - ||Q^T A'||_F^2 (paper Alg. 1,
+ * B = Q* A; Sec. 3.3 states the rank-r error in the Frobenius norm), A' the
+ * sketched operand.  Synchronises stream, then writes out[0] =
+ * sqrt(max(0, ||A'||^2 - ||Bt||^2) / ||A'||^2) (Bt the projection as
+ * computed, so quantised projection formats make it an estimate), out[1] =
+ * ||A'||_F^2, out[2] = ||Bt||_F^2.  out: 3 doubles, host memory.  It is the
+ * quantity a caller's rank choice can test against a tolerance. */
+LRAMM_API lramm_status lramm_error_estimate(const lramm_plan* plan, const void* ws, void* stream,
+                           double* out);
+
 LRAMM_API int64_t lramm_srht_padded(int64_t k);
 LRAMM_API lramm_status lramm_srht_samples(uint64_t seed, int64_t k, int64_t l, int32_t* S,
                          uint32_t* sign_bits, void* stream);

@@ -45,6 +45,36 @@ def matmul(A, B, r, p=16, q=1, fmt=("int8",) * 4, seed=0, omega=None, alpha=1.0,
     return C
 
 
+def auto_rank(A, B, tol, p=16, q=1, fmt=("int8",) * 4, seed=0, l0=None, growth=1.5, l_max=None,
+              sketch="gaussian", out_dtype=None):
+    """The smallest sketch width on a geometric ladder whose a-posteriori
+    estimate of ||A - Q Q^T A||_F / ||A||_F (lramm_error_estimate) is at
+    most ``tol``.  The ladder starts at ``l0`` (default: the rank rule
+    r = ceil(min(m, k) / 10) plus p) and grows by ``growth``, rounded up to
+    a multiple of 32, up to ``l_max`` (default min(m, k, 1024)).  Returns
+    (C, l, estimate, tried) with tried the (l, estimate) pairs in order; the
+    last rung is returned even when it misses ``tol``."""
+    m, k = A.shape
+    n = B.shape[1]
+    As, ta = storage(A)
+    Bs, tb = storage(B)
+    lim = min(m, k, 1024) if l_max is None else min(l_max, m, k)
+    l = min(l0 if l0 is not None else autotune_rank(m, k) + p, lim)
+    tried = []
+    while True:
+        pp = min(p, l - 1)
+        plan = LrammPlan(m, n, k, l - pp, pp, q, fmt, A.dtype, B.dtype, out_dtype or A.dtype, seed,
+                         trans_a=ta, trans_b=tb, sketch=sketch, estimate=True)
+        ws = plan.workspace(A.device)
+        C = plan.forward(As, Bs, ws)
+        plan.status(ws)
+        est = plan.error_estimate(ws)[0]
+        tried.append((l, est))
+        if est <= tol or l >= lim:
+            return C, l, est, tried
+        l = min(lim, -(-int(l * growth) // 32) * 32)
+
+
 class LRAMMConfig:
     """Settings of LRAMMFunction.  ``side``: "left" sketches A, "right"
     sketches B (a low-rank weight on the right of activations).  ``check``:

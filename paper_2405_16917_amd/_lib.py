@@ -24,6 +24,7 @@ INT8, INT4, FP8, BF16F = 0, 1, 2, 3
 FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_SQRTNEG, FLAG_STALL = 0x1, 0x2, 0x4, 0x8
 PLAN_EXCLUSIVE = 0x1
 PLAN_SRHT = 0x2
+PLAN_ESTIMATE = 0x4
 SKETCHES = {"gaussian": 0, "srht": PLAN_SRHT}
 
 FMT = {"int8": INT8, "int4": INT4, "fp8": FP8, "bf16": BF16F}
@@ -40,7 +41,7 @@ EXPORTS = (
     "lramm_cholqr2_noalloc", "lramm_chol_one_launch", "lramm_codes",
     "lramm_ts_plan_create", "lramm_ts_plan_destroy", "lramm_ts_workspace_bytes", "lramm_ts_forward",
     "lramm_ts_intermediate", "lramm_ts_status_poll", "lramm_srht_padded", "lramm_srht_samples",
-    "lramm_srht_sketch",
+    "lramm_srht_sketch", "lramm_error_estimate",
 )
 NSTAGES = 22
 
@@ -116,6 +117,7 @@ def load(path=LIB_PATH):
         "lramm_gemm_nt_workspace": ([I64, I64, I64, I32], SZ),
         "lramm_omega": ([ctypes.c_uint64, I64, I64, P, I64, P], I32),
         "lramm_srht_padded": ([I64], I64),
+        "lramm_error_estimate": ([P, P, P, ctypes.POINTER(ctypes.c_double)], I32),
         "lramm_srht_samples": ([ctypes.c_uint64, I64, I64, P, P, P], I32),
         "lramm_srht_sketch": ([I64, I64, I64, P, I64, I32, P, P, P, I64, P], I32),
         "lramm_cholqr2": ([I64, I64, P, I64, I32, P, I64, P, SZ, P, P], I32),
@@ -324,14 +326,14 @@ class LrammPlan:
 
     def __init__(self, m, n, k, r, p=16, q=1, fmt=("int8",) * 4, a_type=torch.float32,
                  b_type=torch.float32, c_type=torch.float32, seed=0, alpha=1.0, beta=0.0, exclusive=False,
-                 trans_a=False, trans_b=False, side="left", sketch="gaussian"):
+                 trans_a=False, trans_b=False, side="left", sketch="gaussian", estimate=False):
         lib = load()
         d = Desc()
         d.m, d.n, d.k, d.r, d.p, d.q = m, n, k, r, p, q
         d.fmt_sketch, d.fmt_proj, d.fmt_g1, d.fmt_g2 = (_fmt(f) for f in fmt)
         d.a_type, d.b_type, d.c_type = DTYPE[a_type], DTYPE[b_type], DTYPE[c_type]
         d.seed, d.alpha, d.beta = seed, alpha, beta
-        d.flags = (PLAN_EXCLUSIVE if exclusive else 0) | SKETCHES[sketch]
+        d.flags = (PLAN_EXCLUSIVE if exclusive else 0) | SKETCHES[sketch] | (PLAN_ESTIMATE if estimate else 0)
         d.trans_a, d.trans_b, d.side = int(bool(trans_a)), int(bool(trans_b)), SIDES[side]
         self.desc = d
         self.c_type = c_type
@@ -366,6 +368,13 @@ class LrammPlan:
                                     _ptr(omega), 0 if omega is None else omega.stride(0), _ptr(ws),
                                     ws.numel(), _stream()), "lramm_forward")
         return C
+
+    def error_estimate(self, ws):
+        """(rel. Frobenius error estimate of the rank-l range, ||A'||_F^2,
+        ||Bt||_F^2) after a forward of a plan made with estimate=True."""
+        out = (ctypes.c_double * 3)()
+        _check(load().lramm_error_estimate(self._h, _ptr(ws), _stream(), out), "lramm_error_estimate")
+        return float(out[0]), float(out[1]), float(out[2])
 
     def factors(self, ws):
         """Views of (Q [m x l FP64], Bt [l x k FP32]) inside ws."""

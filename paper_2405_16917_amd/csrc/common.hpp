@@ -224,6 +224,15 @@ lramm_status launch_quantize(int64_t rows, int64_t cols, const void* X, int64_t 
                              hipStream_t s, uint32_t* amax_ws = nullptr, bool amax_ready = false,
                              uint32_t* zero = nullptr, int64_t zero_words = 0);
 
+// Row codes (rows x rpitch, row scales) and transposed column codes (cols x
+// cpitch, column scales) of X in one format from two reads of X (FP32 or
+// BF16): the row and column maxima (into caller-zeroed rmax / cmax words;
+// skipped for bf16), then both code matrices.  Bit-identical to the two
+// separate quantisations.
+lramm_status launch_quantize_both(int64_t rows, int64_t cols, const void* X, int64_t ldx, int xtype, int fmt,
+                                  void* Rq, int64_t rpitch, float* rscales, void* Cq, int64_t cpitch,
+                                  float* cscales, uint32_t* rmax, uint32_t* cmax, uint32_t* flags, hipStream_t s);
+
 lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void* Lq, int64_t ldl,
                             const float* dL, const void* Rq, int64_t ldr, const float* dR, float alpha,
                             float beta, void* C, int64_t ldc, int ctype, int32_t* acc_out, int64_t ld_acc,
@@ -248,6 +257,13 @@ lramm_status launch_srht_samples(uint64_t seed, int64_t k, int64_t l, int32_t* S
                                  hipStream_t s);
 lramm_status launch_srht(int64_t m, int64_t k, int64_t l, const void* A, int64_t lda, int a_type,
                          const uint32_t* sign_bits, const int32_t* S, float* Y, int64_t ldy, hipStream_t s);
+
+// Squared Frobenius norm of a rows x cols matrix (FP32 or BF16, ldx) into
+// *out (FP64, device), deterministic: partial sums per band of rows in part
+// (sumsq_parts_max() doubles), then summed in index order.
+lramm_status launch_sumsq(int64_t rows, int64_t cols, const void* X, int64_t ldx, int xtype, double* part,
+                          double* out, hipStream_t s);
+int sumsq_parts_max();
 
 // Optional measurement hook: event pairs around individual launches.
 struct TimingHook {

@@ -13,6 +13,7 @@
 //   Bt   = quant_cols(Q)[fmt_proj] . A_c^T          (Q^T A, l x k)
 //   T^T  = B_c . quant_rows(Bt)[fmt_g1]^T           (n x l)
 //   C    = alpha quant_rows(Q)[fmt_g2] . quant_rows(T^T)[fmt_g2]^T + beta C
+#include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -44,10 +45,12 @@ struct lramm_plan {
   size_t off_W, off_Bte, off_V;
   bool srht = false;        // structured first sketch (LRAMM_PLAN_SRHT)
   size_t off_srS = 0, off_srD = 0;
+  bool estimate = false;    // a-posteriori error estimate (LRAMM_PLAN_ESTIMATE)
+  size_t off_norms = 0;     // ||A'||^2, ||Bt||^2, then the two partial arrays
   // zero-filled at the start of every forward: the status word, then the
   // column-maxima buffers of every column quantisation of the pass
   size_t off_zero, zero_words;
-  size_t mx_A, mx_B, mx_Om, mx_Q, mx_QZ;   // word offsets inside the zero region
+  size_t mx_A, mx_B, mx_Om, mx_Q, mx_QZ, mx_Ar;   // word offsets inside the zero region
   size_t total;
   int64_t pAr, pAc, pBc, pOm, pQZc, pQc, pQr, pBtq, pTtq;
   // A's row codes of the last forward: the workspace copy, or A itself when
@@ -235,7 +238,7 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   if (!valid_fmt(d.fmt_sketch) || !valid_fmt(d.fmt_proj) || !valid_fmt(d.fmt_g1) || !valid_fmt(d.fmt_g2))
     return LRAMM_E_UNSUPPORTED;
   if (!valid_io(d.a_type) || !valid_io(d.b_type) || !valid_io(d.c_type)) return LRAMM_E_UNSUPPORTED;
-  if (d.flags & ~(uint32_t)(LRAMM_PLAN_EXCLUSIVE | LRAMM_PLAN_SRHT)) return LRAMM_E_INVALID;
+  if (d.flags & ~(uint32_t)(LRAMM_PLAN_EXCLUSIVE | LRAMM_PLAN_SRHT | LRAMM_PLAN_ESTIMATE)) return LRAMM_E_INVALID;
   if (d.flags & LRAMM_PLAN_SRHT) {
     // the transform runs along rows of A' stored row-major, k' <= 32768
     const int at0 = desc->side ? 1 - desc->trans_b : desc->trans_a;
@@ -260,6 +263,7 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   p->ct = desc->side;
   p->chain_mode = (d.flags & LRAMM_PLAN_EXCLUSIVE) ? CHAIN_EXCLUSIVE : CHAIN_SHARED;
   p->srht = (d.flags & LRAMM_PLAN_SRHT) != 0;
+  p->estimate = (d.flags & LRAMM_PLAN_ESTIMATE) != 0;
   p->l = l;
   p->lp = lp;
   const int64_t m = d.m, n = d.n, k = d.k;
@@ -286,6 +290,7 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
     p->mx_Om = seg((size_t)l);
     p->mx_Q = seg((size_t)lp * (d.q + 1));
     p->mx_QZ = seg((size_t)lp * (d.q > 0 ? d.q : 1));
+    p->mx_Ar = seg((size_t)m);
     p->zero_words = w;
     p->off_zero = carve(&c, w * 4);
     p->off_flags = p->off_zero;
@@ -299,6 +304,7 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   p->off_OmT = carve(&c, (size_t)l * k * 4);
   p->off_Om = carve(&c, (size_t)l * p->pOm);
   p->off_sOm = carve(&c, (size_t)l * 4);
+  if (p->estimate) p->off_norms = carve(&c, (size_t)(2 + 2 * sumsq_parts_max()) * 8);
   if (p->srht) {
     p->off_srS = carve(&c, (size_t)l * 4);
     p->off_srD = carve(&c, (size_t)(srht_padded(k) + 31) / 32 * 4);
@@ -503,8 +509,14 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   // tiles, 16-byte aligned), no pass over A
   const bool a_direct = d.fmt_sketch == LRAMM_BF16F && d.a_type == LRAMM_BF16 && !P->at && k % 64 == 0 &&
                         (lda * 2) % 16 == 0 && (uintptr_t)A % 16 == 0;
+  // A's row codes (sketch format) and column codes (projection format) in
+  // one format: both from two reads of A, before the sketch
+  const bool fused_a = !(P->srht && d.q == 0) && !a_direct && !P->at && d.fmt_sketch == d.fmt_proj;
   if (P->srht && d.q == 0) {
     Ar = nullptr;   // the structured sketch reads A itself; no sketch-format codes
+  } else if (fused_a) {
+    TIMED(ST_QUANT_A_ROWS, launch_quantize_both(m, k, A, lda, d.a_type, d.fmt_sketch, Ar, P->pAr, sAr, Ac, P->pAc,
+                                                sAc, zero + P->mx_Ar, mxA, flags, s));
   } else if (a_direct) {
     Ar = reinterpret_cast<uint8_t*>(const_cast<void*>(A));
   } else if (!P->at) {
@@ -531,7 +543,9 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
     LRAMM_HIP(hipEventRecord(P->ev_sketch, s));
     LRAMM_HIP(hipStreamWaitEvent(P->side, P->ev_sketch, 0));
   }
-  if (!P->at)
+  if (fused_a) {
+    // written with the row codes
+  } else if (!P->at)
     TIMED_ON(s2, ST_QUANT_A_COLS,
              launch_quantize(m, k, A, lda, d.a_type, d.fmt_proj, 1, Ac, P->pAc, sAc, flags, s2, mxA));
   else   // the columns of A' are the stored rows
@@ -541,6 +555,12 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
     TIMED_ON(s2, ST_QUANT_B, launch_quantize(k, n, B, ldb, d.b_type, d.fmt_g1, 1, Bc, P->pBc, sBc, flags, s2, mxB));
   } else {
     TIMED_ON(s2, ST_QUANT_B, launch_quantize(n, k, B, ldb, d.b_type, d.fmt_g1, 0, Bc, P->pBc, sBc, flags, s2));
+  }
+  double* norms = P->estimate ? at<double>(W, P->off_norms) : nullptr;
+  if (norms) {
+    // ||A'||_F^2 of the stored matrix (any layout), beside the orthonormalisation
+    if (!P->at) LRAMM_TRY(launch_sumsq(m, k, A, lda, d.a_type, norms + 2, norms, s2));
+    else LRAMM_TRY(launch_sumsq(k, m, A, lda, d.a_type, norms + 2, norms, s2));
   }
   if (P->side) LRAMM_HIP(hipEventRecord(P->ev_join, P->side));
   TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(0),
@@ -573,6 +593,8 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
         launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s, mxQ(d.q), true));
   TIMED(ST_PROJ, launch_gemm_nt(l, k, m, d.fmt_proj, Qc, P->pQc, sQc, Ac, P->pAc, sAc, 1.0f, 0.0f, Bt, k, LRAMM_F32,
                                 nullptr, 0, split, sb, s));
+  if (norms)   // ||Bt||_F^2 = ||Q^T A'||_F^2 (up to the projection's quantisation)
+    LRAMM_TRY(launch_sumsq(l, k, Bt, k, LRAMM_F32, norms + 2 + sumsq_parts_max(), norms + 1, s));
   if (range_only) return LRAMM_OK;
   // G1: T^T = B_c . Bt_q^T  (n x l)
   uint8_t* Btq = at<uint8_t>(W, P->off_Btq);
@@ -956,6 +978,22 @@ lramm_status lramm_omega(uint64_t seed, int64_t k, int64_t l, float* OmegaT, int
   if (!OmegaT) return LRAMM_E_INVALID;
   if (ldo < k) return LRAMM_E_SHAPE;
   return launch_omega(seed, k, l, l, OmegaT, ldo, (hipStream_t)stream);
+}
+
+lramm_status lramm_error_estimate(const lramm_plan* P, const void* ws, void* stream, double* out) {
+  if (!P || !ws || !out) return LRAMM_E_INVALID;
+  if (!P->estimate) return LRAMM_E_INVALID;
+  const uint8_t* base = reinterpret_cast<const uint8_t*>(round_up((int64_t)(uintptr_t)ws, 256));
+  double h[2] = {0.0, 0.0};
+  hipStream_t s = (hipStream_t)stream;
+  LRAMM_HIP(hipMemcpyAsync(h, base + P->off_norms, sizeof(h), hipMemcpyDeviceToHost, s));
+  LRAMM_HIP(hipStreamSynchronize(s));
+  const double a2 = h[0], b2 = h[1];
+  const double gap = a2 - b2 > 0.0 ? a2 - b2 : 0.0;
+  out[0] = a2 > 0.0 ? sqrt(gap / a2) : 0.0;
+  out[1] = a2;
+  out[2] = b2;
+  return LRAMM_OK;
 }
 
 lramm_status lramm_srht_samples(uint64_t seed, int64_t k, int64_t l, int32_t* S, uint32_t* sign_bits,

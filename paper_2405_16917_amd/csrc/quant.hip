@@ -127,10 +127,13 @@ __global__ __launch_bounds__(256) void quant_rows_kernel(int64_t rows, int64_t c
 // The band's maxima meet in LDS and go out with one atomicMax per column.
 constexpr int kColmaxRows = 128;   // rows per column-max workgroup
 
+// With rmax_bits, the maxima of the rows' 256-column pieces go to the rows'
+// words by atomicMax as well (both maxima from one read of X).
 template <typename T>
 __global__ __launch_bounds__(256) void colmax_kernel(int64_t rows, int64_t cols, const T* __restrict__ X,
                                                      int64_t ldx, uint32_t* __restrict__ amax_bits,
-                                                     int64_t rows_per_block, int vec) {
+                                                     int64_t rows_per_block, int vec,
+                                                     uint32_t* __restrict__ rmax_bits = nullptr) {
   __shared__ unsigned sm[4][256];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t cb = (int64_t)blockIdx.x * 256;
@@ -139,6 +142,12 @@ __global__ __launch_bounds__(256) void colmax_kernel(int64_t rows, int64_t cols,
   const int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
   unsigned m[4] = {0u, 0u, 0u, 0u};
   int64_t r = r0 + w;
+  auto row_max = [&](int64_t row, const float v[4]) {
+    if (!rmax_bits) return;
+    unsigned x = max(max(abs_bits(v[0]), abs_bits(v[1])), max(abs_bits(v[2]), abs_bits(v[3])));
+    x = wave_max_u32(x);
+    if (lane == 0 && x) atomicMax(rmax_bits + row, x);
+  };
   if (vec && cb + 256 <= cols) {
     for (; r + 28 < r1; r += 32) {
       float v[8][4];
@@ -148,6 +157,8 @@ __global__ __launch_bounds__(256) void colmax_kernel(int64_t rows, int64_t cols,
       for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) m[j] = max(m[j], abs_bits(v[i][j]));
+#pragma unroll
+      for (int i = 0; i < 8; ++i) row_max(r + 4 * i, v[i]);
     }
   }
   for (; r < r1; r += 4) {
@@ -156,6 +167,7 @@ __global__ __launch_bounds__(256) void colmax_kernel(int64_t rows, int64_t cols,
     load4<T>(X + r * ldx, c0, cols, vec != 0, v, live);   // zero past cols
 #pragma unroll
     for (int j = 0; j < 4; ++j) m[j] = max(m[j], abs_bits(v[j]));
+    row_max(r, v);
   }
 #pragma unroll
   for (int j = 0; j < 4; ++j) sm[w][4 * lane + j] = m[j];
@@ -166,12 +178,19 @@ __global__ __launch_bounds__(256) void colmax_kernel(int64_t rows, int64_t cols,
 }
 
 // Quantise a 64 (K) x 64 (cols) tile and write it transposed.
+// With Rq, the tile's row codes (row scales from rmax_bits) are written
+// too, untransposed: one read of X gives both code matrices.  Rows of Rq
+// hold rpitch bytes; tiles past cols (grid.x may extend over the row
+// padding) write zero row codes and no column codes.
 template <typename T, int FMT>
 __global__ __launch_bounds__(256) void quant_cols_t_kernel(int64_t rows, int64_t cols, const T* __restrict__ X,
                                                            int64_t ldx, const uint32_t* __restrict__ amax_bits,
                                                            uint8_t* __restrict__ Xq, int64_t pitch,
                                                            float* __restrict__ scales_out, uint32_t* flags,
-                                                           int vec) {
+                                                           int vec, uint8_t* __restrict__ Rq = nullptr,
+                                                           int64_t rpitch = 0,
+                                                           const uint32_t* __restrict__ rmax_bits = nullptr,
+                                                           float* __restrict__ rscales = nullptr) {
   // codes of the tile, transposed: sT[col][k]; 2 bytes per code for bf16
   __shared__ uint16_t sT[64][66];
   const int t = threadIdx.x;
@@ -186,6 +205,15 @@ __global__ __launch_bounds__(256) void quant_cols_t_kernel(int64_t rows, int64_t
     } else {
       const uint32_t mb = amax_bits[col0 + t];
       scales_out[col0 + t] = qparams(__uint_as_float(mb), qmax).d;
+      if (mb >= 0x7f800000u && flags) atomicOr(flags, LRAMM_FLAG_NONFINITE);
+    }
+  }
+  if (Rq && blockIdx.x == 0 && t < 64 && k0 + t < rows) {
+    if constexpr (FMT == LRAMM_BF16F) {
+      rscales[k0 + t] = 1.0f;
+    } else {
+      const uint32_t mb = rmax_bits[k0 + t];
+      rscales[k0 + t] = qparams(__uint_as_float(mb), qmax).d;
       if (mb >= 0x7f800000u && flags) atomicOr(flags, LRAMM_FLAG_NONFINITE);
     }
   }
@@ -211,7 +239,7 @@ __global__ __launch_bounds__(256) void quant_cols_t_kernel(int64_t rows, int64_t
     for (int i = 0; i < 4; ++i) {
       const int64_t r = k0 + sub + 16 * i;
       bool live[4];
-      if (r < rows) {
+      if (r < rows && c4 < cols) {
         load4<T>(X + r * ldx, c4, cols, vec != 0, v[i], live);
       } else {
 #pragma unroll
@@ -219,6 +247,21 @@ __global__ __launch_bounds__(256) void quant_cols_t_kernel(int64_t rows, int64_t
       }
     }
   }
+  if (Rq) {
+    // row codes of rows k0 + sub + 16 i, columns c4 .. c4 + 3 (zero past cols)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = k0 + sub + 16 * i;
+      if (r >= rows) continue;
+      float rl = 1.0f;
+      if constexpr (FMT != LRAMM_BF16F) rl = qparams(__uint_as_float(rmax_bits[r]), qmax).lam;
+      bool live[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) live[j] = c4 + j < cols && (FMT == LRAMM_BF16F || rl != 0.0f);
+      encode4<FMT>(Rq + r * rpitch, c4, v[i], live, rl);
+    }
+  }
+  if (col0 >= cols) return;   // a tile of row padding only
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -411,6 +454,44 @@ static lramm_status quantize_typed(int64_t rows, int64_t cols, const T* X, int64
   return LRAMM_OK;
 }
 
+// Both code matrices of X from two reads: the row and column maxima
+// (skipped for bf16), then the row codes (rows x rpitch) and the transposed
+// column codes (cols x cpitch).  rmax / cmax: caller-zeroed rows / cols words.
+template <typename T, int FMT>
+static lramm_status quantize_both_typed(int64_t rows, int64_t cols, const T* X, int64_t ldx, uint8_t* Rq,
+                                        int64_t rpitch, float* rscales, uint8_t* Cq, int64_t cpitch,
+                                        float* cscales, uint32_t* rmax, uint32_t* cmax, uint32_t* flags,
+                                        hipStream_t s) {
+  if (rows == 0 || cols == 0) return LRAMM_OK;
+  const int cvec = ((uintptr_t)X % (4 * sizeof(T)) == 0) && (ldx % 4 == 0) ? 1 : 0;
+  if (FMT != LRAMM_BF16F) {
+    dim3 g1((unsigned)ceil_div(cols, 256), (unsigned)ceil_div(rows, (int64_t)kColmaxRows));
+    hipLaunchKernelGGL((colmax_kernel<T>), g1, dim3(256), 0, s, rows, cols, X, ldx, cmax, (int64_t)kColmaxRows,
+                       cvec, rmax);
+    LRAMM_HIP(hipGetLastError());
+  }
+  const int64_t pe_c = pitch_elems(cpitch, FMT), pe_r = pitch_elems(rpitch, FMT);
+  const int64_t tx = ceil_div(pe_r > cols ? pe_r : cols, (int64_t)64);
+  dim3 g2((unsigned)tx, (unsigned)(pe_c / 64));
+  hipLaunchKernelGGL((quant_cols_t_kernel<T, FMT>), g2, dim3(256), 0, s, rows, cols, X, ldx, cmax, Cq, cpitch,
+                     cscales, flags, cvec, Rq, rpitch, rmax, rscales);
+  LRAMM_HIP(hipGetLastError());
+  return LRAMM_OK;
+}
+
+template <typename T>
+static lramm_status quantize_both_fmt(int64_t rows, int64_t cols, const T* X, int64_t ldx, int fmt, uint8_t* Rq,
+                                      int64_t rpitch, float* rscales, uint8_t* Cq, int64_t cpitch, float* cscales,
+                                      uint32_t* rmax, uint32_t* cmax, uint32_t* flags, hipStream_t s) {
+  switch (fmt) {
+    case LRAMM_INT8: return quantize_both_typed<T, LRAMM_INT8>(rows, cols, X, ldx, Rq, rpitch, rscales, Cq, cpitch, cscales, rmax, cmax, flags, s);
+    case LRAMM_INT4: return quantize_both_typed<T, LRAMM_INT4>(rows, cols, X, ldx, Rq, rpitch, rscales, Cq, cpitch, cscales, rmax, cmax, flags, s);
+    case LRAMM_FP8: return quantize_both_typed<T, LRAMM_FP8>(rows, cols, X, ldx, Rq, rpitch, rscales, Cq, cpitch, cscales, rmax, cmax, flags, s);
+    case LRAMM_BF16F: return quantize_both_typed<T, LRAMM_BF16F>(rows, cols, X, ldx, Rq, rpitch, rscales, Cq, cpitch, cscales, rmax, cmax, flags, s);
+    default: return LRAMM_E_INVALID;
+  }
+}
+
 template <typename T>
 static lramm_status quantize_fmt(int64_t rows, int64_t cols, const T* X, int64_t ldx, int fmt, int transpose,
                                  uint8_t* Xq, int64_t pitch, float* scales, uint32_t* flags, hipStream_t s,
@@ -436,6 +517,25 @@ lramm_status launch_quantize(int64_t rows, int64_t cols, const void* X, int64_t 
       return quantize_fmt<uint16_t>(rows, cols, (const uint16_t*)X, ldx, fmt, transpose, q, pitch, scales, flags, s, amax_ws, amax_ready, zero, zero_words);
     case LRAMM_F64:
       return quantize_fmt<double>(rows, cols, (const double*)X, ldx, fmt, transpose, q, pitch, scales, flags, s, amax_ws, amax_ready, zero, zero_words);
+    default:
+      return LRAMM_E_INVALID;
+  }
+}
+
+}  // namespace lramm
+
+namespace lramm {
+
+lramm_status launch_quantize_both(int64_t rows, int64_t cols, const void* X, int64_t ldx, int xtype, int fmt,
+                                  void* Rq, int64_t rpitch, float* rscales, void* Cq, int64_t cpitch,
+                                  float* cscales, uint32_t* rmax, uint32_t* cmax, uint32_t* flags, hipStream_t s) {
+  uint8_t* rq = reinterpret_cast<uint8_t*>(Rq);
+  uint8_t* cq = reinterpret_cast<uint8_t*>(Cq);
+  switch (xtype) {
+    case LRAMM_F32:
+      return quantize_both_fmt<float>(rows, cols, (const float*)X, ldx, fmt, rq, rpitch, rscales, cq, cpitch, cscales, rmax, cmax, flags, s);
+    case LRAMM_BF16:
+      return quantize_both_fmt<uint16_t>(rows, cols, (const uint16_t*)X, ldx, fmt, rq, rpitch, rscales, cq, cpitch, cscales, rmax, cmax, flags, s);
     default:
       return LRAMM_E_INVALID;
   }

@@ -76,7 +76,15 @@ def test_plan_validation(lib):
     assert _create(lib, _desc(L, r=0, p=0))[0] == L.E_RANK            # l < 1
     assert _create(lib, _desc(L, m=0))[0] == L.E_SHAPE
     assert _create(lib, _desc(L, fmt_g2=7))[0] == L.E_UNSUPPORTED
-    assert _create(lib, _desc(L, flags=4))[0] == L.E_INVALID
+    assert _create(lib, _desc(L, flags=8))[0] == L.E_INVALID
+    # the error estimate: only for plans that form the norms
+    code, h = _create(lib, _desc(L))
+    out = (ctypes.c_double * 3)()
+    assert lib.lramm_error_estimate(h, ctypes.c_void_p(256), None, out) == L.E_INVALID
+    lib.lramm_plan_destroy(h)
+    code, h = _create(lib, _desc(L, flags=L.PLAN_ESTIMATE | L.PLAN_SRHT))
+    assert code == L.OK
+    lib.lramm_plan_destroy(h)
     # the structured sketch: A' row-major and k' <= 32768 only
     code, h = _create(lib, _desc(L, flags=L.PLAN_SRHT))
     assert code == L.OK
@@ -142,7 +150,15 @@ def test_one_launch_cholesky_admission(lib):
     assert lib.lramm_chol_one_launch(2000, 256, 0) == 0
     # the plan accepts the exclusive flag and nothing else
     assert _create(lib, _desc(L, flags=L.PLAN_EXCLUSIVE))[0] == L.OK
-    assert _create(lib, _desc(L, flags=4))[0] == L.E_INVALID
+    assert _create(lib, _desc(L, flags=8))[0] == L.E_INVALID
+    # the error estimate: only for plans that form the norms
+    code, h = _create(lib, _desc(L))
+    out = (ctypes.c_double * 3)()
+    assert lib.lramm_error_estimate(h, ctypes.c_void_p(256), None, out) == L.E_INVALID
+    lib.lramm_plan_destroy(h)
+    code, h = _create(lib, _desc(L, flags=L.PLAN_ESTIMATE | L.PLAN_SRHT))
+    assert code == L.OK
+    lib.lramm_plan_destroy(h)
     # the structured sketch: A' row-major and k' <= 32768 only
     code, h = _create(lib, _desc(L, flags=L.PLAN_SRHT))
     assert code == L.OK
