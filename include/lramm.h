@@ -428,8 +428,11 @@ LRAMM_API int32_t lramm_chol_one_launch(int64_t l, int32_t compute_units, uint32
  * library, one per GPU, held until the process ends and looked up by
  * lramm_init() (or by the first call on a device).  It runs on the current
  * device; stream must belong to it.
- *   - Returns LRAMM_E_SCRATCH when lramm_cholqr2_workspace(rows, l) exceeds
- *     LRAMM_NOALLOC_SCRATCH_BYTES (every l <= 768 fits at any row count).
+ *   - Returns LRAMM_E_SCRATCH when even the least CholeskyQR2 workspace
+ *     (the Gram summed in one row chunk, about 5 l'^2 doubles) exceeds
+ *     LRAMM_NOALLOC_SCRATCH_BYTES (every l <= 768 fits at any row count);
+ *     below lramm_cholqr2_workspace(rows, l) it sums the Gram in fewer
+ *     chunks (same results up to the order of the chunk sums).
  *   - Calls no hipMalloc / hipFree or other allocating routine.
  *   - All calls on one GPU share its buffer: calls that overlap in time on
  *     that GPU (several streams, several host threads) race and give wrong

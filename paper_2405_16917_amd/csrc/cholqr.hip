@@ -196,6 +196,102 @@ __global__ __launch_bounds__(256) void gram_kernel(int64_t rows, int lw, int nco
   }
 }
 
+// The same partial Gram with 64 x 64 tiles: workgroup (tile (A, B) of the
+// 64-column blocks, A >= B; row chunk), wavefront (wi, wj) computes the
+// 32 x 32 tile (2A + wi, 2B + wj) over the whole chunk (none above the
+// diagonal or past the last 32-block), so each workgroup reads its two
+// 64-column bands once for four tiles instead of two 32-column bands for
+// one.  Written to the same partial layout as gram_kernel.
+template <typename T>
+__global__ __launch_bounds__(256) void gram64_kernel(int64_t rows, int lw, int ncols, const T* __restrict__ X,
+                                                     int64_t ldx, double* __restrict__ part, int64_t rows_per_chunk) {
+  int A64, B64;
+  lower_tile(blockIdx.x, A64, B64);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ta = 2 * A64 + (wave >> 1), tb = 2 * B64 + (wave & 1);
+  const int Tn = lw / NB;
+  if (ta >= Tn || tb >= Tn || ta < tb) return;   // no barrier below: idle wavefronts leave
+  const int64_t w0 = (int64_t)blockIdx.y * rows_per_chunk;
+  const int64_t w1 = w0 + rows_per_chunk < rows ? w0 + rows_per_chunk : rows;
+  int ca[2], cb[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    ca[s] = ta * NB + 16 * s + li;
+    cb[s] = tb * NB + 16 * s + li;
+    ca[s] = ca[s] < ncols ? ca[s] : 0;
+    cb[s] = cb[s] < ncols ? cb[s] : 0;
+  }
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+  auto mma = [&](const double (*a)[2], const double (*b)[2]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int si = 0; si < 2; ++si)
+#pragma unroll
+        for (int sj = 0; sj < 2; ++sj) acc[si][sj] = mfma_f64(a[q][si], b[q][sj], acc[si][sj]);
+  };
+  const int64_t nfull = w1 > w0 ? (w1 - w0) / 32 : 0;
+  auto fetch = [&](int64_t g, double (*a)[2], double (*b)[2]) {
+    const int64_t r = w0 + 32 * (g < nfull ? g : 0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const T* xr = X + (r + 4 * q + lk) * ldx;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        a[q][s] = (double)xr[ca[s]];
+        b[q][s] = (double)xr[cb[s]];
+      }
+    }
+  };
+  if (nfull > 0) {
+    double a0[8][2], b0[8][2], a1[8][2], b1[8][2], a2[8][2], b2[8][2];
+    fetch(0, a0, b0);
+    fetch(1, a1, b1);
+    for (int64_t g = 0; g < nfull; g += 3) {
+      fetch(g + 2, a2, b2);
+      mma(a0, b0);
+      if (g + 1 >= nfull) break;
+      fetch(g + 3, a0, b0);
+      mma(a1, b1);
+      if (g + 2 >= nfull) break;
+      fetch(g + 4, a1, b1);
+      mma(a2, b2);
+    }
+  }
+  const int64_t rt = w0 + 32 * nfull;
+  if (rt < w1) {
+    double av[8][2], bv[8][2];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t rr = rt + 4 * q + lk;
+      const bool ok = rr < w1;
+      const T* xr = X + (ok ? rr : w0) * ldx;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        av[q][s] = keep_if(ok, (double)xr[ca[s]]);
+        bv[q][s] = keep_if(ok, (double)xr[cb[s]]);
+      }
+    }
+    mma(av, bv);
+  }
+  double* out = part + (int64_t)blockIdx.y * lw * lw + (int64_t)ta * NB * lw + tb * NB;
+#pragma unroll
+  for (int si = 0; si < 2; ++si)
+#pragma unroll
+    for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * si + 4 * r + lk, j = 16 * sj + li;
+        const bool in = ta * NB + i < ncols && tb * NB + j < ncols;
+        out[(int64_t)i * lw + j] = in ? acc[si][sj][r] : 0.0;
+      }
+}
+
 // Second-pass gate bits (one word per orthonormalisation).
 constexpr uint32_t kGateFull = 1u;    // |E| too large for the expansion: full Cholesky of G2
 constexpr uint32_t kGatePass2 = 2u;   // the first pass is not yet orthonormal to the second pass's accuracy
@@ -278,7 +374,10 @@ __host__ __device__ constexpr size_t ts_solve_last_lds(int lw) {
 constexpr int TS_WST = 32 * 18;
 constexpr size_t ts_stage_lds() { return (size_t)TS_WAVES * TS_WST * sizeof(double); }
 
-template <typename T, bool ADD, bool STAGED>
+// RB: 16-row halves per workgroup (1 or 2).  With two, each wavefront feeds
+// the same W fragments to both halves (W is read once per 32 rows, and four
+// accumulators are in flight); the last-block solve needs RB = 1.
+template <typename T, bool ADD, bool STAGED, int RB = 1>
 __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int lw, int ncols, const T* X,
                                                               int64_t ldx, const double* __restrict__ W, double* Q,
                                                               int64_t ldq, int zero_to, int vec,
@@ -286,16 +385,17 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
                                                               const uint32_t* __restrict__ gate,
                                                               const double* __restrict__ Ltri,
                                                               const double* __restrict__ Dlast) {
-  extern __shared__ double sA[];   // TS_ROWS x ts_pitch(lw) [+ the last-block solve's buffers]
+  extern __shared__ double sA[];   // ROWS x ts_pitch(lw) [+ the last-block solve's buffers]
+  constexpr int ROWS = TS_ROWS * RB;
   if (ADD && gate && !(*gate & kGatePass2)) return;   // second pass skipped: Q already holds Q1
   if (colmax) colmax += (blockIdx.x % kCmSlices) * cm_stride;   // this workgroup's copy (cm_stride 0: one copy)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int pitch = ts_pitch(lw);
-  const int64_t r0 = (int64_t)blockIdx.x * TS_ROWS;
+  const int64_t r0 = (int64_t)blockIdx.x * ROWS;
   // stage the row panel: 4 consecutive columns per thread
   const int q4 = lw / 4;
-  for (int e = tid; e < TS_ROWS * q4; e += TS_WAVES * 64) {
+  for (int e = tid; e < ROWS * q4; e += TS_WAVES * 64) {
     const int rr = e / q4, c = (e % q4) * 4;
     const int64_t gr = r0 + rr;
     const bool rok = gr < rows;
@@ -314,7 +414,7 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
   const int Tb = lw / NB;
   // last-block solve: block Tb - 1 of Q1 from the other blocks (below), so
   // row block Tb - 1 of W = L^-1 is never needed
-  const bool solve_last = !ADD && Ltri != nullptr;
+  const bool solve_last = RB == 1 && !ADD && Ltri != nullptr;
   double* sQ = sA + TS_ROWS * pitch;              // the other blocks' results, same layout as sA
   int load[TS_WAVES];
 #pragma unroll
@@ -333,13 +433,14 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
     const double* w0p = W + (int64_t)(cb0 + li) * lw + 4 * lk;
     const double* w1p = W + (int64_t)(cb0 + 16 + li) * lw + 4 * lk;
     const double* ap = sA + li * pitch + 4 * lk;
-    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+    const double* ap2 = ap + TS_ROWS * pitch;     // rows 16 .. 31 (RB = 2)
+    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
     if constexpr (STAGED) {
       // 8 rows of 16 k (128 bytes each) per load instruction; a kstep's 32 x 16
       // tile goes through the wavefront's LDS tile into the MFMA layout.  The
       // next group of four ksteps is loaded while this one is multiplied
       // (past the last kstep the loads repeat it, unused).
-      double* wst = sA + (solve_last ? 2 * TS_ROWS * pitch + (TS_WAVES + 1) * TS_ROWS * NB : TS_ROWS * pitch) +
+      double* wst = sA + (solve_last ? 2 * TS_ROWS * pitch + (TS_WAVES + 1) * TS_ROWS * NB : ROWS * pitch) +
                     wave * TS_WST;
       typedef unsigned int v4u __attribute__((ext_vector_type(4)));
       const int lr = lane >> 3, lj = lane & 7;
@@ -371,13 +472,21 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
             const double2 y1 = *reinterpret_cast<const double2*>(wst + (16 + li) * 18 + 4 * lk + 2);
             b0[0] = x0.x, b0[1] = x0.y, b0[2] = x1.x, b0[3] = x1.y;
             b1[0] = y0.x, b1[1] = y0.y, b1[2] = y1.x, b1[3] = y1.y;
-            double a[4];
+            double a[4], a2[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) a[q] = ap[16 * ks + q];
+            if constexpr (RB == 2) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) a2[q] = ap2[16 * ks + q];
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               acc0 = mfma_f64(a[q], b0[q], acc0);
               acc1 = mfma_f64(a[q], b1[q], acc1);
+              if constexpr (RB == 2) {
+                acc2 = mfma_f64(a2[q], b0[q], acc2);
+                acc3 = mfma_f64(a2[q], b1[q], acc3);
+              }
             }
           }
         }
@@ -406,13 +515,21 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
       for (int st = 0; st < 4; ++st) {
         const int ks = 4 * g + st;
         if (ks < ksteps) {
-          double a[4];
+          double a[4], a2[4];
 #pragma unroll
           for (int q = 0; q < 4; ++q) a[q] = ap[16 * ks + q];
+          if constexpr (RB == 2) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a2[q] = ap2[16 * ks + q];
+          }
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             acc0 = mfma_f64(a[q], b[0][st][q], acc0);
             acc1 = mfma_f64(a[q], b[1][st][q], acc1);
+            if constexpr (RB == 2) {
+              acc2 = mfma_f64(a2[q], b[0][st][q], acc2);
+              acc3 = mfma_f64(a2[q], b[1][st][q], acc3);
+            }
           }
         }
       }
@@ -433,21 +550,23 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
       }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int rr = 4 * r + lk;
-      const int64_t row = r0 + rr;
-      if (row < rows) {
-        double v0 = acc0[r], v1 = acc1[r];
-        if constexpr (ADD) {
-          v0 += sA[rr * pitch + cb0 + li];
-          v1 += sA[rr * pitch + cb0 + 16 + li];
+    for (int h = 0; h < RB; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = 16 * h + 4 * r + lk;
+        const int64_t row = r0 + rr;
+        if (row < rows) {
+          double v0 = h ? acc2[r] : acc0[r], v1 = h ? acc3[r] : acc1[r];
+          if constexpr (ADD) {
+            v0 += sA[rr * pitch + cb0 + li];
+            v1 += sA[rr * pitch + cb0 + 16 + li];
+          }
+          Q[row * ldq + cb0 + li] = v0;
+          Q[row * ldq + cb0 + 16 + li] = v1;
+          m0 = max(m0, __float_as_uint(fabsf((float)v0)));
+          m1 = max(m1, __float_as_uint(fabsf((float)v1)));
         }
-        Q[row * ldq + cb0 + li] = v0;
-        Q[row * ldq + cb0 + 16 + li] = v1;
-        m0 = max(m0, __float_as_uint(fabsf((float)v0)));
-        m1 = max(m1, __float_as_uint(fabsf((float)v1)));
       }
-    }
     if (colmax) {
       // the four lane groups hold the same columns: combine, then one atomic per column
       m0 = max(m0, (uint32_t)__shfl_xor((int)m0, 16));
@@ -539,7 +658,7 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
     }
   }
   const int zc = zero_to - lw;
-  for (int e = tid; e < TS_ROWS * zc; e += TS_WAVES * 64) {
+  for (int e = tid; e < ROWS * zc; e += TS_WAVES * 64) {
     const int64_t row = r0 + e / zc;
     if (row < rows) Q[row * ldq + lw + e % zc] = 0.0;
   }
@@ -1756,14 +1875,30 @@ constexpr double kSkipTau = 0x1p-44;
 
 // Row chunks of the Gram: about two workgroups per compute unit over the
 // lower 32 x 32 tiles, each wavefront at least 4 rows.
-static void cholqr_layout(int64_t rows, int64_t l, int* lw_out, int* nchunks, int64_t* rpc) {
+// The Gram runs on 64 x 64 tiles (gram64_kernel) from four 32-blocks on.
+static bool gram_wide(int lw) { return lw / NB >= 4; }
+
+static size_t cholqr_bytes(int lw, int nc) {
+  const size_t sq = (size_t)lw * lw;
+  const size_t n = 4 * sq + (size_t)lw * NB + lw + (size_t)nc * sq + 32 + (size_t)kCmSlices * lw / 2 + 1;
+  return n * sizeof(double) + 256;
+}
+
+// Row chunks of the Gram (at most 16, about two workgroups per compute unit
+// over the lower tiles, each wavefront at least 4 rows), fewer when the
+// partial sums must fit a workspace of budget bytes.
+static void cholqr_layout(int64_t rows, int64_t l, int* lw_out, int* nchunks, int64_t* rpc,
+                          size_t budget = (size_t)-1) {
   const int lw = (int)round_up(l, NB);
   const int Tn = lw / NB;
-  const int ntri = Tn * (Tn + 1) / 2;
-  int64_t nc = 512 / ntri;
-  if (nc < 1) nc = 1;
-  int64_t r = round_up(ceil_div(rows, nc), (int64_t)16);
-  nc = ceil_div(rows, r);
+  const int T64 = (Tn + 1) / 2;
+  const int ntri = gram_wide(lw) ? T64 * (T64 + 1) / 2 : Tn * (Tn + 1) / 2;
+  int64_t want = 512 / ntri;
+  if (want > 16) want = 16;
+  while (want > 1 && cholqr_bytes(lw, (int)want) > budget) --want;
+  if (want < 1) want = 1;
+  int64_t r = round_up(ceil_div(rows, want), (int64_t)16);
+  int64_t nc = ceil_div(rows, r);
   if (nc < 1) nc = 1;
   *lw_out = lw;
   *nchunks = (int)nc;
@@ -1774,9 +1909,12 @@ size_t cholqr2_workspace(int64_t rows, int64_t l) {
   int lw, nc;
   int64_t rpc;
   cholqr_layout(rows, l, &lw, &nc, &rpc);
-  const size_t sq = (size_t)lw * lw;
-  const size_t n = 4 * sq + (size_t)lw * NB + lw + (size_t)nc * sq + 32 + (size_t)kCmSlices * lw / 2 + 1;
-  return n * sizeof(double) + 256;
+  return cholqr_bytes(lw, nc);
+}
+
+size_t cholqr2_workspace_min(int64_t rows, int64_t l) {
+  (void)rows;
+  return cholqr_bytes((int)round_up(l, NB), 1);
 }
 
 struct HookScope {
@@ -1793,11 +1931,16 @@ template <typename T>
 static lramm_status gram(int64_t rows, int lw, int l_true, const T* X, int64_t ldx, const CholWs& w, int mode,
                          hipStream_t s, const TimingHook* hook) {
   const int Tn = lw / NB;
-  const int ntri = Tn * (Tn + 1) / 2;
   {
     HookScope hs(hook, SUB_CHOL_GRAM);
-    hipLaunchKernelGGL((gram_kernel<T>), dim3(ntri, w.nchunks), dim3(256), 0, s, rows, lw, l_true, X, ldx, w.part,
-                       w.rows_per_chunk);
+    if (gram_wide(lw)) {
+      const int T64 = (Tn + 1) / 2;
+      hipLaunchKernelGGL((gram64_kernel<T>), dim3(T64 * (T64 + 1) / 2, w.nchunks), dim3(256), 0, s, rows, lw, l_true,
+                         X, ldx, w.part, w.rows_per_chunk);
+    } else {
+      hipLaunchKernelGGL((gram_kernel<T>), dim3(Tn * (Tn + 1) / 2, w.nchunks), dim3(256), 0, s, rows, lw, l_true, X,
+                         ldx, w.part, w.rows_per_chunk);
+    }
   }
   LRAMM_HIP(hipGetLastError());
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)ceil_div((int64_t)lw * lw, 256)), dim3(256), 0, s, lw,
@@ -1885,11 +2028,22 @@ static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t l
                                   hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds));
     LRAMM_HIP(hipFuncSetAttribute((const void*)tsmul_kernel<T, ADD, true>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds));
+    LRAMM_HIP(hipFuncSetAttribute((const void*)tsmul_kernel<T, ADD, true, 2>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds));
     attr_set = true;
   }
   HookScope hs(hook, ADD ? SUB_CHOL_APPLY : SUB_CHOL_SOLVE);
   // 4-element vector loads need every row start aligned to 4 elements
   const int vec = ((uintptr_t)X % (4 * sizeof(T)) == 0 && ldx % 4 == 0) ? 1 : 0;
+  // 32 rows per workgroup when their panel and the W tiles fit
+  const size_t shm2 = (size_t)2 * TS_ROWS * ts_pitch(lw) * sizeof(double);
+  if (!Ltri && shm2 + ts_stage_lds() <= kMaxLds) {
+    const dim3 grid2((unsigned)ceil_div(rows, (int64_t)(2 * TS_ROWS)));
+    hipLaunchKernelGGL((tsmul_kernel<T, ADD, true, 2>), grid2, dim3(TS_WAVES * 64), shm2 + ts_stage_lds(), s, rows,
+                       lw, ncols, X, ldx, W, Q, ldq, zero_to, vec, colmax, cm_stride, gate, Ltri, Dlast);
+    LRAMM_HIP(hipGetLastError());
+    return LRAMM_OK;
+  }
   size_t shm = (size_t)TS_ROWS * ts_pitch(lw) * sizeof(double);
   if (Ltri) shm = ts_solve_last_lds(lw);
   const dim3 grid((unsigned)ceil_div(rows, (int64_t)TS_ROWS)), block(TS_WAVES * 64);
@@ -1910,8 +2064,8 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   if (rows == 0 || l == 0) return LRAMM_OK;
   int lw, nc;
   int64_t rpc;
-  cholqr_layout(rows, l, &lw, &nc, &rpc);
-  if (ws_bytes < cholqr2_workspace(rows, l)) return LRAMM_E_WORKSPACE;
+  cholqr_layout(rows, l, &lw, &nc, &rpc, ws_bytes);
+  if (ws_bytes < cholqr_bytes(lw, nc)) return LRAMM_E_WORKSPACE;
   uintptr_t base = round_up((int64_t)(uintptr_t)ws, 256);
   double* p = reinterpret_cast<double*>(base);
   const size_t sq = (size_t)lw * lw;

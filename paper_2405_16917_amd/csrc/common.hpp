@@ -297,6 +297,9 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
                             const TimingHook* hook = nullptr, uint32_t* colmax = nullptr,
                             int chain_mode = CHAIN_SHARED);
 size_t cholqr2_workspace(int64_t rows, int64_t l);
+// The least workspace CholeskyQR2 runs in (one row chunk of the Gram); with
+// less than cholqr2_workspace it uses fewer chunks.
+size_t cholqr2_workspace_min(int64_t rows, int64_t l);
 
 lramm_status launch_dense_gemm_nt(int64_t M, int64_t N, int64_t K, int dtype, const void* L, int64_t ldl,
                                   const void* R, int64_t ldr, float* C, int64_t ldc, hipStream_t s);

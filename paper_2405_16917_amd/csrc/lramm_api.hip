@@ -1044,7 +1044,7 @@ lramm_status lramm_cholqr2_noalloc(int64_t rows, int64_t l, const void* Y, int64
   if (ldy < l || ldq < round_up(l, 32)) return LRAMM_E_SHAPE;
   if (round_up(l, 32) > 1024) return LRAMM_E_UNSUPPORTED;
   if (ytype != LRAMM_F32 && ytype != LRAMM_F64) return LRAMM_E_UNSUPPORTED;
-  const size_t need = cholqr2_workspace(rows, l);
+  const size_t need = cholqr2_workspace_min(rows, l);   // fewer Gram chunks when the default does not fit
   if (need > (size_t)LRAMM_NOALLOC_SCRATCH_BYTES) return LRAMM_E_SCRATCH;
   void* ws = nullptr;
   LRAMM_TRY(scratch_address(&ws));
