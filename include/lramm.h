@@ -205,11 +205,14 @@ LRAMM_API lramm_status lramm_factors(const lramm_plan* plan, const void* ws,
  *   LRAMM_VIEW_Y  (0): the last sketch Y = A Q_Z (or A Omega), m x l, FP32;
  *   LRAMM_VIEW_Q  (1): Q, m x l, FP64 (as lramm_factors);
  *   LRAMM_VIEW_BT (2): Bt = Q^T A, l x k, FP32;
- *   LRAMM_VIEW_TT (3): T^T = (Bt B)^T, n x l, FP32.
+ *   LRAMM_VIEW_TT (3): T^T = (Bt B)^T, n x l, FP32;
+ *   LRAMM_VIEW_T  (4): T = Bt B, l x n, FP32 -- the form the forward keeps
+ *                      when G1 read a bf16 B in place (then VIEW_TT is not
+ *                      available, and the other way round).
  * *ptr points into ws; *ld is the leading dimension in elements, *dtype an
  * lramm_io value (LRAMM_F32 or LRAMM_F64).  Returns LRAMM_E_INVALID for an
- * unknown view or NULL arguments. */
-enum { LRAMM_VIEW_Y = 0, LRAMM_VIEW_Q = 1, LRAMM_VIEW_BT = 2, LRAMM_VIEW_TT = 3 };
+ * unknown or unavailable view or NULL arguments. */
+enum { LRAMM_VIEW_Y = 0, LRAMM_VIEW_Q = 1, LRAMM_VIEW_BT = 2, LRAMM_VIEW_TT = 3, LRAMM_VIEW_T = 4 };
 LRAMM_API lramm_status lramm_intermediate(const lramm_plan* plan, const void* ws,
                            int32_t which, const void** ptr, int64_t* rows,
                            int64_t* cols, int64_t* ld, int32_t* dtype);
@@ -411,6 +414,10 @@ LRAMM_API lramm_status lramm_cholqr2(int64_t rows, int64_t l, const void* Y, int
                            int32_t ytype, double* Q, int64_t ldq, void* ws,
                            size_t ws_bytes, uint32_t* flags, void* stream);
 LRAMM_API size_t lramm_cholqr2_workspace(int64_t rows, int64_t l);
+/* The least workspace lramm_cholqr2 runs in: with fewer bytes than
+ * lramm_cholqr2_workspace (but at least these) it sums the FP64 Gram over
+ * fewer row chunks -- the same arithmetic up to the order of the chunk sums. */
+LRAMM_API size_t lramm_cholqr2_workspace_min(int64_t rows, int64_t l);
 
 /* Host-only query of the schedule rule above: 1 when the Cholesky of an
  * l-column CholeskyQR2 runs as one launch on a GPU with compute_units CUs

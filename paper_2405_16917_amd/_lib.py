@@ -41,7 +41,7 @@ EXPORTS = (
     "lramm_cholqr2_noalloc", "lramm_chol_one_launch", "lramm_codes",
     "lramm_ts_plan_create", "lramm_ts_plan_destroy", "lramm_ts_workspace_bytes", "lramm_ts_forward",
     "lramm_ts_intermediate", "lramm_ts_status_poll", "lramm_srht_padded", "lramm_srht_samples",
-    "lramm_srht_sketch", "lramm_error_estimate",
+    "lramm_srht_sketch", "lramm_error_estimate", "lramm_cholqr2_workspace_min",
 )
 NSTAGES = 22
 
@@ -122,6 +122,7 @@ def load(path=LIB_PATH):
         "lramm_srht_sketch": ([I64, I64, I64, P, I64, I32, P, P, P, I64, P], I32),
         "lramm_cholqr2": ([I64, I64, P, I64, I32, P, I64, P, SZ, P, P], I32),
         "lramm_cholqr2_workspace": ([I64, I64], SZ),
+        "lramm_cholqr2_workspace_min": ([I64, I64], SZ),
         "lramm_cholqr2_noalloc": ([I64, I64, P, I64, I32, P, I64, P, P], I32),
         "lramm_chol_one_launch": ([I64, I32, ctypes.c_uint32], I32),
         "lramm_codes": ([P, P, I32, ctypes.POINTER(P), ctypes.POINTER(I64), ctypes.POINTER(I64),
@@ -389,14 +390,17 @@ class LrammPlan:
         Bt = ws[bo:bo + self.l * ldbt.value * 4].view(torch.float32).view(self.l, ldbt.value)
         return Q, Bt
 
-    VIEWS = {"Y": 0, "Q": 1, "Bt": 2, "Tt": 3}
+    VIEWS = {"Y": 0, "Q": 1, "Bt": 2, "Tt": 3, "T": 4}
 
     def intermediate(self, ws, name):
-        """View of one FP intermediate ("Y", "Q", "Bt" or "Tt") inside ws."""
+        """View of one FP intermediate ("Y", "Q", "Bt" or "Tt") inside ws.
+        "Tt" is returned as a transposed view of T when the forward kept T."""
         ptr, rows, cols, ld, dt = P(), I64(), I64(), I64(), I32()
-        _check(load().lramm_intermediate(self._h, _ptr(ws), self.VIEWS[name], ctypes.byref(ptr), ctypes.byref(rows),
-                                         ctypes.byref(cols), ctypes.byref(ld), ctypes.byref(dt)),
-               "lramm_intermediate")
+        code = load().lramm_intermediate(self._h, _ptr(ws), self.VIEWS[name], ctypes.byref(ptr), ctypes.byref(rows),
+                                         ctypes.byref(cols), ctypes.byref(ld), ctypes.byref(dt))
+        if code == E_INVALID and name == "Tt":
+            return self.intermediate(ws, "T").t()
+        _check(code, "lramm_intermediate")
         esz, tdt = (8, torch.float64) if dt.value == F64 else (4, torch.float32)
         off = ptr.value - ws.data_ptr()
         return ws[off:off + rows.value * ld.value * esz].view(tdt).view(rows.value, ld.value)[:, :cols.value]

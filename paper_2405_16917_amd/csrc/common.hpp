@@ -233,10 +233,13 @@ lramm_status launch_quantize_both(int64_t rows, int64_t cols, const void* X, int
                                   void* Rq, int64_t rpitch, float* rscales, void* Cq, int64_t cpitch,
                                   float* cscales, uint32_t* rmax, uint32_t* cmax, uint32_t* flags, hipStream_t s);
 
+// km (bf16 only): bit 0 -- Lq is a bf16 matrix stored K-major (K rows of M
+// elements, ldl bytes apart) instead of K-contiguous rows; bit 1 -- the same
+// for Rq (K rows of N elements, ldr bytes apart).  Runs on the 128-row tiles.
 lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void* Lq, int64_t ldl,
                             const float* dL, const void* Rq, int64_t ldr, const float* dR, float alpha,
                             float beta, void* C, int64_t ldc, int ctype, int32_t* acc_out, int64_t ld_acc,
-                            void* ws, size_t ws_bytes, hipStream_t s, bool col_first = false);
+                            void* ws, size_t ws_bytes, hipStream_t s, bool col_first = false, int km = 0);
 size_t gemm_nt_workspace(int64_t M, int64_t N, int64_t K, int fmt);
 
 lramm_status launch_omega(uint64_t seed, int64_t k, int64_t l, int64_t lrows, float* OmegaT, int64_t ldo,

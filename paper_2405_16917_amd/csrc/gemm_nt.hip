@@ -25,6 +25,8 @@
 //
 // Integer accumulation is exact and split-K partials are summed as integers
 // in a fixed order, so the result is bit-reproducible for any split.
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace lramm {
@@ -64,6 +66,7 @@ struct GemmArgs {
   int32_t* part;           // split-K partials [split][M][N] (int32 or float bits)
   int tiles_m, tiles_n;
   int group_m;             // rows of tiles per group of the tile order (0: plain band order)
+  int K;                   // K elements (rows of a K-major operand)
 };
 
 // Tile of workgroup blockIdx: consecutive workgroup ids go round robin over
@@ -171,7 +174,8 @@ struct TileLoader {
   // those vectors are loaded from the stage's start in the row (in bounds)
   // and zeroed.  Both forms are straight-line code.
   template <bool MASK>
-  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, const Offsets& o, int st, int kw, int tid) {
+  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, const Offsets& o, int st, int64_t kw64, int tid) {
+    const int kw = (int)kw64;
     const int so = st * kStageBytes;
     uint32_t m = 0xffffffffu;
     int vec = o.vec;
@@ -213,6 +217,65 @@ struct TileLoader {
     }
   }
 };
+
+// Global -> registers -> LDS for a bf16 operand stored K-major (K rows of
+// the operand's M / N elements, ld bytes apart): the LDS tile has the same
+// K-contiguous layout as TileLoader's.  Each of the 256 threads takes a block
+// of KR K rows x 8 elements (KR = 4 for 128-row tiles, 2 for 64; K block
+// t % (64 / KR), element block t / (64 / KR)), loads it as KR 16-byte
+// vectors, transposes it in registers and writes each element row's KR K
+// values with one 2 KR-byte LDS store.  Rows past K (and elements past the
+// operand) are outside the buffer resource and read as zero.
+template <int ROWS>
+struct TileLoaderKM {
+  static constexpr int KR = ROWS == 128 ? 4 : 2;
+  static constexpr int KB = 64 / KR;   // K blocks per 64-row stage
+  static_assert(KB * (ROWS / 8) == 256, "one block per thread");
+  uint4 r[KR];
+  struct Offsets {
+    int off;   // bytes: first K row of the block x ld + first element x 2
+    int kb, mb;
+  };
+  static __device__ __forceinline__ Offsets offsets(int64_t ld, int row0, int rows_total, int tid) {
+    (void)rows_total;
+    Offsets o;
+    o.kb = tid % KB;
+    o.mb = tid / KB;
+    o.off = (int)((int64_t)(KR * o.kb) * ld + (int64_t)(row0 + 8 * o.mb) * 2);
+    return o;
+  }
+  template <bool MASK>
+  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, const Offsets& o, int st, int64_t ld, int tid) {
+    (void)tid;
+    const int so = (int)((int64_t)st * 64 * ld);
+#pragma unroll
+    for (int i = 0; i < KR; ++i) {
+      typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+      const v4u x = __builtin_amdgcn_raw_buffer_load_b128(rs, o.off + (int)(i * ld), so, 0);
+      r[i] = make_uint4(x[0], x[1], x[2], x[3]);
+    }
+  }
+  __device__ __forceinline__ void store(uint8_t* lds, const Offsets& o) const {
+    uint32_t w[KR][4];
+#pragma unroll
+    for (int i = 0; i < KR; ++i) w[i][0] = r[i].x, w[i][1] = r[i].y, w[i][2] = r[i].z, w[i][3] = r[i].w;
+    uint8_t* base = lds + 8 * o.mb * kLdsPitch + 2 * KR * o.kb;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      // elements 2q (low halves) and 2q + 1 (high halves) of the KR K rows
+      if constexpr (KR == 4) {
+        const uint2 e0 = make_uint2(__byte_perm(w[0][q], w[1][q], 0x5410), __byte_perm(w[2][q], w[3][q], 0x5410));
+        const uint2 e1 = make_uint2(__byte_perm(w[0][q], w[1][q], 0x7632), __byte_perm(w[2][q], w[3][q], 0x7632));
+        *reinterpret_cast<uint2*>(base + (2 * q) * kLdsPitch) = e0;
+        *reinterpret_cast<uint2*>(base + (2 * q + 1) * kLdsPitch) = e1;
+      } else {
+        *reinterpret_cast<uint32_t*>(base + (2 * q) * kLdsPitch) = __byte_perm(w[0][q], w[1][q], 0x5410);
+        *reinterpret_cast<uint32_t*>(base + (2 * q + 1) * kLdsPitch) = __byte_perm(w[0][q], w[1][q], 0x7632);
+      }
+    }
+  }
+};
+
 
 template <int KIND>
 __device__ __forceinline__ Frag<KIND> load_frag(const uint8_t* p) {
@@ -377,8 +440,14 @@ __device__ __forceinline__ void store1(const GemmArgs& a, int split, int gm, int
   else reinterpret_cast<uint16_t*>(a.C)[idx] = bf16_bits(out);
 }
 
-template <int BM, int BN, int KIND, bool SPLIT>
+// KM: bit 0 the left operand, bit 1 the right one is a bf16 matrix stored
+// K-major (TileLoaderKM) instead of K-contiguous codes.
+template <int BM, int BN, int KIND, bool SPLIT, int KM = 0>
 __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
+  static_assert(KM == 0 || KIND == KIND_BF16, "K-major operands are bf16");
+  constexpr bool LKM = (KM & 1) != 0, RKM = (KM & 2) != 0;
+  using LoaderL = typename std::conditional<LKM, TileLoaderKM<BM>, TileLoader<BM, KIND>>::type;
+  using LoaderR = typename std::conditional<RKM, TileLoaderKM<BN>, TileLoader<BN, KIND>>::type;
   constexpr int RM = BM / 64;   // 32x32 MFMA tiles per wave along M
   constexpr int kPrefetch = kPrefetchOf<BM, BN, KIND>;
   constexpr int RN = BN / 64;
@@ -419,15 +488,19 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
   // (x - st0) % kPrefetch from its load until it is written to LDS (double
   // buffer) one iteration before its MFMAs, so every global load has about
   // kPrefetch stages of MFMA work to arrive.
-  TileLoader<BM, KIND> la[kPrefetch];
-  TileLoader<BN, KIND> lb[kPrefetch];
-  // operand resources: base and byte extent (rows x pitch, below 2^31)
-  const __amdgpu_buffer_rsrc_t rsL =
-      __builtin_amdgcn_make_buffer_rsrc((void*)a.L, (short)0, (int)((int64_t)a.M * a.ldl), kBufferWord3);
-  const __amdgpu_buffer_rsrc_t rsR =
-      __builtin_amdgcn_make_buffer_rsrc((void*)a.R, (short)0, (int)((int64_t)a.N * a.ldr), kBufferWord3);
-  const typename TileLoader<BM, KIND>::Offsets oa = TileLoader<BM, KIND>::offsets(a.ldl, row0, a.M, tid);
-  const typename TileLoader<BN, KIND>::Offsets ob = TileLoader<BN, KIND>::offsets(a.ldr, col0, a.N, tid);
+  LoaderL la[kPrefetch];
+  LoaderR lb[kPrefetch];
+  // operand resources: base and byte extent (rows x pitch, below 2^31; a
+  // K-major operand has K rows)
+  const __amdgpu_buffer_rsrc_t rsL = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)a.L, (short)0, (int)((int64_t)(LKM ? a.K : a.M) * a.ldl), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t rsR = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)a.R, (short)0, (int)((int64_t)(RKM ? a.K : a.N) * a.ldr), kBufferWord3);
+  const typename LoaderL::Offsets oa = LoaderL::offsets(a.ldl, row0, a.M, tid);
+  const typename LoaderR::Offsets ob = LoaderR::offsets(a.ldr, col0, a.N, tid);
+  // the loaders' last argument: padded K bytes (K-contiguous) or the row
+  // stride (K-major)
+  const int64_t xl = LKM ? a.ldl : (int64_t)a.kw, xr = RKM ? a.ldr : (int64_t)a.kw;
   const int full = a.kw / kStage;          // stages that lie wholly inside the padded K
   // prologue: the first kPrefetch stages (a short slice repeats its last
   // stage; those copies are never stored)
@@ -435,13 +508,21 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
 #pragma unroll
     for (int u = 0; u < kPrefetch; ++u) {
       const int st = st0 + u < st1 ? st0 + u : st1 - 1;
-      la[u].template load<true>(rsL, oa, st, a.kw, tid);
-      lb[u].template load<true>(rsR, ob, st, a.kw, tid);
+      la[u].template load<true>(rsL, oa, st, xl, tid);
+      lb[u].template load<true>(rsR, ob, st, xr, tid);
     }
   }
+  auto store_l = [&](const LoaderL& ld, uint8_t* dst) {
+    if constexpr (LKM) ld.store(dst, oa);
+    else ld.store(dst, tid);
+  };
+  auto store_r = [&](const LoaderR& ld, uint8_t* dst) {
+    if constexpr (RKM) ld.store(dst, ob);
+    else ld.store(dst, tid);
+  };
   if (st0 < st1) {
-    la[0].store(sA, tid);
-    lb[0].store(sB, tid);
+    store_l(la[0], sA);
+    store_r(lb[0], sB);
   }
   __syncthreads();
 
@@ -457,8 +538,8 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
   auto stage = [&](const int u, const int st, const int refill) {
     const int nx = st + kPrefetch < st1 ? st + kPrefetch : st1 - 1;
     if (refill == 2) {
-      la[u].template load<true>(rsL, oa, nx, a.kw, tid);
-      lb[u].template load<true>(rsR, ob, nx, a.kw, tid);
+      la[u].template load<true>(rsL, oa, nx, xl, tid);
+      lb[u].template load<true>(rsR, ob, nx, xr, tid);
     }
     const int buf = (st - st0) & 1;
     const uint8_t* A = sA + buf * BM * kLdsPitch;
@@ -477,8 +558,8 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
     }
     if (st + 1 < st1) {
       const int un = (u + 1) % kPrefetch;
-      la[un].store(sA + (buf ^ 1) * BM * kLdsPitch, tid);
-      lb[un].store(sB + (buf ^ 1) * BN * kLdsPitch, tid);
+      store_l(la[un], sA + (buf ^ 1) * BM * kLdsPitch);
+      store_r(lb[un], sB + (buf ^ 1) * BN * kLdsPitch);
     }
     __syncthreads();
   };
@@ -880,11 +961,11 @@ static bool use_big(int64_t M, int64_t N, int kw, int fmt) {
   return ceil_div(M, 256) * ceil_div(N, 256) >= 256;
 }
 
-static Plan plan_gemm(int64_t M, int64_t N, int64_t K, int fmt, bool allow_split) {
+static Plan plan_gemm(int64_t M, int64_t N, int64_t K, int fmt, bool allow_split, bool allow_big = true) {
   Plan p;
   const int64_t esz = fmt == LRAMM_BF16F ? 2 : 1;     // widened bytes per element
   p.kw = (int)round_up(K * esz > 0 ? K * esz : 1, 64);
-  p.big = use_big(M, N, p.kw, fmt);
+  p.big = allow_big && use_big(M, N, p.kw, fmt);
   if (p.big) {
     p.bm = p.bn = 256;
     p.tiles_m = (int)ceil_div(M, 256);
@@ -932,13 +1013,27 @@ size_t gemm_nt_workspace(int64_t M, int64_t N, int64_t K, int fmt) {
   return p.split > 1 ? (size_t)p.split * M * N * sizeof(int32_t) : 0;
 }
 
-template <int BM, int BN, int KIND>
+template <int BM, int BN, int KIND, int KM = 0>
 static void launch_tile(const GemmArgs& a, int split, hipStream_t s) {
   dim3 grid(a.tiles_m * a.tiles_n, split);
   if (split > 1)
-    hipLaunchKernelGGL((gemm_nt_kernel<BM, BN, KIND, true>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gemm_nt_kernel<BM, BN, KIND, true, KM>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((gemm_nt_kernel<BM, BN, KIND, false>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gemm_nt_kernel<BM, BN, KIND, false, KM>), grid, dim3(256), 0, s, a);
+}
+
+template <int BM, int BN>
+static void launch_tile_km(const GemmArgs& a, int split, int km, hipStream_t s) {
+  if (km == 1) launch_tile<BM, BN, KIND_BF16, 1>(a, split, s);
+  else if (km == 2) launch_tile<BM, BN, KIND_BF16, 2>(a, split, s);
+  else launch_tile<BM, BN, KIND_BF16, 3>(a, split, s);
+}
+
+static void launch_km(const GemmArgs& a, const Plan& p, int km, hipStream_t s) {
+  if (p.bm == 128 && p.bn == 128) launch_tile_km<128, 128>(a, p.split, km, s);
+  else if (p.bm == 128) launch_tile_km<128, 64>(a, p.split, km, s);
+  else if (p.bn == 128) launch_tile_km<64, 128>(a, p.split, km, s);
+  else launch_tile_km<64, 64>(a, p.split, km, s);
 }
 
 template <int KIND>
@@ -958,15 +1053,17 @@ static void launch_kind(const GemmArgs& a, const Plan& p, hipStream_t s) {
 lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void* Lq, int64_t ldl,
                             const float* dL, const void* Rq, int64_t ldr, const float* dR, float alpha,
                             float beta, void* C, int64_t ldc, int ctype, int32_t* acc_out, int64_t ld_acc,
-                            void* ws, size_t ws_bytes, hipStream_t s, bool col_first) {
+                            void* ws, size_t ws_bytes, hipStream_t s, bool col_first, int km) {
   int kind = kind_of(fmt);
   if (kind < 0) return LRAMM_E_UNSUPPORTED;
+  if (km != 0 && (kind != KIND_BF16 || (km & ~3))) return LRAMM_E_UNSUPPORTED;
   if (M == 0 || N == 0) return LRAMM_OK;
   // the tile loads address each operand with 32-bit byte offsets
-  if (M * ldl >= (int64_t)1 << 31 || N * ldr >= (int64_t)1 << 31) return LRAMM_E_UNSUPPORTED;
+  if (((km & 1) ? K : M) * ldl >= (int64_t)1 << 31 || ((km & 2) ? K : N) * ldr >= (int64_t)1 << 31)
+    return LRAMM_E_UNSUPPORTED;
   size_t need = gemm_nt_workspace(M, N, K, fmt);
   bool can_split = ws != nullptr && need > 0 && ws_bytes >= need;
-  Plan p = plan_gemm(M, N, K, fmt, can_split);
+  Plan p = plan_gemm(M, N, K, fmt, can_split, km == 0);
   GemmArgs a;
   a.M = (int)M;
   a.N = (int)N;
@@ -992,8 +1089,12 @@ lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void
   a.col_first = col_first ? 1 : 0;
   a.group_m = p.group;
   a.c_vec = (ldc % 4 == 0) && ((uintptr_t)C % (ctype == LRAMM_F32 ? 16 : 8) == 0);
+  a.K = (int)K;
   if (K == 0) p.nst = a.nst = 0;
-  switch (kind) {
+  if (km) {
+    launch_km(a, p, km, s);
+    LRAMM_HIP(hipGetLastError());
+  } else switch (kind) {
     case KIND_I8: launch_kind<KIND_I8>(a, p, s); break;
     case KIND_I4: launch_kind<KIND_I4>(a, p, s); break;
     case KIND_F8: launch_kind<KIND_F8>(a, p, s); break;

@@ -57,6 +57,9 @@ struct lramm_plan {
   // the bf16 input fed the bf16 sketch directly
   const void* last_Ar = nullptr;
   int64_t last_pAr = 0;
+  // whether the last forward's projection / G1 read A / B in place (bf16,
+  // K-major) instead of their column codes
+  bool last_km_a = false, last_km_b = false;
   // side stream for the work independent of the orthonormalisation chain
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_omega = nullptr, ev_sketch = nullptr;
@@ -509,9 +512,17 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   // tiles, 16-byte aligned), no pass over A
   const bool a_direct = d.fmt_sketch == LRAMM_BF16F && d.a_type == LRAMM_BF16 && !P->at && k % 64 == 0 &&
                         (lda * 2) % 16 == 0 && (uintptr_t)A % 16 == 0;
+  // bf16 A (B) in a bf16 projection (G1): the products read the operand
+  // itself, stored K-major, instead of a transposed copy
+  const bool km_a = d.fmt_proj == LRAMM_BF16F && d.a_type == LRAMM_BF16 && !P->at && (lda * 2) % 16 == 0 &&
+                    (uintptr_t)A % 16 == 0;
+  const bool km_b = !range_only && d.fmt_g1 == LRAMM_BF16F && d.b_type == LRAMM_BF16 && !P->bt &&
+                    (ldb * 2) % 16 == 0 && (uintptr_t)B % 16 == 0;
+  P->last_km_a = km_a;
+  P->last_km_b = km_b;
   // A's row codes (sketch format) and column codes (projection format) in
   // one format: both from two reads of A, before the sketch
-  const bool fused_a = !(P->srht && d.q == 0) && !a_direct && !P->at && d.fmt_sketch == d.fmt_proj;
+  const bool fused_a = !(P->srht && d.q == 0) && !a_direct && !km_a && !P->at && d.fmt_sketch == d.fmt_proj;
   if (P->srht && d.q == 0) {
     Ar = nullptr;   // the structured sketch reads A itself; no sketch-format codes
   } else if (fused_a) {
@@ -543,14 +554,14 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
     LRAMM_HIP(hipEventRecord(P->ev_sketch, s));
     LRAMM_HIP(hipStreamWaitEvent(P->side, P->ev_sketch, 0));
   }
-  if (fused_a) {
-    // written with the row codes
+  if (fused_a || km_a) {
+    // written with the row codes, or read in place
   } else if (!P->at)
     TIMED_ON(s2, ST_QUANT_A_COLS,
              launch_quantize(m, k, A, lda, d.a_type, d.fmt_proj, 1, Ac, P->pAc, sAc, flags, s2, mxA));
   else   // the columns of A' are the stored rows
     TIMED_ON(s2, ST_QUANT_A_COLS, launch_quantize(k, m, A, lda, d.a_type, d.fmt_proj, 0, Ac, P->pAc, sAc, flags, s2));
-  if (range_only) {
+  if (range_only || km_b) {
   } else if (!P->bt) {
     TIMED_ON(s2, ST_QUANT_B, launch_quantize(k, n, B, ldb, d.b_type, d.fmt_g1, 1, Bc, P->pBc, sBc, flags, s2, mxB));
   } else {
@@ -575,8 +586,12 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
     float* sQZc = at<float>(W, P->off_sQZc);
     TIMED(ST_QUANT_Q_COLS,
           launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s, mxQ(it), true));
-    TIMED(ST_POWER_Z, launch_gemm_nt(k, l, m, d.fmt_proj, Ac, P->pAc, sAc, Qc, P->pQc, sQc, 1.0f, 0.0f, Z, lp,
-                                     LRAMM_F32, nullptr, 0, split, sb, s));
+    if (km_a)
+      TIMED(ST_POWER_Z, launch_gemm_nt(k, l, m, d.fmt_proj, A, lda * 2, sAc, Qc, P->pQc, sQc, 1.0f, 0.0f, Z, lp,
+                                       LRAMM_F32, nullptr, 0, split, sb, s, false, 1));
+    else
+      TIMED(ST_POWER_Z, launch_gemm_nt(k, l, m, d.fmt_proj, Ac, P->pAc, sAc, Qc, P->pQc, sQc, 1.0f, 0.0f, Z, lp,
+                                       LRAMM_F32, nullptr, 0, split, sb, s));
     TIMED(ST_CHOLQR2, launch_cholqr2(k, l, Z, lp, LRAMM_F32, QZ, lp, cws, P->chol_bytes, flags, s, hk, mxQZ(it),
                                      P->chain_mode));
     TIMED(ST_QUANT_QZ,
@@ -591,8 +606,12 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   float* Bt = at<float>(W, P->off_Bt);
   TIMED(ST_QUANT_Q_COLS,
         launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s, mxQ(d.q), true));
-  TIMED(ST_PROJ, launch_gemm_nt(l, k, m, d.fmt_proj, Qc, P->pQc, sQc, Ac, P->pAc, sAc, 1.0f, 0.0f, Bt, k, LRAMM_F32,
-                                nullptr, 0, split, sb, s));
+  if (km_a)
+    TIMED(ST_PROJ, launch_gemm_nt(l, k, m, d.fmt_proj, Qc, P->pQc, sQc, A, lda * 2, sAc, 1.0f, 0.0f, Bt, k,
+                                  LRAMM_F32, nullptr, 0, split, sb, s, false, 2));
+  else
+    TIMED(ST_PROJ, launch_gemm_nt(l, k, m, d.fmt_proj, Qc, P->pQc, sQc, Ac, P->pAc, sAc, 1.0f, 0.0f, Bt, k,
+                                  LRAMM_F32, nullptr, 0, split, sb, s));
   if (norms)   // ||Bt||_F^2 = ||Q^T A'||_F^2 (up to the projection's quantisation)
     LRAMM_TRY(launch_sumsq(l, k, Bt, k, LRAMM_F32, norms + 2 + sumsq_parts_max(), norms + 1, s));
   if (range_only) return LRAMM_OK;
@@ -603,15 +622,22 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   TIMED(ST_QUANT_BT, launch_quantize(l, k, Bt, k, LRAMM_F32, d.fmt_g1, 0, Btq, P->pBtq, sBt, flags, s));
   // Tt is T transposed: the row factor of T (that of B~) is this product's
   // column factor, so the epilogue applies it first
-  TIMED(ST_G1, launch_gemm_nt(n, l, k, d.fmt_g1, Bc, P->pBc, sBc, Btq, P->pBtq, sBt, 1.0f, 0.0f, Tt, lp, LRAMM_F32,
-                              nullptr, 0, split, sb, s, true));
+  if (km_b)   // T = Bt_q B (l x n, ld n in the same buffer), B read in place as the right operand
+    TIMED(ST_G1, launch_gemm_nt(l, n, k, d.fmt_g1, Btq, P->pBtq, sBt, B, ldb * 2, sBc, 1.0f, 0.0f, Tt, n, LRAMM_F32,
+                                nullptr, 0, split, sb, s, false, 2));
+  else
+    TIMED(ST_G1, launch_gemm_nt(n, l, k, d.fmt_g1, Bc, P->pBc, sBc, Btq, P->pBtq, sBt, 1.0f, 0.0f, Tt, lp, LRAMM_F32,
+                                nullptr, 0, split, sb, s, true));
   // G2: C = alpha Q_r . Tt_q^T + beta C  (m x n)
   uint8_t* Qr = at<uint8_t>(W, P->off_Qr);
   float* sQr = at<float>(W, P->off_sQr);
   uint8_t* Ttq = at<uint8_t>(W, P->off_Ttq);
   float* sTt = at<float>(W, P->off_sTt);
   TIMED(ST_QUANT_Q_ROWS, launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_g2, 0, Qr, P->pQr, sQr, flags, s));
-  TIMED(ST_QUANT_TT, launch_quantize(n, l, Tt, lp, LRAMM_F32, d.fmt_g2, 0, Ttq, P->pTtq, sTt, flags, s));
+  if (km_b)   // the rows of T^T are the columns of T
+    TIMED(ST_QUANT_TT, launch_quantize(l, n, Tt, n, LRAMM_F32, d.fmt_g2, 1, Ttq, P->pTtq, sTt, flags, s));
+  else
+    TIMED(ST_QUANT_TT, launch_quantize(n, l, Tt, lp, LRAMM_F32, d.fmt_g2, 0, Ttq, P->pTtq, sTt, flags, s));
   if (!P->ct) {
     TIMED(ST_G2, launch_gemm_nt(m, n, l, d.fmt_g2, Qr, P->pQr, sQr, Ttq, P->pTtq, sTt, d.alpha, d.beta, C, ldc,
                                 d.c_type, nullptr, 0, split, sb, s));
@@ -660,8 +686,13 @@ lramm_status lramm_intermediate(const lramm_plan* P, const void* ws, int32_t whi
     case LRAMM_VIEW_BT:
       *ptr = base + P->off_Bt, *rows = P->l, *cols = d.k, *ld = d.k, *dtype = LRAMM_F32;
       break;
-    case LRAMM_VIEW_TT:
+    case LRAMM_VIEW_TT:   // stored as T when G1 read B in place
+      if (P->last_km_b) return LRAMM_E_INVALID;
       *ptr = base + P->off_Tt, *rows = d.n, *cols = P->l, *ld = P->lp, *dtype = LRAMM_F32;
+      break;
+    case LRAMM_VIEW_T:
+      if (!P->last_km_b) return LRAMM_E_INVALID;
+      *ptr = base + P->off_Tt, *rows = P->l, *cols = d.n, *ld = d.n, *dtype = LRAMM_F32;
       break;
     default: return LRAMM_E_INVALID;
   }
@@ -690,9 +721,15 @@ lramm_status lramm_codes(const lramm_plan* P, const void* ws, int32_t which, con
       else set(P->off_Om, P->off_sOm, l, k, P->pOm, d.fmt_sketch);
       break;
     case LRAMM_CODES_Q_COLS: set(P->off_Qc, P->off_sQc, l, m, P->pQc, d.fmt_proj); break;
-    case LRAMM_CODES_A_COLS: set(P->off_Ac, P->off_sAc, k, m, P->pAc, d.fmt_proj); break;
+    case LRAMM_CODES_A_COLS:   // not formed when the products read A in place
+      if (P->last_km_a) return LRAMM_E_INVALID;
+      set(P->off_Ac, P->off_sAc, k, m, P->pAc, d.fmt_proj);
+      break;
     case LRAMM_CODES_BT_ROWS: set(P->off_Btq, P->off_sBt, l, k, P->pBtq, d.fmt_g1); break;
-    case LRAMM_CODES_B_COLS: set(P->off_Bc, P->off_sBc, n, k, P->pBc, d.fmt_g1); break;
+    case LRAMM_CODES_B_COLS:
+      if (P->last_km_b) return LRAMM_E_INVALID;
+      set(P->off_Bc, P->off_sBc, n, k, P->pBc, d.fmt_g1);
+      break;
     case LRAMM_CODES_Q_ROWS: set(P->off_Qr, P->off_sQr, m, l, P->pQr, d.fmt_g2); break;
     case LRAMM_CODES_TT_ROWS: set(P->off_Ttq, P->off_sTt, n, l, P->pTtq, d.fmt_g2); break;
     default: return LRAMM_E_INVALID;
@@ -1015,6 +1052,8 @@ lramm_status lramm_srht_sketch(int64_t m, int64_t k, int64_t l, const void* A, i
 int64_t lramm_srht_padded(int64_t k) { return k < 1 ? 0 : srht_padded(k); }
 
 size_t lramm_cholqr2_workspace(int64_t rows, int64_t l) { return cholqr2_workspace(rows, l); }
+
+size_t lramm_cholqr2_workspace_min(int64_t rows, int64_t l) { return cholqr2_workspace_min(rows, l); }
 
 int32_t lramm_chol_one_launch(int64_t l, int32_t compute_units, uint32_t plan_flags) {
   if (l < 1 || round_up(l, 32) > 1024 || compute_units < 1) return 0;

@@ -121,8 +121,9 @@ def test_noalloc_cholqr2_host_checks(lib):
     import paper_2405_16917_amd._lib as L
     cap = L.NOALLOC_SCRATCH_BYTES
     for rows in (768, 4096, 65536, 1 << 22):
-        assert lib.lramm_cholqr2_workspace(rows, 768) <= cap
-    assert lib.lramm_cholqr2_workspace(1 << 20, 800) > cap
+        assert lib.lramm_cholqr2_workspace_min(rows, 768) <= cap
+        assert lib.lramm_cholqr2_workspace_min(rows, 768) <= lib.lramm_cholqr2_workspace(rows, 768)
+    assert lib.lramm_cholqr2_workspace_min(1 << 20, 800) > cap
     assert lib.lramm_cholqr2_noalloc(1 << 20, 800, 1, 800, L.F32, 1, 800, None, None) == L.E_SCRATCH
     assert lib.lramm_cholqr2_noalloc(10, 20, 1, 20, L.F32, 1, 32, None, None) == L.E_RANK
     assert lib.lramm_cholqr2_noalloc(100, 20, 1, 20, L.F32, 1, 20, None, None) == L.E_SHAPE

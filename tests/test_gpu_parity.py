@@ -463,12 +463,21 @@ def check_stages(lib, plan, ws, A, B, C, fmt, q, Ad=None, omega=None, omega_mism
     # projection: Q by columns x A by columns -> Bt (l x k)
     rawQc, dLq, Kq, _ = _raw(plan, ws, "Q_cols")
     Lq = _check_codes("Q cols", rawQc, Kq, fp, OQ.fl32(Qg).T)
-    rawAc, dRa, _, _ = _raw(plan, ws, "A_cols", rows=cols)
-    Ra = _check_codes("A cols", rawAc, Kq, fp, A.T[cols])
+    try:
+        rawAc, dRa, _, _ = _raw(plan, ws, "A_cols", rows=cols)
+        Ra = _check_codes("A cols", rawAc, Kq, fp, A.T[cols])
+    except lib.LrammError as e:
+        # bf16 A read in place (stored K-major): its values are the codes
+        assert e.code == lib._lib.E_INVALID and fp == "bf16"
+        Ra, dRa = A.T[cols], np.ones(len(cols))
     _check_product("projection", Bt[:, cols], Lq, dLq, Ra, dRa, fp)
     # G1: B by columns x Bt by rows -> T^T (n x l), T's row factor first
-    rawBc, dLb, Kb, _ = _raw(plan, ws, "B_cols", rows=ncols)
-    Lb = _check_codes("B cols", rawBc, Kb, f1, B.T[ncols])
+    try:
+        rawBc, dLb, Kb, _ = _raw(plan, ws, "B_cols", rows=ncols)
+        Lb = _check_codes("B cols", rawBc, Kb, f1, B.T[ncols])
+    except lib.LrammError as e:
+        assert e.code == lib._lib.E_INVALID and f1 == "bf16"
+        Lb, dLb, Kb = B.T[ncols], np.ones(len(ncols)), B.shape[0]
     rawBt, dRb, _, _ = _raw(plan, ws, "Bt_rows")
     Rb = _check_codes("Bt rows", rawBt, Kb, f1, Bt)
     _check_product("G1", Tt[ncols], Lb, dLb, Rb, dRb, f1, col_first=True)
