@@ -44,14 +44,14 @@ TARGET_RELF = 1e-2
 
 # Fastest setting per decay rate with rel-F <= 1e-2 on 8192^3 bf16, from
 # ``bench.py --sweep`` (summary: profiles/target_8192_setting_sweep.md):
-# (l, p, q, formats).  None: no setting within l <= 1024 reaches 1e-2; the
-# closest one is reported instead.
+# (l, p, q, formats, test matrix).  None: no setting within l <= 1024
+# reaches 1e-2; the closest one is reported instead.
 BEST = {
-    64.0: (448, 32, 0, ("bf16",) * 4),
-    128.0: (896, 32, 0, ("bf16",) * 4),
+    64.0: (416, 32, 0, ("bf16",) * 4, "srht"),
+    128.0: (896, 32, 0, ("bf16",) * 4, "srht"),
     256.0: None,
 }
-CLOSEST = {256.0: (1024, 32, 1, ("bf16",) * 4)}
+CLOSEST = {256.0: (1024, 32, 1, ("bf16",) * 4, "gaussian")}
 
 SWEEP = {
     64.0: [256, 320, 384, 416, 448, 480, 512],
