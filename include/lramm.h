@@ -376,8 +376,11 @@ LRAMM_API lramm_status lramm_omega(uint64_t seed, int64_t k, int64_t l, float* O
  * lramm_srht_padded: k' (0 for k < 1).
  * lramm_srht_samples: S (l int32, device) and the sign mask sign_bits
  * (ceil(k' / 32) uint32 words, device; bit i % 32 of word i / 32 set when
- * d_i = -1).  One workgroup.  Needs 2 <= k, k' <= 32768 (else
- * LRAMM_E_UNSUPPORTED) and 1 <= l <= k' (else LRAMM_E_RANK).
+ * d_i = -1).  keys: k' uint32 of device scratch (the drawn keys; contents
+ * unspecified on return).  Two launches: the keys and signs over k' / 256
+ * workgroups, then the selection in one.  Needs 2 <= k, k' <= 32768 (else
+ * LRAMM_E_UNSUPPORTED) and 1 <= l <= k' (else LRAMM_E_RANK); a null pointer
+ * is LRAMM_E_INVALID.
  * lramm_srht_sketch: Y (m x l FP32, ldy >= l, device) = A Omega for A m x k
  * row-major (a_type F32 or BF16, lda >= k, device) from S and sign_bits as
  * lramm_srht_samples writes them: the fast Walsh-Hadamard transform of each
@@ -398,7 +401,7 @@ LRAMM_API lramm_status lramm_error_estimate(const lramm_plan* plan, const void* 
 
 LRAMM_API int64_t lramm_srht_padded(int64_t k);
 LRAMM_API lramm_status lramm_srht_samples(uint64_t seed, int64_t k, int64_t l, int32_t* S,
-                         uint32_t* sign_bits, void* stream);
+                         uint32_t* sign_bits, uint32_t* keys, void* stream);
 LRAMM_API lramm_status lramm_srht_sketch(int64_t m, int64_t k, int64_t l, const void* A,
                          int64_t lda, int32_t a_type, const int32_t* S,
                          const uint32_t* sign_bits, float* Y, int64_t ldy, void* stream);

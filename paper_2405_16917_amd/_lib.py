@@ -118,7 +118,7 @@ def load(path=LIB_PATH):
         "lramm_omega": ([ctypes.c_uint64, I64, I64, P, I64, P], I32),
         "lramm_srht_padded": ([I64], I64),
         "lramm_error_estimate": ([P, P, P, ctypes.POINTER(ctypes.c_double)], I32),
-        "lramm_srht_samples": ([ctypes.c_uint64, I64, I64, P, P, P], I32),
+        "lramm_srht_samples": ([ctypes.c_uint64, I64, I64, P, P, P, P], I32),
         "lramm_srht_sketch": ([I64, I64, I64, P, I64, I32, P, P, P, I64, P], I32),
         "lramm_cholqr2": ([I64, I64, P, I64, I32, P, I64, P, SZ, P, P], I32),
         "lramm_cholqr2_workspace": ([I64, I64], SZ),
@@ -239,7 +239,8 @@ def lramm_srht_samples(seed, k, l, device="cuda"):
     kp = lramm_srht_padded(k)
     S = torch.empty(l, dtype=torch.int32, device=device)
     bits = torch.empty((kp + 31) // 32, dtype=torch.int32, device=device)
-    _check(load().lramm_srht_samples(seed, k, l, _ptr(S), _ptr(bits), _stream()), "lramm_srht_samples")
+    keys = torch.empty(kp, dtype=torch.int32, device=device)
+    _check(load().lramm_srht_samples(seed, k, l, _ptr(S), _ptr(bits), _ptr(keys), _stream()), "lramm_srht_samples")
     return S, bits
 
 

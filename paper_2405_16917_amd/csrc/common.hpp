@@ -257,7 +257,7 @@ int64_t omega_quant_max_k();
 // or BF16), one workgroup per row.
 int64_t srht_padded(int64_t k);
 lramm_status launch_srht_samples(uint64_t seed, int64_t k, int64_t l, int32_t* S, uint32_t* sign_bits,
-                                 hipStream_t s);
+                                 uint32_t* keys, hipStream_t s);
 lramm_status launch_srht(int64_t m, int64_t k, int64_t l, const void* A, int64_t lda, int a_type,
                          const uint32_t* sign_bits, const int32_t* S, float* Y, int64_t ldy, hipStream_t s);
 

@@ -44,7 +44,7 @@ struct lramm_plan {
   size_t off_chol, chol_bytes, off_split, split_bytes;
   size_t off_W, off_Bte, off_V;
   bool srht = false;        // structured first sketch (LRAMM_PLAN_SRHT)
-  size_t off_srS = 0, off_srD = 0;
+  size_t off_srS = 0, off_srD = 0, off_srK = 0;
   bool estimate = false;    // a-posteriori error estimate (LRAMM_PLAN_ESTIMATE)
   size_t off_norms = 0;     // ||A'||^2, ||Bt||^2, then the two partial arrays
   // zero-filled at the start of every forward: the status word, then the
@@ -311,6 +311,7 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   if (p->srht) {
     p->off_srS = carve(&c, (size_t)l * 4);
     p->off_srD = carve(&c, (size_t)(srht_padded(k) + 31) / 32 * 4);
+    p->off_srK = carve(&c, (size_t)srht_padded(k) * 4);
   }
   p->off_Y = carve(&c, (size_t)m * lp * 4);
   p->off_Q = carve(&c, (size_t)m * lp * 8);
@@ -492,10 +493,14 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   }
   int32_t* srS = P->srht ? at<int32_t>(W, P->off_srS) : nullptr;
   uint32_t* srD = P->srht ? at<uint32_t>(W, P->off_srD) : nullptr;
+  // without power iterations nothing precedes the structured sketch on the
+  // main stream, so its samples go there directly (no event hop)
+  const bool srht_main = P->srht && d.q == 0;
   if (P->srht) {
-    // the sample set and the sign mask (one workgroup)
-    TIMED_ON(s2, ST_OMEGA, launch_srht_samples(d.seed, k, l, srS, srD, s2));
-    if (P->side) LRAMM_HIP(hipEventRecord(P->ev_omega, P->side));
+    // the sample set and the sign mask
+    hipStream_t so = srht_main ? s : s2;
+    TIMED_ON(so, ST_OMEGA, launch_srht_samples(d.seed, k, l, srS, srD, at<uint32_t>(W, P->off_srK), so));
+    if (P->side && !srht_main) LRAMM_HIP(hipEventRecord(P->ev_omega, P->side));
   } else if (!omega) {
     if (d.fmt_sketch == LRAMM_BF16F || k <= omega_quant_max_k()) {
       // generated and quantised in one pass
@@ -541,7 +546,7 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   if (omega) {
     TIMED(ST_QUANT_OMEGA, launch_quantize(k, l, omega, ldo, LRAMM_F32, d.fmt_sketch, 1, Om, P->pOm, sOm, flags, s,
                                           zero + P->mx_Om));
-  } else if (P->side) {
+  } else if (P->side && !srht_main) {
     LRAMM_HIP(hipStreamWaitEvent(s, P->ev_omega, 0));   // Omega's codes ready
   }
   // sketch, then the side stream's column codes, then the orthonormalisation
@@ -1034,10 +1039,10 @@ lramm_status lramm_error_estimate(const lramm_plan* P, const void* ws, void* str
 }
 
 lramm_status lramm_srht_samples(uint64_t seed, int64_t k, int64_t l, int32_t* S, uint32_t* sign_bits,
-                                void* stream) {
+                                uint32_t* keys, void* stream) {
   if (k < 2 || l < 1) return l < 1 ? LRAMM_E_RANK : LRAMM_E_UNSUPPORTED;
-  if (!S || !sign_bits) return LRAMM_E_INVALID;
-  return launch_srht_samples(seed, k, l, S, sign_bits, (hipStream_t)stream);
+  if (!S || !sign_bits || !keys) return LRAMM_E_INVALID;
+  return launch_srht_samples(seed, k, l, S, sign_bits, keys, (hipStream_t)stream);
 }
 
 lramm_status lramm_srht_sketch(int64_t m, int64_t k, int64_t l, const void* A, int64_t lda, int32_t a_type,

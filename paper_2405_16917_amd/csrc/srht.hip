@@ -9,10 +9,13 @@
 // counter (i, 0, 1, 0) is set, and S = the indices of the l smallest pairs
 // (x0 at counter (i, 0, 2, 0), i).
 //
-// srht_samples_kernel: one workgroup of 1024 threads finds S by a radix
-// select of the l-th smallest 32-bit key (8 bits per pass), takes every key
-// below it and the first of the keys equal to it in index order, and writes
-// the signs as a bit mask (bit i of word i / 32 set for d_i = -1).
+// srht_keys_kernel: one thread per index of [0, k') draws its key and its
+// sign (the two Philox words are the costly part, so they are spread over
+// k' / 256 workgroups); the keys go to a scratch array, the signs to a bit
+// mask (bit i of word i / 32 set for d_i = -1) from each wavefront's ballot.
+// srht_samples_kernel: one workgroup of 1024 threads reads the keys, finds
+// the l-th smallest by a radix select (8 bits per pass), and takes every key
+// below it and the first of the keys equal to it in index order.
 // srht_kernel: one workgroup per row of A; each thread holds EPT consecutive
 // elements of the signed row in registers and applies the butterflies of
 // the low log2(EPT) index bits there, then the remaining bits in rounds of
@@ -65,36 +68,45 @@ __device__ __forceinline__ uint32_t block_scan_incl(uint32_t v, uint32_t* wsum) 
   return incl + off;
 }
 
-__global__ __launch_bounds__(kSelThreads) void srht_samples_kernel(uint64_t seed, int kp, int l, int32_t* __restrict__ S,
-                                                                 uint32_t* __restrict__ sign_bits) {
+__global__ __launch_bounds__(256) void srht_keys_kernel(uint64_t seed, int kp, uint32_t* __restrict__ keys,
+                                                        uint32_t* __restrict__ sign_bits) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  uint32_t neg = 0;
+  if (i < kp) {
+    keys[i] = srht_word(seed, (uint32_t)i, 2u);
+    neg = srht_word(seed, (uint32_t)i, 1u) & 1u;
+  }
+  // every lane takes part in the ballot; lanes 0 and 1 store the wavefront's
+  // two words (only the first when k' < 64 leaves the second out of range)
+  const uint64_t mask = __ballot(neg != 0);
+  const int base = i - lane;
+  if (lane < 2 && base + 32 * lane < kp) sign_bits[(base >> 5) + lane] = (uint32_t)(mask >> (32 * lane));
+}
+
+__global__ __launch_bounds__(kSelThreads) void srht_samples_kernel(int kp, int l, const uint32_t* __restrict__ keys,
+                                                                 int32_t* __restrict__ S) {
   __shared__ uint32_t hist[256];
-  __shared__ uint32_t words[kSrhtMaxK / 32];
   __shared__ uint32_t wsum[kSelThreads / 64];
   __shared__ uint32_t s_prefix, s_rank;
   const int t = threadIdx.x, lane = t & 63;
-  const int nwords = (kp + 31) / 32;
-  for (int w = t; w < nwords; w += kSelThreads) words[w] = 0;
   if (t == 0) {
     s_prefix = 0;
     s_rank = (uint32_t)l;   // 1-based rank of the threshold key
   }
-  __syncthreads();
   // this thread's indices: [t c, t c + c) of [0, kp), c a power of two
-  // <= 32; their keys (0xffffffff marks no index: it never counts below
-  // the threshold, and ties at that value are resolved by the live flags)
+  // <= 32 (live marks the ones in range)
   const int c = (kp + kSelThreads - 1) / kSelThreads;
   uint32_t u[32];
-  uint32_t live = 0, sg = 0;
+  uint32_t live = 0;
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
     const int i = t * c + j;
     const bool in = j < c && i < kp;
-    u[j] = in ? srht_word(seed, (uint32_t)i, 2u) : 0xffffffffu;
+    u[j] = in ? keys[i] : 0xffffffffu;
     if (in) live |= 1u << j;
-    if (in && (srht_word(seed, (uint32_t)i, 1u) & 1u)) sg |= 1u << j;
   }
-  // this thread's signs sit in one word at bit (t c) % 32
-  if (sg) atomicOr(&words[(t * c) >> 5], sg << ((t * c) & 31));
+  __syncthreads();
   // radix select of the l-th smallest key: digits of 8 bits from the top
   for (int shift = 24; shift >= 0; shift -= 8) {
     if (t < 256) hist[t] = 0;
@@ -123,7 +135,6 @@ __global__ __launch_bounds__(kSelThreads) void srht_samples_kernel(uint64_t seed
     }
     __syncthreads();
   }
-  for (int w = t; w < nwords; w += kSelThreads) sign_bits[w] = words[w];
   // the threshold key T and how many of the keys equal to T are taken (the
   // first ones in index order): s_rank of them
   const uint32_t T = s_prefix, take_eq = s_rank;
@@ -274,11 +285,14 @@ __global__ __launch_bounds__(1024) void srht_kernel(int64_t k, int kp, int l, co
 }
 
 lramm_status launch_srht_samples(uint64_t seed, int64_t k, int64_t l, int32_t* S, uint32_t* sign_bits,
-                                 hipStream_t s) {
+                                 uint32_t* keys, hipStream_t s) {
   const int64_t kp = srht_padded(k);
   if (k < 2 || kp > kSrhtMaxK) return LRAMM_E_UNSUPPORTED;
   if (l < 1 || l > kp) return LRAMM_E_RANK;
-  hipLaunchKernelGGL(srht_samples_kernel, dim3(1), dim3(kSelThreads), 0, s, seed, (int)kp, (int)l, S, sign_bits);
+  hipLaunchKernelGGL(srht_keys_kernel, dim3((unsigned)ceil_div(kp, (int64_t)256)), dim3(256), 0, s, seed, (int)kp,
+                     keys, sign_bits);
+  LRAMM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(srht_samples_kernel, dim3(1), dim3(kSelThreads), 0, s, (int)kp, (int)l, keys, S);
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }

@@ -173,11 +173,12 @@ def test_srht_host_checks(lib):
     import paper_2405_16917_amd._lib as L
     assert [lib.lramm_srht_padded(k) for k in (0, 1, 2, 3, 512, 513, 32768)] == [0, 1, 2, 4, 512, 1024, 32768]
     dummy = ctypes.c_void_p(16)
-    assert lib.lramm_srht_samples(1, 1, 1, dummy, dummy, None) == L.E_UNSUPPORTED       # k < 2
-    assert lib.lramm_srht_samples(1, 40000, 8, dummy, dummy, None) == L.E_UNSUPPORTED   # k' > 32768
-    assert lib.lramm_srht_samples(1, 100, 0, dummy, dummy, None) == L.E_RANK
-    assert lib.lramm_srht_samples(1, 100, 129, dummy, dummy, None) == L.E_RANK          # l > k'
-    assert lib.lramm_srht_samples(1, 100, 8, None, dummy, None) == L.E_INVALID
+    assert lib.lramm_srht_samples(1, 1, 1, dummy, dummy, dummy, None) == L.E_UNSUPPORTED       # k < 2
+    assert lib.lramm_srht_samples(1, 40000, 8, dummy, dummy, dummy, None) == L.E_UNSUPPORTED   # k' > 32768
+    assert lib.lramm_srht_samples(1, 100, 0, dummy, dummy, dummy, None) == L.E_RANK
+    assert lib.lramm_srht_samples(1, 100, 129, dummy, dummy, dummy, None) == L.E_RANK          # l > k'
+    assert lib.lramm_srht_samples(1, 100, 8, None, dummy, dummy, None) == L.E_INVALID
+    assert lib.lramm_srht_samples(1, 100, 8, dummy, dummy, None, None) == L.E_INVALID         # no key scratch
     assert lib.lramm_srht_sketch(4, 100, 8, dummy, 99, L.F32, dummy, dummy, dummy, 8, None) == L.E_SHAPE
     assert lib.lramm_srht_sketch(4, 100, 8, dummy, 100, L.F32, dummy, dummy, dummy, 7, None) == L.E_SHAPE
     assert lib.lramm_srht_sketch(4, 100, 8, dummy, 100, L.F64, dummy, dummy, dummy, 8, None) == L.E_UNSUPPORTED
