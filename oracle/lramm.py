@@ -3,7 +3,8 @@
 
 What is computed (paper references):
   * range finder (Sec. 2.2, two-stage method; Alg. 1's first step B <- Q* A):
-    Y = A Omega with a Gaussian k x l test matrix, l = r + p, then Q = qr(Y);
+    Y = A Omega with a Gaussian k x l test matrix, l = r + p, then Q = qr(Y)
+    (Householder, or one pass of Cholesky QR when asked);
   * power (subspace) iterations, q of them (the paper's exponent q of
     Sec. 3.3 / eq. rsvderror; the procedure is the randomised subspace
     iteration of Halko, Martinsson & Tropp 2011, Alg. 4.4, which
@@ -42,7 +43,7 @@ import numpy as np
 
 from .quant import fl32
 from .qgemm import qgemm
-from .qr import householder_qr, householder_qr_dropping
+from .qr import cholesky_qr, householder_qr, householder_qr_dropping
 from .philox import gaussian_omega
 from .srht import srht_omega, srht_sketch
 
@@ -62,18 +63,24 @@ def _q_operand(Q, fmt):
     return Q if fmt == "fp64" else fl32(Q)
 
 
-def range_finder(A, l, q, fs, fp, omega, drop_dependent=False, out=None, keep=True, y0=None):
+def range_finder(A, l, q, fs, fp, omega, drop_dependent=False, out=None, keep=True, y0=None, one_pass=False):
     """Q with l orthonormal columns spanning the sketch of A (Sec. 2.2,
     first stage): Y = A Omega in format fs (or y0 when given: the structured
     sketch, formed without operand codes), Q = qr(Y), then q subspace
     iterations Z = A^T Q (format fp), Q_Z = qr(Z), Y = A Q_Z (fs), Q = qr(Y).
-    Intermediates go into ``out`` (when given, with ``keep``).  Returns
-    (Q, R) of the last orthonormalisation."""
+    Intermediates go into ``out`` (when given, with ``keep``).  With
+    ``one_pass`` every qr is one pass of Cholesky QR (qr.cholesky_qr, which
+    drops dependent columns by the same rule) instead of Householder.
+    Returns (Q, R) of the last orthonormalisation."""
     if out is None:
         out = {}
     tol = 64.0 * l * 2.0**-53
 
     def orth(X):
+        if one_pass:
+            Qd, Rd, dropped = cholesky_qr(X, tol)
+            out.setdefault("dropped", []).append(dropped)
+            return Qd, Rd
         if drop_dependent:
             Qd, Rd, dropped = householder_qr_dropping(X, tol)
             out.setdefault("dropped", []).append(dropped)
@@ -99,7 +106,8 @@ def range_finder(A, l, q, fs, fp, omega, drop_dependent=False, out=None, keep=Tr
 
 
 def lramm_forward(A, B, r, p, q, fmt=("int8",) * 4, omega=None, seed=None,
-                  alpha=1.0, beta=0.0, Cin=None, keep=True, drop_dependent=False, sketch="gaussian"):
+                  alpha=1.0, beta=0.0, Cin=None, keep=True, drop_dependent=False, sketch="gaussian",
+                  one_pass=False):
     """One-sided LRAMM.  A: m x k, B: k x n (binary32 values unless every
     stage is fp64).  Returns a dict with C and, with ``keep``, every
     intermediate (Omega, Y, Q, B~, T, and the power-iteration Z / Q_Z).
@@ -115,7 +123,11 @@ def lramm_forward(A, B, r, p, q, fmt=("int8",) * 4, omega=None, seed=None,
     the basis then spans exactly the kept sketch columns.  This is the reading
     used for rank(A) < l, where the completion vectors of a plain Householder
     QR are arbitrary directions outside range(A) and would change the row
-    scales of Q."""
+    scales of Q.
+
+    ``one_pass``: orthonormalise with one pass of Cholesky QR (Q = Y R^-1,
+    R the Cholesky factor of Y^T Y, same dropping rule): the cheaper basis,
+    orthonormal only to about 2^-53 cond(Y)^2."""
     A = np.asarray(A, np.float64)
     B = np.asarray(B, np.float64)
     m, k = A.shape
@@ -146,7 +158,7 @@ def lramm_forward(A, B, r, p, q, fmt=("int8",) * 4, omega=None, seed=None,
         raise ValueError("omega must be k x l")
 
     out = {"l": l}
-    Q, R = range_finder(A, l, q, fs, fp, omega, drop_dependent, out, keep, y0)
+    Q, R = range_finder(A, l, q, fs, fp, omega, drop_dependent, out, keep, y0, one_pass)
     Bt = _product(_q_operand(Q, fp).T, A, fp)
     T = _product(Bt, B, f1)
     C = _product(_q_operand(Q, f2), T, f2)

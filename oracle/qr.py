@@ -19,13 +19,26 @@ falls below 64 l 2^-53 times its Gram diagonal): a column whose unexplained
 part is that small is left out entirely, so the kept columns are the QR of
 the kept columns of Y and the dropped ones are zero.
 
+One pass of Cholesky QR (``cholesky_qr``, the cheaper orthonormalisation a
+plan may ask for instead of the two-pass one): R from the Cholesky factor of
+the Gram matrix Y^T Y, Q = Y R^-1, with the same dependent-column rule (a
+pivot at most tol times its Gram diagonal drops the column: zero row of R,
+zero column of Q, no part in later eliminations).  Its Q spans range(Y) but
+is orthonormal only to about 2^-53 cond(Y)^2; Yamamoto, Nakatsukasa,
+Yanagisawa and Fukaya (2015, Thm. 3.3) bound ||Q^T Q - I||_2 by (5/64) d^2,
+d = 8 cond_2(Y) sqrt(m n u + n (n + 1) u), u = 2^-53, whenever d < 1.
+
 Pins (tests/test_oracle_qr.py): ||Q^T Q - I||_max <= 1e-13,
 ||QR - Y||_F <= 1e-14 ||Y||_F, R upper triangular with a non-negative
 diagonal, agreement with LAPACK's QR after the same sign normalisation, and a
-hand-worked 3x2 example.
+hand-worked 3x2 example; for ``cholesky_qr`` (tests/test_oracle_cholqr.py):
+exact on orthogonal columns, x / ||x|| for one column, Q^T Q - I within the
+bound above, agreement with Householder QR within its first-order forward
+error, and the dropped set and span of exactly dependent integer columns.
 """
 
 import numpy as np
+from scipy.linalg import solve_triangular
 
 
 def householder_qr_dropping(Y, tol):
@@ -114,3 +127,33 @@ def householder_qr(Y):
     s = np.sign(np.diag(R))
     s[s == 0] = 1.0
     return Q * s[None, :], R * s[:, None]
+
+
+def cholesky_qr(Y, tol):
+    """One pass of Cholesky QR in FP64: G = Y^T Y; the column-by-column
+    Cholesky G = R^T R (pivot j: the Schur complement entry S_jj, accepted
+    when it exceeds tol * G_jj, else column j is dropped and eliminates
+    nothing); Q = Y R^-1 on the kept columns.  Returns Q (m x n), R (n x n)
+    and the list of dropped column indices."""
+    Y = np.asarray(Y, dtype=np.float64)
+    m, n = Y.shape
+    if n > m:
+        raise ValueError("thin QR needs at least as many rows as columns")
+    G = Y.T @ Y
+    S = G.copy()
+    R = np.zeros((n, n))
+    dropped = []
+    for j in range(n):
+        piv = S[j, j]
+        if not piv > tol * G[j, j]:
+            dropped.append(j)
+            continue
+        R[j, j:] = S[j, j:] / np.sqrt(piv)
+        S[j + 1:, j + 1:] -= np.outer(R[j, j + 1:], R[j, j + 1:])
+    kept = [j for j in range(n) if j not in dropped]
+    Q = np.zeros((m, n))
+    if kept:
+        Rk = R[np.ix_(kept, kept)]
+        # Q_k R_k = Y_k: one triangular solve per row of Y (R_k^T q = y)
+        Q[:, kept] = solve_triangular(Rk, Y[:, kept].T, trans="T", lower=False).T
+    return Q, R, dropped
