@@ -44,14 +44,14 @@ TARGET_RELF = 1e-2
 
 # Fastest setting per decay rate with rel-F <= 1e-2 on 8192^3 bf16, from
 # ``bench.py --sweep`` (summary: profiles/target_8192_setting_sweep.md):
-# (l, p, q, formats, test matrix).  None: no setting within l <= 1024
-# reaches 1e-2; the closest one is reported instead.
+# (l, p, q, formats, test matrix, orthonormalisation).  None: no setting
+# within l <= 1024 reaches 1e-2; the closest one is reported instead.
 BEST = {
-    64.0: (416, 32, 0, ("bf16",) * 4, "srht"),
-    128.0: (896, 32, 0, ("bf16",) * 4, "srht"),
+    64.0: (416, 32, 0, ("bf16",) * 4, "srht", "cholqr"),
+    128.0: (896, 32, 0, ("bf16",) * 4, "srht", "cholqr"),
     256.0: None,
 }
-CLOSEST = {256.0: (1024, 32, 1, ("bf16",) * 4, "gaussian")}
+CLOSEST = {256.0: (1024, 32, 1, ("bf16",) * 4, "gaussian", "cholqr")}
 
 SWEEP = {
     64.0: [256, 320, 384, 416, 448, 480, 512],
@@ -60,7 +60,17 @@ SWEEP = {
 }
 SWEEP_FMTS = {"bf16": ("bf16",) * 4, "int8_sketch": ("int8", "bf16", "bf16", "bf16"),
               "fp8": ("fp8",) * 4, "int8": ("int8",) * 4, "srht+bf16": (("bf16",) * 4, "srht"),
-              "srht+fp8": (("fp8",) * 4, "srht")}
+              "srht+fp8": (("fp8",) * 4, "srht"), "srht+bf16+1pass": (("bf16",) * 4, "srht", "cholqr"),
+              "bf16+1pass": (("bf16",) * 4, "gaussian", "cholqr")}
+
+
+def setting_parts(setting):
+    """(l, p, q, formats, test matrix, orthonormalisation) of a setting tuple
+    (the last two optional: "gaussian", "cholqr2")."""
+    l, p, q, fmt = setting[:4]
+    sketch = setting[4] if len(setting) > 4 else "gaussian"
+    orth = setting[5] if len(setting) > 5 else "cholqr2"
+    return l, p, q, fmt, sketch, orth
 
 
 def parse():
@@ -76,6 +86,8 @@ def parse():
     ap.add_argument("--fmt", default=None, help="one format for every stage, or four comma-separated")
     ap.add_argument("--sketch", default=None, choices=["gaussian", "srht"],
                     help="test matrix of the first sketch (default: the setting's)")
+    ap.add_argument("--orth", default=None, choices=["cholqr2", "cholqr"],
+                    help="orthonormalisation: two Cholesky QR passes or one (default: the setting's)")
     ap.add_argument("--sweep", action="store_true", help="search (l, q, formats) per decay rate")
     ap.add_argument("--taus", default="64,128,256")
     ap.add_argument("--precision-sweep", action="store_true",
@@ -139,12 +151,11 @@ def exact_product(A64, B64):
 def run_setting(lramm, A, B, setting, steps, warmup, seed=1, timing=False):
     """Time `steps` forwards of one setting; returns (ms per step, C, plan, ws)."""
     import torch
-    l, p, q, fmt = setting[:4]
-    sketch = setting[4] if len(setting) > 4 else "gaussian"
+    l, p, q, fmt, sketch, orth = setting_parts(setting)
     m, k = A.shape
     n = B.shape[1]
     plan = lramm.LrammPlan(m, n, k, l - p, p, q, fmt, A.dtype, B.dtype, A.dtype, seed, exclusive=True,
-                           sketch=sketch)
+                           sketch=sketch, orth=orth)
     ws = plan.workspace(A.device)
     C = torch.empty((m, n), dtype=A.dtype, device=A.device)
     for _ in range(warmup):
@@ -307,6 +318,29 @@ def dense_bf16(lramm, A, B, reps=10):
     return e0.elapsed_time(e1) / reps, Cd
 
 
+def dense_library(A, B, reps=10):
+    """The vendor library's dense bf16 GEMM (torch.matmul, which calls
+    hipBLASLt) on the same inputs, bf16 output: ms per product with B as
+    stored (row-major, NN) and with B transposed beforehand outside the
+    timing (NT).  A comparator only: no LRAMM stage calls it."""
+    import torch
+    out = {}
+    for name, Bx in (("nn", B), ("nt", B.t().contiguous().t())):
+        for _ in range(3):
+            C = A @ Bx
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            C = A @ Bx
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"ms_{name}"] = e0.elapsed_time(e1) / reps
+        del C, Bx
+    out["ms"] = min(out["ms_nn"], out["ms_nt"])
+    return out
+
+
 def sweep(args, lramm, dev):
     import torch
     taus = [float(x) for x in args.taus.split(",")]
@@ -320,10 +354,10 @@ def sweep(args, lramm, dev):
         for l in SWEEP.get(tau, SWEEP[64.0]):
             for q in (0, 1):
                 for fname, fmt in SWEEP_FMTS.items():
-                    sk = "gaussian"
-                    if isinstance(fmt[1], tuple) or fmt[-1] == "srht":
-                        fmt, sk = fmt
-                    setting = (l, 32, q, fmt, sk)
+                    sk, orth = "gaussian", "cholqr2"
+                    if isinstance(fmt[0], tuple):
+                        fmt, sk, orth = (tuple(fmt) + ("cholqr2",))[:3]
+                    setting = (l, 32, q, fmt, sk, orth)
                     try:
                         ms, C, plan, ws = run_setting(lramm, A, B, setting, 5, 2)
                     except lramm.LrammError as e:
@@ -418,12 +452,11 @@ def main():
         p = args.p if args.p is not None else setting[1]
         fmt = tuple(args.fmt.split(",")) if args.fmt and "," in args.fmt else ((args.fmt,) * 4 if args.fmt
                                                                                 else setting[3])
-        setting = (args.l, p, args.q if args.q is not None else setting[2], fmt,
-                   args.sketch or (setting[4] if len(setting) > 4 else "gaussian"))
-    elif args.sketch:
-        setting = tuple(setting[:4]) + (args.sketch,)
-    l, p, q, fmt = setting[:4]
-    sketch = setting[4] if len(setting) > 4 else "gaussian"
+        setting = (args.l, p, args.q if args.q is not None else setting[2], fmt) + setting_parts(setting)[4:]
+    l, p, q, fmt, sketch, orth = setting_parts(setting)
+    sketch = args.sketch or sketch
+    orth = args.orth or orth
+    setting = (l, p, q, fmt, sketch, orth)
     r = l - p
 
     A, B, A64, B64, info = make_inputs(args.workload, tau, dev)
@@ -455,19 +488,27 @@ def main():
           f"{'bf16' if c_bytes == 2 else 'fp32'}, A = U diag(sigma) V^T, sigma_i = exp(-i/{tau:g})"
           f"{' + entrywise noise var 1e-4' if args.workload != 'target' else ''}, B ~ N(0,1); "
           f"l = {l} (r = {r}, p = {p}), q = {q}, formats {','.join(fmt)}, "
-          f"{'structured (SRHT)' if sketch == 'srht' else 'Gaussian'} test matrix from Philox seed {seed}")
+          f"{'structured (SRHT)' if sketch == 'srht' else 'Gaussian'} test matrix from Philox seed {seed}, "
+          f"{'one Cholesky QR pass' if orth == 'cholqr' else 'CholeskyQR2'} per orthonormalisation")
     out = {
         "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "ms_per_step_instrumented": ms_instr,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
         "data": "synthetic (seeded low-rank A with exponential singular-value decay, Gaussian B)",
         "config": {"workload": wl, "m": m, "n": n, "k": k, "tau": tau, "r": r, "p": p, "q": q, "l": l,
-                   "formats": list(fmt), "sketch": sketch, "io": "bf16" if c_bytes == 2 else "fp32"},
+                   "formats": list(fmt), "sketch": sketch, "orth": orth,
+                   "io": "bf16" if c_bytes == 2 else "fp32"},
         "stages_ms": {st: round(v[0], 5) for st, v in stage_ms.items()},
         "roofline": top,
         "kernels": kernels,
     }
 
+    if orth == "cholqr" and not args.no_other_decays:
+        # the same setting with CholeskyQR2, untimed by the line's value
+        ms2q, C2q, plan2q, ws2q = run_setting(lramm, A, B, setting[:5] + ("cholqr2",), args.steps, args.warmup, seed)
+        out["cholqr2_same_setting"] = {"ms_per_step": ms2q, "value": 2.0 * m * n * k / (ms2q * 1e-3) / 1e12}
+        C2q_keep = C2q
+        del plan2q, ws2q
     Cex = None
     if not args.no_error or not args.no_dense:
         Cex = exact_product(A64, B64)
@@ -477,6 +518,10 @@ def main():
         out["error"] = {"rel_fro_vs_exact": e, "max_abs_vs_exact": mx, "max_abs_exact": float(np.max(np.abs(Cex))),
                         "target_rel_fro": TARGET_RELF, "meets_target": e <= TARGET_RELF}
         out["error"].update(floors(info, r, l))
+        if "cholqr2_same_setting" in out:
+            out["cholqr2_same_setting"]["rel_fro_vs_exact"] = rel_errors(C2q_keep, Cex, nrm)[0]
+            out["error"]["rel_fro_one_pass_vs_cholqr2"] = float(
+                np.linalg.norm(Cg - C2q_keep.double().cpu().numpy()) / nrm)
     del C, plan, ws
     torch.cuda.empty_cache()
 
@@ -491,6 +536,13 @@ def main():
                              "roofline_ms": roof_ms}
         out["speedup_vs_dense_bf16"] = dms / ms_step
         out["speedup_vs_dense_bf16_roofline"] = roof_ms / ms_step
+        lib_d = dense_library(A if A.dtype == torch.bfloat16 else A.to(torch.bfloat16),
+                              B if B.dtype == torch.bfloat16 else B.to(torch.bfloat16))
+        lib_d["tflops"] = 2.0 * m * n * k / (lib_d["ms"] * 1e-3) / 1e12
+        out["dense_bf16_library"] = lib_d
+        out["speedup_vs_dense_bf16_library"] = lib_d["ms"] / ms_step
+        log(f"dense bf16: own kernel {dms:.3f} ms, library {lib_d['ms']:.3f} ms "
+            f"(NN {lib_d['ms_nn']:.3f}, NT {lib_d['ms_nt']:.3f})")
 
     if args.workload == "target" and not args.no_other_decays and args.tau is None and args.l is None:
         others = {}
@@ -503,13 +555,14 @@ def main():
             Cex2 = exact_product(A2_64, B2_64)
             e2, mx2, _ = rel_errors(C2, Cex2, float(np.linalg.norm(Cex2)))
             row = {"l": st[0], "p": st[1], "q": st[2], "formats": list(st[3]),
-                   "sketch": st[4] if len(st) > 4 else "gaussian", "ms_per_step": ms2,
+                   "sketch": setting_parts(st)[4], "orth": setting_parts(st)[5], "ms_per_step": ms2,
                    "value": 2.0 * m * n * k / (ms2 * 1e-3) / 1e12, "rel_fro_vs_exact": e2, "max_abs_vs_exact": mx2,
                    "reaches_target": reach and e2 <= TARGET_RELF}
             row.update(floors(info2, st[0] - st[1], st[0]))
             if "dense_bf16" in out:
                 row["speedup_vs_dense_bf16"] = out["dense_bf16"]["ms"] / ms2
                 row["speedup_vs_dense_bf16_roofline"] = out["dense_bf16"]["roofline_ms"] / ms2
+                row["speedup_vs_dense_bf16_library"] = out["dense_bf16_library"]["ms"] / ms2
             others[f"tau={t2_:g}"] = row
             del A2, B2, A2_64, B2_64, C2, plan2, ws2, Cex2
             torch.cuda.empty_cache()
@@ -523,7 +576,8 @@ def main():
         with threadpool_limits(limits=cores):
             used = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
             t = time.time()
-            ref = OL.lramm_forward(A64, B64, r, p, q, fmt, seed=seed, keep=False, sketch=sketch)
+            ref = OL.lramm_forward(A64, B64, r, p, q, fmt, seed=seed, keep=False, sketch=sketch,
+                                   one_pass=orth == "cholqr")
             dt = time.time() - t
         out["cpu_baseline"] = {"value": 2.0 * m * n * k / dt / 1e12, "unit": "TFLOP/s", "cores": used,
                                "kind": "oracle", "seconds": dt,

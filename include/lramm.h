@@ -121,7 +121,7 @@ typedef struct {
   int32_t reserved0;
   uint64_t seed;        /* Philox key when the caller passes no Omega      */
   float alpha, beta;
-  uint32_t flags;       /* LRAMM_PLAN_EXCLUSIVE | _SRHT | _ESTIMATE        */
+  uint32_t flags;       /* LRAMM_PLAN_EXCLUSIVE | _SRHT | _ESTIMATE | _ONE_PASS */
   uint32_t reserved1;
   /* Storage of A and B: 0 row-major as m x k (k x n), 1 stored as the
    * transpose, k x m (n x k) row-major.  C is always m x n row-major. */
@@ -155,6 +155,18 @@ typedef struct {
  * the projection), both in FP64 and deterministic, for
  * lramm_error_estimate. */
 #define LRAMM_PLAN_ESTIMATE 0x4u
+/* desc.flags: every orthonormalisation of the forward is one pass of
+ * Cholesky QR (Gram, Cholesky, triangular solve in FP64) instead of
+ * CholeskyQR2 -- the first of the two passes, with the same dependent-column
+ * rule.  Q still spans range(Y) exactly as far as the factorisation goes,
+ * but is orthonormal only to about 2^-53 cond(Y)^2 (Yamamoto, Nakatsukasa,
+ * Yanagisawa & Fukaya 2015, Thm. 3.3: ||Q^T Q - I||_2 <= (5/64) d^2 with
+ * d = 8 cond(Y) sqrt(m l u + l (l + 1) u) when d < 1), against the unit
+ * roundoff level of the second pass.  The paper's range finder (Sec. 2.2)
+ * asks only for an orthonormal basis of the sketch; a caller whose stage
+ * formats quantise Q to 2^-8 (bf16) or coarser loses nothing measurable
+ * while the sketch's condition number stays far below 2^26. */
+#define LRAMM_PLAN_ONE_PASS 0x8u
 
 typedef struct lramm_plan lramm_plan;   /* opaque, host memory */
 

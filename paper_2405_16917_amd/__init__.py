@@ -19,12 +19,13 @@ from ._lib import (  # noqa: F401
 
 
 def matmul(A, B, r, p=16, q=1, fmt=("int8",) * 4, seed=0, omega=None, alpha=1.0, beta=0.0, out=None,
-           out_dtype=None, return_plan=False, check=True, side="left", sketch="gaussian"):
+           out_dtype=None, return_plan=False, check=True, side="left", sketch="gaussian", orth="cholqr2"):
     """C ~ alpha A B + beta out by LRAMM (one-sided, rank l = r + p).
     ``side="right"`` sketches B instead of A.  A or B may be transposed views
     (e.g. ``W.t()``): they are passed as transposed storage, not copied.
     ``sketch="srht"``: the first sketch uses the structured (subsampled
-    randomised Hadamard) test matrix drawn from ``seed``.
+    randomised Hadamard) test matrix drawn from ``seed``.  ``orth="cholqr"``:
+    one Cholesky QR pass per orthonormalisation instead of CholeskyQR2.
 
     With ``check`` (the default) the device status word is read after the
     forward (this synchronises the stream): a non-finite input or a Cholesky
@@ -35,7 +36,7 @@ def matmul(A, B, r, p=16, q=1, fmt=("int8",) * 4, seed=0, omega=None, alpha=1.0,
     Bs, tb = storage(B)
     c_type = out.dtype if out is not None else (out_dtype or A.dtype)
     plan = LrammPlan(m, n, k, r, p, q, fmt, A.dtype, B.dtype, c_type, seed, alpha, beta, trans_a=ta, trans_b=tb,
-                     side=side, sketch=sketch)
+                     side=side, sketch=sketch, orth=orth)
     ws = plan.workspace(A.device)
     C = plan.forward(As, Bs, ws, C=out, omega=omega)
     if check:
@@ -79,11 +80,13 @@ class LRAMMConfig:
     """Settings of LRAMMFunction.  ``side``: "left" sketches A, "right"
     sketches B (a low-rank weight on the right of activations).  ``check``:
     read the device status word after each forward (synchronises the stream)
-    and raise LrammError on a non-finite input or an invalid Cholesky factor."""
+    and raise LrammError on a non-finite input or an invalid Cholesky factor.
+    ``orth``: "cholqr2" (two Cholesky QR passes) or "cholqr" (one)."""
 
     def __init__(self, r, p=16, q=1, fmt=("int8",) * 4, seed=0, omega=None, recompute=False, check=True,
-                 side="left", sketch="gaussian"):
+                 side="left", sketch="gaussian", orth="cholqr2"):
         self.r, self.p, self.q, self.fmt, self.seed, self.omega = r, p, q, fmt, seed, omega
+        self.orth = orth
         self.recompute = recompute
         self.check = check
         self.side = side
@@ -104,7 +107,7 @@ class LRAMMFunction(torch.autograd.Function):
         As, ta = storage(A)
         Bs, tb = storage(B)
         plan = LrammPlan(m, n, k, cfg.r, cfg.p, cfg.q, cfg.fmt, A.dtype, B.dtype, A.dtype, cfg.seed,
-                         trans_a=ta, trans_b=tb, side=cfg.side, sketch=cfg.sketch)
+                         trans_a=ta, trans_b=tb, side=cfg.side, sketch=cfg.sketch, orth=cfg.orth)
         ws = plan.workspace(A.device)
         C = plan.forward(As, Bs, ws, omega=cfg.omega)
         if cfg.check:

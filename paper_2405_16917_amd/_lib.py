@@ -25,6 +25,8 @@ FLAG_NONFINITE, FLAG_BREAKDOWN, FLAG_SQRTNEG, FLAG_STALL = 0x1, 0x2, 0x4, 0x8
 PLAN_EXCLUSIVE = 0x1
 PLAN_SRHT = 0x2
 PLAN_ESTIMATE = 0x4
+PLAN_ONE_PASS = 0x8
+ORTHS = {"cholqr2": 0, "cholqr": PLAN_ONE_PASS}
 SKETCHES = {"gaussian": 0, "srht": PLAN_SRHT}
 
 FMT = {"int8": INT8, "int4": INT4, "fp8": FP8, "bf16": BF16F}
@@ -324,18 +326,21 @@ class LrammPlan:
     """lramm_plan_create / lramm_forward / lramm_backward / lramm_factors /
     lramm_status_poll on one problem description.  A and B are passed as
     their storage: A row-major m x k (or k x m with trans_a), B k x n (or
-    n x k with trans_b); ``side`` "right" sketches B instead of A."""
+    n x k with trans_b); ``side`` "right" sketches B instead of A;
+    ``orth`` "cholqr" orthonormalises with one Cholesky QR pass instead of
+    CholeskyQR2 (LRAMM_PLAN_ONE_PASS)."""
 
     def __init__(self, m, n, k, r, p=16, q=1, fmt=("int8",) * 4, a_type=torch.float32,
                  b_type=torch.float32, c_type=torch.float32, seed=0, alpha=1.0, beta=0.0, exclusive=False,
-                 trans_a=False, trans_b=False, side="left", sketch="gaussian", estimate=False):
+                 trans_a=False, trans_b=False, side="left", sketch="gaussian", estimate=False, orth="cholqr2"):
         lib = load()
         d = Desc()
         d.m, d.n, d.k, d.r, d.p, d.q = m, n, k, r, p, q
         d.fmt_sketch, d.fmt_proj, d.fmt_g1, d.fmt_g2 = (_fmt(f) for f in fmt)
         d.a_type, d.b_type, d.c_type = DTYPE[a_type], DTYPE[b_type], DTYPE[c_type]
         d.seed, d.alpha, d.beta = seed, alpha, beta
-        d.flags = (PLAN_EXCLUSIVE if exclusive else 0) | SKETCHES[sketch] | (PLAN_ESTIMATE if estimate else 0)
+        d.flags = ((PLAN_EXCLUSIVE if exclusive else 0) | SKETCHES[sketch] | (PLAN_ESTIMATE if estimate else 0)
+                   | ORTHS[orth])
         d.trans_a, d.trans_b, d.side = int(bool(trans_a)), int(bool(trans_b)), SIDES[side]
         self.desc = d
         self.c_type = c_type

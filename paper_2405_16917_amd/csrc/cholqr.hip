@@ -2066,8 +2066,9 @@ static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t l
 
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
                             int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s,
-                            const TimingHook* hook, uint32_t* colmax, int chain_mode) {
+                            const TimingHook* hook, uint32_t* colmax, int chain_mode, int passes) {
   if (rows == 0 || l == 0) return LRAMM_OK;
+  if (passes != 1 && passes != 2) return LRAMM_E_INVALID;
   int lw, nc;
   int64_t rpc;
   cholqr_layout(rows, l, &lw, &nc, &rpc, ws_bytes);
@@ -2099,8 +2100,11 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   const int lt = (int)l;
   // pass 1 on Y (columns at or past l are never read): Q1 = Y L1^-T, written
   // into Q (columns lw .. ldq-1 zero), with its column maxima when asked
+  // (sliced copies that the second pass merges; one pass writes the
+  // caller's maxima directly)
   const int zero_to = (int)ldq;
-  uint32_t* cm1 = colmax ? w.cm1 : nullptr;
+  uint32_t* cm1 = colmax ? (passes == 1 ? colmax : w.cm1) : nullptr;
+  const int cm_stride = passes == 1 ? 0 : lw;
   // an odd block count leaves X's last row block to the solve, when its LDS
   // fits and the 32-row solve (faster than the last-block one) does not
   const int Tn1 = lw / NB;
@@ -2111,15 +2115,16 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
     LRAMM_TRY(gram<float>(rows, lw, lt, (const float*)Y, ldy, w, 0, s, hook));
     LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last, chain_mode));
     LRAMM_TRY((tsmul<float, false>(rows, lw, lt, (const float*)Y, ldy, w.X, Q, ldq, zero_to, s, hook, cm1, nullptr,
-                                   Ltri, Dlast, lw)));
+                                   Ltri, Dlast, cm_stride)));
   } else if (ytype == LRAMM_F64) {
     LRAMM_TRY(gram<double>(rows, lw, lt, (const double*)Y, ldy, w, 0, s, hook));
     LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last, chain_mode));
     LRAMM_TRY((tsmul<double, false>(rows, lw, lt, (const double*)Y, ldy, w.X, Q, ldq, zero_to, s, hook, cm1,
-                                    nullptr, Ltri, Dlast, lw)));
+                                    nullptr, Ltri, Dlast, cm_stride)));
   } else {
     return LRAMM_E_UNSUPPORTED;
   }
+  if (passes == 1) return LRAMM_OK;
   // pass 2 on Q1 (in place in Q): expansion of the near-identity factor, or
   // (gated) the full factor; skipped on the device when Q1 is already
   // orthonormal to the second pass's own accuracy (then the expansion kernel

@@ -294,11 +294,12 @@ enum ChainMode { CHAIN_OFF = 0, CHAIN_SHARED = 1, CHAIN_EXCLUSIVE = 2 };
 bool chain_admits(int64_t l, int compute_units, int chain_mode);
 
 // colmax (nullable, caller-zeroed, ldq entries): column maxima of fl32(|Q|)
-// as bit patterns, accumulated while Q is written.
+// as bit patterns, accumulated while Q is written.  passes = 1 stops after
+// the first Cholesky QR pass (Q = Y R1^-1).
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
                             int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s,
                             const TimingHook* hook = nullptr, uint32_t* colmax = nullptr,
-                            int chain_mode = CHAIN_SHARED);
+                            int chain_mode = CHAIN_SHARED, int passes = 2);
 size_t cholqr2_workspace(int64_t rows, int64_t l);
 // The least workspace CholeskyQR2 runs in (one row chunk of the Gram); with
 // less than cholqr2_workspace it uses fewer chunks.

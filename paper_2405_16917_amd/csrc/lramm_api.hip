@@ -46,6 +46,7 @@ struct lramm_plan {
   bool srht = false;        // structured first sketch (LRAMM_PLAN_SRHT)
   size_t off_srS = 0, off_srD = 0, off_srK = 0;
   bool estimate = false;    // a-posteriori error estimate (LRAMM_PLAN_ESTIMATE)
+  int passes = 2;           // Cholesky QR passes per orthonormalisation (1: LRAMM_PLAN_ONE_PASS)
   size_t off_norms = 0;     // ||A'||^2, ||Bt||^2, then the two partial arrays
   // zero-filled at the start of every forward: the status word, then the
   // column-maxima buffers of every column quantisation of the pass
@@ -241,7 +242,8 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   if (!valid_fmt(d.fmt_sketch) || !valid_fmt(d.fmt_proj) || !valid_fmt(d.fmt_g1) || !valid_fmt(d.fmt_g2))
     return LRAMM_E_UNSUPPORTED;
   if (!valid_io(d.a_type) || !valid_io(d.b_type) || !valid_io(d.c_type)) return LRAMM_E_UNSUPPORTED;
-  if (d.flags & ~(uint32_t)(LRAMM_PLAN_EXCLUSIVE | LRAMM_PLAN_SRHT | LRAMM_PLAN_ESTIMATE)) return LRAMM_E_INVALID;
+  if (d.flags & ~(uint32_t)(LRAMM_PLAN_EXCLUSIVE | LRAMM_PLAN_SRHT | LRAMM_PLAN_ESTIMATE | LRAMM_PLAN_ONE_PASS))
+    return LRAMM_E_INVALID;
   if (d.flags & LRAMM_PLAN_SRHT) {
     // the transform runs along rows of A' stored row-major, k' <= 32768
     const int at0 = desc->side ? 1 - desc->trans_b : desc->trans_a;
@@ -267,6 +269,7 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   p->chain_mode = (d.flags & LRAMM_PLAN_EXCLUSIVE) ? CHAIN_EXCLUSIVE : CHAIN_SHARED;
   p->srht = (d.flags & LRAMM_PLAN_SRHT) != 0;
   p->estimate = (d.flags & LRAMM_PLAN_ESTIMATE) != 0;
+  p->passes = (d.flags & LRAMM_PLAN_ONE_PASS) ? 1 : 2;
   p->l = l;
   p->lp = lp;
   const int64_t m = d.m, n = d.n, k = d.k;
@@ -580,7 +583,7 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   }
   if (P->side) LRAMM_HIP(hipEventRecord(P->ev_join, P->side));
   TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(0),
-                                   P->chain_mode));
+                                   P->chain_mode, P->passes));
   uint8_t* Qc = at<uint8_t>(W, P->off_Qc);
   float* sQc = at<float>(W, P->off_sQc);
   if (P->side) LRAMM_HIP(hipStreamWaitEvent(s, P->ev_join, 0));   // join: A_c and B_c ready
@@ -598,14 +601,14 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
       TIMED(ST_POWER_Z, launch_gemm_nt(k, l, m, d.fmt_proj, Ac, P->pAc, sAc, Qc, P->pQc, sQc, 1.0f, 0.0f, Z, lp,
                                        LRAMM_F32, nullptr, 0, split, sb, s));
     TIMED(ST_CHOLQR2, launch_cholqr2(k, l, Z, lp, LRAMM_F32, QZ, lp, cws, P->chol_bytes, flags, s, hk, mxQZ(it),
-                                     P->chain_mode));
+                                     P->chain_mode, P->passes));
     TIMED(ST_QUANT_QZ,
           launch_quantize(k, l, QZ, lp, LRAMM_F64, d.fmt_sketch, 1, QZc, P->pQZc, sQZc, flags, s, mxQZ(it), true));
     TIMED(ST_POWER_Y, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, pAr, sAr, QZc, P->pQZc, sQZc, 1.0f, 0.0f, Y, lp,
                                      LRAMM_F32, nullptr, 0, split, sb, s));
     TIMED(ST_CHOLQR2,
           launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(it + 1),
-                         P->chain_mode));
+                         P->chain_mode, P->passes));
   }
   // projection Bt = Q^T A  (l x k)
   float* Bt = at<float>(W, P->off_Bt);

@@ -76,7 +76,7 @@ def test_plan_validation(lib):
     assert _create(lib, _desc(L, r=0, p=0))[0] == L.E_RANK            # l < 1
     assert _create(lib, _desc(L, m=0))[0] == L.E_SHAPE
     assert _create(lib, _desc(L, fmt_g2=7))[0] == L.E_UNSUPPORTED
-    assert _create(lib, _desc(L, flags=8))[0] == L.E_INVALID
+    assert _create(lib, _desc(L, flags=16))[0] == L.E_INVALID
     # the error estimate: only for plans that form the norms
     code, h = _create(lib, _desc(L))
     out = (ctypes.c_double * 3)()
@@ -90,6 +90,10 @@ def test_plan_validation(lib):
     assert code == L.OK
     lib.lramm_plan_destroy(h)
     assert _create(lib, _desc(L, flags=L.PLAN_SRHT, trans_a=1))[0] == L.E_UNSUPPORTED
+    # one Cholesky QR pass: any combination with the other flags
+    code, h = _create(lib, _desc(L, flags=L.PLAN_ONE_PASS | L.PLAN_SRHT | L.PLAN_ESTIMATE | L.PLAN_EXCLUSIVE))
+    assert code == L.OK
+    lib.lramm_plan_destroy(h)
     assert _create(lib, _desc(L, k=200000))[0] == L.E_OVERFLOW        # K * 127^2 > 2^31
     assert lib.lramm_plan_create(None, None) == L.E_INVALID
 
@@ -151,7 +155,7 @@ def test_one_launch_cholesky_admission(lib):
     assert lib.lramm_chol_one_launch(2000, 256, 0) == 0
     # the plan accepts the exclusive flag and nothing else
     assert _create(lib, _desc(L, flags=L.PLAN_EXCLUSIVE))[0] == L.OK
-    assert _create(lib, _desc(L, flags=8))[0] == L.E_INVALID
+    assert _create(lib, _desc(L, flags=16))[0] == L.E_INVALID
     # the error estimate: only for plans that form the norms
     code, h = _create(lib, _desc(L))
     out = (ctypes.c_double * 3)()
