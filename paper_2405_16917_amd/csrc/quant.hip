@@ -387,6 +387,35 @@ __global__ __launch_bounds__(256) void quant_rows_reg_kernel(int64_t rows, int64
   }
 }
 
+// bf16 codes of a row-major matrix are the rounded values themselves (no
+// maxima, every scale 1): 8 elements of one row per thread over the padded
+// row, so that the grid covers every row with full wavefronts however few the
+// rows are; zero past cols.  A buffer of zero_words words is cleared on the
+// way, as in the row quantisers.
+template <typename T>
+__global__ __launch_bounds__(256) void bf16_rows_kernel(int64_t rows, int64_t cols, const T* __restrict__ X,
+                                                        int64_t ldx, uint8_t* __restrict__ Xq, int64_t pitch,
+                                                        int64_t pelems, float* __restrict__ scales, int vec,
+                                                        uint32_t* zero, int64_t zero_words) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < zero_words; e += (int64_t)gridDim.x * 256) zero[e] = 0u;
+  // 32-bit index arithmetic (the host checks that rows * pelems / 8 fits)
+  const uint32_t per_row = (uint32_t)(pelems / 8);
+  const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
+  if ((uint64_t)idx >= (uint64_t)rows * per_row) return;
+  const uint32_t rw = idx / per_row;
+  const int64_t row = rw;
+  const int64_t c0 = (int64_t)(idx - rw * per_row) * 8;
+  const T* xr = X + row * ldx;
+  uint8_t* qr = Xq + row * pitch;
+  float v[2][4];
+  bool live[2][4];
+  load4<T>(xr, c0, cols, vec != 0, v[0], live[0]);
+  load4<T>(xr, c0 + 4, cols, vec != 0, v[1], live[1]);
+  encode4<LRAMM_BF16F>(qr, c0, v[0], live[0], 1.0f);
+  encode4<LRAMM_BF16F>(qr, c0 + 4, v[1], live[1], 1.0f);
+  if (c0 == 0) scales[row] = 1.0f;
+}
+
 // ---------------------------------------------------------------- launch --
 
 template <typename T, int FMT>
@@ -399,6 +428,13 @@ static lramm_status quantize_typed(int64_t rows, int64_t cols, const T* X, int64
     bool vec = ((uintptr_t)X % (4 * sizeof(T)) == 0) && (ldx % 4 == 0);
     dim3 grid((unsigned)ceil_div(rows, 4));
     const int v = vec ? 1 : 0;
+    if (FMT == LRAMM_BF16F && rows * (pe / 8) < ((int64_t)1 << 31)) {
+      const int64_t threads = rows * (pe / 8);
+      hipLaunchKernelGGL((bf16_rows_kernel<T>), dim3((unsigned)ceil_div(threads, (int64_t)256)), dim3(256), 0, s,
+                         rows, cols, X, ldx, Xq, pitch, pe, scales, v, zero, zero_words);
+      LRAMM_HIP(hipGetLastError());
+      return LRAMM_OK;
+    }
     const int64_t groups = ceil_div(pe, (int64_t)256);   // 4-element groups per lane
 #define ROWS_REG(NV)                                                                                            \
   hipLaunchKernelGGL((quant_rows_reg_kernel<T, FMT, NV>), grid, dim3(256), 0, s, rows, cols, X, ldx, Xq, pitch, pe, \
@@ -433,6 +469,15 @@ static lramm_status quantize_typed(int64_t rows, int64_t cols, const T* X, int64
     dim3 g2((unsigned)ceil_div(cols, 64), (unsigned)(pe / 64));
     hipLaunchKernelGGL((quant_cols_t_kernel<T, FMT>), g2, dim3(256), 0, s, rows, cols, X, ldx, amax_ws, Xq, pitch,
                        scales, flags, cvec);
+    LRAMM_HIP(hipGetLastError());
+    return LRAMM_OK;
+  }
+  if constexpr (FMT == LRAMM_BF16F) {
+    // no maxima: the transposing pass writes the codes and the unit scales
+    int64_t pe = pitch_elems(pitch, FMT);
+    dim3 g2((unsigned)ceil_div(cols, 64), (unsigned)(pe / 64));
+    hipLaunchKernelGGL((quant_cols_t_kernel<T, FMT>), g2, dim3(256), 0, s, rows, cols, X, ldx,
+                       (const uint32_t*)nullptr, Xq, pitch, scales, flags, cvec);
     LRAMM_HIP(hipGetLastError());
     return LRAMM_OK;
   }

@@ -84,6 +84,8 @@ __global__ __launch_bounds__(256) void srht_keys_kernel(uint64_t seed, int kp, u
   if (lane < 2 && base + 32 * lane < kp) sign_bits[(base >> 5) + lane] = (uint32_t)(mask >> (32 * lane));
 }
 
+// C = the keys per thread, max(1, k' / 1024).
+template <int C>
 __global__ __launch_bounds__(kSelThreads) void srht_samples_kernel(int kp, int l, const uint32_t* __restrict__ keys,
                                                                  int32_t* __restrict__ S) {
   __shared__ uint32_t hist[256];
@@ -94,15 +96,15 @@ __global__ __launch_bounds__(kSelThreads) void srht_samples_kernel(int kp, int l
     s_prefix = 0;
     s_rank = (uint32_t)l;   // 1-based rank of the threshold key
   }
-  // this thread's indices: [t c, t c + c) of [0, kp), c a power of two
-  // <= 32 (live marks the ones in range)
-  const int c = (kp + kSelThreads - 1) / kSelThreads;
-  uint32_t u[32];
+  // this thread's indices: [t C, t C + C) of [0, kp) (live marks the ones
+  // in range: all of them unless k' < 1024)
+  constexpr int c = C;
+  uint32_t u[C];
   uint32_t live = 0;
 #pragma unroll
-  for (int j = 0; j < 32; ++j) {
+  for (int j = 0; j < C; ++j) {
     const int i = t * c + j;
-    const bool in = j < c && i < kp;
+    const bool in = i < kp;
     u[j] = in ? keys[i] : 0xffffffffu;
     if (in) live |= 1u << j;
   }
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(kSelThreads) void srht_samples_kernel(int kp, int l
     const uint32_t pre = s_prefix;
     const uint32_t hi_mask = shift == 24 ? 0u : (0xffffffffu << (shift + 8));
 #pragma unroll
-    for (int j = 0; j < 32; ++j)
+    for (int j = 0; j < C; ++j)
       if (((live >> j) & 1u) && (u[j] & hi_mask) == pre) atomicAdd(&hist[(u[j] >> shift) & 255u], 1u);
     __syncthreads();
     if (t < 64) {
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(kSelThreads) void srht_samples_kernel(int kp, int l
   const uint32_t T = s_prefix, take_eq = s_rank;
   uint32_t nlt = 0, neq = 0;
 #pragma unroll
-  for (int j = 0; j < 32; ++j)
+  for (int j = 0; j < C; ++j)
     if ((live >> j) & 1u) {
       nlt += u[j] < T ? 1u : 0u;
       neq += u[j] == T ? 1u : 0u;
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(kSelThreads) void srht_samples_kernel(int kp, int l
   const uint32_t eq_before = block_scan_incl(neq, wsum) - neq;
   uint32_t eq_seen = eq_before, kept = 0;
 #pragma unroll
-  for (int j = 0; j < 32; ++j)
+  for (int j = 0; j < C; ++j)
     if (((live >> j) & 1u) && u[j] == T) {
       if (eq_seen < take_eq) ++kept;
       ++eq_seen;
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(kSelThreads) void srht_samples_kernel(int kp, int l
   uint32_t pos = block_scan_incl(mine, wsum) - mine;
   eq_seen = eq_before;
 #pragma unroll
-  for (int j = 0; j < 32; ++j) {
+  for (int j = 0; j < C; ++j) {
     if (!((live >> j) & 1u)) continue;
     bool sel = u[j] < T;
     if (u[j] == T) {
@@ -292,7 +294,18 @@ lramm_status launch_srht_samples(uint64_t seed, int64_t k, int64_t l, int32_t* S
   hipLaunchKernelGGL(srht_keys_kernel, dim3((unsigned)ceil_div(kp, (int64_t)256)), dim3(256), 0, s, seed, (int)kp,
                      keys, sign_bits);
   LRAMM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(srht_samples_kernel, dim3(1), dim3(kSelThreads), 0, s, (int)kp, (int)l, keys, S);
+  const int c = kp >= kSelThreads ? (int)(kp / kSelThreads) : 1;
+#define SAMPLES(C) \
+  hipLaunchKernelGGL(srht_samples_kernel<C>, dim3(1), dim3(kSelThreads), 0, s, (int)kp, (int)l, keys, S)
+  switch (c) {
+    case 1: SAMPLES(1); break;
+    case 2: SAMPLES(2); break;
+    case 4: SAMPLES(4); break;
+    case 8: SAMPLES(8); break;
+    case 16: SAMPLES(16); break;
+    default: SAMPLES(32); break;
+  }
+#undef SAMPLES
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }
