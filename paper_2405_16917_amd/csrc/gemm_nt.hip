@@ -147,6 +147,7 @@ struct TileLoader {
   static constexpr int kPerThread = (kVecs + 255) / 256;
   static constexpr int kStageBytes = KIND == KIND_I4 ? kStage / 2 : kStage;   // global bytes per stage
   uint4 r[kPerThread];
+  uint32_t m;   // all ones, or zero when the stage's vector lies past the padded K
 
   // Per-lane offsets: row part (clamped row: results of rows past the end
   // are discarded) and the vector's byte offset inside a stage.
@@ -172,12 +173,13 @@ struct TileLoader {
 
   // MASK: the stage may reach past the padded K (only the last one can);
   // those vectors are loaded from the stage's start in the row (in bounds)
-  // and zeroed.  Both forms are straight-line code.
+  // and zeroed when stored to LDS, so that nothing waits for the loaded data
+  // before the store that needs it anyway.  Both forms are straight-line code.
   template <bool MASK>
   __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, const Offsets& o, int st, int64_t kw64, int tid) {
     const int kw = (int)kw64;
     const int so = st * kStageBytes;
-    uint32_t m = 0xffffffffu;
+    m = 0xffffffffu;
     int vec = o.vec;
     if constexpr (MASK) {
       const bool in = st * kStage + o.wvec < kw;
@@ -191,8 +193,7 @@ struct TileLoader {
       if (kVecs % 256 == 0 || v < kVecs) {
         typedef unsigned int v4u __attribute__((ext_vector_type(4)));
         const v4u x = __builtin_amdgcn_raw_buffer_load_b128(rs, o.row[i] + vec, so, 0);
-        if constexpr (MASK) r[i] = make_uint4(x[0] & m, x[1] & m, x[2] & m, x[3] & m);
-        else r[i] = make_uint4(x[0], x[1], x[2], x[3]);
+        r[i] = make_uint4(x[0], x[1], x[2], x[3]);
       }
     }
   }
@@ -204,14 +205,15 @@ struct TileLoader {
       if (kVecs % 256 == 0 || v < kVecs) {
         const int row = v / kVecPerRow;
         const int c = v % kVecPerRow;
+        const uint4 x = make_uint4(r[i].x & m, r[i].y & m, r[i].z & m, r[i].w & m);
         if constexpr (KIND == KIND_I4) {
-          uint2 a = widen_int4(r[i].x), b = widen_int4(r[i].y);
-          uint2 cc = widen_int4(r[i].z), d = widen_int4(r[i].w);
+          uint2 a = widen_int4(x.x), b = widen_int4(x.y);
+          uint2 cc = widen_int4(x.z), d = widen_int4(x.w);
           uint4* dst = reinterpret_cast<uint4*>(lds + row * kLdsPitch + c * 32);
           dst[0] = make_uint4(a.x, a.y, b.x, b.y);
           dst[1] = make_uint4(cc.x, cc.y, d.x, d.y);
         } else {
-          *reinterpret_cast<uint4*>(lds + row * kLdsPitch + c * 16) = r[i];
+          *reinterpret_cast<uint4*>(lds + row * kLdsPitch + c * 16) = x;
         }
       }
     }
@@ -993,7 +995,12 @@ static Plan plan_gemm(int64_t M, int64_t N, int64_t K, int fmt, bool allow_split
   p.tiles_n = (int)ceil_div(N, p.bn);
   const int tiles = p.tiles_m * p.tiles_n;
   p.split = 1;
-  if (allow_split && tiles < 128) {
+  if (allow_split && tiles >= 128 && tiles <= 256 && p.nst >= 64) {
+    // one round of at most one workgroup per CU over a long K (l x n
+    // products with K = 8192): two K slices give every CU two workgroups
+    // (416 x 8192 x 8192 bf16: 108 against 122 us, partial sums included)
+    p.split = 2;
+  } else if (allow_split && tiles < 128) {
     // too few tiles to occupy half of the 256 CUs and a long K: split K as
     // far as one round of 512 workgroups allows, each slice keeping at least
     // 4 stages; the partials are summed in a second pass.  From 128 tiles on

@@ -346,6 +346,7 @@ lramm_status lramm_plan_create(const lramm_desc* desc, lramm_plan** out) {
   t = gemm_nt_workspace(k, l, m, d.fmt_proj); sb = t > sb ? t : sb;
   t = gemm_nt_workspace(l, k, m, d.fmt_proj); sb = t > sb ? t : sb;
   t = gemm_nt_workspace(n, l, k, d.fmt_g1); sb = t > sb ? t : sb;
+  t = gemm_nt_workspace(l, n, k, d.fmt_g1); sb = t > sb ? t : sb;   // G1 as T = Bt B
   t = gemm_nt_workspace(m, n, l, d.fmt_g2); sb = t > sb ? t : sb;
   t = gemm_nt_workspace(n, m, l, d.fmt_g2); sb = t > sb ? t : sb;   // C' written transposed
   p->split_bytes = sb;

@@ -168,7 +168,9 @@ def _pack(codes, fmt, K):
                                  # 128 x 64 and 64 x 128 tiles (skinny products at l = 272)
                                  (8192, 272, 1024), (272, 8192, 1024), (8192, 448, 640), (448, 8192, 520),
                                  # 256 x 256 tiles with 64-byte stages: whole and ragged M, N, K
-                                 (4096, 4096, 2048), (4100, 4000, 2100)])
+                                 (4096, 4096, 2048), (4100, 4000, 2100),
+                                 # one round of 128 .. 256 tiles over a long K: two K slices
+                                 (416, 8192, 8192), (450, 4000, 8200)])
 def test_gemm_int_bit_exact(lib, fmt, MNK):
     M, N, K = MNK
     rng = np.random.default_rng(M * 7 + N * 11 + K)
@@ -205,7 +207,8 @@ def test_gemm_alpha_beta_and_bf16_out(lib):
     assert np.array_equal(Cb.float().cpu().numpy().astype(np.float64), refb)
 
 
-@pytest.mark.parametrize("MNK", [(64, 64, 64), (100, 37, 257), (512, 512, 2048), (4100, 4000, 2100)])
+@pytest.mark.parametrize("MNK", [(64, 64, 64), (100, 37, 257), (512, 512, 2048), (4100, 4000, 2100),
+                                 (416, 8192, 8192)])
 def test_gemm_bf16_operands(lib, MNK):
     M, N, K = MNK
     rng = np.random.default_rng(K)

@@ -92,6 +92,9 @@ SRHT_CASES = [
     (640, 384, 512, 100, 12, 0, 40.0, ("int8", "int8", "int4", "int4"), "fp32"),
     (1024, 2048, 512, 112, 16, 0, 64.0, ("bf16",) * 4, "bf16"),
     (2048, 4096, 512, 240, 16, 0, 64.0, ("bf16",) * 4, "bf16"),
+    # the projection and G1 read A and B in place over K = 4096 and 6144 in
+    # two K slices (144 tiles each)
+    (4096, 6144, 6144, 368, 16, 0, 64.0, ("bf16",) * 4, "bf16"),
 ]
 
 
