@@ -2017,9 +2017,13 @@ static lramm_status cholesky_inverse(int lw, int l_true, const CholWs& w, uint32
 }
 
 // Whether the tall-skinny product takes 32 rows per workgroup (RB = 2): the
-// staged panel of 32 rows and the W tiles fit LDS.
-static bool ts_two_halves(int lw) {
-  return (size_t)2 * TS_ROWS * ts_pitch(lw) * sizeof(double) + ts_stage_lds() <= (size_t)160 * 1024;
+// staged panel of 32 rows and the W tiles fit LDS, and 32-row workgroups
+// still cover every CU (8192 x 416: 60 -> 49 us per solve with 32 rows;
+// 4096 x 288: 22 us with 16 rows against 27 with 32).
+static bool ts_two_halves(int64_t rows, int lw) {
+  const int cus = device_compute_units();
+  return (size_t)2 * TS_ROWS * ts_pitch(lw) * sizeof(double) + ts_stage_lds() <= (size_t)160 * 1024 &&
+         ceil_div(rows, (int64_t)(2 * TS_ROWS)) >= (cus > 0 ? cus : 256);
 }
 
 template <typename T, bool ADD>
@@ -2043,7 +2047,7 @@ static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t l
   const int vec = ((uintptr_t)X % (4 * sizeof(T)) == 0 && ldx % 4 == 0) ? 1 : 0;
   // 32 rows per workgroup when their panel and the W tiles fit
   const size_t shm2 = (size_t)2 * TS_ROWS * ts_pitch(lw) * sizeof(double);
-  if (!Ltri && ts_two_halves(lw)) {
+  if (!Ltri && ts_two_halves(rows, lw)) {
     const dim3 grid2((unsigned)ceil_div(rows, (int64_t)(2 * TS_ROWS)));
     hipLaunchKernelGGL((tsmul_kernel<T, ADD, true, 2>), grid2, dim3(TS_WAVES * 64), shm2 + ts_stage_lds(), s, rows,
                        lw, ncols, X, ldx, W, Q, ldq, zero_to, vec, colmax, cm_stride, gate, Ltri, Dlast);
@@ -2108,7 +2112,7 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   // an odd block count leaves X's last row block to the solve, when its LDS
   // fits and the 32-row solve (faster than the last-block one) does not
   const int Tn1 = lw / NB;
-  const bool solve_last = (Tn1 % 2 == 1) && ts_solve_last_lds(lw) <= 160 * 1024 && !ts_two_halves(lw);
+  const bool solve_last = (Tn1 % 2 == 1) && ts_solve_last_lds(lw) <= 160 * 1024 && !ts_two_halves(rows, lw);
   const double* Ltri = solve_last ? w.L : nullptr;
   const double* Dlast = solve_last ? w.Dinv + (size_t)(Tn1 - 1) * NB * NB : nullptr;
   if (ytype == LRAMM_F32) {

@@ -428,12 +428,16 @@ static lramm_status quantize_typed(int64_t rows, int64_t cols, const T* X, int64
     bool vec = ((uintptr_t)X % (4 * sizeof(T)) == 0) && (ldx % 4 == 0);
     dim3 grid((unsigned)ceil_div(rows, 4));
     const int v = vec ? 1 : 0;
-    if (FMT == LRAMM_BF16F && rows * (pe / 8) < ((int64_t)1 << 31)) {
-      const int64_t threads = rows * (pe / 8);
-      hipLaunchKernelGGL((bf16_rows_kernel<T>), dim3((unsigned)ceil_div(threads, (int64_t)256)), dim3(256), 0, s,
-                         rows, cols, X, ldx, Xq, pitch, pe, scales, v, zero, zero_words);
-      LRAMM_HIP(hipGetLastError());
-      return LRAMM_OK;
+    // FP64 rows (Q for G2) stay on the register kernel: 7.5 against 8.9 us
+    // for 8192 x 416
+    if constexpr (FMT == LRAMM_BF16F && sizeof(T) <= 4) {
+      if (rows * (pe / 8) < ((int64_t)1 << 31)) {
+        const int64_t threads = rows * (pe / 8);
+        hipLaunchKernelGGL((bf16_rows_kernel<T>), dim3((unsigned)ceil_div(threads, (int64_t)256)), dim3(256), 0, s,
+                           rows, cols, X, ldx, Xq, pitch, pe, scales, v, zero, zero_words);
+        LRAMM_HIP(hipGetLastError());
+        return LRAMM_OK;
+      }
     }
     const int64_t groups = ceil_div(pe, (int64_t)256);   // 4-element groups per lane
 #define ROWS_REG(NV)                                                                                            \

@@ -205,17 +205,26 @@ __device__ __forceinline__ void srht_load_vec(const T* p, float x[EPT]) {
 
 __device__ __forceinline__ int lds_at(int i) { return i + (i >> 5); }
 
-template <typename T, int EPT>
-__global__ __launch_bounds__(1024) void srht_kernel(int64_t k, int kp, int l, const T* __restrict__ A, int64_t lda,
+// Elements per thread for k' = 2^P: 32 from k' = 8192 on (256 .. 1024
+// threads), else k' / 256 (at least 2).
+constexpr int srht_ept(int P) { return P >= 13 ? 32 : P == 12 ? 16 : P == 11 ? 8 : P == 10 ? 4 : 2; }
+
+// P = log2 k' is a template parameter, so every LDS round below is
+// straight-line code: its index bits, element counts and (for rounds above
+// bit 5) its LDS strides are constants.
+template <typename T, int P>
+__global__ __launch_bounds__(1024) void srht_kernel(int64_t k, int l, const T* __restrict__ A, int64_t lda,
                                                     const uint32_t* __restrict__ sign_bits,
                                                     const int32_t* __restrict__ S, float scale, float* __restrict__ Y,
                                                     int64_t ldy) {
   extern __shared__ float buf[];
+  constexpr int kp = 1 << P;
+  constexpr int EPT = srht_ept(P);
   constexpr int E = EPT == 2 ? 1 : EPT == 4 ? 2 : EPT == 8 ? 3 : EPT == 16 ? 4 : 5;
   static_assert((1 << E) == EPT, "EPT is a power of two in 2 .. 32");
   constexpr int RW = E < 4 ? E : 4;   // index bits per LDS round (at most 16 registers)
   constexpr int RN = 1 << RW;
-  const int nt = blockDim.x;
+  constexpr int nt = kp / EPT;
   const int t = threadIdx.x;
   const int64_t row = blockIdx.x;
   const T* a = A + row * lda;
@@ -248,25 +257,28 @@ __global__ __launch_bounds__(1024) void srht_kernel(int64_t k, int kp, int l, co
         x[j] = u + w;
         x[j + s] = u - w;
       }
-  int p = 0;
-  while ((1 << p) < kp) ++p;
   // LDS holds element i at i + i / 32: the 32-element runs of consecutive
   // threads then start in different banks
 #pragma unroll
   for (int j = 0; j < EPT; ++j) buf[lds_at(i0 + j)] = x[j];
   __syncthreads();
-  // the remaining bits [E, p) in rounds of w <= RW bits
-  for (int b = E; b < p; b += RW) {
-    const int w = (p - b) < RW ? (p - b) : RW;
+  // the remaining bits [E, P) in rounds of w <= RW bits
+#pragma unroll
+  for (int b = E; b < P; b += RW) {
+    const int w = (P - b) < RW ? (P - b) : RW;
     const int n = 1 << w;
     const int groups = EPT >> w;
+#pragma unroll
     for (int g = 0; g < groups; ++g) {
       const int o = g * nt + t;
       const int base = (o & ((1 << b) - 1)) | ((o >> b) << (b + w));
+      // from bit 5 on, element base + (v << b) sits at lds_at(base) plus v
+      // times a constant stride
+      const int a0 = lds_at(base);
       float y[RN];
 #pragma unroll
       for (int v = 0; v < RN; ++v)
-        if (v < n) y[v] = buf[lds_at(base + (v << b))];
+        if (v < n) y[v] = buf[b >= 5 ? a0 + v * ((1 << b) + (1 << (b - 5))) : lds_at(base + (v << b))];
 #pragma unroll
       for (int s = 1; s < RN; s <<= 1)
 #pragma unroll
@@ -278,7 +290,7 @@ __global__ __launch_bounds__(1024) void srht_kernel(int64_t k, int kp, int l, co
           }
 #pragma unroll
       for (int v = 0; v < RN; ++v)
-        if (v < n) buf[lds_at(base + (v << b))] = y[v];
+        if (v < n) buf[b >= 5 ? a0 + v * ((1 << b) + (1 << (b - 5))) : lds_at(base + (v << b))] = y[v];
     }
     __syncthreads();
   }
@@ -310,20 +322,20 @@ lramm_status launch_srht_samples(uint64_t seed, int64_t k, int64_t l, int32_t* S
   return LRAMM_OK;
 }
 
-template <typename T, int EPT>
-static lramm_status launch_srht_t(int64_t m, int64_t k, int kp, int l, const T* A, int64_t lda,
-                                  const uint32_t* sign_bits, const int32_t* S, float scale, float* Y, int64_t ldy,
-                                  hipStream_t s) {
-  const int nt = kp / EPT;
+template <typename T, int P>
+static lramm_status launch_srht_t(int64_t m, int64_t k, int l, const T* A, int64_t lda, const uint32_t* sign_bits,
+                                  const int32_t* S, float scale, float* Y, int64_t ldy, hipStream_t s) {
+  constexpr int kp = 1 << P;
+  constexpr int nt = kp / srht_ept(P);
   const size_t shm = (size_t)(kp + kp / 32 + 1) * sizeof(float);
   static bool attr_set = false;
   if (!attr_set) {   // rows up to 132 KiB in LDS
-    LRAMM_HIP(hipFuncSetAttribute((const void*)srht_kernel<T, EPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    LRAMM_HIP(hipFuncSetAttribute((const void*)srht_kernel<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)((kSrhtMaxK + kSrhtMaxK / 32 + 1) * sizeof(float))));
     attr_set = true;
   }
-  hipLaunchKernelGGL((srht_kernel<T, EPT>), dim3((unsigned)m), dim3(nt), shm, s, k, kp, l, A, lda, sign_bits, S,
-                     scale, Y, ldy);
+  hipLaunchKernelGGL((srht_kernel<T, P>), dim3((unsigned)m), dim3(nt), shm, s, k, l, A, lda, sign_bits, S, scale, Y,
+                     ldy);
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }
@@ -332,13 +344,14 @@ template <typename T>
 static lramm_status launch_srht_type(int64_t m, int64_t k, int kp, int l, const T* A, int64_t lda,
                                      const uint32_t* sign_bits, const int32_t* S, float scale, float* Y, int64_t ldy,
                                      hipStream_t s) {
-  // 32 elements per thread from k' = 8192 on (256 .. 1024 threads), 256
-  // threads below that (at least 2 elements each)
-  if (kp >= 8192) return launch_srht_t<T, 32>(m, k, kp, l, A, lda, sign_bits, S, scale, Y, ldy, s);
-  if (kp == 4096) return launch_srht_t<T, 16>(m, k, kp, l, A, lda, sign_bits, S, scale, Y, ldy, s);
-  if (kp == 2048) return launch_srht_t<T, 8>(m, k, kp, l, A, lda, sign_bits, S, scale, Y, ldy, s);
-  if (kp == 1024) return launch_srht_t<T, 4>(m, k, kp, l, A, lda, sign_bits, S, scale, Y, ldy, s);
-  return launch_srht_t<T, 2>(m, k, kp, l, A, lda, sign_bits, S, scale, Y, ldy, s);
+  switch (kp) {
+#define SRHT_P(P) \
+  case 1 << P: return launch_srht_t<T, P>(m, k, l, A, lda, sign_bits, S, scale, Y, ldy, s);
+    SRHT_P(1) SRHT_P(2) SRHT_P(3) SRHT_P(4) SRHT_P(5) SRHT_P(6) SRHT_P(7) SRHT_P(8)
+    SRHT_P(9) SRHT_P(10) SRHT_P(11) SRHT_P(12) SRHT_P(13) SRHT_P(14) SRHT_P(15)
+#undef SRHT_P
+    default: return LRAMM_E_UNSUPPORTED;
+  }
 }
 
 lramm_status launch_srht(int64_t m, int64_t k, int64_t l, const void* A, int64_t lda, int a_type,
