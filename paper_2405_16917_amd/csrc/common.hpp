@@ -256,8 +256,9 @@ int64_t omega_quant_max_k();
 // Y (m x l, ldy) = (A_pad D H)[:, S] / sqrt(l) from A (m x k row-major, FP32
 // or BF16), one workgroup per row.
 int64_t srht_padded(int64_t k);
+// zero (nullable): zero_words words cleared by the first launch on the way.
 lramm_status launch_srht_samples(uint64_t seed, int64_t k, int64_t l, int32_t* S, uint32_t* sign_bits,
-                                 uint32_t* keys, hipStream_t s);
+                                 uint32_t* keys, hipStream_t s, uint32_t* zero = nullptr, int64_t zero_words = 0);
 lramm_status launch_srht(int64_t m, int64_t k, int64_t l, const void* A, int64_t lda, int a_type,
                          const uint32_t* sign_bits, const int32_t* S, float* Y, int64_t ldy, hipStream_t s);
 

@@ -489,22 +489,26 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   hipStream_t s2 = P->side ? P->side : s;
   // the status word and the column-maxima accumulators start at zero: one
   // fill on s before any kernel that may set a flag (the side stream forks
-  // after it)
-  LRAMM_TRY(fill_u32(zero, 0u, (int64_t)P->zero_words, s));
+  // after it).  Without power iterations nothing precedes the structured
+  // sketch on the main stream, so its samples go there directly (no event
+  // hop), and their first launch clears the zero region instead of a fill.
+  const bool srht_main = P->srht && d.q == 0;
+  if (!srht_main) LRAMM_TRY(fill_u32(zero, 0u, (int64_t)P->zero_words, s));
+  int32_t* srS = P->srht ? at<int32_t>(W, P->off_srS) : nullptr;
+  uint32_t* srD = P->srht ? at<uint32_t>(W, P->off_srD) : nullptr;
+  if (srht_main)
+    TIMED(ST_OMEGA, launch_srht_samples(d.seed, k, l, srS, srD, at<uint32_t>(W, P->off_srK), s, zero,
+                                        (int64_t)P->zero_words));
   if (P->side) {
     LRAMM_HIP(hipEventRecord(P->ev_fork, s));
     LRAMM_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
   }
-  int32_t* srS = P->srht ? at<int32_t>(W, P->off_srS) : nullptr;
-  uint32_t* srD = P->srht ? at<uint32_t>(W, P->off_srD) : nullptr;
-  // without power iterations nothing precedes the structured sketch on the
-  // main stream, so its samples go there directly (no event hop)
-  const bool srht_main = P->srht && d.q == 0;
   if (P->srht) {
-    // the sample set and the sign mask
-    hipStream_t so = srht_main ? s : s2;
-    TIMED_ON(so, ST_OMEGA, launch_srht_samples(d.seed, k, l, srS, srD, at<uint32_t>(W, P->off_srK), so));
-    if (P->side && !srht_main) LRAMM_HIP(hipEventRecord(P->ev_omega, P->side));
+    if (!srht_main) {
+      // the sample set and the sign mask, beside A's row codes
+      TIMED_ON(s2, ST_OMEGA, launch_srht_samples(d.seed, k, l, srS, srD, at<uint32_t>(W, P->off_srK), s2));
+      if (P->side) LRAMM_HIP(hipEventRecord(P->ev_omega, P->side));
+    }
   } else if (!omega) {
     if (d.fmt_sketch == LRAMM_BF16F || k <= omega_quant_max_k()) {
       // generated and quantised in one pass
@@ -613,8 +617,16 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   }
   // projection Bt = Q^T A  (l x k)
   float* Bt = at<float>(W, P->off_Bt);
-  TIMED(ST_QUANT_Q_COLS,
-        launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s, mxQ(d.q), true));
+  // bf16 projection and G2: Q's transposed and row codes from one read of Q
+  // (no maxima; the G2 codes are formed before they are needed)
+  const bool q_both = d.fmt_proj == LRAMM_BF16F && d.fmt_g2 == LRAMM_BF16F;
+  if (q_both)
+    TIMED(ST_QUANT_Q_COLS, launch_quantize_both(m, l, Q, lp, LRAMM_F64, LRAMM_BF16F, at<uint8_t>(W, P->off_Qr),
+                                                P->pQr, at<float>(W, P->off_sQr), Qc, P->pQc, sQc, nullptr, nullptr,
+                                                flags, s));
+  else
+    TIMED(ST_QUANT_Q_COLS,
+          launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s, mxQ(d.q), true));
   if (km_a)
     TIMED(ST_PROJ, launch_gemm_nt(l, k, m, d.fmt_proj, Qc, P->pQc, sQc, A, lda * 2, sAc, 1.0f, 0.0f, Bt, k,
                                   LRAMM_F32, nullptr, 0, split, sb, s, false, 2));
@@ -642,7 +654,7 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   float* sQr = at<float>(W, P->off_sQr);
   uint8_t* Ttq = at<uint8_t>(W, P->off_Ttq);
   float* sTt = at<float>(W, P->off_sTt);
-  TIMED(ST_QUANT_Q_ROWS, launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_g2, 0, Qr, P->pQr, sQr, flags, s));
+  if (!q_both) TIMED(ST_QUANT_Q_ROWS, launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_g2, 0, Qr, P->pQr, sQr, flags, s));
   if (km_b)   // the rows of T^T are the columns of T
     TIMED(ST_QUANT_TT, launch_quantize(l, n, Tt, n, LRAMM_F32, d.fmt_g2, 1, Ttq, P->pTtq, sTt, flags, s));
   else

@@ -585,6 +585,8 @@ lramm_status launch_quantize_both(int64_t rows, int64_t cols, const void* X, int
       return quantize_both_fmt<float>(rows, cols, (const float*)X, ldx, fmt, rq, rpitch, rscales, cq, cpitch, cscales, rmax, cmax, flags, s);
     case LRAMM_BF16:
       return quantize_both_fmt<uint16_t>(rows, cols, (const uint16_t*)X, ldx, fmt, rq, rpitch, rscales, cq, cpitch, cscales, rmax, cmax, flags, s);
+    case LRAMM_F64:
+      return quantize_both_fmt<double>(rows, cols, (const double*)X, ldx, fmt, rq, rpitch, rscales, cq, cpitch, cscales, rmax, cmax, flags, s);
     default:
       return LRAMM_E_INVALID;
   }

@@ -69,7 +69,10 @@ __device__ __forceinline__ uint32_t block_scan_incl(uint32_t v, uint32_t* wsum) 
 }
 
 __global__ __launch_bounds__(256) void srht_keys_kernel(uint64_t seed, int kp, uint32_t* __restrict__ keys,
-                                                        uint32_t* __restrict__ sign_bits) {
+                                                        uint32_t* __restrict__ sign_bits, uint32_t* zero,
+                                                        int64_t zero_words) {
+  // a buffer of zero_words words cleared on the way (saves the caller a launch)
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < zero_words; e += (int64_t)gridDim.x * 256) zero[e] = 0u;
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int lane = threadIdx.x & 63;
   uint32_t neg = 0;
@@ -299,12 +302,12 @@ __global__ __launch_bounds__(1024) void srht_kernel(int64_t k, int l, const T* _
 }
 
 lramm_status launch_srht_samples(uint64_t seed, int64_t k, int64_t l, int32_t* S, uint32_t* sign_bits,
-                                 uint32_t* keys, hipStream_t s) {
+                                 uint32_t* keys, hipStream_t s, uint32_t* zero, int64_t zero_words) {
   const int64_t kp = srht_padded(k);
   if (k < 2 || kp > kSrhtMaxK) return LRAMM_E_UNSUPPORTED;
   if (l < 1 || l > kp) return LRAMM_E_RANK;
   hipLaunchKernelGGL(srht_keys_kernel, dim3((unsigned)ceil_div(kp, (int64_t)256)), dim3(256), 0, s, seed, (int)kp,
-                     keys, sign_bits);
+                     keys, sign_bits, zero, zero ? zero_words : (int64_t)0);
   LRAMM_HIP(hipGetLastError());
   const int c = kp >= kSelThreads ? (int)(kp / kSelThreads) : 1;
 #define SAMPLES(C) \
