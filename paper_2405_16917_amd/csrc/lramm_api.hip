@@ -499,7 +499,10 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   if (srht_main)
     TIMED(ST_OMEGA, launch_srht_samples(d.seed, k, l, srS, srD, at<uint32_t>(W, P->off_srK), s, zero,
                                         (int64_t)P->zero_words));
-  if (P->side) {
+  // the side stream works before the sketch only for the test matrix (the
+  // Gaussian one, or the structured one's samples beside A's row codes)
+  const bool side_before = P->side && (P->srht ? !srht_main : omega == nullptr);
+  if (side_before) {
     LRAMM_HIP(hipEventRecord(P->ev_fork, s));
     LRAMM_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
   }
@@ -563,7 +566,11 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   else
     TIMED(ST_SKETCH, launch_gemm_nt(m, l, k, d.fmt_sketch, Ar, pAr, sAr, Om, P->pOm, sOm, 1.0f, 0.0f, Y, lp,
                                     LRAMM_F32, nullptr, 0, split, sb, s));
-  if (P->side) {
+  // after the sketch it forms A's column codes, B's codes and ||A'||^2 when
+  // they are needed; with none of them (bf16 operands read in place) it is
+  // left out, and so are the two event hops
+  const bool side_after = P->side && (!(fused_a || km_a) || !(range_only || km_b) || P->estimate);
+  if (side_after) {
     LRAMM_HIP(hipEventRecord(P->ev_sketch, s));
     LRAMM_HIP(hipStreamWaitEvent(P->side, P->ev_sketch, 0));
   }
@@ -586,12 +593,12 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
     if (!P->at) LRAMM_TRY(launch_sumsq(m, k, A, lda, d.a_type, norms + 2, norms, s2));
     else LRAMM_TRY(launch_sumsq(k, m, A, lda, d.a_type, norms + 2, norms, s2));
   }
-  if (P->side) LRAMM_HIP(hipEventRecord(P->ev_join, P->side));
+  if (side_after) LRAMM_HIP(hipEventRecord(P->ev_join, P->side));
   TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(0),
                                    P->chain_mode, P->passes));
   uint8_t* Qc = at<uint8_t>(W, P->off_Qc);
   float* sQc = at<float>(W, P->off_sQc);
-  if (P->side) LRAMM_HIP(hipStreamWaitEvent(s, P->ev_join, 0));   // join: A_c and B_c ready
+  if (side_after) LRAMM_HIP(hipStreamWaitEvent(s, P->ev_join, 0));   // join: A_c and B_c ready
   for (int it = 0; it < d.q; ++it) {
     float* Z = at<float>(W, P->off_Z);
     double* QZ = at<double>(W, P->off_QZ);
