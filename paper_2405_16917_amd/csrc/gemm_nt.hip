@@ -444,18 +444,27 @@ __device__ __forceinline__ void store1(const GemmArgs& a, int split, int gm, int
 
 // KM: bit 0 the left operand, bit 1 the right one is a bf16 matrix stored
 // K-major (TileLoaderKM) instead of K-contiguous codes.
-template <int BM, int BN, int KIND, bool SPLIT, int KM = 0>
-__global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
+// OCC: more workgroups per CU for short K, where the pipeline's start and
+// the epilogue weigh most: one LDS stage buffer (two barriers per stage),
+// one stage of register prefetch, and the epilogue staged in two row halves,
+// so that LDS (36 KiB per workgroup) and registers (at most 168) admit three
+// or four workgroups per CU instead of two.  8192 x 8192 x 416 bf16: 94
+// against 121 us; with K = 8192 it loses (115 against 108 us).
+template <int BM, int BN, int KIND, bool SPLIT, int KM = 0, bool OCC = false>
+__global__ __launch_bounds__(256, OCC ? 3 : 2) void gemm_nt_kernel(GemmArgs a) {
   static_assert(KM == 0 || KIND == KIND_BF16, "K-major operands are bf16");
   constexpr bool LKM = (KM & 1) != 0, RKM = (KM & 2) != 0;
   using LoaderL = typename std::conditional<LKM, TileLoaderKM<BM>, TileLoader<BM, KIND>>::type;
   using LoaderR = typename std::conditional<RKM, TileLoaderKM<BN>, TileLoader<BN, KIND>>::type;
   constexpr int RM = BM / 64;   // 32x32 MFMA tiles per wave along M
-  constexpr int kPrefetch = kPrefetchOf<BM, BN, KIND>;
+  constexpr int kPrefetch = OCC ? 1 : kPrefetchOf<BM, BN, KIND>;
   constexpr int RN = BN / 64;
-  constexpr int kABytes = 2 * BM * kLdsPitch, kBBytes = 2 * BN * kLdsPitch;
+  constexpr int NB = OCC ? 1 : 2;                       // LDS stage buffers
+  constexpr int kABytes = NB * BM * kLdsPitch, kBBytes = NB * BN * kLdsPitch;
   constexpr int kCPitch = BN + 4;                       // floats per staged output row
-  constexpr int kLds = (kABytes + kBBytes) > BM * kCPitch * 4 ? (kABytes + kBBytes) : BM * kCPitch * 4;
+  constexpr int kPasses = OCC ? 2 : 1;                  // epilogue passes over row slices
+  constexpr int kERows = BM / kPasses;
+  constexpr int kLds = (kABytes + kBBytes) > kERows * kCPitch * 4 ? (kABytes + kBBytes) : kERows * kCPitch * 4;
   __shared__ __attribute__((aligned(16))) uint8_t smem[kLds];
   uint8_t* sA = smem;
   uint8_t* sB = smem + kABytes;
@@ -534,7 +543,8 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
   const int kofs = (lane >> 5) * (CH / 2);
 
   // one stage: refill slot u (if asked), MFMAs on LDS buffer (st - st0) & 1,
-  // then the next stage's slot into the other buffer
+  // then the next stage's slot into the other buffer (single buffer: into
+  // the same one, once every wavefront has read it)
   // refill 0: none; 2: stage st + kPrefetch, which may reach past the padded
   // K (clamped to the slice: a repeat of its last stage is never stored)
   auto stage = [&](const int u, const int st, const int refill) {
@@ -543,7 +553,7 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
       la[u].template load<true>(rsL, oa, nx, xl, tid);
       lb[u].template load<true>(rsR, ob, nx, xr, tid);
     }
-    const int buf = (st - st0) & 1;
+    const int buf = NB == 1 ? 0 : (st - st0) & 1;
     const uint8_t* A = sA + buf * BM * kLdsPitch;
     const uint8_t* B = sB + buf * BN * kLdsPitch;
 #pragma unroll
@@ -559,9 +569,10 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
         for (int j = 0; j < RN; ++j) mfma_32x32<KIND>(acc[i][j], av[i], bv[j]);
     }
     if (st + 1 < st1) {
+      if constexpr (NB == 1) __syncthreads();
       const int un = (u + 1) % kPrefetch;
-      store_l(la[un], sA + (buf ^ 1) * BM * kLdsPitch);
-      store_r(lb[un], sB + (buf ^ 1) * BN * kLdsPitch);
+      store_l(la[un], sA + (NB == 1 ? 0 : buf ^ 1) * BM * kLdsPitch);
+      store_r(lb[un], sB + (NB == 1 ? 0 : buf ^ 1) * BN * kLdsPitch);
     }
     __syncthreads();
   };
@@ -580,57 +591,67 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_kernel(GemmArgs a) {
     if (sb + u < st1) stage(u, sb + u, 0);
 
   // ---- epilogue: stage raw accumulators in LDS, then coalesced 4-wide stores
+  // (kPasses slices of kERows rows; in slice h the wavefronts holding its
+  // rows stage them)
   int32_t* sC = reinterpret_cast<int32_t*>(smem);
-#pragma unroll
-  for (int i = 0; i < RM; ++i)
-#pragma unroll
-    for (int j = 0; j < RN; ++j) {
-      const int cc = wn * (BN / 2) + 32 * j + (lane & 31);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int rr = wm * (BM / 2) + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        int32_t bits;
-        if constexpr (kIntAcc<KIND>) bits = acc[i][j][r];
-        else bits = __float_as_int(acc[i][j][r]);
-        sC[rr * kCPitch + cc] = bits;
-      }
-    }
-  __syncthreads();
-  constexpr int kQuads = BM * BN / 4;
+  constexpr int kQuads = kERows * BN / 4;
   constexpr int kIters = kQuads / 256;
   static_assert(256 % (BN / 4) == 0, "a thread's quads share their columns");
+  static_assert(kPasses == 1 || kERows == BM / 2, "a slice is one wavefront row");
   // a thread's quads all sit in columns cq..cq+3 and in rows rq + (256 / (BN / 4)) it
   const int cq = (tid % (BN / 4)) * 4, rq = tid / (BN / 4);
   const int gn = col0 + cq;
-  if constexpr (SPLIT || !kScaled<KIND>) {
+#pragma unroll
+  for (int h = 0; h < kPasses; ++h) {
+    const int rbase = h * kERows;
+    if (h > 0) __syncthreads();   // the previous slice has been read
+    if (kPasses == 1 || wm == h) {
+#pragma unroll
+      for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int j = 0; j < RN; ++j) {
+          const int cc = wn * (BN / 2) + 32 * j + (lane & 31);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int rr = wm * (BM / 2) + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3) - rbase;
+            int32_t bits;
+            if constexpr (kIntAcc<KIND>) bits = acc[i][j][r];
+            else bits = __float_as_int(acc[i][j][r]);
+            sC[rr * kCPitch + cc] = bits;
+          }
+        }
+    }
+    __syncthreads();
+    if constexpr (SPLIT || !kScaled<KIND>) {
 #pragma unroll 4
-    for (int it = 0; it < kIters; ++it) {
-      const int rr = rq + (256 / (BN / 4)) * it;
-      const int gm = row0 + rr;
-      if (gm < a.M && gn < a.N) {
-        const int4 w = *reinterpret_cast<const int4*>(sC + rr * kCPitch + cq);
-        const int32_t v[4] = {w.x, w.y, w.z, w.w};
-        store4<KIND, SPLIT>(a, split, gm, gn, v);
+      for (int it = 0; it < kIters; ++it) {
+        const int rr = rq + (256 / (BN / 4)) * it;
+        const int gm = row0 + rbase + rr;
+        if (gm < a.M && gn < a.N) {
+          const int4 w = *reinterpret_cast<const int4*>(sC + rr * kCPitch + cq);
+          const int32_t v[4] = {w.x, w.y, w.z, w.w};
+          store4<KIND, SPLIT>(a, split, gm, gn, v);
+        }
       }
-    }
-  } else {
-    // dequantisation factors gathered once, all loads issued together
-    float dr[4], dl[kIters];
+    } else {
+      // dequantisation factors gathered once, all loads issued together
+      float dr[4], dl[kIters];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) dr[q] = a.dR[gn + q < a.N ? gn + q : a.N - 1];
+      for (int q = 0; q < 4; ++q) dr[q] = a.dR[gn + q < a.N ? gn + q : a.N - 1];
 #pragma unroll
-    for (int it = 0; it < kIters; ++it) {
-      const int gm = row0 + rq + (256 / (BN / 4)) * it;
-      dl[it] = a.dL[gm < a.M ? gm : a.M - 1];
-    }
+      for (int it = 0; it < kIters; ++it) {
+        const int gm = row0 + rbase + rq + (256 / (BN / 4)) * it;
+        dl[it] = a.dL[gm < a.M ? gm : a.M - 1];
+      }
 #pragma unroll 4
-    for (int it = 0; it < kIters; ++it) {
-      const int rr = rq + (256 / (BN / 4)) * it;
-      const int gm = row0 + rr;
-      if (gm < a.M && gn < a.N) {
-        const int4 w = *reinterpret_cast<const int4*>(sC + rr * kCPitch + cq);
-        const int32_t v[4] = {w.x, w.y, w.z, w.w};
-        store4_scaled<KIND>(a, gm, gn, v, dl[it], dr);
+      for (int it = 0; it < kIters; ++it) {
+        const int rr = rq + (256 / (BN / 4)) * it;
+        const int gm = row0 + rbase + rr;
+        if (gm < a.M && gn < a.N) {
+          const int4 w = *reinterpret_cast<const int4*>(sC + rr * kCPitch + cq);
+          const int32_t v[4] = {w.x, w.y, w.z, w.w};
+          store4_scaled<KIND>(a, gm, gn, v, dl[it], dr);
+        }
       }
     }
   }
@@ -949,6 +970,7 @@ static int kind_of(int fmt) {
 struct Plan {
   int bm, bn, split, st_per_split, nst, kw, tiles_m, tiles_n;
   bool big;    // the 256 x 256 kernel (64-byte K stages)
+  bool occ;    // the 128 x 128 kernel at three or four workgroups per CU (short K)
   int group;   // rows of tiles per group of the tile order
 };
 
@@ -965,6 +987,7 @@ static bool use_big(int64_t M, int64_t N, int kw, int fmt) {
 
 static Plan plan_gemm(int64_t M, int64_t N, int64_t K, int fmt, bool allow_split, bool allow_big = true) {
   Plan p;
+  p.occ = false;
   const int64_t esz = fmt == LRAMM_BF16F ? 2 : 1;     // widened bytes per element
   p.kw = (int)round_up(K * esz > 0 ? K * esz : 1, 64);
   p.big = allow_big && use_big(M, N, p.kw, fmt);
@@ -1012,6 +1035,10 @@ static Plan plan_gemm(int64_t M, int64_t N, int64_t K, int fmt, bool allow_split
   }
   p.st_per_split = (int)ceil_div(p.nst, p.split);
   p.split = (int)ceil_div(p.nst, p.st_per_split);
+  // bf16 K-contiguous codes (allow_big: no K-major operand), 128 x 128
+  // tiles, at most 16 stages and at least two workgroups per CU to place
+  p.occ = allow_big && fmt == LRAMM_BF16F && p.bm == 128 && p.bn == 128 && p.split == 1 && p.nst <= 16 &&
+          tiles >= 512;
   return p;
 }
 
@@ -1048,6 +1075,13 @@ static void launch_kind(const GemmArgs& a, const Plan& p, hipStream_t s) {
   if constexpr (KIND == KIND_I8 || KIND == KIND_BF16) {
     if (p.big) {
       hipLaunchKernelGGL((gemm_big_kernel<256, 256, KIND, false>), dim3(a.tiles_m * a.tiles_n), dim3(256), 0, s, a);
+      return;
+    }
+  }
+  if constexpr (KIND == KIND_BF16) {
+    if (p.occ) {
+      hipLaunchKernelGGL((gemm_nt_kernel<128, 128, KIND_BF16, false, 0, true>), dim3(a.tiles_m * a.tiles_n),
+                         dim3(256), 0, s, a);
       return;
     }
   }

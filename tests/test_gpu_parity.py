@@ -221,6 +221,25 @@ def test_gemm_bf16_operands(lib, MNK):
     assert OL.rel_fro(C, ref) <= 1e-6 * np.sqrt(K / 64) + 1e-7
 
 
+@pytest.mark.parametrize("MNK", [(3000, 2900, 300), (4096, 4096, 448), (2200, 4100, 1000)])
+@pytest.mark.parametrize("c_bf16", [False, True])
+def test_gemm_bf16_short_k(lib, MNK, c_bf16):
+    """bf16 codes with K of at most 16 stages over at least 512 tiles of
+    128 x 128 (the single-buffered kernel at three or four workgroups per CU,
+    as in G2): every output within the FP32 accumulation bound, ragged M, N
+    and K included."""
+    M, N, K = MNK
+    print(f"bf16 short-K GEMM {M}x{N}x{K} bf16 out {c_bf16}", flush=True)
+    rng = np.random.default_rng(M + N + K)
+    L = bf16_round(rng.standard_normal((M, K)))
+    R = bf16_round(rng.standard_normal((N, K)) * np.exp(rng.uniform(-3, 3, (N, 1))))
+    Lq, dL = lib.lramm_quantize(g(L), "bf16")
+    Rq, dR = lib.lramm_quantize(g(R), "bf16")
+    C = lib.lramm_gemm_nt(M, N, K, "bf16", Lq, dL, Rq, dR, ctype=torch.bfloat16 if c_bf16 else torch.float32)
+    _check_product("short K", C.double().cpu().numpy(), L, dL.cpu().numpy().astype(np.float64), R,
+                   dR.cpu().numpy().astype(np.float64), "bf16", c_bf16=c_bf16)
+
+
 @pytest.mark.parametrize("MNK", [(1, 1, 1), (64, 64, 64), (100, 37, 257), (130, 200, 1000), (512, 512, 4096)])
 def test_gemm_fp8_operands(lib, MNK):
     # fp8 products are exact in FP32, but the 32x32x64 MFMA adds the 64
