@@ -21,8 +21,9 @@
 // the low log2(EPT) index bits there, then the remaining bits in rounds of
 // at most min(log2(EPT), 4) bits through LDS (each thread loading the 2^w
 // elements that differ only in the round's bits); the l sampled outputs, scaled by
-// fl32(1 / sqrt(l)), form row i of Y.  The work is O(k' log k') additions per
-// row and one pass over A.
+// fl32(1 / sqrt(l)), form row i of Y.  When l is small against k' the last
+// round is formed only along the sampled outputs' paths.  The work is
+// O(k' log k') additions per row and one pass over A.
 #include <math.h>
 
 #include "common.hpp"
@@ -265,9 +266,19 @@ __global__ __launch_bounds__(1024) void srht_kernel(int64_t k, int l, const T* _
 #pragma unroll
   for (int j = 0; j < EPT; ++j) buf[lds_at(i0 + j)] = x[j];
   __syncthreads();
-  // the remaining bits [E, P) in rounds of w <= RW bits
+  // the remaining bits [E, P) in rounds of w <= RW bits.  Only l of the k'
+  // outputs are kept, so when they are few the last round (bits [BL, P)) is
+  // left to the output loop, which forms just the entries that a kept output
+  // depends on (2^WL - 1 of the round's additions per output instead of WL
+  // per element): every value it forms is the same sum, in the same order,
+  // as in the full round
+  constexpr int NR = (P - E + RW - 1) / RW;   // LDS rounds (none when P == E)
+  constexpr int BL = E + (NR > 0 ? (NR - 1) * RW : 0);
+  constexpr int WL = P - BL;
+  const bool prune = NR > 0 && (int64_t)l * ((1 << WL) - 1) < (int64_t)kp * WL;
 #pragma unroll
   for (int b = E; b < P; b += RW) {
+    if (b == BL && prune) break;
     const int w = (P - b) < RW ? (P - b) : RW;
     const int n = 1 << w;
     const int groups = EPT >> w;
@@ -298,6 +309,33 @@ __global__ __launch_bounds__(1024) void srht_kernel(int64_t k, int l, const T* _
     __syncthreads();
   }
   float* yr = Y + row * ldy;
+  if constexpr (NR > 0) {
+    if (prune) {
+      constexpr int NL = 1 << WL;
+      for (int j = t; j < l; j += nt) {
+        const int idx = S[j] & (kp - 1);
+        const int base = idx & ((1 << BL) - 1);
+        const uint32_t h = (uint32_t)idx >> BL;   // the output's bits in the round
+        float y[NL];
+#pragma unroll
+        for (int v = 0; v < NL; ++v) {
+          if constexpr (BL >= 5) y[v] = buf[lds_at(base) + v * ((1 << BL) + (1 << (BL - 5)))];
+          else y[v] = buf[lds_at(base + (v << BL))];
+        }
+        // bit s of the round: of the pair (u, z) the output needs u + z when
+        // bit s of h is clear and u - z = u + (-z) when it is set; the value
+        // for the entry whose lower round bits match h's stays in slot v
+#pragma unroll
+        for (int sb = 1; sb < NL; sb <<= 1) {
+          const uint32_t flip = (h & (uint32_t)sb) ? 0x80000000u : 0u;
+#pragma unroll
+          for (int v = 0; v < NL; v += 2 * sb) y[v] = y[v] + __uint_as_float(__float_as_uint(y[v + sb]) ^ flip);
+        }
+        yr[j] = __fmul_rn(y[0], scale);
+      }
+      return;
+    }
+  }
   for (int j = t; j < l; j += nt) yr[j] = __fmul_rn(buf[lds_at(S[j] & (kp - 1))], scale);
 }
 

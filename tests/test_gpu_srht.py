@@ -41,9 +41,14 @@ def test_samples_and_signs_bit_exact(lib, skl):
 
 @pytest.mark.parametrize("mkl", [(5, 2, 1), (3, 3, 2), (37, 100, 16), (64, 300, 37), (16, 512, 64),
                                  (9, 1000, 200), (33, 2048, 100), (40, 4096, 272), (20, 5000, 448),
-                                 (24, 8192, 448), (8, 16384, 500), (4, 32768, 1000)])
+                                 (24, 8192, 448), (8, 16384, 500), (4, 32768, 1000),
+                                 # many samples: the last transform round runs over every element
+                                 (12, 1000, 1000), (6, 8192, 4096), (7, 2, 2)])
 @pytest.mark.parametrize("dtype", ["fp32", "bf16"])
 def test_sketch_bit_exact(lib, mkl, dtype):
+    """Few samples (l * (2^w - 1) < k' * w for the last round's w bits) take the
+    output loop's restricted last round, many take the full round; both are
+    the oracle's butterflies to the bit."""
     m, k, l = mkl
     print(f"srht sketch {m}x{k} l {l} {dtype}", flush=True)
     rng = np.random.default_rng(m + k)
@@ -68,6 +73,22 @@ def test_sketch_padded_leading_dimensions(lib):
     got = Y.double().cpu().numpy()
     assert np.array_equal(got[:, :l], OS.srht_sketch(A[:, :k].astype(np.float64), 4, l, "fp32"))
     assert np.all(got[:, l:] == 7.0)
+
+
+@pytest.mark.parametrize("case", [(20000, 300, 37, "fp32", 0), (5000, 4096, 272, "bf16", 0),
+                                  (3000, 1000, 50, "fp32", 3), (2500, 2048, 2048, "bf16", 0)])
+def test_sketch_many_rows(lib, case):
+    """Many rows (one workgroup each), aligned and unaligned, with the
+    pruned and the full last round."""
+    m, k, l, dtype, pad = case
+    print(f"srht sketch {m}x{k} l {l} {dtype} ld pad {pad}", flush=True)
+    rng = np.random.default_rng(m + l)
+    A = synth.to_dtype(rng.standard_normal((m, k + pad)), dtype)
+    Ad = torch.from_numpy(A).to(DEV).to(torch.bfloat16 if dtype == "bf16" else torch.float32)[:, :k]
+    S, bits = lib.lramm_srht_samples(6, k, l)
+    Y = lib.lramm_srht_sketch(Ad, l, S, bits).double().cpu().numpy()
+    ref = OS.srht_sketch(A[:, :k].astype(np.float64), 6, l, "fp32")
+    assert np.array_equal(Y, ref), f"{np.sum(Y != ref)} entries differ"
 
 
 def test_target_shape_sketch_bit_exact(lib):
