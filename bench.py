@@ -370,7 +370,8 @@ def sweep(args, lramm, dev):
                     del plan, ws, C
                     torch.cuda.empty_cache()
         ok = [c for c in cands if c["rel_fro"] <= TARGET_RELF]
-        pick = min(ok, key=lambda c: c["ms"]) if ok else min(cands, key=lambda c: c["rel_fro"])
+        # none within the target: the lowest error, the fastest among equal ones
+        pick = min(ok, key=lambda c: c["ms"]) if ok else min(cands, key=lambda c: (c["rel_fro"], c["ms"]))
         best[tau] = dict(pick, reaches_target=bool(ok))
         del A, B, A64, B64, Cex
     print(json.dumps({"sweep_best": best}), flush=True)
