@@ -34,7 +34,9 @@ C = Q Q^T A B, so dA = Q Q^T dC B^T and dB = A^T Q Q^T dC, in FP64.
 Pins: tests/test_oracle_lramm.py (exact recovery when rank(A) <= l, the
 Eckart-Young floor, Halko's average-case bound, the brute-force 64 x 64 SVD
 check, reduction to Alg. 2 when l = m = k, the chain's agreement with a
-direct evaluation of Q(Q^T A)B, monotone convergence in bit width) and
+direct evaluation of Q(Q^T A)B, monotone convergence in bit width, pure
+Python brute-force chains in one format and with int4 / int8 alternating
+over the stages) and
 tests/test_oracle_backward.py (central finite differences of the bilinear
 surrogate).
 """

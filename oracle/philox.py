@@ -23,7 +23,8 @@ same with (x2, x3) for z2, z3.  Element e takes z_(e mod 4), computed in FP64
 and rounded once to binary32.
 
 Pins (tests/test_oracle_philox.py): the published Random123 known-answer
-vectors for Philox4x32-10, and moments / normality of the generated matrix.
+vectors for Philox4x32-10, moments / normality of the generated matrix, and
+Box-Muller closed forms (radius and angle of words with exact uniforms).
 """
 
 import numpy as np

@@ -23,8 +23,9 @@ product of the bf16-rounded values.
 Pins (tests/test_oracle_qgemm.py): the integer product equals brute-force
 Python integer loops on small shapes and numpy int64 matmul on larger ones;
 the epilogue equals an independent binary32 evaluation with numpy float32
-scalars; the size-invariance of the relative error (Sec. 3.3) and the
-Theorem 4.3 bound hold on random inputs.
+scalars; hand-worked bf16 and fp8 products (rounding ties, the e4m3 grid and
+the amax-to-448 scaling); the size-invariance of the relative error
+(Sec. 3.3) and the Theorem 4.3 bound hold on random inputs.
 """
 
 import numpy as np

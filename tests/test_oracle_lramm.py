@@ -141,18 +141,18 @@ def _r32(x):
     return struct.unpack("<f", struct.pack("<f", x))[0]
 
 
-def _quant(v):
+def _quant(v, qmax=127):
     amax = max(abs(x) for x in v)
     if amax == 0:
         return [0] * len(v), 0.0
-    lam = _r32(127.0 / amax)
-    return [max(-127, min(127, round(_r32(x * lam)))) for x in v], _r32(amax / 127.0)
+    lam = _r32(qmax / amax)
+    return [max(-qmax, min(qmax, round(_r32(x * lam)))) for x in v], _r32(amax / qmax)
 
 
-def _qmm(Lm, Rm):
+def _qmm(Lm, Rm, qmax=127):
     M, K, N = len(Lm), len(Rm), len(Rm[0])
-    lq = [_quant(row) for row in Lm]
-    rq = [_quant([Rm[t][j] for t in range(K)]) for j in range(N)]
+    lq = [_quant(row, qmax) for row in Lm]
+    rq = [_quant([Rm[t][j] for t in range(K)], qmax) for j in range(N)]
     out = []
     for i in range(M):
         row = []
@@ -207,6 +207,34 @@ def test_tiny_chain_against_pure_python():
     assert np.array_equal(out["Bt"], np.array(Bt))
     assert np.array_equal(out["T"], np.array(T))
     assert np.array_equal(out["C"], np.array(C))
+
+
+def test_tiny_mixed_format_chain_against_pure_python():
+    """The stage-to-format mapping: the sketch products in the first format,
+    the power step's A^T Q and the projection in the second, G1 in the third,
+    G2 in the fourth.  With int4 (q_max 7) and int8 (127) alternating, any
+    stage that took another stage's format changes its codes."""
+    rng = np.random.default_rng(12)
+    m, k, n, l = 9, 8, 7, 3
+    A = np.float32(rng.standard_normal((m, k)) * np.exp(-np.arange(k) / 2.0)).astype(np.float64)
+    B = np.float32(rng.standard_normal((k, n))).astype(np.float64)
+    om = np.float32(rng.standard_normal((k, l))).astype(np.float64)
+    for fmt in (("int4", "int8", "int4", "int8"), ("int8", "int4", "int8", "int4")):
+        qs, qp, q1, q2 = (7 if f == "int4" else 127 for f in fmt)
+        out = L.lramm_forward(A, B, 2, 1, 1, fmt, omega=om)
+        Al, Bl, Ol = A.tolist(), B.tolist(), om.tolist()
+        Y = _qmm(Al, Ol, qs)
+        Qm = _gs(Y)
+        Z = _qmm(_T(Al), _f32m(Qm), qp)
+        QZ = _gs(Z)
+        Y = _qmm(Al, _f32m(QZ), qs)
+        Qm = _gs(Y)
+        Bt = _qmm(_T(_f32m(Qm)), Al, qp)
+        T = _qmm(Bt, Bl, q1)
+        C = _qmm(_f32m(Qm), T, q2)
+        assert np.array_equal(out["Bt"], np.array(Bt)), fmt
+        assert np.array_equal(out["T"], np.array(T)), fmt
+        assert np.array_equal(out["C"], np.array(C)), fmt
 
 
 def test_exact_recovery_with_dropped_sketch_columns():

@@ -131,3 +131,36 @@ def test_fp8_and_bf16_products():
     ei4 = np.linalg.norm(G.qgemm(L, R, "int4") - ex) / np.linalg.norm(ex)
     assert eb < e8 < ei4 and eb < ei8 < ei4
     assert eb < 5e-3
+
+
+def test_bf16_product_hand_worked():
+    """bf16 operands are the inputs rounded to nearest-even on the 8-bit
+    significand, multiplied exactly, unit scales: 1 + 2^-8 is a tie and
+    rounds down to 1, 1 + 3 2^-8 a tie that rounds up to 1 + 2^-6, so
+    [1 + 2^-8, 3] . [1 + 3 2^-8, 2^-9] = 1 + 2^-6 + 3 2^-9 = 1 + 11 2^-9
+    (truncation would give 1 + 7 2^-9, no rounding 1 + 11 2^-9 + 3 2^-16)."""
+    L = np.array([[1.0 + 2.0**-8, 3.0]])
+    R = np.array([[1.0 + 3.0 * 2.0**-8], [2.0**-9]])
+    out = G.qgemm(L, R, "bf16", parts=True)
+    assert out["out"][0, 0] == 1.0 + 11.0 * 2.0**-9
+    assert np.all(np.asarray(out["dL"]) == 1.0) and np.all(np.asarray(out["dR"]) == 1.0)
+    # the transposed layout: R's column is the quantised vector, not its row
+    assert G.qgemm(R.T, L.T, "bf16")[0, 0] == 1.0 + 11.0 * 2.0**-9
+
+
+def test_fp8_product_hand_worked():
+    """fp8 e4m3: each row (column) is scaled so that its largest magnitude
+    maps to 448, rounded to the e4m3 grid, and dequantised by amax / 448.
+    Row [448, -3.5] keeps its values (scale 1); column [0.25, 2.75] maps to
+    0.25 * 448 / 2.75 = 40.73, whose e4m3 neighbours are 40 and 44 (step 4
+    in [32, 64)), so 40, and to 448.  The exact code product is
+    448 * 40 - 3.5 * 448 = 16352."""
+    L = np.array([[448.0, -3.5]])
+    R = np.array([[0.25], [2.75]])
+    out = G.qgemm(L, R, "fp8", parts=True)
+    assert [float(x) for x in np.asarray(out["Lq"]).ravel()] == [448.0, -3.5]
+    assert [float(x) for x in np.asarray(out["Rq"]).ravel()] == [40.0, 448.0]
+    assert float(np.asarray(out["dL"]).ravel()[0]) == 1.0
+    assert float(np.asarray(out["dR"]).ravel()[0]) == float(np.float32(2.75) / np.float32(448.0))
+    assert float(out["acc"][0, 0]) == 16352.0
+    assert abs(out["out"][0, 0] - 16352.0 * 2.75 / 448.0) <= 2.0**-23 * 100.375 * 2
