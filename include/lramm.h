@@ -429,6 +429,22 @@ LRAMM_API lramm_status lramm_cholqr2(int64_t rows, int64_t l, const void* Y, int
                            int32_t ytype, double* Q, int64_t ldq, void* ws,
                            size_t ws_bytes, uint32_t* flags, void* stream);
 LRAMM_API size_t lramm_cholqr2_workspace(int64_t rows, int64_t l);
+/* The triangular factor of the range finder's QR (paper Sec. 2.2, Alg. 1:
+ * Y = Q R): R = Q^T Y on and above the diagonal, zero below, for the Q that
+ * lramm_cholqr2 (or the forward, through lramm_factors) returned for Y.
+ *   Y: rows x l, ytype F32 or F64, row-major, ldy >= l (device).
+ *   Q: rows x l FP64, ldq >= l (device; columns past l are not read).
+ *   R: l x l FP64, row-major, ldr >= l (device, caller-owned; columns past l
+ *      are not written).  A column that lramm_cholqr2 dropped (its Q column
+ *      is zero) gives a zero row of R.
+ * Each entry is an FP64 sum over the rows in row order (bit-reproducible).
+ * Returns LRAMM_E_SHAPE for negative sizes or short leading dimensions,
+ * LRAMM_E_RANK for l > rows, LRAMM_E_INVALID for a null pointer,
+ * LRAMM_E_UNSUPPORTED for another ytype; l = 0 does nothing.  Asynchronous
+ * on stream. */
+LRAMM_API lramm_status lramm_r_factor(int64_t rows, int64_t l, const void* Y, int64_t ldy,
+                           int32_t ytype, const double* Q, int64_t ldq, double* R,
+                           int64_t ldr, void* stream);
 /* The least workspace lramm_cholqr2 runs in: with fewer bytes than
  * lramm_cholqr2_workspace (but at least these) it sums the FP64 Gram over
  * fewer row chunks -- the same arithmetic up to the order of the chunk sums. */

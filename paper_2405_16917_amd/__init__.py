@@ -12,7 +12,7 @@ import torch
 
 from ._lib import (  # noqa: F401
     EXPORTS, LIB_PATH, LrammBatch, LrammError, LrammPlan, LrammTsPlan, autotune_rank, load, lramm_cholqr2, storage,
-    lramm_cholqr2_workspace, lramm_cholqr2_noalloc, NOALLOC_SCRATCH_BYTES, E_SCRATCH,
+    lramm_cholqr2_workspace, lramm_cholqr2_noalloc, lramm_r_factor, NOALLOC_SCRATCH_BYTES, E_SCRATCH,
     lramm_dense_gemm_nt, lramm_gemm_nt, lramm_gemm_nt_workspace, lramm_init, lramm_omega,
     lramm_pitch, lramm_quantize, lramm_srht_padded, lramm_srht_samples, lramm_srht_sketch, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_SQRTNEG, FLAG_STALL,
 )

@@ -43,7 +43,7 @@ EXPORTS = (
     "lramm_cholqr2_noalloc", "lramm_chol_one_launch", "lramm_codes",
     "lramm_ts_plan_create", "lramm_ts_plan_destroy", "lramm_ts_workspace_bytes", "lramm_ts_forward",
     "lramm_ts_intermediate", "lramm_ts_status_poll", "lramm_srht_padded", "lramm_srht_samples",
-    "lramm_srht_sketch", "lramm_error_estimate", "lramm_cholqr2_workspace_min",
+    "lramm_srht_sketch", "lramm_error_estimate", "lramm_cholqr2_workspace_min", "lramm_r_factor",
 )
 NSTAGES = 22
 
@@ -113,6 +113,7 @@ def load(path=LIB_PATH):
         "lramm_backward": ([P, P, I64, P, I64, P, I64, P, I64, P, I64, P, SZ, P], I32),
         "lramm_status_poll": ([P, P, P, ctypes.POINTER(ctypes.c_uint32)], I32),
         "lramm_quantize": ([I64, I64, P, I64, I32, I32, I32, P, I64, P, P, P], I32),
+        "lramm_r_factor": ([I64, I64, P, I64, I32, P, I64, P, I64, P], I32),
         "lramm_pitch": ([I64, I32], I64),
         "lramm_gemm_nt": ([I64, I64, I64, I32, P, I64, P, P, I64, P, ctypes.c_float, ctypes.c_float,
                            P, I64, I32, P, I64, P, SZ, P], I32),
@@ -276,6 +277,17 @@ def lramm_cholqr2(Y, l=None, Q=None, ws=None, flags=None):
     _check(lib.lramm_cholqr2(rows, l, _ptr(Y), Y.stride(0), DTYPE[Y.dtype], _ptr(Q), Q.stride(0), _ptr(ws),
                              ws.numel(), _ptr(flags), _stream()), "lramm_cholqr2")
     return Q
+
+
+def lramm_r_factor(Y, Q, l=None, R=None):
+    """R = Q^T Y on and above the diagonal (zero below), l x l FP64: the
+    triangular factor of Y = Q R for Q from lramm_cholqr2."""
+    l = Y.shape[1] if l is None else l
+    if R is None:
+        R = torch.empty((l, l), dtype=torch.float64, device=Y.device)
+    _check(load().lramm_r_factor(Y.shape[0], l, _ptr(Y), Y.stride(0), DTYPE[Y.dtype], _ptr(Q), Q.stride(0), _ptr(R),
+                                 R.stride(0), _stream()), "lramm_r_factor")
+    return R
 
 
 def lramm_cholqr2_noalloc(Y, l=None, Q=None, flags=None):

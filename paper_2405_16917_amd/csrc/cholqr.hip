@@ -2068,6 +2068,69 @@ static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t l
   return LRAMM_OK;
 }
 
+// R = Q^T Y on and above the diagonal, zero below: the triangular factor of
+// Y = Q R for the orthonormal Q of a Cholesky QR of Y (R = Q^T Q R).  One
+// workgroup per 32 x 32 tile of R; rows of Q and Y pass through LDS in chunks
+// of 64, and each thread sums its 4 entries over the rows in row order
+// (FP64 fused multiply-adds, the same order on every call).
+constexpr int kRChunk = 64;
+
+template <typename T>
+__global__ __launch_bounds__(256) void r_factor_kernel(int64_t rows, int l, const double* __restrict__ Q, int64_t ldq,
+                                                       const T* __restrict__ Y, int64_t ldy, double* __restrict__ R,
+                                                       int64_t ldr) {
+  __shared__ double sQ[kRChunk][33];
+  __shared__ double sY[kRChunk][33];
+  const int tb = (l + 31) / 32;
+  const int bi = blockIdx.x / tb, bj = blockIdx.x % tb;
+  const int t = threadIdx.x;
+  const int a = t & 31, b0 = (t >> 5) * 4;   // entries (32 bi + a, 32 bj + b0 .. b0 + 3)
+  const int gi = 32 * bi + a;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (bi <= bj) {
+    for (int64_t r0 = 0; r0 < rows; r0 += kRChunk) {
+      // stage 64 rows of Q's column block bi and Y's column block bj
+      for (int e = t; e < kRChunk * 32; e += 256) {
+        const int rr = e >> 5, c = e & 31;
+        const int64_t row = r0 + rr;
+        const int qc = 32 * bi + c, yc = 32 * bj + c;
+        sQ[rr][c] = (row < rows && qc < l) ? Q[row * ldq + qc] : 0.0;
+        sY[rr][c] = (row < rows && yc < l) ? (double)Y[row * ldy + yc] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int rr = 0; rr < kRChunk; ++rr) {
+        const double q = sQ[rr][a];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = fma(q, sY[rr][b0 + u], acc[u]);
+      }
+      __syncthreads();
+    }
+  }
+  if (gi < l)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int gj = 32 * bj + b0 + u;
+      if (gj < l) R[(int64_t)gi * ldr + gj] = gi <= gj ? acc[u] : 0.0;
+    }
+}
+
+lramm_status launch_r_factor(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, const double* Q,
+                             int64_t ldq, double* R, int64_t ldr, hipStream_t s) {
+  const int tb = (int)ceil_div(l, (int64_t)32);
+  const dim3 grid((unsigned)(tb * tb));
+  if (ytype == LRAMM_F32)
+    hipLaunchKernelGGL(r_factor_kernel<float>, grid, dim3(256), 0, s, rows, (int)l, Q, ldq, (const float*)Y, ldy, R,
+                       ldr);
+  else if (ytype == LRAMM_F64)
+    hipLaunchKernelGGL(r_factor_kernel<double>, grid, dim3(256), 0, s, rows, (int)l, Q, ldq, (const double*)Y, ldy,
+                       R, ldr);
+  else
+    return LRAMM_E_UNSUPPORTED;
+  LRAMM_HIP(hipGetLastError());
+  return LRAMM_OK;
+}
+
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
                             int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s,
                             const TimingHook* hook, uint32_t* colmax, int chain_mode, int passes) {

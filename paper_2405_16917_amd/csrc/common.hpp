@@ -297,6 +297,8 @@ bool chain_admits(int64_t l, int compute_units, int chain_mode);
 // colmax (nullable, caller-zeroed, ldq entries): column maxima of fl32(|Q|)
 // as bit patterns, accumulated while Q is written.  passes = 1 stops after
 // the first Cholesky QR pass (Q = Y R1^-1).
+lramm_status launch_r_factor(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, const double* Q,
+                             int64_t ldq, double* R, int64_t ldr, hipStream_t s);
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
                             int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s,
                             const TimingHook* hook = nullptr, uint32_t* colmax = nullptr,

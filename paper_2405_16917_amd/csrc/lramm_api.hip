@@ -1102,6 +1102,17 @@ lramm_status lramm_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, 
   return launch_cholqr2(rows, l, Y, ldy, ytype, Q, ldq, ws, ws_bytes, flags, (hipStream_t)stream);
 }
 
+lramm_status lramm_r_factor(int64_t rows, int64_t l, const void* Y, int64_t ldy, int32_t ytype, const double* Q,
+                            int64_t ldq, double* R, int64_t ldr, void* stream) {
+  if (rows < 0 || l < 0) return LRAMM_E_SHAPE;
+  if (l == 0) return LRAMM_OK;
+  if (!Y || !Q || !R) return LRAMM_E_INVALID;
+  if (l > rows) return LRAMM_E_RANK;
+  if (ldy < l || ldq < l || ldr < l) return LRAMM_E_SHAPE;
+  if (ytype != LRAMM_F32 && ytype != LRAMM_F64) return LRAMM_E_UNSUPPORTED;
+  return launch_r_factor(rows, l, Y, ldy, ytype, Q, ldq, R, ldr, (hipStream_t)stream);
+}
+
 lramm_status lramm_cholqr2_noalloc(int64_t rows, int64_t l, const void* Y, int64_t ldy, int32_t ytype, double* Q,
                                    int64_t ldq, uint32_t* flags, void* stream) {
   if (rows < 0 || l < 0) return LRAMM_E_SHAPE;

@@ -136,6 +136,18 @@ def test_noalloc_cholqr2_host_checks(lib):
     assert lib.lramm_status_string(L.E_SCRATCH).startswith(b"problem needs more scratch")
 
 
+def test_r_factor_host_checks(lib):
+    """lramm_r_factor's argument errors, returned on the host."""
+    import paper_2405_16917_amd._lib as L
+    assert lib.lramm_r_factor(-1, 4, 1, 4, L.F32, 1, 4, 1, 4, None) == L.E_SHAPE
+    assert lib.lramm_r_factor(10, 0, None, 4, L.F32, None, 4, None, 4, None) == L.OK
+    assert lib.lramm_r_factor(10, 4, None, 4, L.F32, 1, 4, 1, 4, None) == L.E_INVALID
+    assert lib.lramm_r_factor(3, 4, 1, 4, L.F32, 1, 4, 1, 4, None) == L.E_RANK
+    assert lib.lramm_r_factor(10, 4, 1, 3, L.F32, 1, 4, 1, 4, None) == L.E_SHAPE
+    assert lib.lramm_r_factor(10, 4, 1, 4, L.F32, 1, 4, 1, 3, None) == L.E_SHAPE
+    assert lib.lramm_r_factor(10, 4, 1, 4, L.BF16, 1, 4, 1, 4, None) == L.E_UNSUPPORTED
+
+
 def test_one_launch_cholesky_admission(lib):
     """The one-launch Cholesky's grid (1 + (T-2)(T-1)/2 + T workgroups, T =
     ceil(l/32)) must fit the CUs less 16, or half of that unless the plan is

@@ -299,12 +299,13 @@ def test_omega_matches_oracle_philox(lib, kl):
 
 # ---------------------------------------------------------------- CholQR2 --
 
-# l' / 32 = 1 .. 23 blocks: odd and even block counts, the one-launch chain
-# up to l' = 704 and the launch-per-two-panels schedule past it (l' = 736)
+# l' / 32 = 1 .. 32 blocks: odd and even block counts, the one-launch chain
+# up to l' = 704 and the launch-per-two-panels schedule past it (l' = 736),
+# up to the largest width the library takes (l' = 1024)
 @pytest.mark.parametrize("case", [(100, 5, 10.0), (64, 32, 10.0),
                                   (300, 40, 1.0), (512, 74, 1e3), (1000, 96, 1e6), (2048, 272, 30.0),
                                   (700, 33, 10.0), (800, 128, 100.0), (2000, 200, 1e4), (4096, 528, 30.0),
-                                  (2500, 700, 10.0), (1500, 736, 10.0)])
+                                  (2500, 700, 10.0), (1500, 736, 10.0), (2048, 1024, 10.0)])
 def test_cholqr2_matches_householder(lib, case):
     rows, l, cond = case
     rng = np.random.default_rng(rows + l)
@@ -317,10 +318,30 @@ def test_cholqr2_matches_householder(lib, case):
     Qg = Q.cpu().numpy()
     assert not Qg[:, l:].any()
     Qg = Qg[:, :l]
-    Qh, _ = householder_qr(Y)
+    Qh, Rh = householder_qr(Y)
     assert np.max(np.abs(Qg.T @ Qg - np.eye(l))) <= 1e-13
     assert np.max(np.abs(Qg - Qh)) <= 2e-14 * cond * np.sqrt(l)
     assert int(flags.item()) == 0
+    _check_r_factor(lib, Y, Q, Qg, l, Qh, Rh)
+
+
+def _check_r_factor(lib, Y, Q, Qg, l, Qh=None, Rh=None):
+    """lramm_r_factor on the GPU's own Q: exact zeros below the diagonal,
+    each entry within the FP64 summation bound of Q^T Y (rows terms), and,
+    given Householder's factors, R within |(Q - Q_h)^T Y| of theirs plus the
+    two computations' rounding (Householder's backward error, first order
+    gamma_{rows l}, and the sum's)."""
+    R = lib.lramm_r_factor(g(Y, torch.float64 if Y.dtype == np.float64 else torch.float32), Q, l).cpu().numpy()
+    rows = Y.shape[0]
+    assert not np.tril(R, -1).any()
+    ref = np.triu(Qg.T @ Y)
+    bound = np.triu(2.0 * rows * 2.0**-53 * (np.abs(Qg).T @ np.abs(Y)))
+    assert np.all(np.abs(R - ref) <= bound)
+    if Rh is not None:
+        dq = np.linalg.norm(Qg - Qh, axis=0)[:, None] * np.linalg.norm(Y, axis=0)[None, :]
+        tol = dq + 2.0 * rows * (l + 2) * 2.0**-53 * np.linalg.norm(Y, axis=0)[None, :]
+        assert np.all(np.abs(R - Rh) <= np.triu(tol) + 1e-300)
+    return R
 
 
 def test_cholqr2_two_streams_at_once(lib):
@@ -367,6 +388,10 @@ def test_cholqr2_f64_input_and_rank_deficiency(lib, l, dead):
     assert np.max(np.abs(Qg[:, keep].T @ Qg[:, keep] - np.eye(l - 1))) <= 1e-13
     # span is kept: Y = Q Q^T Y
     assert np.linalg.norm(Y - Qg @ (Qg.T @ Y)) <= 1e-12 * np.linalg.norm(Y)
+    # the triangular factor: the dropped column's row is zero, Y = Q R
+    R = _check_r_factor(lib, Y, Q, Qg, l)
+    assert not R[dead].any()
+    assert np.linalg.norm(Y - Qg @ R) <= 1e-12 * np.linalg.norm(Y)
 
 
 # ------------------------------------------------------------- end to end --
@@ -726,6 +751,32 @@ def test_target_workload_sampled_stages(lib):
     Cs = C.float().cpu().numpy().astype(np.float64)
     check_stages(lib, plan, ws, A.astype(np.float64), B.astype(np.float64), Cs, fmt, 0, Ad=Ad, omega=om,
                  omega_mismatch=3, sample=sample, c_bf16=True)
+
+
+def test_headline_setting_sampled_stages(lib):
+    """The bench's headline setting at full size: 8192^3 bf16, sigma_i =
+    exp(-i/64), l = 416 (r = 384, p = 32), q = 0, bf16 in every stage, the
+    structured sketch from seed 1 and one Cholesky QR pass, in the launch
+    configuration the bench times (exclusive plan, bf16 C).  The sketch is
+    the oracle's binary32 transform to the bit on 96 sampled rows; every
+    product is checked on 96 sampled rows / columns against its own codes;
+    Q's orthonormality (one-pass bound) and span are checked at full size."""
+    m = k = n = 8192
+    print("headline setting 8192^3 bf16 l 416 srht one pass", flush=True)
+    A, _ = synth.lowrank(m, k, synth.spectrum("exp", m, 64.0), 0, dtype="bf16")
+    B = synth.gaussian(k, n, 100, dtype="bf16")
+    fmt = ("bf16",) * 4
+    plan = lib.LrammPlan(m, n, k, 384, 32, 0, fmt, torch.bfloat16, torch.bfloat16, torch.bfloat16, 1,
+                         exclusive=True, sketch="srht", orth="cholqr")
+    ws = plan.workspace()
+    Ad, Bd = g(A, torch.bfloat16), g(B, torch.bfloat16)
+    C = plan.forward(Ad, Bd, ws)
+    assert plan.status(ws) == 0
+    rng = np.random.default_rng(6)
+    sample = np.sort(rng.choice(8192, 96, replace=False))
+    Cs = C.float().cpu().numpy().astype(np.float64)
+    check_stages(lib, plan, ws, A.astype(np.float64), B.astype(np.float64), Cs, fmt, 0, Ad=Ad, sample=sample,
+                 c_bf16=True, srht_seed=1, one_pass=True)
 
 
 def test_lramm_seeded_omega_and_alpha_beta(lib):
