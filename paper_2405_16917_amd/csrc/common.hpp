@@ -236,10 +236,22 @@ lramm_status launch_quantize_both(int64_t rows, int64_t cols, const void* X, int
 // km (bf16 only): bit 0 -- Lq is a bf16 matrix stored K-major (K rows of M
 // elements, ldl bytes apart) instead of K-contiguous rows; bit 1 -- the same
 // for Rq (K rows of N elements, ldr bytes apart).  Runs on the 128-row tiles.
+// Optional second output of a bf16 product summed over K slices with the
+// identity epilogue: C's bf16 row codes (pitch and pe in elements) and unit
+// scales.  *written tells whether they were formed (else the caller runs the
+// row quantiser on C).
+struct CodesOut {
+  uint16_t* codes;
+  int64_t pitch;
+  int64_t pe;
+  float* scales;
+  bool* written;
+};
 lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void* Lq, int64_t ldl,
                             const float* dL, const void* Rq, int64_t ldr, const float* dR, float alpha,
                             float beta, void* C, int64_t ldc, int ctype, int32_t* acc_out, int64_t ld_acc,
-                            void* ws, size_t ws_bytes, hipStream_t s, bool col_first = false, int km = 0);
+                            void* ws, size_t ws_bytes, hipStream_t s, bool col_first = false, int km = 0,
+                            const CodesOut* codes = nullptr);
 size_t gemm_nt_workspace(int64_t M, int64_t N, int64_t K, int fmt);
 
 lramm_status launch_omega(uint64_t seed, int64_t k, int64_t l, int64_t lrows, float* OmegaT, int64_t ldo,

@@ -894,6 +894,55 @@ __global__ __launch_bounds__(256, 1) void gemm_big_kernel(GemmArgs a) {
 template __global__ void gemm_big_kernel<256, 256, KIND_I8, false>(GemmArgs);
 template __global__ void gemm_big_kernel<256, 256, KIND_BF16, false>(GemmArgs);
 
+// The split-K sum of a bf16 product whose epilogue is the identity (alpha
+// 1, beta 0, FP32 output, no scales), which also writes the sums' bf16 codes
+// as the bf16 row quantiser would from C: row r of the codes (pe elements,
+// zero past N) and its unit scale.  The sums are formed in split order, as
+// in the plain sum below, so C is the same to the bit; the codes save that
+// quantiser's read of C.  One thread per 4 columns of the padded rows.
+__global__ __launch_bounds__(256) void splitk_reduce_bf16_codes_kernel(GemmArgs a, int nsplit,
+                                                                       uint16_t* __restrict__ codes, int64_t cpitch,
+                                                                       int pe, float* __restrict__ cscales) {
+  const int64_t total = (int64_t)a.M * a.N;
+  const uint32_t per_row = (uint32_t)pe / 4;
+  const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
+  if ((uint64_t)idx >= (uint64_t)a.M * per_row) return;
+  const uint32_t row = idx / per_row;
+  const int c0 = (int)(idx - row * per_row) * 4;
+  const int64_t e0 = (int64_t)row * a.N + c0;
+  float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if ((a.N & 3) == 0 && c0 < a.N) {
+    // a whole quad inside the row: 16-byte loads of each slice
+    const int4* p4 = reinterpret_cast<const int4*>(a.part + e0);
+    const int64_t stride4 = total / 4;
+    for (int k = 0; k < nsplit; ++k) {
+      const int4 x = p4[(int64_t)k * stride4];
+      v[0] = __fadd_rn(v[0], __int_as_float(x.x));
+      v[1] = __fadd_rn(v[1], __int_as_float(x.y));
+      v[2] = __fadd_rn(v[2], __int_as_float(x.z));
+      v[3] = __fadd_rn(v[3], __int_as_float(x.w));
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (c0 + j < a.N)
+        for (int k = 0; k < nsplit; ++k) v[j] = __fadd_rn(v[j], __int_as_float(a.part[(int64_t)k * total + e0 + j]));
+  }
+  float* C = reinterpret_cast<float*>(a.C) + (int64_t)row * a.ldc;
+  if (a.c_vec && c0 + 3 < a.N) {
+    *reinterpret_cast<float4*>(C + c0) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (c0 + j < a.N) C[c0 + j] = v[j];
+  }
+  uint32_t h[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) h[j] = c0 + j < a.N ? (uint32_t)bf16_bits(v[j]) : 0u;
+  *reinterpret_cast<uint2*>(codes + (int64_t)row * cpitch + c0) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+  if (c0 == 0) cscales[row] = 1.0f;
+}
+
 // Sum the split-K partials in split order and apply the epilogue.
 template <int KIND>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs a, int nsplit) {
@@ -1094,7 +1143,8 @@ static void launch_kind(const GemmArgs& a, const Plan& p, hipStream_t s) {
 lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void* Lq, int64_t ldl,
                             const float* dL, const void* Rq, int64_t ldr, const float* dR, float alpha,
                             float beta, void* C, int64_t ldc, int ctype, int32_t* acc_out, int64_t ld_acc,
-                            void* ws, size_t ws_bytes, hipStream_t s, bool col_first, int km) {
+                            void* ws, size_t ws_bytes, hipStream_t s, bool col_first, int km, const CodesOut* codes) {
+  if (codes) *codes->written = false;
   int kind = kind_of(fmt);
   if (kind < 0) return LRAMM_E_UNSUPPORTED;
   if (km != 0 && (kind != KIND_BF16 || (km & ~3))) return LRAMM_E_UNSUPPORTED;
@@ -1142,6 +1192,15 @@ lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void
     default: launch_kind<KIND_BF16>(a, p, s); break;
   }
   LRAMM_HIP(hipGetLastError());
+  if (p.split > 1 && codes && kind == KIND_BF16 && alpha == 1.0f && beta == 0.0f && ctype == LRAMM_F32 &&
+      !acc_out && codes->pe >= N && codes->pe % 4 == 0 && M * (codes->pe / 4) < ((int64_t)1 << 31)) {
+    const int64_t threads = M * (codes->pe / 4);
+    hipLaunchKernelGGL(splitk_reduce_bf16_codes_kernel, dim3((unsigned)ceil_div(threads, (int64_t)256)), dim3(256), 0,
+                       s, a, p.split, codes->codes, codes->pitch, (int)codes->pe, codes->scales);
+    LRAMM_HIP(hipGetLastError());
+    *codes->written = true;
+    return LRAMM_OK;
+  }
   if (p.split > 1) {
     int64_t quads = ceil_div(M * N, 4);
     const dim3 g((unsigned)ceil_div(quads, 256));

@@ -634,20 +634,27 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   else
     TIMED(ST_QUANT_Q_COLS,
           launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s, mxQ(d.q), true));
+  uint8_t* Btq = at<uint8_t>(W, P->off_Btq);
+  float* sBt = at<float>(W, P->off_sBt);
+  // bf16 G1 and a projection summed over K slices: the slice sum also writes
+  // Bt's bf16 row codes (when it does not, the row quantiser below runs)
+  bool bt_codes = false;
+  const CodesOut bt_out = {reinterpret_cast<uint16_t*>(Btq), P->pBtq / 2, pitch_elems(P->pBtq, LRAMM_BF16F), sBt,
+                           &bt_codes};
+  const CodesOut* bt_co = (!range_only && d.fmt_g1 == LRAMM_BF16F) ? &bt_out : nullptr;
   if (km_a)
     TIMED(ST_PROJ, launch_gemm_nt(l, k, m, d.fmt_proj, Qc, P->pQc, sQc, A, lda * 2, sAc, 1.0f, 0.0f, Bt, k,
-                                  LRAMM_F32, nullptr, 0, split, sb, s, false, 2));
+                                  LRAMM_F32, nullptr, 0, split, sb, s, false, 2, bt_co));
   else
     TIMED(ST_PROJ, launch_gemm_nt(l, k, m, d.fmt_proj, Qc, P->pQc, sQc, Ac, P->pAc, sAc, 1.0f, 0.0f, Bt, k,
-                                  LRAMM_F32, nullptr, 0, split, sb, s));
+                                  LRAMM_F32, nullptr, 0, split, sb, s, false, 0, bt_co));
   if (norms)   // ||Bt||_F^2 = ||Q^T A'||_F^2 (up to the projection's quantisation)
     LRAMM_TRY(launch_sumsq(l, k, Bt, k, LRAMM_F32, norms + 2 + sumsq_parts_max(), norms + 1, s));
   if (range_only) return LRAMM_OK;
   // G1: T^T = B_c . Bt_q^T  (n x l)
-  uint8_t* Btq = at<uint8_t>(W, P->off_Btq);
-  float* sBt = at<float>(W, P->off_sBt);
   float* Tt = at<float>(W, P->off_Tt);
-  TIMED(ST_QUANT_BT, launch_quantize(l, k, Bt, k, LRAMM_F32, d.fmt_g1, 0, Btq, P->pBtq, sBt, flags, s));
+  if (!bt_codes)
+    TIMED(ST_QUANT_BT, launch_quantize(l, k, Bt, k, LRAMM_F32, d.fmt_g1, 0, Btq, P->pBtq, sBt, flags, s));
   // Tt is T transposed: the row factor of T (that of B~) is this product's
   // column factor, so the epilogue applies it first
   if (km_b)   // T = Bt_q B (l x n, ld n in the same buffer), B read in place as the right operand

@@ -700,6 +700,10 @@ FP_CASES = [
     (1024, 2048, 512, 200, 16, 0, 48.0, ("bf16",) * 4, torch.bfloat16, True),
     (1024, 2048, 512, 120, 16, 1, 48.0, ("bf16",) * 4, torch.bfloat16, True),
     (700, 1536, 300, 90, 10, 0, 32.0, ("int8", "bf16", "bf16", "bf16"), torch.bfloat16, True),
+    # projections summed over K slices whose slice sum also writes Bt's bf16
+    # codes: a ragged k (1002, padded to 1024; scalar quads) and k % 4 == 0
+    (4096, 1002, 300, 84, 16, 0, 32.0, ("bf16",) * 4, torch.float32, False),
+    (4096, 1000, 300, 84, 16, 1, 32.0, ("int8", "bf16", "bf16", "bf16"), torch.bfloat16, True),
 ]
 
 
