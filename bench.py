@@ -425,8 +425,8 @@ def precision_sweep(args, lramm, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the multi-GPU path is a "
-              "design in DESIGN.md and is not built.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the library runs on one GPU, "
+              "and its row-sharded multi-GPU form is designed but not built.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -1,9 +1,9 @@
 """Philox4x32-10 and the Gaussian test matrix -- TEST INFRASTRUCTURE ONLY.
 
 The range finder samples A with a Gaussian test matrix (Sec. 2.2 lists
-Gaussian sampling among the strategies; the spec method uses it).  When
-the caller does not pass Omega, the library draws it from a counter-based
-generator so that any element can be recomputed independently.  Both sides
+Gaussian sampling among the strategies; the library's default sketch uses
+it).  When the caller does not pass Omega, the library draws it from a
+counter-based generator so that any element can be recomputed independently.  Both sides
 implement the same published generator from its definition:
 
   Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
