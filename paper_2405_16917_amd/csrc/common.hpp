@@ -237,16 +237,20 @@ lramm_status launch_quantize_both(int64_t rows, int64_t cols, const void* X, int
 // elements, ldl bytes apart) instead of K-contiguous rows; bit 1 -- the same
 // for Rq (K rows of N elements, ldr bytes apart).  Runs on the 128-row tiles.
 // Optional second output of a bf16 product summed over K slices with the
-// identity epilogue: C's bf16 row codes (pitch and pe in elements) and unit
-// scales.  *written tells whether they were formed (else the caller runs the
-// row quantiser on C).
+// identity epilogue: C's bf16 row codes, or with ``transposed`` the codes of
+// C's columns (one codes row per column of C), pitch and pe in elements, and
+// unit scales.  *written tells whether they were formed (else the caller runs
+// the quantiser on C).
 struct CodesOut {
   uint16_t* codes;
   int64_t pitch;
   int64_t pe;
   float* scales;
   bool* written;
+  bool transposed;
 };
+lramm_status launch_bf16_cols_from_parts(int64_t rows, int64_t cols, const float* parts, int nsplit, float* C,
+                                         int64_t ldc, uint8_t* Xq, int64_t pitch, float* scales, hipStream_t s);
 lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void* Lq, int64_t ldl,
                             const float* dL, const void* Rq, int64_t ldr, const float* dR, float alpha,
                             float beta, void* C, int64_t ldc, int ctype, int32_t* acc_out, int64_t ld_acc,

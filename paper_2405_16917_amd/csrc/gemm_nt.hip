@@ -1192,8 +1192,18 @@ lramm_status launch_gemm_nt(int64_t M, int64_t N, int64_t K, int fmt, const void
     default: launch_kind<KIND_BF16>(a, p, s); break;
   }
   LRAMM_HIP(hipGetLastError());
-  if (p.split > 1 && codes && kind == KIND_BF16 && alpha == 1.0f && beta == 0.0f && ctype == LRAMM_F32 &&
-      !acc_out && codes->pe >= N && codes->pe % 4 == 0 && M * (codes->pe / 4) < ((int64_t)1 << 31)) {
+  if (p.split > 1 && codes && codes->transposed && kind == KIND_BF16 && alpha == 1.0f && beta == 0.0f &&
+      ctype == LRAMM_F32 && !acc_out && codes->pe >= M && codes->pe % 64 == 0) {
+    // the slice sum and the transposed codes of C's columns in one pass
+    LRAMM_TRY(launch_bf16_cols_from_parts(M, N, reinterpret_cast<const float*>(a.part), p.split,
+                                          reinterpret_cast<float*>(C), ldc, reinterpret_cast<uint8_t*>(codes->codes),
+                                          2 * codes->pitch, codes->scales, s));
+    *codes->written = true;
+    return LRAMM_OK;
+  }
+  if (p.split > 1 && codes && !codes->transposed && kind == KIND_BF16 && alpha == 1.0f && beta == 0.0f &&
+      ctype == LRAMM_F32 && !acc_out && codes->pe >= N && codes->pe % 4 == 0 &&
+      M * (codes->pe / 4) < ((int64_t)1 << 31)) {
     const int64_t threads = M * (codes->pe / 4);
     hipLaunchKernelGGL(splitk_reduce_bf16_codes_kernel, dim3((unsigned)ceil_div(threads, (int64_t)256)), dim3(256), 0,
                        s, a, p.split, codes->codes, codes->pitch, (int)codes->pe, codes->scales);

@@ -640,7 +640,7 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
   // Bt's bf16 row codes (when it does not, the row quantiser below runs)
   bool bt_codes = false;
   const CodesOut bt_out = {reinterpret_cast<uint16_t*>(Btq), P->pBtq / 2, pitch_elems(P->pBtq, LRAMM_BF16F), sBt,
-                           &bt_codes};
+                           &bt_codes, false};
   const CodesOut* bt_co = (!range_only && d.fmt_g1 == LRAMM_BF16F) ? &bt_out : nullptr;
   if (km_a)
     TIMED(ST_PROJ, launch_gemm_nt(l, k, m, d.fmt_proj, Qc, P->pQc, sQc, A, lda * 2, sAc, 1.0f, 0.0f, Bt, k,
@@ -657,21 +657,27 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
     TIMED(ST_QUANT_BT, launch_quantize(l, k, Bt, k, LRAMM_F32, d.fmt_g1, 0, Btq, P->pBtq, sBt, flags, s));
   // Tt is T transposed: the row factor of T (that of B~) is this product's
   // column factor, so the epilogue applies it first
+  // bf16 G2 and T = Bt_q B summed over K slices: the slice sum also writes
+  // T's column codes (when it does not, the column quantiser below runs)
+  uint8_t* Ttq = at<uint8_t>(W, P->off_Ttq);
+  float* sTt = at<float>(W, P->off_sTt);
+  bool tt_codes = false;
+  const CodesOut tt_out = {reinterpret_cast<uint16_t*>(Ttq), P->pTtq / 2, pitch_elems(P->pTtq, LRAMM_BF16F), sTt,
+                           &tt_codes, true};
   if (km_b)   // T = Bt_q B (l x n, ld n in the same buffer), B read in place as the right operand
     TIMED(ST_G1, launch_gemm_nt(l, n, k, d.fmt_g1, Btq, P->pBtq, sBt, B, ldb * 2, sBc, 1.0f, 0.0f, Tt, n, LRAMM_F32,
-                                nullptr, 0, split, sb, s, false, 2));
+                                nullptr, 0, split, sb, s, false, 2, d.fmt_g2 == LRAMM_BF16F ? &tt_out : nullptr));
   else
     TIMED(ST_G1, launch_gemm_nt(n, l, k, d.fmt_g1, Bc, P->pBc, sBc, Btq, P->pBtq, sBt, 1.0f, 0.0f, Tt, lp, LRAMM_F32,
                                 nullptr, 0, split, sb, s, true));
   // G2: C = alpha Q_r . Tt_q^T + beta C  (m x n)
   uint8_t* Qr = at<uint8_t>(W, P->off_Qr);
   float* sQr = at<float>(W, P->off_sQr);
-  uint8_t* Ttq = at<uint8_t>(W, P->off_Ttq);
-  float* sTt = at<float>(W, P->off_sTt);
   if (!q_both) TIMED(ST_QUANT_Q_ROWS, launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_g2, 0, Qr, P->pQr, sQr, flags, s));
-  if (km_b)   // the rows of T^T are the columns of T
-    TIMED(ST_QUANT_TT, launch_quantize(l, n, Tt, n, LRAMM_F32, d.fmt_g2, 1, Ttq, P->pTtq, sTt, flags, s));
-  else
+  if (km_b) {   // the rows of T^T are the columns of T
+    if (!tt_codes)
+      TIMED(ST_QUANT_TT, launch_quantize(l, n, Tt, n, LRAMM_F32, d.fmt_g2, 1, Ttq, P->pTtq, sTt, flags, s));
+  } else
     TIMED(ST_QUANT_TT, launch_quantize(n, l, Tt, lp, LRAMM_F32, d.fmt_g2, 0, Ttq, P->pTtq, sTt, flags, s));
   if (!P->ct) {
     TIMED(ST_G2, launch_gemm_nt(m, n, l, d.fmt_g2, Qr, P->pQr, sQr, Ttq, P->pTtq, sTt, d.alpha, d.beta, C, ldc,

@@ -322,6 +322,90 @@ __global__ __launch_bounds__(256) void quant_cols_t_kernel(int64_t rows, int64_t
   }
 }
 
+// The K-slice sum of a product (slices [nsplit][rows][cols], FP32) written
+// once as C (rows x cols, ldc) and once as bf16 codes of C's columns,
+// transposed: codes row c holds column c of C (pitch bytes, zero past rows),
+// with unit scales.  The sums are formed in split order from zero, as the
+// plain slice sum forms them, so C and the codes are those of the sum-then-
+// quantise passes to the bit, with one read of the slices instead of three
+// passes.  Tiles of 64 (rows) x 64 (cols), as in quant_cols_t_kernel.
+__global__ __launch_bounds__(256) void bf16_cols_from_parts_kernel(int64_t rows, int64_t cols,
+                                                                   const float* __restrict__ parts, int nsplit,
+                                                                   float* __restrict__ C, int64_t ldc,
+                                                                   uint8_t* __restrict__ Xq, int64_t pitch,
+                                                                   float* __restrict__ scales, int cvec) {
+  __shared__ uint16_t sT[64][66];
+  const int t = threadIdx.x;
+  const int64_t col0 = (int64_t)blockIdx.x * 64;
+  const int64_t k0 = (int64_t)blockIdx.y * 64;
+  const int64_t pstride = rows * cols;
+  if (blockIdx.y == 0 && t < 64 && col0 + t < cols) scales[col0 + t] = 1.0f;
+  const int cg = t & 15, sub = t >> 4;
+  const int64_t c4 = col0 + 4 * cg;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t r = k0 + sub + 16 * i;
+    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (r < rows && c4 < cols) {
+      const int64_t e0 = r * cols + c4;
+      if ((cols & 3) == 0) {
+        // a whole quad inside the row: 16-byte loads of each slice
+        for (int k = 0; k < nsplit; ++k) {
+          const float4 x = *reinterpret_cast<const float4*>(parts + k * pstride + e0);
+          v[0] = __fadd_rn(v[0], x.x);
+          v[1] = __fadd_rn(v[1], x.y);
+          v[2] = __fadd_rn(v[2], x.z);
+          v[3] = __fadd_rn(v[3], x.w);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (c4 + j < cols)
+            for (int k = 0; k < nsplit; ++k) v[j] = __fadd_rn(v[j], parts[k * pstride + e0 + j]);
+      }
+      float* cr = C + r * ldc;
+      if (cvec && c4 + 3 < cols) {
+        *reinterpret_cast<float4*>(cr + c4) = make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (c4 + j < cols) cr[c4 + j] = v[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      sT[4 * cg + j][sub + 16 * i] = (r < rows && c4 + j < cols) ? bf16_bits(v[j]) : (uint16_t)0;
+  }
+  __syncthreads();
+  // write: output row = column of C, 64 elements of K starting at k0
+  const int orow = t >> 2;
+  const int part = t & 3;
+  const int64_t oc = col0 + orow;
+  if (oc >= cols) return;
+  uint32_t w[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int kk = part * 16 + 2 * q;
+    w[q] = (uint32_t)sT[orow][kk] | ((uint32_t)sT[orow][kk + 1] << 16);
+  }
+  uint4* d4 = reinterpret_cast<uint4*>(Xq + oc * pitch + 2 * k0 + part * 32);
+  d4[0] = make_uint4(w[0], w[1], w[2], w[3]);
+  d4[1] = make_uint4(w[4], w[5], w[6], w[7]);
+}
+
+lramm_status launch_bf16_cols_from_parts(int64_t rows, int64_t cols, const float* parts, int nsplit, float* C,
+                                         int64_t ldc, uint8_t* Xq, int64_t pitch, float* scales, hipStream_t s) {
+  if (rows == 0 || cols == 0) return LRAMM_OK;
+  const int64_t pe = pitch_elems(pitch, LRAMM_BF16F);
+  if (pe < rows || pe % 64 != 0) return LRAMM_E_INVALID;
+  const int cvec = (ldc % 4 == 0) && ((uintptr_t)C % 16 == 0) ? 1 : 0;
+  const dim3 g((unsigned)ceil_div(cols, (int64_t)64), (unsigned)(pe / 64));
+  hipLaunchKernelGGL(bf16_cols_from_parts_kernel, g, dim3(256), 0, s, rows, cols, parts, nsplit, C, ldc, Xq, pitch,
+                     scales, cvec);
+  LRAMM_HIP(hipGetLastError());
+  return LRAMM_OK;
+}
+
 template <int FMT>
 __global__ void col_scales_kernel(int64_t cols, float* scales, uint32_t* flags) {
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

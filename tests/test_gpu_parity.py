@@ -704,6 +704,9 @@ FP_CASES = [
     # codes: a ragged k (1002, padded to 1024; scalar quads) and k % 4 == 0
     (4096, 1002, 300, 84, 16, 0, 32.0, ("bf16",) * 4, torch.float32, False),
     (4096, 1000, 300, 84, 16, 1, 32.0, ("int8", "bf16", "bf16", "bf16"), torch.bfloat16, True),
+    # G1 as T = Bt_q B with B read in place, summed over 16 K slices whose sum
+    # also writes T's column codes, transposed (n = 1000: a ragged last tile)
+    (1024, 4096, 1000, 84, 16, 0, 32.0, ("bf16",) * 4, torch.bfloat16, True),
 ]
 
 
