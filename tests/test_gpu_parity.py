@@ -456,7 +456,10 @@ def _raw(plan, ws, name, A=None, rows=None):
     c, sc, K, f = plan.codes(ws, name, A)
     if rows is not None:
         c, sc = c[torch.as_tensor(rows, device=c.device)], sc[torch.as_tensor(rows, device=c.device)]
-    return c.cpu().numpy(), sc.cpu().numpy().astype(np.float64), K, f
+    # on the direct bf16 path the A_rows scales are not written (the codes
+    # are A itself, scale 1): whatever bits they hold are never used
+    with np.errstate(invalid="ignore"):
+        return c.cpu().numpy(), sc.cpu().numpy().astype(np.float64), K, f
 
 
 def _check_codes(name, raw, K, fmt, X_rows, mismatch=0):
