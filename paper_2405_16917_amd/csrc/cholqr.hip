@@ -377,6 +377,25 @@ constexpr size_t ts_stage_lds() { return (size_t)TS_WAVES * TS_WST * sizeof(doub
 // RB: 16-row halves per workgroup (1 or 2).  With two, each wavefront feeds
 // the same W fragments to both halves (W is read once per 32 rows, and four
 // accumulators are in flight); the last-block solve needs RB = 1.
+// Q's bf16 codes written beside Q (rows codes and the transposed codes; null
+// rows: none), for a solve whose Q is final.
+struct TsCodes {
+  uint16_t* rows;
+  int64_t rpitch;       // elements
+  int rpe;              // elements per codes row (zero from lw on)
+  float* rscales;
+  uint16_t* cols;       // one row per column c < ncols
+  int64_t cpitch;       // elements
+  int64_t cpe;          // elements per transposed codes row (zero from rows on)
+  float* cscales;
+};
+
+__device__ __forceinline__ void ts_put_codes(const TsCodes& tc, int64_t row, int col, int ncols, double v) {
+  const uint16_t h = bf16_bits((float)v);
+  tc.rows[row * tc.rpitch + col] = h;
+  if (col < ncols) tc.cols[(int64_t)col * tc.cpitch + row] = h;
+}
+
 template <typename T, bool ADD, bool STAGED, int RB = 1>
 __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int lw, int ncols, const T* X,
                                                               int64_t ldx, const double* __restrict__ W, double* Q,
@@ -384,7 +403,7 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
                                                               uint32_t* __restrict__ colmax, int cm_stride,
                                                               const uint32_t* __restrict__ gate,
                                                               const double* __restrict__ Ltri,
-                                                              const double* __restrict__ Dlast) {
+                                                              const double* __restrict__ Dlast, TsCodes tc) {
   extern __shared__ double sA[];   // ROWS x ts_pitch(lw) [+ the last-block solve's buffers]
   constexpr int ROWS = TS_ROWS * RB;
   if (ADD && gate && !(*gate & kGatePass2)) return;   // second pass skipped: Q already holds Q1
@@ -563,6 +582,10 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
           }
           Q[row * ldq + cb0 + li] = v0;
           Q[row * ldq + cb0 + 16 + li] = v1;
+          if (tc.rows) {
+            ts_put_codes(tc, row, cb0 + li, ncols, v0);
+            ts_put_codes(tc, row, cb0 + 16 + li, ncols, v1);
+          }
           m0 = max(m0, __float_as_uint(fabsf((float)v0)));
           m1 = max(m1, __float_as_uint(fabsf((float)v1)));
         }
@@ -641,6 +664,10 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
         if (row < rows) {
           Q[row * ldq + cb0 + li] = o0[r];
           Q[row * ldq + cb0 + 16 + li] = o1[r];
+          if (tc.rows) {
+            ts_put_codes(tc, row, cb0 + li, ncols, o0[r]);
+            ts_put_codes(tc, row, cb0 + 16 + li, ncols, o1[r]);
+          }
           m0 = max(m0, __float_as_uint(fabsf((float)o0[r])));
           m1 = max(m1, __float_as_uint(fabsf((float)o1[r])));
         }
@@ -661,6 +688,23 @@ __global__ __launch_bounds__(TS_WAVES * 64) void tsmul_kernel(int64_t rows, int 
   for (int e = tid; e < ROWS * zc; e += TS_WAVES * 64) {
     const int64_t row = r0 + e / zc;
     if (row < rows) Q[row * ldq + lw + e % zc] = 0.0;
+  }
+  if (tc.rows) {
+    // the row codes' padding past lw, the unit scales of the rows (and, in
+    // workgroup 0, of the transposed codes)
+    const int zr = tc.rpe - lw;
+    for (int e = tid; e < ROWS * zr; e += TS_WAVES * 64) {
+      const int64_t row = r0 + e / zr;
+      if (row < rows) tc.rows[row * tc.rpitch + lw + e % zr] = 0;
+    }
+    for (int e = tid; e < ROWS; e += TS_WAVES * 64)
+      if (r0 + e < rows) tc.rscales[r0 + e] = 1.0f;
+    if (blockIdx.x == 0)
+      for (int c = tid; c < ncols; c += TS_WAVES * 64) tc.cscales[c] = 1.0f;
+    // the transposed codes' padding past the last row, by the last workgroup
+    const int zt = (int)(tc.cpe - rows);
+    if (r0 + ROWS >= rows && zt > 0)
+      for (int e = tid; e < ncols * zt; e += TS_WAVES * 64) tc.cols[(int64_t)(e / zt) * tc.cpitch + rows + e % zt] = 0;
   }
 }
 
@@ -2030,7 +2074,8 @@ template <typename T, bool ADD>
 static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t ldx, const double* W, double* Q,
                           int64_t ldq, int zero_to, hipStream_t s, const TimingHook* hook,
                           uint32_t* colmax = nullptr, const uint32_t* gate = nullptr,
-                          const double* Ltri = nullptr, const double* Dlast = nullptr, int cm_stride = 0) {
+                          const double* Ltri = nullptr, const double* Dlast = nullptr, int cm_stride = 0,
+                          const TsCodes& tc = TsCodes{}) {
   constexpr size_t kMaxLds = 160 * 1024;
   static bool attr_set = false;
   if (!attr_set) {   // up to 160 KiB of LDS
@@ -2050,7 +2095,7 @@ static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t l
   if (!Ltri && ts_two_halves(rows, lw)) {
     const dim3 grid2((unsigned)ceil_div(rows, (int64_t)(2 * TS_ROWS)));
     hipLaunchKernelGGL((tsmul_kernel<T, ADD, true, 2>), grid2, dim3(TS_WAVES * 64), shm2 + ts_stage_lds(), s, rows,
-                       lw, ncols, X, ldx, W, Q, ldq, zero_to, vec, colmax, cm_stride, gate, Ltri, Dlast);
+                       lw, ncols, X, ldx, W, Q, ldq, zero_to, vec, colmax, cm_stride, gate, Ltri, Dlast, tc);
     LRAMM_HIP(hipGetLastError());
     return LRAMM_OK;
   }
@@ -2060,10 +2105,10 @@ static lramm_status tsmul(int64_t rows, int lw, int ncols, const T* X, int64_t l
   // W staged through LDS when the tiles fit beside the row panel
   if (shm + ts_stage_lds() <= kMaxLds)
     hipLaunchKernelGGL((tsmul_kernel<T, ADD, true>), grid, block, shm + ts_stage_lds(), s, rows, lw, ncols, X, ldx, W,
-                       Q, ldq, zero_to, vec, colmax, cm_stride, gate, Ltri, Dlast);
+                       Q, ldq, zero_to, vec, colmax, cm_stride, gate, Ltri, Dlast, tc);
   else
     hipLaunchKernelGGL((tsmul_kernel<T, ADD, false>), grid, block, shm, s, rows, lw, ncols, X, ldx, W, Q, ldq,
-                       zero_to, vec, colmax, cm_stride, gate, Ltri, Dlast);
+                       zero_to, vec, colmax, cm_stride, gate, Ltri, Dlast, tc);
   LRAMM_HIP(hipGetLastError());
   return LRAMM_OK;
 }
@@ -2133,7 +2178,9 @@ lramm_status launch_r_factor(int64_t rows, int64_t l, const void* Y, int64_t ldy
 
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
                             int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s,
-                            const TimingHook* hook, uint32_t* colmax, int chain_mode, int passes) {
+                            const TimingHook* hook, uint32_t* colmax, int chain_mode, int passes,
+                            const QCodesOut* qcodes) {
+  if (qcodes) *qcodes->written = false;
   if (rows == 0 || l == 0) return LRAMM_OK;
   if (passes != 1 && passes != 2) return LRAMM_E_INVALID;
   int lw, nc;
@@ -2178,11 +2225,24 @@ lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy,
   const bool solve_last = (Tn1 % 2 == 1) && ts_solve_last_lds(lw) <= 160 * 1024 && !ts_two_halves(rows, lw);
   const double* Ltri = solve_last ? w.L : nullptr;
   const double* Dlast = solve_last ? w.Dinv + (size_t)(Tn1 - 1) * NB * NB : nullptr;
+  // one pass: the solve's Q is final, and it can write Q's bf16 codes too
+  TsCodes tc{};
+  if (passes == 1 && qcodes && ytype == LRAMM_F32 && round_up(l, (int64_t)64) >= lw) {
+    tc.rows = qcodes->rows;
+    tc.rpitch = qcodes->rpitch;
+    tc.rpe = (int)round_up(l, (int64_t)64);
+    tc.rscales = qcodes->rscales;
+    tc.cols = qcodes->cols;
+    tc.cpitch = qcodes->cpitch;
+    tc.cpe = round_up(rows, (int64_t)64);
+    tc.cscales = qcodes->cscales;
+  }
   if (ytype == LRAMM_F32) {
     LRAMM_TRY(gram<float>(rows, lw, lt, (const float*)Y, ldy, w, 0, s, hook));
     LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last, chain_mode));
     LRAMM_TRY((tsmul<float, false>(rows, lw, lt, (const float*)Y, ldy, w.X, Q, ldq, zero_to, s, hook, cm1, nullptr,
-                                   Ltri, Dlast, cm_stride)));
+                                   Ltri, Dlast, cm_stride, tc)));
+    if (tc.rows) *qcodes->written = true;
   } else if (ytype == LRAMM_F64) {
     LRAMM_TRY(gram<double>(rows, lw, lt, (const double*)Y, ldy, w, 0, s, hook));
     LRAMM_TRY(cholesky_inverse(lw, lt, w, flags, s, hook, solve_last, chain_mode));

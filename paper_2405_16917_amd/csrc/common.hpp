@@ -315,10 +315,23 @@ bool chain_admits(int64_t l, int compute_units, int chain_mode);
 // the first Cholesky QR pass (Q = Y R1^-1).
 lramm_status launch_r_factor(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, const double* Q,
                              int64_t ldq, double* R, int64_t ldr, hipStream_t s);
+// Optional output of a one-pass Cholesky QR: Q's bf16 codes in both layouts
+// the bf16 products read (row codes, rows x rpitch elements, and the
+// transposed codes, one row per column of Q, l x cpitch elements), each code
+// bf16(fl32(q)), with unit scales.  *written tells whether they were formed.
+struct QCodesOut {
+  uint16_t* rows;
+  int64_t rpitch;
+  float* rscales;
+  uint16_t* cols;
+  int64_t cpitch;
+  float* cscales;
+  bool* written;
+};
 lramm_status launch_cholqr2(int64_t rows, int64_t l, const void* Y, int64_t ldy, int ytype, double* Q,
                             int64_t ldq, void* ws, size_t ws_bytes, uint32_t* flags, hipStream_t s,
                             const TimingHook* hook = nullptr, uint32_t* colmax = nullptr,
-                            int chain_mode = CHAIN_SHARED, int passes = 2);
+                            int chain_mode = CHAIN_SHARED, int passes = 2, const QCodesOut* qcodes = nullptr);
 size_t cholqr2_workspace(int64_t rows, int64_t l);
 // The least workspace CholeskyQR2 runs in (one row chunk of the Gram); with
 // less than cholqr2_workspace it uses fewer chunks.

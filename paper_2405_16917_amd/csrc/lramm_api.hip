@@ -594,10 +594,17 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
     else LRAMM_TRY(launch_sumsq(k, m, A, lda, d.a_type, norms + 2, norms, s2));
   }
   if (side_after) LRAMM_HIP(hipEventRecord(P->ev_join, P->side));
-  TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(0),
-                                   P->chain_mode, P->passes));
   uint8_t* Qc = at<uint8_t>(W, P->off_Qc);
   float* sQc = at<float>(W, P->off_sQc);
+  // bf16 projection and G2: Q's transposed and row codes from one read of Q,
+  // or, with one Cholesky QR pass, written by the last solve beside Q itself
+  const bool q_both = d.fmt_proj == LRAMM_BF16F && d.fmt_g2 == LRAMM_BF16F;
+  bool q_codes = false;
+  const QCodesOut q_out = {reinterpret_cast<uint16_t*>(at<uint8_t>(W, P->off_Qr)), P->pQr / 2,
+                           at<float>(W, P->off_sQr), reinterpret_cast<uint16_t*>(Qc), P->pQc / 2, sQc, &q_codes};
+  const QCodesOut* q_co = (q_both && P->passes == 1) ? &q_out : nullptr;
+  TIMED(ST_CHOLQR2, launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(0),
+                                   P->chain_mode, P->passes, d.q == 0 ? q_co : nullptr));
   if (side_after) LRAMM_HIP(hipStreamWaitEvent(s, P->ev_join, 0));   // join: A_c and B_c ready
   for (int it = 0; it < d.q; ++it) {
     float* Z = at<float>(W, P->off_Z);
@@ -620,18 +627,17 @@ lramm_status forward_impl(lramm_plan* P, const void* A, int64_t lda, const void*
                                      LRAMM_F32, nullptr, 0, split, sb, s));
     TIMED(ST_CHOLQR2,
           launch_cholqr2(m, l, Y, lp, LRAMM_F32, Q, lp, cws, P->chol_bytes, flags, s, hk, mxQ(it + 1),
-                         P->chain_mode, P->passes));
+                         P->chain_mode, P->passes, it + 1 == d.q ? q_co : nullptr));
   }
   // projection Bt = Q^T A  (l x k)
   float* Bt = at<float>(W, P->off_Bt);
-  // bf16 projection and G2: Q's transposed and row codes from one read of Q
   // (no maxima; the G2 codes are formed before they are needed)
-  const bool q_both = d.fmt_proj == LRAMM_BF16F && d.fmt_g2 == LRAMM_BF16F;
-  if (q_both)
-    TIMED(ST_QUANT_Q_COLS, launch_quantize_both(m, l, Q, lp, LRAMM_F64, LRAMM_BF16F, at<uint8_t>(W, P->off_Qr),
-                                                P->pQr, at<float>(W, P->off_sQr), Qc, P->pQc, sQc, nullptr, nullptr,
-                                                flags, s));
-  else
+  if (q_both) {
+    if (!q_codes)
+      TIMED(ST_QUANT_Q_COLS, launch_quantize_both(m, l, Q, lp, LRAMM_F64, LRAMM_BF16F, at<uint8_t>(W, P->off_Qr),
+                                                  P->pQr, at<float>(W, P->off_sQr), Qc, P->pQc, sQc, nullptr, nullptr,
+                                                  flags, s));
+  } else
     TIMED(ST_QUANT_Q_COLS,
           launch_quantize(m, l, Q, lp, LRAMM_F64, d.fmt_proj, 1, Qc, P->pQc, sQc, flags, s, mxQ(d.q), true));
   uint8_t* Btq = at<uint8_t>(W, P->off_Btq);

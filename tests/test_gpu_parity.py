@@ -621,6 +621,11 @@ ONE_PASS_CASES = [
     (300, 257, 190, 20, 5, 2, 12.0, ("int8",) * 4, "fp32", "gaussian"),
     (4096, 4096, 4096, 256, 16, 1, 128.0, ("int8",) * 4, "fp32", "gaussian", 1e-4),
     (2048, 8192, 1024, 384, 32, 0, 64.0, ("bf16",) * 4, "bf16", "srht"),
+    # bf16 projection and G2: the last solve also writes Q's two code layouts
+    # (l = 400 inside l' = 416, ragged rows, after a power step; the odd block
+    # count takes the solve that forms the last block from the others)
+    (1000, 3000, 700, 368, 32, 1, 48.0, ("bf16",) * 4, "fp32", "gaussian"),
+    (3000, 1000, 500, 100, 28, 0, 24.0, ("int8", "bf16", "int8", "bf16"), "fp32", "gaussian"),
 ]
 
 
