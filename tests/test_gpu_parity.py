@@ -626,6 +626,8 @@ ONE_PASS_CASES = [
     # count takes the solve that forms the last block from the others)
     (1000, 3000, 700, 368, 32, 1, 48.0, ("bf16",) * 4, "fp32", "gaussian"),
     (3000, 1000, 500, 100, 28, 0, 24.0, ("int8", "bf16", "int8", "bf16"), "fp32", "gaussian"),
+    # 8192 rows: the solve with two 16-row halves per workgroup, l = 400 inside l' = 416
+    (8192, 2048, 512, 368, 32, 0, 64.0, ("bf16",) * 4, "bf16", "srht"),
 ]
 
 
